@@ -1,0 +1,215 @@
+"""Reference elements, nodal Lagrange bases and quadrature rules (oracle).
+
+Readings fixed here (the paper names no basis or rule, Sec. 2.1 and Sec. 4
+only require "a nodal basis" and "a quadrature rule"):
+
+* segments / quadrilaterals, DG: Lagrange basis at the p+1 Gauss-Legendre
+  points per direction; volume rule = the same (p+1)^d Gauss points
+  (collocated, so the element mass matrix is diagonal and exact).
+* segments / quadrilaterals, CG: Lagrange basis at the p+1 Gauss-Lobatto
+  points per direction (vertices are nodes); volume rule = (p+1)^d Gauss points.
+* triangles: Lagrange basis at the equispaced points (i/p, j/p), i+j<=p;
+  volume rule = the (p+1)^2-point conical-product (Stroud) rule, exact for
+  total degree 2p+1.
+* face rules: p+1 Gauss points on [-1, 1].
+
+All routines are plain numpy in float64.
+"""
+from __future__ import annotations
+
+import numpy as np
+from numpy.polynomial import legendre as npleg
+from numpy.polynomial import polynomial as nppoly
+from scipy.special import roots_jacobi
+
+
+def gauss_legendre(n: int):
+    """n-point Gauss-Legendre rule on [-1, 1]."""
+    x, w = npleg.leggauss(n)
+    return x.astype(np.float64), w.astype(np.float64)
+
+
+def gauss_lobatto(n: int):
+    """n-point Gauss-Lobatto-Legendre rule on [-1, 1] (n >= 2)."""
+    if n == 2:
+        return np.array([-1.0, 1.0]), np.array([1.0, 1.0])
+    P = npleg.Legendre.basis(n - 1)
+    inner = np.sort(P.deriv().roots().real)
+    x = np.concatenate([[-1.0], inner, [1.0]])
+    w = 2.0 / (n * (n - 1) * P(x) ** 2)
+    return x, w
+
+
+class Lagrange1D:
+    """Lagrange polynomials l_j on the given nodes, with derivatives of any order."""
+
+    def __init__(self, nodes):
+        self.nodes = np.asarray(nodes, dtype=np.float64)
+        n = len(self.nodes)
+        self.coef = []
+        for j in range(n):
+            others = np.delete(self.nodes, j)
+            c = nppoly.polyfromroots(others)
+            c = c / np.prod(self.nodes[j] - others)
+            self.coef.append(c)
+
+    def __call__(self, x, order: int = 0):
+        """Matrix [len(x), n] of d^order l_j / dx^order evaluated at x."""
+        x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+        cols = []
+        for c in self.coef:
+            d = nppoly.polyder(c, order) if order > 0 else c
+            cols.append(nppoly.polyval(x, d) if len(d) else np.zeros_like(x))
+        return np.stack(cols, axis=-1)
+
+
+def stroud_triangle(n: int):
+    """n*n-point conical-product rule on the triangle (0,0),(1,0),(0,1).
+
+    Collapsed coordinates xi = a (1 - b), eta = b with a, b in [0, 1]; Gauss-
+    Legendre in a and Gauss-Jacobi (weight 1-b) in b.  Exact for total
+    degree 2n-1.  Point index = ia + n * ib.
+    """
+    xa, wa = gauss_legendre(n)
+    a = 0.5 * (xa + 1.0)
+    wa = 0.5 * wa
+    xb, wb = roots_jacobi(n, 1.0, 0.0)
+    b = 0.5 * (xb + 1.0)
+    wb = wb / 4.0
+    pts, wts = [], []
+    for ib in range(n):
+        for ia in range(n):
+            pts.append((a[ia] * (1.0 - b[ib]), b[ib]))
+            wts.append(wa[ia] * wb[ib])
+    return np.array(pts), np.array(wts)
+
+
+def multi_indices(dim: int, p: int):
+    """Derivative multi-indices k with 1 <= |k| <= p, ordered by |k|, then by
+    decreasing first component: (1,0),(0,1),(2,0),(1,1),(0,2),..."""
+    out = []
+    for n in range(1, p + 1):
+        if dim == 1:
+            out.append((n,))
+        else:
+            for j in range(n + 1):
+                out.append((n - j, j))
+    return out
+
+
+class RefSeg:
+    dim = 1
+    n_vert = 2
+    n_faces = 2
+
+    def __init__(self, p: int, nodes: str):
+        self.p = p
+        x, _ = gauss_legendre(p + 1) if nodes == "gauss" else gauss_lobatto(p + 1)
+        self.x1d = x
+        self.L = Lagrange1D(x)
+        self.n_loc = p + 1
+        self.nodes = x[:, None]
+        self.vertices = np.array([[-1.0], [1.0]])
+        qx, qw = gauss_legendre(p + 1)
+        self.vol_pts, self.vol_w = qx[:, None], qw
+        qx2, qw2 = gauss_legendre(p + 2)
+        self.norm_pts, self.norm_w = qx2[:, None], qw2
+
+    def deriv(self, pts, m):
+        return self.L(np.asarray(pts)[:, 0], m[0])
+
+    def face_points(self, f):
+        """Face f (0 = left vertex, 1 = right vertex): reference points of the face rule, weights."""
+        return self.vertices[f][None, :], np.array([1.0])
+
+
+class RefQuad:
+    dim = 2
+    n_vert = 4
+    n_faces = 4
+
+    def __init__(self, p: int, nodes: str):
+        self.p = p
+        x, _ = gauss_legendre(p + 1) if nodes == "gauss" else gauss_lobatto(p + 1)
+        self.x1d = x
+        self.L = Lagrange1D(x)
+        self.n_loc = (p + 1) ** 2
+        X, Y = np.meshgrid(x, x, indexing="xy")       # index a + (p+1) b
+        self.nodes = np.stack([X.ravel(), Y.ravel()], axis=1)
+        self.vertices = np.array([[-1.0, -1.0], [1.0, -1.0], [1.0, 1.0], [-1.0, 1.0]])
+        qx, qw = gauss_legendre(p + 1)
+        QX, QY = np.meshgrid(qx, qx, indexing="xy")
+        self.vol_pts = np.stack([QX.ravel(), QY.ravel()], axis=1)
+        self.vol_w = np.outer(qw, qw).ravel()
+        qx2, qw2 = gauss_legendre(p + 2)
+        QX2, QY2 = np.meshgrid(qx2, qx2, indexing="xy")
+        self.norm_pts = np.stack([QX2.ravel(), QY2.ravel()], axis=1)
+        self.norm_w = np.outer(qw2, qw2).ravel()
+        self.face_x, self.face_w = gauss_legendre(p + 1)
+
+    def deriv(self, pts, m):
+        pts = np.asarray(pts)
+        Lx = self.L(pts[:, 0], m[0])          # [n, p+1]
+        Ly = self.L(pts[:, 1], m[1])
+        return (Lx[:, None, :] * Ly[:, :, None]).reshape(len(pts), -1)
+
+    def face_points(self, f):
+        """Face f joins local vertices f and f+1 (mod 4); points ordered from vertex f to f+1."""
+        s = self.face_x
+        a, b = self.vertices[f], self.vertices[(f + 1) % 4]
+        pts = 0.5 * (1 - s)[:, None] * a + 0.5 * (1 + s)[:, None] * b
+        return pts, self.face_w
+
+
+class RefTri:
+    dim = 2
+    n_vert = 3
+    n_faces = 3
+
+    def __init__(self, p: int, nodes: str = "equispaced"):
+        self.p = p
+        self.n_loc = (p + 1) * (p + 2) // 2
+        nd = []
+        for j in range(p + 1):
+            for i in range(p + 1 - j):
+                nd.append((i / p, j / p) if p > 0 else (1 / 3, 1 / 3))
+        self.nodes = np.array(nd)
+        self.mono = [(a, n - a) for n in range(p + 1) for a in range(n, -1, -1)]
+        V = np.stack([self.nodes[:, 0] ** a * self.nodes[:, 1] ** b for a, b in self.mono], axis=1)
+        self.Vinv = np.linalg.inv(V)      # column j = monomial coefficients of phi_j
+        self.vertices = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+        self.vol_pts, self.vol_w = stroud_triangle(p + 1)
+        self.norm_pts, self.norm_w = self.vol_pts, self.vol_w
+        self.face_x, self.face_w = gauss_legendre(p + 1)
+
+    def deriv(self, pts, m):
+        pts = np.asarray(pts)
+        cols = []
+        for a, b in self.mono:
+            if a < m[0] or b < m[1]:
+                cols.append(np.zeros(len(pts)))
+                continue
+            ca = np.prod(np.arange(a - m[0] + 1, a + 1)) if m[0] else 1.0
+            cb = np.prod(np.arange(b - m[1] + 1, b + 1)) if m[1] else 1.0
+            cols.append(ca * cb * pts[:, 0] ** (a - m[0]) * pts[:, 1] ** (b - m[1]))
+        M = np.stack(cols, axis=1)
+        return M @ self.Vinv
+
+    def face_points(self, f):
+        s = self.face_x
+        a, b = self.vertices[f], self.vertices[(f + 1) % 3]
+        pts = 0.5 * (1 - s)[:, None] * a + 0.5 * (1 + s)[:, None] * b
+        # the face rule on [-1,1] is scaled to the reference edge by the physical
+        # edge length / 2 in the caller
+        return pts, self.face_w
+
+
+def make_ref(cell: int, p: int, space: int):
+    """cell: 1 segment, 2 triangle, 3 quadrilateral; space: 0 CG, 1 DG."""
+    if cell == 1:
+        return RefSeg(p, "lobatto" if space == 0 else "gauss")
+    if cell == 3:
+        return RefQuad(p, "lobatto" if space == 0 else "gauss")
+    if cell == 2:
+        return RefTri(p)
+    raise ValueError(cell)

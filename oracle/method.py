@@ -1,0 +1,435 @@
+"""The cell-vertex WENO stabilised scheme, step by step, in float64 (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Every function follows
+the paper's definitions in its order and notation:
+
+* Hermite data D^k u_h^{e'}(x_i), 1 <= |k| <= p, of each cell at each of its
+  vertices: the Taylor expansion eq. (taylorsol), Sec. 3.2;
+* vertex smoothness indicators beta_{e'}^i = ||u_h^{e'}||_{x_i}^q with the
+  pointwise semi-norm eq. (pointsnorm), Jiang-Shu weights with equal linear
+  weights, eps = 1e-6, r = 2, and the vertex candidate eq. (taylorcand);
+* cell candidates u_{h,l}^e (the vertex Taylor polynomials), their element
+  semi-norms eq. (snorm), the nonlinear weights with linear weights 1e-3 for
+  the vertex candidates and 1 - v_e 1e-3 for the cell candidate, the
+  reconstruction eq. (finalweno) and the sensor eq. (gamma), Sec. 2.2 / 3.2;
+* low-order viscosity nu_e = lambda_e h_e / (2p), eq. (lostab);
+* the shock-capturing quadrature weights alpha_q, eqs. (dissrateorig) to
+  (alpha_prelim), used only where gamma_e < C_gamma (Sec. 5);
+* the stabilised residual of eq. (stabform) / (sdstab) with the DG form
+  (P_h = identity on gradients, so s^H = 0) or the simplified CG form
+  nu_e (grad v, grad u - gamma_e P_h grad u), and LLF / HLL interface fluxes;
+* the mass matrix solve and the three-stage SSP Runge-Kutta method.
+
+Readings of points the paper leaves open (all listed in the design doc):
+q = 1 for every exponent, lambda_e = max of the wave speed over the volume
+quadrature points, h_e = diam(K_e) of the cell whose polynomial is measured,
+gamma_e = 1 when ||u_h^e||_e = 0, alpha_q = 1 when either sum in eq. (alphaq)
+is not positive, P_h for CG = nodal averaging of the broken gradient, exact
+element mass for DG and the consistent global mass for CG.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sps
+import scipy.sparse.linalg as spla
+
+from synth import Params, ADVECT_CONST, ADVECT_ROT, BURGERS, KPP, EULER
+from .geometry import physical_derivatives, map_jacobian, map_points, basis_gradients
+
+
+# ---------------------------------------------------------------------------
+# semi-norms
+# ---------------------------------------------------------------------------
+def _orders(sp):
+    return np.array([sum(k) for k in sp.ks], dtype=np.float64)
+
+
+def pointwise_seminorm(sp, D, h):
+    """eq. (pointsnorm): (sum_k h^{2|k|} |D^k v(x)|^2)^{1/2}; D [..., n_k], h broadcastable."""
+    w = h[..., None] ** (2.0 * _orders(sp))
+    return np.sqrt((w * D * D).sum(-1))
+
+
+def element_seminorm_sq(sp, D, W):
+    """eq. (snorm) squared: sum_k h_e^{2|k|-d} int_K |D^k v|^2, with D [E, nq, n_k]
+    sampled at the cell's semi-norm rule and W [E, nq] its physical weights."""
+    d = sp.ref.dim
+    w = sp.h[:, None] ** (2.0 * _orders(sp) - d)          # [E, n_k]
+    return np.einsum("eq,eqk,ek->e", W, D * D, w)
+
+
+# ---------------------------------------------------------------------------
+# vertex stage (Sec. 3.2)
+# ---------------------------------------------------------------------------
+def hermite_at_vertices(sp, s):
+    """H[E, v_e, n_k] = D^k s^e(x_i) at each local vertex (eq. taylorsol)."""
+    D = physical_derivatives(sp.ref, sp.cell, sp.X, s, sp.ref.vertices, sp.ks)
+    return np.stack([D[k] for k in sp.ks], axis=-1)
+
+
+def vertex_candidates(sp, s, prm: Params, return_weights: bool = False):
+    """Vertex HWENO candidate data c_i[k] = sum_{e in C(x_i)} omega_e^i D^k s^e(x_i) (eq. taylorcand)."""
+    H = hermite_at_vertices(sp, s)
+    beta = pointwise_seminorm(sp, H, sp.h[:, None]) ** prm.q_beta       # [E, v_e]
+    wt = (prm.eps_vertex + beta) ** (-prm.r)
+    pc, plv, ptr = sp.patch_cell, sp.patch_lv, sp.patch_ptr
+    w_ent = wt[pc, plv]
+    row = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))
+    tot = np.zeros(len(ptr) - 1)
+    np.add.at(tot, row, w_ent)
+    omega = w_ent / tot[row]
+    c = np.zeros((len(ptr) - 1, len(sp.ks)))
+    np.add.at(c, row, omega[:, None] * H[pc, plv])
+    if return_weights:
+        return c, omega, H, beta
+    return c
+
+
+# ---------------------------------------------------------------------------
+# cell stage (Sec. 3.2, eq. finalweno, eq. gamma)
+# ---------------------------------------------------------------------------
+def taylor_derivatives(sp, coef, x, x0):
+    """D^m of s(x) = sum_{k in ks} coef[k] (x - x0)^k / k! at points x, for every m in ks.
+
+    coef [E, n_k], x [E, nq, d], x0 [E, d]; returns [E, nq, n_k].
+    """
+    dx = x - x0[:, None, :]
+    out = np.zeros(x.shape[:2] + (len(sp.ks),))
+    for im, m in enumerate(sp.ks):
+        for ik, k in enumerate(sp.ks):
+            if any(kk < mm for kk, mm in zip(k, m)):
+                continue
+            term = coef[:, ik][:, None] * np.ones(x.shape[:2])
+            for a in range(len(k)):
+                e = k[a] - m[a]
+                term = term * dx[:, :, a] ** e / math.factorial(e)
+            out[:, :, im] += term
+    return out
+
+
+def cell_sensor(sp, s, c, prm: Params, return_parts: bool = False):
+    """gamma_e of eq. (gamma) from the cell-vertex WENO reconstruction u_h^{e,*}."""
+    ref = sp.ref
+    pts = ref.norm_pts
+    J, _ = map_jacobian(sp.cell, sp.X, pts)
+    W = ref.norm_w[None, :] * np.abs(np.linalg.det(J))
+    xq = map_points(sp.cell, sp.X, pts)
+    Du = physical_derivatives(ref, sp.cell, sp.X, s, pts, sp.ks)
+    U = np.stack([Du[k] for k in sp.ks], axis=-1)              # [E, nq, n_k]
+    ve = sp.mesh.cell_vertices.shape[1]
+    S = []
+    for l in range(ve):
+        ci = c[sp.mesh.cell_vertices[:, l]]
+        S.append(taylor_derivatives(sp, ci, xq, sp.X[:, l]))
+    n0 = np.sqrt(element_seminorm_sq(sp, U, W))
+    betas = [n0 ** prm.q_beta] + [np.sqrt(element_seminorm_sq(sp, Sl, W)) ** prm.q_beta for Sl in S]
+    lin = [1.0 - ve * prm.lin_w_vertex] + [prm.lin_w_vertex] * ve
+    wt = np.stack([g / (prm.eps_cell + b) ** prm.r for g, b in zip(lin, betas)], axis=1)
+    omega = wt / wt.sum(axis=1, keepdims=True)                 # [E, v_e + 1]
+    diff = np.zeros_like(U)
+    for l in range(ve):
+        diff += omega[:, l + 1][:, None, None] * (U - S[l])
+    d = np.sqrt(element_seminorm_sq(sp, diff, W))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(n0 > 0, d / np.where(n0 > 0, n0, 1.0), 0.0)
+    gamma = np.where(n0 > 0, 1.0 - np.minimum(1.0, ratio) ** prm.q_sensor, 1.0)
+    if return_parts:
+        return gamma, dict(n=n0, d=d, omega=omega, betas=np.stack(betas, 1))
+    return gamma
+
+
+# ---------------------------------------------------------------------------
+# shock-capturing quadrature (Sec. 4)
+# ---------------------------------------------------------------------------
+def sc_weights(sp, s, gamma, prm: Params, pg=None, return_parts: bool = False):
+    """alpha_q of eq. (alphaq) at the volume quadrature points; [E, nq].
+
+    pg: CG only, (P_h grad s)(x_q) [E, nq, d].
+    """
+    ref = sp.ref
+    pts = ref.vol_pts
+    J, _ = map_jacobian(sp.cell, sp.X, pts)
+    W = ref.vol_w[None, :] * np.abs(np.linalg.det(J))
+    Du = physical_derivatives(ref, sp.cell, sp.X, s, pts, sp.ks)
+    D = np.stack([Du[k] for k in sp.ks], axis=-1)
+    atil = pointwise_seminorm(sp, D, sp.h[:, None])            # eq. (alpha_prelim), R8
+    d = ref.dim
+    grad = D[:, :, :d]                                          # first-order multi-indices come first
+    g2 = (grad * grad).sum(-1)
+    if sp.kind == 1:
+        f = (1.0 - gamma)[:, None] * g2
+    else:
+        f = g2 - gamma[:, None] * (grad * pg).sum(-1)
+    S = (W * f).sum(1)
+    T = (W * atil * f).sum(1)
+    active = (prm.sc_on != 0) & (gamma < prm.c_gamma) & (S > 0) & (T > 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        alpha = np.where(active[:, None], atil * (S / np.where(T > 0, T, 1.0))[:, None], 1.0)
+    if return_parts:
+        return alpha, dict(f=f, W=W, atil=atil, active=active)
+    return alpha
+
+
+# ---------------------------------------------------------------------------
+# fluxes
+# ---------------------------------------------------------------------------
+def flux(prm: Params, U, x):
+    """Physical flux f(U) [n_var, ..., d] at points x [..., d]."""
+    d = x.shape[-1]
+    if prm.flux == ADVECT_CONST:
+        v = np.array(prm.flux_param[:d])
+        return U[..., None] * v
+    if prm.flux == ADVECT_ROT:
+        cx, cy, om = prm.flux_param[0], prm.flux_param[1], prm.flux_param[2]
+        v = np.stack([om * (cy - x[..., 1]), om * (x[..., 0] - cx)], axis=-1)
+        return U[..., None] * v[None]
+    if prm.flux == BURGERS:
+        b = np.array(prm.flux_param[:d])
+        return 0.5 * U[..., None] ** 2 * b
+    if prm.flux == KPP:
+        return np.stack([np.sin(U), np.cos(U)], axis=-1)
+    if prm.flux == EULER:
+        g = prm.flux_param[0]
+        rho, mx, my, En = U
+        vx, vy = mx / rho, my / rho
+        p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy))
+        Fx = np.stack([mx, mx * vx + p, my * vx, (En + p) * vx])
+        Fy = np.stack([my, mx * vy, my * vy + p, (En + p) * vy])
+        return np.stack([Fx, Fy], axis=-1)
+    raise ValueError(prm.flux)
+
+
+def wave_speed(prm: Params, U, x):
+    """Local maximum wave speed |f'(u)| (systems: |v| + c) at points; shape of U[0]."""
+    d = x.shape[-1]
+    if prm.flux == ADVECT_CONST:
+        return np.full(U.shape[1:], float(np.linalg.norm(prm.flux_param[:d])))
+    if prm.flux == ADVECT_ROT:
+        cx, cy, om = prm.flux_param[0], prm.flux_param[1], prm.flux_param[2]
+        return abs(om) * np.hypot(cy - x[..., 1], x[..., 0] - cx)
+    if prm.flux == BURGERS:
+        return np.abs(U[0]) * float(np.linalg.norm(prm.flux_param[:d]))
+    if prm.flux == KPP:
+        return np.ones(U.shape[1:])
+    if prm.flux == EULER:
+        g = prm.flux_param[0]
+        rho, mx, my, En = U
+        vx, vy = mx / rho, my / rho
+        p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy))
+        c = np.sqrt(np.maximum(g * p / rho, 0.0))
+        return np.hypot(vx, vy) + c
+    raise ValueError(prm.flux)
+
+
+def numerical_flux(prm: Params, Um, Up, n, x):
+    """Interface flux f*(U-, U+, n) [n_var, ...]: local Lax-Friedrichs (scalar)
+    or HLL with Davis wave-speed estimates (Euler)."""
+    Fm = (flux(prm, Um, x) * n).sum(-1)
+    Fp = (flux(prm, Up, x) * n).sum(-1)
+    if prm.flux == EULER:
+        g = prm.flux_param[0]
+
+        def vn_c(U):
+            rho, mx, my, En = U
+            vx, vy = mx / rho, my / rho
+            p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy))
+            return vx * n[..., 0] + vy * n[..., 1], np.sqrt(np.maximum(g * p / rho, 0.0))
+
+        vm, cm = vn_c(Um)
+        vp, cp = vn_c(Up)
+        SL = np.minimum(vm - cm, vp - cp)
+        SR = np.maximum(vm + cm, vp + cp)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            mid = (SR * Fm - SL * Fp + SL * SR * (Up - Um)) / (SR - SL)
+        return np.where(SL >= 0, Fm, np.where(SR <= 0, Fp, mid))
+    if prm.lambda_global > 0:
+        lam = prm.lambda_global
+    else:
+        d = x.shape[-1]
+        if prm.flux == ADVECT_CONST:
+            lam = np.abs((np.array(prm.flux_param[:d]) * n).sum(-1))
+        elif prm.flux == ADVECT_ROT:
+            cx, cy, om = prm.flux_param[0], prm.flux_param[1], prm.flux_param[2]
+            v = np.stack([om * (cy - x[..., 1]), om * (x[..., 0] - cx)], axis=-1)
+            lam = np.abs((v * n).sum(-1))
+        elif prm.flux == BURGERS:
+            bn = np.abs((np.array(prm.flux_param[:d]) * n).sum(-1))
+            lam = np.maximum(np.abs(Um[0]), np.abs(Up[0])) * bn
+        elif prm.flux == KPP:
+            def fpn(u):
+                return np.abs(np.cos(u) * n[..., 0] - np.sin(u) * n[..., 1])
+            lam = np.maximum(fpn(Um[0]), fpn(Up[0]))
+        else:
+            raise ValueError(prm.flux)
+    return 0.5 * (Fm + Fp) - 0.5 * lam * (Up - Um)
+
+
+# ---------------------------------------------------------------------------
+# residual (eq. stabform / sdstab)
+# ---------------------------------------------------------------------------
+def projected_gradient(sp, Uc):
+    """CG: nodal values of P_h grad U (average over the cells sharing each node) [n_var, n_dof, d]."""
+    ref = sp.ref
+    gphi, _ = basis_gradients(ref, sp.cell, sp.X, ref.nodes)    # [E, nloc(pts), nloc, d]
+    g = np.einsum("vei,ejid->vejd", Uc, gphi)
+    nv, d = Uc.shape[0], ref.dim
+    acc = np.zeros((nv, sp.n_dof, d))
+    cnt = np.bincount(sp.cell_dof.ravel(), minlength=sp.n_dof).astype(np.float64)
+    for v in range(nv):
+        for a in range(d):
+            np.add.at(acc[v, :, a], sp.cell_dof.ravel(), g[v, :, :, a].ravel())
+    return acc / cnt[None, :, None]
+
+
+def sensor_gamma(sp, s, prm: Params):
+    if prm.sensor == 2:
+        return np.full(sp.E, prm.fixed_gamma)
+    c = vertex_candidates(sp, s, prm)
+    return cell_sensor(sp, s, c, prm)
+
+
+def residual(sp, U, prm: Params, gamma=None, return_parts: bool = False):
+    """R with M dU/dt = -R (eq. sdstab): volume Galerkin term, stabilisation with
+    the shock-capturing weights, DG interface terms, CG assembly.
+
+    Returns R in the state layout ([n_var, E, n_loc] flattened for DG,
+    [n_var, n_dof] for CG).
+    """
+    ref = sp.ref
+    Uc = sp.to_cells(U)                           # [nv, E, nloc]
+    nv = Uc.shape[0]
+    s = Uc[0]
+    if gamma is None:
+        gamma = sensor_gamma(sp, s, prm)
+    pts = ref.vol_pts
+    gphi, detJ = basis_gradients(ref, sp.cell, sp.X, pts)    # [E, nq, nloc, d]
+    W = ref.vol_w[None, :] * detJ
+    phi = ref.deriv(pts, (0,) * ref.dim)                        # [nq, nloc]
+    Uq = np.einsum("vej,qj->veq", Uc, phi)
+    gU = np.einsum("vej,eqjd->veqd", Uc, gphi)
+    xq = map_points(sp.cell, sp.X, pts)
+    F = flux(prm, Uq, xq)                                       # [nv, E, nq, d]
+    if prm.lambda_global > 0:
+        lam = np.full(sp.E, prm.lambda_global)
+    else:
+        lam = wave_speed(prm, Uq, xq).max(axis=1)
+    nu = lam * sp.h / (2.0 * sp.p)
+    pg = None
+    if sp.kind == 0:
+        PGn = projected_gradient(sp, Uc)                        # [nv, ndof, d]
+        PGq = np.einsum("qj,vejd->veqd", phi, PGn[:, sp.cell_dof])
+        pg = PGq[0]
+        G = gU - gamma[None, :, None, None] * PGq
+    else:
+        G = (1.0 - gamma)[None, :, None, None] * gU
+    alpha = sc_weights(sp, s, gamma, prm, pg)
+    r = (-np.einsum("eq,eqjd,veqd->vej", W, gphi, F)
+         + np.einsum("e,eq,eq,eqjd,veqd->vej", nu, W, alpha, gphi, G))
+    if sp.kind == 1:
+        r = r + face_terms(sp, Uc, prm)
+        R = r.reshape(nv, -1)
+    else:
+        R = np.zeros((nv, sp.n_dof))
+        for v in range(nv):
+            np.add.at(R[v], sp.cell_dof.ravel(), r[v].ravel())
+    if return_parts:
+        return R.ravel(), dict(gamma=gamma, alpha=alpha, nu=nu, lam=lam, r_cell=r)
+    return R.ravel()
+
+
+def face_geometry(sp, f):
+    """Outward unit normal [E, d] and face Jacobian (length / 2) [E] of face f."""
+    X = sp.X
+    if sp.cell == 1:
+        n = np.full((sp.E, 1), -1.0 if f == 0 else 1.0)
+        return n, np.ones(sp.E)
+    nvx = X.shape[1]
+    t = X[:, (f + 1) % nvx] - X[:, f]
+    L = np.hypot(t[:, 0], t[:, 1])
+    n = np.stack([t[:, 1], -t[:, 0]], axis=1) / L[:, None]
+    return n, 0.5 * L
+
+
+def face_terms(sp, Uc, prm: Params):
+    ref = sp.ref
+    nv, E, nloc = Uc.shape
+    out = np.zeros_like(Uc)
+    if (sp.nbr < 0).any():
+        raise NotImplementedError("DG residual requires a mesh without boundary faces")
+    for f in range(ref.n_faces):
+        pts, wf = ref.face_points(f)
+        phif = ref.deriv(pts, (0,) * ref.dim)                    # [ng, nloc]
+        Um = np.einsum("vej,gj->veg", Uc, phif)
+        en, fn = sp.nbr[:, f], sp.nbr_face[:, f]
+        Up = np.zeros_like(Um)
+        for f2 in range(ref.n_faces):
+            sel = fn == f2
+            if not sel.any():
+                continue
+            p2, _ = ref.face_points(f2)
+            phi2 = ref.deriv(p2[::-1], (0,) * ref.dim)            # reversed traversal
+            Up[:, sel] = np.einsum("vej,gj->veg", Uc[:, en[sel]], phi2)
+        n, Jf = face_geometry(sp, f)
+        xf = map_points(sp.cell, sp.X, pts)
+        ng = len(wf)
+        nb = np.broadcast_to(n[:, None, :], (E, ng, n.shape[1]))
+        Fs = numerical_flux(prm, Um, Up, nb, xf)                   # [nv, E, ng]
+        out += np.einsum("g,e,gj,veg->vej", wf, Jf, phif, Fs)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# mass matrix and time stepping
+# ---------------------------------------------------------------------------
+def _cell_mass(sp):
+    ref = sp.ref
+    pts = ref.vol_pts
+    J, _ = map_jacobian(sp.cell, sp.X, pts)
+    W = ref.vol_w[None, :] * np.abs(np.linalg.det(J))
+    phi = ref.deriv(pts, (0,) * ref.dim)
+    return np.einsum("eq,qi,qj->eij", W, phi, phi)
+
+
+def apply_mass_inverse(sp, R):
+    """Solve M L = R (DG: exact element mass per cell; CG: consistent global mass)."""
+    Me = _cell_mass(sp)
+    nv = sp.n_var
+    if sp.kind == 1:
+        r = R.reshape(nv, sp.E, -1)
+        out = np.stack([np.linalg.solve(Me, r[v][..., None])[..., 0] for v in range(nv)])
+        return out.ravel()
+    cd = sp.cell_dof
+    rows = np.repeat(cd, cd.shape[1], axis=1).ravel()
+    cols = np.tile(cd, (1, cd.shape[1])).ravel()
+    M = sps.csr_matrix((Me.ravel(), (rows, cols)), shape=(sp.n_dof, sp.n_dof))
+    r = R.reshape(nv, sp.n_dof)
+    solve = spla.factorized(M.tocsc())
+    return np.concatenate([solve(r[v]) for v in range(nv)])
+
+
+def time_derivative(sp, U, prm: Params):
+    return -apply_mass_inverse(sp, residual(sp, U, prm))
+
+
+def rk3_step(sp, U, dt: float, prm: Params):
+    """Three-stage SSP Runge-Kutta step (Shu-Osher form)."""
+    U1 = U + dt * time_derivative(sp, U, prm)
+    U2 = 0.75 * U + 0.25 * (U1 + dt * time_derivative(sp, U1, prm))
+    return U / 3.0 + 2.0 / 3.0 * (U2 + dt * time_derivative(sp, U2, prm))
+
+
+def nodal_interpolate(sp, funcs):
+    """State vector from the initial data sampled at the nodes (DG) or DOF
+    positions (CG; first occurrence in (cell, local) order).  funcs: one
+    callable per variable taking physical coordinates [..., d]."""
+    xn = sp.node_coords()                       # [E, nloc, d]
+    vals = np.stack([f(xn) for f in funcs])     # [nv, E, nloc]
+    if sp.kind == 1:
+        return vals.reshape(len(funcs), -1).ravel()
+    flat = sp.cell_dof.ravel()
+    _, first = np.unique(flat, return_index=True)
+    out = np.empty((len(funcs), sp.n_dof))
+    out[:, flat[first]] = vals.reshape(len(funcs), -1)[:, first]
+    return out.ravel()
