@@ -70,13 +70,16 @@ def ref_multi(dim: int, seq):
 
 
 def physical_derivatives(ref, cell: int, X: np.ndarray, u: np.ndarray, pts: np.ndarray, ks):
-    """D^k u at reference points for every multi-index k in ks.
+    """D^k u (|k| >= 1) at reference points for every multi-index k in ks.
 
     u: [E, n_loc] nodal values; returns dict k -> [E, n].
     """
     dim = ref.dim
     J, H = map_jacobian(cell, X, pts)
     A = np.linalg.inv(J)                         # A_ba = dxi_b / dx_a
+    # derivatives of order >= 1 annihilate constants: take them of the data
+    # relative to its first nodal value, so that constant data gives exactly 0
+    u = u - u[:, :1]
     cache = {}
 
     def refd(m):

@@ -290,7 +290,7 @@ def sensor_gamma(sp, s, prm: Params):
     return cell_sensor(sp, s, c, prm)
 
 
-def residual(sp, U, prm: Params, gamma=None, return_parts: bool = False):
+def residual(sp, U, prm: Params, gamma=None, return_parts: bool = False, allow_boundary: bool = False):
     """R with M dU/dt = -R (eq. sdstab): volume Galerkin term, stabilisation with
     the shock-capturing weights, DG interface terms, CG assembly.
 
@@ -328,7 +328,7 @@ def residual(sp, U, prm: Params, gamma=None, return_parts: bool = False):
     r = (-np.einsum("eq,eqjd,veqd->vej", W, gphi, F)
          + np.einsum("e,eq,eq,eqjd,veqd->vej", nu, W, alpha, gphi, G))
     if sp.kind == 1:
-        r = r + face_terms(sp, Uc, prm)
+        r = r + face_terms(sp, Uc, prm, allow_boundary)
         R = r.reshape(nv, -1)
     else:
         R = np.zeros((nv, sp.n_dof))
@@ -352,18 +352,21 @@ def face_geometry(sp, f):
     return n, 0.5 * L
 
 
-def face_terms(sp, Uc, prm: Params):
+def face_terms(sp, Uc, prm: Params, allow_boundary: bool = False):
+    """DG interface terms.  allow_boundary=True drops boundary faces; it exists
+    only to evaluate the residual of interior cells of a sub-mesh cut out of a
+    larger periodic mesh (those cells never touch a boundary face)."""
     ref = sp.ref
     nv, E, nloc = Uc.shape
     out = np.zeros_like(Uc)
-    if (sp.nbr < 0).any():
+    if (sp.nbr < 0).any() and not allow_boundary:
         raise NotImplementedError("DG residual requires a mesh without boundary faces")
     for f in range(ref.n_faces):
         pts, wf = ref.face_points(f)
         phif = ref.deriv(pts, (0,) * ref.dim)                    # [ng, nloc]
         Um = np.einsum("vej,gj->veg", Uc, phif)
         en, fn = sp.nbr[:, f], sp.nbr_face[:, f]
-        Up = np.zeros_like(Um)
+        Up = Um.copy()                                             # boundary faces: zero jump, dropped below
         for f2 in range(ref.n_faces):
             sel = fn == f2
             if not sel.any():
@@ -376,6 +379,7 @@ def face_terms(sp, Uc, prm: Params):
         ng = len(wf)
         nb = np.broadcast_to(n[:, None, :], (E, ng, n.shape[1]))
         Fs = numerical_flux(prm, Um, Up, nb, xf)                   # [nv, E, ng]
+        Fs = np.where((en >= 0)[None, :, None], Fs, 0.0)
         out += np.einsum("g,e,gj,veg->vej", wf, Jf, phif, Fs)
     return out
 
