@@ -1,0 +1,219 @@
+"""Benchmark of the stabilised-residual hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (default): 2D Euler (gas gamma 1.4), DG Q3 on a periodic 1024 x 1024
+grid of unit-square cells (1,048,576 cells, 16,777,216 nodes, 67,108,864
+DOFs), float32 state, plain cell-vertex HWENO sensor with shock-capturing
+quadrature.  Input: the seeded four-quadrant data (rho, p, velocities drawn
+from the stated ranges) with its quadrant interfaces smoothed over about half
+a cell, so that the sensor and the shock-capturing weights are active along
+the interfaces.  Everything is resident in HBM before timing starts.
+
+One step = one SSP-RK3 time step = three stages, each stage = the vertex
+HWENO pass (vertex candidates) plus the fused cell pass (sensor, viscosity,
+shock-capturing weights, volume and interface terms, mass inverse, stage
+update).  value = stabilised-residual DOF updates per second
+= 3 * n_dof * n_var * K / (time of K steps).
+
+The roofline object describes the dominant kernel (the fused cell pass,
+dgq_eval_kernel): its launches are bracketed by HIP events on the stream they
+run on, inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SMOOTH_K = 400.0      # sharpness of the quadrant interfaces at n = 1024 (~0.4 cell wide)
+
+
+def euler_config4_state(n: int, ref_nodes: np.ndarray, smooth_k: float):
+    import synth
+    h = 1.0 / n
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    xc = (ii.ravel() + 0.5) * h
+    yc = (jj.ravel() + 0.5) * h
+    X = xc[:, None] + 0.5 * h * ref_nodes[None, :, 0]
+    Y = yc[:, None] + 0.5 * h * ref_nodes[None, :, 1]
+    return np.asarray(synth.euler_state_config4(X, Y, smooth_k=smooth_k), np.float32)
+
+
+def gauss_nodes_2d(p: int):
+    """Reference node coordinates of the Gauss-point Lagrange basis (input sampling only)."""
+    x, _ = np.polynomial.legendre.leggauss(p + 1)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def cpu_baseline(target_seconds: float = 15.0):
+    """The float64 oracle timed on a bounded sample of the same workload: the
+    stabilised residual on periodic n x n sub-problems of the same recipe."""
+    import synth
+    from oracle import build_space, nodal_interpolate, residual
+    prm = synth.Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0))
+    n = 64
+    mesh = synth.quad_mesh(n, n)
+    sp = build_space(mesh, 3, 1, 4)
+    U = nodal_interpolate(sp, [(lambda c: (lambda x: synth.euler_state_config4(
+        x[..., 0], x[..., 1], smooth_k=SMOOTH_K * n / 1024)[c]))(c) for c in range(4)])
+    dofs = U.size
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        residual(sp, U, prm)
+        reps += 1
+        if time.perf_counter() - t0 > target_seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": dofs * reps / dt, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} float64 oracle residual evaluations of a periodic {n}x{n} DG Q3 Euler "
+                      f"mesh ({dofs} DOFs) with the same state recipe, single process, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024, help="cells per direction")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one 256 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the hot path is benchmarked on one MI355X; "
+              "multi-GPU sharding is a design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2601_16911_amd import cvw
+
+    torch.cuda.set_device(0)
+    n, p, nv = args.n, 3, 4
+    mesh = synth.quad_mesh(n, n)
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    prm = synth.Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0))
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, 1)
+    U_h = euler_config4_state(n, gauss_nodes_2d(p), SMOOTH_K * n / 1024)
+    U = torch.from_numpy(U_h.reshape(-1)).cuda()
+    E = mesh.n_cells
+    nloc = (p + 1) ** 2
+    nk = (p + 1) * (p + 2) // 2 - 1
+    ndof = E * nloc
+    U1 = torch.empty_like(U)
+    U2 = torch.empty_like(U)
+    cand = torch.empty((mesh.n_vertices, nk), dtype=torch.float32, device="cuda")
+    # fixed step inside the SSP-RK3 / DG stability region: CFL 0.1 / (2p + 1)
+    rho, mx, my, En = (U_h[c].astype(np.float64) for c in range(4))
+    pres = 0.4 * (En - 0.5 * (mx * mx + my * my) / rho)
+    lam_max = float((np.hypot(mx, my) / rho + np.sqrt(1.4 * pres / rho)).max())
+    dt = 0.1 * (1.0 / n) / ((2 * p + 1) * lam_max)
+    stream = torch.cuda.current_stream()
+
+    ev = []
+
+    def rk_step(record: bool):
+        stages = ((U, None, U1, 0.0, 1.0), (U1, U, U2, 0.75, 0.25), (U2, U, U, 1.0 / 3.0, 2.0 / 3.0))
+        for (us, un, uo, a0, b0) in stages:
+            cvw.vertex_candidates(gm, cp, us, cand, ws)
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
+                e1.record(stream)
+                ev.append((e0, e1))
+            else:
+                cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
+
+    for _ in range(args.warmup):
+        rk_step(False)
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        rk_step(True)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    t_total = t_start.elapsed_time(t_end) / 1e3
+    eval_ms = [a.elapsed_time(b) for a, b in ev]
+    flags = cvw.poll_status(gm, ws)
+
+    # residual-only timing (vertex pass + fused cell pass writing R), same state
+    R = torch.empty_like(U)
+    wsr = cvw.alloc_workspace(gm, cp, 0)
+    for _ in range(3):
+        cvw.residual(gm, cp, U, R, None, wsr)
+    torch.cuda.synchronize()
+    r0 = torch.cuda.Event(enable_timing=True)
+    r1 = torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    nres = 10
+    for _ in range(nres):
+        cvw.residual(gm, cp, U, R, None, wsr)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    t_res = r0.elapsed_time(r1) / 1e3 / nres
+
+    # algorithmic bytes of one fused cell-pass launch (stage mode, averaged over
+    # the three stages): read u_stage, write u_out, read u_n in stages 2 and 3,
+    # read the vertex candidates once per vertex
+    state_bytes = nv * ndof * 4
+    alg_bytes = state_bytes * (1 + 1 + 2.0 / 3.0) + mesh.n_vertices * nk * 4
+    t_eval = float(np.mean(eval_ms)) / 1e3
+    achieved = alg_bytes / t_eval / 1e9
+    traffic = None
+    tr_path = os.path.join(ROOT, "profiles", "traffic_dgq_eval_config4.json")
+    if os.path.exists(tr_path):
+        try:
+            with open(tr_path) as f:
+                tr = json.load(f)
+            traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    value = 3.0 * ndof * nv * args.steps / t_total
+    out = {
+        "metric": "stabilized-residual DOF updates/s", "value": value, "unit": "DOF-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_total / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2D Euler DG Q3, periodic {n}x{n} quads ({E} cells, {ndof * nv} DOFs), "
+                               "four-quadrant data with interfaces smoothed over ~2 cells, plain CV-WENO sensor + SC "
+                               "quadrature, SSP-RK3", "cells": E, "degree": p, "n_var": nv,
+                   "dofs": ndof * nv, "step": "one SSP-RK3 step = 3 x (vertex pass + fused cell pass)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "dgq_eval_kernel<3, EULER> (fused cell pass, stage mode)",
+                     "avg_launch_ms": t_eval * 1e3, "alg_bytes_per_launch": alg_bytes},
+        "residual_only": {"value": ndof * nv / t_res, "unit": "DOF-updates/s", "ms": t_res * 1e3},
+        "status_flags": flags,
+        "wall_s_timed": wall,
+    }
+    if args.copy_calib:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = a.numel() * 4
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

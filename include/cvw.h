@@ -1,0 +1,210 @@
+/*
+ * cvw.h -- C ABI of the cell-vertex WENO stabilised residual library (libcvw.so).
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the per-stage
+ * residual of the dissipation-based WENO stabilisation of continuous (CG) and
+ * discontinuous (DG) Galerkin discretisations of hyperbolic conservation laws
+ * with cell-vertex HWENO smoothness sensors and shock-capturing quadrature
+ * (Vedral & Kuzmin, "Cell-vertex WENO schemes with shock-capturing quadrature
+ * for high-order finite element discretizations of hyperbolic problems").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a cvw_status; no exception crosses the ABI.  After a
+ *   non-zero status cvw_last_error() describes the failure (thread-local text,
+ *   valid until the next call on the same thread).
+ * - Host pointers are read during the call only.  Device pointers (state,
+ *   residual, sensor, workspace) are owned by the caller; they must be
+ *   allocations on the current HIP device, 256-byte aligned and not aliased
+ *   unless stated.  The library never allocates in the evaluation calls; only
+ *   cvw_mesh_build allocates (the mesh's device arrays, freed by
+ *   cvw_mesh_destroy).
+ * - `stream` is a hipStream_t (NULL = default stream).  Evaluation calls only
+ *   enqueue work on it and return; argument errors are detected on the host
+ *   before anything is enqueued.  Numerical trouble detected on the device
+ *   (non-finite residual, non-positive density or pressure) sets bits in the
+ *   workspace status word, read with cvw_poll_status.
+ * - State layout is component-major (structure of arrays):
+ *     DG: U[v][e][j], j = local node (quads: a + (p+1) b, x fastest),
+ *     CG: U[v][I],    I = global DOF in the canonical numbering: vertex DOFs by
+ *         vertex id, then edge DOFs (edges sorted by (min, max) vertex id,
+ *         oriented min -> max), then cell-interior DOFs by cell id.
+ *   Single (CVW_F32) or double (CVW_F64) precision as cvw_params.dtype says.
+ * - Results are deterministic: no floating-point atomics are used; every
+ *   reduction runs in a fixed order.
+ */
+#ifndef CVW_H
+#define CVW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CVW_ABI_VERSION 1
+
+typedef enum {
+  CVW_OK = 0,
+  CVW_EINVAL = 1,          /* malformed argument (null pointer, bad size, bad mesh) */
+  CVW_ENOMEM = 2,          /* device allocation failed (cvw_mesh_build only)        */
+  CVW_EDEVICE = 3,         /* a HIP runtime call failed                              */
+  CVW_EUNSUPPORTED = 4,    /* valid request outside what the GPU path implements    */
+  CVW_ENUMERIC = 5         /* cvw_poll_status: device flagged a numerical problem   */
+} cvw_status;
+
+typedef enum { CVW_SEG = 1, CVW_TRI = 2, CVW_QUAD = 3 } cvw_cell;
+typedef enum { CVW_CG = 0, CVW_DG = 1 } cvw_space;
+typedef enum {
+  CVW_ADVECT_CONST = 0,    /* f = v u, v = (flux_param[0], flux_param[1])                    */
+  CVW_ADVECT_ROT = 1,      /* f = v(x) u, v = w (cy - y, x - cx), (cx, cy, w) = flux_param[0..2] */
+  CVW_BURGERS = 2,         /* f = u^2 / 2 (flux_param[0], flux_param[1])                     */
+  CVW_KPP = 3,             /* f = (sin u, cos u)                                             */
+  CVW_EULER = 4            /* 2D Euler, 4 conserved variables, gas gamma = flux_param[0]     */
+} cvw_flux;
+typedef enum { CVW_F32 = 0, CVW_F64 = 1 } cvw_dtype;
+typedef enum { CVW_SENSOR_PLAIN = 0, CVW_SENSOR_LEARNED = 1, CVW_SENSOR_FIXED = 2 } cvw_sensor_kind;
+
+/* Mesh description (host memory, read during cvw_mesh_build only).
+ * A conforming mesh of segments, triangles or quadrilaterals (Sec. 2.1 of the
+ * paper).  cell_vertices holds topological vertex ids after periodic
+ * identification, counter-clockwise in 2D; cell_coords holds the *unwrapped*
+ * physical coordinates of each cell's vertices, so a cell on a periodic seam
+ * keeps its own geometric position.  Quadrilateral vertices are ordered like
+ * the reference vertices (-1,-1), (1,-1), (1,1), (-1,1). */
+typedef struct {
+  int32_t dim;               /* 1 or 2                                         */
+  int32_t cell;              /* cvw_cell                                       */
+  int32_t degree;            /* polynomial degree p >= 1                       */
+  int32_t space;             /* cvw_space                                      */
+  int64_t n_cells;
+  int64_t n_vertices;
+  const int32_t* cell_vertices;  /* [n_cells][v_e]                              */
+  const double* cell_coords;     /* [n_cells][v_e][dim]                         */
+  int32_t periodic[2];       /* informative: periodic directions               */
+} cvw_mesh_desc;
+
+/* Method parameters.  Defaults (the paper's values): eps = 1e-6 and r = 2 for
+ * both WENO stages (Sec. 3.2), q = 1 (Sec. 5), vertex-candidate linear weight
+ * 1e-3 (Sec. 3.2), shock-capturing quadrature on with cutoff C_gamma = 0.9
+ * (Sec. 5). */
+typedef struct {
+  int32_t dtype;             /* cvw_dtype of state / residual buffers            */
+  int32_t flux;              /* cvw_flux                                         */
+  double flux_param[4];
+  double eps_vertex;         /* epsilon of the vertex-stage Jiang-Shu weights    */
+  double eps_cell;           /* epsilon of the cell-stage weights                */
+  int32_t r;                 /* Jiang-Shu exponent                               */
+  int32_t sc_on;             /* shock-capturing quadrature on/off                */
+  double q_sensor;           /* exponent q of the sensor gamma_e                 */
+  double q_beta;             /* exponent q of the smoothness indicators beta     */
+  double lin_w_vertex;       /* linear weight of each vertex candidate           */
+  double c_gamma;            /* SC active only where gamma_e < c_gamma           */
+  double lambda_global;      /* > 0: global wave-speed bound used for nu_e and LLF */
+  int32_t sensor;            /* cvw_sensor_kind                                  */
+  int32_t pad0;
+  double fixed_gamma;        /* gamma_e for CVW_SENSOR_FIXED                     */
+} cvw_params;
+
+typedef struct {
+  int64_t n_cells, n_vertices, n_dof, nnz_vertex;
+  int32_t n_loc;             /* nodes per cell                                   */
+  int32_t n_k;               /* derivative multi-indices 1 <= |k| <= p           */
+  int32_t n_q;               /* volume quadrature points per cell                */
+  int32_t v_e;               /* vertices per cell                                */
+  int32_t n_faces;
+  int32_t uniform;           /* 1: congruent axis-aligned cells (structured fast path) */
+  double hx, hy;             /* cell sizes when uniform                          */
+} cvw_mesh_info;
+
+typedef struct cvw_mesh cvw_mesh;
+
+/* Export selectors for cvw_mesh_export (all int32 arrays). */
+enum {
+  CVW_EXPORT_VTX_PTR = 0,    /* [n_vertices + 1] CSR row pointer of the vertex patches */
+  CVW_EXPORT_VTX_CELL = 1,   /* [nnz] cell of each patch entry (ascending (cell, lv)) */
+  CVW_EXPORT_VTX_LV = 2,     /* [nnz] local vertex of each patch entry              */
+  CVW_EXPORT_NBR = 3,        /* DG: [n_cells][n_faces] face neighbour, -1 = boundary */
+  CVW_EXPORT_NBR_FACE = 4,   /* DG: [n_cells][n_faces] neighbour's local face        */
+  CVW_EXPORT_CELL_DOF = 5    /* CG: [n_cells][n_loc] global DOF of each local node   */
+};
+
+int cvw_abi_version(void);
+const char* cvw_last_error(void);
+
+/* Build the connectivity the method needs (Sec. 3.2: vertex patches C(x_i);
+ * face neighbours for DG interface terms; CG numbering), per-cell geometry
+ * (h_e = diam K_e, Sec. 2.1) and the reference tables, and upload them to the
+ * current device.  EINVAL for a malformed or non-conforming description,
+ * ENOMEM / EDEVICE for device failures.  *out owns device memory. */
+cvw_status cvw_mesh_build(const cvw_mesh_desc* desc, cvw_mesh** out);
+void cvw_mesh_destroy(cvw_mesh* mesh);
+cvw_status cvw_mesh_get_info(const cvw_mesh* mesh, cvw_mesh_info* info);
+/* Copy one host-side connectivity array (see CVW_EXPORT_*) into host_dst; EINVAL
+ * if bytes is not exactly its size. */
+cvw_status cvw_mesh_export(const cvw_mesh* mesh, int which, void* host_dst, size_t bytes);
+
+/* Workspace size in bytes for an operation: 0 = sensor / residual / candidates,
+ * 1 = time step.  The workspace holds the vertex candidates, the status word and
+ * (time step) the Runge-Kutta stage states; it must stay untouched between the
+ * calls of one operation and may be reused afterwards. */
+size_t cvw_workspace_bytes(const cvw_mesh* mesh, const cvw_params* prm, int op);
+
+/* Vertex stage of the cell-vertex reconstruction (Sec. 3.2, eq. taylorcand and
+ * the Jiang-Shu weights with equal linear weights): for every vertex x_i,
+ *   cand[k][i] = sum_{e in C(x_i)} omega_e^i D^k u_h^e(x_i),  1 <= |k| <= p,
+ * with omega_e^i proportional to (eps + ||u_h^e||_{x_i}^q)^{-r} (eq. pointsnorm),
+ * summed in ascending (cell, local vertex) order.  Multi-indices are ordered
+ * by |k|, then by decreasing first component.  u: state (sensor field = first
+ * variable); cand: device [n_vertices][n_k] in the state precision. */
+cvw_status cvw_vertex_candidates(const cvw_mesh* mesh, const cvw_params* prm, const void* u,
+                                 void* cand, void* ws, size_t ws_bytes, void* stream);
+
+/* Smoothness sensor gamma_e (eq. gamma, cell stage of Sec. 3.2) and the
+ * shock-capturing quadrature weights alpha_q (eqs. alphaq / alpha_prelim,
+ * applied where gamma_e < c_gamma, Sec. 5).  gamma: device [n_cells];
+ * alpha: device [n_cells][n_q] or NULL.  For systems the sensor field is the
+ * density (Sec. 5.4). */
+cvw_status cvw_sensor(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* gamma,
+                      void* alpha, void* ws, size_t ws_bytes, void* stream);
+
+/* Stabilised residual R of M dU/dt = -R (eq. stabform / sdstab): Galerkin
+ * volume term, the blended stabilisation s_h with nonlinear quadrature
+ * weights, DG interface fluxes (LLF / HLL), CG assembly.  R has the state's
+ * layout and precision and must not alias u.  gamma_out: device [n_cells] or
+ * NULL. */
+cvw_status cvw_residual(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* R,
+                        void* gamma_out, void* ws, size_t ws_bytes, void* stream);
+
+/* One stage of the SSP Runge-Kutta method in Shu-Osher form, given the vertex
+ * candidates `cand` of u_stage (from cvw_vertex_candidates):
+ *   u_out = a0 * u_n + b0 * (u_stage + dt * L(u_stage)),  L = -M^{-1} R,
+ * with the exact element mass for DG.  u_n is not read when a0 == 0; u_out may
+ * alias u_n (each entry of u_n is read only by the thread that overwrites it)
+ * but must not alias u_stage or cand. */
+cvw_status cvw_rk_stage(const cvw_mesh* mesh, const cvw_params* prm, const void* u_stage, const void* cand,
+                        const void* u_n, void* u_out, double dt, double a0, double b0, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* n_steps steps of the three-stage SSP Runge-Kutta method with fixed dt,
+ * u updated in place (Sec. 2.2 / Sec. 5).  DG: exact element mass. */
+cvw_status cvw_step(const cvw_mesh* mesh, const cvw_params* prm, void* u, double dt, int n_steps,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronises `stream`, returns the device status bits in *flags and clears
+ * them: bit 0 non-finite residual, bit 1 non-positive density or pressure.
+ * Returns CVW_ENUMERIC when any bit was set. */
+cvw_status cvw_poll_status(const cvw_mesh* mesh, void* ws, size_t ws_bytes, uint32_t* flags, void* stream);
+
+/* Per-variable integrals sum_e int_{K_e} u_h dx accumulated in float64 on the
+ * device (conservation check); writes n_var doubles to host memory and
+ * synchronises `stream`. */
+cvw_status cvw_totals(const cvw_mesh* mesh, const cvw_params* prm, const void* u, double* out_host,
+                      void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CVW_H */

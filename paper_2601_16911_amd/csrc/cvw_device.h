@@ -1,0 +1,209 @@
+// Device helpers shared by the gfx950 kernels of libcvw: cross-lane moves inside
+// 16-lane DPP rows, physical fluxes and interface fluxes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cvw_internal.h"
+
+namespace cvw {
+
+// ---------------------------------------------------------------------------
+// DPP cross-lane moves.  A cell of a tensor-product element occupies one DPP
+// row of 16 lanes, node (a, b) on lane a + 4 b of the row.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dppi(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double x) {
+  const long long v = __builtin_bit_cast(long long, x);
+  const int lo = dppi<CTRL>(static_cast<int>(v & 0xffffffffLL));
+  const int hi = dppi<CTRL>(static_cast<int>(v >> 32));
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// value of lane i of the own quad (= node (i, b) of the own row b)
+template <int I>
+__device__ __forceinline__ float qbcast(float x) {
+  return dpp<(I | (I << 2) | (I << 4) | (I << 6))>(x);
+}
+// rotation by 4 S lanes inside the 16-lane row: a value of the same column a
+// from another row; which row it came from is tracked by rotating the row index
+template <int S>
+__device__ __forceinline__ float rrot(float x) {
+  if constexpr (S == 0) return x; else return dpp<(0x120 | (4 * S))>(x);
+}
+template <int S>
+__device__ __forceinline__ int rroti(int x) {
+  if constexpr (S == 0) return x; else return dppi<(0x120 | (4 * S))>(x);
+}
+
+template <int I>
+__device__ __forceinline__ double qbcastd(double x) {
+  return dppd<(I | (I << 2) | (I << 4) | (I << 6))>(x);
+}
+template <int S>
+__device__ __forceinline__ double rrotd(double x) {
+  if constexpr (S == 0) return x; else return dppd<(0x120 | (4 * S))>(x);
+}
+
+// sums / maxima over the 16 lanes of a row (every lane receives the result)
+__device__ __forceinline__ float row_sum(float x) {
+  x += dpp<0x124>(x);
+  x += dpp<0x128>(x);
+  x += dpp<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
+  x += dpp<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+  return x;
+}
+__device__ __forceinline__ double row_sumd(double x) {
+  x += dppd<0x124>(x);
+  x += dppd<0x128>(x);
+  x += dppd<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
+  x += dppd<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+  return x;
+}
+__device__ __forceinline__ float row_max(float x) {
+  x = fmaxf(x, dpp<0x124>(x));
+  x = fmaxf(x, dpp<0x128>(x));
+  x = fmaxf(x, dpp<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x));
+  x = fmaxf(x, dpp<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x));
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Fluxes (single precision).  fp = flux parameters, lam_g = global wave-speed
+// bound (0 = local).
+// ---------------------------------------------------------------------------
+template <int FLUX> struct NVar { static constexpr int value = 1; };
+template <> struct NVar<CVW_EULER> { static constexpr int value = 4; };
+
+template <int FLUX>
+__device__ __forceinline__ void phys_flux(const MethodScalars& ms, const float* u, float x, float y,
+                                          float* fx, float* fy) {
+  if constexpr (FLUX == CVW_ADVECT_CONST) {
+    fx[0] = ms.fp[0] * u[0];
+    fy[0] = ms.fp[1] * u[0];
+  } else if constexpr (FLUX == CVW_ADVECT_ROT) {
+    const float vx = ms.fp[2] * (ms.fp[1] - y), vy = ms.fp[2] * (x - ms.fp[0]);
+    fx[0] = vx * u[0];
+    fy[0] = vy * u[0];
+  } else if constexpr (FLUX == CVW_BURGERS) {
+    const float h = 0.5f * u[0] * u[0];
+    fx[0] = ms.fp[0] * h;
+    fy[0] = ms.fp[1] * h;
+  } else if constexpr (FLUX == CVW_KPP) {
+    fx[0] = sinf(u[0]);
+    fy[0] = cosf(u[0]);
+  } else {
+    const float g = ms.fp[0];
+    const float rho = u[0], inv = 1.0f / rho;
+    const float vx = u[1] * inv, vy = u[2] * inv;
+    const float p = (g - 1.0f) * (u[3] - 0.5f * rho * (vx * vx + vy * vy));
+    fx[0] = u[1];
+    fx[1] = u[1] * vx + p;
+    fx[2] = u[2] * vx;
+    fx[3] = (u[3] + p) * vx;
+    fy[0] = u[2];
+    fy[1] = u[1] * vy;
+    fy[2] = u[2] * vy + p;
+    fy[3] = (u[3] + p) * vy;
+  }
+}
+
+// local maximum wave speed |f'(u)| (systems: |v| + c)
+template <int FLUX>
+__device__ __forceinline__ float wave_speed(const MethodScalars& ms, const float* u, float x, float y) {
+  if constexpr (FLUX == CVW_ADVECT_CONST) {
+    return sqrtf(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1]);
+  } else if constexpr (FLUX == CVW_ADVECT_ROT) {
+    const float vx = ms.fp[2] * (ms.fp[1] - y), vy = ms.fp[2] * (x - ms.fp[0]);
+    return sqrtf(vx * vx + vy * vy);
+  } else if constexpr (FLUX == CVW_BURGERS) {
+    return fabsf(u[0]) * sqrtf(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1]);
+  } else if constexpr (FLUX == CVW_KPP) {
+    return 1.0f;
+  } else {
+    const float g = ms.fp[0];
+    const float rho = u[0], inv = 1.0f / rho;
+    const float vx = u[1] * inv, vy = u[2] * inv;
+    const float p = (g - 1.0f) * (u[3] - 0.5f * rho * (vx * vx + vy * vy));
+    return sqrtf(vx * vx + vy * vy) + sqrtf(fmaxf(g * p * inv, 0.0f));
+  }
+}
+
+// interface flux f*(u-, u+, n): local Lax-Friedrichs for scalars, HLL with
+// Davis wave-speed estimates for the Euler equations
+template <int FLUX>
+__device__ __forceinline__ void num_flux(const MethodScalars& ms, const float* um, const float* up, float nx,
+                                         float ny, float x, float y, float* fs) {
+  constexpr int NV = NVar<FLUX>::value;
+  float fxm[NV], fym[NV], fxp[NV], fyp[NV];
+  phys_flux<FLUX>(ms, um, x, y, fxm, fym);
+  phys_flux<FLUX>(ms, up, x, y, fxp, fyp);
+  if constexpr (FLUX == CVW_EULER) {
+    const float g = ms.fp[0];
+    auto vnc = [&](const float* u, float& vn, float& c) {
+      const float inv = 1.0f / u[0];
+      const float vx = u[1] * inv, vy = u[2] * inv;
+      const float p = (g - 1.0f) * (u[3] - 0.5f * u[0] * (vx * vx + vy * vy));
+      vn = vx * nx + vy * ny;
+      c = sqrtf(fmaxf(g * p * inv, 0.0f));
+    };
+    float vm, cm, vp, cp;
+    vnc(um, vm, cm);
+    vnc(up, vp, cp);
+    const float SL = fminf(vm - cm, vp - cp);
+    const float SR = fmaxf(vm + cm, vp + cp);
+    for (int v = 0; v < 4; ++v) {
+      const float Fm = fxm[v] * nx + fym[v] * ny;
+      const float Fp = fxp[v] * nx + fyp[v] * ny;
+      float f;
+      if (SL >= 0.0f) f = Fm;
+      else if (SR <= 0.0f) f = Fp;
+      else f = (SR * Fm - SL * Fp + SL * SR * (up[v] - um[v])) / (SR - SL);
+      fs[v] = f;
+    }
+  } else {
+    float lam;
+    if (ms.lam_g > 0.0f) {
+      lam = ms.lam_g;
+    } else if constexpr (FLUX == CVW_ADVECT_CONST) {
+      lam = fabsf(ms.fp[0] * nx + ms.fp[1] * ny);
+    } else if constexpr (FLUX == CVW_ADVECT_ROT) {
+      lam = fabsf(ms.fp[2] * ((ms.fp[1] - y) * nx + (x - ms.fp[0]) * ny));
+    } else if constexpr (FLUX == CVW_BURGERS) {
+      lam = fmaxf(fabsf(um[0]), fabsf(up[0])) * fabsf(ms.fp[0] * nx + ms.fp[1] * ny);
+    } else {
+      lam = fmaxf(fabsf(cosf(um[0]) * nx - sinf(um[0]) * ny), fabsf(cosf(up[0]) * nx - sinf(up[0]) * ny));
+    }
+    const float Fm = fxm[0] * nx + fym[0] * ny;
+    const float Fp = fxp[0] * nx + fyp[0] * ny;
+    fs[0] = 0.5f * (Fm + Fp) - 0.5f * lam * (up[0] - um[0]);
+  }
+}
+
+template <int FLUX>
+__device__ __forceinline__ bool state_admissible(const MethodScalars& ms, const float* u) {
+  if constexpr (FLUX == CVW_EULER) {
+    const float inv = 1.0f / u[0];
+    const float p = (ms.fp[0] - 1.0f) * (u[3] - 0.5f * (u[1] * u[1] + u[2] * u[2]) * inv);
+    return u[0] > 0.0f && p > 0.0f;
+  } else {
+    return true;
+  }
+}
+
+// XCD-aware block order: consecutive logical blocks land on the same XCD so
+// that a block's neighbours (one grid row away) are served by the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks_padded) {
+  const int64_t per = nblocks_padded >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+}  // namespace cvw

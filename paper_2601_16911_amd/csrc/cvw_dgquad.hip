@@ -1,0 +1,662 @@
+// DG on congruent axis-aligned quadrilaterals (Lagrange basis at the Gauss
+// points, collocated (p+1)^2 Gauss rule), p = 1..3, on gfx950.
+//
+// Two kernels per residual evaluation:
+//
+//  * dgq_vertex_kernel  -- one thread per mesh vertex x_i.  Walks the vertex
+//    patch C(x_i) in CSR order, evaluates the Hermite data D^k u_h^e(x_i) of
+//    each cell of the patch (Taylor expansion, eq. taylorsol), the pointwise
+//    indicator beta = ||u_h^e||_{x_i}^q (eq. pointsnorm) and the Jiang-Shu
+//    weight (eps + beta)^{-r}, and writes the vertex candidate data
+//    c_i[k] = sum omega_e^i D^k u_h^e(x_i) (eq. taylorcand).  No atomics.
+//
+//  * dgq_eval_kernel -- one 16-lane DPP row per cell, node (a, b) on lane
+//    a + 4 b.  Each lane evaluates, at its own node / quadrature point, the
+//    derivatives of the cell solution and of the v_e vertex candidates; row
+//    reductions give the element semi-norms (eq. snorm), the cell WENO
+//    weights, ||u_h^e - u_h^{e,*}||_e (FP64) and gamma_e (eq. gamma), the
+//    wave speed lambda_e and nu_e (eq. lostab), and the sums of the
+//    shock-capturing weights alpha_q (eq. alphaq).  The same lanes then
+//    assemble the residual: volume flux and stabilisation contracted with the
+//    1D derivative matrix along rows / columns, LLF / HLL interface fluxes on
+//    the boundary lanes, and optionally the SSP-RK stage update with the
+//    diagonal (exact, collocated) mass matrix.
+//
+// All intra-cell exchanges are DPP moves inside the 16-lane row (quad
+// broadcasts along x, row rotations along y); no LDS is used.
+#include "cvw_device.h"
+
+namespace cvw {
+
+template <int P>
+struct KSet {
+  static constexpr int NK = (P + 1) * (P + 2) / 2 - 1;
+  int x[NK], y[NK];
+  constexpr KSet() : x{}, y{} {
+    int t = 0;
+    for (int n = 1; n <= P; ++n)
+      for (int j = 0; j <= n; ++j) {
+        x[t] = n - j;
+        y[t] = j;
+        ++t;
+      }
+  }
+};
+template <int P>
+inline constexpr KSet<P> kset{};
+
+__device__ __forceinline__ float ipow(float x, int n) {
+  float r = 1.0f;
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+__device__ __forceinline__ double dpow(double x, int n) {
+  double r = 1.0;
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// vertex stage
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void dgq_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
+                                                         const int32_t* __restrict__ vptr,
+                                                         const int32_t* __restrict__ vent, int64_t Nv,
+                                                         int64_t nbp, TensorTables tab, double sx, double sy,
+                                                         double he2, MethodScalars ms) {
+  constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
+  constexpr KSet<P> ks = kset<P>;
+  const int64_t blk = xcd_block(blockIdx.x, nbp);
+  const int64_t i = blk * 256 + threadIdx.x;
+  if (i >= Nv) return;
+  double acc[NK];
+#pragma unroll
+  for (int t = 0; t < NK; ++t) acc[t] = 0.0;
+  double wsum = 0.0;
+  const int beg = vptr[i], end = vptr[i + 1];
+  for (int it = beg; it < end; ++it) {
+    const int ent = vent[it];
+    const int e = ent >> 2, lv = ent & 3;
+    const float* ue = u + static_cast<int64_t>(e) * NLOC;
+    double r[NLOC];
+    if constexpr (NLOC % 4 == 0) {
+#pragma unroll
+      for (int j = 0; j < NLOC / 4; ++j) {
+        const float4 v4 = reinterpret_cast<const float4*>(ue)[j];
+        r[4 * j] = v4.x;
+        r[4 * j + 1] = v4.y;
+        r[4 * j + 2] = v4.z;
+        r[4 * j + 3] = v4.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) r[j] = ue[j];
+    }
+    // derivatives are taken of the data relative to one nodal value, so that
+    // constant data gives exactly zero Hermite data
+    {
+      const double r0 = r[0];
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) r[j] -= r0;
+    }
+    // vertex at xi = +1 (lv 1, 2) / eta = +1 (lv 2, 3): mirror the data so that
+    // only the tables at -1 are needed: l_i^{(m)}(1) = (-1)^m l_{P-i}^{(m)}(-1)
+    const bool fx = (lv == 1) || (lv == 2);
+    const bool fy = (lv >= 2);
+    double rr[NLOC];
+#pragma unroll
+    for (int bb = 0; bb < N1; ++bb)
+#pragma unroll
+      for (int aa = 0; aa < N1; ++aa) {
+        const double v00 = r[aa + N1 * bb], v10 = r[(P - aa) + N1 * bb];
+        const double v01 = r[aa + N1 * (P - bb)], v11 = r[(P - aa) + N1 * (P - bb)];
+        rr[aa + N1 * bb] = fx ? (fy ? v11 : v10) : (fy ? v01 : v00);
+      }
+    // derivatives in float64: high derivatives of smooth data cancel strongly
+    double T[N1][N1];   // T[m][j] = sum_i l_i^{(m)}(-1) rr[i][j]
+#pragma unroll
+    for (int m = 0; m < N1; ++m)
+#pragma unroll
+      for (int j = 0; j < N1; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < N1; ++ii) s = fma(tab.Ld[m][ii], rr[ii + N1 * j], s);
+        T[m][j] = s;
+      }
+    double D[NK];
+    double b2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+      const int kx = ks.x[t], ky = ks.y[t];
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < N1; ++j) s = fma(tab.Ld[ky][j], T[kx][j], s);
+      double sc = dpow(sx, kx) * dpow(sy, ky);
+      if (fx && (kx & 1)) sc = -sc;
+      if (fy && (ky & 1)) sc = -sc;
+      D[t] = s * sc;
+      b2 = fma(dpow(he2, kx + ky) * D[t], D[t], b2);
+    }
+    double w;
+    if (ms.fast_exp) {
+      const double den = ms.eps_vd + sqrt(b2);
+      w = 1.0 / (den * den);
+    } else {
+      const double beta = pow(sqrt(b2), static_cast<double>(ms.q_beta));
+      w = pow(ms.eps_vd + beta, -static_cast<double>(ms.r));
+    }
+#pragma unroll
+    for (int t = 0; t < NK; ++t) acc[t] = fma(w, D[t], acc[t]);
+    wsum += w;
+  }
+  const double inv = 1.0 / wsum;
+  float* out = cand + i * NK;
+#pragma unroll
+  for (int t = 0; t < NK; ++t) out[t] = static_cast<float>(acc[t] * inv);
+}
+
+// ---------------------------------------------------------------------------
+// cell stage + residual
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ float rowsum4(const float (&c)[MAXP + 1], float x) {
+  // sum_i c[i] * x(node (i, b))  for i <= P
+  float s = c[0] * qbcast<0>(x);
+  if constexpr (P >= 1) s = fmaf(c[1], qbcast<1>(x), s);
+  if constexpr (P >= 2) s = fmaf(c[2], qbcast<2>(x), s);
+  if constexpr (P >= 3) s = fmaf(c[3], qbcast<3>(x), s);
+  return s;
+}
+__device__ __forceinline__ float colsum4(const float (&c)[4], float x) {
+  // sum_s c[s] * x(node (a, src row of rotation s)); c[] already matches the source row
+  float s = c[0] * x;
+  s = fmaf(c[1], rrot<1>(x), s);
+  s = fmaf(c[2], rrot<2>(x), s);
+  s = fmaf(c[3], rrot<3>(x), s);
+  return s;
+}
+// value held by node (a, J) of the own column
+template <int J>
+__device__ __forceinline__ float colbcast(float x, const int (&srcb)[4]) {
+  float r = x;
+  const float r1 = rrot<1>(x), r2 = rrot<2>(x), r3 = rrot<3>(x);
+  r = (srcb[1] == J) ? r1 : r;
+  r = (srcb[2] == J) ? r2 : r;
+  r = (srcb[3] == J) ? r3 : r;
+  return r;
+}
+
+template <int P, int FLUX>
+__global__ __launch_bounds__(256) void dgq_eval_kernel(
+    const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
+    float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
+    const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr,
+    const TensorTables* __restrict__ tabp, TensorTables tab, int64_t E, int64_t nbp, float hx, float hy,
+    float he, MethodScalars ms, int mode, float dt, float a0, float b0, uint32_t* __restrict__ status) {
+  constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
+  constexpr int NV = NVar<FLUX>::value;
+  constexpr KSet<P> ks = kset<P>;
+  const int tid = threadIdx.x;
+  const int q = tid & 15;
+  const int a = q & 3, b = q >> 2;
+  const int64_t blk = xcd_block(blockIdx.x, nbp);
+  const int64_t e = blk * 16 + (tid >> 4);
+  if (e >= E) return;                          // whole 16-lane rows leave together
+  const bool nd = (a <= P) && (b <= P);
+  const int node = a + N1 * b;
+  const float sx = 2.0f / hx, sy = 2.0f / hy;
+
+  // ---- per-lane table rows -------------------------------------------------
+  int srcb[4];
+  srcb[0] = b;
+  srcb[1] = rroti<1>(b);
+  srcb[2] = rroti<2>(b);
+  srcb[3] = rroti<3>(b);
+  float CX[N1][MAXP + 1], CY[N1][4];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+#pragma unroll
+    for (int ii = 0; ii <= MAXP; ++ii) CX[m][ii] = tabp->D[m][a][ii];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) CY[m][s] = tabp->D[m][b][srcb[s]];
+  }
+  float TX[MAXP + 1], TY[4], BY0[4], BY1[4];
+#pragma unroll
+  for (int c = 0; c <= MAXP; ++c) TX[c] = sx * tabp->D[1][c][a];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    TY[s] = sy * tabp->D[1][srcb[s]][b];
+    BY0[s] = tabp->B[0][srcb[s]];
+    BY1[s] = tabp->B[1][srcb[s]];
+  }
+  const float Ba0 = tabp->B[0][a], Ba1 = tabp->B[1][a], Bb0 = tabp->B[0][b], Bb1 = tabp->B[1][b];
+  const float wa = tabp->w[a], wb = tabp->w[b];
+  const float Wq = nd ? wa * wb * 0.25f * hx * hy : 0.0f;
+
+  // ---- state ---------------------------------------------------------------
+  float uv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    float dummy = 0.0f;
+    if constexpr (FLUX == CVW_EULER) dummy = (v == 0) ? 1.0f : (v == 3 ? 2.5f : 0.0f);
+    uv[v] = nd ? u[(static_cast<int64_t>(v) * E + e) * NLOC + node] : dummy;
+  }
+  // ---- sensor field derivatives at the own point (eq. taylorsol), float64 ---
+  const double sxd = 2.0 / static_cast<double>(hx), syd = 2.0 / static_cast<double>(hy);
+  // the data is taken relative to its value at node (0, 0), so that constant
+  // data gives exactly zero derivatives (gamma_e = 1, no shock capturing)
+  double rho = nd ? static_cast<double>(uv[0]) : 0.0;
+  {
+    const double q0 = qbcastd<0>(rho);
+    const double r1 = rrotd<1>(q0), r2 = rrotd<2>(q0), r3 = rrotd<3>(q0);
+    double ref = q0;
+    ref = (srcb[1] == 0) ? r1 : ref;
+    ref = (srcb[2] == 0) ? r2 : ref;
+    ref = (srcb[3] == 0) ? r3 : ref;
+    rho = nd ? rho - ref : 0.0;
+  }
+  double Rm[N1];
+  Rm[0] = rho;
+#pragma unroll
+  for (int m = 1; m < N1; ++m) {
+    double sacc = tabp->Dd[m][a][0] * qbcastd<0>(rho);
+    if constexpr (P >= 1) sacc = fma(tabp->Dd[m][a][1], qbcastd<1>(rho), sacc);
+    if constexpr (P >= 2) sacc = fma(tabp->Dd[m][a][2], qbcastd<2>(rho), sacc);
+    if constexpr (P >= 3) sacc = fma(tabp->Dd[m][a][3], qbcastd<3>(rho), sacc);
+    Rm[m] = sacc;
+  }
+  double Du[NK];
+#pragma unroll
+  for (int t = 0; t < NK; ++t) {
+    const int kx = ks.x[t], ky = ks.y[t];
+    double sacc = tabp->Dd[ky][b][srcb[0]] * Rm[kx];
+    sacc = fma(tabp->Dd[ky][b][srcb[1]], rrotd<1>(Rm[kx]), sacc);
+    sacc = fma(tabp->Dd[ky][b][srcb[2]], rrotd<2>(Rm[kx]), sacc);
+    sacc = fma(tabp->Dd[ky][b][srcb[3]], rrotd<3>(Rm[kx]), sacc);
+    Du[t] = sacc * dpow(sxd, kx) * dpow(syd, ky);
+  }
+  const double he2 = static_cast<double>(he) * he;
+  double hk[NK], wk[NK];   // h_e^{2|k|} (pointwise) and h_e^{2|k|-2} (element, d = 2)
+#pragma unroll
+  for (int t = 0; t < NK; ++t) {
+    hk[t] = dpow(he2, ks.x[t] + ks.y[t]);
+    wk[t] = dpow(he2, ks.x[t] + ks.y[t] - 1);
+  }
+
+  // ---- sensor gamma_e -----------------------------------------------------
+  float gam;
+  if (ms.sensor_kind == CVW_SENSOR_FIXED) {
+    gam = ms.fixed_gamma;
+  } else {
+    const double xq = tabp->xi[a], yq = tabp->xi[b];
+    const double Wqd = Wq;
+    double n2p = 0.0;
+#pragma unroll
+    for (int t = 0; t < NK; ++t) n2p = fma(Wqd * wk[t] * Du[t], Du[t], n2p);
+    double Ds[4][NK];
+    double b2p[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int vid = cell_vtx[e * 4 + l];
+      const float* cl = cand + static_cast<int64_t>(vid) * NK;
+      double c[NK];
+#pragma unroll
+      for (int t = 0; t < NK; ++t) c[t] = cl[t];
+      const double xl = (l == 1 || l == 2) ? 1.0 : -1.0;
+      const double yl = (l >= 2) ? 1.0 : -1.0;
+      const double dx = (xq - xl) * 0.5 * hx, dy = (yq - yl) * 0.5 * hy;
+      double px[N1], py[N1];
+      px[0] = 1.0;
+      py[0] = 1.0;
+#pragma unroll
+      for (int n = 1; n < N1; ++n) {
+        px[n] = px[n - 1] * dx / n;
+        py[n] = py[n - 1] * dy / n;
+      }
+      double bp = 0.0;
+#pragma unroll
+      for (int t = 0; t < NK; ++t) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int t2 = 0; t2 < NK; ++t2) {
+          if (ks.x[t2] >= ks.x[t] && ks.y[t2] >= ks.y[t])
+            sacc = fma(c[t2], px[ks.x[t2] - ks.x[t]] * py[ks.y[t2] - ks.y[t]], sacc);
+        }
+        Ds[l][t] = sacc;
+        bp = fma(wk[t] * sacc, sacc, bp);
+      }
+      b2p[l] = Wqd * bp;
+    }
+    const double n2 = row_sumd(n2p);
+    double beta[5];
+    beta[0] = sqrt(n2);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) beta[l + 1] = sqrt(row_sumd(b2p[l]));
+    double om[5], osum = 0.0;
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      const double lin = (l == 0) ? 1.0 - 4.0 * ms.lin_wd : ms.lin_wd;
+      double w;
+      if (ms.fast_exp) {
+        const double den = ms.eps_cd + beta[l];
+        w = lin / (den * den);
+      } else {
+        w = lin * pow(ms.eps_cd + pow(beta[l], static_cast<double>(ms.q_beta)), -static_cast<double>(ms.r));
+      }
+      om[l] = w;
+      osum += w;
+    }
+    const double oinv = 1.0 / osum;
+    double d2p = 0.0;
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+      double dl = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) dl = fma(om[l + 1] * oinv, Du[t] - Ds[l][t], dl);
+      d2p = fma(Wqd * wk[t] * dl, dl, d2p);
+    }
+    const double d2 = row_sumd(d2p);
+    if (n2 > 0.0) {
+      const float ratio = static_cast<float>(sqrt(d2 / n2));
+      const float mr = fminf(1.0f, ratio);
+      gam = 1.0f - (ms.fast_exp ? mr : powf(mr, ms.q_sensor));
+    } else {
+      gam = 1.0f;
+    }
+  }
+
+  // ---- viscosity and shock-capturing weights -------------------------------
+  float lam;
+  if (ms.lam_g > 0.0f) {
+    lam = ms.lam_g;
+  } else {
+    lam = row_max(nd ? wave_speed<FLUX>(ms, uv, 0.0f, 0.0f) : 0.0f);
+  }
+  const float nu = lam * he / (2.0f * P);
+  double atil2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < NK; ++t) atil2 = fma(hk[t] * Du[t], Du[t], atil2);
+  const float atil = static_cast<float>(sqrt(atil2));
+  const float g2 = static_cast<float>(Du[0] * Du[0] + Du[1] * Du[1]);
+  const float fq = (1.0f - gam) * g2;
+  const float S = row_sum(Wq * fq);
+  const float T = row_sum(Wq * atil * fq);
+  const bool sc_active = ms.sc_on && (static_cast<double>(gam) < ms.c_gammad) && (S > 0.0f) && (T > 0.0f);
+  const float alpha = sc_active ? atil * (S / T) : 1.0f;
+
+  if (mode == MODE_SENSOR) {
+    if (q == 0) gamma_out[e] = gam;
+    if (nd && alpha_out) alpha_out[e * NLOC + node] = alpha;
+    return;
+  }
+  if (gamma_out && q == 0) gamma_out[e] = gam;
+
+  // ---- volume terms ---------------------------------------------------------
+  const float coef = nu * (1.0f - gam) * alpha;
+  float fx[NV], fy[NV];
+  phys_flux<FLUX>(ms, uv, 0.0f, 0.0f, fx, fy);
+  float r[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const float uvv = nd ? uv[v] : 0.0f;
+    const float gx = sx * rowsum4<P>(CX[1], uvv);
+    const float gy = sy * colsum4(CY[1], uvv);
+    const float WFx = Wq * (coef * gx - fx[v]);
+    const float WFy = Wq * (coef * gy - fy[v]);
+    float tx[MAXP + 1];
+#pragma unroll
+    for (int c = 0; c <= MAXP; ++c) tx[c] = TX[c];
+    r[v] = rowsum4<P>(tx, WFx) + colsum4(TY, WFy);
+  }
+
+  // ---- interface terms -------------------------------------------------------
+  // own traces on the four faces (every lane computes them; boundary lanes use them)
+  float tW[NV], tE[NV], tS[NV], tN[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const float uvv = nd ? uv[v] : 0.0f;
+    float b0r[MAXP + 1], b1r[MAXP + 1];
+#pragma unroll
+    for (int c = 0; c <= MAXP; ++c) {
+      b0r[c] = tab.B[0][c];
+      b1r[c] = tab.B[1][c];
+    }
+    tW[v] = rowsum4<P>(b0r, uvv);
+    tE[v] = rowsum4<P>(b1r, uvv);
+    tS[v] = colsum4(BY0, uvv);
+    tN[v] = colsum4(BY1, uvv);
+  }
+  float fW[NV], fE[NV], fS[NV], fN[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) fW[v] = fE[v] = fS[v] = fN[v] = 0.0f;
+  const int64_t stride = E * NLOC;
+  if (nd && a == 0) {
+    const int64_t en = nbr[e * 4 + 3];
+    float up[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const float* un = u + v * stride + en * NLOC + N1 * b;
+      float s = 0.0f;
+#pragma unroll
+      for (int ii = 0; ii < N1; ++ii) s = fmaf(tab.B[1][ii], un[ii], s);
+      up[v] = s;
+    }
+    float fs[NV];
+    num_flux<FLUX>(ms, tW, up, -1.0f, 0.0f, 0.0f, 0.0f, fs);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fW[v] = wb * 0.5f * hy * fs[v];
+  }
+  if (nd && a == P) {
+    const int64_t en = nbr[e * 4 + 1];
+    float up[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const float* un = u + v * stride + en * NLOC + N1 * b;
+      float s = 0.0f;
+#pragma unroll
+      for (int ii = 0; ii < N1; ++ii) s = fmaf(tab.B[0][ii], un[ii], s);
+      up[v] = s;
+    }
+    float fs[NV];
+    num_flux<FLUX>(ms, tE, up, 1.0f, 0.0f, 0.0f, 0.0f, fs);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fE[v] = wb * 0.5f * hy * fs[v];
+  }
+  if (nd && b == 0) {
+    const int64_t en = nbr[e * 4 + 0];
+    float up[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const float* un = u + v * stride + en * NLOC + a;
+      float s = 0.0f;
+#pragma unroll
+      for (int jj = 0; jj < N1; ++jj) s = fmaf(tab.B[1][jj], un[N1 * jj], s);
+      up[v] = s;
+    }
+    float fs[NV];
+    num_flux<FLUX>(ms, tS, up, 0.0f, -1.0f, 0.0f, 0.0f, fs);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fS[v] = wa * 0.5f * hx * fs[v];
+  }
+  if (nd && b == P) {
+    const int64_t en = nbr[e * 4 + 2];
+    float up[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const float* un = u + v * stride + en * NLOC + a;
+      float s = 0.0f;
+#pragma unroll
+      for (int jj = 0; jj < N1; ++jj) s = fmaf(tab.B[0][jj], un[N1 * jj], s);
+      up[v] = s;
+    }
+    float fs[NV];
+    num_flux<FLUX>(ms, tN, up, 0.0f, 1.0f, 0.0f, 0.0f, fs);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fN[v] = wa * 0.5f * hx * fs[v];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    r[v] = fmaf(Ba0, qbcast<0>(fW[v]), r[v]);
+    r[v] = fmaf(Ba1, qbcast<P>(fE[v]), r[v]);
+    r[v] = fmaf(Bb0, colbcast<0>(fS[v], srcb), r[v]);
+    r[v] = fmaf(Bb1, colbcast<P>(fN[v], srcb), r[v]);
+  }
+
+  // ---- output -----------------------------------------------------------------
+  bool nonfinite = false, inadmissible = false;
+  if (nd) {
+    inadmissible = !state_admissible<FLUX>(ms, uv);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int64_t idx = (static_cast<int64_t>(v) * E + e) * NLOC + node;
+      float val;
+      if (mode == MODE_RESIDUAL) {
+        val = r[v];
+      } else {
+        const float L = -r[v] / Wq;
+        const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
+        val = base + b0 * (uv[v] + dt * L);
+      }
+      nonfinite = nonfinite || !isfinite(val);
+      out[idx] = val;
+    }
+  }
+  const unsigned long long m1 = __ballot(nonfinite), m2 = __ballot(inadmissible);
+  if ((m1 | m2) && (tid & 63) == __builtin_ctzll(m1 | m2))
+    atomicOr(status, (m1 ? ST_NONFINITE : 0u) | (m2 ? ST_NONPOSITIVE : 0u));
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int64_t pad8(int64_t n) { return (n + 7) / 8 * 8; }
+
+template <int P>
+static void launch_vertex(const cvw_mesh* m, const MethodScalars& ms, const float* u, float* cand, hipStream_t s) {
+  const int64_t nb = pad8((m->Nv + 255) / 256);
+  hipLaunchKernelGGL(dgq_vertex_kernel<P>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, cand, m->d_vtx_ptr,
+                     m->d_vtx_ent, m->Nv, nb, m->tens, 2.0 / m->hx, 2.0 / m->hy, m->he * m->he, ms);
+}
+
+cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand,
+                             hipStream_t s) {
+  const MethodScalars ms = make_scalars(prm);
+  switch (m->degree) {
+    case 1: launch_vertex<1>(m, ms, u, cand, s); break;
+    case 2: launch_vertex<2>(m, ms, u, cand, s); break;
+    case 3: launch_vertex<3>(m, ms, u, cand, s); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+template <int P, int FLUX>
+static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
+                        float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
+                        float a0, float b0, hipStream_t s) {
+  const int64_t nb = pad8((m->E + 15) / 16);
+  hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0, out,
+                     gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_tens, m->tens, m->E, nb,
+                     static_cast<float>(m->hx), static_cast<float>(m->hy), static_cast<float>(m->he), ms, mode, dt,
+                     a0, b0, status);
+}
+
+template <int P>
+static cvw_status eval_p(const cvw_mesh* m, const MethodScalars& ms, int flux, int mode, const float* u,
+                         const float* u0, float* out, float* gamma, float* alpha, const float* cand,
+                         uint32_t* status, float dt, float a0, float b0, hipStream_t s) {
+  switch (flux) {
+    case CVW_ADVECT_CONST:
+      launch_eval<P, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      break;
+    case CVW_BURGERS:
+      launch_eval<P, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      break;
+    case CVW_KPP:
+      launch_eval<P, CVW_KPP>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      break;
+    case CVW_EULER:
+      launch_eval<P, CVW_EULER>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      break;
+    default:
+      set_error("flux not supported by the DG quadrilateral path (position-dependent velocity needs cell coordinates)");
+      return CVW_EUNSUPPORTED;
+  }
+  return CVW_OK;
+}
+
+cvw_status dgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0,
+                       float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
+                       float a0, float b0, hipStream_t s) {
+  const MethodScalars ms = make_scalars(prm);
+  cvw_status st;
+  switch (m->degree) {
+    case 1: st = eval_p<1>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    case 2: st = eval_p<2>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    case 3: st = eval_p<3>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+  if (st != CVW_OK) return st;
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+}  // namespace cvw
+
+namespace cvw {
+
+// ---------------------------------------------------------------------------
+// float64 totals sum_e int_{K_e} u_h dx (collocated Gauss weights), fixed-order
+// reductions: thread partials over a fixed grid-stride set, a shared-memory
+// tree per block, then one block sums the block partials in index order.
+// ---------------------------------------------------------------------------
+constexpr int TOT_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void totals_partial_kernel(const float* __restrict__ u, double* __restrict__ part,
+                                                             int64_t E, int nloc, int n1, TensorTables tab,
+                                                             double jac) {
+  __shared__ double sh[256];
+  const int v = blockIdx.y;
+  const int64_t n = E * nloc;
+  const float* uv = u + static_cast<int64_t>(v) * n;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += static_cast<int64_t>(gridDim.x) * 256) {
+    const int j = static_cast<int>(i % nloc);
+    const int a = j % n1, b = j / n1;
+    acc += static_cast<double>(uv[i]) * static_cast<double>(tab.w[a < 4 ? a : 0]) * static_cast<double>(tab.w[b < 4 ? b : 0]);
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[v * TOT_BLOCKS + blockIdx.x] = sh[0] * jac;
+}
+
+__global__ __launch_bounds__(256) void totals_final_kernel(const double* __restrict__ part, double* __restrict__ res,
+                                                           int nblocks) {
+  __shared__ double sh[256];
+  const int v = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += 256) acc += part[v * TOT_BLOCKS + i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) res[v] = sh[0];
+}
+
+cvw_status totals_f32(const cvw_mesh* m, int nvar, const float* u, double* part, double* res, hipStream_t s) {
+  const int n1 = m->degree + 1;
+  const double jac = 0.25 * m->hx * m->hy;
+  const int64_t n = m->E * m->nloc;
+  int nb = static_cast<int>(std::min<int64_t>(TOT_BLOCKS, (n + 255) / 256));
+  hipLaunchKernelGGL(totals_partial_kernel, dim3(nb, nvar), dim3(256), 0, s, u, part, m->E, m->nloc, n1, m->tens, jac);
+  hipLaunchKernelGGL(totals_final_kernel, dim3(nvar), dim3(256), 0, s, part, res, nb);
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+}  // namespace cvw

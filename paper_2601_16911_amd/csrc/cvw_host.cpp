@@ -1,0 +1,791 @@
+// Host side of libcvw: argument validation, mesh connectivity (vertex patches,
+// face neighbours, canonical CG numbering), reference tables and dispatch of
+// the gfx950 kernels.  Everything here runs once per mesh (cvw_mesh_build) or
+// once per call; no host work depends on the state.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "cvw_internal.h"
+
+namespace cvw {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int n_var_of(int flux) { return flux == CVW_EULER ? 4 : 1; }
+
+MethodScalars make_scalars(const cvw_params* p) {
+  MethodScalars s{};
+  s.eps_v = static_cast<float>(p->eps_vertex);
+  s.eps_c = static_cast<float>(p->eps_cell);
+  s.r = static_cast<float>(p->r);
+  s.q_sensor = static_cast<float>(p->q_sensor);
+  s.q_beta = static_cast<float>(p->q_beta);
+  s.lin_w = static_cast<float>(p->lin_w_vertex);
+  s.c_gamma = static_cast<float>(p->c_gamma);
+  s.lam_g = static_cast<float>(p->lambda_global);
+  for (int i = 0; i < 4; ++i) s.fp[i] = static_cast<float>(p->flux_param[i]);
+  s.sc_on = p->sc_on;
+  s.fast_exp = (p->r == 2 && p->q_sensor == 1.0 && p->q_beta == 1.0) ? 1 : 0;
+  s.sensor_kind = p->sensor;
+  s.fixed_gamma = static_cast<float>(p->fixed_gamma);
+  s.eps_vd = p->eps_vertex;
+  s.eps_cd = p->eps_cell;
+  s.lin_wd = p->lin_w_vertex;
+  s.c_gammad = p->c_gamma;
+  s.lam_gd = p->lambda_global;
+  s.fixed_gammad = p->fixed_gamma;
+  for (int i = 0; i < 4; ++i) s.fpd[i] = p->flux_param[i];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// 1D rules and Lagrange polynomials (double precision, computed here from
+// their definitions: Newton iteration on the Legendre polynomial and its
+// derivative)
+// ---------------------------------------------------------------------------
+static void legendre(int n, double x, double& p, double& dp) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) { p = 1.0; dp = 0.0; return; }
+  for (int k = 2; k <= n; ++k) {
+    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+  dp = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      legendre(n, z, p, dp);
+      const double dz = p / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p, dp;
+    legendre(n, z, p, dp);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+void lobatto_nodes(int n, std::vector<double>& x) {
+  // endpoints and the roots of P'_{n-1}
+  x.assign(n, 0.0);
+  x[0] = -1.0;
+  x[n - 1] = 1.0;
+  const int m = n - 1;
+  for (int i = 1; i < n - 1; ++i) {
+    double z = -std::cos(M_PI * i / m);
+    for (int it = 0; it < 100; ++it) {
+      // f = P'_m(z), f' = P''_m(z) from the Legendre ODE: (1-z^2) P'' = 2 z P' - m(m+1) P
+      double p, dp;
+      legendre(m, z, p, dp);
+      const double d2p = (2.0 * z * dp - m * (m + 1.0) * p) / (1.0 - z * z);
+      const double dz = dp / d2p;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+  }
+}
+
+// value of the m-th derivative of the Lagrange polynomial l_i (nodes xs) at t
+static double lagrange_deriv(const std::vector<double>& xs, int i, int m, double t) {
+  const int n = static_cast<int>(xs.size());
+  // monomial coefficients of l_i
+  std::vector<double> c(1, 1.0);
+  double den = 1.0;
+  for (int j = 0; j < n; ++j) {
+    if (j == i) continue;
+    std::vector<double> nc(c.size() + 1, 0.0);
+    for (size_t k = 0; k < c.size(); ++k) {
+      nc[k + 1] += c[k];
+      nc[k] -= xs[j] * c[k];
+    }
+    c.swap(nc);
+    den *= xs[i] - xs[j];
+  }
+  for (auto& v : c) v /= den;
+  for (int d = 0; d < m; ++d) {
+    if (c.size() <= 1) return 0.0;
+    std::vector<double> nc(c.size() - 1);
+    for (size_t k = 1; k < c.size(); ++k) nc[k - 1] = c[k] * static_cast<double>(k);
+    c.swap(nc);
+  }
+  double v = 0.0;
+  for (size_t k = c.size(); k-- > 0;) v = v * t + c[k];
+  return v;
+}
+
+static void fill_tensor_tables(TensorTables& T, int p, bool lobatto) {
+  std::memset(&T, 0, sizeof(T));
+  std::vector<double> x, w, xn;
+  gauss_rule(p + 1, x, w);
+  if (lobatto) lobatto_nodes(p + 1, xn); else xn = x;
+  for (int a = 0; a <= p; ++a) {
+    T.xi[a] = static_cast<float>(xn[a]);
+    T.w[a] = static_cast<float>(w[a]);
+  }
+  // D[m][a][i] = l_i^{(m)} at the volume quadrature point a (= node a for Gauss nodes)
+  for (int m = 0; m <= p; ++m)
+    for (int a = 0; a <= p; ++a)
+      for (int i = 0; i <= p; ++i) {
+        T.Dd[m][a][i] = lagrange_deriv(xn, i, m, x[a]);
+        T.D[m][a][i] = static_cast<float>(T.Dd[m][a][i]);
+      }
+  for (int i = 0; i <= p; ++i) {
+    T.B[0][i] = static_cast<float>(lagrange_deriv(xn, i, 0, -1.0));
+    T.B[1][i] = static_cast<float>(lagrange_deriv(xn, i, 0, 1.0));
+    for (int m = 0; m <= p; ++m) {
+      T.Ld[m][i] = lagrange_deriv(xn, i, m, -1.0);
+      T.L[m][i] = static_cast<float>(T.Ld[m][i]);
+    }
+  }
+}
+
+static void fill_cg_tables(CGTables& T, int p) {
+  std::memset(&T, 0, sizeof(T));
+  std::vector<double> xn, xv, wv, xs, ws;
+  lobatto_nodes(p + 1, xn);
+  gauss_rule(p + 1, xv, wv);
+  gauss_rule(p + 2, xs, ws);
+  for (int a = 0; a <= p; ++a) {
+    T.xn[a] = static_cast<float>(xn[a]);
+    T.xv[a] = static_cast<float>(xv[a]);
+    T.wv[a] = static_cast<float>(wv[a]);
+  }
+  for (int a = 0; a <= p + 1; ++a) {
+    T.xs[a] = static_cast<float>(xs[a]);
+    T.ws[a] = static_cast<float>(ws[a]);
+  }
+  for (int m = 0; m < 3; ++m)
+    for (int i = 0; i <= p; ++i) {
+      for (int q = 0; q <= p; ++q) {
+        T.Dvd[m][q][i] = lagrange_deriv(xn, i, m, xv[q]);
+        T.Dv[m][q][i] = static_cast<float>(T.Dvd[m][q][i]);
+      }
+      for (int q = 0; q <= p + 1; ++q) {
+        T.Dsd[m][q][i] = lagrange_deriv(xn, i, m, xs[q]);
+        T.Ds[m][q][i] = static_cast<float>(T.Dsd[m][q][i]);
+      }
+      T.Lmd[m][i] = lagrange_deriv(xn, i, m, -1.0);
+      T.Lpd[m][i] = lagrange_deriv(xn, i, m, 1.0);
+      T.Lm[m][i] = static_cast<float>(T.Lmd[m][i]);
+      T.Lp[m][i] = static_cast<float>(T.Lpd[m][i]);
+    }
+  for (int a = 0; a <= p; ++a)
+    for (int i = 0; i <= p; ++i) T.Dn[a][i] = static_cast<float>(lagrange_deriv(xn, i, 1, xn[a]));
+}
+
+static void fill_seg_tables(SegTables& T, int p, bool lobatto) {
+  std::memset(&T, 0, sizeof(T));
+  std::vector<double> xq, wq, xn;
+  gauss_rule(p + 1, xq, wq);
+  if (lobatto) lobatto_nodes(p + 1, xn); else xn = xq;
+  for (int a = 0; a <= p; ++a) {
+    T.xn[a] = xn[a];
+    T.xq[a] = xq[a];
+    T.wq[a] = wq[a];
+  }
+  for (int m = 0; m <= p; ++m)
+    for (int i = 0; i <= p; ++i) {
+      for (int q = 0; q <= p; ++q) T.D[m][q][i] = lagrange_deriv(xn, i, m, xq[q]);
+      T.Lv[0][m][i] = lagrange_deriv(xn, i, m, -1.0);
+      T.Lv[1][m][i] = lagrange_deriv(xn, i, m, 1.0);
+    }
+  for (int a = 0; a <= p; ++a)
+    for (int i = 0; i <= p; ++i) T.Dn[a][i] = lagrange_deriv(xn, i, 1, xn[a]);
+}
+
+// Canonical CG numbering: vertex DOFs by vertex id, then edge DOFs (edges
+// sorted by (min, max) vertex id, oriented min -> max), then cell-interior
+// DOFs by cell id (lexicographic inside the cell).
+static bool cg_number(cvw_mesh* m, const int32_t* cv) {
+  const int p = m->degree;
+  const int64_t E = m->E, Nv = m->Nv;
+  const int nloc = m->nloc;
+  m->h_cell_dof.assign(E * nloc, -1);
+  if (m->cell == CVW_SEG) {
+    for (int64_t e = 0; e < E; ++e) {
+      m->h_cell_dof[e * nloc] = cv[e * 2];
+      m->h_cell_dof[e * nloc + p] = cv[e * 2 + 1];
+      for (int t = 1; t < p; ++t) m->h_cell_dof[e * nloc + t] = static_cast<int32_t>(Nv + e * (p - 1) + t - 1);
+    }
+    m->ndof = Nv + E * (p - 1);
+    return true;
+  }
+  if (m->cell != CVW_QUAD) return false;
+  const int n1 = p + 1;
+  auto loc = [n1](int a, int b) { return a + n1 * b; };
+  const int ca[4][2] = {{0, 0}, {p, 0}, {p, p}, {0, p}};
+  std::vector<std::pair<int64_t, int64_t>> keys(E * 4);
+  for (int64_t e = 0; e < E; ++e) {
+    for (int lv = 0; lv < 4; ++lv) m->h_cell_dof[e * nloc + loc(ca[lv][0], ca[lv][1])] = cv[e * 4 + lv];
+    for (int f = 0; f < 4; ++f) {
+      const int64_t a = cv[e * 4 + f], b = cv[e * 4 + (f + 1) % 4];
+      keys[e * 4 + f] = {std::min(a, b), std::max(a, b)};
+    }
+  }
+  std::vector<std::pair<int64_t, int64_t>> uniq(keys);
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  const int64_t n_edges = static_cast<int64_t>(uniq.size());
+  auto edge_node = [p](int f, int t, int& a, int& b) {
+    switch (f) {
+      case 0: a = t; b = 0; break;
+      case 1: a = p; b = t; break;
+      case 2: a = p - t; b = p; break;
+      default: a = 0; b = p - t; break;
+    }
+  };
+  for (int64_t e = 0; e < E; ++e)
+    for (int f = 0; f < 4; ++f) {
+      const int64_t eid = std::lower_bound(uniq.begin(), uniq.end(), keys[e * 4 + f]) - uniq.begin();
+      const bool same = cv[e * 4 + f] < cv[e * 4 + (f + 1) % 4];
+      for (int t = 1; t < p; ++t) {
+        const int g = same ? t - 1 : p - 1 - t;
+        int a, b;
+        edge_node(f, t, a, b);
+        m->h_cell_dof[e * nloc + loc(a, b)] = static_cast<int32_t>(Nv + eid * (p - 1) + g);
+      }
+    }
+  const int64_t base = Nv + n_edges * (p - 1);
+  const int ni = (p - 1) * (p - 1);
+  for (int64_t e = 0; e < E; ++e)
+    for (int b = 1; b < p; ++b)
+      for (int a = 1; a < p; ++a)
+        m->h_cell_dof[e * nloc + loc(a, b)] = static_cast<int32_t>(base + e * ni + (a - 1) + (p - 1) * (b - 1));
+  m->ndof = base + E * ni;
+  return true;
+}
+
+}  // namespace cvw
+
+using namespace cvw;
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+#define CVW_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t _e = (call);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      set_error(std::string(#call) + ": " + hipGetErrorString(_e));                \
+      return CVW_EDEVICE;                                                          \
+    }                                                                              \
+  } while (0)
+
+template <typename T>
+static cvw_status upload(T** dst, const std::vector<T>& src) {
+  if (src.empty()) { *dst = nullptr; return CVW_OK; }
+  if (hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T)) != hipSuccess) {
+    set_error("hipMalloc failed for mesh arrays");
+    return CVW_ENOMEM;
+  }
+  CVW_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return CVW_OK;
+}
+
+static void free_mesh(cvw_mesh* m) {
+  if (!m) return;
+  (void)hipFree(m->d_vtx_ptr);
+  (void)hipFree(m->d_vtx_ent);
+  (void)hipFree(m->d_cell_vtx);
+  (void)hipFree(m->d_nbr);
+  (void)hipFree(m->d_tens);
+  (void)hipFree(m->d_cell_dof);
+  (void)hipFree(m->d_dof_ptr);
+  (void)hipFree(m->d_dof_ent);
+  (void)hipFree(m->d_geo);
+  (void)hipFree(m->d_he);
+  (void)hipFree(m->d_cgt);
+  (void)hipFree(m->d_hcell);
+  (void)hipFree(m->d_segt);
+  delete m;
+}
+
+extern "C" {
+
+int cvw_abi_version(void) { return CVW_ABI_VERSION; }
+
+const char* cvw_last_error(void) { return g_err.c_str(); }
+
+void cvw_mesh_destroy(cvw_mesh* mesh) { free_mesh(mesh); }
+
+cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
+  if (!d || !out) { set_error("null argument"); return CVW_EINVAL; }
+  *out = nullptr;
+  if (!d->cell_vertices || !d->cell_coords) { set_error("null mesh arrays"); return CVW_EINVAL; }
+  int ve, nf;
+  if (d->cell == CVW_SEG && d->dim == 1) { ve = 2; nf = 2; }
+  else if (d->cell == CVW_TRI && d->dim == 2) { ve = 3; nf = 3; }
+  else if (d->cell == CVW_QUAD && d->dim == 2) { ve = 4; nf = 4; }
+  else { set_error("cell type / dimension mismatch"); return CVW_EINVAL; }
+  if (d->degree < 1 || d->degree > 16) { set_error("degree out of range"); return CVW_EINVAL; }
+  if (d->space != CVW_CG && d->space != CVW_DG) { set_error("space must be CG or DG"); return CVW_EINVAL; }
+  if (d->n_cells <= 0 || d->n_vertices <= 0) { set_error("empty mesh"); return CVW_EINVAL; }
+  if (d->n_cells * ve >= (int64_t(1) << 31) || d->n_vertices >= (int64_t(1) << 31)) {
+    set_error("mesh too large for 32-bit indices"); return CVW_EINVAL;
+  }
+  const int64_t E = d->n_cells, Nv = d->n_vertices;
+  auto* m = new cvw_mesh();
+  m->dim = d->dim; m->cell = d->cell; m->degree = d->degree; m->space = d->space;
+  m->E = E; m->Nv = Nv; m->ve = ve; m->nf = nf;
+  const int p = d->degree;
+  if (d->cell == CVW_TRI) { m->nloc = (p + 1) * (p + 2) / 2; m->nq = (p + 1) * (p + 1); }
+  else if (d->cell == CVW_QUAD) { m->nloc = (p + 1) * (p + 1); m->nq = (p + 1) * (p + 1); }
+  else { m->nloc = p + 1; m->nq = p + 1; }
+  m->nk = (d->dim == 1) ? p : (p + 1) * (p + 2) / 2 - 1;
+  (void)hipGetDevice(&m->device);
+
+  // ---- validation and vertex patches (CSR in ascending (cell, local vertex)) ----
+  m->h_cell_vtx.assign(d->cell_vertices, d->cell_vertices + E * ve);
+  std::vector<int32_t> cnt(Nv, 0);
+  for (int64_t e = 0; e < E; ++e)
+    for (int l = 0; l < ve; ++l) {
+      const int32_t v = d->cell_vertices[e * ve + l];
+      if (v < 0 || v >= Nv) { free_mesh(m); set_error("vertex id out of range"); return CVW_EINVAL; }
+      for (int l2 = 0; l2 < l; ++l2)
+        if (d->cell_vertices[e * ve + l2] == v) { free_mesh(m); set_error("repeated vertex in a cell"); return CVW_EINVAL; }
+      ++cnt[v];
+    }
+  m->h_vtx_ptr.assign(Nv + 1, 0);
+  for (int64_t v = 0; v < Nv; ++v) {
+    if (cnt[v] == 0) { free_mesh(m); set_error("vertex not used by any cell"); return CVW_EINVAL; }
+    m->h_vtx_ptr[v + 1] = m->h_vtx_ptr[v] + cnt[v];
+  }
+  m->nnz = m->h_vtx_ptr[Nv];
+  m->h_vtx_cell.assign(m->nnz, 0);
+  m->h_vtx_lv.assign(m->nnz, 0);
+  std::vector<int32_t> fill(m->h_vtx_ptr.begin(), m->h_vtx_ptr.end() - 1);
+  std::vector<int32_t> ent(m->nnz);
+  for (int64_t e = 0; e < E; ++e)
+    for (int l = 0; l < ve; ++l) {
+      const int32_t v = d->cell_vertices[e * ve + l];
+      const int32_t pos = fill[v]++;
+      m->h_vtx_cell[pos] = static_cast<int32_t>(e);
+      m->h_vtx_lv[pos] = l;
+      ent[pos] = static_cast<int32_t>(e * 4 + l);
+    }
+
+  // ---- geometry ----
+  m->h_coords.assign(d->cell_coords, d->cell_coords + E * ve * d->dim);
+  m->h_he.assign(E, 0.0);
+  for (int64_t e = 0; e < E; ++e) {
+    double hmax = 0.0;
+    for (int i = 0; i < ve; ++i)
+      for (int j = i + 1; j < ve; ++j) {
+        double s = 0.0;
+        for (int c = 0; c < d->dim; ++c) {
+          const double dd = d->cell_coords[(e * ve + i) * d->dim + c] - d->cell_coords[(e * ve + j) * d->dim + c];
+          s += dd * dd;
+        }
+        hmax = std::max(hmax, std::sqrt(s));
+      }
+    if (!(hmax > 0.0) || !std::isfinite(hmax)) { free_mesh(m); set_error("degenerate cell"); return CVW_EINVAL; }
+    m->h_he[e] = hmax;
+  }
+  if (d->cell == CVW_QUAD) {
+    // congruent axis-aligned rectangles?
+    const double* X = d->cell_coords;
+    const double hx0 = X[2] - X[0], hy0 = X[5] - X[3];
+    bool uni = hx0 > 0 && hy0 > 0;
+    const double tol = 1e-9;
+    for (int64_t e = 0; e < E && uni; ++e) {
+      const double* c = X + e * 8;
+      const double hx = c[2] - c[0], hy = c[7] - c[1];
+      uni = std::fabs(c[3] - c[1]) <= tol * hy0 && std::fabs(c[4] - c[2]) <= tol * hx0 &&
+            std::fabs(c[5] - c[7]) <= tol * hy0 && std::fabs(c[6] - c[0]) <= tol * hx0 &&
+            std::fabs(hx - hx0) <= tol * hx0 && std::fabs(hy - hy0) <= tol * hy0;
+    }
+    m->uniform = uni ? 1 : 0;
+    if (uni) { m->hx = hx0; m->hy = hy0; m->he = std::sqrt(hx0 * hx0 + hy0 * hy0); }
+  }
+
+  // ---- DG face neighbours ----
+  if (d->space == CVW_DG) {
+    struct FK { int64_t key; int32_t ef; };
+    std::vector<FK> keys(E * nf);
+    for (int64_t e = 0; e < E; ++e)
+      for (int f = 0; f < nf; ++f) {
+        int64_t key;
+        if (ve == 2) {
+          key = d->cell_vertices[e * 2 + f];
+        } else {
+          const int64_t v0 = d->cell_vertices[e * ve + f], v1 = d->cell_vertices[e * ve + (f + 1) % ve];
+          key = std::min(v0, v1) * Nv + std::max(v0, v1);
+        }
+        keys[e * nf + f] = {key, static_cast<int32_t>(e * nf + f)};
+      }
+    std::sort(keys.begin(), keys.end(), [](const FK& x, const FK& y) { return x.key < y.key || (x.key == y.key && x.ef < y.ef); });
+    m->h_nbr.assign(E * nf, -1);
+    m->h_nbr_face.assign(E * nf, -1);
+    for (size_t i = 0; i < keys.size();) {
+      size_t j = i;
+      while (j + 1 < keys.size() && keys[j + 1].key == keys[i].key) ++j;
+      if (j - i + 1 > 2) { free_mesh(m); set_error("non-conforming mesh: face shared by more than two cells"); return CVW_EINVAL; }
+      if (j == i + 1) {
+        const int32_t a = keys[i].ef, b = keys[j].ef;
+        const int32_t ea = a / nf, fa = a % nf, eb = b / nf, fb = b % nf;
+        if (ve > 2) {
+          const int32_t a0 = d->cell_vertices[ea * ve + fa], a1 = d->cell_vertices[ea * ve + (fa + 1) % ve];
+          const int32_t b0 = d->cell_vertices[eb * ve + fb], b1 = d->cell_vertices[eb * ve + (fb + 1) % ve];
+          if (!(a0 == b1 && a1 == b0)) { free_mesh(m); set_error("inconsistently oriented shared face"); return CVW_EINVAL; }
+        }
+        m->h_nbr[a] = eb; m->h_nbr_face[a] = fb;
+        m->h_nbr[b] = ea; m->h_nbr_face[b] = fa;
+      }
+      i = j + 1;
+    }
+    m->closed = std::all_of(m->h_nbr.begin(), m->h_nbr.end(), [](int32_t x) { return x >= 0; }) ? 1 : 0;
+    if (m->cell == CVW_SEG && m->closed) {
+      // the 1D kernels read the neighbour across face f through its face 1 - f
+      for (int64_t i = 0; i < E * 2; ++i)
+        if (m->h_nbr_face[i] != 1 - (i % 2)) { m->closed = 0; break; }
+    }
+    if (m->cell == CVW_QUAD && m->closed) {
+      // the structured DG path reads the neighbour across face f through its face (f + 2) mod 4
+      for (int64_t i = 0; i < E * 4; ++i)
+        if (m->h_nbr_face[i] != (i % 4 + 2) % 4) { m->uniform = 0; break; }
+    }
+  }
+
+  // ---- CG numbering, DOF patches, per-cell geometry ----
+  std::vector<int32_t> dptr, dent;
+  std::vector<float> geo, hef;
+  if (d->space == CVW_CG) {
+    if (d->cell == CVW_TRI) { free_mesh(m); set_error("CG on triangles is not implemented"); return CVW_EUNSUPPORTED; }
+    cg_number(m, d->cell_vertices);
+    std::vector<int32_t> dc(m->ndof, 0);
+    for (int32_t v : m->h_cell_dof) ++dc[v];
+    dptr.assign(m->ndof + 1, 0);
+    for (int64_t i = 0; i < m->ndof; ++i) dptr[i + 1] = dptr[i] + dc[i];
+    dent.assign(E * m->nloc, 0);
+    std::vector<int32_t> fp(dptr.begin(), dptr.end() - 1);
+    for (int64_t e = 0; e < E; ++e)
+      for (int j = 0; j < m->nloc; ++j) dent[fp[m->h_cell_dof[e * m->nloc + j]]++] = static_cast<int32_t>(e * 16 + j);
+  }
+  if (d->dim == 2) {
+    geo.assign(E * 8, 0.0f);
+    for (int64_t e = 0; e < E; ++e) {
+      const double* X = d->cell_coords + e * ve * 2;
+      geo[e * 8] = static_cast<float>(X[0]);
+      geo[e * 8 + 1] = static_cast<float>(X[1]);
+      for (int v = 1; v < ve && v < 4; ++v) {
+        geo[e * 8 + 2 * v] = static_cast<float>(X[2 * v] - X[0]);
+        geo[e * 8 + 2 * v + 1] = static_cast<float>(X[2 * v + 1] - X[1]);
+      }
+    }
+  }
+  hef.assign(m->h_he.begin(), m->h_he.end());
+
+  // ---- reference tables ----
+  if (d->cell == CVW_QUAD || d->cell == CVW_SEG)
+    fill_tensor_tables(m->tens, std::min(p, MAXP), d->space == CVW_CG);
+  if (d->space == CVW_CG && p <= 2) fill_cg_tables(m->cgt, p);
+
+  // ---- upload ----
+  cvw_status st;
+  std::vector<int32_t> ptr32(m->h_vtx_ptr.begin(), m->h_vtx_ptr.end());
+  if ((st = upload(&m->d_vtx_ptr, ptr32)) != CVW_OK) { free_mesh(m); return st; }
+  if ((st = upload(&m->d_vtx_ent, ent)) != CVW_OK) { free_mesh(m); return st; }
+  if ((st = upload(&m->d_cell_vtx, m->h_cell_vtx)) != CVW_OK) { free_mesh(m); return st; }
+  if ((st = upload(&m->d_nbr, m->h_nbr)) != CVW_OK) { free_mesh(m); return st; }
+  if ((st = upload(&m->d_cell_dof, m->h_cell_dof)) != CVW_OK) { free_mesh(m); return st; }
+  if ((st = upload(&m->d_dof_ptr, dptr)) != CVW_OK) { free_mesh(m); return st; }
+  if ((st = upload(&m->d_dof_ent, dent)) != CVW_OK) { free_mesh(m); return st; }
+  if ((st = upload(&m->d_geo, geo)) != CVW_OK) { free_mesh(m); return st; }
+  if ((st = upload(&m->d_he, hef)) != CVW_OK) { free_mesh(m); return st; }
+  {
+    std::vector<CGTables> t1(1, m->cgt);
+    if ((st = upload(&m->d_cgt, t1)) != CVW_OK) { free_mesh(m); return st; }
+  }
+  if (d->cell == CVW_SEG) {
+    std::vector<double> hc(E);
+    for (int64_t e = 0; e < E; ++e) hc[e] = d->cell_coords[e * 2 + 1] - d->cell_coords[e * 2];
+    for (int64_t e = 0; e < E; ++e)
+      if (!(hc[e] > 0)) { free_mesh(m); set_error("segment cells must have x1 > x0"); return CVW_EINVAL; }
+    if ((st = upload(&m->d_hcell, hc)) != CVW_OK) { free_mesh(m); return st; }
+    std::vector<SegTables> t1(1);
+    fill_seg_tables(t1[0], std::min(p, MAXP), d->space == CVW_CG);
+    if ((st = upload(&m->d_segt, t1)) != CVW_OK) { free_mesh(m); return st; }
+  }
+  if (hipMalloc(reinterpret_cast<void**>(&m->d_tens), sizeof(TensorTables)) != hipSuccess) {
+    free_mesh(m); set_error("hipMalloc failed"); return CVW_ENOMEM;
+  }
+  if (hipMemcpy(m->d_tens, &m->tens, sizeof(TensorTables), hipMemcpyHostToDevice) != hipSuccess) {
+    free_mesh(m); set_error("hipMemcpy failed"); return CVW_EDEVICE;
+  }
+  *out = m;
+  return CVW_OK;
+}
+
+cvw_status cvw_mesh_get_info(const cvw_mesh* m, cvw_mesh_info* info) {
+  if (!m || !info) { set_error("null argument"); return CVW_EINVAL; }
+  info->n_cells = m->E; info->n_vertices = m->Nv; info->n_dof = m->ndof; info->nnz_vertex = m->nnz;
+  info->n_loc = m->nloc; info->n_k = m->nk; info->n_q = m->nq; info->v_e = m->ve; info->n_faces = m->nf;
+  info->uniform = m->uniform; info->hx = m->hx; info->hy = m->hy;
+  return CVW_OK;
+}
+
+cvw_status cvw_mesh_export(const cvw_mesh* m, int which, void* dst, size_t bytes) {
+  if (!m || !dst) { set_error("null argument"); return CVW_EINVAL; }
+  const std::vector<int32_t>* src = nullptr;
+  switch (which) {
+    case CVW_EXPORT_VTX_PTR: src = &m->h_vtx_ptr; break;
+    case CVW_EXPORT_VTX_CELL: src = &m->h_vtx_cell; break;
+    case CVW_EXPORT_VTX_LV: src = &m->h_vtx_lv; break;
+    case CVW_EXPORT_NBR: src = &m->h_nbr; break;
+    case CVW_EXPORT_NBR_FACE: src = &m->h_nbr_face; break;
+    case CVW_EXPORT_CELL_DOF: src = &m->h_cell_dof; break;
+    default: set_error("unknown export selector"); return CVW_EINVAL;
+  }
+  if (bytes != src->size() * sizeof(int32_t)) { set_error("export size mismatch"); return CVW_EINVAL; }
+  std::memcpy(dst, src->data(), bytes);
+  return CVW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace: [status 256 B][candidates n_k * Nv][stage 1][stage 2]
+// ---------------------------------------------------------------------------
+static size_t state_elems(const cvw_mesh* m, int nv) {
+  return static_cast<size_t>(nv) * (m->space == CVW_DG ? static_cast<size_t>(m->E) * m->nloc : static_cast<size_t>(m->ndof));
+}
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static size_t cg_extra(const cvw_mesh* m, size_t es) {
+  if (m->space != CVW_CG) return 0;
+  return align256(2 * static_cast<size_t>(m->ndof) * es) + align256(static_cast<size_t>(m->E) * m->nloc * es);
+}
+
+size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
+  if (!m || !prm) return 0;
+  const size_t es = prm->dtype == CVW_F64 ? 8 : 4;
+  size_t b = 256 + align256(static_cast<size_t>(m->nk) * m->Nv * es) + cg_extra(m, es);
+  if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
+  return b;
+}
+
+static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t ws_bytes, int op, void* ws) {
+  if (!m || !prm) { set_error("null argument"); return CVW_EINVAL; }
+  if (!ws) { set_error("null workspace"); return CVW_EINVAL; }
+  if (ws_bytes < cvw_workspace_bytes(m, prm, op)) { set_error("workspace too small"); return CVW_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(ws) % 256) { set_error("workspace must be 256-byte aligned"); return CVW_EINVAL; }
+  if (prm->flux < 0 || prm->flux > CVW_EULER) { set_error("unknown flux"); return CVW_EINVAL; }
+  if (prm->sensor != CVW_SENSOR_PLAIN && prm->sensor != CVW_SENSOR_FIXED) {
+    set_error("learned sensor not available through this entry point"); return CVW_EUNSUPPORTED;
+  }
+  if (!(prm->eps_vertex > 0) || !(prm->eps_cell > 0) || prm->r < 1 || !(prm->q_sensor >= 1) || !(prm->q_beta >= 1) ||
+      !(prm->lin_w_vertex > 0) || !(prm->lin_w_vertex * m->ve < 1)) {
+    set_error("invalid method parameters"); return CVW_EINVAL;
+  }
+  const bool dgq = m->cell == CVW_QUAD && m->space == CVW_DG;
+  const bool cgq = m->cell == CVW_QUAD && m->space == CVW_CG;
+  const bool seg = m->cell == CVW_SEG;
+  if (!dgq && !cgq && !seg) { set_error("this cell / space combination is not on the GPU path yet"); return CVW_EUNSUPPORTED; }
+  if (seg) {
+    if (m->degree > MAXP) { set_error("degree > 3 not on the GPU path"); return CVW_EUNSUPPORTED; }
+    if (prm->flux != CVW_ADVECT_CONST && prm->flux != CVW_BURGERS) {
+      set_error("1D path: constant-velocity advection and Burgers only"); return CVW_EUNSUPPORTED;
+    }
+    if (m->space == CVW_DG && !m->closed) { set_error("1D DG residual needs a periodic mesh"); return CVW_EUNSUPPORTED; }
+    if (op == 1) { set_error("time stepping on the 1D path is not implemented"); return CVW_EUNSUPPORTED; }
+  }
+  if (cgq) {
+    if (m->degree > 2) { set_error("CG quadrilaterals: degree <= 2 on the GPU path"); return CVW_EUNSUPPORTED; }
+    if (prm->dtype != CVW_F32) { set_error("CG quadrilaterals run in float32"); return CVW_EUNSUPPORTED; }
+    if (prm->flux == CVW_EULER) { set_error("systems are not on the CG quadrilateral path"); return CVW_EUNSUPPORTED; }
+    if (op == 1) { set_error("time stepping with the consistent CG mass is not on the GPU path"); return CVW_EUNSUPPORTED; }
+  }
+  if (dgq) {
+    if (!m->uniform) { set_error("DG quadrilaterals: only congruent axis-aligned cells"); return CVW_EUNSUPPORTED; }
+    if (m->degree > MAXP) { set_error("degree > 3 not on the GPU path"); return CVW_EUNSUPPORTED; }
+    if (prm->dtype != CVW_F32) { set_error("DG quadrilaterals run in float32"); return CVW_EUNSUPPORTED; }
+    if (prm->flux == CVW_ADVECT_ROT) { set_error("rotating velocity not on the DG quadrilateral path"); return CVW_EUNSUPPORTED; }
+    if (!m->closed) { set_error("DG residual needs a mesh without boundary faces"); return CVW_EUNSUPPORTED; }
+  }
+  return CVW_OK;
+}
+
+struct WS {
+  uint32_t* status;
+  void* cand;
+  void* pg;
+  void* rcell;
+  void* st1;
+  void* st2;
+};
+static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
+  const size_t es = prm->dtype == CVW_F64 ? 8 : 4;
+  char* p = static_cast<char*>(ws);
+  WS w{};
+  w.status = reinterpret_cast<uint32_t*>(p);
+  p += 256;
+  w.cand = p;
+  p += align256(static_cast<size_t>(m->nk) * m->Nv * es);
+  if (m->space == CVW_CG) {
+    w.pg = p;
+    p += align256(2 * static_cast<size_t>(m->ndof) * es);
+    w.rcell = p;
+    p += align256(static_cast<size_t>(m->E) * m->nloc * es);
+  }
+  w.st1 = p;
+  p += align256(state_elems(m, n_var_of(prm->flux)) * es);
+  w.st2 = p;
+  return w;
+}
+
+static cvw_status candidates_any(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand,
+                                 hipStream_t s) {
+  if (m->cell == CVW_SEG) return seg_candidates(m, prm, u, cand, s);
+  if (m->space == CVW_CG)
+    return cgquad_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
+  return dgquad_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
+}
+
+cvw_status cvw_vertex_candidates(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
+  if (st != CVW_OK) return st;
+  if (!u || !cand) { set_error("null device pointer"); return CVW_EINVAL; }
+  return candidates_any(m, prm, u, cand, static_cast<hipStream_t>(stream));
+}
+
+cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, void* gamma, void* alpha, void* ws,
+                      size_t ws_bytes, void* stream) {
+  cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
+  if (st != CVW_OK) return st;
+  if (!u || !gamma) { set_error("null device pointer"); return CVW_EINVAL; }
+  const WS w = carve(m, prm, ws);
+  auto s = static_cast<hipStream_t>(stream);
+  if (prm->sensor == CVW_SENSOR_PLAIN) {
+    st = candidates_any(m, prm, u, w.cand, s);
+    if (st != CVW_OK) return st;
+  }
+  if (m->cell == CVW_SEG)
+    return seg_eval(m, prm, MODE_SENSOR, u, w.cand, w.pg, w.rcell, nullptr, gamma, alpha, w.status, s);
+  if (m->space == CVW_CG)
+    return cgquad_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), static_cast<const float*>(w.cand),
+                       static_cast<float*>(w.pg), static_cast<float*>(w.rcell), nullptr, static_cast<float*>(gamma),
+                       static_cast<float*>(alpha), w.status, s);
+  return dgquad_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
+                     static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s);
+}
+
+cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u, void* R, void* gamma_out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
+  if (st != CVW_OK) return st;
+  if (!u || !R) { set_error("null device pointer"); return CVW_EINVAL; }
+  if (u == R) { set_error("R must not alias u"); return CVW_EINVAL; }
+  const WS w = carve(m, prm, ws);
+  auto s = static_cast<hipStream_t>(stream);
+  if (prm->sensor == CVW_SENSOR_PLAIN) {
+    st = candidates_any(m, prm, u, w.cand, s);
+    if (st != CVW_OK) return st;
+  }
+  if (m->cell == CVW_SEG)
+    return seg_eval(m, prm, MODE_RESIDUAL, u, w.cand, w.pg, w.rcell, R, gamma_out, nullptr, w.status, s);
+  if (m->space == CVW_CG)
+    return cgquad_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), static_cast<const float*>(w.cand),
+                       static_cast<float*>(w.pg), static_cast<float*>(w.rcell), static_cast<float*>(R),
+                       static_cast<float*>(gamma_out), nullptr, w.status, s);
+  return dgquad_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
+                     static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
+                     0.f, s);
+}
+
+cvw_status cvw_rk_stage(const cvw_mesh* m, const cvw_params* prm, const void* u_stage, const void* cand,
+                        const void* u_n, void* u_out, double dt, double a0, double b0, void* ws, size_t ws_bytes,
+                        void* stream) {
+  cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
+  if (st != CVW_OK) return st;
+  if (m->space == CVW_CG || m->cell != CVW_QUAD) { set_error("Runge-Kutta stages are implemented for DG quadrilaterals"); return CVW_EUNSUPPORTED; }
+  if (!u_stage || !cand || !u_out || (a0 != 0.0 && !u_n)) { set_error("null device pointer"); return CVW_EINVAL; }
+  if (u_out == u_stage || u_out == cand) { set_error("u_out must not alias u_stage or cand"); return CVW_EINVAL; }
+  if (!std::isfinite(dt) || !std::isfinite(a0) || !std::isfinite(b0)) { set_error("non-finite stage coefficients"); return CVW_EINVAL; }
+  const WS w = carve(m, prm, ws);
+  return dgquad_eval(m, prm, MODE_STAGE, static_cast<const float*>(u_stage), static_cast<const float*>(u_n),
+                     static_cast<float*>(u_out), nullptr, nullptr, static_cast<const float*>(cand), w.status,
+                     static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0),
+                     static_cast<hipStream_t>(stream));
+}
+
+cvw_status cvw_step(const cvw_mesh* m, const cvw_params* prm, void* u, double dt, int n_steps, void* ws,
+                    size_t ws_bytes, void* stream) {
+  cvw_status st = check_common(m, prm, ws_bytes, 1, ws);
+  if (st != CVW_OK) return st;
+  if (!u) { set_error("null device pointer"); return CVW_EINVAL; }
+  if (n_steps < 0 || !(dt > 0) || !std::isfinite(dt)) { set_error("bad dt or step count"); return CVW_EINVAL; }
+  const WS w = carve(m, prm, ws);
+  auto s = static_cast<hipStream_t>(stream);
+  float* U = static_cast<float*>(u);
+  float* U1 = static_cast<float*>(w.st1);
+  float* U2 = static_cast<float*>(w.st2);
+  const float fdt = static_cast<float>(dt);
+  // SSP-RK3 in Shu-Osher form
+  const struct { const float* in; float* out; float a0, b0; } stages[3] = {
+      {U, U1, 0.0f, 1.0f}, {U1, U2, 0.75f, 0.25f}, {U2, U, 1.0f / 3.0f, 2.0f / 3.0f}};
+  for (int n = 0; n < n_steps; ++n)
+    for (const auto& sg : stages) {
+      if (prm->sensor == CVW_SENSOR_PLAIN) {
+        st = dgquad_candidates(m, prm, sg.in, static_cast<float*>(w.cand), s);
+        if (st != CVW_OK) return st;
+      }
+      st = dgquad_eval(m, prm, MODE_STAGE, sg.in, U, sg.out, nullptr, nullptr, static_cast<const float*>(w.cand),
+                       w.status, fdt, sg.a0, sg.b0, s);
+      if (st != CVW_OK) return st;
+    }
+  return CVW_OK;
+}
+
+cvw_status cvw_poll_status(const cvw_mesh* m, void* ws, size_t ws_bytes, uint32_t* flags, void* stream) {
+  if (!m || !ws || !flags || ws_bytes < 256) { set_error("bad argument"); return CVW_EINVAL; }
+  auto s = static_cast<hipStream_t>(stream);
+  uint32_t h = 0;
+  CVW_HIP(hipMemcpyAsync(&h, ws, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  CVW_HIP(hipStreamSynchronize(s));
+  const uint32_t zero = 0;
+  CVW_HIP(hipMemcpyAsync(ws, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  CVW_HIP(hipStreamSynchronize(s));
+  *flags = h;
+  return h ? CVW_ENUMERIC : CVW_OK;
+}
+
+cvw_status cvw_totals(const cvw_mesh* m, const cvw_params* prm, const void* u, double* out_host, void* ws,
+                      size_t ws_bytes, void* stream) {
+  cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
+  if (st != CVW_OK) return st;
+  if (!u || !out_host) { set_error("null pointer"); return CVW_EINVAL; }
+  if (m->space != CVW_DG) { set_error("totals are implemented for the DG path"); return CVW_EUNSUPPORTED; }
+  const int nv = n_var_of(prm->flux);
+  const WS w = carve(m, prm, ws);
+  // partial sums live in the candidate area (n_k * Nv floats >= 2 * 1024 doubles for any mesh
+  // large enough to need more than one block; checked here)
+  const size_t avail = static_cast<size_t>(m->nk) * m->Nv * 4;
+  const size_t need = (static_cast<size_t>(nv) * 1024 + nv) * sizeof(double);
+  if (avail < need) { set_error("mesh too small for the totals scratch"); return CVW_EUNSUPPORTED; }
+  double* part = static_cast<double*>(w.cand);
+  double* res = part + static_cast<size_t>(nv) * 1024;
+  auto s = static_cast<hipStream_t>(stream);
+  st = totals_f32(m, nv, static_cast<const float*>(u), part, res, s);
+  if (st != CVW_OK) return st;
+  CVW_HIP(hipMemcpyAsync(out_host, res, nv * sizeof(double), hipMemcpyDeviceToHost, s));
+  CVW_HIP(hipStreamSynchronize(s));
+  return CVW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal declarations shared by the host side and the kernel launchers of libcvw.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cvw.h"
+
+namespace cvw {
+
+// status bits of the workspace status word
+enum : uint32_t { ST_NONFINITE = 1u, ST_NONPOSITIVE = 2u };
+
+// operation modes of the evaluation kernels
+enum Mode : int { MODE_SENSOR = 0, MODE_RESIDUAL = 1, MODE_STAGE = 2 };
+
+constexpr int MAXP = 3;   // highest degree of the GPU path
+
+// Reference tables of a tensor-product element of degree p on [-1, 1]
+// (nodes: Gauss-Legendre for DG, Gauss-Lobatto for CG).  Filled on the host.
+struct TensorTables {
+  float xi[MAXP + 1];                 // 1D nodes
+  float w[MAXP + 1];                  // 1D Gauss weights of the volume rule (p+1 points)
+  float D[MAXP + 1][MAXP + 1][MAXP + 1];  // D[m][a][i] = l_i^{(m)}(xi_a)
+  float B[2][MAXP + 1];               // B[0][i] = l_i(-1), B[1][i] = l_i(+1)
+  float L[MAXP + 1][MAXP + 1];        // L[m][i] = l_i^{(m)}(-1)
+  // float64 copies for the smoothness-sensor derivatives (high derivatives of
+  // smooth data cancel: table rounding must not multiply the full data)
+  double Dd[MAXP + 1][MAXP + 1][MAXP + 1];
+  double Ld[MAXP + 1][MAXP + 1];
+};
+
+// Reference tables of a tensor-product CG element (Gauss-Lobatto nodes) of
+// degree p <= 2 for the bilinear-map path: Gauss volume rule (p+1 points),
+// Gauss semi-norm rule (p+2 points), derivatives up to order 2.
+struct CGTables {
+  float xn[MAXP + 1];                      // 1D nodes
+  float xv[MAXP + 1], wv[MAXP + 1];        // volume rule
+  float xs[MAXP + 2], ws[MAXP + 2];        // semi-norm rule
+  float Dv[3][MAXP + 1][MAXP + 1];         // Dv[m][q][i] = l_i^{(m)}(xv_q)
+  float Ds[3][MAXP + 2][MAXP + 1];         // Ds[m][q][i] = l_i^{(m)}(xs_q)
+  float Dn[MAXP + 1][MAXP + 1];            // Dn[a][i] = l_i'(xn_a)
+  float Lm[3][MAXP + 1];                   // l_i^{(m)}(-1)
+  float Lp[3][MAXP + 1];                   // l_i^{(m)}(+1)
+  double Dsd[3][MAXP + 2][MAXP + 1];       // float64 copies for the sensor path
+  double Dvd[3][MAXP + 1][MAXP + 1];
+  double Lmd[3][MAXP + 1];
+  double Lpd[3][MAXP + 1];
+};
+
+// Reference tables of a 1D element (float64).
+struct SegTables {
+  double xn[MAXP + 1];                     // nodes (Gauss-Lobatto for CG, Gauss for DG)
+  double xq[MAXP + 1], wq[MAXP + 1];       // (p+1)-point Gauss rule
+  double D[MAXP + 1][MAXP + 1][MAXP + 1];  // D[m][q][i] = l_i^{(m)}(xq_q)
+  double Dn[MAXP + 1][MAXP + 1];           // Dn[a][i] = l_i'(xn_a)
+  double Lv[2][MAXP + 1][MAXP + 1];        // Lv[s][m][i] = l_i^{(m)}(-1) (s = 0), (+1) (s = 1)
+};
+
+// Scalars of the method in the precision of the kernels.
+struct MethodScalars {
+  float eps_v, eps_c, r, q_sensor, q_beta, lin_w, c_gamma, lam_g;
+  float fp[4];                        // flux parameters
+  int sc_on, fast_exp, sensor_kind;   // fast_exp: r == 2 and q == 1
+  float fixed_gamma;
+  // float64 copies for the float64 sensor paths
+  double eps_vd, eps_cd, lin_wd, c_gammad, lam_gd, fixed_gammad, fpd[4];
+};
+
+}  // namespace cvw
+
+struct cvw_mesh {
+  int dim = 0, cell = 0, degree = 0, space = 0;
+  int64_t E = 0, Nv = 0, ndof = 0, nnz = 0;
+  int nloc = 0, nk = 0, nq = 0, ve = 0, nf = 0;
+  int uniform = 0;
+  int closed = 0;                    // DG: every face has a neighbour
+  double hx = 0, hy = 0, he = 0;
+  int device = 0;
+  // host copies
+  std::vector<int32_t> h_vtx_ptr, h_vtx_cell, h_vtx_lv, h_cell_vtx, h_nbr, h_nbr_face, h_cell_dof;
+  std::vector<double> h_coords;      // [E][ve][dim]
+  std::vector<double> h_he;          // [E]
+  cvw::TensorTables tens{};
+  // device arrays (owned)
+  int32_t* d_vtx_ptr = nullptr;      // [Nv + 1]
+  int32_t* d_vtx_ent = nullptr;      // [nnz] packed cell * ve + lv
+  int32_t* d_cell_vtx = nullptr;     // [E][ve]
+  int32_t* d_nbr = nullptr;          // [E][nf]
+  cvw::TensorTables* d_tens = nullptr;
+  // CG
+  int32_t* d_cell_dof = nullptr;     // [E][nloc]
+  int32_t* d_dof_ptr = nullptr;      // [ndof + 1] CSR of the DOF patches
+  int32_t* d_dof_ent = nullptr;      // [E * nloc] packed cell * 16 + local node, ascending (cell, node)
+  float* d_geo = nullptr;            // [E][8] vertex 0 and the other vertices relative to it
+  float* d_he = nullptr;             // [E] diam K_e
+  cvw::CGTables cgt{};
+  cvw::CGTables* d_cgt = nullptr;
+  // 1D
+  double* d_hcell = nullptr;          // [E] cell length
+  cvw::SegTables* d_segt = nullptr;
+};
+
+namespace cvw {
+
+void set_error(const std::string& msg);
+MethodScalars make_scalars(const cvw_params* prm);
+int n_var_of(int flux);
+
+// kernel launchers (cvw_dgquad.hip)
+cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand,
+                             hipStream_t s);
+cvw_status dgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0,
+                       float* out, float* gamma, float* alpha, const float* cand, uint32_t* status,
+                       float dt, float a0, float b0, hipStream_t s);
+// kernel launchers (cvw_cgquad.hip)
+cvw_status cgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
+cvw_status cgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* cand,
+                       float* pg, float* rcell, float* R, float* gamma, float* alpha, uint32_t* status,
+                       hipStream_t s);
+// kernel launchers (cvw_seg.hip)
+cvw_status seg_candidates(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand, hipStream_t s);
+cvw_status seg_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const void* u, const void* cand, void* pg,
+                    void* rcell, void* R, void* gamma, void* alpha, uint32_t* status, hipStream_t s);
+cvw_status totals_f32(const cvw_mesh* m, int nvar, const float* u, double* partial, double* out_dev,
+                      hipStream_t s);
+
+}  // namespace cvw

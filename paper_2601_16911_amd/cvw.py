@@ -1,0 +1,220 @@
+"""ctypes binding of libcvw.so (argument marshalling only).
+
+Every computation runs in the HIP kernels behind the C ABI declared in
+include/cvw.h; this module converts numpy / torch objects to plain pointers
+and sizes and raises on a non-zero status.  Importing it does not need a GPU;
+calling anything that touches device memory does.  There is no CPU fallback:
+if the library is missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcvw.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENUMERIC = range(6)
+SEG, TRI, QUAD = 1, 2, 3
+CG, DG = 0, 1
+F32, F64 = 0, 1
+EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXPORT_CELL_DOF = range(6)
+
+SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
+           "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_residual",
+           "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals"]
+
+
+class CvwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"cvw status {status}: {msg}")
+        self.status = status
+
+
+class MeshDescC(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("cell", C.c_int32), ("degree", C.c_int32), ("space", C.c_int32),
+                ("n_cells", C.c_int64), ("n_vertices", C.c_int64), ("cell_vertices", C.c_void_p),
+                ("cell_coords", C.c_void_p), ("periodic", C.c_int32 * 2)]
+
+
+class ParamsC(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("flux", C.c_int32), ("flux_param", C.c_double * 4),
+                ("eps_vertex", C.c_double), ("eps_cell", C.c_double), ("r", C.c_int32), ("sc_on", C.c_int32),
+                ("q_sensor", C.c_double), ("q_beta", C.c_double), ("lin_w_vertex", C.c_double),
+                ("c_gamma", C.c_double), ("lambda_global", C.c_double), ("sensor", C.c_int32),
+                ("pad0", C.c_int32), ("fixed_gamma", C.c_double)]
+
+
+class MeshInfoC(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_vertices", C.c_int64), ("n_dof", C.c_int64),
+                ("nnz_vertex", C.c_int64), ("n_loc", C.c_int32), ("n_k", C.c_int32), ("n_q", C.c_int32),
+                ("v_e", C.c_int32), ("n_faces", C.c_int32), ("uniform", C.c_int32), ("hx", C.c_double),
+                ("hy", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libcvw.so from the package directory; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_16911_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, sz = C.c_void_p, C.c_size_t
+    lib.cvw_abi_version.restype = C.c_int
+    lib.cvw_last_error.restype = C.c_char_p
+    lib.cvw_mesh_build.argtypes = [C.POINTER(MeshDescC), C.POINTER(vp)]
+    lib.cvw_mesh_destroy.argtypes = [vp]
+    lib.cvw_mesh_destroy.restype = None
+    lib.cvw_mesh_get_info.argtypes = [vp, C.POINTER(MeshInfoC)]
+    lib.cvw_mesh_export.argtypes = [vp, C.c_int, vp, sz]
+    lib.cvw_workspace_bytes.argtypes = [vp, C.POINTER(ParamsC), C.c_int]
+    lib.cvw_workspace_bytes.restype = sz
+    lib.cvw_vertex_candidates.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, sz, vp]
+    lib.cvw_sensor.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, sz, vp]
+    lib.cvw_residual.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, sz, vp]
+    lib.cvw_rk_stage.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
+                                 vp, sz, vp]
+    lib.cvw_step.argtypes = [vp, C.POINTER(ParamsC), vp, C.c_double, C.c_int, vp, sz, vp]
+    lib.cvw_poll_status.argtypes = [vp, vp, sz, C.POINTER(C.c_uint32), vp]
+    lib.cvw_totals.argtypes = [vp, C.POINTER(ParamsC), vp, C.POINTER(C.c_double), vp, sz, vp]
+    for name in SYMBOLS:
+        if name not in ("cvw_abi_version", "cvw_last_error", "cvw_mesh_destroy", "cvw_workspace_bytes"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != OK:
+        raise CvwError(status, load().cvw_last_error().decode())
+
+
+def make_params(prm, dtype: int = F32) -> ParamsC:
+    """Marshal any object with the method-parameter attributes into the C struct."""
+    p = ParamsC()
+    p.dtype = dtype
+    p.flux = int(prm.flux)
+    fp = list(prm.flux_param) + [0.0] * 4
+    for i in range(4):
+        p.flux_param[i] = float(fp[i])
+    p.eps_vertex, p.eps_cell, p.r = float(prm.eps_vertex), float(prm.eps_cell), int(prm.r)
+    p.sc_on = int(prm.sc_on)
+    p.q_sensor, p.q_beta = float(prm.q_sensor), float(prm.q_beta)
+    p.lin_w_vertex, p.c_gamma = float(prm.lin_w_vertex), float(prm.c_gamma)
+    p.lambda_global = float(prm.lambda_global)
+    p.sensor = int(prm.sensor)
+    p.fixed_gamma = float(prm.fixed_gamma)
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+class Mesh:
+    """A mesh built on the current device (owns the device connectivity)."""
+
+    def __init__(self, desc, degree: int, space: int):
+        lib = load()
+        cv = np.ascontiguousarray(desc.cell_vertices, dtype=np.int32)
+        cc = np.ascontiguousarray(desc.cell_coords, dtype=np.float64)
+        d = MeshDescC()
+        d.dim, d.cell, d.degree, d.space = int(desc.dim), int(desc.cell), int(degree), int(space)
+        d.n_cells, d.n_vertices = cv.shape[0], int(desc.n_vertices)
+        d.cell_vertices = cv.ctypes.data
+        d.cell_coords = cc.ctypes.data
+        per = tuple(desc.periodic) + (0, 0)
+        d.periodic[0], d.periodic[1] = int(per[0]), int(per[1])
+        h = C.c_void_p()
+        _check(lib.cvw_mesh_build(C.byref(d), C.byref(h)))
+        self._h = h
+        self.degree, self.space = degree, space
+        info = MeshInfoC()
+        _check(lib.cvw_mesh_get_info(h, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in MeshInfoC._fields_}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self, which: int):
+        sizes = {EXPORT_VTX_PTR: self.info["n_vertices"] + 1, EXPORT_VTX_CELL: self.info["nnz_vertex"],
+                 EXPORT_VTX_LV: self.info["nnz_vertex"],
+                 EXPORT_NBR: self.info["n_cells"] * self.info["n_faces"],
+                 EXPORT_NBR_FACE: self.info["n_cells"] * self.info["n_faces"],
+                 EXPORT_CELL_DOF: self.info["n_cells"] * self.info["n_loc"]}
+        out = np.empty(sizes[which], np.int32)
+        _check(load().cvw_mesh_export(self._h, which, out.ctypes.data, out.nbytes))
+        return out
+
+    def close(self):
+        if self._h:
+            load().cvw_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(mesh: Mesh, prm: ParamsC, op: int) -> int:
+    return int(load().cvw_workspace_bytes(mesh.handle, C.byref(prm), op))
+
+
+def alloc_workspace(mesh: Mesh, prm: ParamsC, op: int, device="cuda"):
+    import torch
+    return torch.zeros(workspace_bytes(mesh, prm, op), dtype=torch.uint8, device=device)
+
+
+def vertex_candidates(mesh, prm, u, cand, ws, stream=None):
+    _check(load().cvw_vertex_candidates(mesh.handle, C.byref(prm), _ptr(u), _ptr(cand), _ptr(ws), ws.numel(),
+                                        _stream(stream)))
+
+
+def sensor(mesh, prm, u, gamma, alpha, ws, stream=None):
+    _check(load().cvw_sensor(mesh.handle, C.byref(prm), _ptr(u), _ptr(gamma), _ptr(alpha), _ptr(ws), ws.numel(),
+                             _stream(stream)))
+
+
+def residual(mesh, prm, u, R, gamma_out, ws, stream=None):
+    _check(load().cvw_residual(mesh.handle, C.byref(prm), _ptr(u), _ptr(R), _ptr(gamma_out), _ptr(ws), ws.numel(),
+                               _stream(stream)))
+
+
+def rk_stage(mesh, prm, u_stage, cand, u_n, u_out, dt: float, a0: float, b0: float, ws, stream=None):
+    _check(load().cvw_rk_stage(mesh.handle, C.byref(prm), _ptr(u_stage), _ptr(cand), _ptr(u_n), _ptr(u_out),
+                               float(dt), float(a0), float(b0), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def step(mesh, prm, u, dt: float, n_steps: int, ws, stream=None):
+    _check(load().cvw_step(mesh.handle, C.byref(prm), _ptr(u), float(dt), int(n_steps), _ptr(ws), ws.numel(),
+                           _stream(stream)))
+
+
+def poll_status(mesh, ws, stream=None) -> int:
+    flags = C.c_uint32(0)
+    st = load().cvw_poll_status(mesh.handle, _ptr(ws), ws.numel(), C.byref(flags), _stream(stream))
+    if st not in (OK, ENUMERIC):
+        _check(st)
+    return int(flags.value)
+
+
+def totals(mesh, prm, u, ws, stream=None, n_var: int = 1):
+    out = (C.c_double * n_var)()
+    _check(load().cvw_totals(mesh.handle, C.byref(prm), _ptr(u), out, _ptr(ws), ws.numel(), _stream(stream)))
+    return np.array(out[:])
