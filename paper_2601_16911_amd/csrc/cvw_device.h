@@ -199,6 +199,50 @@ __device__ __forceinline__ bool state_admissible(const MethodScalars& ms, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// bilinear quadrilateral geometry (vertex 0 absolute, others relative to it)
+// ---------------------------------------------------------------------------
+struct Geo {
+  float x0, y0;          // vertex 0 (absolute)
+  float d[4][2];         // vertex v - vertex 0
+  float h[2];            // d^2 x / dxi deta (constant for a bilinear map)
+};
+
+__device__ __forceinline__ Geo load_geo(const float* __restrict__ g, int64_t e) {
+  Geo G;
+  const float* p = g + e * 8;
+  G.x0 = p[0];
+  G.y0 = p[1];
+  G.d[0][0] = 0.0f;
+  G.d[0][1] = 0.0f;
+  for (int v = 1; v < 4; ++v) {
+    G.d[v][0] = p[2 * v];
+    G.d[v][1] = p[2 * v + 1];
+  }
+  for (int c = 0; c < 2; ++c) G.h[c] = 0.25f * (G.d[0][c] - G.d[1][c] + G.d[2][c] - G.d[3][c]);
+  return G;
+}
+
+// bilinear map at (xi, eta): position relative to vertex 0, Jacobian J[a][b] = dx_a / dxi_b
+__device__ __forceinline__ void geo_eval(const Geo& G, float xi, float eta, float& px, float& py, float J[2][2]) {
+  const float sxv[4] = {-1.f, 1.f, 1.f, -1.f}, syv[4] = {-1.f, -1.f, 1.f, 1.f};
+  px = py = 0.0f;
+  J[0][0] = J[0][1] = J[1][0] = J[1][1] = 0.0f;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const float N = 0.25f * (1.0f + sxv[v] * xi) * (1.0f + syv[v] * eta);
+    const float Nx = 0.25f * sxv[v] * (1.0f + syv[v] * eta);
+    const float Ny = 0.25f * syv[v] * (1.0f + sxv[v] * xi);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      J[c][0] = fmaf(Nx, G.d[v][c], J[c][0]);
+      J[c][1] = fmaf(Ny, G.d[v][c], J[c][1]);
+    }
+    px = fmaf(N, G.d[v][0], px);
+    py = fmaf(N, G.d[v][1], py);
+  }
+}
+
 // XCD-aware block order: consecutive logical blocks land on the same XCD so
 // that a block's neighbours (one grid row away) are served by the same L2.
 __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks_padded) {

@@ -191,47 +191,32 @@ template <int P, int FLUX>
 __global__ __launch_bounds__(256) void dgq_eval_kernel(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
-    const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr,
-    const TensorTables* __restrict__ tabp, TensorTables tab, int64_t E, int64_t nbp, float hx, float hy,
-    float he, MethodScalars ms, int mode, float dt, float a0, float b0, uint32_t* __restrict__ status) {
+    const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* __restrict__ lanes,
+    TensorTables tab, int64_t E, int64_t nbp, float hx, float hy, float he, MethodScalars ms, int mode, float dt,
+    float a0, float b0, uint32_t* __restrict__ status) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr int NV = NVar<FLUX>::value;
   constexpr KSet<P> ks = kset<P>;
+  // per-lane tables: one copy per block in LDS
+  __shared__ LaneRec sl[16];
+  {
+    const float4* src = reinterpret_cast<const float4*>(lanes);
+    float4* dst = reinterpret_cast<float4*>(sl);
+    constexpr int n4 = 16 * sizeof(LaneRec) / 16;
+    for (int i = threadIdx.x; i < n4; i += 256) dst[i] = src[i];
+  }
+  __syncthreads();
   const int tid = threadIdx.x;
   const int q = tid & 15;
   const int a = q & 3, b = q >> 2;
   const int64_t blk = xcd_block(blockIdx.x, nbp);
   const int64_t e = blk * 16 + (tid >> 4);
   if (e >= E) return;                          // whole 16-lane rows leave together
+  const LaneRec& L = sl[q];
   const bool nd = (a <= P) && (b <= P);
   const int node = a + N1 * b;
   const float sx = 2.0f / hx, sy = 2.0f / hy;
-
-  // ---- per-lane table rows -------------------------------------------------
-  int srcb[4];
-  srcb[0] = b;
-  srcb[1] = rroti<1>(b);
-  srcb[2] = rroti<2>(b);
-  srcb[3] = rroti<3>(b);
-  float CX[N1][MAXP + 1], CY[N1][4];
-#pragma unroll
-  for (int m = 0; m < N1; ++m) {
-#pragma unroll
-    for (int ii = 0; ii <= MAXP; ++ii) CX[m][ii] = tabp->D[m][a][ii];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) CY[m][s] = tabp->D[m][b][srcb[s]];
-  }
-  float TX[MAXP + 1], TY[4], BY0[4], BY1[4];
-#pragma unroll
-  for (int c = 0; c <= MAXP; ++c) TX[c] = sx * tabp->D[1][c][a];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    TY[s] = sy * tabp->D[1][srcb[s]][b];
-    BY0[s] = tabp->B[0][srcb[s]];
-    BY1[s] = tabp->B[1][srcb[s]];
-  }
-  const float Ba0 = tabp->B[0][a], Ba1 = tabp->B[1][a], Bb0 = tabp->B[0][b], Bb1 = tabp->B[1][b];
-  const float wa = tabp->w[a], wb = tabp->w[b];
+  const float wa = L.misc[4], wb = L.misc[5];
   const float Wq = nd ? wa * wb * 0.25f * hx * hy : 0.0f;
 
   // ---- state ---------------------------------------------------------------
@@ -242,124 +227,137 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
     if constexpr (FLUX == CVW_EULER) dummy = (v == 0) ? 1.0f : (v == 3 ? 2.5f : 0.0f);
     uv[v] = nd ? u[(static_cast<int64_t>(v) * E + e) * NLOC + node] : dummy;
   }
-  // ---- sensor field derivatives at the own point (eq. taylorsol), float64 ---
-  const double sxd = 2.0 / static_cast<double>(hx), syd = 2.0 / static_cast<double>(hy);
-  // the data is taken relative to its value at node (0, 0), so that constant
-  // data gives exactly zero derivatives (gamma_e = 1, no shock capturing)
+  // vertex candidate data: lane a of each quad fetches vertex a, then quad
+  // broadcasts give every lane all four (eq. taylorcand output)
+  float myc[NK];
+  {
+    const int64_t vid = cell_vtx[e * 4 + a];
+#pragma unroll
+    for (int t = 0; t < NK; ++t) myc[t] = cand[vid * NK + t];
+  }
+
+  // ---- sensor-field derivatives at the own point (eq. taylorsol) ------------
+  // float64: high derivatives of smooth data cancel; the data is taken relative
+  // to its value at node (0, 0) so that constant data gives exactly zero
   double rho = nd ? static_cast<double>(uv[0]) : 0.0;
   {
     const double q0 = qbcastd<0>(rho);
     const double r1 = rrotd<1>(q0), r2 = rrotd<2>(q0), r3 = rrotd<3>(q0);
-    double ref = q0;
-    ref = (srcb[1] == 0) ? r1 : ref;
-    ref = (srcb[2] == 0) ? r2 : ref;
-    ref = (srcb[3] == 0) ? r3 : ref;
+    const double ref = (b == 0) ? q0 : (b == 1) ? r1 : (b == 2) ? r2 : r3;   // row (b - s) & 3 == 0
     rho = nd ? rho - ref : 0.0;
   }
   double Rm[N1];
   Rm[0] = rho;
 #pragma unroll
   for (int m = 1; m < N1; ++m) {
-    double sacc = tabp->Dd[m][a][0] * qbcastd<0>(rho);
-    if constexpr (P >= 1) sacc = fma(tabp->Dd[m][a][1], qbcastd<1>(rho), sacc);
-    if constexpr (P >= 2) sacc = fma(tabp->Dd[m][a][2], qbcastd<2>(rho), sacc);
-    if constexpr (P >= 3) sacc = fma(tabp->Dd[m][a][3], qbcastd<3>(rho), sacc);
+    double sacc = L.DX[m - 1][0] * qbcastd<0>(rho);
+    if constexpr (P >= 1) sacc = fma(L.DX[m - 1][1], qbcastd<1>(rho), sacc);
+    if constexpr (P >= 2) sacc = fma(L.DX[m - 1][2], qbcastd<2>(rho), sacc);
+    if constexpr (P >= 3) sacc = fma(L.DX[m - 1][3], qbcastd<3>(rho), sacc);
     Rm[m] = sacc;
   }
-  double Du[NK];
+  float Du[NK];
+  const double sxd = 2.0 / static_cast<double>(hx), syd = 2.0 / static_cast<double>(hy);
 #pragma unroll
   for (int t = 0; t < NK; ++t) {
     const int kx = ks.x[t], ky = ks.y[t];
-    double sacc = tabp->Dd[ky][b][srcb[0]] * Rm[kx];
-    sacc = fma(tabp->Dd[ky][b][srcb[1]], rrotd<1>(Rm[kx]), sacc);
-    sacc = fma(tabp->Dd[ky][b][srcb[2]], rrotd<2>(Rm[kx]), sacc);
-    sacc = fma(tabp->Dd[ky][b][srcb[3]], rrotd<3>(Rm[kx]), sacc);
-    Du[t] = sacc * dpow(sxd, kx) * dpow(syd, ky);
+    double sacc;
+    if (ky == 0) {
+      sacc = Rm[kx];
+    } else {
+      sacc = L.DY[ky - 1][0] * Rm[kx];
+      sacc = fma(L.DY[ky - 1][1], rrotd<1>(Rm[kx]), sacc);
+      sacc = fma(L.DY[ky - 1][2], rrotd<2>(Rm[kx]), sacc);
+      sacc = fma(L.DY[ky - 1][3], rrotd<3>(Rm[kx]), sacc);
+    }
+    Du[t] = static_cast<float>(sacc * dpow(sxd, kx) * dpow(syd, ky));
   }
-  const double he2 = static_cast<double>(he) * he;
-  double hk[NK], wk[NK];   // h_e^{2|k|} (pointwise) and h_e^{2|k|-2} (element, d = 2)
+  const float he2 = he * he;
+  float hk[NK], wk[NK];   // h_e^{2|k|} (pointwise) and h_e^{2|k|-2} (element, d = 2)
 #pragma unroll
   for (int t = 0; t < NK; ++t) {
-    hk[t] = dpow(he2, ks.x[t] + ks.y[t]);
-    wk[t] = dpow(he2, ks.x[t] + ks.y[t] - 1);
+    hk[t] = ipow(he2, ks.x[t] + ks.y[t]);
+    wk[t] = ipow(he2, ks.x[t] + ks.y[t] - 1);
   }
 
-  // ---- sensor gamma_e -----------------------------------------------------
+  // ---- sensor gamma_e (cell stage of the cell-vertex reconstruction) --------
   float gam;
   if (ms.sensor_kind == CVW_SENSOR_FIXED) {
     gam = ms.fixed_gamma;
   } else {
-    const double xq = tabp->xi[a], yq = tabp->xi[b];
-    const double Wqd = Wq;
-    double n2p = 0.0;
+    const float xq = L.misc[6], yq = L.misc[7];
+    float n2p = 0.0f;
 #pragma unroll
-    for (int t = 0; t < NK; ++t) n2p = fma(Wqd * wk[t] * Du[t], Du[t], n2p);
-    double Ds[4][NK];
-    double b2p[4];
+    for (int t = 0; t < NK; ++t) n2p = fmaf(wk[t] * Du[t], Du[t], n2p);
+    n2p *= Wq;
+    float Ds[4][NK];
+    float b2p[4];
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-      const int vid = cell_vtx[e * 4 + l];
-      const float* cl = cand + static_cast<int64_t>(vid) * NK;
-      double c[NK];
-#pragma unroll
-      for (int t = 0; t < NK; ++t) c[t] = cl[t];
-      const double xl = (l == 1 || l == 2) ? 1.0 : -1.0;
-      const double yl = (l >= 2) ? 1.0 : -1.0;
-      const double dx = (xq - xl) * 0.5 * hx, dy = (yq - yl) * 0.5 * hy;
-      double px[N1], py[N1];
-      px[0] = 1.0;
-      py[0] = 1.0;
-#pragma unroll
-      for (int n = 1; n < N1; ++n) {
-        px[n] = px[n - 1] * dx / n;
-        py[n] = py[n - 1] * dy / n;
-      }
-      double bp = 0.0;
+      float c[NK];
 #pragma unroll
       for (int t = 0; t < NK; ++t) {
-        double sacc = 0.0;
+        if (l == 0) c[t] = qbcast<0>(myc[t]);
+        else if (l == 1) c[t] = qbcast<1>(myc[t]);
+        else if (l == 2) c[t] = qbcast<2>(myc[t]);
+        else c[t] = qbcast<3>(myc[t]);
+      }
+      const float xl = (l == 1 || l == 2) ? 1.0f : -1.0f;
+      const float yl = (l >= 2) ? 1.0f : -1.0f;
+      const float dx = (xq - xl) * 0.5f * hx, dy = (yq - yl) * 0.5f * hy;
+      float px[N1], py[N1];
+      px[0] = 1.0f;
+      py[0] = 1.0f;
+#pragma unroll
+      for (int n = 1; n < N1; ++n) {
+        px[n] = px[n - 1] * dx / static_cast<float>(n);
+        py[n] = py[n - 1] * dy / static_cast<float>(n);
+      }
+      float bp = 0.0f;
+#pragma unroll
+      for (int t = 0; t < NK; ++t) {
+        float sacc = 0.0f;
 #pragma unroll
         for (int t2 = 0; t2 < NK; ++t2) {
           if (ks.x[t2] >= ks.x[t] && ks.y[t2] >= ks.y[t])
-            sacc = fma(c[t2], px[ks.x[t2] - ks.x[t]] * py[ks.y[t2] - ks.y[t]], sacc);
+            sacc = fmaf(c[t2], px[ks.x[t2] - ks.x[t]] * py[ks.y[t2] - ks.y[t]], sacc);
         }
         Ds[l][t] = sacc;
-        bp = fma(wk[t] * sacc, sacc, bp);
+        bp = fmaf(wk[t] * sacc, sacc, bp);
       }
-      b2p[l] = Wqd * bp;
+      b2p[l] = Wq * bp;
     }
-    const double n2 = row_sumd(n2p);
-    double beta[5];
-    beta[0] = sqrt(n2);
+    const float n2 = row_sum(n2p);
+    float beta[5];
+    beta[0] = sqrtf(n2);
 #pragma unroll
-    for (int l = 0; l < 4; ++l) beta[l + 1] = sqrt(row_sumd(b2p[l]));
-    double om[5], osum = 0.0;
+    for (int l = 0; l < 4; ++l) beta[l + 1] = sqrtf(row_sum(b2p[l]));
+    float om[5], osum = 0.0f;
 #pragma unroll
     for (int l = 0; l < 5; ++l) {
-      const double lin = (l == 0) ? 1.0 - 4.0 * ms.lin_wd : ms.lin_wd;
-      double w;
+      const float lin = (l == 0) ? 1.0f - 4.0f * ms.lin_w : ms.lin_w;
+      float w;
       if (ms.fast_exp) {
-        const double den = ms.eps_cd + beta[l];
+        const float den = ms.eps_c + beta[l];
         w = lin / (den * den);
       } else {
-        w = lin * pow(ms.eps_cd + pow(beta[l], static_cast<double>(ms.q_beta)), -static_cast<double>(ms.r));
+        w = lin * powf(ms.eps_c + powf(beta[l], ms.q_beta), -ms.r);
       }
       om[l] = w;
       osum += w;
     }
-    const double oinv = 1.0 / osum;
-    double d2p = 0.0;
+    const float oinv = 1.0f / osum;
+    float d2p = 0.0f;
 #pragma unroll
     for (int t = 0; t < NK; ++t) {
-      double dl = 0.0;
+      float dl = 0.0f;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) dl = fma(om[l + 1] * oinv, Du[t] - Ds[l][t], dl);
-      d2p = fma(Wqd * wk[t] * dl, dl, d2p);
+      for (int l = 0; l < 4; ++l) dl = fmaf(om[l + 1] * oinv, Du[t] - Ds[l][t], dl);
+      d2p = fmaf(wk[t] * dl, dl, d2p);
     }
-    const double d2 = row_sumd(d2p);
-    if (n2 > 0.0) {
-      const float ratio = static_cast<float>(sqrt(d2 / n2));
-      const float mr = fminf(1.0f, ratio);
+    const float d2 = row_sum(Wq * d2p);
+    if (n2 > 0.0f) {
+      const float mr = fminf(1.0f, sqrtf(d2 / n2));
       gam = 1.0f - (ms.fast_exp ? mr : powf(mr, ms.q_sensor));
     } else {
       gam = 1.0f;
@@ -374,11 +372,11 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
     lam = row_max(nd ? wave_speed<FLUX>(ms, uv, 0.0f, 0.0f) : 0.0f);
   }
   const float nu = lam * he / (2.0f * P);
-  double atil2 = 0.0;
+  float atil2 = 0.0f;
 #pragma unroll
-  for (int t = 0; t < NK; ++t) atil2 = fma(hk[t] * Du[t], Du[t], atil2);
-  const float atil = static_cast<float>(sqrt(atil2));
-  const float g2 = static_cast<float>(Du[0] * Du[0] + Du[1] * Du[1]);
+  for (int t = 0; t < NK; ++t) atil2 = fmaf(hk[t] * Du[t], Du[t], atil2);
+  const float atil = sqrtf(atil2);
+  const float g2 = Du[0] * Du[0] + Du[1] * Du[1];
   const float fq = (1.0f - gam) * g2;
   const float S = row_sum(Wq * fq);
   const float T = row_sum(Wq * atil * fq);
@@ -397,110 +395,109 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
   float fx[NV], fy[NV];
   phys_flux<FLUX>(ms, uv, 0.0f, 0.0f, fx, fy);
   float r[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const float uvv = nd ? uv[v] : 0.0f;
-    const float gx = sx * rowsum4<P>(CX[1], uvv);
-    const float gy = sy * colsum4(CY[1], uvv);
-    const float WFx = Wq * (coef * gx - fx[v]);
-    const float WFy = Wq * (coef * gy - fy[v]);
-    float tx[MAXP + 1];
-#pragma unroll
-    for (int c = 0; c <= MAXP; ++c) tx[c] = TX[c];
-    r[v] = rowsum4<P>(tx, WFx) + colsum4(TY, WFy);
-  }
-
-  // ---- interface terms -------------------------------------------------------
-  // own traces on the four faces (every lane computes them; boundary lanes use them)
   float tW[NV], tE[NV], tS[NV], tN[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const float uvv = nd ? uv[v] : 0.0f;
-    float b0r[MAXP + 1], b1r[MAXP + 1];
+    // broadcasts of the own row (x direction) and column (y direction)
+    float rowv[MAXP + 1], colv[4];
 #pragma unroll
-    for (int c = 0; c <= MAXP; ++c) {
-      b0r[c] = tab.B[0][c];
-      b1r[c] = tab.B[1][c];
+    for (int i = 0; i <= P; ++i)
+      rowv[i] = (i == 0) ? qbcast<0>(uvv) : (i == 1) ? qbcast<1>(uvv) : (i == 2) ? qbcast<2>(uvv) : qbcast<3>(uvv);
+    colv[0] = uvv;
+    colv[1] = rrot<1>(uvv);
+    colv[2] = rrot<2>(uvv);
+    colv[3] = rrot<3>(uvv);
+    float gx = 0.0f, gy = 0.0f, sW = 0.0f, sE = 0.0f, sS = 0.0f, sN = 0.0f;
+#pragma unroll
+    for (int i = 0; i <= P; ++i) {
+      gx = fmaf(L.CX1[i], rowv[i], gx);
+      sW = fmaf(tab.B[0][i], rowv[i], sW);
+      sE = fmaf(tab.B[1][i], rowv[i], sE);
     }
-    tW[v] = rowsum4<P>(b0r, uvv);
-    tE[v] = rowsum4<P>(b1r, uvv);
-    tS[v] = colsum4(BY0, uvv);
-    tN[v] = colsum4(BY1, uvv);
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      gy = fmaf(L.CY1[s2], colv[s2], gy);
+      sS = fmaf(L.BY0[s2], colv[s2], sS);
+      sN = fmaf(L.BY1[s2], colv[s2], sN);
+    }
+    tW[v] = sW;
+    tE[v] = sE;
+    tS[v] = sS;
+    tN[v] = sN;
+    const float WFx = Wq * (coef * sx * gx - fx[v]);
+    const float WFy = Wq * (coef * sy * gy - fy[v]);
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c <= P; ++c) {
+      const float wv = (c == 0) ? qbcast<0>(WFx) : (c == 1) ? qbcast<1>(WFx) : (c == 2) ? qbcast<2>(WFx) : qbcast<3>(WFx);
+      acc = fmaf(L.TX[c], wv, acc);
+    }
+    float accy = L.TY[0] * WFy;
+    accy = fmaf(L.TY[1], rrot<1>(WFy), accy);
+    accy = fmaf(L.TY[2], rrot<2>(WFy), accy);
+    accy = fmaf(L.TY[3], rrot<3>(WFy), accy);
+    r[v] = sx * acc + sy * accy;
   }
+
+  // ---- interface terms -------------------------------------------------------
   float fW[NV], fE[NV], fS[NV], fN[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) fW[v] = fE[v] = fS[v] = fN[v] = 0.0f;
   const int64_t stride = E * NLOC;
-  if (nd && a == 0) {
-    const int64_t en = nbr[e * 4 + 3];
+  if (nd && (a == 0 || a == P)) {
+    const bool west = (a == 0);
+    const int64_t en = nbr[e * 4 + (west ? 3 : 1)];
     float up[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const float* un = u + v * stride + en * NLOC + N1 * b;
-      float s = 0.0f;
+      float s2 = 0.0f;
 #pragma unroll
-      for (int ii = 0; ii < N1; ++ii) s = fmaf(tab.B[1][ii], un[ii], s);
-      up[v] = s;
+      for (int ii = 0; ii < N1; ++ii) s2 = fmaf(west ? tab.B[1][ii] : tab.B[0][ii], un[ii], s2);
+      up[v] = s2;
     }
     float fs[NV];
-    num_flux<FLUX>(ms, tW, up, -1.0f, 0.0f, 0.0f, 0.0f, fs);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) fW[v] = wb * 0.5f * hy * fs[v];
-  }
-  if (nd && a == P) {
-    const int64_t en = nbr[e * 4 + 1];
-    float up[NV];
+    num_flux<FLUX>(ms, west ? tW : tE, up, west ? -1.0f : 1.0f, 0.0f, 0.0f, 0.0f, fs);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const float* un = u + v * stride + en * NLOC + N1 * b;
-      float s = 0.0f;
-#pragma unroll
-      for (int ii = 0; ii < N1; ++ii) s = fmaf(tab.B[0][ii], un[ii], s);
-      up[v] = s;
+      if (west) fW[v] = wb * 0.5f * hy * fs[v];
+      else fE[v] = wb * 0.5f * hy * fs[v];
     }
-    float fs[NV];
-    num_flux<FLUX>(ms, tE, up, 1.0f, 0.0f, 0.0f, 0.0f, fs);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) fE[v] = wb * 0.5f * hy * fs[v];
   }
-  if (nd && b == 0) {
-    const int64_t en = nbr[e * 4 + 0];
+  if (nd && (b == 0 || b == P)) {
+    const bool south = (b == 0);
+    const int64_t en = nbr[e * 4 + (south ? 0 : 2)];
     float up[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const float* un = u + v * stride + en * NLOC + a;
-      float s = 0.0f;
+      float s2 = 0.0f;
 #pragma unroll
-      for (int jj = 0; jj < N1; ++jj) s = fmaf(tab.B[1][jj], un[N1 * jj], s);
-      up[v] = s;
+      for (int jj = 0; jj < N1; ++jj) s2 = fmaf(south ? tab.B[1][jj] : tab.B[0][jj], un[N1 * jj], s2);
+      up[v] = s2;
     }
     float fs[NV];
-    num_flux<FLUX>(ms, tS, up, 0.0f, -1.0f, 0.0f, 0.0f, fs);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) fS[v] = wa * 0.5f * hx * fs[v];
-  }
-  if (nd && b == P) {
-    const int64_t en = nbr[e * 4 + 2];
-    float up[NV];
+    num_flux<FLUX>(ms, south ? tS : tN, up, 0.0f, south ? -1.0f : 1.0f, 0.0f, 0.0f, fs);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const float* un = u + v * stride + en * NLOC + a;
-      float s = 0.0f;
-#pragma unroll
-      for (int jj = 0; jj < N1; ++jj) s = fmaf(tab.B[0][jj], un[N1 * jj], s);
-      up[v] = s;
+      if (south) fS[v] = wa * 0.5f * hx * fs[v];
+      else fN[v] = wa * 0.5f * hx * fs[v];
     }
-    float fs[NV];
-    num_flux<FLUX>(ms, tN, up, 0.0f, 1.0f, 0.0f, 0.0f, fs);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) fN[v] = wa * 0.5f * hx * fs[v];
   }
+  // distribute the face fluxes: west / east along the own row, south / north
+  // from row 0 / row P of the own column
+  const int s0 = b & 3, sP = (b - P) & 3;   // rotations that bring row 0 / row P
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    r[v] = fmaf(Ba0, qbcast<0>(fW[v]), r[v]);
-    r[v] = fmaf(Ba1, qbcast<P>(fE[v]), r[v]);
-    r[v] = fmaf(Bb0, colbcast<0>(fS[v], srcb), r[v]);
-    r[v] = fmaf(Bb1, colbcast<P>(fN[v], srcb), r[v]);
+    const float r1 = rrot<1>(fS[v]), r2 = rrot<2>(fS[v]), r3 = rrot<3>(fS[v]);
+    const float fS0 = (s0 == 0) ? fS[v] : (s0 == 1) ? r1 : (s0 == 2) ? r2 : r3;
+    const float n1 = rrot<1>(fN[v]), n2 = rrot<2>(fN[v]), n3 = rrot<3>(fN[v]);
+    const float fNP = (sP == 0) ? fN[v] : (sP == 1) ? n1 : (sP == 2) ? n2 : n3;
+    r[v] = fmaf(L.misc[0], qbcast<0>(fW[v]), r[v]);
+    r[v] = fmaf(L.misc[1], qbcast<P>(fE[v]), r[v]);
+    r[v] = fmaf(L.misc[2], fS0, r[v]);
+    r[v] = fmaf(L.misc[3], fNP, r[v]);
   }
 
   // ---- output -----------------------------------------------------------------
@@ -514,9 +511,9 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
       if (mode == MODE_RESIDUAL) {
         val = r[v];
       } else {
-        const float L = -r[v] / Wq;
+        const float Lv = -r[v] / Wq;
         const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
-        val = base + b0 * (uv[v] + dt * L);
+        val = base + b0 * (uv[v] + dt * Lv);
       }
       nonfinite = nonfinite || !isfinite(val);
       out[idx] = val;
@@ -557,7 +554,7 @@ static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, co
                         float a0, float b0, hipStream_t s) {
   const int64_t nb = pad8((m->E + 15) / 16);
   hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0, out,
-                     gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_tens, m->tens, m->E, nb,
+                     gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, nb,
                      static_cast<float>(m->hx), static_cast<float>(m->hy), static_cast<float>(m->he), ms, mode, dt,
                      a0, b0, status);
 }

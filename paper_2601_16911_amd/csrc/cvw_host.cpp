@@ -156,6 +156,36 @@ static void fill_tensor_tables(TensorTables& T, int p, bool lobatto) {
   }
 }
 
+static void fill_lane_tables(LaneRec* R, const TensorTables& T, int p) {
+  std::memset(R, 0, 16 * sizeof(LaneRec));
+  for (int q = 0; q < 16; ++q) {
+    const int a = q & 3, b = q >> 2;
+    if (a > p || b > p) continue;
+    LaneRec& L = R[q];
+    for (int s = 0; s < 4; ++s) {
+      const int src = (b - s) & 3;         // row brought by a rotation of 4 s lanes
+      L.CX1[s] = static_cast<float>(T.Dd[1][a][s]);
+      L.CY1[s] = static_cast<float>(T.Dd[1][b][src]);
+      L.TX[s] = static_cast<float>(T.Dd[1][s][a]);
+      L.TY[s] = static_cast<float>(T.Dd[1][src][b]);
+      L.BY0[s] = T.B[0][src];
+      L.BY1[s] = T.B[1][src];
+      for (int m = 1; m <= 3; ++m) {
+        L.DX[m - 1][s] = T.Dd[m][a][s];
+        L.DY[m - 1][s] = T.Dd[m][b][src];
+      }
+    }
+    L.misc[0] = T.B[0][a];
+    L.misc[1] = T.B[1][a];
+    L.misc[2] = T.B[0][b];
+    L.misc[3] = T.B[1][b];
+    L.misc[4] = T.w[a];
+    L.misc[5] = T.w[b];
+    L.misc[6] = T.xi[a];
+    L.misc[7] = T.xi[b];
+  }
+}
+
 static void fill_cg_tables(CGTables& T, int p) {
   std::memset(&T, 0, sizeof(T));
   std::vector<double> xn, xv, wv, xs, ws;
@@ -299,6 +329,61 @@ static cvw_status upload(T** dst, const std::vector<T>& src) {
   return CVW_OK;
 }
 
+// Row sums of the mass matrix (CG: the integrals of the nodal basis
+// functions, the lumped mass; 1D DG: the exact, diagonal element mass of the
+// Gauss-node basis), float64.  Empty when the mesh has no time-stepping path.
+static std::vector<double> diag_mass(const cvw_mesh* m, const cvw_mesh_desc* d) {
+  std::vector<double> out;
+  const int p = m->degree;
+  if (p < 1 || p > MAXP) return out;
+  const int64_t E = m->E;
+  if (d->cell == CVW_SEG) {
+    std::vector<double> xq, wq;
+    gauss_rule(p + 1, xq, wq);
+    std::vector<double> xn;
+    if (d->space == CVW_CG) lobatto_nodes(p + 1, xn); else xn = xq;
+    out.assign(d->space == CVW_CG ? m->ndof : E * (p + 1), 0.0);
+    for (int64_t e = 0; e < E; ++e) {
+      const double jac = 0.5 * (d->cell_coords[e * 2 + 1] - d->cell_coords[e * 2]);
+      for (int j = 0; j <= p; ++j) {
+        double s = 0.0;
+        for (int q = 0; q <= p; ++q) s += wq[q] * lagrange_deriv(xn, j, 0, xq[q]);
+        const int64_t I = d->space == CVW_CG ? m->h_cell_dof[e * (p + 1) + j] : e * (p + 1) + j;
+        out[I] += jac * s;
+      }
+    }
+    return out;
+  }
+  if (d->cell == CVW_QUAD && d->space == CVW_CG && p <= 2) {
+    std::vector<double> xq, wq, xn;
+    gauss_rule(p + 1, xq, wq);
+    lobatto_nodes(p + 1, xn);
+    const int N1 = p + 1;
+    const double sxv[4] = {-1, 1, 1, -1}, syv[4] = {-1, -1, 1, 1};
+    out.assign(m->ndof, 0.0);
+    for (int64_t e = 0; e < E; ++e) {
+      const double* X = d->cell_coords + e * 8;
+      for (int qy = 0; qy < N1; ++qy)
+        for (int qx = 0; qx < N1; ++qx) {
+          double J[2][2] = {{0, 0}, {0, 0}};
+          for (int v = 0; v < 4; ++v) {
+            const double Nx = 0.25 * sxv[v] * (1 + syv[v] * xq[qy]), Ny = 0.25 * syv[v] * (1 + sxv[v] * xq[qx]);
+            for (int c = 0; c < 2; ++c) {
+              J[c][0] += Nx * X[2 * v + c];
+              J[c][1] += Ny * X[2 * v + c];
+            }
+          }
+          const double W = wq[qx] * wq[qy] * std::fabs(J[0][0] * J[1][1] - J[0][1] * J[1][0]);
+          for (int b = 0; b < N1; ++b)
+            for (int a = 0; a < N1; ++a)
+              out[m->h_cell_dof[e * N1 * N1 + a + N1 * b]] +=
+                  W * lagrange_deriv(xn, a, 0, xq[qx]) * lagrange_deriv(xn, b, 0, xq[qy]);
+        }
+    }
+  }
+  return out;
+}
+
 static void free_mesh(cvw_mesh* m) {
   if (!m) return;
   (void)hipFree(m->d_vtx_ptr);
@@ -306,6 +391,7 @@ static void free_mesh(cvw_mesh* m) {
   (void)hipFree(m->d_cell_vtx);
   (void)hipFree(m->d_nbr);
   (void)hipFree(m->d_tens);
+  (void)hipFree(m->d_lanes);
   (void)hipFree(m->d_cell_dof);
   (void)hipFree(m->d_dof_ptr);
   (void)hipFree(m->d_dof_ent);
@@ -314,6 +400,8 @@ static void free_mesh(cvw_mesh* m) {
   (void)hipFree(m->d_cgt);
   (void)hipFree(m->d_hcell);
   (void)hipFree(m->d_segt);
+  (void)hipFree(m->d_dinv_f);
+  (void)hipFree(m->d_dinv_d);
   delete m;
 }
 
@@ -513,6 +601,11 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     std::vector<CGTables> t1(1, m->cgt);
     if ((st = upload(&m->d_cgt, t1)) != CVW_OK) { free_mesh(m); return st; }
   }
+  if (d->cell == CVW_QUAD && d->space == CVW_DG && p <= MAXP) {
+    std::vector<LaneRec> lr(16);
+    fill_lane_tables(lr.data(), m->tens, p);
+    if ((st = upload(&m->d_lanes, lr)) != CVW_OK) { free_mesh(m); return st; }
+  }
   if (d->cell == CVW_SEG) {
     std::vector<double> hc(E);
     for (int64_t e = 0; e < E; ++e) hc[e] = d->cell_coords[e * 2 + 1] - d->cell_coords[e * 2];
@@ -522,6 +615,22 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     std::vector<SegTables> t1(1);
     fill_seg_tables(t1[0], std::min(p, MAXP), d->space == CVW_CG);
     if ((st = upload(&m->d_segt, t1)) != CVW_OK) { free_mesh(m); return st; }
+  }
+  {
+    const std::vector<double> dm = diag_mass(m, d);
+    for (double v : dm)
+      if (!(v > 0)) { free_mesh(m); set_error("non-positive lumped mass (degenerate cell)"); return CVW_EINVAL; }
+    if (!dm.empty()) {
+      std::vector<double> inv_d(dm.size());
+      std::vector<float> inv_f(dm.size());
+      for (size_t i = 0; i < dm.size(); ++i) {
+        inv_d[i] = 1.0 / dm[i];
+        inv_f[i] = static_cast<float>(inv_d[i]);
+      }
+      m->n_mass = static_cast<int64_t>(dm.size());
+      if ((st = upload(&m->d_dinv_d, inv_d)) != CVW_OK) { free_mesh(m); return st; }
+      if ((st = upload(&m->d_dinv_f, inv_f)) != CVW_OK) { free_mesh(m); return st; }
+    }
   }
   if (hipMalloc(reinterpret_cast<void**>(&m->d_tens), sizeof(TensorTables)) != hipSuccess) {
     free_mesh(m); set_error("hipMalloc failed"); return CVW_ENOMEM;
@@ -566,15 +675,27 @@ static size_t state_elems(const cvw_mesh* m, int nv) {
 }
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-static size_t cg_extra(const cvw_mesh* m, size_t es) {
-  if (m->space != CVW_CG) return 0;
-  return align256(2 * static_cast<size_t>(m->ndof) * es) + align256(static_cast<size_t>(m->E) * m->nloc * es);
+// true when the mesh has a time-stepping path (stages and steps)
+static bool has_stage(const cvw_mesh* m) { return m->n_mass > 0 || (m->cell == CVW_QUAD && m->space == CVW_DG); }
+
+static size_t cg_extra(const cvw_mesh* m, const cvw_params* prm, size_t es) {
+  size_t b = 0;
+  if (m->space == CVW_CG)
+    b += align256(2 * static_cast<size_t>(m->ndof) * es) + align256(static_cast<size_t>(m->E) * m->nloc * es);
+  if (m->n_mass > 0) {
+    // stage right-hand side R, and for CG the PCG vectors x, r, z, p, Ap and
+    // its block partials and scalars
+    b += align256(state_elems(m, n_var_of(prm->flux)) * es);
+    if (m->space == CVW_CG)
+      b += 5 * align256(static_cast<size_t>(m->ndof) * es) + align256((pcg_partials(m->ndof) + 8) * sizeof(double));
+  }
+  return b;
 }
 
 size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (!m || !prm) return 0;
   const size_t es = prm->dtype == CVW_F64 ? 8 : 4;
-  size_t b = 256 + align256(static_cast<size_t>(m->nk) * m->Nv * es) + cg_extra(m, es);
+  size_t b = 256 + align256(static_cast<size_t>(m->nk) * m->Nv * es) + cg_extra(m, prm, es);
   if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
   return b;
 }
@@ -602,13 +723,11 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
       set_error("1D path: constant-velocity advection and Burgers only"); return CVW_EUNSUPPORTED;
     }
     if (m->space == CVW_DG && !m->closed) { set_error("1D DG residual needs a periodic mesh"); return CVW_EUNSUPPORTED; }
-    if (op == 1) { set_error("time stepping on the 1D path is not implemented"); return CVW_EUNSUPPORTED; }
   }
   if (cgq) {
     if (m->degree > 2) { set_error("CG quadrilaterals: degree <= 2 on the GPU path"); return CVW_EUNSUPPORTED; }
     if (prm->dtype != CVW_F32) { set_error("CG quadrilaterals run in float32"); return CVW_EUNSUPPORTED; }
     if (prm->flux == CVW_EULER) { set_error("systems are not on the CG quadrilateral path"); return CVW_EUNSUPPORTED; }
-    if (op == 1) { set_error("time stepping with the consistent CG mass is not on the GPU path"); return CVW_EUNSUPPORTED; }
   }
   if (dgq) {
     if (!m->uniform) { set_error("DG quadrilaterals: only congruent axis-aligned cells"); return CVW_EUNSUPPORTED; }
@@ -625,6 +744,10 @@ struct WS {
   void* cand;
   void* pg;
   void* rcell;
+  void* rhs;                       // stage right-hand side (R)
+  void* x, *r, *z, *p, *Ap;        // PCG vectors (CG)
+  double* part;                    // PCG block partials, followed by its 8 scalars
+  double* S;
   void* st1;
   void* st2;
 };
@@ -641,6 +764,20 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
     p += align256(2 * static_cast<size_t>(m->ndof) * es);
     w.rcell = p;
     p += align256(static_cast<size_t>(m->E) * m->nloc * es);
+  }
+  if (m->n_mass > 0) {
+    w.rhs = p;
+    p += align256(state_elems(m, n_var_of(prm->flux)) * es);
+    if (m->space == CVW_CG) {
+      void** vecs[5] = {&w.x, &w.r, &w.z, &w.p, &w.Ap};
+      for (void** v : vecs) {
+        *v = p;
+        p += align256(static_cast<size_t>(m->ndof) * es);
+      }
+      w.part = reinterpret_cast<double*>(p);
+      w.S = w.part + pcg_partials(m->ndof);
+      p += align256((pcg_partials(m->ndof) + 8) * sizeof(double));
+    }
   }
   w.st1 = p;
   p += align256(state_elems(m, n_var_of(prm->flux)) * es);
@@ -708,45 +845,93 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
                      0.f, s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Mass-matrix tolerances of the PCG solve (relative, preconditioned norm) and
+// its launch-time iteration cap; converged iterations are no-ops on the device.
+constexpr double PCG_TOL_F32 = 2e-7, PCG_TOL_F64 = 1e-14;
+constexpr int PCG_MAXIT_F32 = 64, PCG_MAXIT_F64 = 160;
+
+template <typename Real>
+cvw_status generic_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, const Real* us, const Real* cand,
+                         const Real* un, Real* uo, double dt, double a0, double b0, hipStream_t s) {
+  cvw_status st;
+  Real* rhs = static_cast<Real*>(w.rhs);
+  if (m->cell == CVW_SEG)
+    st = seg_eval(m, prm, MODE_RESIDUAL, us, cand, w.pg, w.rcell, rhs, nullptr, nullptr, w.status, s);
+  else
+    st = cgquad_eval(m, prm, MODE_RESIDUAL, reinterpret_cast<const float*>(us), reinterpret_cast<const float*>(cand),
+                     static_cast<float*>(w.pg), static_cast<float*>(w.rcell), reinterpret_cast<float*>(rhs), nullptr,
+                     nullptr, w.status, s);
+  if (st != CVW_OK) return st;
+  const bool f64 = std::is_same<Real, double>::value;
+  const Real* dinv = f64 ? reinterpret_cast<const Real*>(m->d_dinv_d) : reinterpret_cast<const Real*>(m->d_dinv_f);
+  const int64_t n = static_cast<int64_t>(state_elems(m, n_var_of(prm->flux)));
+  if (m->space == CVW_CG) {
+    Real* x = static_cast<Real*>(w.x);
+    st = cg_mass_solve<Real>(m, rhs, x, static_cast<Real*>(w.r), static_cast<Real*>(w.z), static_cast<Real*>(w.p),
+                             static_cast<Real*>(w.Ap), static_cast<Real*>(w.rcell), w.part, w.S, dinv,
+                             f64 ? PCG_TOL_F64 : PCG_TOL_F32, f64 ? PCG_MAXIT_F64 : PCG_MAXIT_F32, s);
+    if (st != CVW_OK) return st;
+    return stage_update<Real>(us, un, x, nullptr, uo, a0, b0, dt, n, s);
+  }
+  return stage_update<Real>(us, un, rhs, dinv, uo, a0, b0, dt, n, s);
+}
+
+cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, const void* us, const void* cand,
+                     const void* un, void* uo, double dt, double a0, double b0, hipStream_t s) {
+  if (m->cell == CVW_QUAD && m->space == CVW_DG)
+    return dgquad_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
+                       static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
+                       static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s);
+  if (prm->dtype == CVW_F64)
+    return generic_stage<double>(m, prm, w, static_cast<const double*>(us), static_cast<const double*>(cand),
+                                 static_cast<const double*>(un), static_cast<double*>(uo), dt, a0, b0, s);
+  return generic_stage<float>(m, prm, w, static_cast<const float*>(us), static_cast<const float*>(cand),
+                              static_cast<const float*>(un), static_cast<float*>(uo), dt, a0, b0, s);
+}
+
+}  // namespace
+
+extern "C" {
+
 cvw_status cvw_rk_stage(const cvw_mesh* m, const cvw_params* prm, const void* u_stage, const void* cand,
                         const void* u_n, void* u_out, double dt, double a0, double b0, void* ws, size_t ws_bytes,
                         void* stream) {
   cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
   if (st != CVW_OK) return st;
-  if (m->space == CVW_CG || m->cell != CVW_QUAD) { set_error("Runge-Kutta stages are implemented for DG quadrilaterals"); return CVW_EUNSUPPORTED; }
+  if (!has_stage(m)) { set_error("no Runge-Kutta stage for this mesh (degree out of range)"); return CVW_EUNSUPPORTED; }
   if (!u_stage || !cand || !u_out || (a0 != 0.0 && !u_n)) { set_error("null device pointer"); return CVW_EINVAL; }
   if (u_out == u_stage || u_out == cand) { set_error("u_out must not alias u_stage or cand"); return CVW_EINVAL; }
   if (!std::isfinite(dt) || !std::isfinite(a0) || !std::isfinite(b0)) { set_error("non-finite stage coefficients"); return CVW_EINVAL; }
   const WS w = carve(m, prm, ws);
-  return dgquad_eval(m, prm, MODE_STAGE, static_cast<const float*>(u_stage), static_cast<const float*>(u_n),
-                     static_cast<float*>(u_out), nullptr, nullptr, static_cast<const float*>(cand), w.status,
-                     static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0),
-                     static_cast<hipStream_t>(stream));
+  return any_stage(m, prm, w, u_stage, cand, u_n, u_out, dt, a0, b0, static_cast<hipStream_t>(stream));
 }
 
 cvw_status cvw_step(const cvw_mesh* m, const cvw_params* prm, void* u, double dt, int n_steps, void* ws,
                     size_t ws_bytes, void* stream) {
   cvw_status st = check_common(m, prm, ws_bytes, 1, ws);
   if (st != CVW_OK) return st;
+  if (!has_stage(m)) { set_error("no Runge-Kutta stage for this mesh (degree out of range)"); return CVW_EUNSUPPORTED; }
   if (!u) { set_error("null device pointer"); return CVW_EINVAL; }
   if (n_steps < 0 || !(dt > 0) || !std::isfinite(dt)) { set_error("bad dt or step count"); return CVW_EINVAL; }
   const WS w = carve(m, prm, ws);
   auto s = static_cast<hipStream_t>(stream);
-  float* U = static_cast<float*>(u);
-  float* U1 = static_cast<float*>(w.st1);
-  float* U2 = static_cast<float*>(w.st2);
-  const float fdt = static_cast<float>(dt);
-  // SSP-RK3 in Shu-Osher form
-  const struct { const float* in; float* out; float a0, b0; } stages[3] = {
-      {U, U1, 0.0f, 1.0f}, {U1, U2, 0.75f, 0.25f}, {U2, U, 1.0f / 3.0f, 2.0f / 3.0f}};
+  const bool f64 = prm->dtype == CVW_F64;
+  // stage coefficients in the precision of the kernels (SSP-RK3, Shu-Osher form)
+  const double third = f64 ? 1.0 / 3.0 : static_cast<double>(1.0f / 3.0f);
+  const double two3 = f64 ? 2.0 / 3.0 : static_cast<double>(2.0f / 3.0f);
+  const struct { const void* in; void* out; double a0, b0; } stages[3] = {
+      {u, w.st1, 0.0, 1.0}, {w.st1, w.st2, 0.75, 0.25}, {w.st2, u, third, two3}};
   for (int n = 0; n < n_steps; ++n)
     for (const auto& sg : stages) {
       if (prm->sensor == CVW_SENSOR_PLAIN) {
-        st = dgquad_candidates(m, prm, sg.in, static_cast<float*>(w.cand), s);
+        st = candidates_any(m, prm, sg.in, w.cand, s);
         if (st != CVW_OK) return st;
       }
-      st = dgquad_eval(m, prm, MODE_STAGE, sg.in, U, sg.out, nullptr, nullptr, static_cast<const float*>(w.cand),
-                       w.status, fdt, sg.a0, sg.b0, s);
+      st = any_stage(m, prm, w, sg.in, w.cand, u, sg.out, dt, sg.a0, sg.b0, s);
       if (st != CVW_OK) return st;
     }
   return CVW_OK;

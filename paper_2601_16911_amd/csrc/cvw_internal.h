@@ -33,6 +33,21 @@ struct TensorTables {
   double Ld[MAXP + 1][MAXP + 1];
 };
 
+// Per-lane table record of the DG quadrilateral cell kernel: one 16-lane row
+// per cell, node (a, b) on lane q = a + 4 b.  Row rotations by 4 s lanes bring
+// the value of row (b - s) mod 4; the "rotated" entries are pre-permuted so.
+struct alignas(16) LaneRec {
+  float CX1[4];      // l_i'(xi_a)
+  float CY1[4];      // l'_{(b-s)&3}(xi_b)
+  float TX[4];       // l_a'(xi_c)
+  float TY[4];       // l_b'(xi_{(b-s)&3})
+  float BY0[4];      // l_{(b-s)&3}(-1)
+  float BY1[4];      // l_{(b-s)&3}(+1)
+  float misc[8];     // l_a(-1), l_a(+1), l_b(-1), l_b(+1), w_a, w_b, xi_a, xi_b
+  double DX[3][4];   // l_i^{(m)}(xi_a), m = 1..3
+  double DY[3][4];   // l^{(m)}_{(b-s)&3}(xi_b), m = 1..3
+};
+
 // Reference tables of a tensor-product CG element (Gauss-Lobatto nodes) of
 // degree p <= 2 for the bilinear-map path: Gauss volume rule (p+1 points),
 // Gauss semi-norm rule (p+2 points), derivatives up to order 2.
@@ -91,6 +106,7 @@ struct cvw_mesh {
   int32_t* d_cell_vtx = nullptr;     // [E][ve]
   int32_t* d_nbr = nullptr;          // [E][nf]
   cvw::TensorTables* d_tens = nullptr;
+  cvw::LaneRec* d_lanes = nullptr;   // [16] DG quadrilateral lane tables
   // CG
   int32_t* d_cell_dof = nullptr;     // [E][nloc]
   int32_t* d_dof_ptr = nullptr;      // [ndof + 1] CSR of the DOF patches
@@ -102,6 +118,11 @@ struct cvw_mesh {
   // 1D
   double* d_hcell = nullptr;          // [E] cell length
   cvw::SegTables* d_segt = nullptr;
+  // time stepping: inverse of the lumped CG mass (PCG preconditioner) or of
+  // the exact diagonal 1D DG mass, in both precisions
+  float* d_dinv_f = nullptr;          // [n_mass]
+  double* d_dinv_d = nullptr;         // [n_mass]
+  int64_t n_mass = 0;
 };
 
 namespace cvw {
@@ -125,6 +146,15 @@ cvw_status cgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const
 cvw_status seg_candidates(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand, hipStream_t s);
 cvw_status seg_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const void* u, const void* cand, void* pg,
                     void* rcell, void* R, void* gamma, void* alpha, uint32_t* status, hipStream_t s);
+// time stepping (cvw_cgstep.hip)
+size_t pcg_partials(int64_t n);
+template <typename Real>
+cvw_status cg_mass_solve(const cvw_mesh* m, const Real* b, Real* x, Real* r, Real* z, Real* p, Real* Ap,
+                         Real* ycell, double* part, double* S, const Real* dinv, double tol, int maxit,
+                         hipStream_t s);
+template <typename Real>
+cvw_status stage_update(const Real* us, const Real* un, const Real* x, const Real* dinv, Real* uo, double a0,
+                        double b0, double dt, int64_t n, hipStream_t s);
 cvw_status totals_f32(const cvw_mesh* m, int nvar, const float* u, double* partial, double* out_dev,
                       hipStream_t s);
 

@@ -117,6 +117,28 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _state_len(mesh, prm) -> int:
+    nv = 4 if prm.flux == 4 else 1
+    i = mesh.info
+    return nv * (i["n_dof"] if mesh.space == CG else i["n_cells"] * i["n_loc"])
+
+
+def _fp(t, prm, n: int = 0, name: str = "array"):
+    """Pointer of a floating-point device array after checking what the C ABI
+    cannot: element type (that of the parameters), device, contiguity, length."""
+    if t is None:
+        return None
+    import torch
+    want = torch.float64 if prm.dtype == F64 else torch.float32
+    if t.dtype != want:
+        raise TypeError(f"{name}: dtype {t.dtype}, the parameters ask for {want}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: must be a contiguous device tensor")
+    if t.numel() < n:
+        raise ValueError(f"{name}: {t.numel()} elements, {n} needed")
+    return C.c_void_p(t.data_ptr())
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -181,29 +203,43 @@ def alloc_workspace(mesh: Mesh, prm: ParamsC, op: int, device="cuda"):
     return torch.zeros(workspace_bytes(mesh, prm, op), dtype=torch.uint8, device=device)
 
 
+def _cand_len(mesh) -> int:
+    return mesh.info["n_vertices"] * mesh.info["n_k"]
+
+
 def vertex_candidates(mesh, prm, u, cand, ws, stream=None):
-    _check(load().cvw_vertex_candidates(mesh.handle, C.byref(prm), _ptr(u), _ptr(cand), _ptr(ws), ws.numel(),
+    n = _state_len(mesh, prm)
+    _check(load().cvw_vertex_candidates(mesh.handle, C.byref(prm), _fp(u, prm, n, "u"),
+                                        _fp(cand, prm, _cand_len(mesh), "cand"), _ptr(ws), ws.numel(),
                                         _stream(stream)))
 
 
 def sensor(mesh, prm, u, gamma, alpha, ws, stream=None):
-    _check(load().cvw_sensor(mesh.handle, C.byref(prm), _ptr(u), _ptr(gamma), _ptr(alpha), _ptr(ws), ws.numel(),
+    i = mesh.info
+    _check(load().cvw_sensor(mesh.handle, C.byref(prm), _fp(u, prm, _state_len(mesh, prm), "u"),
+                             _fp(gamma, prm, i["n_cells"], "gamma"),
+                             _fp(alpha, prm, i["n_cells"] * i["n_q"], "alpha"), _ptr(ws), ws.numel(),
                              _stream(stream)))
 
 
 def residual(mesh, prm, u, R, gamma_out, ws, stream=None):
-    _check(load().cvw_residual(mesh.handle, C.byref(prm), _ptr(u), _ptr(R), _ptr(gamma_out), _ptr(ws), ws.numel(),
+    n = _state_len(mesh, prm)
+    _check(load().cvw_residual(mesh.handle, C.byref(prm), _fp(u, prm, n, "u"), _fp(R, prm, n, "R"),
+                               _fp(gamma_out, prm, mesh.info["n_cells"], "gamma_out"), _ptr(ws), ws.numel(),
                                _stream(stream)))
 
 
 def rk_stage(mesh, prm, u_stage, cand, u_n, u_out, dt: float, a0: float, b0: float, ws, stream=None):
-    _check(load().cvw_rk_stage(mesh.handle, C.byref(prm), _ptr(u_stage), _ptr(cand), _ptr(u_n), _ptr(u_out),
-                               float(dt), float(a0), float(b0), _ptr(ws), ws.numel(), _stream(stream)))
+    n = _state_len(mesh, prm)
+    _check(load().cvw_rk_stage(mesh.handle, C.byref(prm), _fp(u_stage, prm, n, "u_stage"),
+                               _fp(cand, prm, _cand_len(mesh), "cand"), _fp(u_n, prm, n, "u_n"),
+                               _fp(u_out, prm, n, "u_out"), float(dt), float(a0), float(b0), _ptr(ws), ws.numel(),
+                               _stream(stream)))
 
 
 def step(mesh, prm, u, dt: float, n_steps: int, ws, stream=None):
-    _check(load().cvw_step(mesh.handle, C.byref(prm), _ptr(u), float(dt), int(n_steps), _ptr(ws), ws.numel(),
-                           _stream(stream)))
+    _check(load().cvw_step(mesh.handle, C.byref(prm), _fp(u, prm, _state_len(mesh, prm), "u"), float(dt),
+                           int(n_steps), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def poll_status(mesh, ws, stream=None) -> int:
@@ -216,5 +252,6 @@ def poll_status(mesh, ws, stream=None) -> int:
 
 def totals(mesh, prm, u, ws, stream=None, n_var: int = 1):
     out = (C.c_double * n_var)()
-    _check(load().cvw_totals(mesh.handle, C.byref(prm), _ptr(u), out, _ptr(ws), ws.numel(), _stream(stream)))
+    _check(load().cvw_totals(mesh.handle, C.byref(prm), _fp(u, prm, _state_len(mesh, prm), "u"), out, _ptr(ws),
+                             ws.numel(), _stream(stream)))
     return np.array(out[:])

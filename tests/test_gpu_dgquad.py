@@ -158,27 +158,70 @@ def test_residual_deterministic_and_gamma_out():
     assert torch.equal(R1, R2)
 
 
+@pytest.mark.parametrize("sensor", ["fixed", "plain"])
 @pytest.mark.parametrize("p", [1, 2, 3])
-def test_one_rk3_step_matches_oracle(p):
-    """One SSP-RK3 step; SC off so that no float decision near gamma_e = 0.9 can
-    differ between the stages of the two sides.  Compared: the increment U1 - U0
-    relative to its own size."""
-    from oracle.method import wave_speed
+def test_rk3_stages_match_oracle(p, sensor):
+    """The three SSP-RK3 stages (Shu-Osher form), SC off, stable dt.  Each
+    stage is compared with the oracle on the stage state the device actually
+    stored (float32), so that one-ulp differences of a stored stage state are
+    not propagated into the next stage: the plain sensor of smooth p = 3 cells
+    reacts to such differences through third derivatives of the rounding.
+    Bar per stage: 8 ulp of |U| plus 1e-5 of the stage increment b0 dt L."""
+    from oracle.method import wave_speed, time_derivative
     mesh = synth.quad_mesh(12, 12)
     sp = build_space(mesh, p, 1, 4)
     U = f32(euler_state(sp, k=6.0))
-    prm = Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0), sc_on=0)
+    prm = Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0), sc_on=0,
+                 sensor=2 if sensor == "fixed" else 0, fixed_gamma=0.5)
     lam = wave_speed(prm, sp.to_cells(U), sp.node_coords()).max()
     dt = 0.1 * (1.0 / 12) / ((2 * p + 1) * lam)     # inside the SSP-RK3 / DG stability region
     gm = cvw.Mesh(mesh, p, cvw.DG)
     cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, 0)
+    nk = (p + 1) * (p + 2) // 2 - 1
+    cand = torch.zeros((mesh.n_vertices, nk), dtype=torch.float32, device="cuda")
+    Un = _dev(U)
+    cur = Un
+    for (a0, b0) in ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0)):
+        if sensor == "plain":
+            cvw.vertex_candidates(gm, cp, cur, cand, ws)
+        out = torch.empty_like(Un)
+        cvw.rk_stage(gm, cp, cur, cand, Un if a0 else None, out, dt, a0, b0, ws)
+        us = cur.cpu().numpy().astype(np.float64)
+        inc = b0 * dt * time_derivative(sp, us, prm)
+        ref = a0 * U + b0 * us + inc
+        err = np.abs(out.cpu().numpy().astype(np.float64) - ref).max()
+        assert err <= 8 * np.finfo(np.float32).eps * np.abs(U).max() + 1e-5 * np.abs(inc).max(), (a0, b0)
+        cur = out
+    assert cvw.poll_status(gm, ws) == 0
+
+
+@pytest.mark.parametrize("sensor", ["fixed", "plain"])
+def test_step_is_the_three_stages(sensor):
+    """cvw_step equals, bit for bit, the stage-by-stage sequence through the
+    public entry points (same kernels, same order)."""
+    p = 3
+    mesh = synth.quad_mesh(12, 12)
+    sp = build_space(mesh, p, 1, 4)
+    U = f32(euler_state(sp, k=6.0))
+    prm = Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0),
+                 sensor=2 if sensor == "fixed" else 0, fixed_gamma=0.5)
+    dt = 2e-4
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    cp = cvw.make_params(prm)
     ws = cvw.alloc_workspace(gm, cp, 1)
     Ud = _dev(U)
-    cvw.step(gm, cp, Ud, dt, 1, ws)
-    U1 = rk3_step(sp, U, dt, prm)
-    # float32 state: the new state carries its own rounding (a few ulp of |U|)
-    err = np.abs(Ud.cpu().numpy().astype(np.float64) - U1).max()
-    assert err <= 8 * np.finfo(np.float32).eps * np.abs(U).max() + 1e-5 * np.abs(U1 - U).max()
+    cvw.step(gm, cp, Ud, dt, 2, ws)
+    cand = torch.zeros((mesh.n_vertices, 9), dtype=torch.float32, device="cuda")
+    V = _dev(U)
+    for _ in range(2):
+        V1, V2 = torch.empty_like(V), torch.empty_like(V)
+        for (us, un, uo, a0, b0) in ((V, None, V1, 0.0, 1.0), (V1, V, V2, 0.75, 0.25),
+                                     (V2, V, V, 1.0 / 3.0, 2.0 / 3.0)):
+            if sensor == "plain":
+                cvw.vertex_candidates(gm, cp, us, cand, ws)
+            cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
+    assert torch.equal(Ud, V)
     assert cvw.poll_status(gm, ws) == 0
 
 
@@ -237,6 +280,11 @@ def test_error_paths():
     with pytest.raises(cvw.CvwError) as ei:
         cvw.residual(gm, cp, u, u, None, ws)
     assert ei.value.status == cvw.EINVAL
+    # the binding checks element type and length before the call
+    with pytest.raises(TypeError):
+        cvw.residual(gm, cp, u.double(), R.double(), None, ws)
+    with pytest.raises(ValueError):
+        cvw.residual(gm, cp, u[:10], R, None, ws)
 
 
 def test_full_size_config4_sampled_cells():
