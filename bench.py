@@ -55,6 +55,31 @@ def gauss_nodes_2d(p: int):
     return np.stack([X.ravel(), Y.ravel()], axis=1)
 
 
+def kernel_source_hash() -> str:
+    """Hash of the sources of the fused DG cell kernel; HBM counter figures are
+    valid only for the kernel they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("cvw_dgquad.hip", "cvw_device.h", "cvw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2601_16911_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per stage-mode launch of the fused cell kernel, from the
+    calibrated FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel
+    changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_dgq_eval_config4.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    if tr.get("source_hash") != kernel_source_hash():
+        return None
+    return tr.get("bytes_per_launch")
+
+
 def cpu_baseline(target_seconds: float = 15.0):
     """The float64 oracle timed on a bounded sample of the same workload: the
     stabilised residual on periodic n x n sub-problems of the same recipe."""
@@ -176,15 +201,7 @@ def main():
     alg_bytes = state_bytes * (1 + 1 + 2.0 / 3.0) + mesh.n_vertices * nk * 4
     t_eval = float(np.mean(eval_ms)) / 1e3
     achieved = alg_bytes / t_eval / 1e9
-    traffic = None
-    tr_path = os.path.join(ROOT, "profiles", "traffic_dgq_eval_config4.json")
-    if os.path.exists(tr_path):
-        try:
-            with open(tr_path) as f:
-                tr = json.load(f)
-            traffic = tr.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic()
 
     value = 3.0 * ndof * nv * args.steps / t_total
     out = {
