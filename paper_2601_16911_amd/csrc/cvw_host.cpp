@@ -220,6 +220,190 @@ static void fill_cg_tables(CGTables& T, int p) {
     for (int i = 0; i <= p; ++i) T.Dn[a][i] = static_cast<float>(lagrange_deriv(xn, i, 1, xn[a]));
 }
 
+// ---------------------------------------------------------------------------
+// Triangle tables
+// ---------------------------------------------------------------------------
+// Gauss rule for the weight (1 - x) on [-1, 1]: nodes are the roots of the
+// Jacobi polynomial P_n^{(1,0)} (three-term recurrence, bracketed by a sign
+// scan and bisected to full precision); weights from the moment equations.
+static double jacobi10(int n, double x) {
+  const double a = 1.0, b = 0.0;
+  double p0 = 1.0, p1 = (a + 1.0) + (a + b + 2.0) * (x - 1.0) / 2.0;
+  if (n == 0) return p0;
+  for (int k = 2; k <= n; ++k) {
+    const double c = 2.0 * k + a + b;
+    const double p2 = ((c - 1.0) * (c * (c - 2.0) * x + a * a - b * b) * p1 - 2.0 * (k + a - 1.0) * (k + b - 1.0) * c * p0) /
+                      (2.0 * k * (k + a + b) * (c - 2.0));
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+static bool solve_dense(std::vector<double> M, std::vector<double>& rhs, int n) {
+  // Gauss-Jordan elimination with partial pivoting on M [n][n]; rhs [n][k] row-major is overwritten
+  // by M^{-1} rhs
+  const int k = static_cast<int>(rhs.size()) / n;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[r * n + c]) > std::fabs(M[piv * n + c])) piv = r;
+    if (!(std::fabs(M[piv * n + c]) > 0)) return false;
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) std::swap(M[c * n + j], M[piv * n + j]);
+      for (int j = 0; j < k; ++j) std::swap(rhs[c * k + j], rhs[piv * k + j]);
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = M[r * n + c] / M[c * n + c];
+      if (f == 0.0) continue;
+      for (int j = c; j < n; ++j) M[r * n + j] -= f * M[c * n + j];
+      for (int j = 0; j < k; ++j) rhs[r * k + j] -= f * rhs[c * k + j];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int j = 0; j < k; ++j) rhs[r * k + j] /= M[r * n + r];
+  return true;
+}
+
+static void gauss_jacobi10(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.clear();
+  const int scan = 4000;
+  double xa = -1.0, fa = jacobi10(n, xa);
+  for (int i = 1; i <= scan && static_cast<int>(x.size()) < n; ++i) {
+    const double xb = -1.0 + 2.0 * i / scan, fb = jacobi10(n, xb);
+    if (fa == 0.0) { x.push_back(xa); }
+    else if (fa * fb < 0.0) {
+      double lo = xa, hi = xb, flo = fa;
+      for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        const double fm = jacobi10(n, mid);
+        if ((fm < 0.0) == (flo < 0.0)) { lo = mid; flo = fm; } else { hi = mid; }
+      }
+      x.push_back(0.5 * (lo + hi));
+    }
+    xa = xb;
+    fa = fb;
+  }
+  // moments int_{-1}^{1} x^k (1 - x) dx
+  std::vector<double> V(n * n), m(n);
+  for (int k = 0; k < n; ++k) {
+    m[k] = ((k % 2 == 0) ? 2.0 / (k + 1) : 0.0) - ((k % 2 == 1) ? 2.0 / (k + 2) : 0.0);
+    for (int i = 0; i < n; ++i) V[k * n + i] = std::pow(x[i], k);
+  }
+  solve_dense(V, m, n);
+  w = m;
+}
+
+// Lagrange basis on the equispaced nodes of the reference triangle: monomial
+// coefficients C[i][j] (monomial i = xi^a eta^b in the order (a, b) of total
+// degree then decreasing a; column j = basis function j)
+struct TriBasis {
+  int p = 0, n = 0;
+  std::vector<std::pair<int, int>> mono;
+  std::vector<double> C;        // [n][n]
+  double deriv(int j, int mx, int my, double xi, double eta) const {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const int a = mono[i].first, b = mono[i].second;
+      if (a < mx || b < my) continue;
+      double ca = 1.0, cb = 1.0;
+      for (int t = 0; t < mx; ++t) ca *= (a - t);
+      for (int t = 0; t < my; ++t) cb *= (b - t);
+      s += C[i * n + j] * ca * cb * std::pow(xi, a - mx) * std::pow(eta, b - my);
+    }
+    return s;
+  }
+};
+
+static TriBasis tri_basis(int p) {
+  TriBasis B;
+  B.p = p;
+  B.n = (p + 1) * (p + 2) / 2;
+  for (int t = 0; t <= p; ++t)
+    for (int a = t; a >= 0; --a) B.mono.push_back({a, t - a});
+  std::vector<std::pair<double, double>> nodes;
+  for (int j = 0; j <= p; ++j)
+    for (int i = 0; i <= p - j; ++i) nodes.push_back({double(i) / p, double(j) / p});
+  const int n = B.n;
+  // V[r][i] = monomial i at node r;  C = V^{-1}
+  std::vector<double> V(n * n), I(n * n, 0.0);
+  for (int r = 0; r < n; ++r) {
+    for (int i = 0; i < n; ++i)
+      V[r * n + i] = std::pow(nodes[r].first, B.mono[i].first) * std::pow(nodes[r].second, B.mono[i].second);
+    I[r * n + r] = 1.0;
+  }
+  solve_dense(V, I, n);
+  B.C = I;
+  return B;
+}
+
+static void fill_tri_tables(TriTables& T, int p) {
+  std::memset(&T, 0, sizeof(T));
+  const TriBasis B = tri_basis(p);
+  const int n = B.n, nq1 = p + 1;
+  std::vector<double> xa, wa, xb, wb;
+  gauss_rule(nq1, xa, wa);
+  gauss_jacobi10(nq1, xb, wb);
+  std::vector<double> qx, qy, qw;
+  for (int ib = 0; ib < nq1; ++ib)
+    for (int ia = 0; ia < nq1; ++ia) {
+      const double a = 0.5 * (xa[ia] + 1.0), b = 0.5 * (xb[ib] + 1.0);
+      qx.push_back(a * (1.0 - b));
+      qy.push_back(b);
+      qw.push_back(0.5 * wa[ia] * wb[ib] / 4.0);
+    }
+  const int nq = nq1 * nq1;
+  for (int q = 0; q < nq; ++q) {
+    T.xq[q] = static_cast<float>(qx[q]);
+    T.yq[q] = static_cast<float>(qy[q]);
+    T.wq[q] = static_cast<float>(qw[q]);
+    T.xqd[q] = qx[q];
+    T.yqd[q] = qy[q];
+    T.wqd[q] = qw[q];
+    for (int j = 0; j < n; ++j) {
+      T.B[q][j] = static_cast<float>(B.deriv(j, 0, 0, qx[q], qy[q]));
+      T.Gx[q][j] = static_cast<float>(B.deriv(j, 1, 0, qx[q], qy[q]));
+      T.Gy[q][j] = static_cast<float>(B.deriv(j, 0, 1, qx[q], qy[q]));
+    }
+  }
+  const double vx[3] = {0.0, 1.0, 0.0}, vy[3] = {0.0, 0.0, 1.0};
+  std::vector<double> gx, gw;
+  gauss_rule(p + 1, gx, gw);
+  for (int g = 0; g <= p; ++g) T.wf[g] = static_cast<float>(gw[g]);
+  for (int f = 0; f < 3; ++f)
+    for (int g = 0; g <= p; ++g) {
+      const int f1 = (f + 1) % 3;
+      const double xi = 0.5 * (1.0 - gx[g]) * vx[f] + 0.5 * (1.0 + gx[g]) * vx[f1];
+      const double eta = 0.5 * (1.0 - gx[g]) * vy[f] + 0.5 * (1.0 + gx[g]) * vy[f1];
+      T.xf[f][g] = static_cast<float>(xi);
+      T.yf[f][g] = static_cast<float>(eta);
+      for (int j = 0; j < n; ++j) T.Bf[f][g][j] = static_cast<float>(B.deriv(j, 0, 0, xi, eta));
+    }
+  for (int l = 0; l < 3; ++l) {
+    int t = 0;
+    for (int ord = 1; ord <= p; ++ord)
+      for (int b = 0; b <= ord; ++b, ++t)
+        for (int j = 0; j < n; ++j) T.TV[l][t][j] = B.deriv(j, ord - b, b, vx[l], vy[l]);
+  }
+  // reference mass (the Stroud rule integrates degree 2p exactly) and its inverse
+  std::vector<double> M(n * n, 0.0), Mi(n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double mv = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      const double pi = B.deriv(i, 0, 0, qx[q], qy[q]);
+      mv += qw[q] * pi;
+      for (int j = 0; j < n; ++j) M[i * n + j] += qw[q] * pi * B.deriv(j, 0, 0, qx[q], qy[q]);
+    }
+    T.mvec[i] = static_cast<float>(mv);
+    Mi[i * n + i] = 1.0;
+  }
+  solve_dense(M, Mi, n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T.Minv[i][j] = static_cast<float>(Mi[i * n + j]);
+}
+
 static void fill_seg_tables(SegTables& T, int p, bool lobatto) {
   std::memset(&T, 0, sizeof(T));
   std::vector<double> xq, wq, xn;
@@ -400,6 +584,9 @@ static void free_mesh(cvw_mesh* m) {
   (void)hipFree(m->d_cgt);
   (void)hipFree(m->d_hcell);
   (void)hipFree(m->d_segt);
+  (void)hipFree(m->d_trit);
+  (void)hipFree(m->d_geot);
+  (void)hipFree(m->d_nbrf);
   (void)hipFree(m->d_dinv_f);
   (void)hipFree(m->d_dinv_d);
   delete m;
@@ -425,7 +612,8 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   if (d->degree < 1 || d->degree > 16) { set_error("degree out of range"); return CVW_EINVAL; }
   if (d->space != CVW_CG && d->space != CVW_DG) { set_error("space must be CG or DG"); return CVW_EINVAL; }
   if (d->n_cells <= 0 || d->n_vertices <= 0) { set_error("empty mesh"); return CVW_EINVAL; }
-  if (d->n_cells * ve >= (int64_t(1) << 31) || d->n_vertices >= (int64_t(1) << 31)) {
+  // packed (cell, local index) entries: cell * 4 + local vertex, cell * 16 + local CG node
+  if (d->n_cells * (d->space == CVW_CG ? 16 : 4) >= (int64_t(1) << 31) || d->n_vertices >= (int64_t(1) << 31)) {
     set_error("mesh too large for 32-bit indices"); return CVW_EINVAL;
   }
   const int64_t E = d->n_cells, Nv = d->n_vertices;
@@ -616,6 +804,27 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     fill_seg_tables(t1[0], std::min(p, MAXP), d->space == CVW_CG);
     if ((st = upload(&m->d_segt, t1)) != CVW_OK) { free_mesh(m); return st; }
   }
+  if (d->cell == CVW_TRI && d->space == CVW_DG && p <= MAXP) {
+    std::vector<double> gt(E * 8, 0.0);
+    for (int64_t e = 0; e < E; ++e) {
+      const double* X = d->cell_coords + e * 6;
+      double* g = gt.data() + e * 8;
+      g[0] = X[0]; g[1] = X[1];
+      g[2] = X[2] - X[0]; g[3] = X[3] - X[1];
+      g[4] = X[4] - X[0]; g[5] = X[5] - X[1];
+      g[6] = m->h_he[e];
+      if (!(g[2] * g[5] - g[4] * g[3] > 0.0)) {
+        free_mesh(m); set_error("triangles must be counter-clockwise and non-degenerate"); return CVW_EINVAL;
+      }
+    }
+    if ((st = upload(&m->d_geot, gt)) != CVW_OK) { free_mesh(m); return st; }
+    std::vector<int32_t> nf32(E * 3);
+    for (int64_t i = 0; i < E * 3; ++i) nf32[i] = m->h_nbr[i] < 0 ? -1 : m->h_nbr[i] * 4 + m->h_nbr_face[i];
+    if ((st = upload(&m->d_nbrf, nf32)) != CVW_OK) { free_mesh(m); return st; }
+    std::vector<TriTables> tt(1);
+    fill_tri_tables(tt[0], p);
+    if ((st = upload(&m->d_trit, tt)) != CVW_OK) { free_mesh(m); return st; }
+  }
   {
     const std::vector<double> dm = diag_mass(m, d);
     for (double v : dm)
@@ -676,7 +885,12 @@ static size_t state_elems(const cvw_mesh* m, int nv) {
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // true when the mesh has a time-stepping path (stages and steps)
-static bool has_stage(const cvw_mesh* m) { return m->n_mass > 0 || (m->cell == CVW_QUAD && m->space == CVW_DG); }
+static bool has_stage(const cvw_mesh* m) {
+  return m->n_mass > 0 || (m->space == CVW_DG && (m->cell == CVW_QUAD || (m->cell == CVW_TRI && m->d_trit)));
+}
+
+// float64 scratch of the totals: block partials of up to four variables and the results
+constexpr size_t TOT_SCRATCH = (4 * 1024 + 4) * sizeof(double) + 224;
 
 static size_t cg_extra(const cvw_mesh* m, const cvw_params* prm, size_t es) {
   size_t b = 0;
@@ -695,7 +909,7 @@ static size_t cg_extra(const cvw_mesh* m, const cvw_params* prm, size_t es) {
 size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (!m || !prm) return 0;
   const size_t es = prm->dtype == CVW_F64 ? 8 : 4;
-  size_t b = 256 + align256(static_cast<size_t>(m->nk) * m->Nv * es) + cg_extra(m, prm, es);
+  size_t b = 256 + TOT_SCRATCH + align256(static_cast<size_t>(m->nk) * m->Nv * es) + cg_extra(m, prm, es);
   if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
   return b;
 }
@@ -716,6 +930,13 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
   const bool dgq = m->cell == CVW_QUAD && m->space == CVW_DG;
   const bool cgq = m->cell == CVW_QUAD && m->space == CVW_CG;
   const bool seg = m->cell == CVW_SEG;
+  const bool dgt = m->cell == CVW_TRI && m->space == CVW_DG;
+  if (dgt) {
+    if (m->degree > MAXP) { set_error("degree > 3 not on the GPU path"); return CVW_EUNSUPPORTED; }
+    if (prm->dtype != CVW_F32) { set_error("DG triangles run in float32"); return CVW_EUNSUPPORTED; }
+    if (!m->closed) { set_error("DG residual needs a mesh without boundary faces"); return CVW_EUNSUPPORTED; }
+    return CVW_OK;
+  }
   if (!dgq && !cgq && !seg) { set_error("this cell / space combination is not on the GPU path yet"); return CVW_EUNSUPPORTED; }
   if (seg) {
     if (m->degree > MAXP) { set_error("degree > 3 not on the GPU path"); return CVW_EUNSUPPORTED; }
@@ -741,6 +962,7 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
 
 struct WS {
   uint32_t* status;
+  double* tot;                     // totals scratch
   void* cand;
   void* pg;
   void* rcell;
@@ -757,6 +979,8 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
   WS w{};
   w.status = reinterpret_cast<uint32_t*>(p);
   p += 256;
+  w.tot = reinterpret_cast<double*>(p);
+  p += TOT_SCRATCH;
   w.cand = p;
   p += align256(static_cast<size_t>(m->nk) * m->Nv * es);
   if (m->space == CVW_CG) {
@@ -788,6 +1012,8 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
 static cvw_status candidates_any(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand,
                                  hipStream_t s) {
   if (m->cell == CVW_SEG) return seg_candidates(m, prm, u, cand, s);
+  if (m->cell == CVW_TRI)
+    return tri_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
   if (m->space == CVW_CG)
     return cgquad_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
   return dgquad_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
@@ -814,6 +1040,9 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
   }
   if (m->cell == CVW_SEG)
     return seg_eval(m, prm, MODE_SENSOR, u, w.cand, w.pg, w.rcell, nullptr, gamma, alpha, w.status, s);
+  if (m->cell == CVW_TRI)
+    return tri_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
+                    static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s);
   if (m->space == CVW_CG)
     return cgquad_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), static_cast<const float*>(w.cand),
                        static_cast<float*>(w.pg), static_cast<float*>(w.rcell), nullptr, static_cast<float*>(gamma),
@@ -836,6 +1065,10 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
   }
   if (m->cell == CVW_SEG)
     return seg_eval(m, prm, MODE_RESIDUAL, u, w.cand, w.pg, w.rcell, R, gamma_out, nullptr, w.status, s);
+  if (m->cell == CVW_TRI)
+    return tri_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
+                    static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
+                    0.f, s);
   if (m->space == CVW_CG)
     return cgquad_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), static_cast<const float*>(w.cand),
                        static_cast<float*>(w.pg), static_cast<float*>(w.rcell), static_cast<float*>(R),
@@ -882,6 +1115,10 @@ cvw_status generic_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, 
 
 cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, const void* us, const void* cand,
                      const void* un, void* uo, double dt, double a0, double b0, hipStream_t s) {
+  if (m->cell == CVW_TRI)
+    return tri_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
+                    static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
+                    static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s);
   if (m->cell == CVW_QUAD && m->space == CVW_DG)
     return dgquad_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
                        static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
@@ -955,18 +1192,16 @@ cvw_status cvw_totals(const cvw_mesh* m, const cvw_params* prm, const void* u, d
   cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
   if (st != CVW_OK) return st;
   if (!u || !out_host) { set_error("null pointer"); return CVW_EINVAL; }
-  if (m->space != CVW_DG) { set_error("totals are implemented for the DG path"); return CVW_EUNSUPPORTED; }
+  if (m->space != CVW_DG || (m->cell != CVW_QUAD && m->cell != CVW_TRI)) {
+    set_error("totals are implemented for DG quadrilaterals and triangles"); return CVW_EUNSUPPORTED;
+  }
   const int nv = n_var_of(prm->flux);
   const WS w = carve(m, prm, ws);
-  // partial sums live in the candidate area (n_k * Nv floats >= 2 * 1024 doubles for any mesh
-  // large enough to need more than one block; checked here)
-  const size_t avail = static_cast<size_t>(m->nk) * m->Nv * 4;
-  const size_t need = (static_cast<size_t>(nv) * 1024 + nv) * sizeof(double);
-  if (avail < need) { set_error("mesh too small for the totals scratch"); return CVW_EUNSUPPORTED; }
-  double* part = static_cast<double*>(w.cand);
-  double* res = part + static_cast<size_t>(nv) * 1024;
+  double* part = w.tot;
+  double* res = part + 4 * 1024;
   auto s = static_cast<hipStream_t>(stream);
-  st = totals_f32(m, nv, static_cast<const float*>(u), part, res, s);
+  st = m->cell == CVW_TRI ? tri_totals(m, nv, static_cast<const float*>(u), part, res, s)
+                          : totals_f32(m, nv, static_cast<const float*>(u), part, res, s);
   if (st != CVW_OK) return st;
   CVW_HIP(hipMemcpyAsync(out_host, res, nv * sizeof(double), hipMemcpyDeviceToHost, s));
   CVW_HIP(hipStreamSynchronize(s));

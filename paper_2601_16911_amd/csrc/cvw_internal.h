@@ -75,6 +75,27 @@ struct SegTables {
   double Lv[2][MAXP + 1][MAXP + 1];        // Lv[s][m][i] = l_i^{(m)}(-1) (s = 0), (+1) (s = 1)
 };
 
+// Reference tables of the P_p Lagrange triangle (equispaced nodes on the
+// reference triangle (0,0), (1,0), (0,1)) with the (p+1)^2-point Stroud
+// conical-product rule and (p+1)-point Gauss rules on the edges.  Filled on
+// the host; the cell kernel reads them with uniform indices.
+constexpr int TRI_NLOC = (MAXP + 1) * (MAXP + 2) / 2;
+constexpr int TRI_NQ = (MAXP + 1) * (MAXP + 1);
+constexpr int TRI_NK = (MAXP + 1) * (MAXP + 2) / 2 - 1;
+struct TriTables {
+  float B[TRI_NQ][TRI_NLOC];               // phi_j(xi_q)
+  float Gx[TRI_NQ][TRI_NLOC];              // d phi_j / d xi at xi_q
+  float Gy[TRI_NQ][TRI_NLOC];              // d phi_j / d eta at xi_q
+  float xq[TRI_NQ], yq[TRI_NQ], wq[TRI_NQ];  // Stroud points and weights (reference area 1/2)
+  float Bf[3][MAXP + 1][TRI_NLOC];         // phi_j at the Gauss points of edge f (vertex f -> f+1)
+  float xf[3][MAXP + 1], yf[3][MAXP + 1];  // reference coordinates of those points
+  float wf[MAXP + 1];                      // Gauss weights on [-1, 1]
+  float Minv[TRI_NLOC][TRI_NLOC];          // inverse reference mass matrix
+  float mvec[TRI_NLOC];                    // int phi_j over the reference triangle
+  double xqd[TRI_NQ], yqd[TRI_NQ], wqd[TRI_NQ];
+  double TV[3][TRI_NK][TRI_NLOC];          // reference derivatives D^m phi_j at reference vertex l (|m| >= 1)
+};
+
 // Scalars of the method in the precision of the kernels.
 struct MethodScalars {
   float eps_v, eps_c, r, q_sensor, q_beta, lin_w, c_gamma, lam_g;
@@ -120,6 +141,10 @@ struct cvw_mesh {
   cvw::SegTables* d_segt = nullptr;
   // time stepping: inverse of the lumped CG mass (PCG preconditioner) or of
   // the exact diagonal 1D DG mass, in both precisions
+  // triangles
+  cvw::TriTables* d_trit = nullptr;
+  double* d_geot = nullptr;           // [E][8] x0, y0, x1-x0, y1-y0, x2-x0, y2-y0, diam, 0
+  int32_t* d_nbrf = nullptr;          // [E][3] neighbour cell * 4 + its face
   float* d_dinv_f = nullptr;          // [n_mass]
   double* d_dinv_d = nullptr;         // [n_mass]
   int64_t n_mass = 0;
@@ -146,6 +171,12 @@ cvw_status cgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const
 cvw_status seg_candidates(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand, hipStream_t s);
 cvw_status seg_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const void* u, const void* cand, void* pg,
                     void* rcell, void* R, void* gamma, void* alpha, uint32_t* status, hipStream_t s);
+// kernel launchers (cvw_tri.hip)
+cvw_status tri_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
+cvw_status tri_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
+                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
+                    hipStream_t s);
+cvw_status tri_totals(const cvw_mesh* m, int nvar, const float* u, double* partial, double* out_dev, hipStream_t s);
 // time stepping (cvw_cgstep.hip)
 size_t pcg_partials(int64_t n);
 template <typename Real>

@@ -1,0 +1,600 @@
+// DG on affine triangles (P_1..P_3, equispaced Lagrange nodes, Stroud rule):
+//
+//  * tri_vertex_kernel -- one thread per mesh vertex: Hermite data D^k u^e(x_i),
+//    1 <= |k| <= p, of every cell of the vertex patch (eq. taylorsol), the
+//    pointwise smoothness indicators and Jiang-Shu weights, and the vertex
+//    candidate (eq. taylorcand), Sec. 3.2.  Float64 (derivatives of order 3 of
+//    smooth data cancel strongly).
+//  * tri_eval_kernel -- one thread per cell: the cell-vertex WENO sensor
+//    (eq. finalweno, eq. gamma) in float64, the viscosity (eq. lostab), the
+//    shock-capturing weights (eqs. dissrateorig to alphaq), the volume and
+//    interface terms of the residual (Sec. 2.1) in float32, and optionally the
+//    exact element mass inverse with a Runge-Kutta stage update.
+//
+// The sensor works on Taylor coefficients: the cell polynomial and the three
+// vertex candidates (Taylor polynomials about their vertices) are all written
+// as D^m v(x_0), |m| >= 1, about the cell's vertex 0, and each element
+// semi-norm (eq. snorm) is evaluated with the Stroud rule (exact: the
+// integrands have degree <= 2p - 2).  Reference tables are read with indices
+// that are uniform across a wavefront (scalar loads), except the neighbour-
+// face tables, which live in LDS.
+#include "cvw_device.h"
+
+namespace cvw {
+
+__host__ __device__ constexpr int kbase(int n) { return n * (n + 1) / 2 - 1; }   // index of (n, 0)
+
+// D^k_x of a function from its reference derivatives of the same order:
+// d/dx = A00 d/dxi + A10 d/deta, d/dy = A01 d/dxi + A11 d/deta (A = J^{-1}).
+// R[kbase(n) + b] = d_xi^{n-b} d_eta^b u; out in the same multi-index order.
+template <int P>
+__device__ __forceinline__ void phys_from_ref(const double A[2][2], const double* R, double* out) {
+#pragma unroll
+  for (int n = 1; n <= P; ++n)
+#pragma unroll
+    for (int j = 0; j <= n; ++j) {
+      double c[P + 1];
+#pragma unroll
+      for (int b = 0; b <= P; ++b) c[b] = (b == 0) ? 1.0 : 0.0;
+#pragma unroll
+      for (int t = 0; t < n; ++t) {
+        const int col = (t < n - j) ? 0 : 1;
+        const double c0 = A[0][col], c1 = A[1][col];
+#pragma unroll
+        for (int b = P; b >= 1; --b) c[b] = c[b] * c0 + c[b - 1] * c1;
+        c[0] *= c0;
+      }
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b <= n; ++b) s = fma(c[b], R[kbase(n) + b], s);
+      out[kbase(n) + j] = s;
+    }
+}
+
+// D^m v(x_0 + d) for every 1 <= |m| <= P from t[k] = D^k v(x_0)
+template <int P>
+__device__ __forceinline__ void taylor_eval(const double* t, double dx, double dy, double* D) {
+  double px[P], py[P];
+  px[0] = 1.0;
+  py[0] = 1.0;
+#pragma unroll
+  for (int a = 1; a < P; ++a) {
+    px[a] = px[a - 1] * dx / a;
+    py[a] = py[a - 1] * dy / a;
+  }
+#pragma unroll
+  for (int n = 1; n <= P; ++n)
+#pragma unroll
+    for (int j = 0; j <= n; ++j) {
+      const int mx = n - j, my = j;
+      double s = 0.0;
+#pragma unroll
+      for (int n2 = P; n2 >= n; --n2)
+#pragma unroll
+        for (int j2 = 0; j2 <= n2; ++j2) {
+          const int kx = n2 - j2, ky = j2;
+          if (kx >= mx && ky >= my) s = fma(t[kbase(n2) + j2], px[kx - mx] * py[ky - my], s);
+        }
+      D[kbase(n) + j] = s;
+    }
+}
+
+struct TriGeo {
+  double x0, y0;
+  double J[2][2];   // J[a][b] = d x_a / d xi_b
+  double A[2][2];   // J^{-1}
+  double det, h;
+};
+
+__device__ __forceinline__ TriGeo load_trigeo(const double* __restrict__ g, int64_t e) {
+  TriGeo G;
+  const double* p = g + e * 8;
+  G.x0 = p[0];
+  G.y0 = p[1];
+  G.J[0][0] = p[2];
+  G.J[1][0] = p[3];
+  G.J[0][1] = p[4];
+  G.J[1][1] = p[5];
+  G.h = p[6];
+  G.det = G.J[0][0] * G.J[1][1] - G.J[0][1] * G.J[1][0];
+  const double inv = 1.0 / G.det;
+  G.A[0][0] = G.J[1][1] * inv;
+  G.A[0][1] = -G.J[0][1] * inv;
+  G.A[1][0] = -G.J[1][0] * inv;
+  G.A[1][1] = G.J[0][0] * inv;
+  return G;
+}
+
+// weights h^{2|k| - 2} of eq. (snorm) in two dimensions, per order n = 1..P
+template <int P>
+__device__ __forceinline__ void order_weights(double h, double* hw) {
+  hw[0] = 1.0;
+#pragma unroll
+  for (int n = 1; n < P; ++n) hw[n] = hw[n - 1] * h * h;
+}
+
+template <int P>
+__device__ __forceinline__ double weighted_sq(const double* D, const double* hw) {
+  double s = 0.0;
+#pragma unroll
+  for (int n = 1; n <= P; ++n)
+#pragma unroll
+    for (int j = 0; j <= n; ++j) s = fma(hw[n - 1] * D[kbase(n) + j], D[kbase(n) + j], s);
+  return s;
+}
+
+// ||v||_e^2 of eq. (snorm) for v given by its Taylor coefficients at x_0
+template <int P>
+__device__ __forceinline__ double seminorm_sq(const double* t, const TriGeo& G, const double* hw,
+                                              const TriTables* __restrict__ tab) {
+  constexpr int NQ = (P + 1) * (P + 1), NK = (P + 1) * (P + 2) / 2 - 1;
+  const double adet = fabs(G.det);
+  double s = 0.0;
+#pragma unroll 1
+  for (int q = 0; q < NQ; ++q) {
+    const double xi = tab->xqd[q], eta = tab->yqd[q];
+    double D[NK];
+    taylor_eval<P>(t, G.J[0][0] * xi + G.J[0][1] * eta, G.J[1][0] * xi + G.J[1][1] * eta, D);
+    s = fma(tab->wqd[q] * adet, weighted_sq<P>(D, hw), s);
+  }
+  return s;
+}
+
+// Taylor coefficients at x_0 of the vertex candidate of local vertex l
+// (a Taylor polynomial about x_l with coefficients c), constant term dropped
+template <int P>
+__device__ __forceinline__ void candidate_at_x0(const float* __restrict__ cand, int32_t vtx, int l, const TriGeo& G,
+                                                double* s) {
+  constexpr int NK = (P + 1) * (P + 2) / 2 - 1;
+  double c[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) c[k] = static_cast<double>(cand[static_cast<int64_t>(vtx) * NK + k]);
+  double dx = 0.0, dy = 0.0;      // x_0 - x_l
+  if (l == 1) { dx = -G.J[0][0]; dy = -G.J[1][0]; }
+  if (l == 2) { dx = -G.J[0][1]; dy = -G.J[1][1]; }
+  taylor_eval<P>(c, dx, dy, s);
+}
+
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void tri_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
+                                                         const int32_t* __restrict__ vptr,
+                                                         const int32_t* __restrict__ vent,
+                                                         const double* __restrict__ geot,
+                                                         const TriTables* __restrict__ tab, int64_t Nv,
+                                                         MethodScalars ms) {
+  constexpr int NLOC = (P + 1) * (P + 2) / 2, NK = NLOC - 1;
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= Nv) return;
+  double num[NK], den = 0.0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) num[k] = 0.0;
+  for (int it = vptr[i]; it < vptr[i + 1]; ++it) {
+    const int ent = vent[it];
+    const int64_t e = ent >> 2;
+    const int lv = ent & 3;
+    const TriGeo G = load_trigeo(geot, e);
+    double uc[NLOC];
+    const float* ue = u + e * NLOC;
+    const double u0 = static_cast<double>(ue[0]);
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) uc[j] = static_cast<double>(ue[j]) - u0;
+    double R[NK], H[NK];
+#pragma unroll
+    for (int m = 0; m < NK; ++m) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 1; j < NLOC; ++j) s = fma(tab->TV[lv][m][j], uc[j], s);
+      R[m] = s;
+    }
+    phys_from_ref<P>(G.A, R, H);
+    // eq. (pointsnorm) with h of the cell whose polynomial is measured
+    double hw[P];
+    order_weights<P>(G.h, hw);
+    const double beta0 = G.h * sqrt(weighted_sq<P>(H, hw));
+    const double beta = ms.fast_exp ? beta0 : pow(beta0, static_cast<double>(ms.q_beta));
+    const double wt = ms.fast_exp ? 1.0 / ((ms.eps_vd + beta) * (ms.eps_vd + beta))
+                                  : pow(ms.eps_vd + beta, -static_cast<double>(ms.r));
+    den += wt;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) num[k] = fma(wt, H[k], num[k]);
+  }
+  const double inv = 1.0 / den;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) cand[i * NK + k] = static_cast<float>(num[k] * inv);
+}
+
+// ---------------------------------------------------------------------------
+constexpr int TRI_EVAL_THREADS = 128;
+
+template <int P, int FLUX>
+__global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float* __restrict__ u, const float* __restrict__ u0,
+                                                       float* __restrict__ out, float* __restrict__ gamma_out,
+                                                       float* __restrict__ alpha_out, const float* __restrict__ cand,
+                                                       const int32_t* __restrict__ cell_vtx,
+                                                       const int32_t* __restrict__ nbrf,
+                                                       const double* __restrict__ geot,
+                                                       const TriTables* __restrict__ tab, int64_t E,
+                                                       MethodScalars ms, int mode, float dt, float a0, float b0,
+                                                       uint32_t* __restrict__ status) {
+  constexpr int NLOC = (P + 1) * (P + 2) / 2, NK = NLOC - 1, NQ = (P + 1) * (P + 1), NG = P + 1;
+  constexpr int NV = NVar<FLUX>::value;
+  __shared__ float sBf[3][NG][NLOC];
+  // per-thread values at the volume points: pointwise semi-norm and |grad s|^2
+  __shared__ float s_at[NQ][TRI_EVAL_THREADS], s_g2[NQ][TRI_EVAL_THREADS];
+  const int tid = threadIdx.x;
+  for (int t = threadIdx.x; t < 3 * NG * NLOC; t += blockDim.x) {
+    const int f = t / (NG * NLOC), g = (t / NLOC) % NG, j = t % NLOC;
+    sBf[f][g][j] = tab->Bf[f][g][j];
+  }
+  __syncthreads();
+  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (e >= E) return;
+  const int64_t stride = E * NLOC;
+  float uv[NV][NLOC];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) uv[v][j] = u[v * stride + e * NLOC + j];
+  const TriGeo G = load_trigeo(geot, e);
+  const double adet = fabs(G.det);
+  double hw[P];
+  order_weights<P>(G.h, hw);
+
+  // ---- sensor field derivatives at the volume points (float64) ----
+  const bool plain = ms.sensor_kind == CVW_SENSOR_PLAIN;
+  double a[NK];
+  {
+    double R[NK];
+    const double s0 = static_cast<double>(uv[0][0]);
+#pragma unroll
+    for (int m = 0; m < NK; ++m) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 1; j < NLOC; ++j) s = fma(tab->TV[0][m][j], static_cast<double>(uv[0][j]) - s0, s);
+      R[m] = s;
+    }
+    phys_from_ref<P>(G.A, R, a);
+  }
+  double n2 = 0.0;
+#pragma unroll 1
+  for (int q = 0; q < NQ; ++q) {
+    const double xi = tab->xqd[q], eta = tab->yqd[q];
+    double D[NK];
+    taylor_eval<P>(a, G.J[0][0] * xi + G.J[0][1] * eta, G.J[1][0] * xi + G.J[1][1] * eta, D);
+    const double pq = weighted_sq<P>(D, hw);
+    n2 = fma(tab->wqd[q] * adet, pq, n2);
+    s_at[q][tid] = static_cast<float>(G.h * sqrt(pq));      // eq. (pointsnorm) at x_q
+    s_g2[q][tid] = static_cast<float>(D[0] * D[0] + D[1] * D[1]);
+  }
+
+  // ---- sensor gamma_e (float64) ----
+  double gam = ms.fixed_gammad;
+  if (plain) {
+    const double n0 = sqrt(n2);
+    const double qb = static_cast<double>(ms.q_beta), rr = static_cast<double>(ms.r);
+    double beta[4];
+    beta[0] = ms.fast_exp ? n0 : pow(n0, qb);
+    int32_t vtx[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) vtx[l] = cell_vtx[e * 3 + l];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      double s[NK];
+      candidate_at_x0<P>(cand, vtx[l], l, G, s);
+      const double nl = sqrt(seminorm_sq<P>(s, G, hw, tab));
+      beta[l + 1] = ms.fast_exp ? nl : pow(nl, qb);
+    }
+    double wt[4], tot = 0.0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const double lin = (l == 0) ? 1.0 - 3.0 * ms.lin_wd : ms.lin_wd;
+      const double b = ms.eps_cd + beta[l];
+      wt[l] = ms.fast_exp ? lin / (b * b) : lin * pow(b, -rr);
+      tot += wt[l];
+    }
+    double diff[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) diff[k] = 0.0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      double s[NK];
+      candidate_at_x0<P>(cand, vtx[l], l, G, s);
+      const double om = wt[l + 1] / tot;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) diff[k] = fma(om, a[k] - s[k], diff[k]);
+    }
+    const double d = sqrt(seminorm_sq<P>(diff, G, hw, tab));
+    if (n0 > 0.0) {
+      const double ratio = fmin(1.0, d / n0);
+      gam = 1.0 - (ms.q_sensor == 1.0f ? ratio : pow(ratio, static_cast<double>(ms.q_sensor)));
+    } else {
+      gam = 1.0;
+    }
+  }
+  const float gf = static_cast<float>(gam);
+
+  // ---- float32 geometry, wave speed, viscosity ----
+  const float J00 = static_cast<float>(G.J[0][0]), J01 = static_cast<float>(G.J[0][1]);
+  const float J10 = static_cast<float>(G.J[1][0]), J11 = static_cast<float>(G.J[1][1]);
+  const float A00 = static_cast<float>(G.A[0][0]), A01 = static_cast<float>(G.A[0][1]);
+  const float A10 = static_cast<float>(G.A[1][0]), A11 = static_cast<float>(G.A[1][1]);
+  const float X0 = static_cast<float>(G.x0), Y0 = static_cast<float>(G.y0);
+  const float fdet = static_cast<float>(adet);
+  float lam = ms.lam_g;
+  if (!(ms.lam_g > 0.0f)) {
+    lam = 0.0f;
+#pragma unroll 1
+    for (int q = 0; q < NQ; ++q) {
+      float uq[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        float s = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NLOC; ++j) s = fmaf(tab->B[q][j], uv[v][j], s);
+        uq[v] = s;
+      }
+      const float px = X0 + J00 * tab->xq[q] + J01 * tab->yq[q];
+      const float py = Y0 + J10 * tab->xq[q] + J11 * tab->yq[q];
+      lam = fmaxf(lam, wave_speed<FLUX>(ms, uq, px, py));
+    }
+  }
+  const float nu = lam * static_cast<float>(G.h) / (2.0f * P);
+
+  // ---- shock-capturing weights (eq. alphaq), from the sensor field ----
+  bool sc_active = false;
+  float ratio = 1.0f;
+  if (ms.sc_on && gam < ms.c_gammad) {
+    float S = 0.0f, T = 0.0f;
+#pragma unroll 1
+    for (int q = 0; q < NQ; ++q) {
+      const float f = (1.0f - gf) * s_g2[q][tid];
+      const float W = tab->wq[q] * fdet;
+      S = fmaf(W, f, S);
+      T = fmaf(W * s_at[q][tid], f, T);
+    }
+    sc_active = S > 0.0f && T > 0.0f;
+    if (sc_active) ratio = S / T;
+  }
+
+  if (mode == MODE_SENSOR) {
+    gamma_out[e] = gf;
+    if (alpha_out)
+      for (int q = 0; q < NQ; ++q) alpha_out[e * NQ + q] = sc_active ? s_at[q][tid] * ratio : 1.0f;
+    return;
+  }
+
+  // ---- volume terms ----
+  float r[NV][NLOC];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) r[v][j] = 0.0f;
+  const float cbase = nu * (1.0f - gf);
+#pragma unroll 1
+  for (int q = 0; q < NQ; ++q) {
+    float uq[NV], ux[NV], uy[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      float s = 0.0f, gx = 0.0f, gy = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) {
+        s = fmaf(tab->B[q][j], uv[v][j], s);
+        gx = fmaf(tab->Gx[q][j], uv[v][j], gx);
+        gy = fmaf(tab->Gy[q][j], uv[v][j], gy);
+      }
+      uq[v] = s;
+      ux[v] = A00 * gx + A10 * gy;
+      uy[v] = A01 * gx + A11 * gy;
+    }
+    const float px = X0 + J00 * tab->xq[q] + J01 * tab->yq[q];
+    const float py = Y0 + J10 * tab->xq[q] + J11 * tab->yq[q];
+    float fx[NV], fy[NV];
+    phys_flux<FLUX>(ms, uq, px, py, fx, fy);
+    const float cst = cbase * (sc_active ? s_at[q][tid] * ratio : 1.0f);
+    const float W = tab->wq[q] * fdet;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const float Gx = -fx[v] + cst * ux[v], Gy = -fy[v] + cst * uy[v];
+      // grad phi_j . G = grad_ref phi_j . (A G)
+      const float Hx = W * (A00 * Gx + A01 * Gy), Hy = W * (A10 * Gx + A11 * Gy);
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) r[v][j] = fmaf(tab->Gx[q][j], Hx, fmaf(tab->Gy[q][j], Hy, r[v][j]));
+    }
+  }
+
+  // ---- interface terms: own faces, the neighbour's trace at the reversed points ----
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int nb = nbrf[e * 3 + f];
+    const int64_t en = nb >> 2;
+    const int fn = nb & 3;
+    float un[NV][NLOC];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) un[v][j] = u[v * stride + en * NLOC + j];
+    // edge from vertex f to vertex f+1 (vertex 0 at the origin of the map)
+    const float ax = (f == 0) ? 0.0f : (f == 1 ? J00 : J01), ay = (f == 0) ? 0.0f : (f == 1 ? J10 : J11);
+    const float bx = (f == 0) ? J00 : (f == 1 ? J01 : 0.0f), by = (f == 0) ? J10 : (f == 1 ? J11 : 0.0f);
+    const float tx = bx - ax, ty = by - ay;
+    const float len = sqrtf(tx * tx + ty * ty);
+    const float nx = ty / len, ny = -tx / len;
+    const float jf = 0.5f * len;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      float um[NV], up[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        float sm = 0.0f, sp = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NLOC; ++j) {
+          sm = fmaf(tab->Bf[f][g][j], uv[v][j], sm);
+          sp = fmaf(sBf[fn][NG - 1 - g][j], un[v][j], sp);
+        }
+        um[v] = sm;
+        up[v] = sp;
+      }
+      const float px = X0 + J00 * tab->xf[f][g] + J01 * tab->yf[f][g];
+      const float py = Y0 + J10 * tab->xf[f][g] + J11 * tab->yf[f][g];
+      float fs[NV];
+      num_flux<FLUX>(ms, um, up, nx, ny, px, py, fs);
+      const float w = tab->wf[g] * jf;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const float wf = w * fs[v];
+#pragma unroll
+        for (int j = 0; j < NLOC; ++j) r[v][j] = fmaf(tab->Bf[f][g][j], wf, r[v][j]);
+      }
+    }
+  }
+
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < NLOC; ++j) {
+    float nodal[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) nodal[v] = uv[v][j];
+    if (!state_admissible<FLUX>(ms, nodal)) bad = true;
+  }
+  if (bad) atomicOr(status, ST_NONPOSITIVE);
+  bool nonfinite = false;
+  if (mode == MODE_RESIDUAL) {
+    if (gamma_out) gamma_out[e] = gf;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) {
+        nonfinite = nonfinite || !isfinite(r[v][j]);
+        out[v * stride + e * NLOC + j] = r[v][j];
+      }
+  } else {
+    // u_out = a0 u_n + b0 (u - dt M_e^{-1} r), M_e = |det J| M_ref
+    const float sc = dt / fdet;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) {
+        float x = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NLOC; ++i) x = fmaf(tab->Minv[j][i], r[v][i], x);
+        const int64_t idx = v * stride + e * NLOC + j;
+        const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
+        const float o = base + b0 * (uv[v][j] - sc * x);
+        nonfinite = nonfinite || !isfinite(o);
+        out[idx] = o;
+      }
+  }
+  if (nonfinite) atomicOr(status, ST_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
+// float64 totals sum_e int_{K_e} u_h = sum_e |det J_e| sum_j m_j u_j, fixed-order
+// reductions (grid-stride thread partials, block tree, then one block)
+constexpr int TRI_TOT_BLOCKS = 512;
+
+template <int NLOC>
+__global__ __launch_bounds__(256) void tri_totals_partial(const float* __restrict__ u,
+                                                          const double* __restrict__ geot,
+                                                          const TriTables* __restrict__ tab,
+                                                          double* __restrict__ part, int64_t E) {
+  __shared__ double sh[256];
+  const int v = blockIdx.y;
+  double acc = 0.0;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < E; e += static_cast<int64_t>(TRI_TOT_BLOCKS) * 256) {
+    const double* g = geot + e * 8;
+    const double det = fabs(g[2] * g[5] - g[4] * g[3]);
+    double s = 0.0;
+    for (int j = 0; j < NLOC; ++j)
+      s += static_cast<double>(tab->mvec[j]) * static_cast<double>(u[(v * E + e) * NLOC + j]);
+    acc += det * s;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[v * TRI_TOT_BLOCKS + blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void tri_totals_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int v = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < TRI_TOT_BLOCKS; i += 256) acc += part[v * TRI_TOT_BLOCKS + i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+static unsigned nblk(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
+
+cvw_status tri_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s) {
+  const MethodScalars ms = make_scalars(prm);
+  const dim3 g(nblk(m->Nv, 256)), b(256);
+  switch (m->degree) {
+    case 1: hipLaunchKernelGGL(tri_vertex_kernel<1>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geot, m->d_trit, m->Nv, ms); break;
+    case 2: hipLaunchKernelGGL(tri_vertex_kernel<2>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geot, m->d_trit, m->Nv, ms); break;
+    case 3: hipLaunchKernelGGL(tri_vertex_kernel<3>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geot, m->d_trit, m->Nv, ms); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+template <int P, int FLUX>
+static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
+                        float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
+                        float a0, float b0, hipStream_t s) {
+  hipLaunchKernelGGL((tri_eval_kernel<P, FLUX>), dim3(nblk(m->E, TRI_EVAL_THREADS)), dim3(TRI_EVAL_THREADS), 0, s, u, u0, out, gamma, alpha,
+                     cand, m->d_cell_vtx, m->d_nbrf, m->d_geot, m->d_trit, m->E, ms, mode, dt, a0, b0, status);
+}
+
+template <int P>
+static cvw_status eval_flux(const cvw_mesh* m, const MethodScalars& ms, int flux, int mode, const float* u,
+                            const float* u0, float* out, float* gamma, float* alpha, const float* cand,
+                            uint32_t* status, float dt, float a0, float b0, hipStream_t s) {
+  switch (flux) {
+    case CVW_ADVECT_CONST: launch_eval<P, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    case CVW_ADVECT_ROT: launch_eval<P, CVW_ADVECT_ROT>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    case CVW_BURGERS: launch_eval<P, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    case CVW_KPP: launch_eval<P, CVW_KPP>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    case CVW_EULER: launch_eval<P, CVW_EULER>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    default: set_error("unknown flux"); return CVW_EINVAL;
+  }
+  return CVW_OK;
+}
+
+cvw_status tri_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
+                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
+                    hipStream_t s) {
+  const MethodScalars ms = make_scalars(prm);
+  cvw_status st;
+  switch (m->degree) {
+    case 1: st = eval_flux<1>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    case 2: st = eval_flux<2>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    case 3: st = eval_flux<3>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+  if (st != CVW_OK) return st;
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+cvw_status tri_totals(const cvw_mesh* m, int nvar, const float* u, double* partial, double* out_dev, hipStream_t s) {
+  const dim3 g(TRI_TOT_BLOCKS, nvar), b(256);
+  switch (m->degree) {
+    case 1: hipLaunchKernelGGL(tri_totals_partial<3>, g, b, 0, s, u, m->d_geot, m->d_trit, partial, m->E); break;
+    case 2: hipLaunchKernelGGL(tri_totals_partial<6>, g, b, 0, s, u, m->d_geot, m->d_trit, partial, m->E); break;
+    case 3: hipLaunchKernelGGL(tri_totals_partial<10>, g, b, 0, s, u, m->d_geot, m->d_trit, partial, m->E); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(tri_totals_final, dim3(nvar), dim3(256), 0, s, partial, out_dev);
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+}  // namespace cvw
