@@ -203,6 +203,49 @@ cvw_status cvw_poll_status(const cvw_mesh* mesh, void* ws, size_t ws_bytes, uint
 cvw_status cvw_totals(const cvw_mesh* mesh, const cvw_params* prm, const void* u, double* out_host,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched time stepping of many independent problems (an ensemble of DG
+ * meshes, Sec. 2 and Sec. 5 applied per instance): every SSP-RK3 stage of all
+ * instances runs as one vertex pass per degree and one cell pass per
+ * (degree, flux), captured once into a HIP graph that is replayed per step.
+ * Instances: DG, congruent axis-aligned periodic quadrilaterals, p <= 3,
+ * float32, scalar flux (constant advection, Burgers, KPP), each with its own
+ * parameters and fixed dt.
+ * ------------------------------------------------------------------------- */
+typedef struct cvw_batch cvw_batch;
+
+typedef struct {
+  const cvw_mesh* mesh;      /* built with cvw_mesh_build; must outlive the batch */
+  cvw_params params;         /* copied at build                                    */
+  void* u;                   /* device state [n_loc * n_cells] float32, updated in
+                                place by cvw_batch_step; must outlive the batch     */
+  double dt;                 /* fixed time step of this instance                    */
+} cvw_batch_instance;
+
+/* Validates the instances, builds the work lists (instance, block) sorted by
+ * estimated cost and uploads the reference tables.  Host arrays are read during
+ * the call only.  The batch handle owns its device descriptors. */
+cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** out);
+void cvw_batch_destroy(cvw_batch* batch);
+
+/* Workspace bytes for cvw_batch_step (256-byte aligned device buffer): a status
+ * word, then per instance the vertex candidates and two stage states. */
+size_t cvw_batch_workspace_bytes(const cvw_batch* batch);
+
+/* n_steps SSP-RK3 steps of every instance.  use_graph != 0: the three stages
+ * are captured once into a graph (on a private stream, for this workspace and
+ * grid) and the graph is launched n_steps times on `stream`; use_graph == 0:
+ * the same kernels are launched directly.  The results are identical, and
+ * bitwise those of cvw_step on each instance alone. */
+cvw_status cvw_batch_step(cvw_batch* batch, int n_steps, int use_graph, void* ws, size_t ws_bytes, void* stream);
+
+/* Blocks per launch of the work-list kernels (grid-stride over the items);
+ * <= 0 selects one block per item.  Invalidates a captured graph. */
+cvw_status cvw_batch_set_grid(cvw_batch* batch, int blocks);
+
+/* As cvw_poll_status, for the status word of a batch workspace. */
+cvw_status cvw_batch_poll_status(void* ws, size_t ws_bytes, uint32_t* flags, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

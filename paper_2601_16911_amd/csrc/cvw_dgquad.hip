@@ -59,15 +59,14 @@ __device__ __forceinline__ double dpow(double x, int n) {
 // ---------------------------------------------------------------------------
 // vertex stage
 // ---------------------------------------------------------------------------
+// One block of 256 vertices (logical block index blk).
 template <int P>
-__global__ __launch_bounds__(256) void dgq_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
-                                                         const int32_t* __restrict__ vptr,
-                                                         const int32_t* __restrict__ vent, int64_t Nv,
-                                                         int64_t nbp, TensorTables tab, double sx, double sy,
-                                                         double he2, MethodScalars ms) {
+__device__ __forceinline__ void dgq_vertex_body(const float* __restrict__ u, float* __restrict__ cand,
+                                                const int32_t* __restrict__ vptr, const int32_t* __restrict__ vent,
+                                                int64_t Nv, int64_t blk, const TensorTables& tab, double sx,
+                                                double sy, double he2, const MethodScalars& ms) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr KSet<P> ks = kset<P>;
-  const int64_t blk = xcd_block(blockIdx.x, nbp);
   const int64_t i = blk * 256 + threadIdx.x;
   if (i >= Nv) return;
   double acc[NK];
@@ -156,6 +155,15 @@ __global__ __launch_bounds__(256) void dgq_vertex_kernel(const float* __restrict
   for (int t = 0; t < NK; ++t) out[t] = static_cast<float>(acc[t] * inv);
 }
 
+template <int P>
+__global__ __launch_bounds__(256) void dgq_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
+                                                         const int32_t* __restrict__ vptr,
+                                                         const int32_t* __restrict__ vent, int64_t Nv,
+                                                         int64_t nbp, TensorTables tab, double sx, double sy,
+                                                         double he2, MethodScalars ms) {
+  dgq_vertex_body<P>(u, cand, vptr, vent, Nv, xcd_block(blockIdx.x, nbp), tab, sx, sy, he2, ms);
+}
+
 // ---------------------------------------------------------------------------
 // cell stage + residual
 // ---------------------------------------------------------------------------
@@ -187,29 +195,20 @@ __device__ __forceinline__ float colbcast(float x, const int (&srcb)[4]) {
   return r;
 }
 
+// One block of 16 cells (logical block index blk); sl = the lane tables in LDS.
 template <int P, int FLUX>
-__global__ __launch_bounds__(256) void dgq_eval_kernel(
+__device__ __forceinline__ void dgq_eval_body(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
-    const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* __restrict__ lanes,
-    TensorTables tab, int64_t E, int64_t nbp, float hx, float hy, float he, MethodScalars ms, int mode, float dt,
-    float a0, float b0, uint32_t* __restrict__ status) {
+    const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* sl,
+    const TensorTables& tab, int64_t E, int64_t blk, float hx, float hy, float he, const MethodScalars& ms,
+    int mode, float dt, float a0, float b0, uint32_t* __restrict__ status) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr int NV = NVar<FLUX>::value;
   constexpr KSet<P> ks = kset<P>;
-  // per-lane tables: one copy per block in LDS
-  __shared__ LaneRec sl[16];
-  {
-    const float4* src = reinterpret_cast<const float4*>(lanes);
-    float4* dst = reinterpret_cast<float4*>(sl);
-    constexpr int n4 = 16 * sizeof(LaneRec) / 16;
-    for (int i = threadIdx.x; i < n4; i += 256) dst[i] = src[i];
-  }
-  __syncthreads();
   const int tid = threadIdx.x;
   const int q = tid & 15;
   const int a = q & 3, b = q >> 2;
-  const int64_t blk = xcd_block(blockIdx.x, nbp);
   const int64_t e = blk * 16 + (tid >> 4);
   if (e >= E) return;                          // whole 16-lane rows leave together
   const LaneRec& L = sl[q];
@@ -524,6 +523,28 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
     atomicOr(status, (m1 ? ST_NONFINITE : 0u) | (m2 ? ST_NONPOSITIVE : 0u));
 }
 
+__device__ __forceinline__ void load_lane_tables(const LaneRec* __restrict__ lanes, LaneRec* sl) {
+  const float4* src = reinterpret_cast<const float4*>(lanes);
+  float4* dst = reinterpret_cast<float4*>(sl);
+  constexpr int n4 = 16 * sizeof(LaneRec) / 16;
+  for (int i = threadIdx.x; i < n4; i += blockDim.x) dst[i] = src[i];
+}
+
+template <int P, int FLUX>
+__global__ __launch_bounds__(256) void dgq_eval_kernel(
+    const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
+    float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
+    const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* __restrict__ lanes,
+    TensorTables tab, int64_t E, int64_t nbp, float hx, float hy, float he, MethodScalars ms, int mode, float dt,
+    float a0, float b0, uint32_t* __restrict__ status) {
+  // per-lane tables: one copy per block in LDS
+  __shared__ LaneRec sl[16];
+  load_lane_tables(lanes, sl);
+  __syncthreads();
+  dgq_eval_body<P, FLUX>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E,
+                         xcd_block(blockIdx.x, nbp), hx, hy, he, ms, mode, dt, a0, b0, status);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -653,6 +674,93 @@ cvw_status totals_f32(const cvw_mesh* m, int nvar, const float* u, double* part,
   int nb = static_cast<int>(std::min<int64_t>(TOT_BLOCKS, (n + 255) / 256));
   hipLaunchKernelGGL(totals_partial_kernel, dim3(nb, nvar), dim3(256), 0, s, u, part, m->E, m->nloc, n1, m->tens, jac);
   hipLaunchKernelGGL(totals_final_kernel, dim3(nvar), dim3(256), 0, s, part, res, nb);
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+}  // namespace cvw
+
+namespace cvw {
+
+// ---------------------------------------------------------------------------
+// Batched stage over many independent meshes: per pass one launch per degree
+// covers every instance of that degree.  Work items (instance, block) are
+// walked by the blocks with a fixed stride; each item runs the same block body
+// as the single-mesh kernels, so results are bitwise those of the single-mesh
+// path.  The cell pass is launched once per (degree, flux) present.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void batch_vertex_kernel(const BatchInst* __restrict__ inst,
+                                                           const int2* __restrict__ items, int n_items,
+                                                           const TensorTables* __restrict__ tabs, int stage) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int2 w = items[it];
+    const BatchInst& I = inst[w.x];
+    dgq_vertex_body<P>(I.u_in[stage], I.cand, I.vptr, I.vent, I.Nv, w.y, tabs[P], I.sxd, I.syd, I.he2d, I.ms);
+  }
+}
+
+template <int P, int FLUX>
+__global__ __launch_bounds__(256) void batch_eval_kernel(const BatchInst* __restrict__ inst,
+                                                         const int2* __restrict__ items, int n_items,
+                                                         const TensorTables* __restrict__ tabs,
+                                                         const LaneRec* __restrict__ lanes, int stage) {
+  __shared__ LaneRec sl[16];
+  load_lane_tables(lanes + 16 * P, sl);
+  __syncthreads();
+  const float A0[3] = {0.0f, 0.75f, 1.0f / 3.0f}, B0[3] = {1.0f, 0.25f, 2.0f / 3.0f};
+  const float a0 = A0[stage], b0 = B0[stage];
+  const TensorTables& tab = tabs[P];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int2 w = items[it];
+    const BatchInst& I = inst[w.x];
+    dgq_eval_body<P, FLUX>(I.u_in[stage], I.u, I.u_out[stage], nullptr, nullptr, I.cand, I.cell_vtx, I.nbr, sl, tab,
+                           I.E, w.y, I.hx, I.hy, I.he, I.ms, MODE_STAGE, I.dt, a0, b0, I.status);
+  }
+}
+
+cvw_status batch_vertex_pass(int P, const BatchInst* inst, const int2* items, int n_items, const TensorTables* tabs,
+                             int stage, int grid, hipStream_t s) {
+  if (n_items <= 0) return CVW_OK;
+  const dim3 g(std::max(1, std::min(grid, n_items))), b(256);
+  switch (P) {
+    case 1: hipLaunchKernelGGL(batch_vertex_kernel<1>, g, b, 0, s, inst, items, n_items, tabs, stage); break;
+    case 2: hipLaunchKernelGGL(batch_vertex_kernel<2>, g, b, 0, s, inst, items, n_items, tabs, stage); break;
+    case 3: hipLaunchKernelGGL(batch_vertex_kernel<3>, g, b, 0, s, inst, items, n_items, tabs, stage); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+template <int P>
+static void launch_batch_eval(int flux, dim3 g, const BatchInst* inst, const int2* items, int n_items,
+                              const TensorTables* tabs, const LaneRec* lanes, int stage, hipStream_t s) {
+  const dim3 b(256);
+  switch (flux) {
+    case CVW_ADVECT_CONST:
+      hipLaunchKernelGGL((batch_eval_kernel<P, CVW_ADVECT_CONST>), g, b, 0, s, inst, items, n_items, tabs, lanes, stage);
+      break;
+    case CVW_BURGERS:
+      hipLaunchKernelGGL((batch_eval_kernel<P, CVW_BURGERS>), g, b, 0, s, inst, items, n_items, tabs, lanes, stage);
+      break;
+    default:
+      hipLaunchKernelGGL((batch_eval_kernel<P, CVW_KPP>), g, b, 0, s, inst, items, n_items, tabs, lanes, stage);
+      break;
+  }
+}
+
+cvw_status batch_eval_pass(int P, int flux, const BatchInst* inst, const int2* items, int n_items,
+                           const TensorTables* tabs, const LaneRec* lanes, int stage, int grid, hipStream_t s) {
+  if (n_items <= 0) return CVW_OK;
+  if (flux != CVW_ADVECT_CONST && flux != CVW_BURGERS && flux != CVW_KPP) {
+    set_error("batched stages: scalar fluxes on DG quadrilaterals"); return CVW_EUNSUPPORTED;
+  }
+  const dim3 g(std::max(1, std::min(grid, n_items)));
+  switch (P) {
+    case 1: launch_batch_eval<1>(flux, g, inst, items, n_items, tabs, lanes, stage, s); break;
+    case 2: launch_batch_eval<2>(flux, g, inst, items, n_items, tabs, lanes, stage, s); break;
+    case 3: launch_batch_eval<3>(flux, g, inst, items, n_items, tabs, lanes, stage, s); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 

@@ -1209,3 +1209,251 @@ cvw_status cvw_totals(const cvw_mesh* m, const cvw_params* prm, const void* u, d
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched stages over many meshes
+// ---------------------------------------------------------------------------
+struct cvw_batch {
+  int n = 0;
+  int device = 0;
+  int grid = 0;                                   // blocks per launch (<= 0: one per item)
+  std::vector<const cvw_mesh*> meshes;
+  std::vector<cvw_params> prms;
+  std::vector<void*> u;
+  std::vector<double> dt;
+  std::vector<size_t> off_cand, off_st1, off_st2;
+  size_t ws_bytes = 0;
+  // work lists: vertex pass per degree, cell pass per (degree, flux)
+  struct List { int P = 0, flux = 0, n = 0; int2* d = nullptr; };
+  std::vector<List> vlists, elists;
+  cvw::BatchInst* d_inst = nullptr;
+  cvw::TensorTables* d_tabs = nullptr;            // [4], index = degree
+  cvw::LaneRec* d_lanes = nullptr;                // [4][16]
+  // captured graph
+  void* graph_ws = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void batch_drop_graph(cvw_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_ws = nullptr;
+}
+
+static void batch_free(cvw_batch* b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  for (auto& l : b->vlists) (void)hipFree(l.d);
+  for (auto& l : b->elists) (void)hipFree(l.d);
+  (void)hipFree(b->d_inst);
+  (void)hipFree(b->d_tabs);
+  (void)hipFree(b->d_lanes);
+  delete b;
+}
+
+// one pass of every stage kernel on stream s (used eagerly and under capture)
+static cvw_status batch_launch_stage(const cvw_batch* b, int stage, hipStream_t s) {
+  for (const auto& l : b->vlists) {
+    const cvw_status st = batch_vertex_pass(l.P, b->d_inst, l.d, l.n, b->d_tabs, stage,
+                                            b->grid > 0 ? b->grid : l.n, s);
+    if (st != CVW_OK) return st;
+  }
+  for (const auto& l : b->elists) {
+    const cvw_status st = batch_eval_pass(l.P, l.flux, b->d_inst, l.d, l.n, b->d_tabs, b->d_lanes, stage,
+                                          b->grid > 0 ? b->grid : l.n, s);
+    if (st != CVW_OK) return st;
+  }
+  return CVW_OK;
+}
+
+static cvw_status batch_upload_descriptors(cvw_batch* b, void* ws) {
+  std::vector<BatchInst> h(b->n);
+  char* base = static_cast<char*>(ws);
+  for (int i = 0; i < b->n; ++i) {
+    const cvw_mesh* m = b->meshes[i];
+    BatchInst& I = h[i];
+    std::memset(&I, 0, sizeof(I));
+    float* u = static_cast<float*>(b->u[i]);
+    float* s1 = reinterpret_cast<float*>(base + b->off_st1[i]);
+    float* s2 = reinterpret_cast<float*>(base + b->off_st2[i]);
+    I.u_in[0] = u;  I.u_out[0] = s1;
+    I.u_in[1] = s1; I.u_out[1] = s2;
+    I.u_in[2] = s2; I.u_out[2] = u;
+    I.u = u;
+    I.cand = reinterpret_cast<float*>(base + b->off_cand[i]);
+    I.cell_vtx = m->d_cell_vtx;
+    I.nbr = m->d_nbr;
+    I.vptr = m->d_vtx_ptr;
+    I.vent = m->d_vtx_ent;
+    I.E = m->E;
+    I.Nv = m->Nv;
+    I.sxd = 2.0 / m->hx;
+    I.syd = 2.0 / m->hy;
+    I.he2d = m->he * m->he;
+    I.hx = static_cast<float>(m->hx);
+    I.hy = static_cast<float>(m->hy);
+    I.he = static_cast<float>(m->he);
+    I.dt = static_cast<float>(b->dt[i]);
+    I.P = m->degree;
+    I.flux = b->prms[i].flux;
+    I.status = reinterpret_cast<uint32_t*>(base);
+    I.ms = make_scalars(&b->prms[i]);
+  }
+  CVW_HIP(hipMemcpy(b->d_inst, h.data(), h.size() * sizeof(BatchInst), hipMemcpyHostToDevice));
+  return CVW_OK;
+}
+
+extern "C" {
+
+cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** out) {
+  if (!inst || !out || n <= 0) { set_error("bad argument"); return CVW_EINVAL; }
+  *out = nullptr;
+  auto* b = new cvw_batch();
+  b->n = n;
+  (void)hipGetDevice(&b->device);
+  size_t off = 256;
+  struct Item { double cost; int inst, blk; };
+  std::vector<Item> vitems[MAXP + 1];
+  std::vector<Item> eitems[MAXP + 1][CVW_EULER + 1];
+  for (int i = 0; i < n; ++i) {
+    const cvw_mesh* m = inst[i].mesh;
+    const cvw_params* prm = &inst[i].params;
+    if (!m || !inst[i].u) { batch_free(b); set_error("null mesh or state"); return CVW_EINVAL; }
+    if (m->device != b->device) { batch_free(b); set_error("instances on different devices"); return CVW_EINVAL; }
+    if (m->cell != CVW_QUAD || m->space != CVW_DG || !m->uniform || !m->closed || m->degree > MAXP) {
+      batch_free(b); set_error("batched stages: DG on congruent axis-aligned periodic quadrilaterals, p <= 3");
+      return CVW_EUNSUPPORTED;
+    }
+    if (prm->dtype != CVW_F32) { batch_free(b); set_error("batched stages run in float32"); return CVW_EUNSUPPORTED; }
+    if (prm->flux != CVW_ADVECT_CONST && prm->flux != CVW_BURGERS && prm->flux != CVW_KPP) {
+      batch_free(b); set_error("batched stages: scalar fluxes (constant advection, Burgers, KPP)");
+      return CVW_EUNSUPPORTED;
+    }
+    if (prm->sensor != CVW_SENSOR_PLAIN && prm->sensor != CVW_SENSOR_FIXED) {
+      batch_free(b); set_error("batched stages: plain or fixed sensor"); return CVW_EUNSUPPORTED;
+    }
+    if (!(inst[i].dt > 0) || !std::isfinite(inst[i].dt)) { batch_free(b); set_error("bad dt"); return CVW_EINVAL; }
+    b->meshes.push_back(m);
+    b->prms.push_back(*prm);
+    b->u.push_back(inst[i].u);
+    b->dt.push_back(inst[i].dt);
+    b->off_cand.push_back(off);
+    off += align256(static_cast<size_t>(m->Nv) * m->nk * 4);
+    b->off_st1.push_back(off);
+    off += align256(static_cast<size_t>(m->E) * m->nloc * 4);
+    b->off_st2.push_back(off);
+    off += align256(static_cast<size_t>(m->E) * m->nloc * 4);
+    // estimated cost of a block: proportional to the nodes per cell
+    const double c = static_cast<double>(m->nloc);
+    const int nvb = static_cast<int>((m->Nv + 255) / 256), neb = static_cast<int>((m->E + 15) / 16);
+    for (int k = 0; k < nvb; ++k) vitems[m->degree].push_back({c, i, k});
+    for (int k = 0; k < neb; ++k) eitems[m->degree][prm->flux].push_back({c, i, k});
+  }
+  b->ws_bytes = off;
+  // longest items first (ties: instance, block), each list uploaded once
+  auto upload_list = [&](std::vector<Item>& v, int P, int flux, std::vector<cvw_batch::List>& dst) -> cvw_status {
+    if (v.empty()) return CVW_OK;
+    std::stable_sort(v.begin(), v.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    std::vector<int2> h(v.size());
+    for (size_t k = 0; k < v.size(); ++k) h[k] = make_int2(v[k].inst, v[k].blk);
+    cvw_batch::List l;
+    l.P = P;
+    l.flux = flux;
+    l.n = static_cast<int>(h.size());
+    const cvw_status st = upload(&l.d, h);
+    if (st != CVW_OK) return st;
+    dst.push_back(l);
+    return CVW_OK;
+  };
+  cvw_status st;
+  for (int P = MAXP; P >= 1; --P) {
+    if ((st = upload_list(vitems[P], P, 0, b->vlists)) != CVW_OK) { batch_free(b); return st; }
+    for (int f = 0; f <= CVW_EULER; ++f)
+      if ((st = upload_list(eitems[P][f], P, f, b->elists)) != CVW_OK) { batch_free(b); return st; }
+  }
+  std::vector<TensorTables> tabs(MAXP + 1);
+  std::vector<LaneRec> lanes(16 * (MAXP + 1));
+  for (int P = 1; P <= MAXP; ++P) {
+    fill_tensor_tables(tabs[P], P, false);
+    fill_lane_tables(lanes.data() + 16 * P, tabs[P], P);
+  }
+  if ((st = upload(&b->d_tabs, tabs)) != CVW_OK) { batch_free(b); return st; }
+  if ((st = upload(&b->d_lanes, lanes)) != CVW_OK) { batch_free(b); return st; }
+  if (hipMalloc(reinterpret_cast<void**>(&b->d_inst), n * sizeof(BatchInst)) != hipSuccess) {
+    batch_free(b); set_error("hipMalloc failed"); return CVW_ENOMEM;
+  }
+  *out = b;
+  return CVW_OK;
+}
+
+void cvw_batch_destroy(cvw_batch* batch) { batch_free(batch); }
+
+size_t cvw_batch_workspace_bytes(const cvw_batch* batch) { return batch ? batch->ws_bytes : 0; }
+
+cvw_status cvw_batch_set_grid(cvw_batch* batch, int blocks) {
+  if (!batch) { set_error("null batch"); return CVW_EINVAL; }
+  batch->grid = blocks;
+  batch_drop_graph(batch);
+  return CVW_OK;
+}
+
+cvw_status cvw_batch_step(cvw_batch* b, int n_steps, int use_graph, void* ws, size_t ws_bytes, void* stream) {
+  if (!b || !ws) { set_error("null argument"); return CVW_EINVAL; }
+  if (ws_bytes < b->ws_bytes) { set_error("workspace too small"); return CVW_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(ws) % 256) { set_error("workspace must be 256-byte aligned"); return CVW_EINVAL; }
+  if (n_steps < 0) { set_error("negative step count"); return CVW_EINVAL; }
+  auto s = static_cast<hipStream_t>(stream);
+  cvw_status st = CVW_OK;
+  if (ws != b->graph_ws) {
+    // descriptors point into this workspace; written before any launch that reads them
+    CVW_HIP(hipStreamSynchronize(s));
+    batch_drop_graph(b);
+    if ((st = batch_upload_descriptors(b, ws)) != CVW_OK) return st;
+    b->graph_ws = ws;
+  }
+  if (!use_graph) {
+    for (int k = 0; k < n_steps; ++k)
+      for (int stage = 0; stage < 3; ++stage)
+        if ((st = batch_launch_stage(b, stage, s)) != CVW_OK) return st;
+    return CVW_OK;
+  }
+  if (!b->exec) {
+    hipStream_t cap;
+    CVW_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    CVW_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    for (int stage = 0; stage < 3 && st == CVW_OK; ++stage) st = batch_launch_stage(b, stage, cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (st != CVW_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e1 != hipSuccess || !g) { set_error("graph capture failed"); return CVW_EDEVICE; }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      set_error("graph instantiation failed");
+      return CVW_EDEVICE;
+    }
+    b->graph = g;
+    b->exec = ex;
+  }
+  for (int k = 0; k < n_steps; ++k) CVW_HIP(hipGraphLaunch(b->exec, s));
+  return CVW_OK;
+}
+
+cvw_status cvw_batch_poll_status(void* ws, size_t ws_bytes, uint32_t* flags, void* stream) {
+  if (!ws || !flags || ws_bytes < 256) { set_error("bad argument"); return CVW_EINVAL; }
+  auto s = static_cast<hipStream_t>(stream);
+  uint32_t h = 0;
+  CVW_HIP(hipMemcpyAsync(&h, ws, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  CVW_HIP(hipStreamSynchronize(s));
+  const uint32_t zero = 0;
+  CVW_HIP(hipMemcpyAsync(ws, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  CVW_HIP(hipStreamSynchronize(s));
+  *flags = h;
+  return h ? CVW_ENUMERIC : CVW_OK;
+}
+
+}  // extern "C"

@@ -106,6 +106,27 @@ struct MethodScalars {
   double eps_vd, eps_cd, lin_wd, c_gammad, lam_gd, fixed_gammad, fpd[4];
 };
 
+// Per-instance descriptor of a batch of independent DG quadrilateral meshes
+// (device memory, written by the host before a batch step).  The Runge-Kutta
+// stage s reads state in[s] and writes out[s]: u -> st1 -> st2 -> u.
+struct alignas(16) BatchInst {
+  const float* u_in[3];
+  float* u_out[3];
+  float* u;                         // u_n (the caller's state)
+  float* cand;
+  const int32_t* cell_vtx;
+  const int32_t* nbr;
+  const int32_t* vptr;
+  const int32_t* vent;
+  int64_t E, Nv;
+  double sxd, syd, he2d;            // 2 / h_x, 2 / h_y, h_e^2 (vertex pass)
+  float hx, hy, he, dt;
+  int P, flux;
+  uint32_t* status;
+  MethodScalars ms;
+};
+
+
 }  // namespace cvw
 
 struct cvw_mesh {
@@ -171,6 +192,14 @@ cvw_status cgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const
 cvw_status seg_candidates(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand, hipStream_t s);
 cvw_status seg_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const void* u, const void* cand, void* pg,
                     void* rcell, void* R, void* gamma, void* alpha, uint32_t* status, hipStream_t s);
+// batched DG quadrilateral stage over many meshes (cvw_dgquad.hip): the
+// vertex pass is launched once per degree P, the cell pass once per (P, flux);
+// items are (instance, logical block) pairs of the instances of that class,
+// processed by a grid-stride loop
+cvw_status batch_vertex_pass(int P, const BatchInst* inst, const int2* items, int n_items, const TensorTables* tabs,
+                             int stage, int grid, hipStream_t s);
+cvw_status batch_eval_pass(int P, int flux, const BatchInst* inst, const int2* items, int n_items,
+                           const TensorTables* tabs, const LaneRec* lanes, int stage, int grid, hipStream_t s);
 // kernel launchers (cvw_tri.hip)
 cvw_status tri_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
 cvw_status tri_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,

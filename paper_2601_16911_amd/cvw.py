@@ -24,7 +24,8 @@ EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXP
 
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
            "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_residual",
-           "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals"]
+           "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_batch_build", "cvw_batch_destroy",
+           "cvw_batch_workspace_bytes", "cvw_batch_step", "cvw_batch_set_grid", "cvw_batch_poll_status"]
 
 
 class CvwError(RuntimeError):
@@ -45,6 +46,10 @@ class ParamsC(C.Structure):
                 ("q_sensor", C.c_double), ("q_beta", C.c_double), ("lin_w_vertex", C.c_double),
                 ("c_gamma", C.c_double), ("lambda_global", C.c_double), ("sensor", C.c_int32),
                 ("pad0", C.c_int32), ("fixed_gamma", C.c_double)]
+
+
+class BatchInstanceC(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("params", ParamsC), ("u", C.c_void_p), ("dt", C.c_double)]
 
 
 class MeshInfoC(C.Structure):
@@ -83,8 +88,17 @@ def load():
     lib.cvw_step.argtypes = [vp, C.POINTER(ParamsC), vp, C.c_double, C.c_int, vp, sz, vp]
     lib.cvw_poll_status.argtypes = [vp, vp, sz, C.POINTER(C.c_uint32), vp]
     lib.cvw_totals.argtypes = [vp, C.POINTER(ParamsC), vp, C.POINTER(C.c_double), vp, sz, vp]
+    lib.cvw_batch_build.argtypes = [C.POINTER(BatchInstanceC), C.c_int, C.POINTER(vp)]
+    lib.cvw_batch_destroy.argtypes = [vp]
+    lib.cvw_batch_destroy.restype = None
+    lib.cvw_batch_workspace_bytes.argtypes = [vp]
+    lib.cvw_batch_workspace_bytes.restype = sz
+    lib.cvw_batch_step.argtypes = [vp, C.c_int, C.c_int, vp, sz, vp]
+    lib.cvw_batch_set_grid.argtypes = [vp, C.c_int]
+    lib.cvw_batch_poll_status.argtypes = [vp, sz, C.POINTER(C.c_uint32), vp]
     for name in SYMBOLS:
-        if name not in ("cvw_abi_version", "cvw_last_error", "cvw_mesh_destroy", "cvw_workspace_bytes"):
+        if name not in ("cvw_abi_version", "cvw_last_error", "cvw_mesh_destroy", "cvw_workspace_bytes",
+                        "cvw_batch_destroy", "cvw_batch_workspace_bytes"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -255,3 +269,56 @@ def totals(mesh, prm, u, ws, stream=None, n_var: int = 1):
     _check(load().cvw_totals(mesh.handle, C.byref(prm), _fp(u, prm, _state_len(mesh, prm), "u"), out, _ptr(ws),
                              ws.numel(), _stream(stream)))
     return np.array(out[:])
+
+
+class Batch:
+    """An ensemble of DG quadrilateral problems stepped together (cvw_batch_*).
+
+    instances: list of (Mesh, ParamsC, u, dt) with u a float32 device tensor of
+    the instance's state, updated in place by step().  The batch keeps
+    references to the meshes and states it was built on."""
+
+    def __init__(self, instances):
+        arr = (BatchInstanceC * len(instances))()
+        self._keep = []
+        for k, (mesh, prm, u, dt) in enumerate(instances):
+            arr[k].mesh = mesh.handle
+            arr[k].params = prm
+            arr[k].u = _fp(u, prm, _state_len(mesh, prm), "u")
+            arr[k].dt = float(dt)
+            self._keep.append((mesh, u))
+        h = C.c_void_p()
+        _check(load().cvw_batch_build(arr, len(instances), C.byref(h)))
+        self._h = h
+
+    def workspace_bytes(self) -> int:
+        return int(load().cvw_batch_workspace_bytes(self._h))
+
+    def alloc_workspace(self, device="cuda"):
+        import torch
+        return torch.zeros(self.workspace_bytes(), dtype=torch.uint8, device=device)
+
+    def set_grid(self, blocks: int):
+        _check(load().cvw_batch_set_grid(self._h, int(blocks)))
+
+    def step(self, n_steps: int, ws, use_graph: bool = True, stream=None):
+        _check(load().cvw_batch_step(self._h, int(n_steps), 1 if use_graph else 0, _ptr(ws), ws.numel(),
+                                     _stream(stream)))
+
+    def poll_status(self, ws, stream=None) -> int:
+        flags = C.c_uint32(0)
+        st = load().cvw_batch_poll_status(_ptr(ws), ws.numel(), C.byref(flags), _stream(stream))
+        if st not in (OK, ENUMERIC):
+            _check(st)
+        return int(flags.value)
+
+    def close(self):
+        if self._h:
+            load().cvw_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -266,6 +266,37 @@ def u0_instance(inst: Instance, x, y):
     return u + amp * np.exp(-(dx * dx + dy * dy) / (2 * sig * sig))
 
 
+def instance_params(inst: Instance) -> "Params":
+    """Method parameters of one ensemble instance (paper defaults, its flux)."""
+    if inst.flux == ADVECT_CONST:
+        return Params(flux=ADVECT_CONST, flux_param=(inst.velocity[0], inst.velocity[1], 0.0, 0.0))
+    return Params(flux=BURGERS, flux_param=(1.0, 1.0, 0.0, 0.0))
+
+
+def instance_case(inst: Instance, n: int = None, cfl: float = 0.1):
+    """(mesh, p, params, nodal state [E * (p+1)^2], dt) of one ensemble instance:
+    periodic n x n unit-square quads (n defaults to the instance's), the initial
+    data sampled at the Gauss-Legendre nodes of each cell (node (a, b) at index
+    a + (p+1) b), and dt = cfl * h / (p * lambda_max) with lambda_max of the
+    initial data."""
+    n = inst.n if n is None else n
+    p = inst.p
+    mesh = quad_mesh(n, n)
+    g, _ = np.polynomial.legendre.leggauss(p + 1)
+    h = 1.0 / n
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    xc = (ii.ravel() + 0.5) * h
+    yc = (jj.ravel() + 0.5) * h
+    gx, gy = np.meshgrid(g, g, indexing="xy")
+    X = xc[:, None] + 0.5 * h * gx.ravel()[None, :]
+    Y = yc[:, None] + 0.5 * h * gy.ravel()[None, :]
+    U = u0_instance(inst, X, Y)
+    prm = instance_params(inst)
+    lam = 1.0 if inst.flux == ADVECT_CONST else float(np.sqrt(2.0) * np.abs(U).max())
+    dt = cfl * h / (p * lam)
+    return mesh, p, prm, U.ravel(), dt
+
+
 def smooth_field(x, y, seed: int, modes: int = 3):
     """A seeded smooth periodic field on the unit square (sum of a few Fourier modes)."""
     rng = np.random.default_rng(seed)
