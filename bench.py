@@ -105,6 +105,72 @@ def cpu_baseline(target_seconds: float = 15.0):
                       f"mesh ({dofs} DOFs) with the same state recipe, single process, {dt:.1f} s"}
 
 
+def _timed(torch, stream, fn, reps: int) -> float:
+    """Seconds per call of fn() on `stream` (HIP events), after one warm-up call."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def bench_ensemble(torch, cvw, steps: int):
+    """The 64-instance DG ensemble (periodic unit squares, n in [64, 512], p in
+    {1, 2, 3}, advection or Burgers, seeded), all instances stepped together by
+    the batched stage, graph-captured and eager."""
+    import synth
+    stream = torch.cuda.current_stream()
+    items, dofs = [], 0
+    for inst in synth.config5_instances():
+        mesh, p, prm, U, dt = synth.instance_case(inst)
+        gm = cvw.Mesh(mesh, p, cvw.DG)
+        u = torch.from_numpy(np.asarray(U, np.float32)).cuda()
+        items.append((gm, cvw.make_params(prm), u, dt))
+        dofs += U.size
+    b = cvw.Batch(items)
+    ws = b.alloc_workspace()
+    out = {"workload": "64-instance DG ensemble, periodic n x n quads (n in [64, 512]), p in {1,2,3}, "
+                       "advection / Burgers, SSP-RK3", "instances": len(items), "dofs": dofs, "steps": steps}
+    for name, graph in (("graph", True), ("eager", False)):
+        t = _timed(torch, stream, lambda: b.step(steps, ws, use_graph=graph), 1) / steps
+        out[name] = {"value": 3.0 * dofs / t, "unit": "DOF-updates/s", "ms_per_step": t * 1e3}
+    out["status_flags"] = b.poll_status(ws)
+    return out
+
+
+def bench_triangles(torch, cvw, steps: int):
+    """512 x 512 squares split into 524,288 jittered triangles, DG P3, KPP."""
+    import synth
+    stream = torch.cuda.current_stream()
+    n, p = 512, 3
+    mesh = synth.tri_mesh(n, n, -2.0, 2.0, -2.5, 1.5, jitter=0.1, seed=1003)
+    X = mesh.cell_coords
+    nodes = np.array([(i / p, j / p) for j in range(p + 1) for i in range(p + 1 - j)])
+    px = X[:, 0, None, 0] + (X[:, 1, None, 0] - X[:, 0, None, 0]) * nodes[None, :, 0] \
+        + (X[:, 2, None, 0] - X[:, 0, None, 0]) * nodes[None, :, 1]
+    py = X[:, 0, None, 1] + (X[:, 1, None, 1] - X[:, 0, None, 1]) * nodes[None, :, 0] \
+        + (X[:, 2, None, 1] - X[:, 0, None, 1]) * nodes[None, :, 1]
+    U = torch.from_numpy(np.asarray(synth.u0_kpp(px, py), np.float32).ravel()).cuda()
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    prm = synth.Params(flux=synth.KPP, lambda_global=1.0)
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, 1)
+    R = torch.empty_like(U)
+    dofs = U.numel()
+    h_min = 4.0 / n * 0.8
+    dt = 0.1 * h_min / (2 * p + 1)
+    t_res = _timed(torch, stream, lambda: cvw.residual(gm, cp, U, R, None, ws), 10)
+    t_step = _timed(torch, stream, lambda: cvw.step(gm, cp, U, dt, steps, ws), 1) / steps
+    return {"workload": f"KPP, DG P3 on {mesh.n_cells} jittered triangles", "dofs": dofs,
+            "residual": {"value": dofs / t_res, "unit": "DOF-updates/s", "ms": t_res * 1e3},
+            "step": {"value": 3.0 * dofs / t_step, "unit": "DOF-updates/s", "ms_per_step": t_step * 1e3},
+            "status_flags": cvw.poll_status(gm, ws)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +178,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024, help="cells per direction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the side measurements (ensemble batch, triangles)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -227,6 +295,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         out["copy_calib_bytes"] = a.numel() * 4
+    if not args.no_extra:
+        torch.cuda.empty_cache()
+        out["ensemble_batch"] = bench_ensemble(torch, cvw, 10)
+        torch.cuda.empty_cache()
+        out["triangles_kpp"] = bench_triangles(torch, cvw, 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -277,8 +277,9 @@ def instance_case(inst: Instance, n: int = None, cfl: float = 0.1):
     """(mesh, p, params, nodal state [E * (p+1)^2], dt) of one ensemble instance:
     periodic n x n unit-square quads (n defaults to the instance's), the initial
     data sampled at the Gauss-Legendre nodes of each cell (node (a, b) at index
-    a + (p+1) b), and dt = cfl * h / (p * lambda_max) with lambda_max of the
-    initial data."""
+    a + (p+1) b), and dt = cfl * h / ((2p + 1) lambda_max) with lambda_max of
+    the initial data (the explicit DG limit; the shock-capturing viscosity
+    needs cfl well below 0.2)."""
     n = inst.n if n is None else n
     p = inst.p
     mesh = quad_mesh(n, n)
@@ -293,7 +294,7 @@ def instance_case(inst: Instance, n: int = None, cfl: float = 0.1):
     U = u0_instance(inst, X, Y)
     prm = instance_params(inst)
     lam = 1.0 if inst.flux == ADVECT_CONST else float(np.sqrt(2.0) * np.abs(U).max())
-    dt = cfl * h / (p * lam)
+    dt = cfl * h / ((2 * p + 1) * lam)
     return mesh, p, prm, U.ravel(), dt
 
 
