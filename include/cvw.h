@@ -177,18 +177,25 @@ cvw_status cvw_sensor(const cvw_mesh* mesh, const cvw_params* prm, const void* u
 cvw_status cvw_residual(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* R,
                         void* gamma_out, void* ws, size_t ws_bytes, void* stream);
 
-/* One stage of the SSP Runge-Kutta method in Shu-Osher form, given the vertex
- * candidates `cand` of u_stage (from cvw_vertex_candidates):
- *   u_out = a0 * u_n + b0 * (u_stage + dt * L(u_stage)),  L = -M^{-1} R,
- * with the exact element mass for DG.  u_n is not read when a0 == 0; u_out may
- * alias u_n (each entry of u_n is read only by the thread that overwrites it)
- * but must not alias u_stage or cand. */
+/* One stage of the SSP Runge-Kutta method in Shu-Osher form (Sec. 5), given
+ * the vertex candidates `cand` of u_stage (from cvw_vertex_candidates):
+ *   u_out = a0 * u_n + b0 * (u_stage + dt * L(u_stage)),  L = -M^{-1} R
+ * (eq. sdstab).  M: DG exact element mass (diagonal on Gauss-node quads and
+ * segments, M_ref |det J| on triangles); CG the consistent global mass,
+ * inverted on the device by preconditioned conjugate gradients (lumped-mass
+ * preconditioner, relative tolerance 2e-7 in float32 and 1e-14 in float64,
+ * at most 64 / 160 iterations; no host synchronisation).  u_n is not read
+ * when a0 == 0; u_out may alias u_n (each entry of u_n is read only by the
+ * thread that overwrites it) but must not alias u_stage or cand.  Meshes:
+ * every mesh with a GPU path (DG quads and triangles, CG quads, segments). */
 cvw_status cvw_rk_stage(const cvw_mesh* mesh, const cvw_params* prm, const void* u_stage, const void* cand,
                         const void* u_n, void* u_out, double dt, double a0, double b0, void* ws, size_t ws_bytes,
                         void* stream);
 
 /* n_steps steps of the three-stage SSP Runge-Kutta method with fixed dt,
- * u updated in place (Sec. 2.2 / Sec. 5).  DG: exact element mass. */
+ * u updated in place (Sec. 2.2 / Sec. 5): per stage the vertex candidates
+ * (plain sensor) and cvw_rk_stage, with the two intermediate states in the
+ * workspace (op = 1). */
 cvw_status cvw_step(const cvw_mesh* mesh, const cvw_params* prm, void* u, double dt, int n_steps,
                     void* ws, size_t ws_bytes, void* stream);
 
@@ -198,8 +205,8 @@ cvw_status cvw_step(const cvw_mesh* mesh, const cvw_params* prm, void* u, double
 cvw_status cvw_poll_status(const cvw_mesh* mesh, void* ws, size_t ws_bytes, uint32_t* flags, void* stream);
 
 /* Per-variable integrals sum_e int_{K_e} u_h dx accumulated in float64 on the
- * device (conservation check); writes n_var doubles to host memory and
- * synchronises `stream`. */
+ * device (conservation check), DG quadrilaterals and triangles; writes n_var
+ * doubles to host memory and synchronises `stream`. */
 cvw_status cvw_totals(const cvw_mesh* mesh, const cvw_params* prm, const void* u, double* out_host,
                       void* ws, size_t ws_bytes, void* stream);
 
