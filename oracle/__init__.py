@@ -15,6 +15,9 @@ method     Hermite data, vertex HWENO candidates, cell WENO weights,
            sensor gamma_e (Sec. 3.2, eq. gamma / snorm / pointsnorm),
            shock-capturing quadrature weights alpha_q (Sec. 4),
            stabilised residual and SSP-RK3 (Sec. 2, eq. stabform / sdstab).
+learned    a learned replacement of the sensor gamma_e: features of the
+           normalised cell and vertex Hermite data, a 48-64-64-1 network,
+           its backward pass, Adam (not from the paper; see its docstring).
 """
 from .space import Space, build_space
 from .method import (hermite_at_vertices, vertex_candidates, cell_sensor, sc_weights,
