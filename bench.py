@@ -118,6 +118,54 @@ def _timed(torch, stream, fn, reps: int) -> float:
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
+def bench_learned(torch, cvw, gm, prm, U, dt, steps: int):
+    """The learned sensor on the benchmark workload: a network trained for a
+    few seconds by the library's kernels on snapshots of a plain-sensor run
+    of the same problem at 256 x 256, then the sensor alone (cells/s) and the
+    full SSP-RK3 step (DOF-updates/s), plain vs learned."""
+    import synth
+    from paper_2601_16911_amd import learned
+    stream = torch.cuda.current_stream()
+    n_small = 256
+    mesh_s = synth.quad_mesh(n_small, n_small)
+    gs = cvw.Mesh(mesh_s, 3, cvw.DG)
+    Us = torch.from_numpy(euler_config4_state(n_small, gauss_nodes_2d(3), SMOOTH_K * n_small / 1024).reshape(-1)).cuda()
+    sref_s = learned.sigma_reference(gs, cvw.make_params(prm), Us)
+    F, G = learned.collect(gs, prm, Us, dt * 1024 / n_small, 8, 4, sref_s)
+    net = cvw.Mlp(learned.init_params(4))
+    t0 = time.perf_counter()
+    learned.train(net, F, G, epochs=20, batch=4096, lr=1e-3, seed=4)
+    t_train = time.perf_counter() - t0
+    E = gm.info["n_cells"]
+    sref = learned.sigma_reference(gm, cvw.make_params(prm), U)
+    prm_l = synth.Params(**{**prm.__dict__, "sensor": cvw.LEARNED})
+    cpp = cvw.make_params(prm)
+    cpl = cvw.make_params(prm_l, mlp=net, sigma_ref=sref)
+    wsp = cvw.alloc_workspace(gm, cpp, 1)
+    wsl = cvw.alloc_workspace(gm, cpl, 1)
+    gam = torch.empty(E, dtype=torch.float32, device="cuda")
+    t_sp = _timed(torch, stream, lambda: cvw.sensor(gm, cpp, U, gam, None, wsp), 10)
+    t_sl = _timed(torch, stream, lambda: cvw.sensor(gm, cpl, U, gam, None, wsl), 10)
+    ndof = U.numel()
+    u1 = U.clone()
+    t_step_p = _timed(torch, stream, lambda: cvw.step(gm, cpp, u1, dt, steps, wsp), 1) / steps
+    u2 = U.clone()
+    t_step_l = _timed(torch, stream, lambda: cvw.step(gm, cpl, u2, dt, steps, wsl), 1) / steps
+    feat = torch.empty((E, 48), dtype=torch.int16, device="cuda")
+    cand = torch.empty((gm.info["n_vertices"], gm.info["n_k"]), dtype=torch.float32, device="cuda")
+    cvw.vertex_candidates(gm, cpl, U, cand, wsl)
+    t_feat = _timed(torch, stream, lambda: cvw.mlp_features(gm, cpl, U, cand, feat), 10)
+    t_inf = _timed(torch, stream, lambda: net.infer(feat, gam), 10)
+    return {"training": {"snapshot_cells": int(F.shape[0]), "epochs": 20, "batch": 4096, "seconds": t_train},
+            "sensor_plain": {"value": E / t_sp, "unit": "cells/s", "ms": t_sp * 1e3},
+            "sensor_learned": {"value": E / t_sl, "unit": "cells/s", "ms": t_sl * 1e3},
+            "step_plain": {"value": 3.0 * ndof / t_step_p, "unit": "DOF-updates/s", "ms_per_step": t_step_p * 1e3},
+            "step_learned": {"value": 3.0 * ndof / t_step_l, "unit": "DOF-updates/s", "ms_per_step": t_step_l * 1e3},
+            "features_ms": t_feat * 1e3, "network_ms": t_inf * 1e3,
+            "network_tflops": 14464.0 * E / t_inf / 1e12,
+            "status_flags": [cvw.poll_status(gm, wsp), cvw.poll_status(gm, wsl)]}
+
+
 def bench_ensemble(torch, cvw, steps: int):
     """The 64-instance DG ensemble (periodic unit squares, n in [64, 512], p in
     {1, 2, 3}, advection or Burgers, seeded), all instances stepped together by
@@ -296,6 +344,8 @@ def main():
         torch.cuda.synchronize()
         out["copy_calib_bytes"] = a.numel() * 4
     if not args.no_extra:
+        torch.cuda.empty_cache()
+        out["learned_sensor"] = bench_learned(torch, cvw, gm, prm, U, dt, 5)
         torch.cuda.empty_cache()
         out["ensemble_batch"] = bench_ensemble(torch, cvw, 10)
         torch.cuda.empty_cache()

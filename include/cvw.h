@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 1
+#define CVW_ABI_VERSION 2
 
 typedef enum {
   CVW_OK = 0,
@@ -105,6 +105,8 @@ typedef struct {
   int32_t sensor;            /* cvw_sensor_kind                                  */
   int32_t pad0;
   double fixed_gamma;        /* gamma_e for CVW_SENSOR_FIXED                     */
+  double sigma_ref;          /* CVW_SENSOR_LEARNED: reference scale of the features (> 0) */
+  const struct cvw_mlp* mlp; /* CVW_SENSOR_LEARNED: the network (cvw_mlp_create)  */
 } cvw_params;
 
 typedef struct {
@@ -209,6 +211,53 @@ cvw_status cvw_poll_status(const cvw_mesh* mesh, void* ws, size_t ws_bytes, uint
  * doubles to host memory and synchronises `stream`. */
 cvw_status cvw_totals(const cvw_mesh* mesh, const cvw_params* prm, const void* u, double* out_host,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned smoothness sensor (not in the paper: a replacement of gamma_e of
+ * eq. gamma by a small network, trained on gamma_e of the method itself).
+ * Features, per cell of a DG quadrilateral mesh (48, bfloat16, [n_cells][48]):
+ * 4 vertex slots x 9 multi-indices 1 <= |k| <= 3 of
+ * h_e^|k| (c_i[k] - D^k s^e(x_i)) / sigma_e (vertex candidate of eq. taylorcand
+ * minus the cell's own Hermite data of eq. taylorsol), 9 slots
+ * h_e^|k| D^k s^e(x_c) / sigma_e at the cell centre, log10(sigma_e / sigma_ref),
+ * and the largest and the mean of the four per-vertex mismatch 2-norms;
+ * sigma_e = ||s^e||_e + 1e-12 sigma_ref (eq. snorm), orders above p are 0.
+ * Network: 48 -> 64 -> 64 -> 1, GELU (erf form) after both hidden layers,
+ * sigmoid output.  Packed float32 parameters (7361): W1 [48][64], b1 [64],
+ * W2 [64][64], b2 [64], w3 [64], b3.  Inference on bfloat16 matrix cores
+ * (inputs, weights and hidden activations rounded to bfloat16, float32
+ * accumulation); training with Adam on float32 master weights.
+ * ------------------------------------------------------------------------- */
+typedef struct cvw_mlp cvw_mlp;
+#define CVW_MLP_NPARAM 7361
+
+/* Creates a network on the current device from packed host parameters (read
+ * during the call).  Adam moments start at zero. */
+cvw_status cvw_mlp_create(const float* params, cvw_mlp** out);
+void cvw_mlp_destroy(cvw_mlp* mlp);
+/* Copies the float32 master parameters to / from host memory (synchronous);
+ * set also resets the Adam state. */
+cvw_status cvw_mlp_get_params(const cvw_mlp* mlp, float* params);
+cvw_status cvw_mlp_set_params(cvw_mlp* mlp, const float* params);
+
+/* Features of every cell (DG quadrilaterals, float32): u the state (the first
+ * variable is the sensor field), cand its vertex candidates, prm->sigma_ref
+ * the reference scale; feat: device bfloat16 [n_cells][48]. */
+cvw_status cvw_mlp_features(const cvw_mesh* mesh, const cvw_params* prm, const void* u, const void* cand,
+                            void* feat, void* stream);
+/* gamma[i] = network(feat[i]) for i < n: device float32 [n]. */
+cvw_status cvw_mlp_infer(const cvw_mlp* mlp, const void* feat, int64_t n, void* gamma, void* stream);
+
+/* Workspace bytes of cvw_mlp_train_step for a batch size. */
+size_t cvw_mlp_train_workspace_bytes(int batch);
+/* One training step on the rows idx[0..batch) of feat (device int32), with
+ * targets target[row] (device float32): loss mean((gamma - target)^2), its
+ * gradient (float32 activations through the bfloat16 weights and inputs),
+ * written to grad_out (device float32 [7361]) when not NULL, then one Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8) with rate lr on the master weights
+ * (lr = 0: gradient only).  1 <= batch <= 65536. */
+cvw_status cvw_mlp_train_step(cvw_mlp* mlp, const void* feat, const void* target, const void* idx, int batch,
+                              float lr, void* grad_out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched time stepping of many independent problems (an ensemble of DG

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcvw.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["cvw_host.cpp", "cvw_dgquad.hip", "cvw_cgquad.hip", "cvw_seg.hip", "cvw_cgstep.hip", "cvw_tri.hip"]
+SOURCES = ["cvw_host.cpp", "cvw_dgquad.hip", "cvw_cgquad.hip", "cvw_seg.hip", "cvw_cgstep.hip", "cvw_tri.hip", "cvw_mlp.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

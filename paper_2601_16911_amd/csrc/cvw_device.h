@@ -245,6 +245,14 @@ __device__ __forceinline__ void geo_eval(const Geo& G, float xi, float eta, floa
 
 // XCD-aware block order: consecutive logical blocks land on the same XCD so
 // that a block's neighbours (one grid row away) are served by the same L2.
+// bfloat16 bit patterns, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return static_cast<uint16_t>(b >> 16);
+}
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
 __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks_padded) {
   const int64_t per = nblocks_padded >> 3;
   return (bid & 7) * per + (bid >> 3);

@@ -202,7 +202,8 @@ __device__ __forceinline__ void dgq_eval_body(
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
     const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* sl,
     const TensorTables& tab, int64_t E, int64_t blk, float hx, float hy, float he, const MethodScalars& ms,
-    int mode, float dt, float a0, float b0, uint32_t* __restrict__ status) {
+    int mode, float dt, float a0, float b0, uint32_t* __restrict__ status,
+    const float* __restrict__ gamma_in = nullptr) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr int NV = NVar<FLUX>::value;
   constexpr KSet<P> ks = kset<P>;
@@ -283,6 +284,8 @@ __device__ __forceinline__ void dgq_eval_body(
   float gam;
   if (ms.sensor_kind == CVW_SENSOR_FIXED) {
     gam = ms.fixed_gamma;
+  } else if (ms.sensor_kind == CVW_SENSOR_LEARNED) {
+    gam = gamma_in[e];                         // from the network, one value per cell
   } else {
     const float xq = L.misc[6], yq = L.misc[7];
     float n2p = 0.0f;
@@ -536,13 +539,13 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
     const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* __restrict__ lanes,
     TensorTables tab, int64_t E, int64_t nbp, float hx, float hy, float he, MethodScalars ms, int mode, float dt,
-    float a0, float b0, uint32_t* __restrict__ status) {
+    float a0, float b0, uint32_t* __restrict__ status, const float* __restrict__ gamma_in) {
   // per-lane tables: one copy per block in LDS
   __shared__ LaneRec sl[16];
   load_lane_tables(lanes, sl);
   __syncthreads();
   dgq_eval_body<P, FLUX>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E,
-                         xcd_block(blockIdx.x, nbp), hx, hy, he, ms, mode, dt, a0, b0, status);
+                         xcd_block(blockIdx.x, nbp), hx, hy, he, ms, mode, dt, a0, b0, status, gamma_in);
 }
 
 // ---------------------------------------------------------------------------
@@ -572,30 +575,30 @@ cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const flo
 template <int P, int FLUX>
 static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
                         float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
-                        float a0, float b0, hipStream_t s) {
+                        float a0, float b0, const float* gamma_in, hipStream_t s) {
   const int64_t nb = pad8((m->E + 15) / 16);
   hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0, out,
                      gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, nb,
                      static_cast<float>(m->hx), static_cast<float>(m->hy), static_cast<float>(m->he), ms, mode, dt,
-                     a0, b0, status);
+                     a0, b0, status, gamma_in);
 }
 
 template <int P>
 static cvw_status eval_p(const cvw_mesh* m, const MethodScalars& ms, int flux, int mode, const float* u,
                          const float* u0, float* out, float* gamma, float* alpha, const float* cand,
-                         uint32_t* status, float dt, float a0, float b0, hipStream_t s) {
+                         uint32_t* status, float dt, float a0, float b0, const float* gin, hipStream_t s) {
   switch (flux) {
     case CVW_ADVECT_CONST:
-      launch_eval<P, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      launch_eval<P, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, gin, s);
       break;
     case CVW_BURGERS:
-      launch_eval<P, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      launch_eval<P, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, gin, s);
       break;
     case CVW_KPP:
-      launch_eval<P, CVW_KPP>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      launch_eval<P, CVW_KPP>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, gin, s);
       break;
     case CVW_EULER:
-      launch_eval<P, CVW_EULER>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      launch_eval<P, CVW_EULER>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, gin, s);
       break;
     default:
       set_error("flux not supported by the DG quadrilateral path (position-dependent velocity needs cell coordinates)");
@@ -606,16 +609,159 @@ static cvw_status eval_p(const cvw_mesh* m, const MethodScalars& ms, int flux, i
 
 cvw_status dgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0,
                        float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
-                       float a0, float b0, hipStream_t s) {
+                       float a0, float b0, hipStream_t s, const float* gamma_in) {
   const MethodScalars ms = make_scalars(prm);
+  if (ms.sensor_kind == CVW_SENSOR_LEARNED && !gamma_in) { set_error("learned sensor without its gamma"); return CVW_EINVAL; }
   cvw_status st;
   switch (m->degree) {
-    case 1: st = eval_p<1>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
-    case 2: st = eval_p<2>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
-    case 3: st = eval_p<3>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s); break;
+    case 1: st = eval_p<1>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, gamma_in, s); break;
+    case 2: st = eval_p<2>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, gamma_in, s); break;
+    case 3: st = eval_p<3>(m, ms, prm->flux, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, gamma_in, s); break;
     default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
   }
   if (st != CVW_OK) return st;
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// Features of the learned sensor, one thread per cell (float64):
+// 4 x 9 vertex mismatch slots h^|k| (c_i[k] - D^k s^e(x_i)) / sigma_e,
+// 9 centre slots h^|k| D^k s^e(x_c) / sigma_e, log10(sigma_e / sigma_ref),
+// the largest and the mean per-vertex mismatch 2-norm; sigma_e =
+// ||s^e||_e + 1e-12 sigma_ref (eq. snorm, collocated Gauss rule, exact).
+// Orders above p are zero.  Stored as bfloat16 [E][48].
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void dgq_feat_kernel(const float* __restrict__ u, const float* __restrict__ cand,
+                                                       const int32_t* __restrict__ cell_vtx, TensorTables tab,
+                                                       int64_t E, double hx, double hy, double he,
+                                                       double sigma_ref, uint16_t* __restrict__ feat) {
+  constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
+  constexpr KSet<P> ks = kset<P>;
+  const int64_t e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= E) return;
+  double r[NLOC];
+  {
+    const float* ue = u + e * NLOC;
+    const double r0 = ue[0];
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) r[j] = static_cast<double>(ue[j]) - r0;
+  }
+  const double sx = 2.0 / hx, sy = 2.0 / hy;
+  double sc[NK], hk[NK], wk[NK];
+#pragma unroll
+  for (int t = 0; t < NK; ++t) {
+    const int kx = ks.x[t], ky = ks.y[t];
+    sc[t] = dpow(sx, kx) * dpow(sy, ky);
+    hk[t] = dpow(he, kx + ky);
+    wk[t] = dpow(he * he, kx + ky - 1);
+  }
+  // sigma_e: semi-norm on the Gauss nodes
+  double n2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < N1; ++a) {
+    double T[N1][N1];   // T[m][j] = sum_i l_i^{(m)}(xi_a) r[i][j]
+#pragma unroll
+    for (int m = 0; m < N1; ++m)
+#pragma unroll
+      for (int j = 0; j < N1; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) s = fma(tab.Dd[m][a][i], r[i + N1 * j], s);
+        T[m][j] = s;
+      }
+#pragma unroll
+    for (int b = 0; b < N1; ++b) {
+      double pq = 0.0;
+#pragma unroll
+      for (int t = 0; t < NK; ++t) {
+        double d = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) d = fma(tab.Dd[ks.y[t]][b][j], T[ks.x[t]][j], d);
+        d *= sc[t];
+        pq = fma(wk[t] * d, d, pq);
+      }
+      n2 = fma(tab.wd[a] * tab.wd[b] * 0.25 * hx * hy, pq, n2);
+    }
+  }
+  const double sigma = sqrt(n2) + 1e-12 * sigma_ref;
+  const double inv = 1.0 / sigma;
+  float f[48];
+#pragma unroll
+  for (int t = 0; t < 48; ++t) f[t] = 0.0f;
+  double nmax = 0.0, nsum = 0.0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const bool fx = (l == 1) || (l == 2), fy = (l >= 2);
+    double Tx[N1][N1];   // Tx[m][j] = sum_i l_i^{(m)}(+-1) r[i][j]
+#pragma unroll
+    for (int m = 0; m < N1; ++m)
+#pragma unroll
+      for (int j = 0; j < N1; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) {
+          const double Lx = fx ? ((m & 1) ? -tab.Ld[m][P - i] : tab.Ld[m][P - i]) : tab.Ld[m][i];
+          s = fma(Lx, r[i + N1 * j], s);
+        }
+        Tx[m][j] = s;
+      }
+    const int64_t vtx = cell_vtx[e * 4 + l];
+    double nrm = 0.0;
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+      const int kx = ks.x[t], ky = ks.y[t];
+      double d = 0.0;
+#pragma unroll
+      for (int j = 0; j < N1; ++j) {
+        const double Ly = fy ? ((ky & 1) ? -tab.Ld[ky][P - j] : tab.Ld[ky][P - j]) : tab.Ld[ky][j];
+        d = fma(Ly, Tx[kx][j], d);
+      }
+      const double mis = hk[t] * (static_cast<double>(cand[vtx * NK + t]) - d * sc[t]) * inv;
+      f[9 * l + t] = static_cast<float>(mis);
+      nrm = fma(mis, mis, nrm);
+    }
+    nrm = sqrt(nrm);
+    nmax = fmax(nmax, nrm);
+    nsum += nrm;
+  }
+#pragma unroll
+  for (int t = 0; t < NK; ++t) {
+    const int kx = ks.x[t], ky = ks.y[t];
+    double d = 0.0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) s = fma(tab.Cd[kx][i], r[i + N1 * j], s);
+      d = fma(tab.Cd[ky][j], s, d);
+    }
+    f[36 + t] = static_cast<float>(hk[t] * d * sc[t] * inv);
+  }
+  f[45] = static_cast<float>(log10(sigma / sigma_ref));
+  f[46] = static_cast<float>(nmax);
+  f[47] = static_cast<float>(0.25 * nsum);
+  uint4* dst = reinterpret_cast<uint4*>(feat + e * 48);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    uint32_t w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      w[h] = static_cast<uint32_t>(bf16_bits(f[8 * q + 2 * h])) |
+             (static_cast<uint32_t>(bf16_bits(f[8 * q + 2 * h + 1])) << 16);
+    dst[q] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+cvw_status dgquad_features(const cvw_mesh* m, const float* u, const float* cand, double sigma_ref, uint16_t* feat,
+                           hipStream_t s) {
+  const dim3 g(static_cast<unsigned>((m->E + 255) / 256)), b(256);
+  switch (m->degree) {
+    case 1: hipLaunchKernelGGL(dgq_feat_kernel<1>, g, b, 0, s, u, cand, m->d_cell_vtx, m->tens, m->E, m->hx, m->hy, m->he, sigma_ref, feat); break;
+    case 2: hipLaunchKernelGGL(dgq_feat_kernel<2>, g, b, 0, s, u, cand, m->d_cell_vtx, m->tens, m->E, m->hx, m->hy, m->he, sigma_ref, feat); break;
+    case 3: hipLaunchKernelGGL(dgq_feat_kernel<3>, g, b, 0, s, u, cand, m->d_cell_vtx, m->tens, m->E, m->hx, m->hy, m->he, sigma_ref, feat); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 

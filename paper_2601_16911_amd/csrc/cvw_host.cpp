@@ -138,6 +138,7 @@ static void fill_tensor_tables(TensorTables& T, int p, bool lobatto) {
   for (int a = 0; a <= p; ++a) {
     T.xi[a] = static_cast<float>(xn[a]);
     T.w[a] = static_cast<float>(w[a]);
+    T.wd[a] = w[a];
   }
   // D[m][a][i] = l_i^{(m)} at the volume quadrature point a (= node a for Gauss nodes)
   for (int m = 0; m <= p; ++m)
@@ -152,6 +153,7 @@ static void fill_tensor_tables(TensorTables& T, int p, bool lobatto) {
     for (int m = 0; m <= p; ++m) {
       T.Ld[m][i] = lagrange_deriv(xn, i, m, -1.0);
       T.L[m][i] = static_cast<float>(T.Ld[m][i]);
+      T.Cd[m][i] = lagrange_deriv(xn, i, m, 0.0);
     }
   }
 }
@@ -879,6 +881,26 @@ cvw_status cvw_mesh_export(const cvw_mesh* m, int which, void* dst, size_t bytes
 // ---------------------------------------------------------------------------
 // workspace: [status 256 B][candidates n_k * Nv][stage 1][stage 2]
 // ---------------------------------------------------------------------------
+// learned-sensor network: float32 master parameters, Adam moments and the
+// device compute copies, in one allocation
+struct cvw_mlp {
+  int device = 0;
+  int64_t steps = 0;
+  void* mem = nullptr;
+  float* master = nullptr;
+  float* m1 = nullptr;
+  float* m2 = nullptr;
+  float* b1 = nullptr;
+  float* b2 = nullptr;
+  float* b3 = nullptr;
+  uint16_t* W1t = nullptr;
+  uint16_t* W2t = nullptr;
+  uint16_t* W2r = nullptr;
+  uint16_t* w3 = nullptr;
+  cvw::MlpDev dev() const { return {W1t, W2t, W2r, w3, b1, b2, b3}; }
+  cvw::MlpDevMut mut() const { return {W1t, W2t, W2r, w3, b1, b2, b3}; }
+};
+
 static size_t state_elems(const cvw_mesh* m, int nv) {
   return static_cast<size_t>(nv) * (m->space == CVW_DG ? static_cast<size_t>(m->E) * m->nloc : static_cast<size_t>(m->ndof));
 }
@@ -910,6 +932,8 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (!m || !prm) return 0;
   const size_t es = prm->dtype == CVW_F64 ? 8 : 4;
   size_t b = 256 + TOT_SCRATCH + align256(static_cast<size_t>(m->nk) * m->Nv * es) + cg_extra(m, prm, es);
+  if (prm->sensor == CVW_SENSOR_LEARNED)
+    b += align256(static_cast<size_t>(m->E) * MLP_IN * 2) + align256(static_cast<size_t>(m->E) * 4);
   if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
   return b;
 }
@@ -920,8 +944,16 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
   if (ws_bytes < cvw_workspace_bytes(m, prm, op)) { set_error("workspace too small"); return CVW_EINVAL; }
   if (reinterpret_cast<uintptr_t>(ws) % 256) { set_error("workspace must be 256-byte aligned"); return CVW_EINVAL; }
   if (prm->flux < 0 || prm->flux > CVW_EULER) { set_error("unknown flux"); return CVW_EINVAL; }
-  if (prm->sensor != CVW_SENSOR_PLAIN && prm->sensor != CVW_SENSOR_FIXED) {
-    set_error("learned sensor not available through this entry point"); return CVW_EUNSUPPORTED;
+  if (prm->sensor == CVW_SENSOR_LEARNED) {
+    if (!(m->cell == CVW_QUAD && m->space == CVW_DG)) {
+      set_error("learned sensor: DG quadrilaterals only"); return CVW_EUNSUPPORTED;
+    }
+    if (!prm->mlp || !(prm->sigma_ref > 0) || !std::isfinite(prm->sigma_ref)) {
+      set_error("learned sensor needs a network and sigma_ref > 0"); return CVW_EINVAL;
+    }
+    if (prm->mlp->device != m->device) { set_error("network and mesh on different devices"); return CVW_EINVAL; }
+  } else if (prm->sensor != CVW_SENSOR_PLAIN && prm->sensor != CVW_SENSOR_FIXED) {
+    set_error("unknown sensor kind"); return CVW_EINVAL;
   }
   if (!(prm->eps_vertex > 0) || !(prm->eps_cell > 0) || prm->r < 1 || !(prm->q_sensor >= 1) || !(prm->q_beta >= 1) ||
       !(prm->lin_w_vertex > 0) || !(prm->lin_w_vertex * m->ve < 1)) {
@@ -970,6 +1002,8 @@ struct WS {
   void* x, *r, *z, *p, *Ap;        // PCG vectors (CG)
   double* part;                    // PCG block partials, followed by its 8 scalars
   double* S;
+  uint16_t* feat;                  // learned sensor: features [E][48] and gamma [E]
+  float* glearn;
   void* st1;
   void* st2;
 };
@@ -1003,10 +1037,25 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
       p += align256((pcg_partials(m->ndof) + 8) * sizeof(double));
     }
   }
+  if (prm->sensor == CVW_SENSOR_LEARNED) {
+    w.feat = reinterpret_cast<uint16_t*>(p);
+    p += align256(static_cast<size_t>(m->E) * MLP_IN * 2);
+    w.glearn = reinterpret_cast<float*>(p);
+    p += align256(static_cast<size_t>(m->E) * 4);
+  }
   w.st1 = p;
   p += align256(state_elems(m, n_var_of(prm->flux)) * es);
   w.st2 = p;
   return w;
+}
+
+// learned sensor: features of u, then the network; gamma in the workspace
+static cvw_status learned_gamma(const cvw_mesh* m, const cvw_params* prm, const void* u, const void* cand, const WS& w,
+                                hipStream_t s) {
+  cvw_status st = dgquad_features(m, static_cast<const float*>(u), static_cast<const float*>(cand), prm->sigma_ref,
+                                  w.feat, s);
+  if (st != CVW_OK) return st;
+  return mlp_infer(prm->mlp->dev(), w.feat, m->E, w.glearn, s);
 }
 
 static cvw_status candidates_any(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand,
@@ -1034,10 +1083,11 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
   if (!u || !gamma) { set_error("null device pointer"); return CVW_EINVAL; }
   const WS w = carve(m, prm, ws);
   auto s = static_cast<hipStream_t>(stream);
-  if (prm->sensor == CVW_SENSOR_PLAIN) {
+  if (prm->sensor != CVW_SENSOR_FIXED) {
     st = candidates_any(m, prm, u, w.cand, s);
     if (st != CVW_OK) return st;
   }
+  if (prm->sensor == CVW_SENSOR_LEARNED && (st = learned_gamma(m, prm, u, w.cand, w, s)) != CVW_OK) return st;
   if (m->cell == CVW_SEG)
     return seg_eval(m, prm, MODE_SENSOR, u, w.cand, w.pg, w.rcell, nullptr, gamma, alpha, w.status, s);
   if (m->cell == CVW_TRI)
@@ -1048,7 +1098,8 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
                        static_cast<float*>(w.pg), static_cast<float*>(w.rcell), nullptr, static_cast<float*>(gamma),
                        static_cast<float*>(alpha), w.status, s);
   return dgquad_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
-                     static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s);
+                     static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s,
+                     w.glearn);
 }
 
 cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u, void* R, void* gamma_out, void* ws,
@@ -1059,10 +1110,11 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
   if (u == R) { set_error("R must not alias u"); return CVW_EINVAL; }
   const WS w = carve(m, prm, ws);
   auto s = static_cast<hipStream_t>(stream);
-  if (prm->sensor == CVW_SENSOR_PLAIN) {
+  if (prm->sensor != CVW_SENSOR_FIXED) {
     st = candidates_any(m, prm, u, w.cand, s);
     if (st != CVW_OK) return st;
   }
+  if (prm->sensor == CVW_SENSOR_LEARNED && (st = learned_gamma(m, prm, u, w.cand, w, s)) != CVW_OK) return st;
   if (m->cell == CVW_SEG)
     return seg_eval(m, prm, MODE_RESIDUAL, u, w.cand, w.pg, w.rcell, R, gamma_out, nullptr, w.status, s);
   if (m->cell == CVW_TRI)
@@ -1075,7 +1127,7 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
                        static_cast<float*>(gamma_out), nullptr, w.status, s);
   return dgquad_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
                      static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
-                     0.f, s);
+                     0.f, s, w.glearn);
 }
 
 }  // extern "C"
@@ -1119,10 +1171,15 @@ cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, cons
     return tri_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
                     static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
                     static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s);
-  if (m->cell == CVW_QUAD && m->space == CVW_DG)
+  if (m->cell == CVW_QUAD && m->space == CVW_DG) {
+    if (prm->sensor == CVW_SENSOR_LEARNED) {
+      const cvw_status st = learned_gamma(m, prm, us, cand, w, s);
+      if (st != CVW_OK) return st;
+    }
     return dgquad_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
                        static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
-                       static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s);
+                       static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s, w.glearn);
+  }
   if (prm->dtype == CVW_F64)
     return generic_stage<double>(m, prm, w, static_cast<const double*>(us), static_cast<const double*>(cand),
                                  static_cast<const double*>(un), static_cast<double*>(uo), dt, a0, b0, s);
@@ -1164,7 +1221,7 @@ cvw_status cvw_step(const cvw_mesh* m, const cvw_params* prm, void* u, double dt
       {u, w.st1, 0.0, 1.0}, {w.st1, w.st2, 0.75, 0.25}, {w.st2, u, third, two3}};
   for (int n = 0; n < n_steps; ++n)
     for (const auto& sg : stages) {
-      if (prm->sensor == CVW_SENSOR_PLAIN) {
+      if (prm->sensor != CVW_SENSOR_FIXED) {
         st = candidates_any(m, prm, sg.in, w.cand, s);
         if (st != CVW_OK) return st;
       }
@@ -1454,6 +1511,138 @@ cvw_status cvw_batch_poll_status(void* ws, size_t ws_bytes, uint32_t* flags, voi
   CVW_HIP(hipStreamSynchronize(s));
   *flags = h;
   return h ? CVW_ENUMERIC : CVW_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned-sensor network
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t MLP_BF16 = static_cast<size_t>(MLP_IN) * MLP_HID + 2 * MLP_HID * MLP_HID + MLP_HID;
+
+cvw_status mlp_refresh(cvw_mlp* m, hipStream_t s) {
+  // compute copies from the master weights (no gradient, no update)
+  return mlp_update(nullptr, 0, m->master, m->m1, m->m2, 0.0f, 0.9, 0.999, 1e-8f, 1.0, 1.0, nullptr, m->mut(), s);
+}
+
+bool finite_params(const float* p) {
+  for (int i = 0; i < MLP_NPARAM; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+cvw_status cvw_mlp_create(const float* params, cvw_mlp** out) {
+  if (!params || !out) { set_error("null argument"); return CVW_EINVAL; }
+  *out = nullptr;
+  if (!finite_params(params)) { set_error("non-finite network parameters"); return CVW_EINVAL; }
+  auto* m = new cvw_mlp();
+  (void)hipGetDevice(&m->device);
+  const size_t nf = 3 * static_cast<size_t>(MLP_NPARAM) + 2 * MLP_HID + 1;
+  const size_t bytes = align256(nf * 4) + align256(MLP_BF16 * 2);
+  if (hipMalloc(&m->mem, bytes) != hipSuccess) { delete m; set_error("hipMalloc failed"); return CVW_ENOMEM; }
+  float* f = static_cast<float*>(m->mem);
+  m->master = f;
+  m->m1 = f + MLP_NPARAM;
+  m->m2 = f + 2 * MLP_NPARAM;
+  m->b1 = f + 3 * MLP_NPARAM;
+  m->b2 = m->b1 + MLP_HID;
+  m->b3 = m->b2 + MLP_HID;
+  uint16_t* h = reinterpret_cast<uint16_t*>(static_cast<char*>(m->mem) + align256(nf * 4));
+  m->W1t = h;
+  m->W2t = m->W1t + MLP_IN * MLP_HID;
+  m->W2r = m->W2t + MLP_HID * MLP_HID;
+  m->w3 = m->W2r + MLP_HID * MLP_HID;
+  if (hipMemset(m->mem, 0, bytes) != hipSuccess ||
+      hipMemcpy(m->master, params, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      mlp_refresh(m, nullptr) != CVW_OK || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(m->mem);
+    delete m;
+    set_error("network upload failed");
+    return CVW_EDEVICE;
+  }
+  *out = m;
+  return CVW_OK;
+}
+
+void cvw_mlp_destroy(cvw_mlp* mlp) {
+  if (!mlp) return;
+  (void)hipFree(mlp->mem);
+  delete mlp;
+}
+
+cvw_status cvw_mlp_get_params(const cvw_mlp* mlp, float* params) {
+  if (!mlp || !params) { set_error("null argument"); return CVW_EINVAL; }
+  CVW_HIP(hipDeviceSynchronize());
+  CVW_HIP(hipMemcpy(params, mlp->master, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+  return CVW_OK;
+}
+
+cvw_status cvw_mlp_set_params(cvw_mlp* mlp, const float* params) {
+  if (!mlp || !params) { set_error("null argument"); return CVW_EINVAL; }
+  if (!finite_params(params)) { set_error("non-finite network parameters"); return CVW_EINVAL; }
+  CVW_HIP(hipDeviceSynchronize());
+  CVW_HIP(hipMemcpy(mlp->master, params, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+  CVW_HIP(hipMemset(mlp->m1, 0, 2 * MLP_NPARAM * sizeof(float)));
+  mlp->steps = 0;
+  const cvw_status st = mlp_refresh(mlp, nullptr);
+  if (st != CVW_OK) return st;
+  CVW_HIP(hipDeviceSynchronize());
+  return CVW_OK;
+}
+
+cvw_status cvw_mlp_features(const cvw_mesh* mesh, const cvw_params* prm, const void* u, const void* cand,
+                            void* feat, void* stream) {
+  if (!mesh || !prm || !u || !cand || !feat) { set_error("null argument"); return CVW_EINVAL; }
+  if (mesh->cell != CVW_QUAD || mesh->space != CVW_DG || !mesh->uniform || mesh->degree > MAXP) {
+    set_error("features: DG on congruent axis-aligned quadrilaterals, p <= 3"); return CVW_EUNSUPPORTED;
+  }
+  if (prm->dtype != CVW_F32) { set_error("features: float32 state"); return CVW_EUNSUPPORTED; }
+  if (!(prm->sigma_ref > 0) || !std::isfinite(prm->sigma_ref)) { set_error("sigma_ref must be > 0"); return CVW_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(feat) % 16) { set_error("features must be 16-byte aligned"); return CVW_EINVAL; }
+  return dgquad_features(mesh, static_cast<const float*>(u), static_cast<const float*>(cand), prm->sigma_ref,
+                         static_cast<uint16_t*>(feat), static_cast<hipStream_t>(stream));
+}
+
+cvw_status cvw_mlp_infer(const cvw_mlp* mlp, const void* feat, int64_t n, void* gamma, void* stream) {
+  if (!mlp || n < 0) { set_error("bad argument"); return CVW_EINVAL; }
+  if (n == 0) return CVW_OK;
+  if (!feat || !gamma) { set_error("null device pointer"); return CVW_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(feat) % 16) { set_error("features must be 16-byte aligned"); return CVW_EINVAL; }
+  return mlp_infer(mlp->dev(), static_cast<const uint16_t*>(feat), n, static_cast<float*>(gamma),
+                   static_cast<hipStream_t>(stream));
+}
+
+size_t cvw_mlp_train_workspace_bytes(int batch) {
+  if (batch <= 0) return 0;
+  return align256(static_cast<size_t>((batch + 31) / 32) * MLP_NPARAM * sizeof(float));
+}
+
+cvw_status cvw_mlp_train_step(cvw_mlp* mlp, const void* feat, const void* target, const void* idx, int batch,
+                              float lr, void* grad_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!mlp || !feat || !target || !idx || !ws) { set_error("null argument"); return CVW_EINVAL; }
+  if (batch < 1 || batch > 65536) { set_error("batch must be in [1, 65536]"); return CVW_EINVAL; }
+  if (!(lr >= 0) || !std::isfinite(lr)) { set_error("bad learning rate"); return CVW_EINVAL; }
+  if (ws_bytes < cvw_mlp_train_workspace_bytes(batch)) { set_error("workspace too small"); return CVW_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(feat) % 16) { set_error("features must be 16-byte aligned"); return CVW_EINVAL; }
+  auto s = static_cast<hipStream_t>(stream);
+  float* part = static_cast<float*>(ws);
+  cvw_status st = mlp_train(mlp->dev(), static_cast<const uint16_t*>(feat), static_cast<const float*>(target),
+                            static_cast<const int32_t*>(idx), batch, part, s);
+  if (st != CVW_OK) return st;
+  const double b1 = 0.9, b2 = 0.999;
+  const int64_t t = lr > 0 ? mlp->steps + 1 : mlp->steps;
+  const double bc1 = lr > 0 ? 1.0 - std::pow(b1, static_cast<double>(t)) : 1.0;
+  const double bc2 = lr > 0 ? 1.0 - std::pow(b2, static_cast<double>(t)) : 1.0;
+  st = mlp_update(part, (batch + 31) / 32, mlp->master, mlp->m1, mlp->m2, lr, b1, b2, 1e-8f, bc1, bc2,
+                  static_cast<float*>(grad_out), mlp->mut(), s);
+  if (st == CVW_OK) mlp->steps = t;
+  return st;
 }
 
 }  // extern "C"

@@ -31,6 +31,8 @@ struct TensorTables {
   // smooth data cancel: table rounding must not multiply the full data)
   double Dd[MAXP + 1][MAXP + 1][MAXP + 1];
   double Ld[MAXP + 1][MAXP + 1];
+  double Cd[MAXP + 1][MAXP + 1];      // Cd[m][i] = l_i^{(m)}(0) (cell centre)
+  double wd[MAXP + 1];                // float64 copy of w
 };
 
 // Per-lane table record of the DG quadrilateral cell kernel: one 16-lane row
@@ -104,6 +106,34 @@ struct MethodScalars {
   float fixed_gamma;
   // float64 copies for the float64 sensor paths
   double eps_vd, eps_cd, lin_wd, c_gammad, lam_gd, fixed_gammad, fpd[4];
+};
+
+// Learned sensor network 48 -> 64 -> 64 -> 1.  Packed float32 parameters:
+// W1 [48][64] (input, hidden), b1 [64], W2 [64][64] (hidden 1, hidden 2),
+// b2 [64], w3 [64], b3.
+constexpr int MLP_IN = 48, MLP_HID = 64;
+constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = MLP_IN * MLP_HID, MLP_OFF_W2 = MLP_OFF_B1 + MLP_HID;
+constexpr int MLP_OFF_B2 = MLP_OFF_W2 + MLP_HID * MLP_HID, MLP_OFF_W3 = MLP_OFF_B2 + MLP_HID;
+constexpr int MLP_OFF_B3 = MLP_OFF_W3 + MLP_HID, MLP_NPARAM = MLP_OFF_B3 + 1;
+// device compute copies: bfloat16 W1^T [64][48], W2^T [64][64], W2 [64][64],
+// w3 [64]; float32 biases
+struct MlpDev {
+  const uint16_t* W1t;
+  const uint16_t* W2t;
+  const uint16_t* W2r;
+  const uint16_t* w3;
+  const float* b1;
+  const float* b2;
+  const float* b3;
+};
+struct MlpDevMut {
+  uint16_t* W1t;
+  uint16_t* W2t;
+  uint16_t* W2r;
+  uint16_t* w3;
+  float* b1;
+  float* b2;
+  float* b3;
 };
 
 // Per-instance descriptor of a batch of independent DG quadrilateral meshes
@@ -182,7 +212,10 @@ cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const flo
                              hipStream_t s);
 cvw_status dgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0,
                        float* out, float* gamma, float* alpha, const float* cand, uint32_t* status,
-                       float dt, float a0, float b0, hipStream_t s);
+                       float dt, float a0, float b0, hipStream_t s, const float* gamma_in = nullptr);
+// learned-sensor features of every cell, bfloat16 [E][48] (cvw_dgquad.hip)
+cvw_status dgquad_features(const cvw_mesh* m, const float* u, const float* cand, double sigma_ref, uint16_t* feat,
+                           hipStream_t s);
 // kernel launchers (cvw_cgquad.hip)
 cvw_status cgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
 cvw_status cgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* cand,
@@ -200,6 +233,13 @@ cvw_status batch_vertex_pass(int P, const BatchInst* inst, const int2* items, in
                              int stage, int grid, hipStream_t s);
 cvw_status batch_eval_pass(int P, int flux, const BatchInst* inst, const int2* items, int n_items,
                            const TensorTables* tabs, const LaneRec* lanes, int stage, int grid, hipStream_t s);
+// learned-sensor network (cvw_mlp.hip)
+cvw_status mlp_infer(const MlpDev& W, const uint16_t* feat, int64_t n, float* gamma, hipStream_t s);
+cvw_status mlp_train(const MlpDev& W, const uint16_t* feat, const float* target, const int32_t* idx, int batch,
+                     float* part, hipStream_t s);
+cvw_status mlp_update(const float* part, int nblk, float* master, float* m1, float* m2, float lr, double beta1,
+                      double beta2, float eps, double bc1, double bc2, float* grad_out, const MlpDevMut& W,
+                      hipStream_t s);
 // kernel launchers (cvw_tri.hip)
 cvw_status tri_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
 cvw_status tri_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,

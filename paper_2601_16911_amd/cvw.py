@@ -25,7 +25,9 @@ EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXP
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
            "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_residual",
            "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_batch_build", "cvw_batch_destroy",
-           "cvw_batch_workspace_bytes", "cvw_batch_step", "cvw_batch_set_grid", "cvw_batch_poll_status"]
+           "cvw_batch_workspace_bytes", "cvw_batch_step", "cvw_batch_set_grid", "cvw_batch_poll_status",
+           "cvw_mlp_create", "cvw_mlp_destroy", "cvw_mlp_get_params", "cvw_mlp_set_params", "cvw_mlp_features",
+           "cvw_mlp_infer", "cvw_mlp_train_workspace_bytes", "cvw_mlp_train_step"]
 
 
 class CvwError(RuntimeError):
@@ -45,7 +47,8 @@ class ParamsC(C.Structure):
                 ("eps_vertex", C.c_double), ("eps_cell", C.c_double), ("r", C.c_int32), ("sc_on", C.c_int32),
                 ("q_sensor", C.c_double), ("q_beta", C.c_double), ("lin_w_vertex", C.c_double),
                 ("c_gamma", C.c_double), ("lambda_global", C.c_double), ("sensor", C.c_int32),
-                ("pad0", C.c_int32), ("fixed_gamma", C.c_double)]
+                ("pad0", C.c_int32), ("fixed_gamma", C.c_double), ("sigma_ref", C.c_double),
+                ("mlp", C.c_void_p)]
 
 
 class BatchInstanceC(C.Structure):
@@ -96,9 +99,21 @@ def load():
     lib.cvw_batch_step.argtypes = [vp, C.c_int, C.c_int, vp, sz, vp]
     lib.cvw_batch_set_grid.argtypes = [vp, C.c_int]
     lib.cvw_batch_poll_status.argtypes = [vp, sz, C.POINTER(C.c_uint32), vp]
+    fp = C.POINTER(C.c_float)
+    lib.cvw_mlp_create.argtypes = [fp, C.POINTER(vp)]
+    lib.cvw_mlp_destroy.argtypes = [vp]
+    lib.cvw_mlp_destroy.restype = None
+    lib.cvw_mlp_get_params.argtypes = [vp, fp]
+    lib.cvw_mlp_set_params.argtypes = [vp, fp]
+    lib.cvw_mlp_features.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp]
+    lib.cvw_mlp_infer.argtypes = [vp, vp, C.c_int64, vp, vp]
+    lib.cvw_mlp_train_workspace_bytes.argtypes = [C.c_int]
+    lib.cvw_mlp_train_workspace_bytes.restype = sz
+    lib.cvw_mlp_train_step.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, vp, vp, sz, vp]
     for name in SYMBOLS:
         if name not in ("cvw_abi_version", "cvw_last_error", "cvw_mesh_destroy", "cvw_workspace_bytes",
-                        "cvw_batch_destroy", "cvw_batch_workspace_bytes"):
+                        "cvw_batch_destroy", "cvw_batch_workspace_bytes", "cvw_mlp_destroy",
+                        "cvw_mlp_train_workspace_bytes"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -109,9 +124,12 @@ def _check(status):
         raise CvwError(status, load().cvw_last_error().decode())
 
 
-def make_params(prm, dtype: int = F32) -> ParamsC:
-    """Marshal any object with the method-parameter attributes into the C struct."""
+def make_params(prm, dtype: int = F32, mlp=None, sigma_ref: float = 1.0) -> ParamsC:
+    """Marshal any object with the method-parameter attributes into the C struct
+    (mlp: a Mlp for the learned sensor, sigma_ref its reference scale)."""
     p = ParamsC()
+    p.sigma_ref = float(sigma_ref)
+    p.mlp = mlp.handle if mlp is not None else None
     p.dtype = dtype
     p.flux = int(prm.flux)
     fp = list(prm.flux_param) + [0.0] * 4
@@ -322,3 +340,101 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# learned sensor
+# ---------------------------------------------------------------------------
+MLP_IN, MLP_HID = 48, 64
+MLP_NPARAM = MLP_IN * MLP_HID + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_HID + 1
+LEARNED = 1
+
+
+def pack_params(P) -> np.ndarray:
+    """Packed float32 parameter vector from a dict W1 [48,64], b1, W2 [64,64], b2, w3, b3."""
+    parts = [np.asarray(P[k], np.float64).reshape(-1) for k in ("W1", "b1", "W2", "b2", "w3", "b3")]
+    v = np.concatenate(parts).astype(np.float32)
+    assert v.size == MLP_NPARAM
+    return v
+
+
+def unpack_params(v) -> dict:
+    v = np.asarray(v, np.float64)
+    o, out = 0, {}
+    for k, shape in (("W1", (MLP_IN, MLP_HID)), ("b1", (MLP_HID,)), ("W2", (MLP_HID, MLP_HID)),
+                     ("b2", (MLP_HID,)), ("w3", (MLP_HID,)), ("b3", (1,))):
+        n = int(np.prod(shape))
+        out[k] = v[o:o + n].reshape(shape)
+        o += n
+    return out
+
+
+class Mlp:
+    """The learned-sensor network on the current device (cvw_mlp_*)."""
+
+    def __init__(self, params):
+        v = np.ascontiguousarray(params, np.float32)
+        if v.size != MLP_NPARAM:
+            raise ValueError(f"{v.size} parameters, {MLP_NPARAM} expected")
+        h = C.c_void_p()
+        _check(load().cvw_mlp_create(v.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(MLP_NPARAM, np.float32)
+        _check(load().cvw_mlp_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def set_params(self, params):
+        v = np.ascontiguousarray(params, np.float32)
+        _check(load().cvw_mlp_set_params(self._h, v.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def infer(self, feat, gamma, stream=None):
+        import torch
+        if feat.dtype != torch.int16 or gamma.dtype != torch.float32 or not feat.is_cuda or not gamma.is_cuda:
+            raise TypeError("feat: int16 (bfloat16 bits) device tensor [n, 48]; gamma: float32 device tensor")
+        n = feat.numel() // MLP_IN
+        if gamma.numel() < n or not feat.is_contiguous():
+            raise ValueError("gamma too short or feat not contiguous")
+        _check(load().cvw_mlp_infer(self._h, _ptr(feat), n, _ptr(gamma), _stream(stream)))
+
+    def train_step(self, feat, target, idx, lr: float, ws, grad_out=None, stream=None):
+        import torch
+        if idx.dtype != torch.int32 or target.dtype != torch.float32 or feat.dtype != torch.int16:
+            raise TypeError("feat int16 (bfloat16 bits), target float32, idx int32")
+        n = feat.numel() // MLP_IN
+        if target.numel() < n:
+            raise ValueError("target shorter than the feature rows")
+        if grad_out is not None and (grad_out.dtype != torch.float32 or grad_out.numel() < MLP_NPARAM):
+            raise ValueError("grad_out: float32 [7361]")
+        _check(load().cvw_mlp_train_step(self._h, _ptr(feat), _ptr(target), _ptr(idx), idx.numel(), float(lr),
+                                         _ptr(grad_out), _ptr(ws), ws.numel(), _stream(stream)))
+
+    @staticmethod
+    def train_workspace(batch: int, device="cuda"):
+        import torch
+        return torch.zeros(int(load().cvw_mlp_train_workspace_bytes(int(batch))), dtype=torch.uint8, device=device)
+
+    def close(self):
+        if self._h:
+            load().cvw_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlp_features(mesh, prm, u, cand, feat, stream=None):
+    """Learned-sensor features of every cell into feat (int16 device tensor [n_cells, 48] of bfloat16 bits)."""
+    import torch
+    if feat.dtype != torch.int16 or feat.numel() < mesh.info["n_cells"] * MLP_IN or not feat.is_contiguous():
+        raise ValueError("feat: contiguous int16 device tensor [n_cells, 48]")
+    _check(load().cvw_mlp_features(mesh.handle, C.byref(prm), _fp(u, prm, _state_len(mesh, prm), "u"),
+                                   _fp(cand, prm, _cand_len(mesh), "cand"), _ptr(feat), _stream(stream)))
