@@ -12,13 +12,16 @@ namespace cvw {
 // DPP cross-lane moves.  A cell of a tensor-product element occupies one DPP
 // row of 16 lanes, node (a, b) on lane a + 4 b of the row.
 // ---------------------------------------------------------------------------
+// Every pattern used here (quad_perm, row_ror) reads a lane of the same row,
+// so no source is out of range: the moves need no old value and can be folded
+// into the consuming VOP2 instruction by the compiler.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ int dppi(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ double dppd(double x) {
@@ -80,6 +83,9 @@ __device__ __forceinline__ float row_max(float x) {
 // Fluxes (single precision).  fp = flux parameters, lam_g = global wave-speed
 // bound (0 = local).
 // ---------------------------------------------------------------------------
+// hardware reciprocal (1 ulp): the hot kernels divide through it
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <int FLUX> struct NVar { static constexpr int value = 1; };
 template <> struct NVar<CVW_EULER> { static constexpr int value = 4; };
 
@@ -102,7 +108,7 @@ __device__ __forceinline__ void phys_flux(const MethodScalars& ms, const float* 
     fy[0] = cosf(u[0]);
   } else {
     const float g = ms.fp[0];
-    const float rho = u[0], inv = 1.0f / rho;
+    const float rho = u[0], inv = frcp(rho);
     const float vx = u[1] * inv, vy = u[2] * inv;
     const float p = (g - 1.0f) * (u[3] - 0.5f * rho * (vx * vx + vy * vy));
     fx[0] = u[1];
@@ -130,7 +136,7 @@ __device__ __forceinline__ float wave_speed(const MethodScalars& ms, const float
     return 1.0f;
   } else {
     const float g = ms.fp[0];
-    const float rho = u[0], inv = 1.0f / rho;
+    const float rho = u[0], inv = frcp(rho);
     const float vx = u[1] * inv, vy = u[2] * inv;
     const float p = (g - 1.0f) * (u[3] - 0.5f * rho * (vx * vx + vy * vy));
     return sqrtf(vx * vx + vy * vy) + sqrtf(fmaxf(g * p * inv, 0.0f));
@@ -142,34 +148,38 @@ __device__ __forceinline__ float wave_speed(const MethodScalars& ms, const float
 template <int FLUX>
 __device__ __forceinline__ void num_flux(const MethodScalars& ms, const float* um, const float* up, float nx,
                                          float ny, float x, float y, float* fs) {
-  constexpr int NV = NVar<FLUX>::value;
-  float fxm[NV], fym[NV], fxp[NV], fyp[NV];
-  phys_flux<FLUX>(ms, um, x, y, fxm, fym);
-  phys_flux<FLUX>(ms, up, x, y, fxp, fyp);
   if constexpr (FLUX == CVW_EULER) {
+    // velocities, pressure and sound speed once per state
     const float g = ms.fp[0];
-    auto vnc = [&](const float* u, float& vn, float& c) {
-      const float inv = 1.0f / u[0];
-      const float vx = u[1] * inv, vy = u[2] * inv;
-      const float p = (g - 1.0f) * (u[3] - 0.5f * u[0] * (vx * vx + vy * vy));
-      vn = vx * nx + vy * ny;
-      c = sqrtf(fmaxf(g * p * inv, 0.0f));
-    };
-    float vm, cm, vp, cp;
-    vnc(um, vm, cm);
-    vnc(up, vp, cp);
+    const float im = frcp(um[0]), ip = frcp(up[0]);
+    const float vxm = um[1] * im, vym = um[2] * im, vxp = up[1] * ip, vyp = up[2] * ip;
+    const float pm = (g - 1.0f) * (um[3] - 0.5f * um[0] * (vxm * vxm + vym * vym));
+    const float pp = (g - 1.0f) * (up[3] - 0.5f * up[0] * (vxp * vxp + vyp * vyp));
+    const float vm = vxm * nx + vym * ny, vp = vxp * nx + vyp * ny;
+    const float cm = sqrtf(fmaxf(g * pm * im, 0.0f)), cp = sqrtf(fmaxf(g * pp * ip, 0.0f));
     const float SL = fminf(vm - cm, vp - cp);
     const float SR = fmaxf(vm + cm, vp + cp);
+    // normal fluxes F.n of both states
+    const float mnm = um[0] * vm, mnp = up[0] * vp;
+    float Fm[4], Fp[4];
+    Fm[0] = mnm;
+    Fm[1] = um[1] * vm + pm * nx;
+    Fm[2] = um[2] * vm + pm * ny;
+    Fm[3] = (um[3] + pm) * vm;
+    Fp[0] = mnp;
+    Fp[1] = up[1] * vp + pp * nx;
+    Fp[2] = up[2] * vp + pp * ny;
+    Fp[3] = (up[3] + pp) * vp;
+    const float inv = frcp(SR - SL);
+#pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const float Fm = fxm[v] * nx + fym[v] * ny;
-      const float Fp = fxp[v] * nx + fyp[v] * ny;
-      float f;
-      if (SL >= 0.0f) f = Fm;
-      else if (SR <= 0.0f) f = Fp;
-      else f = (SR * Fm - SL * Fp + SL * SR * (up[v] - um[v])) / (SR - SL);
-      fs[v] = f;
+      const float mid = (SR * Fm[v] - SL * Fp[v] + SL * SR * (up[v] - um[v])) * inv;
+      fs[v] = (SL >= 0.0f) ? Fm[v] : ((SR <= 0.0f) ? Fp[v] : mid);
     }
   } else {
+    float fxm[1], fym[1], fxp[1], fyp[1];
+    phys_flux<FLUX>(ms, um, x, y, fxm, fym);
+    phys_flux<FLUX>(ms, up, x, y, fxp, fyp);
     float lam;
     if (ms.lam_g > 0.0f) {
       lam = ms.lam_g;
@@ -191,7 +201,7 @@ __device__ __forceinline__ void num_flux(const MethodScalars& ms, const float* u
 template <int FLUX>
 __device__ __forceinline__ bool state_admissible(const MethodScalars& ms, const float* u) {
   if constexpr (FLUX == CVW_EULER) {
-    const float inv = 1.0f / u[0];
+    const float inv = frcp(u[0]);
     const float p = (ms.fp[0] - 1.0f) * (u[3] - 0.5f * (u[1] * u[1] + u[2] * u[2]) * inv);
     return u[0] > 0.0f && p > 0.0f;
   } else {

@@ -312,8 +312,9 @@ __device__ __forceinline__ void dgq_eval_body(
       py[0] = 1.0f;
 #pragma unroll
       for (int n = 1; n < N1; ++n) {
-        px[n] = px[n - 1] * dx / static_cast<float>(n);
-        py[n] = py[n - 1] * dy / static_cast<float>(n);
+        constexpr float inv_n[4] = {1.0f, 1.0f, 0.5f, 1.0f / 3.0f};
+        px[n] = px[n - 1] * dx * inv_n[n];
+        py[n] = py[n - 1] * dy * inv_n[n];
       }
       float bp = 0.0f;
 #pragma unroll
@@ -341,14 +342,14 @@ __device__ __forceinline__ void dgq_eval_body(
       float w;
       if (ms.fast_exp) {
         const float den = ms.eps_c + beta[l];
-        w = lin / (den * den);
+        w = lin * frcp(den * den);
       } else {
         w = lin * powf(ms.eps_c + powf(beta[l], ms.q_beta), -ms.r);
       }
       om[l] = w;
       osum += w;
     }
-    const float oinv = 1.0f / osum;
+    const float oinv = frcp(osum);
     float d2p = 0.0f;
 #pragma unroll
     for (int t = 0; t < NK; ++t) {
@@ -359,7 +360,7 @@ __device__ __forceinline__ void dgq_eval_body(
     }
     const float d2 = row_sum(Wq * d2p);
     if (n2 > 0.0f) {
-      const float mr = fminf(1.0f, sqrtf(d2 / n2));
+      const float mr = fminf(1.0f, sqrtf(d2 / n2));      // n2 may be subnormal: IEEE division
       gam = 1.0f - (ms.fast_exp ? mr : powf(mr, ms.q_sensor));
     } else {
       gam = 1.0f;
@@ -383,7 +384,7 @@ __device__ __forceinline__ void dgq_eval_body(
   const float S = row_sum(Wq * fq);
   const float T = row_sum(Wq * atil * fq);
   const bool sc_active = ms.sc_on && (static_cast<double>(gam) < ms.c_gammad) && (S > 0.0f) && (T > 0.0f);
-  const float alpha = sc_active ? atil * (S / T) : 1.0f;
+  const float alpha = sc_active ? atil * (S / T) : 1.0f;      // T may be subnormal: IEEE division
 
   if (mode == MODE_SENSOR) {
     if (q == 0) gamma_out[e] = gam;
@@ -503,6 +504,7 @@ __device__ __forceinline__ void dgq_eval_body(
   }
 
   // ---- output -----------------------------------------------------------------
+  const float invWq = nd ? frcp(Wq) : 0.0f;
   bool nonfinite = false, inadmissible = false;
   if (nd) {
     inadmissible = !state_admissible<FLUX>(ms, uv);
@@ -513,7 +515,7 @@ __device__ __forceinline__ void dgq_eval_body(
       if (mode == MODE_RESIDUAL) {
         val = r[v];
       } else {
-        const float Lv = -r[v] / Wq;
+        const float Lv = -r[v] * invWq;
         const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
         val = base + b0 * (uv[v] + dt * Lv);
       }
