@@ -398,6 +398,9 @@ __device__ __forceinline__ void dgq_eval_body(
   float fx[NV], fy[NV];
   phys_flux<FLUX>(ms, uv, 0.0f, 0.0f, fx, fy);
   float r[NV];
+  // face traces of the own node values.  P < 3: all four sides; P = 3: only
+  // the two each lane can need (its own x side; the S side in rows 0, 1 and
+  // the N side in rows 2, 3), see the interface terms
   float tW[NV], tE[NV], tS[NV], tN[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -411,23 +414,40 @@ __device__ __forceinline__ void dgq_eval_body(
     colv[1] = rrot<1>(uvv);
     colv[2] = rrot<2>(uvv);
     colv[3] = rrot<3>(uvv);
-    float gx = 0.0f, gy = 0.0f, sW = 0.0f, sE = 0.0f, sS = 0.0f, sN = 0.0f;
+    float gx = 0.0f, gy = 0.0f;
+    if constexpr (P == 3) {
+      float sXs = 0.0f, sYs = 0.0f;
 #pragma unroll
-    for (int i = 0; i <= P; ++i) {
-      gx = fmaf(L.CX1[i], rowv[i], gx);
-      sW = fmaf(tab.B[0][i], rowv[i], sW);
-      sE = fmaf(tab.B[1][i], rowv[i], sE);
-    }
+      for (int i = 0; i <= P; ++i) {
+        gx = fmaf(L.CX1[i], rowv[i], gx);
+        sXs = fmaf(a == 0 ? tab.B[0][i] : tab.B[1][i], rowv[i], sXs);
+      }
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      gy = fmaf(L.CY1[s2], colv[s2], gy);
-      sS = fmaf(L.BY0[s2], colv[s2], sS);
-      sN = fmaf(L.BY1[s2], colv[s2], sN);
+      for (int s2 = 0; s2 < 4; ++s2) {
+        gy = fmaf(L.CY1[s2], colv[s2], gy);
+        sYs = fmaf(b <= 1 ? L.BY0[s2] : L.BY1[s2], colv[s2], sYs);
+      }
+      tW[v] = sXs;                // x-side trace (W on a = 0, E otherwise)
+      tS[v] = sYs;                // y-side trace (S in rows 0, 1; N in rows 2, 3)
+    } else {
+      float sW = 0.0f, sE = 0.0f, sS = 0.0f, sN = 0.0f;
+#pragma unroll
+      for (int i = 0; i <= P; ++i) {
+        gx = fmaf(L.CX1[i], rowv[i], gx);
+        sW = fmaf(tab.B[0][i], rowv[i], sW);
+        sE = fmaf(tab.B[1][i], rowv[i], sE);
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        gy = fmaf(L.CY1[s2], colv[s2], gy);
+        sS = fmaf(L.BY0[s2], colv[s2], sS);
+        sN = fmaf(L.BY1[s2], colv[s2], sN);
+      }
+      tW[v] = sW;
+      tE[v] = sE;
+      tS[v] = sS;
+      tN[v] = sN;
     }
-    tW[v] = sW;
-    tE[v] = sE;
-    tS[v] = sS;
-    tN[v] = sN;
     const float WFx = Wq * (coef * sx * gx - fx[v]);
     const float WFy = Wq * (coef * sy * gy - fy[v]);
     float acc = 0.0f;
@@ -444,63 +464,114 @@ __device__ __forceinline__ void dgq_eval_body(
   }
 
   // ---- interface terms -------------------------------------------------------
-  float fW[NV], fE[NV], fS[NV], fN[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) fW[v] = fE[v] = fS[v] = fN[v] = 0.0f;
   const int64_t stride = E * NLOC;
-  if (nd && (a == 0 || a == P)) {
-    const bool west = (a == 0);
-    const int64_t en = nbr[e * 4 + (west ? 3 : 1)];
-    float up[NV];
+  if constexpr (P == 3) {
+    // One face quadrature point per lane (4 faces x 4 points = 16 lanes):
+    // x-faces on the columns a = 0 (W) and a = 3 (E), point b; y-faces on the
+    // rows b = 0 (S) and b = 3 (N) for the columns 1, 2; the S / N points of
+    // the corner columns 0 and 3 go to the inner lanes (1,1), (2,1) / (1,2), (2,2).
+    const bool xf = (a == 0 || a == 3);
+    const bool inner = !xf && (b == 1 || b == 2);
+    const bool south = inner ? (b == 1) : (b == 0);
+    const int col = inner ? (a == 1 ? 0 : 3) : a;
+    const int slot = xf ? (a == 0 ? 3 : 1) : (south ? 0 : 2);       // neighbour: S 0, E 1, N 2, W 3
+    const int64_t en = nbr[e * 4 + slot];
+    const bool far_plus = (slot == 3 || slot == 0);                 // W / S neighbour: its +1 side
+    const int base = xf ? N1 * b : col, step = xf ? 1 : N1;
+    float um[NV], up[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const float* un = u + v * stride + en * NLOC + N1 * b;
+      // the inner lanes take the corner columns' y-side traces from the lanes
+      // a = 0 / 3 of their row (rows 1 / 2 hold S / N traces)
+      const float q0 = qbcast<0>(tS[v]), q3 = qbcast<3>(tS[v]);
+      um[v] = xf ? tW[v] : (inner ? (a == 1 ? q0 : q3) : tS[v]);
+      const float* un = u + v * stride + en * NLOC + base;
       float s2 = 0.0f;
 #pragma unroll
-      for (int ii = 0; ii < N1; ++ii) s2 = fmaf(west ? tab.B[1][ii] : tab.B[0][ii], un[ii], s2);
+      for (int ii = 0; ii < N1; ++ii) s2 = fmaf(far_plus ? tab.B[1][ii] : tab.B[0][ii], un[step * ii], s2);
       up[v] = s2;
     }
+    const float nx = xf ? (a == 0 ? -1.0f : 1.0f) : 0.0f, ny = xf ? 0.0f : (south ? -1.0f : 1.0f);
     float fs[NV];
-    num_flux<FLUX>(ms, west ? tW : tE, up, west ? -1.0f : 1.0f, 0.0f, 0.0f, 0.0f, fs);
+    num_flux<FLUX>(ms, um, up, nx, ny, 0.0f, 0.0f, fs);
+    const float wpt = xf ? wb * 0.5f * hy : (inner ? tab.w[0] : wa) * 0.5f * hx;   // Gauss weights are symmetric
+    // distribution: W / E along the own row from the lanes a = 0 / 3; S / N of
+    // the columns 1, 2 from the rows 0 / 3, of the corner columns from the rows
+    // 1 / 2 after moving the inner lanes' values there (quad permutation 1,1,2,2)
+    const bool ccol = (a == 0 || a == 3);
+    const int shS = (b - (ccol ? 1 : 0)) & 3, shN = (b - (ccol ? 2 : 3)) & 3;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      if (west) fW[v] = wb * 0.5f * hy * fs[v];
-      else fE[v] = wb * 0.5f * hy * fs[v];
+      const float fl = wpt * fs[v];
+      r[v] = fmaf(L.misc[0], qbcast<0>(fl), r[v]);
+      r[v] = fmaf(L.misc[1], qbcast<3>(fl), r[v]);
+      const float mv = dpp<(1 | (1 << 2) | (2 << 4) | (2 << 6))>(fl);
+      const float ys = ccol ? mv : fl;
+      const float y1 = rrot<1>(ys), y2 = rrot<2>(ys), y3 = rrot<3>(ys);
+      const float fS0 = (shS == 0) ? ys : (shS == 1) ? y1 : (shS == 2) ? y2 : y3;
+      const float fNP = (shN == 0) ? ys : (shN == 1) ? y1 : (shN == 2) ? y2 : y3;
+      r[v] = fmaf(L.misc[2], fS0, r[v]);
+      r[v] = fmaf(L.misc[3], fNP, r[v]);
     }
-  }
-  if (nd && (b == 0 || b == P)) {
-    const bool south = (b == 0);
-    const int64_t en = nbr[e * 4 + (south ? 0 : 2)];
-    float up[NV];
+  } else {
+    float fW[NV], fE[NV], fS[NV], fN[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fW[v] = fE[v] = fS[v] = fN[v] = 0.0f;
+    if (nd && (a == 0 || a == P)) {
+      const bool west = (a == 0);
+      const int64_t en = nbr[e * 4 + (west ? 3 : 1)];
+      float up[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const float* un = u + v * stride + en * NLOC + N1 * b;
+        float s2 = 0.0f;
+#pragma unroll
+        for (int ii = 0; ii < N1; ++ii) s2 = fmaf(west ? tab.B[1][ii] : tab.B[0][ii], un[ii], s2);
+        up[v] = s2;
+      }
+      float fs[NV];
+      num_flux<FLUX>(ms, west ? tW : tE, up, west ? -1.0f : 1.0f, 0.0f, 0.0f, 0.0f, fs);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (west) fW[v] = wb * 0.5f * hy * fs[v];
+        else fE[v] = wb * 0.5f * hy * fs[v];
+      }
+    }
+    if (nd && (b == 0 || b == P)) {
+      const bool south = (b == 0);
+      const int64_t en = nbr[e * 4 + (south ? 0 : 2)];
+      float up[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const float* un = u + v * stride + en * NLOC + a;
+        float s2 = 0.0f;
+#pragma unroll
+        for (int jj = 0; jj < N1; ++jj) s2 = fmaf(south ? tab.B[1][jj] : tab.B[0][jj], un[N1 * jj], s2);
+        up[v] = s2;
+      }
+      float fs[NV];
+      num_flux<FLUX>(ms, south ? tS : tN, up, 0.0f, south ? -1.0f : 1.0f, 0.0f, 0.0f, fs);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (south) fS[v] = wa * 0.5f * hx * fs[v];
+        else fN[v] = wa * 0.5f * hx * fs[v];
+      }
+    }
+    // distribute the face fluxes: west / east along the own row, south / north
+    // from row 0 / row P of the own column
+    const int s0 = b & 3, sP = (b - P) & 3;   // rotations that bring row 0 / row P
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const float* un = u + v * stride + en * NLOC + a;
-      float s2 = 0.0f;
-#pragma unroll
-      for (int jj = 0; jj < N1; ++jj) s2 = fmaf(south ? tab.B[1][jj] : tab.B[0][jj], un[N1 * jj], s2);
-      up[v] = s2;
+      const float r1 = rrot<1>(fS[v]), r2 = rrot<2>(fS[v]), r3 = rrot<3>(fS[v]);
+      const float fS0 = (s0 == 0) ? fS[v] : (s0 == 1) ? r1 : (s0 == 2) ? r2 : r3;
+      const float n1 = rrot<1>(fN[v]), n2 = rrot<2>(fN[v]), n3 = rrot<3>(fN[v]);
+      const float fNP = (sP == 0) ? fN[v] : (sP == 1) ? n1 : (sP == 2) ? n2 : n3;
+      r[v] = fmaf(L.misc[0], qbcast<0>(fW[v]), r[v]);
+      r[v] = fmaf(L.misc[1], qbcast<P>(fE[v]), r[v]);
+      r[v] = fmaf(L.misc[2], fS0, r[v]);
+      r[v] = fmaf(L.misc[3], fNP, r[v]);
     }
-    float fs[NV];
-    num_flux<FLUX>(ms, south ? tS : tN, up, 0.0f, south ? -1.0f : 1.0f, 0.0f, 0.0f, fs);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if (south) fS[v] = wa * 0.5f * hx * fs[v];
-      else fN[v] = wa * 0.5f * hx * fs[v];
-    }
-  }
-  // distribute the face fluxes: west / east along the own row, south / north
-  // from row 0 / row P of the own column
-  const int s0 = b & 3, sP = (b - P) & 3;   // rotations that bring row 0 / row P
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const float r1 = rrot<1>(fS[v]), r2 = rrot<2>(fS[v]), r3 = rrot<3>(fS[v]);
-    const float fS0 = (s0 == 0) ? fS[v] : (s0 == 1) ? r1 : (s0 == 2) ? r2 : r3;
-    const float n1 = rrot<1>(fN[v]), n2 = rrot<2>(fN[v]), n3 = rrot<3>(fN[v]);
-    const float fNP = (sP == 0) ? fN[v] : (sP == 1) ? n1 : (sP == 2) ? n2 : n3;
-    r[v] = fmaf(L.misc[0], qbcast<0>(fW[v]), r[v]);
-    r[v] = fmaf(L.misc[1], qbcast<P>(fE[v]), r[v]);
-    r[v] = fmaf(L.misc[2], fS0, r[v]);
-    r[v] = fmaf(L.misc[3], fNP, r[v]);
+
   }
 
   // ---- output -----------------------------------------------------------------
