@@ -47,6 +47,20 @@ __device__ __forceinline__ int rroti(int x) {
   if constexpr (S == 0) return x; else return dppi<(0x120 | (4 * S))>(x);
 }
 
+// value of lane N of the own 16-lane row (row_newbcast, gfx90a and later)
+template <int N>
+__device__ __forceinline__ double rowbcastd(double x) {
+  return dppd<(0x150 | N)>(x);
+}
+// sum over the four lanes of the own quad (every lane receives bitwise the
+// same value: butterfly order, no contraction, as for row_sum)
+__device__ __forceinline__ float quad_sum(float x) {
+#pragma clang fp contract(off)
+  x = x + dpp<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
+  x = x + dpp<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+  return x;
+}
+
 template <int I>
 __device__ __forceinline__ double qbcastd(double x) {
   return dppd<(I | (I << 2) | (I << 4) | (I << 6))>(x);
@@ -56,26 +70,32 @@ __device__ __forceinline__ double rrotd(double x) {
   if constexpr (S == 0) return x; else return dppd<(0x120 | (4 * S))>(x);
 }
 
-// sums / maxima over the 16 lanes of a row (every lane receives the result)
+// Sums / maxima over the 16 lanes of a row.  Butterfly order (lane i pairs
+// with i^1, i^2, then the mirrored lane of the other quad and of the other half
+// row): every lane adds the same two partial values, so all 16 lanes receive
+// bitwise the same result.  Contraction is off so that a product feeding the
+// sum is not fused into its first addition on one side of a pair only.
 __device__ __forceinline__ float row_sum(float x) {
-  x += dpp<0x124>(x);
-  x += dpp<0x128>(x);
-  x += dpp<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
-  x += dpp<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+#pragma clang fp contract(off)
+  x = x + dpp<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
+  x = x + dpp<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+  x = x + dpp<0x141>(x);
+  x = x + dpp<0x140>(x);
   return x;
 }
 __device__ __forceinline__ double row_sumd(double x) {
-  x += dppd<0x124>(x);
-  x += dppd<0x128>(x);
-  x += dppd<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
-  x += dppd<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+#pragma clang fp contract(off)
+  x = x + dppd<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
+  x = x + dppd<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+  x = x + dppd<0x141>(x);
+  x = x + dppd<0x140>(x);
   return x;
 }
 __device__ __forceinline__ float row_max(float x) {
-  x = fmaxf(x, dpp<0x124>(x));
-  x = fmaxf(x, dpp<0x128>(x));
   x = fmaxf(x, dpp<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x));
   x = fmaxf(x, dpp<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x));
+  x = fmaxf(x, dpp<0x141>(x));
+  x = fmaxf(x, dpp<0x140>(x));
   return x;
 }
 

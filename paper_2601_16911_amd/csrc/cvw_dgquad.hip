@@ -45,6 +45,91 @@ struct KSet {
 template <int P>
 inline constexpr KSet<P> kset{};
 
+// Derivatives D^k (|k| = 1..P, KSet order) at z + (X, Y) of the degree-P
+// polynomial whose derivatives at z are c (Taylor expansion, eq. taylorsol)
+template <int P>
+__device__ __forceinline__ void taylor_move(const float (&c)[KSet<P>::NK], float X, float Y,
+                                            float (&o)[KSet<P>::NK]) {
+  constexpr int NK = KSet<P>::NK;
+  constexpr KSet<P> ks = kset<P>;
+  constexpr float inv_n[4] = {1.0f, 1.0f, 0.5f, 1.0f / 3.0f};
+  float px[P + 1], py[P + 1];
+  px[0] = 1.0f;
+  py[0] = 1.0f;
+#pragma unroll
+  for (int n = 1; n <= P; ++n) {
+    px[n] = px[n - 1] * X * inv_n[n];
+    py[n] = py[n - 1] * Y * inv_n[n];
+  }
+#pragma unroll
+  for (int t = 0; t < NK; ++t) {
+    float s = c[t];
+#pragma unroll
+    for (int t2 = NK - 1; t2 >= 0; --t2) {
+      const int i = ks.x[t2] - ks.x[t], j = ks.y[t2] - ks.y[t];
+      if (t2 != t && i >= 0 && j >= 0) s = fmaf(c[t2], (i == 0) ? py[j] : (j == 0) ? px[i] : px[i] * py[j], s);
+    }
+    o[t] = s;
+  }
+}
+
+// sum_k h_e^{2|k|-2} x_k y_k over |k| = 1..P (the weights of eq. snorm, d = 2)
+template <int P>
+__device__ __forceinline__ float order_weighted_dot(const float (&x)[KSet<P>::NK], const float (&y)[KSet<P>::NK],
+                                                    float he2) {
+  constexpr KSet<P> ks = kset<P>;
+  float s[P + 1] = {};
+#pragma unroll
+  for (int t = 0; t < KSet<P>::NK; ++t) {
+    const int o = ks.x[t] + ks.y[t];
+    s[o] = fmaf(x[t], y[t], s[o]);
+  }
+  float r = s[P];
+#pragma unroll
+  for (int o = P - 1; o >= 1; --o) r = fmaf(he2, r, s[o]);
+  return r;
+}
+
+// Cell mean of sum_k h_e^{2|k|-2} (D^k p)^2 (eq. snorm divided by |e|) for the
+// degree-P polynomial p with derivatives ch at the centre of a hx x hy cell.
+// Exact: D^k p has degree <= 2 in the centred coordinates (X, Y); written in
+// the orthogonal basis 1, X, (X^2 - hx^2/12)/2, Y, XY, ... its mean square is a
+// sum of squares with the weights mean(X^2) = hx^2/12,
+// mean(((X^2 - hx^2/12)/2)^2) = hx^4/720, mean(X^2 Y^2) = hx^2 hy^2/144.
+template <int P>
+__device__ __forceinline__ float centred_seminorm_mean(const float (&ch)[KSet<P>::NK], float mx2, float my2,
+                                                      float qx4, float qy4, float he2) {
+  constexpr int NK = KSet<P>::NK;
+  constexpr KSet<P> ks = kset<P>;
+  float ms[NK];
+#pragma unroll
+  for (int t = 0; t < NK; ++t) {
+    float A = ch[t], rest = 0.0f;
+#pragma unroll
+    for (int t2 = 0; t2 < NK; ++t2) {
+      const int i = ks.x[t2] - ks.x[t], j = ks.y[t2] - ks.y[t];
+      if (t2 == t || i < 0 || j < 0) continue;
+      const float c = ch[t2];
+      if (i == 1 && j == 0) rest = fmaf(c * mx2, c, rest);
+      if (i == 0 && j == 1) rest = fmaf(c * my2, c, rest);
+      if (i == 1 && j == 1) rest = fmaf(c * (mx2 * my2), c, rest);
+      if (i == 2 && j == 0) {
+        A = fmaf(c, 0.5f * mx2, A);
+        rest = fmaf(c * qx4, c, rest);
+      }
+      if (i == 0 && j == 2) {
+        A = fmaf(c, 0.5f * my2, A);
+        rest = fmaf(c * qy4, c, rest);
+      }
+    }
+    ms[t] = fmaf(A, A, rest);
+  }
+  float one[NK];
+#pragma unroll
+  for (int t = 0; t < NK; ++t) one[t] = 1.0f;
+  return order_weighted_dot<P>(ms, one, he2);
+}
+
 __device__ __forceinline__ float ipow(float x, int n) {
   float r = 1.0f;
   for (int i = 0; i < n; ++i) r *= x;
@@ -229,8 +314,9 @@ __device__ __forceinline__ void dgq_eval_body(
   }
   // vertex candidate data: lane a of each quad fetches vertex a, then quad
   // broadcasts give every lane all four (eq. taylorcand output)
-  float myc[NK];
-  {
+  const bool plain = (ms.sensor_kind == CVW_SENSOR_PLAIN);
+  float myc[NK] = {};
+  if (plain) {
     const int64_t vid = cell_vtx[e * 4 + a];
 #pragma unroll
     for (int t = 0; t < NK; ++t) myc[t] = cand[vid * NK + t];
@@ -239,46 +325,50 @@ __device__ __forceinline__ void dgq_eval_body(
   // ---- sensor-field derivatives at the own point (eq. taylorsol) ------------
   // float64: high derivatives of smooth data cancel; the data is taken relative
   // to its value at node (0, 0) so that constant data gives exactly zero
-  double rho = nd ? static_cast<double>(uv[0]) : 0.0;
-  {
-    const double q0 = qbcastd<0>(rho);
-    const double r1 = rrotd<1>(q0), r2 = rrotd<2>(q0), r3 = rrotd<3>(q0);
-    const double ref = (b == 0) ? q0 : (b == 1) ? r1 : (b == 2) ? r2 : r3;   // row (b - s) & 3 == 0
+  // (needed by the plain sensor and by the shock-capturing weights only)
+  float Du[NK] = {};
+  if (plain || ms.sc_on) {
+    double rho = nd ? static_cast<double>(uv[0]) : 0.0;
+    const double ref = rowbcastd<0>(rho);          // node (0, 0) = lane 0 of the row
     rho = nd ? rho - ref : 0.0;
-  }
-  double Rm[N1];
-  Rm[0] = rho;
+    double Rm[N1];
+    Rm[0] = rho;
 #pragma unroll
-  for (int m = 1; m < N1; ++m) {
-    double sacc = L.DX[m - 1][0] * qbcastd<0>(rho);
-    if constexpr (P >= 1) sacc = fma(L.DX[m - 1][1], qbcastd<1>(rho), sacc);
-    if constexpr (P >= 2) sacc = fma(L.DX[m - 1][2], qbcastd<2>(rho), sacc);
-    if constexpr (P >= 3) sacc = fma(L.DX[m - 1][3], qbcastd<3>(rho), sacc);
-    Rm[m] = sacc;
-  }
-  float Du[NK];
-  const double sxd = 2.0 / static_cast<double>(hx), syd = 2.0 / static_cast<double>(hy);
-#pragma unroll
-  for (int t = 0; t < NK; ++t) {
-    const int kx = ks.x[t], ky = ks.y[t];
-    double sacc;
-    if (ky == 0) {
-      sacc = Rm[kx];
-    } else {
-      sacc = L.DY[ky - 1][0] * Rm[kx];
-      sacc = fma(L.DY[ky - 1][1], rrotd<1>(Rm[kx]), sacc);
-      sacc = fma(L.DY[ky - 1][2], rrotd<2>(Rm[kx]), sacc);
-      sacc = fma(L.DY[ky - 1][3], rrotd<3>(Rm[kx]), sacc);
+    for (int m = 1; m < N1; ++m) {
+      double sacc = L.DX[m - 1][0] * qbcastd<0>(rho);
+      if constexpr (P >= 1) sacc = fma(L.DX[m - 1][1], qbcastd<1>(rho), sacc);
+      if constexpr (P >= 2) sacc = fma(L.DX[m - 1][2], qbcastd<2>(rho), sacc);
+      if constexpr (P >= 3) sacc = fma(L.DX[m - 1][3], qbcastd<3>(rho), sacc);
+      Rm[m] = sacc;
     }
-    Du[t] = static_cast<float>(sacc * dpow(sxd, kx) * dpow(syd, ky));
+    // reference derivatives, rounded to float, times (2/hx)^kx (2/hy)^ky
+    float spx[N1], spy[N1];
+    spx[0] = 1.0f;
+    spy[0] = 1.0f;
+#pragma unroll
+    for (int n = 1; n < N1; ++n) {
+      spx[n] = spx[n - 1] * sx;
+      spy[n] = spy[n - 1] * sy;
+    }
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+      const int kx = ks.x[t], ky = ks.y[t];
+      double sacc;
+      if (ky == 0) {
+        sacc = Rm[kx];
+      } else {
+        sacc = L.DY[ky - 1][0] * Rm[kx];
+        sacc = fma(L.DY[ky - 1][1], rrotd<1>(Rm[kx]), sacc);
+        sacc = fma(L.DY[ky - 1][2], rrotd<2>(Rm[kx]), sacc);
+        sacc = fma(L.DY[ky - 1][3], rrotd<3>(Rm[kx]), sacc);
+      }
+      Du[t] = static_cast<float>(sacc) * (spx[kx] * spy[ky]);
+    }
   }
   const float he2 = he * he;
-  float hk[NK], wk[NK];   // h_e^{2|k|} (pointwise) and h_e^{2|k|-2} (element, d = 2)
-#pragma unroll
-  for (int t = 0; t < NK; ++t) {
-    hk[t] = ipow(he2, ks.x[t] + ks.y[t]);
-    wk[t] = ipow(he2, ks.x[t] + ks.y[t] - 1);
-  }
+  // sum_k h_e^{2|k|-2} (D^k u_h)^2 at the own point: the integrand of eq. snorm
+  // (d = 2) and, times h_e^2, the pointwise indicator of eq. alphaq
+  const float sw = order_weighted_dot<P>(Du, Du, he2);
 
   // ---- sensor gamma_e (cell stage of the cell-vertex reconstruction) --------
   float gam;
@@ -287,78 +377,40 @@ __device__ __forceinline__ void dgq_eval_body(
   } else if (ms.sensor_kind == CVW_SENSOR_LEARNED) {
     gam = gamma_in[e];                         // from the network, one value per cell
   } else {
+    // The vertex candidates p_l (eq. taylorcand) are re-expanded about the
+    // cell centre, one vertex per quad lane (lane a holds vertex a; the rows
+    // repeat it), and their element semi-norms taken in closed form (the
+    // Gauss rule integrates them exactly).  The blend sum_l omega_l p_l is one
+    // polynomial again, evaluated once per quadrature point for eq. gamma.
     const float xq = L.misc[6], yq = L.misc[7];
-    float n2p = 0.0f;
-#pragma unroll
-    for (int t = 0; t < NK; ++t) n2p = fmaf(wk[t] * Du[t], Du[t], n2p);
-    n2p *= Wq;
-    float Ds[4][NK];
-    float b2p[4];
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      float c[NK];
-#pragma unroll
-      for (int t = 0; t < NK; ++t) {
-        if (l == 0) c[t] = qbcast<0>(myc[t]);
-        else if (l == 1) c[t] = qbcast<1>(myc[t]);
-        else if (l == 2) c[t] = qbcast<2>(myc[t]);
-        else c[t] = qbcast<3>(myc[t]);
-      }
-      const float xl = (l == 1 || l == 2) ? 1.0f : -1.0f;
-      const float yl = (l >= 2) ? 1.0f : -1.0f;
-      const float dx = (xq - xl) * 0.5f * hx, dy = (yq - yl) * 0.5f * hy;
-      float px[N1], py[N1];
-      px[0] = 1.0f;
-      py[0] = 1.0f;
-#pragma unroll
-      for (int n = 1; n < N1; ++n) {
-        constexpr float inv_n[4] = {1.0f, 1.0f, 0.5f, 1.0f / 3.0f};
-        px[n] = px[n - 1] * dx * inv_n[n];
-        py[n] = py[n - 1] * dy * inv_n[n];
-      }
-      float bp = 0.0f;
-#pragma unroll
-      for (int t = 0; t < NK; ++t) {
-        float sacc = 0.0f;
-#pragma unroll
-        for (int t2 = 0; t2 < NK; ++t2) {
-          if (ks.x[t2] >= ks.x[t] && ks.y[t2] >= ks.y[t])
-            sacc = fmaf(c[t2], px[ks.x[t2] - ks.x[t]] * py[ks.y[t2] - ks.y[t]], sacc);
-        }
-        Ds[l][t] = sacc;
-        bp = fmaf(wk[t] * sacc, sacc, bp);
-      }
-      b2p[l] = Wq * bp;
+    const float n2 = row_sum(Wq * sw);
+    const float xl = (a == 1 || a == 2) ? 1.0f : -1.0f, yl = (a >= 2) ? 1.0f : -1.0f;
+    float ch[NK];
+    taylor_move<P>(myc, -0.5f * xl * hx, -0.5f * yl * hy, ch);
+    const float mx2 = hx * hx * (1.0f / 12.0f), my2 = hy * hy * (1.0f / 12.0f);
+    const float qx4 = hx * hx * hx * hx * (1.0f / 720.0f), qy4 = hy * hy * hy * hy * (1.0f / 720.0f);
+    const float b2v = hx * hy * centred_seminorm_mean<P>(ch, mx2, my2, qx4, qy4, he2);
+    float w0, wv;
+    if (ms.fast_exp) {
+      const float d0 = ms.eps_c + sqrtf(n2), dv = ms.eps_c + sqrtf(b2v);
+      w0 = (1.0f - 4.0f * ms.lin_w) * frcp(d0 * d0);
+      wv = ms.lin_w * frcp(dv * dv);
+    } else {
+      w0 = (1.0f - 4.0f * ms.lin_w) * powf(ms.eps_c + powf(sqrtf(n2), ms.q_beta), -ms.r);
+      wv = ms.lin_w * powf(ms.eps_c + powf(sqrtf(b2v), ms.q_beta), -ms.r);
     }
-    const float n2 = row_sum(n2p);
-    float beta[5];
-    beta[0] = sqrtf(n2);
+    const float wq = quad_sum(wv);                   // sum over the four vertices
+    const float oinv = frcp(w0 + wq);
+    const float whv = wv * oinv;
+    float cb[NK], db[NK], dl[NK];
 #pragma unroll
-    for (int l = 0; l < 4; ++l) beta[l + 1] = sqrtf(row_sum(b2p[l]));
-    float om[5], osum = 0.0f;
+    for (int t = 0; t < NK; ++t) cb[t] = quad_sum(whv * ch[t]);
+    taylor_move<P>(cb, 0.5f * xq * hx, 0.5f * yq * hy, db);
+    // u_h - u* = sum_l omega_l (u_h - p_l) with the normalised weights
+    const float wrest = wq * oinv;
 #pragma unroll
-    for (int l = 0; l < 5; ++l) {
-      const float lin = (l == 0) ? 1.0f - 4.0f * ms.lin_w : ms.lin_w;
-      float w;
-      if (ms.fast_exp) {
-        const float den = ms.eps_c + beta[l];
-        w = lin * frcp(den * den);
-      } else {
-        w = lin * powf(ms.eps_c + powf(beta[l], ms.q_beta), -ms.r);
-      }
-      om[l] = w;
-      osum += w;
-    }
-    const float oinv = frcp(osum);
-    float d2p = 0.0f;
-#pragma unroll
-    for (int t = 0; t < NK; ++t) {
-      float dl = 0.0f;
-#pragma unroll
-      for (int l = 0; l < 4; ++l) dl = fmaf(om[l + 1] * oinv, Du[t] - Ds[l][t], dl);
-      d2p = fmaf(wk[t] * dl, dl, d2p);
-    }
-    const float d2 = row_sum(Wq * d2p);
+    for (int t = 0; t < NK; ++t) dl[t] = fmaf(wrest, Du[t], -db[t]);
+    const float d2 = row_sum(Wq * order_weighted_dot<P>(dl, dl, he2));
     if (n2 > 0.0f) {
       const float mr = fminf(1.0f, sqrtf(d2 / n2));      // n2 may be subnormal: IEEE division
       gam = 1.0f - (ms.fast_exp ? mr : powf(mr, ms.q_sensor));
@@ -375,10 +427,7 @@ __device__ __forceinline__ void dgq_eval_body(
     lam = row_max(nd ? wave_speed<FLUX>(ms, uv, 0.0f, 0.0f) : 0.0f);
   }
   const float nu = lam * he / (2.0f * P);
-  float atil2 = 0.0f;
-#pragma unroll
-  for (int t = 0; t < NK; ++t) atil2 = fmaf(hk[t] * Du[t], Du[t], atil2);
-  const float atil = sqrtf(atil2);
+  const float atil = sqrtf(he2 * sw);
   const float g2 = Du[0] * Du[0] + Du[1] * Du[1];
   const float fq = (1.0f - gam) * g2;
   const float S = row_sum(Wq * fq);
