@@ -469,12 +469,12 @@ __device__ __forceinline__ void dgq_eval_body(
 #pragma unroll
       for (int i = 0; i <= P; ++i) {
         gx = fmaf(L.CX1[i], rowv[i], gx);
-        sXs = fmaf(a == 0 ? tab.B[0][i] : tab.B[1][i], rowv[i], sXs);
+        sXs = fmaf(L.OX[i], rowv[i], sXs);
       }
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
         gy = fmaf(L.CY1[s2], colv[s2], gy);
-        sYs = fmaf(b <= 1 ? L.BY0[s2] : L.BY1[s2], colv[s2], sYs);
+        sYs = fmaf(L.OY[s2], colv[s2], sYs);
       }
       tW[v] = sXs;                // x-side trace (W on a = 0, E otherwise)
       tS[v] = sYs;                // y-side trace (S in rows 0, 1; N in rows 2, 3)
@@ -515,50 +515,40 @@ __device__ __forceinline__ void dgq_eval_body(
   // ---- interface terms -------------------------------------------------------
   const int64_t stride = E * NLOC;
   if constexpr (P == 3) {
-    // One face quadrature point per lane (4 faces x 4 points = 16 lanes):
-    // x-faces on the columns a = 0 (W) and a = 3 (E), point b; y-faces on the
-    // rows b = 0 (S) and b = 3 (N) for the columns 1, 2; the S / N points of
-    // the corner columns 0 and 3 go to the inner lanes (1,1), (2,1) / (1,2), (2,2).
+    // One face quadrature point per lane (4 faces x 4 points = 16 lanes; the
+    // assignment and the lane's coefficients are in its lane record)
     const bool xf = (a == 0 || a == 3);
     const bool inner = !xf && (b == 1 || b == 2);
-    const bool south = inner ? (b == 1) : (b == 0);
-    const int col = inner ? (a == 1 ? 0 : 3) : a;
-    const int slot = xf ? (a == 0 ? 3 : 1) : (south ? 0 : 2);       // neighbour: S 0, E 1, N 2, W 3
-    const int64_t en = nbr[e * 4 + slot];
-    const bool far_plus = (slot == 3 || slot == 0);                 // W / S neighbour: its +1 side
-    const int base = xf ? N1 * b : col, step = xf ? 1 : N1;
+    const int64_t en = nbr[e * 4 + L.slot];
+    const float* un0 = u + en * NLOC + L.noff;
+    const int nst = L.nstep;
     float um[NV], up[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       // the inner lanes take the corner columns' y-side traces from the lanes
       // a = 0 / 3 of their row (rows 1 / 2 hold S / N traces)
-      const float q0 = qbcast<0>(tS[v]), q3 = qbcast<3>(tS[v]);
-      um[v] = xf ? tW[v] : (inner ? (a == 1 ? q0 : q3) : tS[v]);
-      const float* un = u + v * stride + en * NLOC + base;
+      const float tc = dpp<(0 | (0 << 2) | (3 << 4) | (3 << 6))>(tS[v]);
+      um[v] = xf ? tW[v] : (inner ? tc : tS[v]);
+      const float* un = un0 + v * stride;
       float s2 = 0.0f;
 #pragma unroll
-      for (int ii = 0; ii < N1; ++ii) s2 = fmaf(far_plus ? tab.B[1][ii] : tab.B[0][ii], un[step * ii], s2);
+      for (int ii = 0; ii < N1; ++ii) s2 = fmaf(L.FB[ii], un[nst * ii], s2);
       up[v] = s2;
     }
-    const float nx = xf ? (a == 0 ? -1.0f : 1.0f) : 0.0f, ny = xf ? 0.0f : (south ? -1.0f : 1.0f);
     float fs[NV];
-    num_flux<FLUX>(ms, um, up, nx, ny, 0.0f, 0.0f, fs);
-    const float wpt = xf ? wb * 0.5f * hy : (inner ? tab.w[0] : wa) * 0.5f * hx;   // Gauss weights are symmetric
+    num_flux<FLUX>(ms, um, up, L.nx, L.ny, 0.0f, 0.0f, fs);
+    const float wpt = fmaf(L.fwx, hy, L.fwy * hx);
     // distribution: W / E along the own row from the lanes a = 0 / 3; S / N of
-    // the columns 1, 2 from the rows 0 / 3, of the corner columns from the rows
-    // 1 / 2 after moving the inner lanes' values there (quad permutation 1,1,2,2)
-    const bool ccol = (a == 0 || a == 3);
-    const int shS = (b - (ccol ? 1 : 0)) & 3, shN = (b - (ccol ? 2 : 3)) & 3;
+    // column a from the lanes named in the lane record (lane permutes)
+    const int rowbase = (tid & 63) & ~15;
+    const int addrS = 4 * (rowbase + L.srcS), addrN = 4 * (rowbase + L.srcN);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const float fl = wpt * fs[v];
+      const float fS0 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addrS, __builtin_bit_cast(int, fl)));
+      const float fNP = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addrN, __builtin_bit_cast(int, fl)));
       r[v] = fmaf(L.misc[0], qbcast<0>(fl), r[v]);
       r[v] = fmaf(L.misc[1], qbcast<3>(fl), r[v]);
-      const float mv = dpp<(1 | (1 << 2) | (2 << 4) | (2 << 6))>(fl);
-      const float ys = ccol ? mv : fl;
-      const float y1 = rrot<1>(ys), y2 = rrot<2>(ys), y3 = rrot<3>(ys);
-      const float fS0 = (shS == 0) ? ys : (shS == 1) ? y1 : (shS == 2) ? y2 : y3;
-      const float fNP = (shN == 0) ? ys : (shN == 1) ? y1 : (shN == 2) ? y2 : y3;
       r[v] = fmaf(L.misc[2], fS0, r[v]);
       r[v] = fmaf(L.misc[3], fNP, r[v]);
     }

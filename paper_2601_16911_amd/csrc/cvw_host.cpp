@@ -185,6 +185,30 @@ static void fill_lane_tables(LaneRec* R, const TensorTables& T, int p) {
     L.misc[5] = T.w[b];
     L.misc[6] = T.xi[a];
     L.misc[7] = T.xi[b];
+    if (p == 3) {
+      const bool xf = (a == 0 || a == 3);
+      const bool inner = !xf && (b == 1 || b == 2);
+      const bool south = inner ? (b == 1) : (b == 0);
+      const int col = inner ? (a == 1 ? 0 : 3) : a;
+      L.slot = xf ? (a == 0 ? 3 : 1) : (south ? 0 : 2);
+      const bool far_plus = (L.slot == 3 || L.slot == 0);      // W / S neighbour: its +1 side
+      for (int i = 0; i < 4; ++i) {
+        L.OX[i] = (a == 0) ? T.B[0][i] : T.B[1][i];
+        const int src = (b - i) & 3;
+        L.OY[i] = (b <= 1) ? T.B[0][src] : T.B[1][src];
+        L.FB[i] = far_plus ? T.B[1][i] : T.B[0][i];
+      }
+      L.noff = xf ? 4 * b : col;
+      L.nstep = xf ? 1 : 4;
+      L.nx = xf ? (a == 0 ? -1.0f : 1.0f) : 0.0f;
+      L.ny = xf ? 0.0f : (south ? -1.0f : 1.0f);
+      L.fwx = xf ? 0.5f * T.w[b] : 0.0f;
+      L.fwy = xf ? 0.0f : 0.5f * T.w[col];
+      const bool ccol = (a == 0 || a == 3);
+      const int ia = (a == 0) ? 1 : 2;
+      L.srcS = ccol ? ia + 4 : a;
+      L.srcN = ccol ? ia + 8 : a + 12;
+    }
   }
 }
 

@@ -48,6 +48,19 @@ struct alignas(16) LaneRec {
   float misc[8];     // l_a(-1), l_a(+1), l_b(-1), l_b(+1), w_a, w_b, xi_a, xi_b
   double DX[3][4];   // l_i^{(m)}(xi_a), m = 1..3
   double DY[3][4];   // l^{(m)}_{(b-s)&3}(xi_b), m = 1..3
+  // p = 3 interface step, one face quadrature point per lane: x-faces on the
+  // columns a = 0 (W) and 3 (E) at point b; y-faces on the rows b = 0 (S) and
+  // 3 (N) for the columns 1, 2; the S / N points of the corner columns 0 / 3
+  // on the inner lanes (1, 1), (2, 1) / (1, 2), (2, 2).  Zero for p < 3.
+  float OX[4];       // own x-side trace: l_i(-1) on a = 0, l_i(+1) otherwise
+  float OY[4];       // own y-side trace, rotated: l_{(b-s)&3}(-1) in rows 0, 1, (+1) in rows 2, 3
+  float FB[4];       // neighbour trace along its normal line (its side facing this cell)
+  float fwx, fwy;    // face weight: w * h / 2 = fwx * hy + fwy * hx
+  float nx, ny;      // outward unit normal of the lane's face point
+  int slot;          // neighbour slot (S 0, E 1, N 2, W 3)
+  int noff, nstep;   // neighbour node index of the normal line's first node, and its stride
+  int srcS, srcN;    // lanes of the row that hold the S / N flux of column a
+  int pad_[3];
 };
 
 // Reference tables of a tensor-product CG element (Gauss-Lobatto nodes) of
