@@ -105,6 +105,9 @@ __device__ __forceinline__ float row_max(float x) {
 // ---------------------------------------------------------------------------
 // hardware reciprocal (1 ulp): the hot kernels divide through it
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// hardware square root (v_sqrt_f32, about 1 ulp): the correctly rounded
+// sqrtf costs a dozen instructions of range scaling and correction
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 template <int FLUX> struct NVar { static constexpr int value = 1; };
 template <> struct NVar<CVW_EULER> { static constexpr int value = 4; };
@@ -146,12 +149,12 @@ __device__ __forceinline__ void phys_flux(const MethodScalars& ms, const float* 
 template <int FLUX>
 __device__ __forceinline__ float wave_speed(const MethodScalars& ms, const float* u, float x, float y) {
   if constexpr (FLUX == CVW_ADVECT_CONST) {
-    return sqrtf(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1]);
+    return fsqrt(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1]);
   } else if constexpr (FLUX == CVW_ADVECT_ROT) {
     const float vx = ms.fp[2] * (ms.fp[1] - y), vy = ms.fp[2] * (x - ms.fp[0]);
-    return sqrtf(vx * vx + vy * vy);
+    return fsqrt(vx * vx + vy * vy);
   } else if constexpr (FLUX == CVW_BURGERS) {
-    return fabsf(u[0]) * sqrtf(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1]);
+    return fabsf(u[0]) * fsqrt(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1]);
   } else if constexpr (FLUX == CVW_KPP) {
     return 1.0f;
   } else {
@@ -159,7 +162,7 @@ __device__ __forceinline__ float wave_speed(const MethodScalars& ms, const float
     const float rho = u[0], inv = frcp(rho);
     const float vx = u[1] * inv, vy = u[2] * inv;
     const float p = (g - 1.0f) * (u[3] - 0.5f * rho * (vx * vx + vy * vy));
-    return sqrtf(vx * vx + vy * vy) + sqrtf(fmaxf(g * p * inv, 0.0f));
+    return fsqrt(vx * vx + vy * vy) + fsqrt(fmaxf(g * p * inv, 0.0f));
   }
 }
 
@@ -176,7 +179,7 @@ __device__ __forceinline__ void num_flux(const MethodScalars& ms, const float* u
     const float pm = (g - 1.0f) * (um[3] - 0.5f * um[0] * (vxm * vxm + vym * vym));
     const float pp = (g - 1.0f) * (up[3] - 0.5f * up[0] * (vxp * vxp + vyp * vyp));
     const float vm = vxm * nx + vym * ny, vp = vxp * nx + vyp * ny;
-    const float cm = sqrtf(fmaxf(g * pm * im, 0.0f)), cp = sqrtf(fmaxf(g * pp * ip, 0.0f));
+    const float cm = fsqrt(fmaxf(g * pm * im, 0.0f)), cp = fsqrt(fmaxf(g * pp * ip, 0.0f));
     const float SL = fminf(vm - cm, vp - cp);
     const float SR = fmaxf(vm + cm, vp + cp);
     // normal fluxes F.n of both states

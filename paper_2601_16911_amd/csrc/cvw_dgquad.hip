@@ -392,7 +392,7 @@ __device__ __forceinline__ void dgq_eval_body(
     const float b2v = hx * hy * centred_seminorm_mean<P>(ch, mx2, my2, qx4, qy4, he2);
     float w0, wv;
     if (ms.fast_exp) {
-      const float d0 = ms.eps_c + sqrtf(n2), dv = ms.eps_c + sqrtf(b2v);
+      const float d0 = ms.eps_c + fsqrt(n2), dv = ms.eps_c + fsqrt(b2v);
       w0 = (1.0f - 4.0f * ms.lin_w) * frcp(d0 * d0);
       wv = ms.lin_w * frcp(dv * dv);
     } else {
@@ -412,7 +412,7 @@ __device__ __forceinline__ void dgq_eval_body(
     for (int t = 0; t < NK; ++t) dl[t] = fmaf(wrest, Du[t], -db[t]);
     const float d2 = row_sum(Wq * order_weighted_dot<P>(dl, dl, he2));
     if (n2 > 0.0f) {
-      const float mr = fminf(1.0f, sqrtf(d2 / n2));      // n2 may be subnormal: IEEE division
+      const float mr = fminf(1.0f, fsqrt(d2 / n2));      // n2 may be subnormal: IEEE division
       gam = 1.0f - (ms.fast_exp ? mr : powf(mr, ms.q_sensor));
     } else {
       gam = 1.0f;
@@ -426,8 +426,8 @@ __device__ __forceinline__ void dgq_eval_body(
   } else {
     lam = row_max(nd ? wave_speed<FLUX>(ms, uv, 0.0f, 0.0f) : 0.0f);
   }
-  const float nu = lam * he / (2.0f * P);
-  const float atil = sqrtf(he2 * sw);
+  const float nu = lam * he * (0.5f / P);
+  const float atil = fsqrt(he2 * sw);
   const float g2 = Du[0] * Du[0] + Du[1] * Du[1];
   const float fq = (1.0f - gam) * g2;
   const float S = row_sum(Wq * fq);
