@@ -20,7 +20,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["cvw_host.cpp", "cvw_dgquad.hip", "cvw_cgquad.hip", "cvw_seg.hip", "cvw_cgstep.hip", "cvw_tri.hip", "cvw_mlp.hip"]
 
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+# -ffp-contract=on: a * b + c is fused only within one expression, so kernels
+# that share a device body (single mesh, batch) round identically
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -292,7 +292,8 @@ __device__ __forceinline__ void dgq_eval_body(
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr int NV = NVar<FLUX>::value;
   constexpr KSet<P> ks = kset<P>;
-  const int tid = threadIdx.x;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   const int q = tid & 15;
   const int a = q & 3, b = q >> 2;
   const int64_t e = blk * 16 + (tid >> 4);
@@ -314,6 +315,8 @@ __device__ __forceinline__ void dgq_eval_body(
   }
   // vertex candidate data: lane a of each quad fetches vertex a, then quad
   // broadcasts give every lane all four (eq. taylorcand output)
+  // neighbour of the lane's face point (degree 3), fetched early
+  const int32_t en_pre = (P == 3) ? nbr[e * 4 + L.slot] : 0;
   const bool plain = (ms.sensor_kind == CVW_SENSOR_PLAIN);
   float myc[NK] = {};
   if (plain) {
@@ -514,13 +517,17 @@ __device__ __forceinline__ void dgq_eval_body(
 
   // ---- interface terms -------------------------------------------------------
   const int64_t stride = E * NLOC;
+  // the previous stage's values of the stage update, in flight during the faces
+  float u0v[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    u0v[v] = (mode != MODE_RESIDUAL && a0 != 0.0f && nd) ? u0[(static_cast<int64_t>(v) * E + e) * NLOC + node] : 0.0f;
   if constexpr (P == 3) {
     // One face quadrature point per lane (4 faces x 4 points = 16 lanes; the
     // assignment and the lane's coefficients are in its lane record)
     const bool xf = (a == 0 || a == 3);
     const bool inner = !xf && (b == 1 || b == 2);
-    const int64_t en = nbr[e * 4 + L.slot];
-    const float* un0 = u + en * NLOC + L.noff;
+    const float* un0 = u + static_cast<int64_t>(en_pre) * NLOC + L.noff;
     const int nst = L.nstep;
     float um[NV], up[NV];
 #pragma unroll
@@ -626,7 +633,7 @@ __device__ __forceinline__ void dgq_eval_body(
         val = r[v];
       } else {
         const float Lv = -r[v] * invWq;
-        const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
+        const float base = (a0 != 0.0f) ? a0 * u0v[v] : 0.0f;
         val = base + b0 * (uv[v] + dt * Lv);
       }
       nonfinite = nonfinite || !isfinite(val);
@@ -638,11 +645,23 @@ __device__ __forceinline__ void dgq_eval_body(
     atomicOr(status, (m1 ? ST_NONFINITE : 0u) | (m2 ? ST_NONPOSITIVE : 0u));
 }
 
+// 256-thread blocks: all loads in flight before the LDS stores
 __device__ __forceinline__ void load_lane_tables(const LaneRec* __restrict__ lanes, LaneRec* sl) {
   const float4* src = reinterpret_cast<const float4*>(lanes);
   float4* dst = reinterpret_cast<float4*>(sl);
   constexpr int n4 = 16 * sizeof(LaneRec) / 16;
-  for (int i = threadIdx.x; i < n4; i += blockDim.x) dst[i] = src[i];
+  constexpr int it = (n4 + 255) / 256;
+  float4 tmp[it];
+#pragma unroll
+  for (int k = 0; k < it; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < n4) tmp[k] = src[i];
+  }
+#pragma unroll
+  for (int k = 0; k < it; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < n4) dst[i] = tmp[k];
+  }
 }
 
 template <int P, int FLUX>
@@ -650,14 +669,25 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
     const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* __restrict__ lanes,
-    TensorTables tab, int64_t E, int64_t nbp, float hx, float hy, float he, MethodScalars ms, int mode, float dt,
-    float a0, float b0, uint32_t* __restrict__ status, const float* __restrict__ gamma_in) {
+    TensorTables tab, int64_t E, int64_t ntile, int64_t tpb, float hx, float hy, float he, MethodScalars ms,
+    int mode, float dt, float a0, float b0, uint32_t* __restrict__ status, const float* __restrict__ gamma_in) {
   // per-lane tables: one copy per block in LDS
   __shared__ LaneRec sl[16];
   load_lane_tables(lanes, sl);
   __syncthreads();
-  dgq_eval_body<P, FLUX>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E,
-                         xcd_block(blockIdx.x, nbp), hx, hy, he, ms, mode, dt, a0, b0, status, gamma_in);
+  // each block walks a contiguous run of tpb tiles of 16 cells; the blocks of
+  // one XCD hold consecutive runs (neighbour rows share its L2)
+  const int64_t first = xcd_block(blockIdx.x, gridDim.x) * tpb;
+  for (int64_t t = 0; t < tpb; ++t) {
+    const int64_t blk = first + t;
+    if (blk >= ntile) break;
+    // keeps the lane-table reads inside the loop (hoisted, they would hold
+    // every table entry in registers for the whole run)
+    float hx_ = hx, hy_ = hy, he_ = he;
+    asm volatile("" : "+v"(hx_), "+v"(hy_), "+v"(he_) :: "memory");
+    dgq_eval_body<P, FLUX>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E, blk, hx_, hy_, he_,
+                           ms, mode, dt, a0, b0, status, gamma_in);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -684,13 +714,21 @@ cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const flo
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 
+// grid of the fused cell pass: a few resident rounds of 256-thread blocks
+#ifndef CVW_EVAL_GRID
+#define CVW_EVAL_GRID 8192
+#endif
+static constexpr int64_t EVAL_GRID = CVW_EVAL_GRID;
+
 template <int P, int FLUX>
 static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
                         float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
                         float a0, float b0, const float* gamma_in, hipStream_t s) {
-  const int64_t nb = pad8((m->E + 15) / 16);
+  const int64_t ntile = (m->E + 15) / 16;
+  const int64_t nb = pad8(std::min<int64_t>(ntile, EVAL_GRID));
+  const int64_t tpb = (ntile + nb - 1) / nb;
   hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0, out,
-                     gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, nb,
+                     gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, ntile, tpb,
                      static_cast<float>(m->hx), static_cast<float>(m->hy), static_cast<float>(m->he), ms, mode, dt,
                      a0, b0, status, gamma_in);
 }
