@@ -61,6 +61,13 @@ __device__ __forceinline__ float quad_sum(float x) {
   return x;
 }
 
+__device__ __forceinline__ double quad_sumd(double x) {
+#pragma clang fp contract(off)
+  x = x + dppd<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
+  x = x + dppd<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+  return x;
+}
+
 template <int I>
 __device__ __forceinline__ double qbcastd(double x) {
   return dppd<(I | (I << 2) | (I << 4) | (I << 6))>(x);

@@ -152,7 +152,7 @@ __device__ __forceinline__ void dgq_vertex_body(const float* __restrict__ u, flo
                                                 double sy, double he2, const MethodScalars& ms) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr KSet<P> ks = kset<P>;
-  const int64_t i = blk * 256 + threadIdx.x;
+  const int64_t i = blk * VTX_PER_BLOCK + threadIdx.x;
   if (i >= Nv) return;
   double acc[NK];
 #pragma unroll
@@ -163,63 +163,63 @@ __device__ __forceinline__ void dgq_vertex_body(const float* __restrict__ u, flo
     const int ent = vent[it];
     const int e = ent >> 2, lv = ent & 3;
     const float* ue = u + static_cast<int64_t>(e) * NLOC;
-    double r[NLOC];
-    if constexpr (NLOC % 4 == 0) {
-#pragma unroll
-      for (int j = 0; j < NLOC / 4; ++j) {
-        const float4 v4 = reinterpret_cast<const float4*>(ue)[j];
-        r[4 * j] = v4.x;
-        r[4 * j + 1] = v4.y;
-        r[4 * j + 2] = v4.z;
-        r[4 * j + 3] = v4.w;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < NLOC; ++j) r[j] = ue[j];
-    }
-    // derivatives are taken of the data relative to one nodal value, so that
-    // constant data gives exactly zero Hermite data
-    {
-      const double r0 = r[0];
-#pragma unroll
-      for (int j = 0; j < NLOC; ++j) r[j] -= r0;
-    }
-    // vertex at xi = +1 (lv 1, 2) / eta = +1 (lv 2, 3): mirror the data so that
-    // only the tables at -1 are needed: l_i^{(m)}(1) = (-1)^m l_{P-i}^{(m)}(-1)
+    // vertex at xi = +1 (lv 1, 2) / eta = +1 (lv 2, 3): the data is mirrored
+    // so that only the tables at -1 are needed, l_i^{(m)}(1) = (-1)^m
+    // l_{P-i}^{(m)}(-1): rows through the load addresses, columns by selects
     const bool fx = (lv == 1) || (lv == 2);
     const bool fy = (lv >= 2);
-    double rr[NLOC];
+    float rf[NLOC];
 #pragma unroll
-    for (int bb = 0; bb < N1; ++bb)
+    for (int bb = 0; bb < N1; ++bb) {
+      const float* row = ue + N1 * (fy ? P - bb : bb);
+      float v[N1];
+      if constexpr (N1 == 4) {
+        const float4 v4 = *reinterpret_cast<const float4*>(row);
+        v[0] = v4.x;
+        v[1] = v4.y;
+        v[2] = v4.z;
+        v[3] = v4.w;
+      } else {
 #pragma unroll
-      for (int aa = 0; aa < N1; ++aa) {
-        const double v00 = r[aa + N1 * bb], v10 = r[(P - aa) + N1 * bb];
-        const double v01 = r[aa + N1 * (P - bb)], v11 = r[(P - aa) + N1 * (P - bb)];
-        rr[aa + N1 * bb] = fx ? (fy ? v11 : v10) : (fy ? v01 : v00);
+        for (int aa = 0; aa < N1; ++aa) v[aa] = row[aa];
       }
-    // derivatives in float64: high derivatives of smooth data cancel strongly
-    double T[N1][N1];   // T[m][j] = sum_i l_i^{(m)}(-1) rr[i][j]
 #pragma unroll
-    for (int m = 0; m < N1; ++m)
-#pragma unroll
-      for (int j = 0; j < N1; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int ii = 0; ii < N1; ++ii) s = fma(tab.Ld[m][ii], rr[ii + N1 * j], s);
-        T[m][j] = s;
-      }
+      for (int aa = 0; aa < N1; ++aa) rf[aa + N1 * bb] = fx ? v[P - aa] : v[aa];
+    }
+    // derivatives are taken of the data relative to one nodal value, so that
+    // constant data gives exactly zero Hermite data (differences of two floats
+    // are exact in float64)
+    const double r0 = static_cast<double>(rf[0]);
+    // derivatives in float64 (high derivatives of smooth data cancel strongly),
+    // one column j of nodes at a time:
+    //   T_j[m] = sum_i l_i^{(m)}(-1) (u_ij - u_00),   D^k u = sum_j l_j^{(ky)}(-1) T_j[kx]
     double D[NK];
+#pragma unroll
+    for (int t = 0; t < NK; ++t) D[t] = 0.0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      double rc[N1];
+#pragma unroll
+      for (int ii = 0; ii < N1; ++ii) rc[ii] = static_cast<double>(rf[ii + N1 * j]) - r0;
+      double Tj[N1];
+#pragma unroll
+      for (int m = 0; m < N1; ++m) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < N1; ++ii) sacc = fma(tab.Ld[m][ii], rc[ii], sacc);
+        Tj[m] = sacc;
+      }
+#pragma unroll
+      for (int t = 0; t < NK; ++t) D[t] = fma(tab.Ld[ks.y[t]][j], Tj[ks.x[t]], D[t]);
+    }
     double b2 = 0.0;
 #pragma unroll
     for (int t = 0; t < NK; ++t) {
       const int kx = ks.x[t], ky = ks.y[t];
-      double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < N1; ++j) s = fma(tab.Ld[ky][j], T[kx][j], s);
       double sc = dpow(sx, kx) * dpow(sy, ky);
       if (fx && (kx & 1)) sc = -sc;
       if (fy && (ky & 1)) sc = -sc;
-      D[t] = s * sc;
+      D[t] *= sc;
       b2 = fma(dpow(he2, kx + ky) * D[t], D[t], b2);
     }
     double w;
@@ -697,7 +697,7 @@ static int64_t pad8(int64_t n) { return (n + 7) / 8 * 8; }
 
 template <int P>
 static void launch_vertex(const cvw_mesh* m, const MethodScalars& ms, const float* u, float* cand, hipStream_t s) {
-  const int64_t nb = pad8((m->Nv + 255) / 256);
+  const int64_t nb = pad8((m->Nv + VTX_PER_BLOCK - 1) / VTX_PER_BLOCK);
   hipLaunchKernelGGL(dgq_vertex_kernel<P>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, cand, m->d_vtx_ptr,
                      m->d_vtx_ent, m->Nv, nb, m->tens, 2.0 / m->hx, 2.0 / m->hy, m->he * m->he, ms);
 }

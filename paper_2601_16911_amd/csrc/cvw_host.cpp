@@ -1429,7 +1429,8 @@ cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** ou
     off += align256(static_cast<size_t>(m->E) * m->nloc * 4);
     // estimated cost of a block: proportional to the nodes per cell
     const double c = static_cast<double>(m->nloc);
-    const int nvb = static_cast<int>((m->Nv + 255) / 256), neb = static_cast<int>((m->E + 15) / 16);
+    const int nvb = static_cast<int>((m->Nv + VTX_PER_BLOCK - 1) / VTX_PER_BLOCK);
+    const int neb = static_cast<int>((m->E + 15) / 16);
     for (int k = 0; k < nvb; ++k) vitems[m->degree].push_back({c, i, k});
     for (int k = 0; k < neb; ++k) eitems[m->degree][prm->flux].push_back({c, i, k});
   }

@@ -17,6 +17,9 @@ enum : uint32_t { ST_NONFINITE = 1u, ST_NONPOSITIVE = 2u };
 // operation modes of the evaluation kernels
 enum Mode : int { MODE_SENSOR = 0, MODE_RESIDUAL = 1, MODE_STAGE = 2 };
 
+// vertices per 256-thread block of the DG quadrilateral vertex pass
+constexpr int VTX_PER_BLOCK = 256;
+
 constexpr int MAXP = 3;   // highest degree of the GPU path
 
 // Reference tables of a tensor-product element of degree p on [-1, 1]
