@@ -18,7 +18,9 @@ update).  value = stabilised-residual DOF updates per second
 
 The roofline object describes the dominant kernel (the fused cell pass,
 dgq_eval_kernel): its launches are bracketed by HIP events on the stream they
-run on, inside the timed region.
+run on, inside the timed region.  The kernel is bound by VALU instruction
+issue, not by HBM: valu_issue relates its counted VALU wave instructions per
+launch (profiles/valu_dgq_eval_config4.json) to the issue roof of the chip.
 """
 from __future__ import annotations
 
@@ -78,6 +80,24 @@ def measured_traffic():
     if tr.get("source_hash") != kernel_source_hash():
         return None
     return tr.get("bytes_per_launch")
+
+
+def measured_valu():
+    """VALU wave instructions per stage-mode launch of the fused cell kernel,
+    from the SQ counter run, or None when the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", "valu_dgq_eval_config4.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        v = json.load(f)
+    if v.get("source_hash") != kernel_source_hash():
+        return None
+    return v.get("valu_instr_per_launch")
+
+
+# VALU issue roof: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles of
+# a 16-lane SIMD, 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def cpu_baseline(target_seconds: float = 15.0):
@@ -318,6 +338,7 @@ def main():
     t_eval = float(np.mean(eval_ms)) / 1e3
     achieved = alg_bytes / t_eval / 1e9
     traffic = measured_traffic()
+    valu = measured_valu()
 
     value = 3.0 * ndof * nv * args.steps / t_total
     out = {
@@ -333,6 +354,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "dgq_eval_kernel<3, EULER> (fused cell pass, stage mode)",
                      "avg_launch_ms": t_eval * 1e3, "alg_bytes_per_launch": alg_bytes},
+        "valu_issue": {"instr_per_launch": valu, "achieved": (valu / t_eval) if valu else None,
+                       "peak": VALU_ISSUE_PEAK, "unit": "wave-instr/s",
+                       "frac": (valu / t_eval / VALU_ISSUE_PEAK) if valu else None,
+                       "kernel": "dgq_eval_kernel<3, EULER>"},
         "residual_only": {"value": ndof * nv / t_res, "unit": "DOF-updates/s", "ms": t_res * 1e3},
         "status_flags": flags,
         "wall_s_timed": wall,
