@@ -286,7 +286,7 @@ __device__ __forceinline__ void dgq_eval_body(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
     const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* sl,
-    const TensorTables& tab, int64_t E, int64_t blk, float hx, float hy, float he, const MethodScalars& ms,
+    const TensorTables& tab, int64_t E, int64_t blk, const CellGeo& G, const MethodScalars& ms,
     int mode, float dt, float a0, float b0, uint32_t* __restrict__ status,
     const float* __restrict__ gamma_in = nullptr) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
@@ -301,9 +301,9 @@ __device__ __forceinline__ void dgq_eval_body(
   const LaneRec& L = sl[q];
   const bool nd = (a <= P) && (b <= P);
   const int node = a + N1 * b;
-  const float sx = 2.0f / hx, sy = 2.0f / hy;
+  const float sx = G.sx, sy = G.sy;
   const float wa = L.misc[4], wb = L.misc[5];
-  const float Wq = nd ? wa * wb * 0.25f * hx * hy : 0.0f;
+  const float Wq = nd ? wa * wb * G.area4 : 0.0f;
 
   // ---- state ---------------------------------------------------------------
   float uv[NV];
@@ -368,7 +368,7 @@ __device__ __forceinline__ void dgq_eval_body(
       Du[t] = static_cast<float>(sacc) * (spx[kx] * spy[ky]);
     }
   }
-  const float he2 = he * he;
+  const float he2 = G.he2;
   // sum_k h_e^{2|k|-2} (D^k u_h)^2 at the own point: the integrand of eq. snorm
   // (d = 2) and, times h_e^2, the pointwise indicator of eq. alphaq
   const float sw = order_weighted_dot<P>(Du, Du, he2);
@@ -389,10 +389,8 @@ __device__ __forceinline__ void dgq_eval_body(
     const float n2 = row_sum(Wq * sw);
     const float xl = (a == 1 || a == 2) ? 1.0f : -1.0f, yl = (a >= 2) ? 1.0f : -1.0f;
     float ch[NK];
-    taylor_move<P>(myc, -0.5f * xl * hx, -0.5f * yl * hy, ch);
-    const float mx2 = hx * hx * (1.0f / 12.0f), my2 = hy * hy * (1.0f / 12.0f);
-    const float qx4 = hx * hx * hx * hx * (1.0f / 720.0f), qy4 = hy * hy * hy * hy * (1.0f / 720.0f);
-    const float b2v = hx * hy * centred_seminorm_mean<P>(ch, mx2, my2, qx4, qy4, he2);
+    taylor_move<P>(myc, -xl * G.hhx, -yl * G.hhy, ch);
+    const float b2v = 4.0f * G.area4 * centred_seminorm_mean<P>(ch, G.mx2, G.my2, G.qx4, G.qy4, he2);
     float w0, wv;
     if (ms.fast_exp) {
       const float d0 = ms.eps_c + fsqrt(n2), dv = ms.eps_c + fsqrt(b2v);
@@ -408,7 +406,7 @@ __device__ __forceinline__ void dgq_eval_body(
     float cb[NK], db[NK], dl[NK];
 #pragma unroll
     for (int t = 0; t < NK; ++t) cb[t] = quad_sum(whv * ch[t]);
-    taylor_move<P>(cb, 0.5f * xq * hx, 0.5f * yq * hy, db);
+    taylor_move<P>(cb, xq * G.hhx, yq * G.hhy, db);
     // u_h - u* = sum_l omega_l (u_h - p_l) with the normalised weights
     const float wrest = wq * oinv;
 #pragma unroll
@@ -429,7 +427,7 @@ __device__ __forceinline__ void dgq_eval_body(
   } else {
     lam = row_max(nd ? wave_speed<FLUX>(ms, uv, 0.0f, 0.0f) : 0.0f);
   }
-  const float nu = lam * he * (0.5f / P);
+  const float nu = lam * G.nuf;
   const float atil = fsqrt(he2 * sw);
   const float g2 = Du[0] * Du[0] + Du[1] * Du[1];
   const float fq = (1.0f - gam) * g2;
@@ -544,7 +542,7 @@ __device__ __forceinline__ void dgq_eval_body(
     }
     float fs[NV];
     num_flux<FLUX>(ms, um, up, L.nx, L.ny, 0.0f, 0.0f, fs);
-    const float wpt = fmaf(L.fwx, hy, L.fwy * hx);
+    const float wpt = fmaf(L.fwx, G.hy, L.fwy * G.hx);
     // distribution: W / E along the own row from the lanes a = 0 / 3; S / N of
     // column a from the lanes named in the lane record (lane permutes)
     const int rowbase = (tid & 63) & ~15;
@@ -579,8 +577,8 @@ __device__ __forceinline__ void dgq_eval_body(
       num_flux<FLUX>(ms, west ? tW : tE, up, west ? -1.0f : 1.0f, 0.0f, 0.0f, 0.0f, fs);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        if (west) fW[v] = wb * 0.5f * hy * fs[v];
-        else fE[v] = wb * 0.5f * hy * fs[v];
+        if (west) fW[v] = wb * G.hhy * fs[v];
+        else fE[v] = wb * G.hhy * fs[v];
       }
     }
     if (nd && (b == 0 || b == P)) {
@@ -599,8 +597,8 @@ __device__ __forceinline__ void dgq_eval_body(
       num_flux<FLUX>(ms, south ? tS : tN, up, 0.0f, south ? -1.0f : 1.0f, 0.0f, 0.0f, fs);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        if (south) fS[v] = wa * 0.5f * hx * fs[v];
-        else fN[v] = wa * 0.5f * hx * fs[v];
+        if (south) fS[v] = wa * G.hhx * fs[v];
+        else fN[v] = wa * G.hhx * fs[v];
       }
     }
     // distribute the face fluxes: west / east along the own row, south / north
@@ -669,7 +667,7 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
     const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* __restrict__ lanes,
-    TensorTables tab, int64_t E, int64_t ntile, int64_t tpb, float hx, float hy, float he, MethodScalars ms,
+    TensorTables tab, int64_t E, int64_t ntile, int64_t tpb, CellGeo G, MethodScalars ms,
     int mode, float dt, float a0, float b0, uint32_t* __restrict__ status, const float* __restrict__ gamma_in) {
   // per-lane tables: one copy per block in LDS
   __shared__ LaneRec sl[16];
@@ -683,10 +681,12 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
     if (blk >= ntile) break;
     // keeps the lane-table reads inside the loop (hoisted, they would hold
     // every table entry in registers for the whole run)
-    float hx_ = hx, hy_ = hy, he_ = he;
-    asm volatile("" : "+v"(hx_), "+v"(hy_), "+v"(he_) :: "memory");
-    dgq_eval_body<P, FLUX>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E, blk, hx_, hy_, he_,
-                           ms, mode, dt, a0, b0, status, gamma_in);
+    CellGeo g = G;
+    asm volatile("" : "+s"(g.hx), "+s"(g.hy), "+s"(g.he), "+s"(g.sx), "+s"(g.sy), "+s"(g.he2), "+s"(g.mx2),
+                 "+s"(g.my2), "+s"(g.qx4), "+s"(g.qy4), "+s"(g.area4), "+s"(g.hhx), "+s"(g.hhy), "+s"(g.nuf)
+                 :: "memory");
+    dgq_eval_body<P, FLUX>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E, blk, g, ms, mode, dt,
+                           a0, b0, status, gamma_in);
   }
 }
 
@@ -729,8 +729,7 @@ static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, co
   const int64_t tpb = (ntile + nb - 1) / nb;
   hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0, out,
                      gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, ntile, tpb,
-                     static_cast<float>(m->hx), static_cast<float>(m->hy), static_cast<float>(m->he), ms, mode, dt,
-                     a0, b0, status, gamma_in);
+                     make_cell_geo(m->hx, m->hy, m->he, P), ms, mode, dt, a0, b0, status, gamma_in);
 }
 
 template <int P>
@@ -1010,7 +1009,7 @@ __global__ __launch_bounds__(256) void batch_eval_kernel(const BatchInst* __rest
     const int2 w = items[it];
     const BatchInst& I = inst[w.x];
     dgq_eval_body<P, FLUX>(I.u_in[stage], I.u, I.u_out[stage], nullptr, nullptr, I.cand, I.cell_vtx, I.nbr, sl, tab,
-                           I.E, w.y, I.hx, I.hy, I.he, I.ms, MODE_STAGE, I.dt, a0, b0, I.status);
+                           I.E, w.y, I.g, I.ms, MODE_STAGE, I.dt, a0, b0, I.status);
   }
 }
 

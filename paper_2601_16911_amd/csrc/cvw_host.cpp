@@ -1374,9 +1374,7 @@ static cvw_status batch_upload_descriptors(cvw_batch* b, void* ws) {
     I.sxd = 2.0 / m->hx;
     I.syd = 2.0 / m->hy;
     I.he2d = m->he * m->he;
-    I.hx = static_cast<float>(m->hx);
-    I.hy = static_cast<float>(m->hy);
-    I.he = static_cast<float>(m->he);
+    I.g = make_cell_geo(m->hx, m->hy, m->he, m->degree);
     I.dt = static_cast<float>(b->dt[i]);
     I.P = m->degree;
     I.flux = b->prms[i].flux;

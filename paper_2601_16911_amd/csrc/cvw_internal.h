@@ -152,6 +152,38 @@ struct MlpDevMut {
   float* b3;
 };
 
+// Uniform geometry factors of a DG quadrilateral mesh for the cell pass,
+// formed once on the host (the device has no scalar floating-point unit, so
+// every uniform product computed in a kernel costs a vector instruction).
+struct CellGeo {
+  float hx, hy, he;        // cell sizes, h_e
+  float sx, sy;            // 2 / hx, 2 / hy
+  float he2;               // h_e^2
+  float mx2, my2;          // hx^2 / 12, hy^2 / 12 (cell mean of X^2, Y^2 about the centre)
+  float qx4, qy4;          // hx^4 / 720, hy^4 / 720
+  float area4;             // hx hy / 4 (quadrature weight factor)
+  float hhx, hhy;          // hx / 2, hy / 2
+  float nuf;               // h_e / (2 p): nu_e = lambda_e nuf
+};
+inline CellGeo make_cell_geo(double hx, double hy, double he, int p) {
+  CellGeo g;
+  g.hx = static_cast<float>(hx);
+  g.hy = static_cast<float>(hy);
+  g.he = static_cast<float>(he);
+  g.sx = static_cast<float>(2.0 / hx);
+  g.sy = static_cast<float>(2.0 / hy);
+  g.he2 = static_cast<float>(he * he);
+  g.mx2 = static_cast<float>(hx * hx / 12.0);
+  g.my2 = static_cast<float>(hy * hy / 12.0);
+  g.qx4 = static_cast<float>(hx * hx * hx * hx / 720.0);
+  g.qy4 = static_cast<float>(hy * hy * hy * hy / 720.0);
+  g.area4 = static_cast<float>(0.25 * hx * hy);
+  g.hhx = static_cast<float>(0.5 * hx);
+  g.hhy = static_cast<float>(0.5 * hy);
+  g.nuf = static_cast<float>(he / (2.0 * p));
+  return g;
+}
+
 // Per-instance descriptor of a batch of independent DG quadrilateral meshes
 // (device memory, written by the host before a batch step).  The Runge-Kutta
 // stage s reads state in[s] and writes out[s]: u -> st1 -> st2 -> u.
@@ -166,7 +198,8 @@ struct alignas(16) BatchInst {
   const int32_t* vent;
   int64_t E, Nv;
   double sxd, syd, he2d;            // 2 / h_x, 2 / h_y, h_e^2 (vertex pass)
-  float hx, hy, he, dt;
+  CellGeo g;
+  float dt;
   int P, flux;
   uint32_t* status;
   MethodScalars ms;
