@@ -77,6 +77,62 @@ __device__ __forceinline__ double rrotd(double x) {
   if constexpr (S == 0) return x; else return dppd<(0x120 | (4 * S))>(x);
 }
 
+// Cross-lane dot products with the DPP source fused into the multiply-add
+// (v_fmac_f32 with DPP; the compiler does not fuse DPP moves into
+// multiply-adds, so each term would otherwise cost a move and an FMA).  The
+// leading s_nop gives the two wait states a DPP read of a VGPR written by the
+// previous VALU instruction needs; the other reads in a block are of the same
+// source.  All sources lie inside the own 16-lane row.
+#define CVW_DPP_TAIL " row_mask:0xf bank_mask:0xf bound_ctrl:1"
+// sum_i c[i] x(lane i of the own quad)
+__device__ __forceinline__ float qdot4(float x, const float (&c)[4]) {
+  float a;
+  asm("s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %1, %2 quad_perm:[0,0,0,0]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,1,1,1]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %4 quad_perm:[2,2,2,2]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %5 quad_perm:[3,3,3,3]" CVW_DPP_TAIL
+      : "=&v"(a) : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+  return a;
+}
+// a = sum_i c[i] x(lane i of the quad), b = sum_i d[i] x(lane i of the quad)
+__device__ __forceinline__ void qdot4x2(float x, const float (&c)[4], const float (&d)[4], float& a, float& b) {
+  asm("s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %2, %3 quad_perm:[0,0,0,0]" CVW_DPP_TAIL "\n\t"
+      "v_mul_f32_dpp %1, %2, %7 quad_perm:[0,0,0,0]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %2, %4 quad_perm:[1,1,1,1]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %1, %2, %8 quad_perm:[1,1,1,1]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %2, %5 quad_perm:[2,2,2,2]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %1, %2, %9 quad_perm:[2,2,2,2]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %2, %6 quad_perm:[3,3,3,3]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %1, %2, %10 quad_perm:[3,3,3,3]" CVW_DPP_TAIL
+      : "=&v"(a), "=&v"(b)
+      : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]));
+}
+// c[0] x + sum_{s=1..3} c[s] x(lane rotated by 4 s in the row)  (rows (b - s) & 3)
+__device__ __forceinline__ float rdot4(float x, const float (&c)[4]) {
+  float a;
+  asm("v_mul_f32 %0, %1, %2\n\t"
+      "s_nop 0\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 row_ror:4" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %4 row_ror:8" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %5 row_ror:12" CVW_DPP_TAIL
+      : "=&v"(a) : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+  return a;
+}
+__device__ __forceinline__ void rdot4x2(float x, const float (&c)[4], const float (&d)[4], float& a, float& b) {
+  asm("v_mul_f32 %0, %2, %3\n\t"
+      "v_mul_f32 %1, %2, %7\n\t"
+      "v_fmac_f32_dpp %0, %2, %4 row_ror:4" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %1, %2, %8 row_ror:4" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %2, %5 row_ror:8" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %1, %2, %9 row_ror:8" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %2, %6 row_ror:12" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %1, %2, %10 row_ror:12" CVW_DPP_TAIL
+      : "=&v"(a), "=&v"(b)
+      : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]));
+}
+
 // Sums / maxima over the 16 lanes of a row.  Butterfly order (lane i pairs
 // with i^1, i^2, then the mirrored lane of the other quad and of the other half
 // row): every lane adds the same two partial values, so all 16 lanes receive

@@ -452,6 +452,22 @@ __device__ __forceinline__ void dgq_eval_body(
   // the two each lane can need (its own x side; the S side in rows 0, 1 and
   // the N side in rows 2, 3), see the interface terms
   float tW[NV], tE[NV], tS[NV], tN[NV];
+  if constexpr (P == 3) {
+    // contractions along the row (quad broadcasts) and the column (row
+    // rotations) as DPP-fused multiply-adds; the 2/h factors ride on the weights
+    const float Wqx = Wq * sx, Wqy = Wq * sy, cfx = coef * sx, cfy = coef * sy;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      float gx, gy, sXs, sYs;
+      qdot4x2(uv[v], L.CX1, L.OX, gx, sXs);
+      rdot4x2(uv[v], L.CY1, L.OY, gy, sYs);
+      tW[v] = sXs;                // x-side trace (W on a = 0, E otherwise)
+      tS[v] = sYs;                // y-side trace (S in rows 0, 1; N in rows 2, 3)
+      const float WFx = Wqx * (cfx * gx - fx[v]);
+      const float WFy = Wqy * (cfy * gy - fy[v]);
+      r[v] = qdot4(WFx, L.TX) + rdot4(WFy, L.TY);
+    }
+  } else {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const float uvv = nd ? uv[v] : 0.0f;
@@ -511,6 +527,7 @@ __device__ __forceinline__ void dgq_eval_body(
     accy = fmaf(L.TY[2], rrot<2>(WFy), accy);
     accy = fmaf(L.TY[3], rrot<3>(WFy), accy);
     r[v] = sx * acc + sy * accy;
+  }
   }
 
   // ---- interface terms -------------------------------------------------------
