@@ -109,6 +109,14 @@ __device__ __forceinline__ void qdot4x2(float x, const float (&c)[4], const floa
       : "=&v"(a), "=&v"(b)
       : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]));
 }
+// r + c0 x(lane 0 of the quad) + c3 x(lane 3 of the quad)
+__device__ __forceinline__ float qfma03(float r, float x, float c0, float c3) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %1, %2 quad_perm:[0,0,0,0]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 quad_perm:[3,3,3,3]" CVW_DPP_TAIL
+      : "+v"(r) : "v"(x), "v"(c0), "v"(c3));
+  return r;
+}
 // c[0] x + sum_{s=1..3} c[s] x(lane rotated by 4 s in the row)  (rows (b - s) & 3)
 __device__ __forceinline__ float rdot4(float x, const float (&c)[4]) {
   float a;
@@ -131,6 +139,22 @@ __device__ __forceinline__ void rdot4x2(float x, const float (&c)[4], const floa
       "v_fmac_f32_dpp %1, %2, %10 row_ror:12" CVW_DPP_TAIL
       : "=&v"(a), "=&v"(b)
       : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]));
+}
+
+// Raw buffer access (gfx9 resource word 3 = 0x00020000: 32-bit data format):
+// a uniform base in scalar registers, a 32-bit per-lane byte offset and a
+// uniform 32-bit byte offset, no 64-bit address arithmetic per lane.  Offsets
+// at or beyond `bytes` read 0 and drop stores (range-checked by the hardware).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(voff),
+                                                                        static_cast<int>(soff), 0));
+}
+__device__ __forceinline__ void buf_store(float x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, static_cast<int>(voff),
+                                        static_cast<int>(soff), 0);
 }
 
 // Sums / maxima over the 16 lanes of a row.  Butterfly order (lane i pairs

@@ -24,6 +24,8 @@
 //
 // All intra-cell exchanges are DPP moves inside the 16-lane row (quad
 // broadcasts along x, row rotations along y); no LDS is used.
+#include <cstdlib>
+
 #include "cvw_device.h"
 
 namespace cvw {
@@ -281,7 +283,9 @@ __device__ __forceinline__ float colbcast(float x, const int (&srcb)[4]) {
 }
 
 // One block of 16 cells (logical block index blk); sl = the lane tables in LDS.
-template <int P, int FLUX>
+// BUF: the state arrays (all variables) and the candidates are each under
+// 4 GiB and are accessed as raw buffers with 32-bit offsets.
+template <int P, int FLUX, bool BUF = false>
 __device__ __forceinline__ void dgq_eval_body(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
@@ -305,13 +309,20 @@ __device__ __forceinline__ void dgq_eval_body(
   const float wa = L.misc[4], wb = L.misc[5];
   const float Wq = nd ? wa * wb * G.area4 : 0.0f;
 
+  // byte offset of the own node in a variable's block, and the block size
+  [[maybe_unused]] const uint32_t offn = BUF ? static_cast<uint32_t>((e * NLOC + node) * 4) : 0u;
+  [[maybe_unused]] const uint32_t sbytes = BUF ? static_cast<uint32_t>(E * NLOC * 4) : 0u;
+
   // ---- state ---------------------------------------------------------------
   float uv[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     float dummy = 0.0f;
     if constexpr (FLUX == CVW_EULER) dummy = (v == 0) ? 1.0f : (v == 3 ? 2.5f : 0.0f);
-    uv[v] = nd ? u[(static_cast<int64_t>(v) * E + e) * NLOC + node] : dummy;
+    if constexpr (BUF)
+      uv[v] = nd ? buf_load(buf_rsrc(u, sbytes * NV), offn, v * sbytes) : dummy;
+    else
+      uv[v] = nd ? u[(static_cast<int64_t>(v) * E + e) * NLOC + node] : dummy;
   }
   // vertex candidate data: lane a of each quad fetches vertex a, then quad
   // broadcasts give every lane all four (eq. taylorcand output)
@@ -322,7 +333,12 @@ __device__ __forceinline__ void dgq_eval_body(
   if (plain) {
     const int64_t vid = cell_vtx[e * 4 + a];
 #pragma unroll
-    for (int t = 0; t < NK; ++t) myc[t] = cand[vid * NK + t];
+    for (int t = 0; t < NK; ++t) {
+      if constexpr (BUF)
+        myc[t] = buf_load(buf_rsrc(cand, 0xFFFFFFFFu), static_cast<uint32_t>(vid * NK * 4), 4u * t);
+      else
+        myc[t] = cand[vid * NK + t];
+    }
   }
 
   // ---- sensor-field derivatives at the own point (eq. taylorsol) ------------
@@ -536,7 +552,12 @@ __device__ __forceinline__ void dgq_eval_body(
   float u0v[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
-    u0v[v] = (mode != MODE_RESIDUAL && a0 != 0.0f && nd) ? u0[(static_cast<int64_t>(v) * E + e) * NLOC + node] : 0.0f;
+    if constexpr (BUF)
+      u0v[v] = (mode != MODE_RESIDUAL && a0 != 0.0f && nd) ? buf_load(buf_rsrc(u0, sbytes * NV), offn, v * sbytes)
+                                                           : 0.0f;
+    else
+      u0v[v] = (mode != MODE_RESIDUAL && a0 != 0.0f && nd) ? u0[(static_cast<int64_t>(v) * E + e) * NLOC + node]
+                                                           : 0.0f;
   if constexpr (P == 3) {
     // One face quadrature point per lane (4 faces x 4 points = 16 lanes; the
     // assignment and the lane's coefficients are in its lane record)
@@ -551,10 +572,17 @@ __device__ __forceinline__ void dgq_eval_body(
       // a = 0 / 3 of their row (rows 1 / 2 hold S / N traces)
       const float tc = dpp<(0 | (0 << 2) | (3 << 4) | (3 << 6))>(tS[v]);
       um[v] = xf ? tW[v] : (inner ? tc : tS[v]);
-      const float* un = un0 + v * stride;
       float s2 = 0.0f;
+      if constexpr (BUF) {
+        const uint32_t o0 = static_cast<uint32_t>((static_cast<int64_t>(en_pre) * NLOC + L.noff) * 4);
 #pragma unroll
-      for (int ii = 0; ii < N1; ++ii) s2 = fmaf(L.FB[ii], un[nst * ii], s2);
+        for (int ii = 0; ii < N1; ++ii)
+          s2 = fmaf(L.FB[ii], buf_load(buf_rsrc(u, sbytes * NV), o0 + 4u * nst * ii, v * sbytes), s2);
+      } else {
+        const float* un = un0 + v * stride;
+#pragma unroll
+        for (int ii = 0; ii < N1; ++ii) s2 = fmaf(L.FB[ii], un[nst * ii], s2);
+      }
       up[v] = s2;
     }
     float fs[NV];
@@ -569,8 +597,7 @@ __device__ __forceinline__ void dgq_eval_body(
       const float fl = wpt * fs[v];
       const float fS0 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addrS, __builtin_bit_cast(int, fl)));
       const float fNP = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addrN, __builtin_bit_cast(int, fl)));
-      r[v] = fmaf(L.misc[0], qbcast<0>(fl), r[v]);
-      r[v] = fmaf(L.misc[1], qbcast<3>(fl), r[v]);
+      r[v] = qfma03(r[v], fl, L.misc[0], L.misc[1]);
       r[v] = fmaf(L.misc[2], fS0, r[v]);
       r[v] = fmaf(L.misc[3], fNP, r[v]);
     }
@@ -652,7 +679,10 @@ __device__ __forceinline__ void dgq_eval_body(
         val = base + b0 * (uv[v] + dt * Lv);
       }
       nonfinite = nonfinite || !isfinite(val);
-      out[idx] = val;
+      if constexpr (BUF)
+        buf_store(val, buf_rsrc(out, sbytes * NV), offn, v * sbytes);
+      else
+        out[idx] = val;
     }
   }
   const unsigned long long m1 = __ballot(nonfinite), m2 = __ballot(inadmissible);
@@ -679,8 +709,11 @@ __device__ __forceinline__ void load_lane_tables(const LaneRec* __restrict__ lan
   }
 }
 
-template <int P, int FLUX>
-__global__ __launch_bounds__(256) void dgq_eval_kernel(
+#ifndef CVW_EVAL_WPE
+#define CVW_EVAL_WPE
+#endif
+template <int P, int FLUX, bool BUF>
+__global__ __launch_bounds__(256) CVW_EVAL_WPE void dgq_eval_kernel(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
     const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec* __restrict__ lanes,
@@ -702,8 +735,8 @@ __global__ __launch_bounds__(256) void dgq_eval_kernel(
     asm volatile("" : "+s"(g.hx), "+s"(g.hy), "+s"(g.he), "+s"(g.sx), "+s"(g.sy), "+s"(g.he2), "+s"(g.mx2),
                  "+s"(g.my2), "+s"(g.qx4), "+s"(g.qy4), "+s"(g.area4), "+s"(g.hhx), "+s"(g.hhy), "+s"(g.nuf)
                  :: "memory");
-    dgq_eval_body<P, FLUX>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E, blk, g, ms, mode, dt,
-                           a0, b0, status, gamma_in);
+    dgq_eval_body<P, FLUX, BUF>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E, blk, g, ms, mode,
+                                dt, a0, b0, status, gamma_in);
   }
 }
 
@@ -737,6 +770,14 @@ cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const flo
 #endif
 static constexpr int64_t EVAL_GRID = CVW_EVAL_GRID;
 
+// CVW_WIDE_ADDRESSING=1 in the environment selects the 64-bit addressed cell
+// pass for every mesh (the two variants compute bitwise the same results; the
+// switch lets small meshes exercise the path of the > 4 GiB states)
+static bool wide_addressing_forced() {
+  const char* v = std::getenv("CVW_WIDE_ADDRESSING");
+  return v && v[0] == '1';
+}
+
 template <int P, int FLUX>
 static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
                         float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
@@ -744,9 +785,19 @@ static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, co
   const int64_t ntile = (m->E + 15) / 16;
   const int64_t nb = pad8(std::min<int64_t>(ntile, EVAL_GRID));
   const int64_t tpb = (ntile + nb - 1) / nb;
-  hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0, out,
-                     gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, ntile, tpb,
-                     make_cell_geo(m->hx, m->hy, m->he, P), ms, mode, dt, a0, b0, status, gamma_in);
+  // raw-buffer addressing when the state (all variables) and the candidates fit in 32-bit byte offsets
+  constexpr int64_t NV = NVar<FLUX>::value;
+  const bool buf = !wide_addressing_forced() && m->E * m->nloc * NV * 4 < (int64_t(1) << 32) - 4096 &&
+                   m->Nv * m->nk * 4 < (int64_t(1) << 32) - 4096;
+  const CellGeo geo = make_cell_geo(m->hx, m->hy, m->he, P);
+  if (buf)
+    hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX, true>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0,
+                       out, gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, ntile, tpb, geo,
+                       ms, mode, dt, a0, b0, status, gamma_in);
+  else
+    hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX, false>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0,
+                       out, gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, ntile, tpb, geo,
+                       ms, mode, dt, a0, b0, status, gamma_in);
 }
 
 template <int P>

@@ -158,6 +158,45 @@ def test_residual_deterministic_and_gamma_out():
     assert torch.equal(R1, R2)
 
 
+@pytest.mark.parametrize("flux", ["euler", "burgers"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_wide_addressing_path_matches(p, flux, monkeypatch):
+    """The 64-bit addressed cell pass (taken for states over 4 GiB) computes
+    bitwise what the 32-bit buffer-addressed pass computes: residual, gamma
+    and a stage update, forced here on a small mesh."""
+    mesh = synth.quad_mesh(16, 12)
+    if flux == "euler":
+        sp = build_space(mesh, p, 1, 4)
+        U = f32(euler_state(sp, k=6.0))
+        prm = EULER
+    else:
+        sp = build_space(mesh, p, 1)
+        U = f32(rough_scalar(sp, 3))
+        prm = SCALARS["burgers"]
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, 0)
+    Ud = _dev(U)
+    cand = torch.empty((mesh.n_vertices, len(sp.ks)), dtype=torch.float32, device="cuda")
+    cvw.vertex_candidates(gm, cp, Ud, cand, ws)
+
+    def run():
+        R = torch.empty_like(Ud)
+        g = torch.empty(sp.E, dtype=torch.float32, device="cuda")
+        cvw.residual(gm, cp, Ud, R, g, ws)
+        S = torch.empty_like(Ud)
+        cvw.rk_stage(gm, cp, Ud, cand, Ud, S, 1e-4, 0.75, 0.25, ws)
+        torch.cuda.synchronize()
+        return R, g, S
+
+    a = run()
+    monkeypatch.setenv("CVW_WIDE_ADDRESSING", "1")
+    b = run()
+    monkeypatch.delenv("CVW_WIDE_ADDRESSING")
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
 @pytest.mark.parametrize("sensor", ["fixed", "plain"])
 @pytest.mark.parametrize("p", [1, 2, 3])
 def test_rk3_stages_match_oracle(p, sensor):
