@@ -59,9 +59,29 @@ __device__ __forceinline__ f32x16 mma(bf16x8 a, bf16x8 b, f32x16 c) {
 // row of accumulator v for lane group g within a 32-row tile
 __device__ __forceinline__ int acc_row(int v, int g) { return 8 * (v >> 2) + 4 * g + (v & 3); }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf(z) by the rational-exponential approximation of Abramowitz and Stegun,
+// formula 7.1.26 (after Hastings): erf(z) = 1 - t (a1 + a2 t + ... + a5 t^4)
+// exp(-z^2), t = 1 / (1 + p z), z >= 0, |error| <= 1.5e-7 (far below the
+// bfloat16 rounding of the activations).  Also returns exp(-z^2).
+__device__ __forceinline__ float erf_as(float z, float& ez) {
+  const float az = fabsf(z);
+  const float t = frcp(fmaf(0.3275911f, az, 1.0f));
+  float q = fmaf(1.061405429f, t, -1.453152027f);
+  q = fmaf(q, t, 1.421413741f);
+  q = fmaf(q, t, -0.284496736f);
+  q = fmaf(q, t, 0.254829592f);
+  ez = __builtin_amdgcn_exp2f(-1.44269504088896341f * az * az);      // exp(-z^2) = 2^(-z^2 log2 e)
+  const float y = fmaf(-q * t, ez, 1.0f);
+  return z < 0.0f ? -y : y;
+}
+__device__ __forceinline__ float gelu(float x) {
+  float e;
+  return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f, e));
+}
 __device__ __forceinline__ float gelu_prime(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+  float e;                                                            // e = exp(-x^2 / 2)
+  const float ef = erf_as(x * 0.70710678118654752f, e);
+  return fmaf(x * 0.39894228040143268f, e, 0.5f * (1.0f + ef));
 }
 
 // ---------------------------------------------------------------------------
@@ -70,31 +90,34 @@ __device__ __forceinline__ float gelu_prime(float x) {
 __global__ __launch_bounds__(256) void mlp_infer_kernel(const uint16_t* __restrict__ feat, int64_t n, MlpDev W,
                                                         float* __restrict__ gamma) {
   __shared__ float sb1[MLP_HID], sb2[MLP_HID], sw3[MLP_HID];
+  // the weight operands of every lane, fragment-major (14 fragments x 64 lanes):
+  // read per tile from LDS rather than held in registers
+  __shared__ u32x4 sA[14][64];
   for (int t = threadIdx.x; t < MLP_HID; t += blockDim.x) {
     sb1[t] = W.b1[t];
     sb2[t] = W.b2[t];
     sw3[t] = bf16_value(W.w3[t]);
   }
+  for (int i = threadIdx.x; i < 14 * 64; i += blockDim.x) {
+    const int f = i >> 6, l = i & 63, cl = l & 31, gl = l >> 5;
+    bf16x8 a;
+    if (f < 6) {
+      const int ht = f / 3, kb = f % 3;
+      a = load8(W.W1t + (32 * ht + cl) * MLP_IN + 16 * kb + 8 * gl);
+    } else {
+      const int ht = (f - 6) >> 2, st = ((f - 6) >> 1) & 1, kb = (f - 6) & 1;
+      const uint16_t* row = W.W2t + (32 * ht + cl) * MLP_HID + 32 * st + 16 * kb + 4 * gl;
+      a = load4x2(row, row + 8);
+    }
+    sA[f][l] = __builtin_bit_cast(u32x4, a);
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = lane & 31, g = lane >> 5;
-  bf16x8 A1[2][3], A2[2][2][2];
-#pragma unroll
-  for (int ht = 0; ht < 2; ++ht)
-#pragma unroll
-    for (int kb = 0; kb < 3; ++kb) A1[ht][kb] = load8(W.W1t + (32 * ht + c) * MLP_IN + 16 * kb + 8 * g);
-#pragma unroll
-  for (int ht = 0; ht < 2; ++ht)
-#pragma unroll
-    for (int st = 0; st < 2; ++st)
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb) {
-        const uint16_t* row = W.W2t + (32 * ht + c) * MLP_HID + 32 * st + 16 * kb + 4 * g;
-        A2[ht][st][kb] = load4x2(row, row + 8);
-      }
   const float b3 = W.b3[0];
   const int64_t ntiles = (n + 31) / 32;
   for (int64_t t = blockIdx.x * 4LL + wave; t < ntiles; t += static_cast<int64_t>(gridDim.x) * 4) {
+    asm volatile("" ::: "memory");              // keeps the LDS weight reads in the loop
     const int64_t cell = t * 32 + c;
     const bool ok = cell < n;
     bf16x8 B1[3];
@@ -105,7 +128,7 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const uint16_t* __restri
     for (int ht = 0; ht < 2; ++ht) {
       C1[ht] = zero16();
 #pragma unroll
-      for (int kb = 0; kb < 3; ++kb) C1[ht] = mma(A1[ht][kb], B1[kb], C1[ht]);
+      for (int kb = 0; kb < 3; ++kb) C1[ht] = mma(__builtin_bit_cast(bf16x8, sA[3 * ht + kb][lane]), B1[kb], C1[ht]);
     }
     bf16x8 B2[2][2];
 #pragma unroll
@@ -127,7 +150,8 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const uint16_t* __restri
 #pragma unroll
       for (int st = 0; st < 2; ++st)
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb) C2 = mma(A2[ht][st][kb], B2[st][kb], C2);
+        for (int kb = 0; kb < 2; ++kb)
+          C2 = mma(__builtin_bit_cast(bf16x8, sA[6 + 4 * ht + 2 * st + kb][lane]), B2[st][kb], C2);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int r = 32 * ht + acc_row(v, g);
