@@ -32,6 +32,10 @@
  *   Single (CVW_F32) or double (CVW_F64) precision as cvw_params.dtype says.
  * - Results are deterministic: no floating-point atomics are used; every
  *   reduction runs in a fixed order.
+ * - Environment: CVW_WIDE_ADDRESSING=1 makes the DG quadrilateral cell pass
+ *   use 64-bit addresses for every mesh (by default it uses 32-bit buffer
+ *   offsets while the state and the vertex candidates each fit in 4 GiB);
+ *   both give bitwise the same results.  Read at every launch.
  */
 #ifndef CVW_H
 #define CVW_H
