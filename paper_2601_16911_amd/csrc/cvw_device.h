@@ -141,6 +141,49 @@ __device__ __forceinline__ void rdot4x2(float x, const float (&c)[4], const floa
       : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]));
 }
 
+// Degree-1 and degree-2 variants over the lanes / rows that hold nodes:
+// quad lanes 0..p; for p = 1 the rows 0, 1 are reached by the rotations 4
+// and 12 (rotation 8 brings only unused rows).
+__device__ __forceinline__ float qdot2(float x, const float (&c)[4]) {
+  float a;
+  asm("s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %1, %2 quad_perm:[0,0,0,0]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,1,1,1]" CVW_DPP_TAIL
+      : "=&v"(a) : "v"(x), "v"(c[0]), "v"(c[1]));
+  return a;
+}
+__device__ __forceinline__ float qdot3(float x, const float (&c)[4]) {
+  float a;
+  asm("s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %1, %2 quad_perm:[0,0,0,0]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,1,1,1]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %4 quad_perm:[2,2,2,2]" CVW_DPP_TAIL
+      : "=&v"(a) : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]));
+  return a;
+}
+__device__ __forceinline__ float rdot3p1(float x, const float (&c)[4]) {
+  float a;
+  asm("v_mul_f32 %0, %1, %2\n\t"
+      "s_nop 0\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 row_ror:4" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %4 row_ror:12" CVW_DPP_TAIL
+      : "=&v"(a) : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[3]));
+  return a;
+}
+// sum over the node lanes of the quad (p + 1 of them)
+template <int P>
+__device__ __forceinline__ float qdotp(float x, const float (&c)[4]) {
+  if constexpr (P == 1) return qdot2(x, c);
+  else if constexpr (P == 2) return qdot3(x, c);
+  else return qdot4(x, c);
+}
+// sum over the node rows of the column
+template <int P>
+__device__ __forceinline__ float rdotp(float x, const float (&c)[4]) {
+  if constexpr (P == 1) return rdot3p1(x, c);
+  else return rdot4(x, c);
+}
+
 // Raw buffer access (gfx9 resource word 3 = 0x00020000: 32-bit data format):
 // a uniform base in scalar registers, a 32-bit per-lane byte offset and a
 // uniform 32-bit byte offset, no 64-bit address arithmetic per lane.  Offsets

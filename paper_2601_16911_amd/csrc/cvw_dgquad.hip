@@ -484,66 +484,21 @@ __device__ __forceinline__ void dgq_eval_body(
       r[v] = qdot4(WFx, L.TX) + rdot4(WFy, L.TY);
     }
   } else {
+    // p < 3: the same fused contractions over the whole quad / column; the
+    // lane tables are zero beyond p and so are the values of the unused lanes
+    const float Wqx = Wq * sx, Wqy = Wq * sy, cfx = coef * sx, cfy = coef * sy;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const float uvv = nd ? uv[v] : 0.0f;
-    // broadcasts of the own row (x direction) and column (y direction)
-    float rowv[MAXP + 1], colv[4];
-#pragma unroll
-    for (int i = 0; i <= P; ++i)
-      rowv[i] = (i == 0) ? qbcast<0>(uvv) : (i == 1) ? qbcast<1>(uvv) : (i == 2) ? qbcast<2>(uvv) : qbcast<3>(uvv);
-    colv[0] = uvv;
-    colv[1] = rrot<1>(uvv);
-    colv[2] = rrot<2>(uvv);
-    colv[3] = rrot<3>(uvv);
-    float gx = 0.0f, gy = 0.0f;
-    if constexpr (P == 3) {
-      float sXs = 0.0f, sYs = 0.0f;
-#pragma unroll
-      for (int i = 0; i <= P; ++i) {
-        gx = fmaf(L.CX1[i], rowv[i], gx);
-        sXs = fmaf(L.OX[i], rowv[i], sXs);
-      }
-#pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) {
-        gy = fmaf(L.CY1[s2], colv[s2], gy);
-        sYs = fmaf(L.OY[s2], colv[s2], sYs);
-      }
-      tW[v] = sXs;                // x-side trace (W on a = 0, E otherwise)
-      tS[v] = sYs;                // y-side trace (S in rows 0, 1; N in rows 2, 3)
-    } else {
-      float sW = 0.0f, sE = 0.0f, sS = 0.0f, sN = 0.0f;
-#pragma unroll
-      for (int i = 0; i <= P; ++i) {
-        gx = fmaf(L.CX1[i], rowv[i], gx);
-        sW = fmaf(tab.B[0][i], rowv[i], sW);
-        sE = fmaf(tab.B[1][i], rowv[i], sE);
-      }
-#pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) {
-        gy = fmaf(L.CY1[s2], colv[s2], gy);
-        sS = fmaf(L.BY0[s2], colv[s2], sS);
-        sN = fmaf(L.BY1[s2], colv[s2], sN);
-      }
-      tW[v] = sW;
-      tE[v] = sE;
-      tS[v] = sS;
-      tN[v] = sN;
+    for (int v = 0; v < NV; ++v) {
+      const float uvv = nd ? uv[v] : 0.0f;
+      const float gx = qdotp<P>(uvv, L.CX1), gy = rdotp<P>(uvv, L.CY1);
+      tW[v] = qdotp<P>(uvv, L.BX0);
+      tE[v] = qdotp<P>(uvv, L.BX1);
+      tS[v] = rdotp<P>(uvv, L.BY0);
+      tN[v] = rdotp<P>(uvv, L.BY1);
+      const float WFx = Wqx * (cfx * gx - fx[v]);
+      const float WFy = Wqy * (cfy * gy - fy[v]);
+      r[v] = qdotp<P>(WFx, L.TX) + rdotp<P>(WFy, L.TY);
     }
-    const float WFx = Wq * (coef * sx * gx - fx[v]);
-    const float WFy = Wq * (coef * sy * gy - fy[v]);
-    float acc = 0.0f;
-#pragma unroll
-    for (int c = 0; c <= P; ++c) {
-      const float wv = (c == 0) ? qbcast<0>(WFx) : (c == 1) ? qbcast<1>(WFx) : (c == 2) ? qbcast<2>(WFx) : qbcast<3>(WFx);
-      acc = fmaf(L.TX[c], wv, acc);
-    }
-    float accy = L.TY[0] * WFy;
-    accy = fmaf(L.TY[1], rrot<1>(WFy), accy);
-    accy = fmaf(L.TY[2], rrot<2>(WFy), accy);
-    accy = fmaf(L.TY[3], rrot<3>(WFy), accy);
-    r[v] = sx * acc + sy * accy;
-  }
   }
 
   // ---- interface terms -------------------------------------------------------

@@ -185,6 +185,10 @@ static void fill_lane_tables(LaneRec* R, const TensorTables& T, int p) {
     L.misc[5] = T.w[b];
     L.misc[6] = T.xi[a];
     L.misc[7] = T.xi[b];
+    for (int i = 0; i < 4; ++i) {
+      L.BX0[i] = T.B[0][i];
+      L.BX1[i] = T.B[1][i];
+    }
     if (p == 3) {
       const bool xf = (a == 0 || a == 3);
       const bool inner = !xf && (b == 1 || b == 2);

@@ -63,7 +63,8 @@ struct alignas(16) LaneRec {
   int slot;          // neighbour slot (S 0, E 1, N 2, W 3)
   int noff, nstep;   // neighbour node index of the normal line's first node, and its stride
   int srcS, srcN;    // lanes of the row that hold the S / N flux of column a
-  int pad_[7];       // record stride 108 dwords: the 16 lanes of a row read distinct LDS banks
+  float BX0[4], BX1[4];   // l_i(-1), l_i(+1) (x-side traces of p < 3; zero beyond p)
+  int pad_[7];       // record stride 116 dwords: 8 consecutive lanes read distinct LDS banks
 };
 
 // Reference tables of a tensor-product CG element (Gauss-Lobatto nodes) of
