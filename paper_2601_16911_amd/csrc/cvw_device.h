@@ -109,6 +109,30 @@ __device__ __forceinline__ void qdot4x2(float x, const float (&c)[4], const floa
       : "=&v"(a), "=&v"(b)
       : "v"(x), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]));
 }
+// Degree-1 packed cells (node (a, b) on lane a + 2 b of a quad): the pair
+// along x, c0 x(0, b) + c1 x(1, b), and the pair along y, c0 x(a, 0) + c1 x(a, 1).
+__device__ __forceinline__ float qx2(float x, float c0, float c1) {
+  float r;
+  asm("s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %1, %2 quad_perm:[0,0,2,2]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,1,3,3]" CVW_DPP_TAIL
+      : "=&v"(r) : "v"(x), "v"(c0), "v"(c1));
+  return r;
+}
+__device__ __forceinline__ float qy2(float x, float c0, float c1) {
+  float r;
+  asm("s_nop 1\n\t"
+      "v_mul_f32_dpp %0, %1, %2 quad_perm:[0,1,0,1]" CVW_DPP_TAIL "\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 quad_perm:[2,3,2,3]" CVW_DPP_TAIL
+      : "=&v"(r) : "v"(x), "v"(c0), "v"(c1));
+  return r;
+}
+__device__ __forceinline__ float quad_max(float x) {
+  x = fmaxf(x, dpp<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x));
+  x = fmaxf(x, dpp<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x));
+  return x;
+}
+
 // r + c0 x(lane 0 of the quad) + c3 x(lane 3 of the quad)
 __device__ __forceinline__ float qfma03(float r, float x, float c0, float c3) {
   asm("s_nop 1\n\t"

@@ -645,6 +645,194 @@ __device__ __forceinline__ void dgq_eval_body(
     atomicOr(status, (m1 ? ST_NONFINITE : 0u) | (m2 ? ST_NONPOSITIVE : 0u));
 }
 
+// Degree 1, four cells per 16-lane row: cell (tid >> 2) of the 64-cell tile
+// blk, node (a, b) = (l & 1, l >> 1) on lane l = tid & 3 of its quad, so every
+// exchange inside a cell is a quad permutation.  Each lane evaluates one point
+// of an x face (side a, point b) and one of a y face (side b, point a).  The
+// same steps as the 16-lane body: derivatives of the sensor field (float64),
+// gamma_e (eq. gamma; the candidates' first derivatives are constant, so their
+// centred expansion is the candidate itself), lambda_e, alpha_q, volume and
+// interface terms, stage update.
+template <int FLUX, bool BUF = false>
+__device__ __forceinline__ void dgq_eval_body_p1(
+    const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
+    float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
+    const int32_t* __restrict__ cell_vtx, const int32_t* __restrict__ nbr, const LaneRec1* sl, int64_t E,
+    int64_t blk, const CellGeo& G, const MethodScalars& ms, int mode, float dt, float a0, float b0,
+    uint32_t* __restrict__ status, const float* __restrict__ gamma_in = nullptr) {
+  constexpr int P = 1, NLOC = 4, NK = 2;
+  constexpr int NV = NVar<FLUX>::value;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int l = tid & 3;
+  const int a = l & 1, b = l >> 1;
+  const int64_t e = blk * 64 + (tid >> 2);
+  if (e >= E) return;                          // whole quads leave together
+  const LaneRec1& L = sl[l];
+  const float sx = G.sx, sy = G.sy, he2 = G.he2;
+  const float Wq = L.wa * L.wb * G.area4;
+  const int64_t stride = E * NLOC;
+  [[maybe_unused]] const uint32_t offn = BUF ? static_cast<uint32_t>((e * NLOC + l) * 4) : 0u;
+  [[maybe_unused]] const uint32_t sbytes = BUF ? static_cast<uint32_t>(stride * 4) : 0u;
+
+  float uv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if constexpr (BUF)
+      uv[v] = buf_load(buf_rsrc(u, sbytes * NV), offn, v * sbytes);
+    else
+      uv[v] = u[v * stride + e * NLOC + l];
+  }
+  // neighbours across the lane's x and y face points, fetched early
+  const int32_t enx = nbr[e * 4 + L.slotx], eny = nbr[e * 4 + L.sloty];
+  const bool plain = (ms.sensor_kind == CVW_SENSOR_PLAIN);
+  float myc[NK] = {};
+  if (plain) {                                 // lane l fetches vertex l (eq. taylorcand output)
+    const int64_t vid = cell_vtx[e * 4 + l];
+#pragma unroll
+    for (int t = 0; t < NK; ++t) myc[t] = cand[vid * NK + t];
+  }
+
+  // first derivatives of the sensor field at the own node, float64, relative
+  // to node (0, 0) of the cell
+  float Du[NK] = {};
+  if (plain || ms.sc_on) {
+    double rho = static_cast<double>(uv[0]);
+    rho -= qbcastd<0>(rho);
+    constexpr int X0 = 0 | (0 << 2) | (2 << 4) | (2 << 6), X1 = 1 | (1 << 2) | (3 << 4) | (3 << 6);
+    constexpr int Y0 = 0 | (1 << 2) | (0 << 4) | (1 << 6), Y1 = 2 | (3 << 2) | (2 << 4) | (3 << 6);
+    const double dx = fma(L.DX[1], dppd<X1>(rho), L.DX[0] * dppd<X0>(rho));
+    const double dy = fma(L.DY[1], dppd<Y1>(rho), L.DY[0] * dppd<Y0>(rho));
+    Du[0] = static_cast<float>(dx) * sx;
+    Du[1] = static_cast<float>(dy) * sy;
+  }
+  const float sw = order_weighted_dot<P>(Du, Du, he2);
+
+  float gam;
+  if (ms.sensor_kind == CVW_SENSOR_FIXED) {
+    gam = ms.fixed_gamma;
+  } else if (ms.sensor_kind == CVW_SENSOR_LEARNED) {
+    gam = gamma_in[e];
+  } else {
+    const float n2 = quad_sum(Wq * sw);
+    // the candidates' derivatives are constant: the centred expansion is the
+    // candidate data itself, its semi-norm |e| (c_x^2 + c_y^2)
+    const float b2v = 4.0f * G.area4 * centred_seminorm_mean<P>(myc, G.mx2, G.my2, G.qx4, G.qy4, he2);
+    float w0, wv;
+    if (ms.fast_exp) {
+      const float d0 = ms.eps_c + fsqrt(n2), dv = ms.eps_c + fsqrt(b2v);
+      w0 = (1.0f - 4.0f * ms.lin_w) * frcp(d0 * d0);
+      wv = ms.lin_w * frcp(dv * dv);
+    } else {
+      w0 = (1.0f - 4.0f * ms.lin_w) * powf(ms.eps_c + powf(sqrtf(n2), ms.q_beta), -ms.r);
+      wv = ms.lin_w * powf(ms.eps_c + powf(sqrtf(b2v), ms.q_beta), -ms.r);
+    }
+    const float wq = quad_sum(wv);
+    const float oinv = frcp(w0 + wq);
+    const float whv = wv * oinv;
+    const float wrest = wq * oinv;
+    float dl[NK];
+#pragma unroll
+    for (int t = 0; t < NK; ++t) dl[t] = fmaf(wrest, Du[t], -quad_sum(whv * myc[t]));
+    const float d2 = quad_sum(Wq * order_weighted_dot<P>(dl, dl, he2));
+    if (n2 > 0.0f) {
+      const float mr = fminf(1.0f, fsqrt(d2 / n2));      // n2 may be subnormal: IEEE division
+      gam = 1.0f - (ms.fast_exp ? mr : powf(mr, ms.q_sensor));
+    } else {
+      gam = 1.0f;
+    }
+  }
+
+  const float lam = (ms.lam_g > 0.0f) ? ms.lam_g : quad_max(wave_speed<FLUX>(ms, uv, 0.0f, 0.0f));
+  const float nu = lam * G.nuf;
+  const float atil = fsqrt(he2 * sw);
+  const float g2 = Du[0] * Du[0] + Du[1] * Du[1];
+  const float fq = (1.0f - gam) * g2;
+  const float S = quad_sum(Wq * fq);
+  const float T = quad_sum(Wq * atil * fq);
+  const bool sc_active = ms.sc_on && (static_cast<double>(gam) < ms.c_gammad) && (S > 0.0f) && (T > 0.0f);
+  const float alpha = sc_active ? atil * (S / T) : 1.0f;      // T may be subnormal: IEEE division
+
+  if (mode == MODE_SENSOR) {
+    if (l == 0) gamma_out[e] = gam;
+    if (alpha_out) alpha_out[e * NLOC + l] = alpha;
+    return;
+  }
+  if (gamma_out && l == 0) gamma_out[e] = gam;
+
+  // ---- volume terms and own traces ------------------------------------------
+  const float coef = nu * (1.0f - gam) * alpha;
+  const float Wqx = Wq * sx, Wqy = Wq * sy, cfx = coef * sx, cfy = coef * sy;
+  float fx[NV], fy[NV], r[NV], tX[NV], tY[NV];
+  phys_flux<FLUX>(ms, uv, 0.0f, 0.0f, fx, fy);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const float gx = qx2(uv[v], L.CX1[0], L.CX1[1]), gy = qy2(uv[v], L.CY1[0], L.CY1[1]);
+    tX[v] = qx2(uv[v], L.OX[0], L.OX[1]);
+    tY[v] = qy2(uv[v], L.OY[0], L.OY[1]);
+    const float WFx = Wqx * (cfx * gx - fx[v]);
+    const float WFy = Wqy * (cfy * gy - fy[v]);
+    r[v] = qx2(WFx, L.TX[0], L.TX[1]) + qy2(WFy, L.TY[0], L.TY[1]);
+  }
+
+  // ---- interface terms: x face (side a, point b) and y face (side b, point a)
+  float px[NV], py[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int64_t ox = v * stride + static_cast<int64_t>(enx) * NLOC + 2 * b;
+    const int64_t oy = v * stride + static_cast<int64_t>(eny) * NLOC + a;
+    if constexpr (BUF) {
+      const __amdgpu_buffer_rsrc_t ru = buf_rsrc(u, sbytes * NV);
+      const uint32_t bx = static_cast<uint32_t>((static_cast<int64_t>(enx) * NLOC + 2 * b) * 4);
+      const uint32_t by = static_cast<uint32_t>((static_cast<int64_t>(eny) * NLOC + a) * 4);
+      px[v] = fmaf(L.FX[1], buf_load(ru, bx + 4u, v * sbytes), L.FX[0] * buf_load(ru, bx, v * sbytes));
+      py[v] = fmaf(L.FY[1], buf_load(ru, by + 8u, v * sbytes), L.FY[0] * buf_load(ru, by, v * sbytes));
+    } else {
+      px[v] = fmaf(L.FX[1], u[ox + 1], L.FX[0] * u[ox]);
+      py[v] = fmaf(L.FY[1], u[oy + 2], L.FY[0] * u[oy]);
+    }
+  }
+  float fsx[NV], fsy[NV];
+  num_flux<FLUX>(ms, tX, px, L.nx, 0.0f, 0.0f, 0.0f, fsx);
+  num_flux<FLUX>(ms, tY, py, 0.0f, L.ny, 0.0f, 0.0f, fsy);
+  const float wx = L.wb * G.hhy, wy = L.wa * G.hhx;      // face weights of the two points
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    // W / E fluxes of the own row from the lanes (0, b) / (1, b), S / N fluxes
+    // of the own column from the lanes (a, 0) / (a, 1)
+    r[v] += qx2(wx * fsx[v], L.lift[0], L.lift[1]) + qy2(wy * fsy[v], L.lift[2], L.lift[3]);
+  }
+
+  // ---- output -------------------------------------------------------------------
+  const float invWq = frcp(Wq);
+  bool nonfinite = false;
+  const bool inadmissible = !state_admissible<FLUX>(ms, uv);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    float val;
+    if (mode == MODE_RESIDUAL) {
+      val = r[v];
+    } else {
+      float base = 0.0f;
+      if (a0 != 0.0f) {
+        if constexpr (BUF)
+          base = a0 * buf_load(buf_rsrc(u0, sbytes * NV), offn, v * sbytes);
+        else
+          base = a0 * u0[v * stride + e * NLOC + l];
+      }
+      val = base + b0 * (uv[v] + dt * (-r[v] * invWq));
+    }
+    nonfinite = nonfinite || !isfinite(val);
+    if constexpr (BUF)
+      buf_store(val, buf_rsrc(out, sbytes * NV), offn, v * sbytes);
+    else
+      out[v * stride + e * NLOC + l] = val;
+  }
+  const unsigned long long m1 = __ballot(nonfinite), m2 = __ballot(inadmissible);
+  if ((m1 | m2) && (tid & 63) == __builtin_ctzll(m1 | m2))
+    atomicOr(status, (m1 ? ST_NONFINITE : 0u) | (m2 ? ST_NONPOSITIVE : 0u));
+}
+
 // 256-thread blocks: all loads in flight before the LDS stores
 __device__ __forceinline__ void load_lane_tables(const LaneRec* __restrict__ lanes, LaneRec* sl) {
   const float4* src = reinterpret_cast<const float4*>(lanes);
@@ -690,8 +878,13 @@ __global__ __launch_bounds__(256) CVW_EVAL_WPE void dgq_eval_kernel(
     asm volatile("" : "+s"(g.hx), "+s"(g.hy), "+s"(g.he), "+s"(g.sx), "+s"(g.sy), "+s"(g.he2), "+s"(g.mx2),
                  "+s"(g.my2), "+s"(g.qx4), "+s"(g.qy4), "+s"(g.area4), "+s"(g.hhx), "+s"(g.hhy), "+s"(g.nuf)
                  :: "memory");
-    dgq_eval_body<P, FLUX, BUF>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E, blk, g, ms, mode,
-                                dt, a0, b0, status, gamma_in);
+    if constexpr (P == 1)
+      dgq_eval_body_p1<FLUX, BUF>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr,
+                                  reinterpret_cast<const LaneRec1*>(sl), E, blk, g, ms, mode, dt, a0, b0, status,
+                                  gamma_in);
+    else
+      dgq_eval_body<P, FLUX, BUF>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E, blk, g, ms,
+                                  mode, dt, a0, b0, status, gamma_in);
   }
 }
 
@@ -737,7 +930,7 @@ template <int P, int FLUX>
 static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
                         float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
                         float a0, float b0, const float* gamma_in, hipStream_t s) {
-  const int64_t ntile = (m->E + 15) / 16;
+  const int64_t ntile = (m->E + cells_per_tile(P) - 1) / cells_per_tile(P);
   const int64_t nb = pad8(std::min<int64_t>(ntile, EVAL_GRID));
   const int64_t tpb = (ntile + nb - 1) / nb;
   // raw-buffer addressing when the state (all variables) and the candidates fit in 32-bit byte offsets
@@ -1031,8 +1224,13 @@ __global__ __launch_bounds__(256) void batch_eval_kernel(const BatchInst* __rest
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int2 w = items[it];
     const BatchInst& I = inst[w.x];
-    dgq_eval_body<P, FLUX>(I.u_in[stage], I.u, I.u_out[stage], nullptr, nullptr, I.cand, I.cell_vtx, I.nbr, sl, tab,
-                           I.E, w.y, I.g, I.ms, MODE_STAGE, I.dt, a0, b0, I.status);
+    if constexpr (P == 1)
+      dgq_eval_body_p1<FLUX>(I.u_in[stage], I.u, I.u_out[stage], nullptr, nullptr, I.cand, I.cell_vtx, I.nbr,
+                             reinterpret_cast<const LaneRec1*>(sl), I.E, w.y, I.g, I.ms, MODE_STAGE, I.dt, a0, b0,
+                             I.status);
+    else
+      dgq_eval_body<P, FLUX>(I.u_in[stage], I.u, I.u_out[stage], nullptr, nullptr, I.cand, I.cell_vtx, I.nbr, sl,
+                             tab, I.E, w.y, I.g, I.ms, MODE_STAGE, I.dt, a0, b0, I.status);
   }
 }
 

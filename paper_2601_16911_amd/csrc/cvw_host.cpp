@@ -158,7 +158,46 @@ static void fill_tensor_tables(TensorTables& T, int p, bool lobatto) {
   }
 }
 
+static void fill_lane_tables1(LaneRec* R, const TensorTables& T) {
+  std::memset(R, 0, 16 * sizeof(LaneRec));
+  LaneRec1 r[4];
+  std::memset(r, 0, sizeof(r));
+  for (int l = 0; l < 4; ++l) {
+    const int a = l & 1, b = l >> 1;
+    LaneRec1& L = r[l];
+    for (int i = 0; i < 2; ++i) {
+      L.CX1[i] = static_cast<float>(T.Dd[1][a][i]);
+      L.CY1[i] = static_cast<float>(T.Dd[1][b][i]);
+      L.TX[i] = static_cast<float>(T.Dd[1][i][a]);
+      L.TY[i] = static_cast<float>(T.Dd[1][i][b]);
+      L.OX[i] = T.B[a][i];
+      L.OY[i] = T.B[b][i];
+      L.FX[i] = T.B[1 - a][i];
+      L.FY[i] = T.B[1 - b][i];
+      L.DX[i] = T.Dd[1][a][i];
+      L.DY[i] = T.Dd[1][b][i];
+    }
+    L.lift[0] = T.B[0][a];
+    L.lift[1] = T.B[1][a];
+    L.lift[2] = T.B[0][b];
+    L.lift[3] = T.B[1][b];
+    L.wa = T.w[a];
+    L.wb = T.w[b];
+    L.xq = T.xi[a];
+    L.yq = T.xi[b];
+    L.nx = a == 0 ? -1.0f : 1.0f;
+    L.ny = b == 0 ? -1.0f : 1.0f;
+    L.slotx = a == 0 ? 3 : 1;
+    L.sloty = b == 0 ? 0 : 2;
+  }
+  std::memcpy(static_cast<void*>(R), r, sizeof(r));
+}
+
 static void fill_lane_tables(LaneRec* R, const TensorTables& T, int p) {
+  if (p == 1) {
+    fill_lane_tables1(R, T);
+    return;
+  }
   std::memset(R, 0, 16 * sizeof(LaneRec));
   for (int q = 0; q < 16; ++q) {
     const int a = q & 3, b = q >> 2;
@@ -1432,7 +1471,8 @@ cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** ou
     // estimated cost of a block: proportional to the nodes per cell
     const double c = static_cast<double>(m->nloc);
     const int nvb = static_cast<int>((m->Nv + VTX_PER_BLOCK - 1) / VTX_PER_BLOCK);
-    const int neb = static_cast<int>((m->E + 15) / 16);
+    const int cpt = cells_per_tile(m->degree);
+    const int neb = static_cast<int>((m->E + cpt - 1) / cpt);
     for (int k = 0; k < nvb; ++k) vitems[m->degree].push_back({c, i, k});
     for (int k = 0; k < neb; ++k) eitems[m->degree][prm->flux].push_back({c, i, k});
   }

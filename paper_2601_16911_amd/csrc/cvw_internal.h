@@ -19,6 +19,9 @@ enum Mode : int { MODE_SENSOR = 0, MODE_RESIDUAL = 1, MODE_STAGE = 2 };
 
 // vertices per 256-thread block of the DG quadrilateral vertex pass
 constexpr int VTX_PER_BLOCK = 256;
+// cells per 256-thread tile of the DG quadrilateral cell pass: one 16-lane row
+// per cell, four cells per row at degree 1
+constexpr int cells_per_tile(int p) { return p == 1 ? 64 : 16; }
 
 constexpr int MAXP = 3;   // highest degree of the GPU path
 
@@ -66,6 +69,24 @@ struct alignas(16) LaneRec {
   float BX0[4], BX1[4];   // l_i(-1), l_i(+1) (x-side traces of p < 3; zero beyond p)
   int pad_[7];       // record stride 116 dwords: 8 consecutive lanes read distinct LDS banks
 };
+
+// Per-lane record of the degree-1 DG quadrilateral cell kernel, which packs
+// four cells into a 16-lane row: node (a, b) = (l & 1, l >> 1) on lane l of
+// the cell's quad.  Each lane takes one point of an x face (side a, point b)
+// and one of a y face (side b, point a).  The four records are stored at the
+// start of the mesh's lane-table array (which holds 16 LaneRec).
+struct alignas(16) LaneRec1 {
+  float CX1[2], CY1[2];    // l_i'(xi_a), l_j'(xi_b)
+  float TX[2], TY[2];      // l_a'(xi_c), l_b'(xi_d)
+  float OX[2], OY[2];      // own traces on the sides a and b: l_i(-1 or +1), l_j(-1 or +1)
+  float FX[2], FY[2];      // the neighbours' traces across those faces (their facing sides)
+  float lift[4];           // l_a(-1), l_a(+1), l_b(-1), l_b(+1)
+  float wa, wb, xq, yq;    // Gauss weights and reference coordinates of the node
+  float nx, ny;            // outward normals of the x face (side a) and the y face (side b)
+  int slotx, sloty;        // their neighbour slots (S 0, E 1, N 2, W 3)
+  double DX[2], DY[2];     // float64 l_i'(xi_a), l_j'(xi_b)
+};
+static_assert(4 * sizeof(LaneRec1) <= 16 * sizeof(LaneRec), "degree-1 lane records fit the lane-table array");
 
 // Reference tables of a tensor-product CG element (Gauss-Lobatto nodes) of
 // degree p <= 2 for the bilinear-map path: Gauss volume rule (p+1 points),
