@@ -186,7 +186,7 @@ def bench_learned(torch, cvw, gm, prm, U, dt, steps: int):
             "status_flags": [cvw.poll_status(gm, wsp), cvw.poll_status(gm, wsl)]}
 
 
-def bench_ensemble(torch, cvw, steps: int):
+def bench_ensemble(torch, cvw, steps: int, tune: bool = True):
     """The 64-instance DG ensemble (periodic unit squares, n in [64, 512], p in
     {1, 2, 3}, advection or Burgers, seeded), all instances stepped together by
     the batched stage, graph-captured and eager."""
@@ -201,8 +201,18 @@ def bench_ensemble(torch, cvw, steps: int):
         dofs += U.size
     b = cvw.Batch(items)
     ws = b.alloc_workspace()
+    grid = 0
+    if tune:
+        from paper_2601_16911_amd import autotune
+        entry = autotune.load_cache().get(autotune.batch_key(b))
+        if entry is not None:
+            grid = int(entry["grid"])
+            b.set_grid(grid)
+        else:
+            grid = autotune.tune_batch(b, ws)
     out = {"workload": "64-instance DG ensemble, periodic n x n quads (n in [64, 512]), p in {1,2,3}, "
-                       "advection / Burgers, SSP-RK3", "instances": len(items), "dofs": dofs, "steps": steps}
+                       "advection / Burgers, SSP-RK3", "instances": len(items), "dofs": dofs, "steps": steps,
+           "blocks": grid if grid else "one per item"}
     for name, graph in (("graph", True), ("eager", False)):
         t = _timed(torch, stream, lambda: b.step(steps, ws, use_graph=graph), 1) / steps
         out[name] = {"value": 3.0 * dofs / t, "unit": "DOF-updates/s", "ms_per_step": t * 1e3}
@@ -250,6 +260,8 @@ def main():
                     help="skip the side measurements (ensemble batch, triangles)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in launch shapes (no autotuner launches before the timed region)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is benchmarked on one MI355X; "
@@ -282,6 +294,16 @@ def main():
     lam_max = float((np.hypot(mx, my) / rho + np.sqrt(1.4 * pres / rho)).max())
     dt = 0.1 * (1.0 / n) / ((2 * p + 1) * lam_max)
     stream = torch.cuda.current_stream()
+
+    # launch shape of the cell pass: the autotuner's cached choice, else tuned
+    # here (outside the timed region; results do not depend on it)
+    grid = 0
+    if not args.no_tune:
+        from paper_2601_16911_amd import autotune
+        grid = autotune.apply_cached(gm, n_var=nv)
+        if grid is None:
+            cvw.vertex_candidates(gm, cp, U, cand, ws)
+            grid = autotune.tune_mesh(gm, cp, U, cand, ws, n_var=nv)
 
     ev = []
 
@@ -349,7 +371,8 @@ def main():
         "config": {"workload": f"2D Euler DG Q3, periodic {n}x{n} quads ({E} cells, {ndof * nv} DOFs), "
                                "four-quadrant data with interfaces smoothed over ~2 cells, plain CV-WENO sensor + SC "
                                "quadrature, SSP-RK3", "cells": E, "degree": p, "n_var": nv,
-                   "dofs": ndof * nv, "step": "one SSP-RK3 step = 3 x (vertex pass + fused cell pass)"},
+                   "dofs": ndof * nv, "step": "one SSP-RK3 step = 3 x (vertex pass + fused cell pass)",
+                   "cell_pass_blocks": grid if grid else "default"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "dgq_eval_kernel<3, EULER> (fused cell pass, stage mode)",
@@ -372,7 +395,7 @@ def main():
         torch.cuda.empty_cache()
         out["learned_sensor"] = bench_learned(torch, cvw, gm, prm, U, dt, 5)
         torch.cuda.empty_cache()
-        out["ensemble_batch"] = bench_ensemble(torch, cvw, 10)
+        out["ensemble_batch"] = bench_ensemble(torch, cvw, 10, tune=not args.no_tune)
         torch.cuda.empty_cache()
         out["triangles_kpp"] = bench_triangles(torch, cvw, 5)
     if not args.no_cpu_baseline:

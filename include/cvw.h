@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 2
+#define CVW_ABI_VERSION 3
 
 typedef enum {
   CVW_OK = 0,
@@ -147,6 +147,12 @@ const char* cvw_last_error(void);
 cvw_status cvw_mesh_build(const cvw_mesh_desc* desc, cvw_mesh** out);
 void cvw_mesh_destroy(cvw_mesh* mesh);
 cvw_status cvw_mesh_get_info(const cvw_mesh* mesh, cvw_mesh_info* info);
+/* Launch shape of the DG quadrilateral cell pass on this mesh: the number of
+ * 256-thread blocks per launch, each walking a contiguous run of cell tiles
+ * (blocks <= 0: the built-in default).  Results do not depend on it; it is the
+ * knob of the host autotuner (paper_2601_16911_amd/autotune.py).  Not
+ * thread-safe against concurrent evaluations on the same mesh. */
+cvw_status cvw_mesh_set_grid(cvw_mesh* mesh, int blocks);
 /* Copy one host-side connectivity array (see CVW_EXPORT_*) into host_dst; EINVAL
  * if bytes is not exactly its size. */
 cvw_status cvw_mesh_export(const cvw_mesh* mesh, int which, void* host_dst, size_t bytes);

@@ -931,7 +931,7 @@ static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, co
                         float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
                         float a0, float b0, const float* gamma_in, hipStream_t s) {
   const int64_t ntile = (m->E + cells_per_tile(P) - 1) / cells_per_tile(P);
-  const int64_t nb = pad8(std::min<int64_t>(ntile, EVAL_GRID));
+  const int64_t nb = pad8(std::min<int64_t>(ntile, m->eval_grid > 0 ? m->eval_grid : EVAL_GRID));
   const int64_t tpb = (ntile + nb - 1) / nb;
   // raw-buffer addressing when the state (all variables) and the candidates fit in 32-bit byte offsets
   constexpr int64_t NV = NVar<FLUX>::value;

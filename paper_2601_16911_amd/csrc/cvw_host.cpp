@@ -928,6 +928,12 @@ cvw_status cvw_mesh_get_info(const cvw_mesh* m, cvw_mesh_info* info) {
   return CVW_OK;
 }
 
+cvw_status cvw_mesh_set_grid(cvw_mesh* m, int blocks) {
+  if (!m) { set_error("null mesh"); return CVW_EINVAL; }
+  m->eval_grid = blocks > 0 ? blocks : 0;
+  return CVW_OK;
+}
+
 cvw_status cvw_mesh_export(const cvw_mesh* m, int which, void* dst, size_t bytes) {
   if (!m || !dst) { set_error("null argument"); return CVW_EINVAL; }
   const std::vector<int32_t>* src = nullptr;

@@ -24,7 +24,8 @@ EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXP
 
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
            "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_residual",
-           "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_batch_build", "cvw_batch_destroy",
+           "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_batch_build",
+           "cvw_batch_destroy",
            "cvw_batch_workspace_bytes", "cvw_batch_step", "cvw_batch_set_grid", "cvw_batch_poll_status",
            "cvw_mlp_create", "cvw_mlp_destroy", "cvw_mlp_get_params", "cvw_mlp_set_params", "cvw_mlp_features",
            "cvw_mlp_infer", "cvw_mlp_train_workspace_bytes", "cvw_mlp_train_step"]
@@ -81,6 +82,7 @@ def load():
     lib.cvw_mesh_destroy.restype = None
     lib.cvw_mesh_get_info.argtypes = [vp, C.POINTER(MeshInfoC)]
     lib.cvw_mesh_export.argtypes = [vp, C.c_int, vp, sz]
+    lib.cvw_mesh_set_grid.argtypes = [vp, C.c_int]
     lib.cvw_workspace_bytes.argtypes = [vp, C.POINTER(ParamsC), C.c_int]
     lib.cvw_workspace_bytes.restype = sz
     lib.cvw_vertex_candidates.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, sz, vp]
@@ -204,6 +206,10 @@ class Mesh:
     def handle(self):
         return self._h
 
+    def set_grid(self, blocks: int):
+        """Blocks per launch of the DG quadrilateral cell pass (<= 0: default)."""
+        _check(load().cvw_mesh_set_grid(self._h, int(blocks)))
+
     def export(self, which: int):
         sizes = {EXPORT_VTX_PTR: self.info["n_vertices"] + 1, EXPORT_VTX_CELL: self.info["nnz_vertex"],
                  EXPORT_VTX_LV: self.info["nnz_vertex"],
@@ -308,6 +314,17 @@ class Batch:
         h = C.c_void_p()
         _check(load().cvw_batch_build(arr, len(instances), C.byref(h)))
         self._h = h
+        self._sig = ";".join(f"{m.degree}:{p.flux}:{m.info['n_cells']}" for m, p, _, _ in instances)
+
+    @property
+    def states(self):
+        """The instances' device states (updated in place by step)."""
+        return [u for _, u in self._keep]
+
+    def signature(self) -> str:
+        """(degree, flux, cells) of every instance, in order: the tuning-cache key."""
+        import hashlib
+        return hashlib.sha1(self._sig.encode()).hexdigest()[:16]
 
     def workspace_bytes(self) -> int:
         return int(load().cvw_batch_workspace_bytes(self._h))
