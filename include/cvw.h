@@ -18,7 +18,8 @@
  *   allocations on the current HIP device, 256-byte aligned and not aliased
  *   unless stated.  The library never allocates in the evaluation calls; only
  *   cvw_mesh_build allocates (the mesh's device arrays, freed by
- *   cvw_mesh_destroy).
+ *   cvw_mesh_destroy; cvw_mesh_build_in puts them in a caller buffer instead),
+ *   and the learned-sensor and batch handles their small descriptor arrays.
  * - `stream` is a hipStream_t (NULL = default stream).  Evaluation calls only
  *   enqueue work on it and return; argument errors are detected on the host
  *   before anything is enqueued.  Numerical trouble detected on the device
@@ -145,6 +146,14 @@ const char* cvw_last_error(void);
  * current device.  EINVAL for a malformed or non-conforming description,
  * ENOMEM / EDEVICE for device failures.  *out owns device memory. */
 cvw_status cvw_mesh_build(const cvw_mesh_desc* desc, cvw_mesh** out);
+/* The same mesh with its device arrays placed in a caller-owned device buffer
+ * (e.g. a torch allocation): cvw_mesh_plan gives the bytes the buffer needs
+ * (host work only, no device memory touched), cvw_mesh_build_in builds into
+ * device_buf (256-byte aligned, at least that many bytes; EINVAL if smaller).
+ * The buffer must outlive the mesh; cvw_mesh_destroy then frees only the
+ * host-side part. */
+cvw_status cvw_mesh_plan(const cvw_mesh_desc* desc, size_t* device_bytes);
+cvw_status cvw_mesh_build_in(const cvw_mesh_desc* desc, void* device_buf, size_t bytes, cvw_mesh** out);
 void cvw_mesh_destroy(cvw_mesh* mesh);
 cvw_status cvw_mesh_get_info(const cvw_mesh* mesh, cvw_mesh_info* info);
 /* Launch shape of the DG quadrilateral cell pass on this mesh: the number of

@@ -571,13 +571,45 @@ using namespace cvw;
     }                                                                              \
   } while (0)
 
+// Device storage of a mesh under construction: one hipMalloc per array, or
+// 256-byte aligned pieces of a caller-provided buffer (cvw_mesh_build_in), or
+// only a byte count (cvw_mesh_plan).
+struct MeshArena {
+  char* base = nullptr;
+  size_t size = 0, off = 0;
+  bool count_only = false;
+};
+static thread_local MeshArena* g_arena = nullptr;
+
+static cvw_status dev_alloc(void** dst, size_t bytes) {
+  if (!g_arena) {
+    if (hipMalloc(dst, bytes) != hipSuccess) { set_error("hipMalloc failed for mesh arrays"); return CVW_ENOMEM; }
+    return CVW_OK;
+  }
+  MeshArena& A = *g_arena;
+  A.off = (A.off + 255) / 256 * 256;
+  if (A.count_only) {
+    *dst = nullptr;
+    A.off += bytes;
+    return CVW_OK;
+  }
+  if (A.off + bytes > A.size) {
+    set_error("device buffer too small for the mesh (cvw_mesh_plan gives the size)");
+    return CVW_EINVAL;
+  }
+  *dst = A.base + A.off;
+  A.off += bytes;
+  return CVW_OK;
+}
+
 template <typename T>
 static cvw_status upload(T** dst, const std::vector<T>& src) {
   if (src.empty()) { *dst = nullptr; return CVW_OK; }
-  if (hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T)) != hipSuccess) {
-    set_error("hipMalloc failed for mesh arrays");
-    return CVW_ENOMEM;
-  }
+  void* p = nullptr;
+  const cvw_status st = dev_alloc(&p, src.size() * sizeof(T));
+  if (st != CVW_OK) return st;
+  *dst = static_cast<T*>(p);
+  if (g_arena && g_arena->count_only) return CVW_OK;
   CVW_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
   return CVW_OK;
 }
@@ -639,6 +671,10 @@ static std::vector<double> diag_mass(const cvw_mesh* m, const cvw_mesh_desc* d) 
 
 static void free_mesh(cvw_mesh* m) {
   if (!m) return;
+  if (m->external) {                 // device arrays live in the caller's buffer
+    delete m;
+    return;
+  }
   (void)hipFree(m->d_vtx_ptr);
   (void)hipFree(m->d_vtx_ent);
   (void)hipFree(m->d_cell_vtx);
@@ -687,6 +723,7 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   }
   const int64_t E = d->n_cells, Nv = d->n_vertices;
   auto* m = new cvw_mesh();
+  m->external = g_arena != nullptr;
   m->dim = d->dim; m->cell = d->cell; m->degree = d->degree; m->space = d->space;
   m->E = E; m->Nv = Nv; m->ve = ve; m->nf = nf;
   const int p = d->degree;
@@ -910,11 +947,9 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
       if ((st = upload(&m->d_dinv_f, inv_f)) != CVW_OK) { free_mesh(m); return st; }
     }
   }
-  if (hipMalloc(reinterpret_cast<void**>(&m->d_tens), sizeof(TensorTables)) != hipSuccess) {
-    free_mesh(m); set_error("hipMalloc failed"); return CVW_ENOMEM;
-  }
-  if (hipMemcpy(m->d_tens, &m->tens, sizeof(TensorTables), hipMemcpyHostToDevice) != hipSuccess) {
-    free_mesh(m); set_error("hipMemcpy failed"); return CVW_EDEVICE;
+  {
+    std::vector<TensorTables> t1(1, m->tens);
+    if ((st = upload(&m->d_tens, t1)) != CVW_OK) { free_mesh(m); return st; }
   }
   *out = m;
   return CVW_OK;
@@ -926,6 +961,32 @@ cvw_status cvw_mesh_get_info(const cvw_mesh* m, cvw_mesh_info* info) {
   info->n_loc = m->nloc; info->n_k = m->nk; info->n_q = m->nq; info->v_e = m->ve; info->n_faces = m->nf;
   info->uniform = m->uniform; info->hx = m->hx; info->hy = m->hy;
   return CVW_OK;
+}
+
+cvw_status cvw_mesh_plan(const cvw_mesh_desc* d, size_t* device_bytes) {
+  if (!d || !device_bytes) { set_error("null argument"); return CVW_EINVAL; }
+  MeshArena A;
+  A.count_only = true;
+  g_arena = &A;
+  cvw_mesh* m = nullptr;
+  const cvw_status st = cvw_mesh_build(d, &m);
+  g_arena = nullptr;
+  if (st != CVW_OK) return st;
+  free_mesh(m);
+  *device_bytes = (A.off + 255) / 256 * 256;
+  return CVW_OK;
+}
+
+cvw_status cvw_mesh_build_in(const cvw_mesh_desc* d, void* device_buf, size_t bytes, cvw_mesh** out) {
+  if (!d || !out || !device_buf) { set_error("null argument"); return CVW_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(device_buf) % 256 != 0) { set_error("device buffer not 256-byte aligned"); return CVW_EINVAL; }
+  MeshArena A;
+  A.base = static_cast<char*>(device_buf);
+  A.size = bytes;
+  g_arena = &A;
+  const cvw_status st = cvw_mesh_build(d, out);
+  g_arena = nullptr;
+  return st;
 }
 
 cvw_status cvw_mesh_set_grid(cvw_mesh* m, int blocks) {

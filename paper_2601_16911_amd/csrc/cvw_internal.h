@@ -239,6 +239,7 @@ struct cvw_mesh {
   double hx = 0, hy = 0, he = 0;
   int device = 0;
   int eval_grid = 0;                 // DG quad cell pass: blocks per launch (0 = default)
+  int external = 0;                  // device arrays in a caller-provided buffer (not freed here)
   // host copies
   std::vector<int32_t> h_vtx_ptr, h_vtx_cell, h_vtx_lv, h_cell_vtx, h_nbr, h_nbr_face, h_cell_dof;
   std::vector<double> h_coords;      // [E][ve][dim]

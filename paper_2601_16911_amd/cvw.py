@@ -24,7 +24,8 @@ EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXP
 
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
            "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_residual",
-           "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_batch_build",
+           "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_mesh_plan",
+           "cvw_mesh_build_in", "cvw_batch_build",
            "cvw_batch_destroy",
            "cvw_batch_workspace_bytes", "cvw_batch_step", "cvw_batch_set_grid", "cvw_batch_poll_status",
            "cvw_mlp_create", "cvw_mlp_destroy", "cvw_mlp_get_params", "cvw_mlp_set_params", "cvw_mlp_features",
@@ -83,6 +84,8 @@ def load():
     lib.cvw_mesh_get_info.argtypes = [vp, C.POINTER(MeshInfoC)]
     lib.cvw_mesh_export.argtypes = [vp, C.c_int, vp, sz]
     lib.cvw_mesh_set_grid.argtypes = [vp, C.c_int]
+    lib.cvw_mesh_plan.argtypes = [C.POINTER(MeshDescC), C.POINTER(sz)]
+    lib.cvw_mesh_build_in.argtypes = [C.POINTER(MeshDescC), vp, sz, C.POINTER(vp)]
     lib.cvw_workspace_bytes.argtypes = [vp, C.POINTER(ParamsC), C.c_int]
     lib.cvw_workspace_bytes.restype = sz
     lib.cvw_vertex_candidates.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, sz, vp]
@@ -180,22 +183,42 @@ def _stream(stream):
     return C.c_void_p(stream)
 
 
-class Mesh:
-    """A mesh built on the current device (owns the device connectivity)."""
+def _mesh_desc(desc, degree: int, space: int):
+    cv = np.ascontiguousarray(desc.cell_vertices, dtype=np.int32)
+    cc = np.ascontiguousarray(desc.cell_coords, dtype=np.float64)
+    d = MeshDescC()
+    d.dim, d.cell, d.degree, d.space = int(desc.dim), int(desc.cell), int(degree), int(space)
+    d.n_cells, d.n_vertices = cv.shape[0], int(desc.n_vertices)
+    d.cell_vertices = cv.ctypes.data
+    d.cell_coords = cc.ctypes.data
+    per = tuple(desc.periodic) + (0, 0)
+    d.periodic[0], d.periodic[1] = int(per[0]), int(per[1])
+    return d, (cv, cc)
 
-    def __init__(self, desc, degree: int, space: int):
+
+def mesh_plan(desc, degree: int, space: int) -> int:
+    """Device bytes cvw_mesh_build_in needs for this mesh (host work only)."""
+    d, keep = _mesh_desc(desc, degree, space)
+    n = C.c_size_t(0)
+    _check(load().cvw_mesh_plan(C.byref(d), C.byref(n)))
+    return int(n.value)
+
+
+class Mesh:
+    """A mesh built on the current device.  By default the library allocates
+    its device arrays; with device_buffer (a device tensor of at least
+    mesh_plan(...) bytes, kept alive by the mesh) they are placed there."""
+
+    def __init__(self, desc, degree: int, space: int, device_buffer=None):
         lib = load()
-        cv = np.ascontiguousarray(desc.cell_vertices, dtype=np.int32)
-        cc = np.ascontiguousarray(desc.cell_coords, dtype=np.float64)
-        d = MeshDescC()
-        d.dim, d.cell, d.degree, d.space = int(desc.dim), int(desc.cell), int(degree), int(space)
-        d.n_cells, d.n_vertices = cv.shape[0], int(desc.n_vertices)
-        d.cell_vertices = cv.ctypes.data
-        d.cell_coords = cc.ctypes.data
-        per = tuple(desc.periodic) + (0, 0)
-        d.periodic[0], d.periodic[1] = int(per[0]), int(per[1])
+        d, keep = _mesh_desc(desc, degree, space)
         h = C.c_void_p()
-        _check(lib.cvw_mesh_build(C.byref(d), C.byref(h)))
+        if device_buffer is None:
+            _check(lib.cvw_mesh_build(C.byref(d), C.byref(h)))
+        else:
+            nbytes = device_buffer.numel() * device_buffer.element_size()
+            _check(lib.cvw_mesh_build_in(C.byref(d), C.c_void_p(device_buffer.data_ptr()), nbytes, C.byref(h)))
+        self._buffer = device_buffer
         self._h = h
         self.degree, self.space = degree, space
         info = MeshInfoC()

@@ -66,3 +66,21 @@ def test_params_defaults_marshal():
     p = cvw.make_params(synth.Params())
     assert p.eps_vertex == 1e-6 and p.eps_cell == 1e-6 and p.r == 2 and p.c_gamma == 0.9
     assert p.lin_w_vertex == 1e-3 and p.sc_on == 1 and p.q_sensor == 1.0
+
+
+def test_mesh_plan_without_gpu():
+    """cvw_mesh_plan is host work only: a byte count, 256-aligned, reproducible,
+    growing with the mesh; cvw_mesh_build_in refuses a buffer that is too small
+    before touching it."""
+    import ctypes as C
+    import synth
+    lib = cvw.load()
+    a = cvw.mesh_plan(synth.quad_mesh(8, 8), 3, cvw.DG)
+    b = cvw.mesh_plan(synth.quad_mesh(8, 8), 3, cvw.DG)
+    c = cvw.mesh_plan(synth.quad_mesh(16, 16), 3, cvw.DG)
+    assert a == b and a > 0 and a % 256 == 0 and c > a
+    d, keep = cvw._mesh_desc(synth.quad_mesh(8, 8), 3, cvw.DG)
+    h = C.c_void_p()
+    st = lib.cvw_mesh_build_in(C.byref(d), C.c_void_p(4096), 256, C.byref(h))
+    assert st == cvw.EINVAL and not h.value
+    assert b"too small" in lib.cvw_last_error()

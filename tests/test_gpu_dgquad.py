@@ -158,6 +158,26 @@ def test_residual_deterministic_and_gamma_out():
     assert torch.equal(R1, R2)
 
 
+@pytest.mark.parametrize("p", [1, 3])
+def test_mesh_in_caller_buffer_matches(p):
+    """A mesh built into a caller-owned device buffer (cvw_mesh_plan /
+    cvw_mesh_build_in) gives bitwise the residual of a library-allocated one."""
+    mesh = synth.quad_mesh(16, 12)
+    sp = build_space(mesh, p, 1, 4)
+    U = _dev(f32(euler_state(sp, k=6.0)))
+    cp = cvw.make_params(EULER)
+    nbytes = cvw.mesh_plan(mesh, p, cvw.DG)
+    buf = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    ga = cvw.Mesh(mesh, p, cvw.DG)
+    gb = cvw.Mesh(mesh, p, cvw.DG, device_buffer=buf)
+    Ra, Rb = torch.empty_like(U), torch.empty_like(U)
+    cvw.residual(ga, cp, U, Ra, None, cvw.alloc_workspace(ga, cp, 0))
+    cvw.residual(gb, cp, U, Rb, None, cvw.alloc_workspace(gb, cp, 0))
+    assert torch.equal(Ra, Rb)
+    with pytest.raises(cvw.CvwError):
+        cvw.Mesh(mesh, p, cvw.DG, device_buffer=buf[: nbytes // 2])
+
+
 @pytest.mark.parametrize("flux", ["euler", "burgers"])
 @pytest.mark.parametrize("p", [1, 2, 3])
 def test_wide_addressing_path_matches(p, flux, monkeypatch):
