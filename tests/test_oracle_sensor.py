@@ -134,6 +134,37 @@ def test_sympy_brute_force_quads_q2():
     assert g.min() < 0.9          # the data is rough enough to exercise the sensor
 
 
+@pytest.mark.parametrize("p", [1, 3])
+def test_sympy_brute_force_dg_quads(p):
+    """Uniform periodic 3x3 quads, DG Q_p at the Gauss-Legendre nodes (the
+    benchmark's element at p = 3), rough discontinuous data: the nodes enter
+    as the exact rationals of their float64 values."""
+    mesh = synth.quad_mesh(3, 3, periodic=(True, True))
+    prm = Params()
+    sp = build_space(mesh, p, 1)
+    n1 = p + 1
+    rng = np.random.default_rng(30 + p)
+    u = rng.integers(-2, 3, size=(sp.E, n1 * n1)) / 8.0
+    u[4, :] += 3.0                                   # a jump cell
+    u[4, 0] -= 6.0                                   # and a spike inside it, so that the sensor is active
+    L = _lagrange_1d_sym([_R(x) for x in sp.ref.x1d])
+    polys, boxes = [], []
+    for e in range(sp.E):
+        x0, x1 = _R(mesh.cell_coords[e, 0, 0]), _R(mesh.cell_coords[e, 1, 0])
+        y0, y1 = _R(mesh.cell_coords[e, 0, 1]), _R(mesh.cell_coords[e, 3, 1])
+        xi = 2 * (xs - (x0 + x1) / 2) / (x1 - x0)
+        eta = 2 * (ys - (y0 + y1) / 2) / (y1 - y0)
+        polys.append(symp.Poly(sum(_R(u[e, a + n1 * b]) * L[a](xi) * L[b](eta)
+                                   for a in range(n1) for b in range(n1)), xs, ys))
+        boxes.append((x0, x1, y0, y1))
+    g_sym, c_sym = _sympy_sensor(mesh, polys, p, lambda e, f: _box_integral(f, *boxes[e]), prm)
+    c = vertex_candidates(sp, u, prm)
+    g = cell_sensor(sp, u, c, prm)
+    assert np.abs(c - c_sym).max() < 1e-9 * (1 + np.abs(c_sym).max())
+    assert np.abs(g - g_sym).max() < 1e-10
+    assert g.min() < 0.9
+
+
 def test_sympy_brute_force_jittered_triangles_p2():
     mesh = synth.tri_mesh(3, 3, jitter=0.15, seed=8, periodic=(True, True))
     prm = Params()
