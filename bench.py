@@ -125,17 +125,23 @@ def cpu_baseline(target_seconds: float = 15.0):
                       f"mesh ({dofs} DOFs) with the same state recipe, single process, {dt:.1f} s"}
 
 
-def _timed(torch, stream, fn, reps: int) -> float:
-    """Seconds per call of fn() on `stream` (HIP events), after one warm-up call."""
+def _timed(torch, stream, fn, reps: int, trials: int = 3) -> float:
+    """Seconds per call of fn() on `stream` (HIP events), after one warm-up
+    call: the median over `trials` runs of `reps` calls, so that one host
+    stall between launches (the GPU idles, the events still count it) does
+    not set the figure."""
     fn()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        fn()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / reps
+    per = []
+    for _ in range(trials):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1) / 1e3 / reps)
+    return sorted(per)[len(per) // 2]
 
 
 def bench_learned(torch, cvw, gm, prm, U, dt, steps: int):
