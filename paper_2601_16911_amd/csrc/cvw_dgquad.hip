@@ -146,12 +146,80 @@ __device__ __forceinline__ double dpow(double x, int n) {
 // ---------------------------------------------------------------------------
 // vertex stage
 // ---------------------------------------------------------------------------
+// Hermite data of one patch cell at the vertex (corner lv of the cell):
+// Ek[t] = h_e^{|k|} D^k u_h^e(x_i); returns sum_k Ek^2 = ||u_h^e||_{x_i}^2.
+// The vertex is moved to the reference corner (-1, -1) by mirroring the data,
+// l_i^{(m)}(1) = (-1)^m l_{P-i}^{(m)}(-1): rows through the load addresses,
+// columns by selects.  MX (MY) = 0: the vertex is at xi = -1 (eta = -1); 1: at
+// +1; 2: taken from lv at run time.  Every variant performs the same
+// floating-point operations on the same values (sign changes are exact), so a
+// vertex's result does not depend on the variant its wave takes.
+template <int P, int MX, int MY>
+__device__ __forceinline__ double vertex_cell(const float* __restrict__ ue, int lv, const VertexTables& vt,
+                                              double (&Ek)[KSet<P>::NK]) {
+  constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
+  constexpr KSet<P> ks = kset<P>;
+  const bool fx = (MX == 2) ? (lv == 1 || lv == 2) : (MX == 1);
+  const bool fy = (MY == 2) ? (lv >= 2) : (MY == 1);
+  float rf[NLOC];
+#pragma unroll
+  for (int bb = 0; bb < N1; ++bb) {
+    const float* row = ue + N1 * (fy ? P - bb : bb);
+    float v[N1];
+    if constexpr (N1 == 4) {
+      const float4 v4 = *reinterpret_cast<const float4*>(row);
+      v[0] = v4.x;
+      v[1] = v4.y;
+      v[2] = v4.z;
+      v[3] = v4.w;
+    } else {
+#pragma unroll
+      for (int aa = 0; aa < N1; ++aa) v[aa] = row[aa];
+    }
+#pragma unroll
+    for (int aa = 0; aa < N1; ++aa) rf[aa + N1 * bb] = fx ? v[P - aa] : v[aa];
+  }
+  // derivatives of the data relative to the corner's nodal value, so that
+  // constant data gives exactly zero Hermite data (differences of two floats
+  // are exact in float64); float64 because high derivatives of smooth data
+  // cancel strongly.  One node column j at a time:
+  //   T_j[m] = sum_i L[m][i] (u_ij - u_00),   D^k = sum_j L[ky][j] T_j[kx]
+  const double r0 = static_cast<double>(rf[0]);
+#pragma unroll
+  for (int j = 0; j < N1; ++j) {
+    // the corner node's own difference is zero: column 0 starts at i = 1
+    const int ib = (j == 0) ? 1 : 0;
+    double rc[N1];
+#pragma unroll
+    for (int ii = ib; ii < N1; ++ii) rc[ii] = static_cast<double>(rf[ii + N1 * j]) - r0;
+    double Tj[N1];
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      double sacc = vt.L[m][ib] * rc[ib];
+#pragma unroll
+      for (int ii = ib + 1; ii < N1; ++ii) sacc = fma(vt.L[m][ii], rc[ii], sacc);
+      Tj[m] = sacc;
+    }
+#pragma unroll
+    for (int t = 0; t < NK; ++t)
+      Ek[t] = (j == 0) ? vt.L[ks.y[t]][0] * Tj[ks.x[t]] : fma(vt.L[ks.y[t]][j], Tj[ks.x[t]], Ek[t]);
+  }
+  double b2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < NK; ++t) {
+    const bool flip = (fx && (ks.x[t] & 1)) != (fy && (ks.y[t] & 1));
+    Ek[t] *= flip ? -vt.sk[t] : vt.sk[t];
+    b2 = fma(Ek[t], Ek[t], b2);
+  }
+  return b2;
+}
+
 // One block of 256 vertices (logical block index blk).
 template <int P>
 __device__ __forceinline__ void dgq_vertex_body(const float* __restrict__ u, float* __restrict__ cand,
                                                 const int32_t* __restrict__ vptr, const int32_t* __restrict__ vent,
-                                                int64_t Nv, int64_t blk, const TensorTables& tab, double sx,
-                                                double sy, double he2, const MethodScalars& ms) {
+                                                int64_t Nv, int64_t blk, const VertexTables& vt,
+                                                const MethodScalars& ms) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr KSet<P> ks = kset<P>;
   const int64_t i = blk * VTX_PER_BLOCK + threadIdx.x;
@@ -165,90 +233,48 @@ __device__ __forceinline__ void dgq_vertex_body(const float* __restrict__ u, flo
     const int ent = vent[it];
     const int e = ent >> 2, lv = ent & 3;
     const float* ue = u + static_cast<int64_t>(e) * NLOC;
-    // vertex at xi = +1 (lv 1, 2) / eta = +1 (lv 2, 3): the data is mirrored
-    // so that only the tables at -1 are needed, l_i^{(m)}(1) = (-1)^m
-    // l_{P-i}^{(m)}(-1): rows through the load addresses, columns by selects
-    const bool fx = (lv == 1) || (lv == 2);
-    const bool fy = (lv >= 2);
-    float rf[NLOC];
-#pragma unroll
-    for (int bb = 0; bb < N1; ++bb) {
-      const float* row = ue + N1 * (fy ? P - bb : bb);
-      float v[N1];
-      if constexpr (N1 == 4) {
-        const float4 v4 = *reinterpret_cast<const float4*>(row);
-        v[0] = v4.x;
-        v[1] = v4.y;
-        v[2] = v4.z;
-        v[3] = v4.w;
-      } else {
-#pragma unroll
-        for (int aa = 0; aa < N1; ++aa) v[aa] = row[aa];
+    // on structured meshes the it-th patch cell of neighbouring vertices sits
+    // at the same corner: then the whole wave takes a variant with the
+    // mirroring fixed at compile time
+    double Ek[NK], b2;
+    const int lv0 = __builtin_amdgcn_readfirstlane(lv);
+    if (__builtin_amdgcn_ballot_w64(lv != lv0) == 0) {
+      switch (lv0) {
+        case 0: b2 = vertex_cell<P, 0, 0>(ue, lv, vt, Ek); break;
+        case 1: b2 = vertex_cell<P, 1, 0>(ue, lv, vt, Ek); break;
+        case 2: b2 = vertex_cell<P, 1, 1>(ue, lv, vt, Ek); break;
+        default: b2 = vertex_cell<P, 0, 1>(ue, lv, vt, Ek); break;
       }
-#pragma unroll
-      for (int aa = 0; aa < N1; ++aa) rf[aa + N1 * bb] = fx ? v[P - aa] : v[aa];
+    } else {
+      b2 = vertex_cell<P, 2, 2>(ue, lv, vt, Ek);
     }
-    // derivatives are taken of the data relative to one nodal value, so that
-    // constant data gives exactly zero Hermite data (differences of two floats
-    // are exact in float64)
-    const double r0 = static_cast<double>(rf[0]);
-    // derivatives in float64 (high derivatives of smooth data cancel strongly),
-    // one column j of nodes at a time:
-    //   T_j[m] = sum_i l_i^{(m)}(-1) (u_ij - u_00),   D^k u = sum_j l_j^{(ky)}(-1) T_j[kx]
-    double D[NK];
-#pragma unroll
-    for (int t = 0; t < NK; ++t) D[t] = 0.0;
-#pragma unroll
-    for (int j = 0; j < N1; ++j) {
-      double rc[N1];
-#pragma unroll
-      for (int ii = 0; ii < N1; ++ii) rc[ii] = static_cast<double>(rf[ii + N1 * j]) - r0;
-      double Tj[N1];
-#pragma unroll
-      for (int m = 0; m < N1; ++m) {
-        double sacc = 0.0;
-#pragma unroll
-        for (int ii = 0; ii < N1; ++ii) sacc = fma(tab.Ld[m][ii], rc[ii], sacc);
-        Tj[m] = sacc;
-      }
-#pragma unroll
-      for (int t = 0; t < NK; ++t) D[t] = fma(tab.Ld[ks.y[t]][j], Tj[ks.x[t]], D[t]);
-    }
-    double b2 = 0.0;
-#pragma unroll
-    for (int t = 0; t < NK; ++t) {
-      const int kx = ks.x[t], ky = ks.y[t];
-      double sc = dpow(sx, kx) * dpow(sy, ky);
-      if (fx && (kx & 1)) sc = -sc;
-      if (fy && (ky & 1)) sc = -sc;
-      D[t] *= sc;
-      b2 = fma(dpow(he2, kx + ky) * D[t], D[t], b2);
-    }
+    // weight (eps + beta)^{-r}, beta = ||u_h^e||_{x_i}^q; for r = 2, q = 1 from
+    // the hardware float64 square root and reciprocal (about single
+    // precision: the weights enter a normalised average)
     double w;
     if (ms.fast_exp) {
-      const double den = ms.eps_vd + sqrt(b2);
-      w = 1.0 / (den * den);
+      const double den = ms.eps_vd + __builtin_amdgcn_sqrt(b2);
+      w = __builtin_amdgcn_rcp(den * den);
     } else {
       const double beta = pow(sqrt(b2), static_cast<double>(ms.q_beta));
       w = pow(ms.eps_vd + beta, -static_cast<double>(ms.r));
     }
 #pragma unroll
-    for (int t = 0; t < NK; ++t) acc[t] = fma(w, D[t], acc[t]);
+    for (int t = 0; t < NK; ++t) acc[t] = fma(w, Ek[t], acc[t]);
     wsum += w;
   }
   const double inv = 1.0 / wsum;
   float* out = cand + i * NK;
 #pragma unroll
-  for (int t = 0; t < NK; ++t) out[t] = static_cast<float>(acc[t] * inv);
+  for (int t = 0; t < NK; ++t) out[t] = static_cast<float>(acc[t] * inv * vt.hinv[ks.x[t] + ks.y[t]]);
 }
 
 template <int P>
 __global__ __launch_bounds__(256) void dgq_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
                                                          const int32_t* __restrict__ vptr,
                                                          const int32_t* __restrict__ vent, int64_t Nv,
-                                                         int64_t nbp, TensorTables tab, double sx, double sy,
-                                                         double he2, MethodScalars ms) {
-  dgq_vertex_body<P>(u, cand, vptr, vent, Nv, xcd_block(blockIdx.x, nbp), tab, sx, sy, he2, ms);
+                                                         int64_t nbp, VertexTables vt, MethodScalars ms) {
+  dgq_vertex_body<P>(u, cand, vptr, vent, Nv, xcd_block(blockIdx.x, nbp), vt, ms);
 }
 
 // ---------------------------------------------------------------------------
@@ -897,7 +923,7 @@ template <int P>
 static void launch_vertex(const cvw_mesh* m, const MethodScalars& ms, const float* u, float* cand, hipStream_t s) {
   const int64_t nb = pad8((m->Nv + VTX_PER_BLOCK - 1) / VTX_PER_BLOCK);
   hipLaunchKernelGGL(dgq_vertex_kernel<P>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, cand, m->d_vtx_ptr,
-                     m->d_vtx_ent, m->Nv, nb, m->tens, 2.0 / m->hx, 2.0 / m->hy, m->he * m->he, ms);
+                     m->d_vtx_ent, m->Nv, nb, make_vertex_tables(m->tens, m->hx, m->hy, m->he, P), ms);
 }
 
 cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand,
@@ -1206,7 +1232,7 @@ __global__ __launch_bounds__(256) void batch_vertex_kernel(const BatchInst* __re
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int2 w = items[it];
     const BatchInst& I = inst[w.x];
-    dgq_vertex_body<P>(I.u_in[stage], I.cand, I.vptr, I.vent, I.Nv, w.y, tabs[P], I.sxd, I.syd, I.he2d, I.ms);
+    dgq_vertex_body<P>(I.u_in[stage], I.cand, I.vptr, I.vent, I.Nv, w.y, I.vt, I.ms);
   }
 }
 

@@ -1481,9 +1481,7 @@ static cvw_status batch_upload_descriptors(cvw_batch* b, void* ws) {
     I.vent = m->d_vtx_ent;
     I.E = m->E;
     I.Nv = m->Nv;
-    I.sxd = 2.0 / m->hx;
-    I.syd = 2.0 / m->hy;
-    I.he2d = m->he * m->he;
+    I.vt = make_vertex_tables(m->tens, m->hx, m->hy, m->he, m->degree);
     I.g = make_cell_geo(m->hx, m->hy, m->he, m->degree);
     I.dt = static_cast<float>(b->dt[i]);
     I.P = m->degree;

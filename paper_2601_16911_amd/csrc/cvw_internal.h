@@ -187,6 +187,27 @@ struct CellGeo {
   float hhx, hhy;          // hx / 2, hy / 2
   float nuf;               // h_e / (2 p): nu_e = lambda_e nuf
 };
+// Float64 tables of the DG quadrilateral vertex pass for one mesh: L[m][i] =
+// l_i^{(m)}(-1), and per multi-index k (in the order of the derivative set)
+// sk[t] = h_e^{|k|} (2 / h_x)^{kx} (2 / h_y)^{ky}, which turns reference
+// derivatives at the corner into h_e^{|k|} D^k u_h, and hinv[n] = h_e^{-n}.
+struct VertexTables {
+  double L[MAXP + 1][MAXP + 1];
+  double sk[(MAXP + 1) * (MAXP + 2) / 2 - 1];
+  double hinv[MAXP + 1];
+};
+inline VertexTables make_vertex_tables(const TensorTables& t, double hx, double hy, double he, int p) {
+  VertexTables v{};
+  for (int m = 0; m <= MAXP; ++m)
+    for (int i = 0; i <= MAXP; ++i) v.L[m][i] = t.Ld[m][i];
+  auto pw = [](double x, int n) { double r = 1.0; for (int i = 0; i < n; ++i) r *= x; return r; };
+  int k = 0;
+  for (int n = 1; n <= p && n <= MAXP; ++n)       // the derivative set's order: |k| = n, kx = n - j, ky = j
+    for (int j = 0; j <= n; ++j) v.sk[k++] = pw(he, n) * pw(2.0 / hx, n - j) * pw(2.0 / hy, j);
+  for (int n = 0; n <= MAXP; ++n) v.hinv[n] = 1.0 / pw(he, n);
+  return v;
+}
+
 inline CellGeo make_cell_geo(double hx, double hy, double he, int p) {
   CellGeo g;
   g.hx = static_cast<float>(hx);
@@ -219,7 +240,7 @@ struct alignas(16) BatchInst {
   const int32_t* vptr;
   const int32_t* vent;
   int64_t E, Nv;
-  double sxd, syd, he2d;            // 2 / h_x, 2 / h_y, h_e^2 (vertex pass)
+  VertexTables vt;                  // vertex pass tables of the mesh
   CellGeo g;
   float dt;
   int P, flux;

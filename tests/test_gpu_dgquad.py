@@ -75,6 +75,30 @@ def test_vertex_candidates(p):
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
+def test_vertex_candidates_structured_waves(p):
+    """128 x 128 periodic quads: the 64-vertex waves away from the periodic
+    seam see their k-th patch cell at one corner for every vertex and take the
+    vertex pass's variants with the mirroring fixed at compile time; waves
+    holding a seam vertex take the run-time variant.  Same bound as above."""
+    n = 128
+    mesh, sp, gm = _setup(n, n, p)
+    u = f32(rough_scalar(sp, 1))
+    prm = Params()
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, 0)
+    cand = torch.empty((mesh.n_vertices, len(sp.ks)), dtype=torch.float32, device="cuda")
+    cvw.vertex_candidates(gm, cp, _dev(u), cand, ws)
+    c_o = o_cand(sp, u, prm)
+    got = cand.cpu().numpy()
+    h = 1.0 / n
+    for t, k in enumerate(sp.ks):
+        cond = np.abs(sp.ref.deriv(sp.ref.vertices, k)).sum(1).max() * (2 / h) ** (k[0] + k[1])
+        bound = 64 * np.finfo(np.float32).eps * cond * np.abs(u).max()
+        assert np.abs(got[:, t] - c_o[:, t]).max() < bound, (k, np.abs(got[:, t] - c_o[:, t]).max(), bound)
+    assert rel_err(got[:, :2], c_o[:, :2]) < 1e-5
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
 @pytest.mark.parametrize("sc_on", [1, 0])
 def test_sensor_and_sc_weights(p, sc_on):
     mesh, sp, gm = _setup(13, 11, p)
