@@ -130,11 +130,13 @@ def _timed(torch, stream, fn, reps: int, trials: int = 3) -> float:
     call: the median over `trials` runs of `reps` calls, so that one host
     stall between launches (the GPU idles, the events still count it) does
     not set the figure."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)                   # created before the timing
+    e1.record(stream)
     fn()
     torch.cuda.synchronize()
     per = []
     for _ in range(trials):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(reps):
             fn()
@@ -311,26 +313,34 @@ def main():
             cvw.vertex_candidates(gm, cp, U, cand, ws)
             grid = autotune.tune_mesh(gm, cp, U, cand, ws, n_var=nv)
 
-    ev = []
+    # every timing event is created (torch creates HIP events at their first
+    # record, and the first event of a process initialises the runtime's event
+    # machinery) and recorded once before the timed region, so that no host
+    # stall of that kind lands between the events
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3 * args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    for e in [t_start, t_end] + [x for pair in ev for x in pair]:
+        e.record(stream)
+    torch.cuda.synchronize()
+    n_rec = [0]
 
     def rk_step(record: bool):
         stages = ((U, None, U1, 0.0, 1.0), (U1, U, U2, 0.75, 0.25), (U2, U, U, 1.0 / 3.0, 2.0 / 3.0))
         for (us, un, uo, a0, b0) in stages:
             cvw.vertex_candidates(gm, cp, us, cand, ws)
             if record:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0, e1 = ev[n_rec[0]]
+                n_rec[0] += 1
                 e0.record(stream)
                 cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
                 e1.record(stream)
-                ev.append((e0, e1))
             else:
                 cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
 
     for _ in range(args.warmup):
         rk_step(False)
     torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     t_start.record(stream)
     for _ in range(args.steps):
@@ -350,6 +360,8 @@ def main():
     torch.cuda.synchronize()
     r0 = torch.cuda.Event(enable_timing=True)
     r1 = torch.cuda.Event(enable_timing=True)
+    r1.record(stream)
+    torch.cuda.synchronize()
     r0.record(stream)
     nres = 10
     for _ in range(nres):

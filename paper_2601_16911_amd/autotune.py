@@ -69,10 +69,12 @@ def store(key: str, entry: dict, path: str | None = None) -> None:
 
 def _time(torch, fn, reps: int) -> float:
     stream = torch.cuda.current_stream()
-    fn()
-    torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)                   # the events exist before the timing
+    t1.record(stream)
+    fn()
+    torch.cuda.synchronize()
     t0.record(stream)
     for _ in range(reps):
         fn()
