@@ -125,6 +125,47 @@ def cpu_baseline(target_seconds: float = 15.0):
                       f"mesh ({dofs} DOFs) with the same state recipe, single process, {dt:.1f} s"}
 
 
+class HipEvents:
+    """Timing events of the HIP runtime in use (the one torch loaded: same
+    soname), created with hipEventDisableSystemFence: a record then writes its
+    timestamp without the system-scope cache write-back and invalidation that
+    a default event performs, which would otherwise sit between the timed
+    launches.  Elapsed times are read only after a device synchronisation."""
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    def __init__(self):
+        import ctypes
+        self.C = ctypes
+        self.lib = ctypes.CDLL("libamdhip64.so.7")
+        self.lib.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        self.lib.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        ev = self.C.c_void_p()
+        rc = self.lib.hipEventCreateWithFlags(self.C.byref(ev), self.DISABLE_SYSTEM_FENCE)
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
+        return ev
+
+    def record(self, ev, stream):
+        rc = self.lib.hipEventRecord(ev, self.C.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"hipEventRecord failed ({rc})")
+
+    def elapsed_ms(self, a, b) -> float:
+        ms = self.C.c_float()
+        rc = self.lib.hipEventElapsedTime(self.C.byref(ms), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return ms.value
+
+    def destroy(self, *evs):
+        for ev in evs:
+            self.lib.hipEventDestroy(ev)
+
+
 def _timed(torch, stream, fn, reps: int, trials: int = 3) -> float:
     """Seconds per call of fn() on `stream` (HIP events), after one warm-up
     call: the median over `trials` runs of `reps` calls, so that one host
@@ -313,15 +354,14 @@ def main():
             cvw.vertex_candidates(gm, cp, U, cand, ws)
             grid = autotune.tune_mesh(gm, cp, U, cand, ws, n_var=nv)
 
-    # every timing event is created (torch creates HIP events at their first
-    # record, and the first event of a process initialises the runtime's event
-    # machinery) and recorded once before the timed region, so that no host
-    # stall of that kind lands between the events
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3 * args.steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
+    # every timing event is created and recorded once before the timed region
+    # (the first event record of a process initialises the runtime's event
+    # machinery, a host stall of tens of ms)
+    hev = HipEvents()
+    ev = [(hev.create(), hev.create()) for _ in range(3 * args.steps)]
+    t_start, t_end = hev.create(), hev.create()
     for e in [t_start, t_end] + [x for pair in ev for x in pair]:
-        e.record(stream)
+        hev.record(e, stream)
     torch.cuda.synchronize()
     n_rec = [0]
 
@@ -332,9 +372,9 @@ def main():
             if record:
                 e0, e1 = ev[n_rec[0]]
                 n_rec[0] += 1
-                e0.record(stream)
+                hev.record(e0, stream)
                 cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
-                e1.record(stream)
+                hev.record(e1, stream)
             else:
                 cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
 
@@ -342,14 +382,15 @@ def main():
         rk_step(False)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    t_start.record(stream)
+    hev.record(t_start, stream)
     for _ in range(args.steps):
         rk_step(True)
-    t_end.record(stream)
+    hev.record(t_end, stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    t_total = t_start.elapsed_time(t_end) / 1e3
-    eval_ms = [a.elapsed_time(b) for a, b in ev]
+    t_total = hev.elapsed_ms(t_start, t_end) / 1e3
+    eval_ms = [hev.elapsed_ms(a, b) for a, b in ev]
+    hev.destroy(t_start, t_end, *[x for pair in ev for x in pair])
     flags = cvw.poll_status(gm, ws)
 
     # residual-only timing (vertex pass + fused cell pass writing R), same state
