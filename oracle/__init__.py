@@ -21,7 +21,8 @@ learned    a learned replacement of the sensor gamma_e: features of the
 """
 from .space import Space, build_space
 from .method import (hermite_at_vertices, vertex_candidates, cell_sensor, sc_weights,
-                     residual, apply_mass_inverse, rk3_step, nodal_interpolate, Params)
+                     residual, apply_mass_inverse, rk3_step, nodal_interpolate, hweno_limit, Params)
 
 __all__ = ["Space", "build_space", "hermite_at_vertices", "vertex_candidates", "cell_sensor",
-           "sc_weights", "residual", "apply_mass_inverse", "rk3_step", "nodal_interpolate", "Params"]
+           "sc_weights", "residual", "apply_mass_inverse", "rk3_step", "nodal_interpolate", "hweno_limit",
+           "Params"]

@@ -18,7 +18,10 @@ the paper's definitions in its order and notation:
 * the stabilised residual of eq. (stabform) / (sdstab) with the DG form
   (P_h = identity on gradients, so s^H = 0) or the simplified CG form
   nu_e (grad v, grad u - gamma_e P_h grad u), and LLF / HLL interface fluxes;
-* the mass matrix solve and the three-stage SSP Runge-Kutta method.
+* the mass matrix solve and the three-stage SSP Runge-Kutta method;
+* the reconstruction used as an HWENO limiter (Sec. 3): on cells with gamma_e
+  below a threshold, u_h^e is overwritten by u_h^{e,*} built from vertex
+  candidates with corrected cell averages (Sec. 3.2), componentwise.
 
 Readings of points the paper leaves open (all listed in the design doc):
 q = 1 for every exponent, lambda_e = max of the wave speed over the volume
@@ -281,6 +284,75 @@ def projected_gradient(sp, Uc):
         for a in range(d):
             np.add.at(acc[v, :, a], sp.cell_dof.ravel(), g[v, :, :, a].ravel())
     return acc / cnt[None, :, None]
+
+
+# ---------------------------------------------------------------------------
+# HWENO limiter (Sec. 3: the cell-vertex reconstruction may overwrite u_h^e
+# by u_h^{e,*}; Sec. 3.2: candidates with corrected cell averages)
+# ---------------------------------------------------------------------------
+def taylor_value(sp, c0, coef, x, x0):
+    """s(x) = c0 + sum_{k in ks} coef[k] (x - x0)^k / k! (eq. taylorcand with its
+    k = 0 term); c0 [E], coef [E, n_k], x [E, n, d], x0 [E, d]; returns [E, n]."""
+    dx = x - x0[:, None, :]
+    out = np.repeat(c0[:, None], x.shape[1], axis=1).astype(np.float64)
+    for ik, k in enumerate(sp.ks):
+        term = coef[:, ik][:, None] * np.ones(x.shape[:2])
+        for a in range(len(k)):
+            term = term * dx[:, :, a] ** k[a] / math.factorial(k[a])
+        out += term
+    return out
+
+
+def hweno_limit(sp, U, prm: Params, threshold: float, gamma=None):
+    """CV-WENO used as an HWENO limiter for DG: on every cell whose sensor value
+    gamma_e (eq. gamma, of the sensor field U[0]) is below `threshold`, the
+    nodal values of u_h^e are replaced by those of u_h^{e,*} = sum_l omega_l^e
+    ubar_{h,l}^e (eq. finalweno) with the cell candidate ubar_0 = u_h^e and the
+    vertex candidates with corrected cell averages,
+        ubar_{h,i}^*(x) = u_{h,i}^*(x) + mean_{K_e}(u_h^e - u_{h,i}^*),
+    where u_{h,i}^* is the Taylor polynomial of eq. (taylorcand) including its
+    k = 0 term sum_e' omega_e'^i u_h^{e'}(x_i).  Each variable is reconstructed
+    with its own candidates and weights (componentwise).
+
+    U: [E, n_loc] (scalar) or [n_var, E, n_loc]; returns the same shape.
+    threshold > 1 limits every cell, threshold <= 0 none.
+    """
+    scalar = np.ndim(U) == 2
+    Us = np.asarray(U, np.float64)[None] if scalar else np.asarray(U, np.float64)
+    if gamma is None:
+        gamma = sensor_gamma(sp, Us[0], prm)
+    troubled = gamma < threshold
+    ref = sp.ref
+    xn = sp.node_coords()                                          # [E, n_loc, d]
+    pts = ref.norm_pts                                             # exact for Q_p products
+    J, _ = map_jacobian(sp.cell, sp.X, pts)
+    W = ref.norm_w[None, :] * np.abs(np.linalg.det(J))             # [E, nq]
+    xq = map_points(sp.cell, sp.X, pts)
+    Bq = ref.deriv(pts, (0,) * ref.dim)                            # values at the rule's points
+    Bv = ref.deriv(ref.vertices, (0,) * ref.dim)                   # values at the vertices
+    cv = sp.mesh.cell_vertices
+    ve = cv.shape[1]
+    pc, plv, ptr = sp.patch_cell, sp.patch_lv, sp.patch_ptr
+    row = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))
+    out = Us.copy()
+    for v in range(Us.shape[0]):
+        s = Us[v]
+        c, omega_ent, _, _ = vertex_candidates(sp, s, prm, return_weights=True)
+        vals = s @ Bv.T                                            # u_h^{e'}(x_i) [E, v_e]
+        c0 = np.zeros(len(ptr) - 1)
+        np.add.at(c0, row, omega_ent * vals[pc, plv])
+        _, parts = cell_sensor(sp, s, c, prm, return_parts=True)
+        om = parts["omega"]                                        # [E, v_e + 1]
+        mean_u = (W * (s @ Bq.T)).sum(1) / W.sum(1)
+        rec = om[:, :1] * s
+        for l in range(ve):
+            i = cv[:, l]
+            at_nodes = taylor_value(sp, c0[i], c[i], xn, sp.X[:, l])
+            at_pts = taylor_value(sp, c0[i], c[i], xq, sp.X[:, l])
+            corr = mean_u - (W * at_pts).sum(1) / W.sum(1)
+            rec = rec + om[:, l + 1][:, None] * (at_nodes + corr[:, None])
+        out[v] = np.where(troubled[:, None], rec, s)
+    return out[0] if scalar else out
 
 
 def sensor_gamma(sp, s, prm: Params):

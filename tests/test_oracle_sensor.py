@@ -30,10 +30,12 @@ def _R(v):
     return symp.Rational(float(v))
 
 
-def _sympy_sensor(mesh, polys, p, integrate, prm):
+def _sympy_sensor(mesh, polys, p, integrate, prm, parts=False):
     """gamma_e and vertex candidates computed with exact rational polynomials
     (sympy Poly in x, y): symbolic derivatives, exact integrals; only the
-    square roots and the weights are taken in floating point."""
+    square roots and the weights are taken in floating point.  parts: also
+    the per-cell weights omega_l^e and vertex candidate polynomials (without
+    their constant terms)."""
     ks = multi_indices(2, p)
     E, ve = mesh.cell_vertices.shape
     X = mesh.cell_coords
@@ -66,7 +68,7 @@ def _sympy_sensor(mesh, polys, p, integrate, prm):
     def seminorm(e, f):
         return math.sqrt(float(sum(hs[e] ** (sum(k) - 1) * integrate(e, D(f, k) ** 2) for k in ks)))
 
-    gam = []
+    gam, oms, cls = [], [], []
     for e in range(E):
         ue = polys[e]
         cl = []
@@ -83,6 +85,10 @@ def _sympy_sensor(mesh, polys, p, integrate, prm):
         diff = sum(((ue - cl[l]) * _R(om[l + 1]) for l in range(ve)), symp.Poly(0, xs, ys))
         n0, d = betas[0], seminorm(e, diff)
         gam.append(1.0 if n0 == 0 else 1.0 - min(1.0, d / n0))
+        oms.append(om)
+        cls.append(cl)
+    if parts:
+        return np.array(gam), np.array([cand[i] for i in range(mesh.n_vertices)]), oms, cls
     return np.array(gam), np.array([cand[i] for i in range(mesh.n_vertices)])
 
 
