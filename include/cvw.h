@@ -167,7 +167,7 @@ cvw_status cvw_mesh_set_grid(cvw_mesh* mesh, int blocks);
 cvw_status cvw_mesh_export(const cvw_mesh* mesh, int which, void* host_dst, size_t bytes);
 
 /* Workspace size in bytes for an operation: 0 = sensor / residual / candidates,
- * 1 = time step.  The workspace holds the vertex candidates, the status word and
+ * 1 = time step, 2 = HWENO limiter.  The workspace holds the vertex candidates, the status word and
  * (time step) the Runge-Kutta stage states; it must stay untouched between the
  * calls of one operation and may be reused afterwards. */
 size_t cvw_workspace_bytes(const cvw_mesh* mesh, const cvw_params* prm, int op);
@@ -189,6 +189,23 @@ cvw_status cvw_vertex_candidates(const cvw_mesh* mesh, const cvw_params* prm, co
  * density (Sec. 5.4). */
 cvw_status cvw_sensor(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* gamma,
                       void* alpha, void* ws, size_t ws_bytes, void* stream);
+
+/* HWENO limiter (Sec. 3: the cell-vertex reconstruction u_h^{e,*} of eq.
+ * finalweno may overwrite the DG solution u_h^e; Sec. 3.2: the vertex
+ * candidates with cell averages corrected to that of u_h^e).  DG
+ * quadrilaterals only.  On every cell whose sensor value gamma_e (eq. gamma,
+ * of the sensor field = variable 0, plain or fixed sensor) is below
+ * `threshold`, the nodal values of each variable are replaced by those of its
+ * own reconstruction (componentwise: each variable with its own vertex
+ * candidates and weights); all other cells are copied unchanged.  Cell
+ * averages are preserved.  threshold > 1 limits every cell, <= 0 none.
+ * u, u_out: device float32 [n_var][E][n_loc]; u_out may be u (in place).
+ * gamma_out: device float32 [E] receiving the sensor values used, or NULL.
+ * ws: cvw_workspace_bytes(mesh, prm, 2) bytes, 256-byte aligned.
+ * Errors: CVW_EUNSUPPORTED for other meshes or the learned sensor, CVW_EINVAL
+ * for null pointers, a NaN threshold or a small workspace. */
+cvw_status cvw_limit(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* u_out, double threshold,
+                     void* gamma_out, void* ws, size_t ws_bytes, void* stream);
 
 /* Stabilised residual R of M dU/dt = -R (eq. stabform / sdstab): Galerkin
  * volume term, the blended stabilisation s_h with nonlinear quadrature

@@ -1069,6 +1069,8 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (prm->sensor == CVW_SENSOR_LEARNED)
     b += align256(static_cast<size_t>(m->E) * MLP_IN * 2) + align256(static_cast<size_t>(m->E) * 4);
   if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
+  if (op == 2)    // limiter: vertex candidates of every variable, and gamma
+    b += align256(static_cast<size_t>(n_var_of(prm->flux)) * m->nk * m->Nv * es) + align256(static_cast<size_t>(m->E) * 4);
   return b;
 }
 
@@ -1234,6 +1236,46 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
   return dgquad_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
                      static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s,
                      w.glearn);
+}
+
+cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, void* u_out, double threshold,
+                     void* gamma_out, void* ws, size_t ws_bytes, void* stream) {
+  cvw_status st = check_common(m, prm, ws_bytes, 2, ws);
+  if (st != CVW_OK) return st;
+  if (!(m->cell == CVW_QUAD && m->space == CVW_DG)) {
+    set_error("HWENO limiter: DG quadrilaterals only"); return CVW_EUNSUPPORTED;
+  }
+  if (prm->sensor == CVW_SENSOR_LEARNED) {
+    set_error("HWENO limiter: plain or fixed sensor"); return CVW_EUNSUPPORTED;
+  }
+  if (!u || !u_out) { set_error("null device pointer"); return CVW_EINVAL; }
+  if (std::isnan(threshold)) { set_error("threshold is NaN"); return CVW_EINVAL; }
+  const WS w = carve(m, prm, ws);
+  auto s = static_cast<hipStream_t>(stream);
+  const int nv = n_var_of(prm->flux);
+  float* cand = static_cast<float*>(w.st1);
+  float* gam = gamma_out ? static_cast<float*>(gamma_out)
+                         : reinterpret_cast<float*>(static_cast<char*>(w.st1) +
+                                                    align256(static_cast<size_t>(nv) * m->nk * m->Nv * 4));
+  const float* uf = static_cast<const float*>(u);
+  // every variable's vertex candidates (all of them read the state before
+  // the limiter writes, so u_out may be u)
+  for (int v = 0; v < nv; ++v)
+    if ((st = dgquad_candidates(m, prm, uf + static_cast<int64_t>(v) * m->E * m->nloc,
+                                cand + static_cast<int64_t>(v) * m->Nv * m->nk, s)) != CVW_OK)
+      return st;
+  // sensor values of the sensor field (variable 0)
+  if ((st = dgquad_eval(m, prm, MODE_SENSOR, uf, nullptr, nullptr, gam, nullptr, cand, w.status, 0.f, 0.f, 0.f, s)) !=
+      CVW_OK)
+    return st;
+  LimitNodes ln{};
+  std::vector<double> x, wq;
+  gauss_rule(m->degree + 1, x, wq);
+  for (int i = 0; i <= m->degree; ++i) {
+    ln.xi[i] = x[i];
+    ln.w[i] = wq[i];
+  }
+  return dgquad_limit(m, prm, uf, static_cast<float*>(u_out), cand, gam, ln, threshold, s);
 }
 
 cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u, void* R, void* gamma_out, void* ws,

@@ -187,6 +187,13 @@ struct CellGeo {
   float hhx, hhy;          // hx / 2, hy / 2
   float nuf;               // h_e / (2 p): nu_e = lambda_e nuf
 };
+// Float64 1D Gauss nodes and weights of the DG quadrilateral element (the
+// limiter evaluates its reconstruction there)
+struct LimitNodes {
+  double xi[MAXP + 1];
+  double w[MAXP + 1];
+};
+
 // Float64 tables of the DG quadrilateral vertex pass for one mesh: L[m][i] =
 // l_i^{(m)}(-1), and per multi-index k (in the order of the derivative set)
 // sk[t] = h_e^{|k|} (2 / h_x)^{kx} (2 / h_y)^{ky}, which turns reference
@@ -307,6 +314,10 @@ cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const flo
 cvw_status dgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0,
                        float* out, float* gamma, float* alpha, const float* cand, uint32_t* status,
                        float dt, float a0, float b0, hipStream_t s, const float* gamma_in = nullptr);
+// HWENO limiter on DG quadrilaterals (cvw_dgquad.hip): cand holds the vertex
+// candidates of every variable, [n_var][Nv][n_k]; gamma the sensor values
+cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, const float* cand,
+                        const float* gamma, const LimitNodes& ln, double threshold, hipStream_t s);
 // learned-sensor features of every cell, bfloat16 [E][48] (cvw_dgquad.hip)
 cvw_status dgquad_features(const cvw_mesh* m, const float* u, const float* cand, double sigma_ref, uint16_t* feat,
                            hipStream_t s);

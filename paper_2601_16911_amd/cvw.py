@@ -20,10 +20,12 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENUMERIC = range(6)
 SEG, TRI, QUAD = 1, 2, 3
 CG, DG = 0, 1
 F32, F64 = 0, 1
+OP_EVAL, OP_STEP, OP_LIMIT = 0, 1, 2
 EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXPORT_CELL_DOF = range(6)
 
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
-           "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_residual",
+           "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_limit",
+           "cvw_residual",
            "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_mesh_plan",
            "cvw_mesh_build_in", "cvw_batch_build",
            "cvw_batch_destroy",
@@ -90,6 +92,7 @@ def load():
     lib.cvw_workspace_bytes.restype = sz
     lib.cvw_vertex_candidates.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, sz, vp]
     lib.cvw_sensor.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, sz, vp]
+    lib.cvw_limit.argtypes = [vp, C.POINTER(ParamsC), vp, vp, C.c_double, vp, vp, sz, vp]
     lib.cvw_residual.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, sz, vp]
     lib.cvw_rk_stage.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                  vp, sz, vp]
@@ -281,6 +284,14 @@ def sensor(mesh, prm, u, gamma, alpha, ws, stream=None):
                              _fp(gamma, prm, i["n_cells"], "gamma"),
                              _fp(alpha, prm, i["n_cells"] * i["n_q"], "alpha"), _ptr(ws), ws.numel(),
                              _stream(stream)))
+
+
+def limit(mesh, prm, u, u_out, threshold: float, gamma_out, ws, stream=None):
+    """HWENO limiter (cvw_limit): u_out may be u; ws from alloc_workspace(mesh, prm, OP_LIMIT)."""
+    n = _state_len(mesh, prm)
+    _check(load().cvw_limit(mesh.handle, C.byref(prm), _fp(u, prm, n, "u"), _fp(u_out, prm, n, "u_out"),
+                            float(threshold), _fp(gamma_out, prm, mesh.info["n_cells"], "gamma_out"), _ptr(ws),
+                            ws.numel(), _stream(stream)))
 
 
 def residual(mesh, prm, u, R, gamma_out, ws, stream=None):

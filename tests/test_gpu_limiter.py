@@ -1,0 +1,155 @@
+"""GPU parity: the HWENO limiter (cvw_limit, DG quadrilaterals) against the
+oracle's hweno_limit on the same float32-rounded inputs.
+
+Tolerance: max |u_gpu - u_oracle| <= 1e-5 max |u| per variable.  The device
+reconstructs in float64 from float32 vertex candidates (relative rounding
+6e-8 of each Hermite datum) and float32 sensor values; the weights move by
+~1e-7 relative, so the nodal values move by ~1e-7 of the data's variation.
+Whether a cell is limited is the float decision gamma_e < threshold: cells
+with |gamma_e - threshold| < 1e-4 are left out of the element-by-element
+comparison (counted), the other cells not limited must be copied bit for bit.
+"""
+import numpy as np
+import pytest
+
+import synth
+from synth import Params
+from oracle import build_space, hweno_limit
+from oracle.method import sensor_gamma
+from tests.parity_helpers import f32, rough_scalar, euler_state, subset_ring
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2601_16911_amd import cvw  # noqa: E402
+
+EULER = Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0))
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32).reshape(-1)).cuda()
+
+
+def _run(gm, prm, u, threshold, in_place=False):
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, cvw.OP_LIMIT)
+    ud = _dev(u)
+    out = ud if in_place else torch.empty_like(ud)
+    gam = torch.empty(gm.info["n_cells"], dtype=torch.float32, device="cuda")
+    cvw.limit(gm, cp, ud, out, threshold, gam, ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().reshape(np.shape(u)), gam.cpu().numpy()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("threshold", [0.9, 2.0])
+def test_limiter_scalar(p, threshold):
+    mesh = synth.quad_mesh(13, 11)
+    sp = build_space(mesh, p, 1)
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    u = f32(rough_scalar(sp, 2))
+    prm = Params()
+    got, gam = _run(gm, prm, u, threshold)
+    g_o = sensor_gamma(sp, u, prm)
+    ref = hweno_limit(sp, u, prm, threshold, gamma=g_o)
+    sure = np.abs(g_o - threshold) >= 1e-4
+    assert (g_o < threshold).sum() >= 3
+    assert np.abs(got - ref)[sure].max() <= 1e-5 * np.abs(u).max()
+    kept = sure & (g_o >= threshold)
+    assert np.array_equal(got[kept], u.astype(np.float32)[kept])
+
+
+@pytest.mark.parametrize("threshold", [0.9, 2.0])
+def test_limiter_euler(threshold):
+    mesh = synth.quad_mesh(10, 9)
+    sp = build_space(mesh, 3, 1, 4)
+    gm = cvw.Mesh(mesh, 3, cvw.DG)
+    U = f32(sp.to_cells(euler_state(sp, k=200.0)))
+    got, gam = _run(gm, EULER, U, threshold)
+    g_o = sensor_gamma(sp, U[0], EULER)
+    ref = hweno_limit(sp, U, EULER, threshold, gamma=g_o)
+    sure = np.abs(g_o - threshold) >= 1e-4
+    assert (g_o < threshold).sum() >= 3
+    for v in range(4):
+        assert np.abs(got[v] - ref[v])[sure].max() <= 1e-5 * np.abs(U[v]).max(), v
+
+
+def test_limiter_in_place_and_gamma_out():
+    mesh = synth.quad_mesh(13, 11)
+    sp = build_space(mesh, 3, 1)
+    gm = cvw.Mesh(mesh, 3, cvw.DG)
+    u = f32(rough_scalar(sp, 2))
+    a, ga = _run(gm, Params(), u, 0.9)
+    b, gb = _run(gm, Params(), u, 0.9, in_place=True)
+    assert np.array_equal(a, b) and np.array_equal(ga, gb)
+    # the sensor values are those of cvw_sensor
+    cp = cvw.make_params(Params())
+    ws = cvw.alloc_workspace(gm, cp, 0)
+    g2 = torch.empty(gm.info["n_cells"], dtype=torch.float32, device="cuda")
+    cvw.sensor(gm, cp, _dev(u), g2, None, ws)
+    assert np.array_equal(ga, g2.cpu().numpy())
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_limiter_preserves_cell_averages(p):
+    mesh = synth.quad_mesh(13, 11)
+    sp = build_space(mesh, p, 1)
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    u = f32(rough_scalar(sp, 2))
+    got, _ = _run(gm, Params(), u, 2.0)
+    w1 = np.polynomial.legendre.leggauss(p + 1)[1]
+    w = np.outer(w1, w1).ravel() / 4.0                 # collocated Gauss rule, node a + (p+1) b
+    m0 = u @ w
+    m1 = got.astype(np.float64) @ w
+    assert np.abs(m1 - m0).max() <= 1e-6 * np.abs(u).max()
+    assert np.abs(got - u).max() > 1e-2
+
+
+def test_limiter_errors():
+    mesh = synth.quad_mesh(8, 8)
+    u = torch.zeros(64 * 9, device="cuda")
+    gc = cvw.Mesh(mesh, 2, cvw.CG)
+    cp = cvw.make_params(Params())
+    with pytest.raises(cvw.CvwError) as ei:
+        cvw.limit(gc, cp, torch.zeros(gc.info["n_dof"], device="cuda"), torch.zeros(gc.info["n_dof"], device="cuda"),
+                  0.9, None, cvw.alloc_workspace(gc, cp, cvw.OP_LIMIT))
+    assert ei.value.status == cvw.EUNSUPPORTED
+    gm = cvw.Mesh(mesh, 2, cvw.DG)
+    ws = cvw.alloc_workspace(gm, cp, cvw.OP_LIMIT)
+    with pytest.raises(cvw.CvwError) as ei:
+        cvw.limit(gm, cp, u, u, float("nan"), None, ws)
+    assert ei.value.status == cvw.EINVAL
+    with pytest.raises(cvw.CvwError) as ei:
+        cvw.limit(gm, cp, u, u, 0.9, None, cvw.alloc_workspace(gm, cp, 0))
+    assert ei.value.status == cvw.EINVAL
+
+
+def test_full_size_config4_limiter_sampled_cells():
+    """1024^2 DG Q3 Euler (the benchmark state), threshold C_gamma = 0.9:
+    sampled cells against the oracle on the sub-mesh of their vertex rings."""
+    n = 1024
+    mesh = synth.quad_mesh(n, n)
+    gm = cvw.Mesh(mesh, 3, cvw.DG)
+    sp_small = build_space(synth.quad_mesh(1, 1, periodic=(False, False)), 3, 1)
+    ref_nodes = sp_small.ref.nodes
+    h = 1.0 / n
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    xc = (ii.ravel() + 0.5) * h
+    yc = (jj.ravel() + 0.5) * h
+    X = xc[:, None] + 0.5 * h * ref_nodes[None, :, 0]
+    Y = yc[:, None] + 0.5 * h * ref_nodes[None, :, 1]
+    U = np.asarray(synth.euler_state_config4(X, Y, smooth_k=400.0), np.float32)   # [4, E, 16]
+    got, gam = _run(gm, EULER, U, 0.9)
+    rng = np.random.default_rng(1)
+    edge = np.nonzero((np.abs(xc - 0.5) < 3 * h) | (np.abs(yc - 0.5) < 3 * h))[0]
+    cells = np.unique(np.concatenate([rng.choice(n * n, 24, replace=False), rng.choice(edge, 40, replace=False),
+                                      [0, n - 1, n * n - 1]]))
+    sub, ids, pos = subset_ring(mesh, cells)
+    sp = build_space(sub, 3, 1, 4)
+    Us = U[:, ids, :].astype(np.float64)
+    g_o = sensor_gamma(sp, Us[0], EULER)
+    ref = hweno_limit(sp, Us, EULER, 0.9, gamma=g_o)[:, pos, :]
+    keep = np.abs(g_o[pos] - 0.9) >= 1e-4
+    assert (g_o[pos] < 0.9).sum() >= 5
+    for v in range(4):
+        assert np.abs(got[v, cells][keep] - ref[v][keep]).max() <= 1e-5 * np.abs(U[v]).max(), v
