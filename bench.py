@@ -269,6 +269,24 @@ def bench_ensemble(torch, cvw, steps: int, tune: bool = True):
     return out
 
 
+def bench_limiter(torch, cvw, gm, prm, U):
+    """The HWENO limiter (cvw_limit) on the benchmark state after the timed
+    steps: every variable's vertex candidates, the sensor, and the
+    componentwise reconstruction of the cells below the threshold, for
+    threshold C_gamma = 0.9 (troubled cells) and 2 (every cell)."""
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, cvw.OP_LIMIT)
+    out = torch.empty_like(U)
+    gam = torch.empty(gm.info["n_cells"], dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {"workload": "HWENO limiter on the 2D Euler DG Q3 1024x1024 state (67108864 DOFs), componentwise"}
+    for name, thr in (("troubled", 0.9), ("all_cells", 2.0)):
+        t = _timed(torch, stream, lambda: cvw.limit(gm, cp, U, out, thr, gam, ws), 5)
+        res[name] = {"threshold": thr, "value": U.numel() / t, "unit": "DOF-updates/s", "ms": t * 1e3}
+    res["limited_cells"] = int((gam < 0.9).sum().item())
+    return res
+
+
 def bench_triangles(torch, cvw, steps: int):
     """512 x 512 squares split into 524,288 jittered triangles, DG P3, KPP."""
     import synth
@@ -457,6 +475,8 @@ def main():
         out["ensemble_batch"] = bench_ensemble(torch, cvw, 10, tune=not args.no_tune)
         torch.cuda.empty_cache()
         out["triangles_kpp"] = bench_triangles(torch, cvw, 5)
+        torch.cuda.empty_cache()
+        out["hweno_limiter"] = bench_limiter(torch, cvw, gm, prm, U)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -1229,18 +1229,35 @@ __device__ __forceinline__ double centred_seminorm_d(const double (&ch)[KSet<P>:
   return hx * hy * tot;
 }
 
+// Cells to reconstruct: list[0 .. *count) (any order: every cell's result is
+// its own), appended by one atomic per selected cell.
+__global__ __launch_bounds__(256) void dgq_limit_select_kernel(const float* __restrict__ gamma, int64_t E,
+                                                               double threshold, uint32_t* __restrict__ count,
+                                                               int32_t* __restrict__ list) {
+  const int64_t e = blockIdx.x * 256LL + threadIdx.x;
+  if (e < E && static_cast<double>(gamma[e]) < threshold) list[atomicAdd(count, 1u)] = static_cast<int32_t>(e);
+}
+
+__global__ void dgq_limit_clear_kernel(uint32_t* __restrict__ count) {
+  if (threadIdx.x == 0) *count = 0u;
+}
+
+// One thread per listed cell (the grid covers every cell; threads past the
+// count leave), or with list == nullptr one thread per cell.  Cells not
+// reconstructed have been copied from u to out beforehand where they differ.
 template <int P, int NV>
 __global__ __launch_bounds__(256) void dgq_limit_kernel(const float* __restrict__ u, float* __restrict__ out,
                                                         const float* __restrict__ cand,
-                                                        const float* __restrict__ gamma,
+                                                        const uint32_t* __restrict__ count,
+                                                        const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ cell_vtx, TensorTables tab,
                                                         LimitNodes ln, int64_t E, int64_t Nv, double hx, double hy,
-                                                        double he, double threshold, MethodScalars ms) {
+                                                        double he, MethodScalars ms) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr KSet<P> ks = kset<P>;
-  const int64_t e = blockIdx.x * 256LL + threadIdx.x;
-  if (e >= E) return;
-  const bool lim = static_cast<double>(gamma[e]) < threshold;
+  const int64_t k = blockIdx.x * 256LL + threadIdx.x;
+  if (k >= (list ? static_cast<int64_t>(*count) : E)) return;
+  const int64_t e = list ? list[k] : k;
   const double sx = 2.0 / hx, sy = 2.0 / hy, he2 = he * he;
   const double lin = ms.lin_wd, lin0 = 1.0 - 4.0 * ms.lin_wd;
   const double q = static_cast<double>(ms.q_beta), rr = static_cast<double>(ms.r);
@@ -1254,13 +1271,6 @@ __global__ __launch_bounds__(256) void dgq_limit_kernel(const float* __restrict_
     float raw[NLOC];
 #pragma unroll
     for (int j = 0; j < NLOC; ++j) raw[j] = ue[j];
-    if (!lim) {
-      if (out != u) {
-#pragma unroll
-        for (int j = 0; j < NLOC; ++j) oe[j] = raw[j];
-      }
-      continue;
-    }
     // data relative to the first node (exact differences in float64)
     const double r0 = raw[0];
     double r[NLOC];
@@ -1358,17 +1368,31 @@ __global__ __launch_bounds__(256) void dgq_limit_kernel(const float* __restrict_
 }
 
 cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, const float* cand,
-                        const float* gamma, const LimitNodes& ln, double threshold, hipStream_t s) {
+                        const float* gamma, const LimitNodes& ln, double threshold, uint32_t* count,
+                        int32_t* list, hipStream_t s) {
   const MethodScalars ms = make_scalars(prm);
   const dim3 g(static_cast<unsigned>((m->E + 255) / 256)), b(256);
   const bool sys = prm->flux == CVW_EULER;
+  // the plain sensor gives gamma_e <= 1: a threshold above 1 (and above a
+  // fixed gamma) selects every cell, which are then taken in order without a list
+  if (threshold > 1.0 && (prm->sensor != CVW_SENSOR_FIXED || prm->fixed_gamma < threshold)) {
+    list = nullptr;
+  } else {
+    if (out != u &&
+        hipMemcpyAsync(out, u, static_cast<size_t>(m->E) * m->nloc * (sys ? 4 : 1) * sizeof(float),
+                       hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      set_error("state copy failed"); return CVW_EDEVICE;
+    }
+    hipLaunchKernelGGL(dgq_limit_clear_kernel, dim3(1), dim3(64), 0, s, count);
+    hipLaunchKernelGGL(dgq_limit_select_kernel, g, b, 0, s, gamma, m->E, threshold, count, list);
+  }
 #define CVW_LIMIT_LAUNCH(P)                                                                                        \
   if (sys)                                                                                                          \
-    hipLaunchKernelGGL((dgq_limit_kernel<P, 4>), g, b, 0, s, u, out, cand, gamma, m->d_cell_vtx, m->tens, ln, m->E, \
-                       m->Nv, m->hx, m->hy, m->he, threshold, ms);                                                  \
+    hipLaunchKernelGGL((dgq_limit_kernel<P, 4>), g, b, 0, s, u, out, cand, count, list, m->d_cell_vtx, m->tens, ln, \
+                       m->E, m->Nv, m->hx, m->hy, m->he, ms);                                                       \
   else                                                                                                              \
-    hipLaunchKernelGGL((dgq_limit_kernel<P, 1>), g, b, 0, s, u, out, cand, gamma, m->d_cell_vtx, m->tens, ln, m->E, \
-                       m->Nv, m->hx, m->hy, m->he, threshold, ms);
+    hipLaunchKernelGGL((dgq_limit_kernel<P, 1>), g, b, 0, s, u, out, cand, count, list, m->d_cell_vtx, m->tens, ln, \
+                       m->E, m->Nv, m->hx, m->hy, m->he, ms);
   switch (m->degree) {
     case 1: CVW_LIMIT_LAUNCH(1) break;
     case 2: CVW_LIMIT_LAUNCH(2) break;

@@ -1069,8 +1069,9 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (prm->sensor == CVW_SENSOR_LEARNED)
     b += align256(static_cast<size_t>(m->E) * MLP_IN * 2) + align256(static_cast<size_t>(m->E) * 4);
   if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
-  if (op == 2)    // limiter: vertex candidates of every variable, and gamma
-    b += align256(static_cast<size_t>(n_var_of(prm->flux)) * m->nk * m->Nv * es) + align256(static_cast<size_t>(m->E) * 4);
+  if (op == 2)    // limiter: vertex candidates of every variable, gamma, the selected cells and their count
+    b += align256(static_cast<size_t>(n_var_of(prm->flux)) * m->nk * m->Nv * es) +
+         2 * align256(static_cast<size_t>(m->E) * 4) + 256;
   return b;
 }
 
@@ -1253,10 +1254,14 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
   const WS w = carve(m, prm, ws);
   auto s = static_cast<hipStream_t>(stream);
   const int nv = n_var_of(prm->flux);
-  float* cand = static_cast<float*>(w.st1);
-  float* gam = gamma_out ? static_cast<float*>(gamma_out)
-                         : reinterpret_cast<float*>(static_cast<char*>(w.st1) +
-                                                    align256(static_cast<size_t>(nv) * m->nk * m->Nv * 4));
+  char* lp = static_cast<char*>(w.st1);
+  float* cand = reinterpret_cast<float*>(lp);
+  lp += align256(static_cast<size_t>(nv) * m->nk * m->Nv * 4);
+  float* gam = gamma_out ? static_cast<float*>(gamma_out) : reinterpret_cast<float*>(lp);
+  lp += align256(static_cast<size_t>(m->E) * 4);
+  int32_t* list = reinterpret_cast<int32_t*>(lp);
+  lp += align256(static_cast<size_t>(m->E) * 4);
+  uint32_t* count = reinterpret_cast<uint32_t*>(lp);
   const float* uf = static_cast<const float*>(u);
   // every variable's vertex candidates (all of them read the state before
   // the limiter writes, so u_out may be u)
@@ -1275,7 +1280,7 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
     ln.xi[i] = x[i];
     ln.w[i] = wq[i];
   }
-  return dgquad_limit(m, prm, uf, static_cast<float*>(u_out), cand, gam, ln, threshold, s);
+  return dgquad_limit(m, prm, uf, static_cast<float*>(u_out), cand, gam, ln, threshold, count, list, s);
 }
 
 cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u, void* R, void* gamma_out, void* ws,
