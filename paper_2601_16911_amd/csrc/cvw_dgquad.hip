@@ -269,12 +269,19 @@ __device__ __forceinline__ void dgq_vertex_body(const float* __restrict__ u, flo
   for (int t = 0; t < NK; ++t) out[t] = static_cast<float>(acc[t] * inv * vt.hinv[ks.x[t] + ks.y[t]]);
 }
 
-template <int P>
+// FLAG: only the vertices with vflag[i] != 0 (the limiter's selected cells)
+template <int P, bool FLAG = false>
 __global__ __launch_bounds__(256) void dgq_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
                                                          const int32_t* __restrict__ vptr,
                                                          const int32_t* __restrict__ vent, int64_t Nv,
-                                                         int64_t nbp, VertexTables vt, MethodScalars ms) {
-  dgq_vertex_body<P>(u, cand, vptr, vent, Nv, xcd_block(blockIdx.x, nbp), vt, ms);
+                                                         int64_t nbp, VertexTables vt, MethodScalars ms,
+                                                         const uint8_t* __restrict__ vflag) {
+  const int64_t blk = xcd_block(blockIdx.x, nbp);
+  if constexpr (FLAG) {
+    const int64_t i = blk * VTX_PER_BLOCK + threadIdx.x;
+    if (i >= Nv || vflag[i] == 0) return;
+  }
+  dgq_vertex_body<P>(u, cand, vptr, vent, Nv, blk, vt, ms);
 }
 
 // ---------------------------------------------------------------------------
@@ -920,19 +927,25 @@ __global__ __launch_bounds__(256) CVW_EVAL_WPE void dgq_eval_kernel(
 static int64_t pad8(int64_t n) { return (n + 7) / 8 * 8; }
 
 template <int P>
-static void launch_vertex(const cvw_mesh* m, const MethodScalars& ms, const float* u, float* cand, hipStream_t s) {
+static void launch_vertex(const cvw_mesh* m, const MethodScalars& ms, const float* u, float* cand,
+                          const uint8_t* vflag, hipStream_t s) {
   const int64_t nb = pad8((m->Nv + VTX_PER_BLOCK - 1) / VTX_PER_BLOCK);
-  hipLaunchKernelGGL(dgq_vertex_kernel<P>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, cand, m->d_vtx_ptr,
-                     m->d_vtx_ent, m->Nv, nb, make_vertex_tables(m->tens, m->hx, m->hy, m->he, P), ms);
+  const VertexTables vt = make_vertex_tables(m->tens, m->hx, m->hy, m->he, P);
+  if (vflag)
+    hipLaunchKernelGGL((dgq_vertex_kernel<P, true>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, cand,
+                       m->d_vtx_ptr, m->d_vtx_ent, m->Nv, nb, vt, ms, vflag);
+  else
+    hipLaunchKernelGGL((dgq_vertex_kernel<P, false>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, cand,
+                       m->d_vtx_ptr, m->d_vtx_ent, m->Nv, nb, vt, ms, vflag);
 }
 
 cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand,
-                             hipStream_t s) {
+                             hipStream_t s, const uint8_t* vflag) {
   const MethodScalars ms = make_scalars(prm);
   switch (m->degree) {
-    case 1: launch_vertex<1>(m, ms, u, cand, s); break;
-    case 2: launch_vertex<2>(m, ms, u, cand, s); break;
-    case 3: launch_vertex<3>(m, ms, u, cand, s); break;
+    case 1: launch_vertex<1>(m, ms, u, cand, vflag, s); break;
+    case 2: launch_vertex<2>(m, ms, u, cand, vflag, s); break;
+    case 3: launch_vertex<3>(m, ms, u, cand, vflag, s); break;
     default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
   }
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
@@ -1242,6 +1255,23 @@ __global__ void dgq_limit_clear_kernel(uint32_t* __restrict__ count) {
   if (threadIdx.x == 0) *count = 0u;
 }
 
+__global__ __launch_bounds__(256) void dgq_limit_clear_flags_kernel(uint8_t* __restrict__ vflag, int64_t Nv) {
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i < Nv) vflag[i] = 0;
+}
+
+// flags the vertices of the listed cells (their candidates are needed)
+__global__ __launch_bounds__(256) void dgq_limit_mark_kernel(const uint32_t* __restrict__ count,
+                                                             const int32_t* __restrict__ list,
+                                                             const int32_t* __restrict__ cell_vtx,
+                                                             uint8_t* __restrict__ vflag, int64_t E) {
+  const int64_t k = blockIdx.x * 256LL + threadIdx.x;
+  if (k >= static_cast<int64_t>(*count) || k >= E) return;
+  const int64_t e = list[k];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) vflag[cell_vtx[e * 4 + l]] = 1;
+}
+
 // One thread per listed cell (the grid covers every cell; threads past the
 // count leave), or with list == nullptr one thread per cell.  Cells not
 // reconstructed have been copied from u to out beforehand where they differ.
@@ -1367,24 +1397,41 @@ __global__ __launch_bounds__(256) void dgq_limit_kernel(const float* __restrict_
   }
 }
 
-cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, const float* cand,
+cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, float* cand,
                         const float* gamma, const LimitNodes& ln, double threshold, uint32_t* count,
-                        int32_t* list, hipStream_t s) {
+                        int32_t* list, uint8_t* vflag, hipStream_t s) {
   const MethodScalars ms = make_scalars(prm);
   const dim3 g(static_cast<unsigned>((m->E + 255) / 256)), b(256);
   const bool sys = prm->flux == CVW_EULER;
+  const int nv = sys ? 4 : 1;
+  cvw_status st;
   // the plain sensor gives gamma_e <= 1: a threshold above 1 (and above a
-  // fixed gamma) selects every cell, which are then taken in order without a list
+  // fixed gamma) selects every cell, which are then taken in order without a
+  // list, and every vertex needs the candidates of every variable
   if (threshold > 1.0 && (prm->sensor != CVW_SENSOR_FIXED || prm->fixed_gamma < threshold)) {
     list = nullptr;
+    for (int v = 1; v < nv; ++v)
+      if ((st = dgquad_candidates(m, prm, u + static_cast<int64_t>(v) * m->E * m->nloc,
+                                  cand + static_cast<int64_t>(v) * m->Nv * m->nk, s)) != CVW_OK)
+        return st;
   } else {
     if (out != u &&
-        hipMemcpyAsync(out, u, static_cast<size_t>(m->E) * m->nloc * (sys ? 4 : 1) * sizeof(float),
-                       hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        hipMemcpyAsync(out, u, static_cast<size_t>(m->E) * m->nloc * nv * sizeof(float), hipMemcpyDeviceToDevice,
+                       s) != hipSuccess) {
       set_error("state copy failed"); return CVW_EDEVICE;
     }
     hipLaunchKernelGGL(dgq_limit_clear_kernel, dim3(1), dim3(64), 0, s, count);
     hipLaunchKernelGGL(dgq_limit_select_kernel, g, b, 0, s, gamma, m->E, threshold, count, list);
+    if (nv > 1) {
+      // the other variables' candidates only at the vertices of selected cells
+      hipLaunchKernelGGL(dgq_limit_clear_flags_kernel, dim3(static_cast<unsigned>((m->Nv + 255) / 256)), b, 0, s,
+                         vflag, m->Nv);
+      hipLaunchKernelGGL(dgq_limit_mark_kernel, g, b, 0, s, count, list, m->d_cell_vtx, vflag, m->E);
+      for (int v = 1; v < nv; ++v)
+        if ((st = dgquad_candidates(m, prm, u + static_cast<int64_t>(v) * m->E * m->nloc,
+                                    cand + static_cast<int64_t>(v) * m->Nv * m->nk, s, vflag)) != CVW_OK)
+          return st;
+    }
   }
 #define CVW_LIMIT_LAUNCH(P)                                                                                        \
   if (sys)                                                                                                          \

@@ -1071,7 +1071,7 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
   if (op == 2)    // limiter: vertex candidates of every variable, gamma, the selected cells and their count
     b += align256(static_cast<size_t>(n_var_of(prm->flux)) * m->nk * m->Nv * es) +
-         2 * align256(static_cast<size_t>(m->E) * 4) + 256;
+         2 * align256(static_cast<size_t>(m->E) * 4) + 256 + align256(static_cast<size_t>(m->Nv));
   return b;
 }
 
@@ -1262,13 +1262,13 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
   int32_t* list = reinterpret_cast<int32_t*>(lp);
   lp += align256(static_cast<size_t>(m->E) * 4);
   uint32_t* count = reinterpret_cast<uint32_t*>(lp);
+  lp += 256;
+  uint8_t* vflag = reinterpret_cast<uint8_t*>(lp);
   const float* uf = static_cast<const float*>(u);
-  // every variable's vertex candidates (all of them read the state before
-  // the limiter writes, so u_out may be u)
-  for (int v = 0; v < nv; ++v)
-    if ((st = dgquad_candidates(m, prm, uf + static_cast<int64_t>(v) * m->E * m->nloc,
-                                cand + static_cast<int64_t>(v) * m->Nv * m->nk, s)) != CVW_OK)
-      return st;
+  // the sensor field's vertex candidates (the other variables' follow inside
+  // the limiter, where they are needed; every candidate is taken from the
+  // state before the reconstruction writes, so u_out may be u)
+  if ((st = dgquad_candidates(m, prm, uf, cand, s)) != CVW_OK) return st;
   // sensor values of the sensor field (variable 0)
   if ((st = dgquad_eval(m, prm, MODE_SENSOR, uf, nullptr, nullptr, gam, nullptr, cand, w.status, 0.f, 0.f, 0.f, s)) !=
       CVW_OK)
@@ -1280,7 +1280,7 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
     ln.xi[i] = x[i];
     ln.w[i] = wq[i];
   }
-  return dgquad_limit(m, prm, uf, static_cast<float*>(u_out), cand, gam, ln, threshold, count, list, s);
+  return dgquad_limit(m, prm, uf, static_cast<float*>(u_out), cand, gam, ln, threshold, count, list, vflag, s);
 }
 
 cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u, void* R, void* gamma_out, void* ws,
