@@ -214,16 +214,13 @@ __device__ __forceinline__ double vertex_cell(const float* __restrict__ ue, int 
   return b2;
 }
 
-// One block of 256 vertices (logical block index blk).
+// The candidate data of vertex i.
 template <int P>
-__device__ __forceinline__ void dgq_vertex_body(const float* __restrict__ u, float* __restrict__ cand,
-                                                const int32_t* __restrict__ vptr, const int32_t* __restrict__ vent,
-                                                int64_t Nv, int64_t blk, const VertexTables& vt,
-                                                const MethodScalars& ms) {
+__device__ __forceinline__ void dgq_vertex_at(const float* __restrict__ u, float* __restrict__ cand,
+                                              const int32_t* __restrict__ vptr, const int32_t* __restrict__ vent,
+                                              int64_t i, const VertexTables& vt, const MethodScalars& ms) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr KSet<P> ks = kset<P>;
-  const int64_t i = blk * VTX_PER_BLOCK + threadIdx.x;
-  if (i >= Nv) return;
   double acc[NK];
 #pragma unroll
   for (int t = 0; t < NK; ++t) acc[t] = 0.0;
@@ -269,19 +266,37 @@ __device__ __forceinline__ void dgq_vertex_body(const float* __restrict__ u, flo
   for (int t = 0; t < NK; ++t) out[t] = static_cast<float>(acc[t] * inv * vt.hinv[ks.x[t] + ks.y[t]]);
 }
 
-// FLAG: only the vertices with vflag[i] != 0 (the limiter's selected cells)
-template <int P, bool FLAG = false>
+// One block of 256 vertices (logical block index blk).
+template <int P>
+__device__ __forceinline__ void dgq_vertex_body(const float* __restrict__ u, float* __restrict__ cand,
+                                                const int32_t* __restrict__ vptr, const int32_t* __restrict__ vent,
+                                                int64_t Nv, int64_t blk, const VertexTables& vt,
+                                                const MethodScalars& ms) {
+  const int64_t i = blk * VTX_PER_BLOCK + threadIdx.x;
+  if (i >= Nv) return;
+  dgq_vertex_at<P>(u, cand, vptr, vent, i, vt, ms);
+}
+
+template <int P>
 __global__ __launch_bounds__(256) void dgq_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
                                                          const int32_t* __restrict__ vptr,
                                                          const int32_t* __restrict__ vent, int64_t Nv,
-                                                         int64_t nbp, VertexTables vt, MethodScalars ms,
-                                                         const uint8_t* __restrict__ vflag) {
-  const int64_t blk = xcd_block(blockIdx.x, nbp);
-  if constexpr (FLAG) {
-    const int64_t i = blk * VTX_PER_BLOCK + threadIdx.x;
-    if (i >= Nv || vflag[i] == 0) return;
-  }
-  dgq_vertex_body<P>(u, cand, vptr, vent, Nv, blk, vt, ms);
+                                                         int64_t nbp, VertexTables vt, MethodScalars ms) {
+  dgq_vertex_body<P>(u, cand, vptr, vent, Nv, xcd_block(blockIdx.x, nbp), vt, ms);
+}
+
+// The listed vertices vlist[0 .. *count) only (the grid covers every vertex;
+// threads past the count leave).
+template <int P>
+__global__ __launch_bounds__(256) void dgq_vertex_list_kernel(const float* __restrict__ u, float* __restrict__ cand,
+                                                              const int32_t* __restrict__ vptr,
+                                                              const int32_t* __restrict__ vent, int64_t Nv,
+                                                              VertexTables vt, MethodScalars ms,
+                                                              const uint32_t* __restrict__ count,
+                                                              const int32_t* __restrict__ vlist) {
+  const int64_t k = blockIdx.x * 256LL + threadIdx.x;
+  if (k >= static_cast<int64_t>(*count) || k >= Nv) return;
+  dgq_vertex_at<P>(u, cand, vptr, vent, vlist[k], vt, ms);
 }
 
 // ---------------------------------------------------------------------------
@@ -928,24 +943,24 @@ static int64_t pad8(int64_t n) { return (n + 7) / 8 * 8; }
 
 template <int P>
 static void launch_vertex(const cvw_mesh* m, const MethodScalars& ms, const float* u, float* cand,
-                          const uint8_t* vflag, hipStream_t s) {
+                          const uint32_t* vcount, const int32_t* vlist, hipStream_t s) {
   const int64_t nb = pad8((m->Nv + VTX_PER_BLOCK - 1) / VTX_PER_BLOCK);
   const VertexTables vt = make_vertex_tables(m->tens, m->hx, m->hy, m->he, P);
-  if (vflag)
-    hipLaunchKernelGGL((dgq_vertex_kernel<P, true>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, cand,
-                       m->d_vtx_ptr, m->d_vtx_ent, m->Nv, nb, vt, ms, vflag);
+  if (vlist)
+    hipLaunchKernelGGL(dgq_vertex_list_kernel<P>, dim3(static_cast<unsigned>((m->Nv + 255) / 256)), dim3(256), 0,
+                       s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->Nv, vt, ms, vcount, vlist);
   else
-    hipLaunchKernelGGL((dgq_vertex_kernel<P, false>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, cand,
-                       m->d_vtx_ptr, m->d_vtx_ent, m->Nv, nb, vt, ms, vflag);
+    hipLaunchKernelGGL(dgq_vertex_kernel<P>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, cand,
+                       m->d_vtx_ptr, m->d_vtx_ent, m->Nv, nb, vt, ms);
 }
 
 cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand,
-                             hipStream_t s, const uint8_t* vflag) {
+                             hipStream_t s, const uint32_t* vcount, const int32_t* vlist) {
   const MethodScalars ms = make_scalars(prm);
   switch (m->degree) {
-    case 1: launch_vertex<1>(m, ms, u, cand, vflag, s); break;
-    case 2: launch_vertex<2>(m, ms, u, cand, vflag, s); break;
-    case 3: launch_vertex<3>(m, ms, u, cand, vflag, s); break;
+    case 1: launch_vertex<1>(m, ms, u, cand, vcount, vlist, s); break;
+    case 2: launch_vertex<2>(m, ms, u, cand, vcount, vlist, s); break;
+    case 3: launch_vertex<3>(m, ms, u, cand, vcount, vlist, s); break;
     default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
   }
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
@@ -1242,17 +1257,52 @@ __device__ __forceinline__ double centred_seminorm_d(const double (&ch)[KSet<P>:
   return hx * hy * tot;
 }
 
-// Cells to reconstruct: list[0 .. *count) (any order: every cell's result is
-// its own), appended by one atomic per selected cell.
-__global__ __launch_bounds__(256) void dgq_limit_select_kernel(const float* __restrict__ gamma, int64_t E,
-                                                               double threshold, uint32_t* __restrict__ count,
-                                                               int32_t* __restrict__ list) {
-  const int64_t e = blockIdx.x * 256LL + threadIdx.x;
-  if (e < E && static_cast<double>(gamma[e]) < threshold) list[atomicAdd(count, 1u)] = static_cast<int32_t>(e);
+// Appends the ids of the selected threads of a 1024-thread block to
+// list[0 .. *count): one atomic per block (atomics on one address serialise
+// in the cache, so they are kept few), the threads in order behind it (the
+// blocks in any order).  Every thread of the block must call it.
+__device__ __forceinline__ void append_selected(bool sel, int64_t id, uint32_t* __restrict__ count,
+                                                int32_t* __restrict__ list) {
+  __shared__ uint32_t wbase[16];
+  __shared__ uint32_t bbase;
+  const uint64_t mask = __builtin_amdgcn_ballot_w64(sel);
+  const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) wbase[wave] = static_cast<uint32_t>(__builtin_popcountll(mask));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < 16; ++w) {
+      const uint32_t c = wbase[w];
+      wbase[w] = run;
+      run += c;
+    }
+    bbase = run ? atomicAdd(count, run) : 0u;
+  }
+  __syncthreads();
+  if (sel) list[bbase + wbase[wave] + below] = static_cast<int32_t>(id);
+}
+
+// Cells to reconstruct: list[0 .. count[0]) (any order: every cell's result
+// is its own).
+__global__ __launch_bounds__(1024) void dgq_limit_select_kernel(const float* __restrict__ gamma, int64_t E,
+                                                                double threshold, uint32_t* __restrict__ count,
+                                                                int32_t* __restrict__ list) {
+  const int64_t e = blockIdx.x * 1024LL + threadIdx.x;
+  append_selected(e < E && static_cast<double>(gamma[e]) < threshold, e, count, list);
+}
+
+// Vertices of the selected cells: vlist[0 .. count[1]).
+__global__ __launch_bounds__(1024) void dgq_limit_select_vertices_kernel(const uint8_t* __restrict__ vflag,
+                                                                         int64_t Nv, uint32_t* __restrict__ count,
+                                                                         int32_t* __restrict__ vlist) {
+  const int64_t i = blockIdx.x * 1024LL + threadIdx.x;
+  append_selected(i < Nv && vflag[i] != 0, i, count + 1, vlist);
 }
 
 __global__ void dgq_limit_clear_kernel(uint32_t* __restrict__ count) {
-  if (threadIdx.x == 0) *count = 0u;
+  if (threadIdx.x < 2) count[threadIdx.x] = 0u;
 }
 
 __global__ __launch_bounds__(256) void dgq_limit_clear_flags_kernel(uint8_t* __restrict__ vflag, int64_t Nv) {
@@ -1272,9 +1322,9 @@ __global__ __launch_bounds__(256) void dgq_limit_mark_kernel(const uint32_t* __r
   for (int l = 0; l < 4; ++l) vflag[cell_vtx[e * 4 + l]] = 1;
 }
 
-// One thread per listed cell (the grid covers every cell; threads past the
-// count leave), or with list == nullptr one thread per cell.  Cells not
-// reconstructed have been copied from u to out beforehand where they differ.
+// One thread per (listed cell, variable) (the grid covers every cell; threads
+// past the count leave), or with list == nullptr per (cell, variable).  Cells
+// not reconstructed have been copied from u to out beforehand where they differ.
 template <int P, int NV>
 __global__ __launch_bounds__(256) void dgq_limit_kernel(const float* __restrict__ u, float* __restrict__ out,
                                                         const float* __restrict__ cand,
@@ -1285,7 +1335,8 @@ __global__ __launch_bounds__(256) void dgq_limit_kernel(const float* __restrict_
                                                         double he, MethodScalars ms) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
   constexpr KSet<P> ks = kset<P>;
-  const int64_t k = blockIdx.x * 256LL + threadIdx.x;
+  const int64_t k = (blockIdx.x * 256LL + threadIdx.x) / NV;
+  const int v = static_cast<int>((blockIdx.x * 256LL + threadIdx.x) % NV);
   if (k >= (list ? static_cast<int64_t>(*count) : E)) return;
   const int64_t e = list ? list[k] : k;
   const double sx = 2.0 / hx, sy = 2.0 / hy, he2 = he * he;
@@ -1294,8 +1345,7 @@ __global__ __launch_bounds__(256) void dgq_limit_kernel(const float* __restrict_
   int32_t vtx[4];
 #pragma unroll
   for (int l = 0; l < 4; ++l) vtx[l] = cell_vtx[e * 4 + l];
-#pragma unroll 1
-  for (int v = 0; v < NV; ++v) {
+  {
     const float* ue = u + (static_cast<int64_t>(v) * E + e) * NLOC;
     float* oe = out + (static_cast<int64_t>(v) * E + e) * NLOC;
     float raw[NLOC];
@@ -1399,11 +1449,12 @@ __global__ __launch_bounds__(256) void dgq_limit_kernel(const float* __restrict_
 
 cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, float* cand,
                         const float* gamma, const LimitNodes& ln, double threshold, uint32_t* count,
-                        int32_t* list, uint8_t* vflag, hipStream_t s) {
+                        int32_t* list, uint8_t* vflag, int32_t* vlist, hipStream_t s) {
   const MethodScalars ms = make_scalars(prm);
   const dim3 g(static_cast<unsigned>((m->E + 255) / 256)), b(256);
   const bool sys = prm->flux == CVW_EULER;
   const int nv = sys ? 4 : 1;
+  const dim3 gv(static_cast<unsigned>((m->E * nv + 255) / 256));
   cvw_status st;
   // the plain sensor gives gamma_e <= 1: a threshold above 1 (and above a
   // fixed gamma) selects every cell, which are then taken in order without a
@@ -1421,24 +1472,28 @@ cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u
       set_error("state copy failed"); return CVW_EDEVICE;
     }
     hipLaunchKernelGGL(dgq_limit_clear_kernel, dim3(1), dim3(64), 0, s, count);
-    hipLaunchKernelGGL(dgq_limit_select_kernel, g, b, 0, s, gamma, m->E, threshold, count, list);
+    hipLaunchKernelGGL(dgq_limit_select_kernel, dim3(static_cast<unsigned>((m->E + 1023) / 1024)), dim3(1024), 0, s,
+                       gamma, m->E, threshold, count, list);
     if (nv > 1) {
       // the other variables' candidates only at the vertices of selected cells
       hipLaunchKernelGGL(dgq_limit_clear_flags_kernel, dim3(static_cast<unsigned>((m->Nv + 255) / 256)), b, 0, s,
                          vflag, m->Nv);
       hipLaunchKernelGGL(dgq_limit_mark_kernel, g, b, 0, s, count, list, m->d_cell_vtx, vflag, m->E);
+      hipLaunchKernelGGL(dgq_limit_select_vertices_kernel, dim3(static_cast<unsigned>((m->Nv + 1023) / 1024)),
+                         dim3(1024), 0, s, vflag, m->Nv, count, vlist);
       for (int v = 1; v < nv; ++v)
         if ((st = dgquad_candidates(m, prm, u + static_cast<int64_t>(v) * m->E * m->nloc,
-                                    cand + static_cast<int64_t>(v) * m->Nv * m->nk, s, vflag)) != CVW_OK)
+                                    cand + static_cast<int64_t>(v) * m->Nv * m->nk, s, count + 1, vlist)) !=
+            CVW_OK)
           return st;
     }
   }
 #define CVW_LIMIT_LAUNCH(P)                                                                                        \
   if (sys)                                                                                                          \
-    hipLaunchKernelGGL((dgq_limit_kernel<P, 4>), g, b, 0, s, u, out, cand, count, list, m->d_cell_vtx, m->tens, ln, \
+    hipLaunchKernelGGL((dgq_limit_kernel<P, 4>), gv, b, 0, s, u, out, cand, count, list, m->d_cell_vtx, m->tens, ln,\
                        m->E, m->Nv, m->hx, m->hy, m->he, ms);                                                       \
   else                                                                                                              \
-    hipLaunchKernelGGL((dgq_limit_kernel<P, 1>), g, b, 0, s, u, out, cand, count, list, m->d_cell_vtx, m->tens, ln, \
+    hipLaunchKernelGGL((dgq_limit_kernel<P, 1>), gv, b, 0, s, u, out, cand, count, list, m->d_cell_vtx, m->tens, ln,\
                        m->E, m->Nv, m->hx, m->hy, m->he, ms);
   switch (m->degree) {
     case 1: CVW_LIMIT_LAUNCH(1) break;

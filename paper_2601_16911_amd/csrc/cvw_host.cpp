@@ -1071,7 +1071,8 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
   if (op == 2)    // limiter: vertex candidates of every variable, gamma, the selected cells and their count
     b += align256(static_cast<size_t>(n_var_of(prm->flux)) * m->nk * m->Nv * es) +
-         2 * align256(static_cast<size_t>(m->E) * 4) + 256 + align256(static_cast<size_t>(m->Nv));
+         2 * align256(static_cast<size_t>(m->E) * 4) + 256 + align256(static_cast<size_t>(m->Nv)) +
+         align256(static_cast<size_t>(m->Nv) * 4);
   return b;
 }
 
@@ -1264,6 +1265,8 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
   uint32_t* count = reinterpret_cast<uint32_t*>(lp);
   lp += 256;
   uint8_t* vflag = reinterpret_cast<uint8_t*>(lp);
+  lp += align256(static_cast<size_t>(m->Nv));
+  int32_t* vlist = reinterpret_cast<int32_t*>(lp);
   const float* uf = static_cast<const float*>(u);
   // the sensor field's vertex candidates (the other variables' follow inside
   // the limiter, where they are needed; every candidate is taken from the
@@ -1280,7 +1283,8 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
     ln.xi[i] = x[i];
     ln.w[i] = wq[i];
   }
-  return dgquad_limit(m, prm, uf, static_cast<float*>(u_out), cand, gam, ln, threshold, count, list, vflag, s);
+  return dgquad_limit(m, prm, uf, static_cast<float*>(u_out), cand, gam, ln, threshold, count, list, vflag, vlist,
+                      s);
 }
 
 cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u, void* R, void* gamma_out, void* ws,

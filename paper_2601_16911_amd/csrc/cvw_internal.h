@@ -310,17 +310,18 @@ int n_var_of(int flux);
 
 // kernel launchers (cvw_dgquad.hip)
 cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand,
-                             hipStream_t s, const uint8_t* vflag = nullptr);
+                             hipStream_t s, const uint32_t* vcount = nullptr, const int32_t* vlist = nullptr);
 cvw_status dgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0,
                        float* out, float* gamma, float* alpha, const float* cand, uint32_t* status,
                        float dt, float a0, float b0, hipStream_t s, const float* gamma_in = nullptr);
 // HWENO limiter on DG quadrilaterals (cvw_dgquad.hip): cand holds the vertex
 // candidates of every variable, [n_var][Nv][n_k], variable 0 already
-// computed; gamma the sensor values; count (one word), list (E entries) and
-// vflag (Nv bytes) are scratch for the selected cells and their vertices
+// computed; gamma the sensor values; count (two words), list (E entries),
+// vflag (Nv bytes) and vlist (Nv entries) are scratch for the selected cells
+// and their vertices
 cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, float* cand,
                         const float* gamma, const LimitNodes& ln, double threshold, uint32_t* count,
-                        int32_t* list, uint8_t* vflag, hipStream_t s);
+                        int32_t* list, uint8_t* vflag, int32_t* vlist, hipStream_t s);
 // learned-sensor features of every cell, bfloat16 [E][48] (cvw_dgquad.hip)
 cvw_status dgquad_features(const cvw_mesh* m, const float* u, const float* cand, double sigma_ref, uint16_t* feat,
                            hipStream_t s);
