@@ -62,7 +62,7 @@ def kernel_source_hash() -> str:
     valid only for the kernel they were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("cvw_dgquad.hip", "cvw_device.h", "cvw_internal.h"):
+    for f in ("cvw_dgquad.hip", "cvw_device.h", "cvw_internal.h", "cvw_dgq_common.h"):
         with open(os.path.join(ROOT, "paper_2601_16911_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
