@@ -59,11 +59,11 @@ def test_limiter_scalar(p, threshold):
     assert np.array_equal(got[kept], u.astype(np.float32)[kept])
 
 
-@pytest.mark.parametrize("threshold", [0.9, 2.0])
-def test_limiter_euler(threshold):
+@pytest.mark.parametrize("p,threshold", [(3, 0.9), (3, 2.0), (1, 2.0), (2, 0.9)])
+def test_limiter_euler(p, threshold):
     mesh = synth.quad_mesh(10, 9)
-    sp = build_space(mesh, 3, 1, 4)
-    gm = cvw.Mesh(mesh, 3, cvw.DG)
+    sp = build_space(mesh, p, 1, 4)
+    gm = cvw.Mesh(mesh, p, cvw.DG)
     U = f32(sp.to_cells(euler_state(sp, k=200.0)))
     got, gam = _run(gm, EULER, U, threshold)
     g_o = sensor_gamma(sp, U[0], EULER)
@@ -72,6 +72,25 @@ def test_limiter_euler(threshold):
     assert (g_o < threshold).sum() >= 3
     for v in range(4):
         assert np.abs(got[v] - ref[v])[sure].max() <= 1e-5 * np.abs(U[v]).max(), v
+
+
+@pytest.mark.parametrize("fixed,threshold", [(0.5, 0.9), (0.95, 0.9), (1.5, 2.0), (2.5, 2.0)])
+def test_limiter_fixed_sensor(fixed, threshold):
+    """gamma_e = fixed everywhere: every cell or none is reconstructed (the
+    direct every-cell path only when the fixed value is below the threshold)."""
+    mesh = synth.quad_mesh(13, 11)
+    sp = build_space(mesh, 2, 1)
+    gm = cvw.Mesh(mesh, 2, cvw.DG)
+    u = f32(rough_scalar(sp, 2))
+    prm = Params(sensor=2, fixed_gamma=fixed)
+    got, gam = _run(gm, prm, u, threshold)
+    assert np.all(gam == np.float32(fixed))
+    ref = hweno_limit(sp, u, prm, threshold)
+    if fixed < threshold:
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(u).max()
+        assert np.abs(got - u).max() > 1e-2
+    else:
+        assert np.array_equal(got, u.astype(np.float32))
 
 
 def test_limiter_in_place_and_gamma_out():
