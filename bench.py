@@ -269,7 +269,7 @@ def bench_ensemble(torch, cvw, steps: int, tune: bool = True):
     return out
 
 
-def bench_limiter(torch, cvw, gm, prm, U):
+def bench_limiter(torch, cvw, gm, prm, U, dt):
     """The HWENO limiter (cvw_limit) on the benchmark state after the timed
     steps: every variable's vertex candidates, the sensor, and the
     componentwise reconstruction of the cells below the threshold, for
@@ -284,6 +284,27 @@ def bench_limiter(torch, cvw, gm, prm, U):
         t = _timed(torch, stream, lambda: cvw.limit(gm, cp, U, out, thr, gam, ws), 5)
         res[name] = {"threshold": thr, "value": U.numel() / t, "unit": "DOF-updates/s", "ms": t * 1e3}
     res["limited_cells"] = int((gam < 0.9).sum().item())
+    # in place, and the RKDG step: SSP-RK3 of the DG residual without
+    # artificial viscosity (gamma = 1, SC off), the limiter after every stage
+    Ui = U.clone()
+    t = _timed(torch, stream, lambda: cvw.limit(gm, cp, Ui, Ui, 0.9, None, ws), 5)
+    res["troubled_in_place"] = {"threshold": 0.9, "value": U.numel() / t, "unit": "DOF-updates/s", "ms": t * 1e3}
+    import synth
+    pr = cvw.make_params(synth.Params(**{**prm.__dict__, "sensor": 2, "fixed_gamma": 1.0, "sc_on": 0}))
+    wr = cvw.alloc_workspace(gm, pr, 0)
+    cand = torch.zeros((gm.info["n_vertices"], gm.info["n_k"]), dtype=torch.float32, device="cuda")
+    Ur, S1, S2 = U.clone(), torch.empty_like(U), torch.empty_like(U)
+
+    def rkdg_step():
+        for us, un, uo, a0, b0 in ((Ur, None, S1, 0.0, 1.0), (S1, Ur, S2, 0.75, 0.25),
+                                   (S2, Ur, Ur, 1.0 / 3.0, 2.0 / 3.0)):
+            cvw.rk_stage(gm, pr, us, cand, un, uo, dt, a0, b0, wr)
+            cvw.limit(gm, cp, uo, uo, 0.9, None, ws)
+
+    t = _timed(torch, stream, rkdg_step, 3)
+    res["rkdg_step"] = {"value": 3 * U.numel() / t, "unit": "DOF-updates/s", "ms_per_step": t * 1e3,
+                        "finite": bool(torch.isfinite(Ur).all().item()),
+                        "min_density": float(Ur[: U.numel() // 4].min().item())}
     return res
 
 
@@ -476,7 +497,7 @@ def main():
         torch.cuda.empty_cache()
         out["triangles_kpp"] = bench_triangles(torch, cvw, 5)
         torch.cuda.empty_cache()
-        out["hweno_limiter"] = bench_limiter(torch, cvw, gm, prm, U)
+        out["hweno_limiter"] = bench_limiter(torch, cvw, gm, prm, U, dt)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
