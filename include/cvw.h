@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 3
+#define CVW_ABI_VERSION 4
 
 typedef enum {
   CVW_OK = 0,
