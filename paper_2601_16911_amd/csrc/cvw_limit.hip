@@ -12,8 +12,8 @@ namespace cvw {
 //   u_h^{e,*} = w_0 u_h^e + (1 - w_0) mean(u_h^e) + V - mean(V),
 //   V(x) = sum_{|k|>=1} cb_k (x - x_c)^k / k!,  cb = sum_{l>=1} w_l D^k u_{h,l}(x_c),
 // since the constant terms of the candidates cancel in the correction.  One
-// thread per cell, float64 inside, each variable with its own candidates and
-// weights (componentwise).
+// thread per (cell, variable), float64 inside, each variable with its own
+// candidates and weights (componentwise).
 // ---------------------------------------------------------------------------
 template <int P>
 __device__ __forceinline__ void taylor_move_d(const double (&c)[KSet<P>::NK], double X, double Y,
