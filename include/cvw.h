@@ -199,7 +199,8 @@ cvw_status cvw_sensor(const cvw_mesh* mesh, const cvw_params* prm, const void* u
  * own reconstruction (componentwise: each variable with its own vertex
  * candidates and weights); all other cells are copied unchanged.  Cell
  * averages are preserved.  threshold > 1 limits every cell, <= 0 none.
- * u, u_out: device float32 [n_var][E][n_loc]; u_out may be u (in place).
+ * u, u_out: device float32 [n_var][E][n_loc]; u_out may be u (in place),
+ * any other overlap is rejected (CVW_EINVAL).
  * gamma_out: device float32 [E] receiving the sensor values used, or NULL.
  * ws: cvw_workspace_bytes(mesh, prm, 2) bytes, 256-byte aligned.
  * Errors: CVW_EUNSUPPORTED for other meshes or the learned sensor, CVW_EINVAL

@@ -1252,9 +1252,15 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
   }
   if (!u || !u_out) { set_error("null device pointer"); return CVW_EINVAL; }
   if (std::isnan(threshold)) { set_error("threshold is NaN"); return CVW_EINVAL; }
+  const int nv = n_var_of(prm->flux);
+  {
+    // u_out is u or a separate array: a partial overlap would be read after written
+    const uintptr_t a = reinterpret_cast<uintptr_t>(u), b = reinterpret_cast<uintptr_t>(u_out);
+    const uintptr_t n = static_cast<uintptr_t>(m->E) * m->nloc * nv * sizeof(float);
+    if (a != b && a < b + n && b < a + n) { set_error("u_out overlaps u without being u"); return CVW_EINVAL; }
+  }
   const WS w = carve(m, prm, ws);
   auto s = static_cast<hipStream_t>(stream);
-  const int nv = n_var_of(prm->flux);
   char* lp = static_cast<char*>(w.st1);
   float* cand = reinterpret_cast<float*>(lp);
   lp += align256(static_cast<size_t>(nv) * m->nk * m->Nv * 4);

@@ -141,6 +141,10 @@ def test_limiter_errors():
     with pytest.raises(cvw.CvwError) as ei:
         cvw.limit(gm, cp, u, u, 0.9, None, cvw.alloc_workspace(gm, cp, 0))
     assert ei.value.status == cvw.EINVAL
+    big = torch.zeros(2 * 64 * 9, device="cuda")
+    with pytest.raises(cvw.CvwError) as ei:
+        cvw.limit(gm, cp, big[:64 * 9], big[9:9 + 64 * 9], 0.9, None, ws)
+    assert ei.value.status == cvw.EINVAL
 
 
 def test_full_size_config4_limiter_sampled_cells():
