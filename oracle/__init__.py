@@ -21,8 +21,9 @@ learned    a learned replacement of the sensor gamma_e: features of the
 """
 from .space import Space, build_space
 from .method import (hermite_at_vertices, vertex_candidates, cell_sensor, sc_weights,
-                     residual, apply_mass_inverse, rk3_step, nodal_interpolate, hweno_limit, Params)
+                     residual, apply_mass_inverse, rk3_step, nodal_interpolate, hweno_limit,
+                     positivity_limit, Params)
 
 __all__ = ["Space", "build_space", "hermite_at_vertices", "vertex_candidates", "cell_sensor",
            "sc_weights", "residual", "apply_mass_inverse", "rk3_step", "nodal_interpolate", "hweno_limit",
-           "Params"]
+           "positivity_limit", "Params"]

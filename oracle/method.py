@@ -355,6 +355,71 @@ def hweno_limit(sp, U, prm: Params, threshold: float, gamma=None):
     return out[0] if scalar else out
 
 
+# ---------------------------------------------------------------------------
+# positivity limiter for the Euler equations on DG quadrilaterals (the
+# Zhang-Shu limiter the paper adds in its double Mach reflection run, Sec. 5;
+# restated from Zhang and Shu's published construction)
+# ---------------------------------------------------------------------------
+def _face_trace_matrix(sp):
+    """Values at the Gauss points of the four faces (W, E, S, N; p + 1 points
+    each, ordered along the face) from the nodal values: [4 (p+1), n_loc]."""
+    ref = sp.ref
+    n1 = sp.p + 1
+    x = ref.x1d
+    pts = []
+    for side in ((-1.0, None), (1.0, None), (None, -1.0), (None, 1.0)):
+        for t in x:
+            pts.append((side[0], t) if side[0] is not None else (t, side[1]))
+    return ref.deriv(np.array(pts), (0, 0))                  # [4 n1, n_loc]
+
+
+def _pressure(U, gam):
+    rho, mx, my, En = U
+    return (gam - 1.0) * (En - 0.5 * (mx * mx + my * my) / rho)
+
+
+def positivity_limit(sp, U, prm: Params, eps0: float = 1e-13, iters: int = 200):
+    """Zhang-Shu scaling limiter: per cell, with the cell averages
+    Ubar and the points Q (the Gauss nodes and the Gauss points of the faces),
+    eps = min(eps0, rhobar, p(Ubar));
+    (1) rho <- rhobar + th1 (rho - rhobar), th1 = min(1, (rhobar - eps) / (rhobar - min_Q rho));
+    (2) U <- Ubar + th2 (U - Ubar), th2 = min over Q of the t in [0, 1] where
+        p(Ubar + t (U_q - Ubar)) = eps (t = 1 where p(U_q) >= eps), found by
+        bisection (p is concave along the segment, positive at t = 0).
+    Cells with th = 1 keep their values bit for bit.
+    U: [4, E, n_loc] nodal values (Euler); returns the limited values."""
+    gam = prm.flux_param[0]
+    U = np.asarray(U, np.float64).copy()
+    w1 = np.polynomial.legendre.leggauss(sp.p + 1)[1]
+    w = np.outer(w1, w1).ravel() / 4.0                        # collocated Gauss rule of the nodes
+    F = _face_trace_matrix(sp)
+    at_pts = lambda V: np.concatenate([V, V @ F.T], axis=-1)                         # nodes, then faces
+    mean = np.einsum("ven,n->ve", U, w)                                             # [4, E]
+    eps = np.minimum(eps0, np.minimum(mean[0], _pressure(mean, gam)))
+    # (1) density
+    rq = at_pts(U[0])
+    rmin = rq.min(1)
+    low = rmin < eps
+    th1 = np.ones_like(rmin)
+    th1[low] = (mean[0][low] - eps[low]) / (mean[0][low] - rmin[low])
+    th1 = np.minimum(1.0, th1)
+    U[0] = np.where((th1 < 1.0)[:, None], mean[0][:, None] + th1[:, None] * (U[0] - mean[0][:, None]), U[0])
+    # (2) pressure
+    Q = np.stack([at_pts(U[v]) for v in range(4)])                                  # [4, E, nq]
+    D = Q - mean[:, :, None]
+    pq = _pressure(Q, gam)
+    lo = np.zeros(pq.shape)
+    hi = np.ones(pq.shape)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        ok = _pressure(mean[:, :, None] + mid[None] * D, gam) >= eps[:, None]
+        lo = np.where(ok, mid, lo)
+        hi = np.where(ok, hi, mid)
+    t = np.where(pq >= eps[:, None], 1.0, lo)
+    th2 = t.min(1)
+    return np.where((th2 < 1.0)[None, :, None], mean[:, :, None] + th2[None, :, None] * (U - mean[:, :, None]), U)
+
+
 def sensor_gamma(sp, s, prm: Params):
     if prm.sensor == 2:
         return np.full(sp.E, prm.fixed_gamma)
