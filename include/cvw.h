@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 4
+#define CVW_ABI_VERSION 5
 
 typedef enum {
   CVW_OK = 0,
@@ -207,6 +207,23 @@ cvw_status cvw_sensor(const cvw_mesh* mesh, const cvw_params* prm, const void* u
  * for null pointers, a NaN threshold or a small workspace. */
 cvw_status cvw_limit(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* u_out, double threshold,
                      void* gamma_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Positivity limiter for the Euler equations on DG quadrilaterals: the
+ * Zhang-Shu scaling limiter that the paper adds in its double Mach
+ * reflection run (Sec. 5), as published by Zhang and Shu.  Per cell, with the
+ * cell averages Ubar and the points Q = the Gauss nodes and the Gauss points
+ * of the four faces, eps = min(eps0, rhobar, p(Ubar)): (1) the density is
+ * scaled towards its average until min_Q rho = eps; (2) the state is scaled
+ * towards Ubar by the smallest t in [0, 1] at which the pressure along
+ * Ubar + t (U_q - Ubar) reaches eps.  Cell averages are preserved; admissible
+ * cells are copied bit for bit.  The arithmetic is float64; the stored state
+ * is float32, so the bound holds up to the rounding of the stored values
+ * (choose eps0 well above it, e.g. 1e-6 of the data's scale).
+ * u, u_out: device float32 [4][E][n_loc]; u_out may be u, any other overlap
+ * is rejected.  No workspace.  Errors: CVW_EUNSUPPORTED for other meshes,
+ * fluxes or precisions; CVW_EINVAL for null pointers, eps0 <= 0 or gamma <= 1. */
+cvw_status cvw_positivity(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* u_out, double eps0,
+                          void* stream);
 
 /* Stabilised residual R of M dU/dt = -R (eq. stabform / sdstab): Galerkin
  * volume term, the blended stabilisation s_h with nonlinear quadrature

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "cvw_internal.h"
+#include "cvw_limit.h"
 
 namespace cvw {
 
@@ -1291,6 +1292,35 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
   }
   return dgquad_limit(m, prm, uf, static_cast<float*>(u_out), cand, gam, ln, threshold, count, list, vflag, vlist,
                       s);
+}
+
+cvw_status cvw_positivity(const cvw_mesh* m, const cvw_params* prm, const void* u, void* u_out, double eps0,
+                          void* stream) {
+  if (!m || !prm) { set_error("null argument"); return CVW_EINVAL; }
+  if (!(m->cell == CVW_QUAD && m->space == CVW_DG && m->uniform)) {
+    set_error("positivity limiter: DG quadrilaterals (congruent axis-aligned cells) only"); return CVW_EUNSUPPORTED;
+  }
+  if (prm->flux != CVW_EULER) { set_error("positivity limiter: Euler equations only"); return CVW_EUNSUPPORTED; }
+  if (prm->dtype != CVW_F32) { set_error("DG quadrilaterals run in float32"); return CVW_EUNSUPPORTED; }
+  if (m->degree < 1 || m->degree > MAXP) { set_error("degree not on the GPU path"); return CVW_EUNSUPPORTED; }
+  const double gam = prm->flux_param[0];
+  if (!(gam > 1.0) || !std::isfinite(gam)) { set_error("gamma must be > 1"); return CVW_EINVAL; }
+  if (!(eps0 > 0.0) || !std::isfinite(eps0)) { set_error("eps0 must be positive and finite"); return CVW_EINVAL; }
+  if (!u || !u_out) { set_error("null device pointer"); return CVW_EINVAL; }
+  {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(u), b = reinterpret_cast<uintptr_t>(u_out);
+    const uintptr_t n = static_cast<uintptr_t>(m->E) * m->nloc * 4 * sizeof(float);
+    if (a != b && a < b + n && b < a + n) { set_error("u_out overlaps u without being u"); return CVW_EINVAL; }
+  }
+  LimitNodes ln{};
+  std::vector<double> x, wq;
+  gauss_rule(m->degree + 1, x, wq);
+  for (int i = 0; i <= m->degree; ++i) {
+    ln.xi[i] = x[i];
+    ln.w[i] = wq[i];
+  }
+  return dgquad_positivity(m, static_cast<const float*>(u), static_cast<float*>(u_out), ln, gam, eps0,
+                           static_cast<hipStream_t>(stream));
 }
 
 cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u, void* R, void* gamma_out, void* ws,

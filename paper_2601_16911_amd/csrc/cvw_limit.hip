@@ -1,6 +1,7 @@
 // HWENO limiter on DG quadrilaterals, gfx950 (the kernels behind cvw_limit).
 #include "cvw_device.h"
 #include "cvw_dgq_common.h"
+#include "cvw_limit.h"
 
 namespace cvw {
 
@@ -322,6 +323,127 @@ cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u
     default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
   }
 #undef CVW_LIMIT_LAUNCH
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// Positivity limiter for the Euler equations (the Zhang-Shu scaling limiter
+// the paper adds for its double Mach reflection run, Sec. 5, restated from the
+// published construction).  One thread per cell, float64 inside.  Points Q:
+// the Gauss nodes and the Gauss points of the four faces; eps = min(eps0,
+// rhobar, p(Ubar)).  (1) density scaled towards its cell average until
+// min_Q rho = eps; (2) the state scaled towards the cell average by the
+// smallest t in [0, 1] at which the pressure along Ubar + t (U_q - Ubar) reaches
+// eps (the root of a quadratic: 2 rho E - |m|^2 - 2 eps rho / (gamma - 1) is
+// quadratic in t and positive at t = 0).  Cells already admissible are copied.
+// ---------------------------------------------------------------------------
+// l_i(-1) of the element, float64 (face traces; l_i(+1) = l_{p-i}(-1) on the
+// symmetric Gauss nodes)
+struct PositivityTraces {
+  double l0[MAXP + 1];
+};
+
+__device__ __forceinline__ double pos_root(double a, double b, double c) {
+  // the root in [0, 1] of a t^2 + b t + c with c >= 0 > a + b + c
+  if (fabs(a) <= 1e-14 * (fabs(b) + fabs(c))) return b != 0.0 ? fmin(1.0, fmax(0.0, -c / b)) : 0.0;
+  const double disc = fmax(0.0, b * b - 4.0 * a * c);
+  const double q = -0.5 * (b + copysign(sqrt(disc), b));
+  const double t1 = q / a, t2 = (q != 0.0) ? c / q : 2.0;
+  double t = 2.0;
+  if (t1 >= 0.0 && t1 <= 1.0) t = t1;
+  if (t2 >= 0.0 && t2 <= 1.0) t = fmin(t, t2);
+  return t <= 1.0 ? t : 0.0;
+}
+
+template <int P>
+__global__ __launch_bounds__(128) void dgq_positivity_kernel(const float* __restrict__ u, float* __restrict__ out,
+                                                              int64_t E, LimitNodes ln, PositivityTraces tr,
+                                                              double gam, double eps0) {
+  constexpr int N1 = P + 1, NLOC = N1 * N1, NQ = NLOC + 4 * N1;
+  const int64_t e = blockIdx.x * 128LL + threadIdx.x;
+  if (e >= E) return;
+  double U[4][NLOC];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) U[v][j] = u[(static_cast<int64_t>(v) * E + e) * NLOC + j];
+  double m[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < N1; ++b)
+#pragma unroll
+      for (int a = 0; a < N1; ++a) s = fma(0.25 * ln.w[a] * ln.w[b], U[v][a + N1 * b], s);
+    m[v] = s;
+  }
+  const double gm1 = gam - 1.0;
+  auto pres = [&](double r, double mx, double my, double en) { return gm1 * (en - 0.5 * (mx * mx + my * my) / r); };
+  const double eps = fmin(eps0, fmin(m[0], pres(m[0], m[1], m[2], m[3])));
+  // the state at point q (nodes, then W, E, S, N face points)
+  auto at = [&](const double (&V)[NLOC], int q) {
+    if (q < NLOC) return V[q];
+    const int f = (q - NLOC) / N1, k = (q - NLOC) % N1;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      const double li = (f == 0 || f == 2) ? tr.l0[i] : tr.l0[P - i];       // l_i(-1) or l_i(+1)
+      s = fma(li, (f < 2) ? V[i + N1 * k] : V[k + N1 * i], s);
+    }
+    return s;
+  };
+  // (1) density
+  double rmin = 1e300;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) rmin = fmin(rmin, at(U[0], q));
+  bool changed = false;
+  if (rmin < eps) {
+    const double th1 = fmin(1.0, (m[0] - eps) / (m[0] - rmin));
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) U[0][j] = m[0] + th1 * (U[0][j] - m[0]);
+    changed = true;
+  }
+  // (2) pressure
+  double th2 = 1.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double r = at(U[0], q), mx = at(U[1], q), my = at(U[2], q), en = at(U[3], q);
+    if (pres(r, mx, my, en) >= eps) continue;
+    const double dr = r - m[0], dx = mx - m[1], dy = my - m[2], de = en - m[3];
+    const double k2 = 2.0 * eps / gm1;
+    const double a = 2.0 * dr * de - (dx * dx + dy * dy);
+    const double b = 2.0 * (m[0] * de + dr * m[3]) - 2.0 * (m[1] * dx + m[2] * dy) - k2 * dr;
+    const double c = 2.0 * m[0] * m[3] - (m[1] * m[1] + m[2] * m[2]) - k2 * m[0];
+    th2 = fmin(th2, pos_root(a, b, c));
+  }
+  if (th2 < 1.0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) U[v][j] = m[v] + th2 * (U[v][j] - m[v]);
+    changed = true;
+  }
+  if (!changed && out == u) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) {
+      float* o = out + (static_cast<int64_t>(v) * E + e) * NLOC + j;
+      *o = changed ? static_cast<float>(U[v][j]) : u[(static_cast<int64_t>(v) * E + e) * NLOC + j];
+    }
+}
+
+cvw_status dgquad_positivity(const cvw_mesh* m, const float* u, float* out, const LimitNodes& ln, double gam,
+                             double eps0, hipStream_t s) {
+  PositivityTraces tr{};
+  for (int i = 0; i <= MAXP; ++i) tr.l0[i] = m->tens.Ld[0][i];
+  const dim3 g(static_cast<unsigned>((m->E + 127) / 128)), b(128);
+  switch (m->degree) {
+    case 1: hipLaunchKernelGGL(dgq_positivity_kernel<1>, g, b, 0, s, u, out, m->E, ln, tr, gam, eps0); break;
+    case 2: hipLaunchKernelGGL(dgq_positivity_kernel<2>, g, b, 0, s, u, out, m->E, ln, tr, gam, eps0); break;
+    case 3: hipLaunchKernelGGL(dgq_positivity_kernel<3>, g, b, 0, s, u, out, m->E, ln, tr, gam, eps0); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 

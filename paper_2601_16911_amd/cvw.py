@@ -24,7 +24,7 @@ OP_EVAL, OP_STEP, OP_LIMIT = 0, 1, 2
 EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXPORT_CELL_DOF = range(6)
 
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
-           "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_limit",
+           "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_limit", "cvw_positivity",
            "cvw_residual",
            "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_mesh_plan",
            "cvw_mesh_build_in", "cvw_batch_build",
@@ -93,6 +93,7 @@ def load():
     lib.cvw_vertex_candidates.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, sz, vp]
     lib.cvw_sensor.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, sz, vp]
     lib.cvw_limit.argtypes = [vp, C.POINTER(ParamsC), vp, vp, C.c_double, vp, vp, sz, vp]
+    lib.cvw_positivity.argtypes = [vp, C.POINTER(ParamsC), vp, vp, C.c_double, vp]
     lib.cvw_residual.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, sz, vp]
     lib.cvw_rk_stage.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                  vp, sz, vp]
@@ -292,6 +293,13 @@ def limit(mesh, prm, u, u_out, threshold: float, gamma_out, ws, stream=None):
     _check(load().cvw_limit(mesh.handle, C.byref(prm), _fp(u, prm, n, "u"), _fp(u_out, prm, n, "u_out"),
                             float(threshold), _fp(gamma_out, prm, mesh.info["n_cells"], "gamma_out"), _ptr(ws),
                             ws.numel(), _stream(stream)))
+
+
+def positivity(mesh, prm, u, u_out, eps0: float, stream=None):
+    """Zhang-Shu positivity limiter (cvw_positivity); u_out may be u."""
+    n = _state_len(mesh, prm)
+    _check(load().cvw_positivity(mesh.handle, C.byref(prm), _fp(u, prm, n, "u"), _fp(u_out, prm, n, "u_out"),
+                                 float(eps0), _stream(stream)))
 
 
 def residual(mesh, prm, u, R, gamma_out, ws, stream=None):
