@@ -335,7 +335,8 @@ cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u
 // min_Q rho = eps; (2) the state scaled towards the cell average by the
 // smallest t in [0, 1] at which the pressure along Ubar + t (U_q - Ubar) reaches
 // eps (the root of a quadratic: 2 rho E - |m|^2 - 2 eps rho / (gamma - 1) is
-// quadratic in t and positive at t = 0).  Cells already admissible are copied.
+// quadratic in t and positive at t = 0).  Cells already admissible are left
+// as they are (out of place, the state is copied to out first).
 // ---------------------------------------------------------------------------
 // l_i(-1) of the element, float64 (face traces; l_i(+1) = l_{p-i}(-1) on the
 // symmetric Gauss nodes)
@@ -423,20 +424,22 @@ __global__ __launch_bounds__(128) void dgq_positivity_kernel(const float* __rest
       for (int j = 0; j < NLOC; ++j) U[v][j] = m[v] + th2 * (U[v][j] - m[v]);
     changed = true;
   }
-  if (!changed && out == u) return;
+  if (!changed) return;                         // out holds u's values already
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int j = 0; j < NLOC; ++j) {
-      float* o = out + (static_cast<int64_t>(v) * E + e) * NLOC + j;
-      *o = changed ? static_cast<float>(U[v][j]) : u[(static_cast<int64_t>(v) * E + e) * NLOC + j];
-    }
+    for (int j = 0; j < NLOC; ++j) out[(static_cast<int64_t>(v) * E + e) * NLOC + j] = static_cast<float>(U[v][j]);
 }
 
 cvw_status dgquad_positivity(const cvw_mesh* m, const float* u, float* out, const LimitNodes& ln, double gam,
                              double eps0, hipStream_t s) {
   PositivityTraces tr{};
   for (int i = 0; i <= MAXP; ++i) tr.l0[i] = m->tens.Ld[0][i];
+  // out of place: copy once, the kernel then writes the limited cells only
+  if (out != u && hipMemcpyAsync(out, u, static_cast<size_t>(m->E) * m->nloc * 4 * sizeof(float),
+                                 hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    set_error("state copy failed"); return CVW_EDEVICE;
+  }
   const dim3 g(static_cast<unsigned>((m->E + 127) / 128)), b(128);
   switch (m->degree) {
     case 1: hipLaunchKernelGGL(dgq_positivity_kernel<1>, g, b, 0, s, u, out, m->E, ln, tr, gam, eps0); break;
