@@ -17,7 +17,7 @@ from synth import Params
 from oracle import build_space, nodal_interpolate, hweno_limit
 from oracle.method import sensor_gamma
 from tests.parity_helpers import rough_scalar, euler_state
-from tests.test_oracle_sensor import _sympy_sensor, _lagrange_1d_sym, _box_integral, _R, xs, ys
+from tests.test_oracle_sensor import _sympy_sensor, _sympy_tri_case, _lagrange_1d_sym, _box_integral, _R, xs, ys
 
 
 def _cell_means(sp, u):
@@ -117,3 +117,57 @@ def test_limiter_threshold_selects_cells():
     assert changed[g < 0.9].all()
     full = hweno_limit(sp, u, prm, threshold=2.0)
     assert np.array_equal(out[g < 0.9], full[g < 0.9])
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_limiter_triangles_preserves_averages(p):
+    """Jittered periodic triangles: the same construction (Taylor polynomials
+    about the vertices, corrected averages, the sensor's weights)."""
+    mesh = synth.tri_mesh(7, 6, jitter=0.1, seed=p)
+    sp = build_space(mesh, p, 1)
+    u = rough_scalar(sp, 4)
+    out = hweno_limit(sp, u, Params(), threshold=2.0)
+    m0, m1 = _cell_means_tri(sp, u), _cell_means_tri(sp, out)
+    assert np.abs(m1 - m0).max() < 1e-13 * np.abs(u).max()
+    assert np.abs(out - u).max() > 1e-2
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_limiter_triangles_reproduce_polynomials(p):
+    mesh = synth.tri_mesh(6, 5, jitter=0.1, seed=7 + p, periodic=(False, False))
+    sp = build_space(mesh, p, 1)
+    rng = np.random.default_rng(10 + p)
+    coef = {(a, b): rng.normal() for a in range(p + 1) for b in range(p + 1 - a)}
+    f = lambda x: sum(c * (x[..., 0] - 0.4) ** a * (x[..., 1] - 0.7) ** b for (a, b), c in coef.items())
+    u = sp.to_cells(nodal_interpolate(sp, [f]))[0]
+    out = hweno_limit(sp, u, Params(), threshold=2.0)
+    assert np.abs(out - u).max() < 1e-10 * np.abs(u).max()
+
+
+def _cell_means_tri(sp, u):
+    from oracle.geometry import map_jacobian
+    pts = sp.ref.vol_pts
+    J, _ = map_jacobian(sp.cell, sp.X, pts)
+    W = sp.ref.vol_w[None, :] * np.abs(np.linalg.det(J))
+    return (W * (u @ sp.ref.deriv(pts, (0, 0)).T)).sum(1) / W.sum(1)
+
+
+def test_sympy_brute_force_limiter_triangles_p2():
+    """Jittered periodic triangles, P2: the reconstructed nodal values with
+    exact polynomials and exact cell integrals."""
+    mesh, sp, u, polys, integ, prm, p = _sympy_tri_case()
+    _, _, oms, cls = _sympy_sensor(mesh, polys, p, integ, prm, parts=True)
+    xn = sp.node_coords()
+    ref = np.zeros_like(u)
+    one = symp.Poly(1, xs, ys)
+    for e in range(sp.E):
+        area = integ(e, one)
+        mean_u = integ(e, polys[e]) / area
+        rec = polys[e] * _R(oms[e][0])
+        for l, cl in enumerate(cls[e]):
+            rec = rec + (cl + symp.Poly(mean_u - integ(e, cl) / area, xs, ys)) * _R(oms[e][l + 1])
+        for j in range(sp.ref.n_loc):
+            ref[e, j] = float(rec.eval({xs: _R(xn[e, j, 0]), ys: _R(xn[e, j, 1])}))
+    got = hweno_limit(sp, u, prm, threshold=2.0)
+    assert np.abs(got - ref).max() < 1e-9 * (1 + np.abs(ref).max())
+    assert np.abs(got - u).max() > 1e-2

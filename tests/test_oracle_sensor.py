@@ -171,7 +171,9 @@ def test_sympy_brute_force_dg_quads(p):
     assert g.min() < 0.9
 
 
-def test_sympy_brute_force_jittered_triangles_p2():
+def _sympy_tri_case():
+    """Jittered periodic 3 x 3 x 2 triangles, P2, rough data: the mesh, space,
+    nodal data, exact polynomials and an exact cell integral."""
     mesh = synth.tri_mesh(3, 3, jitter=0.15, seed=8, periodic=(True, True))
     prm = Params()
     p = 2
@@ -208,6 +210,11 @@ def test_sympy_brute_force_jittered_triangles_p2():
             tot += cf * symp.factorial(a) * symp.factorial(b) / symp.factorial(a + b + 2)
         return det * tot
 
+    return mesh, sp, u, polys, integ, prm, p
+
+
+def test_sympy_brute_force_jittered_triangles_p2():
+    mesh, sp, u, polys, integ, prm, p = _sympy_tri_case()
     g_sym, c_sym = _sympy_sensor(mesh, polys, p, integ, prm)
     c = vertex_candidates(sp, u, prm)
     g = cell_sensor(sp, u, c, prm)
