@@ -193,7 +193,7 @@ cvw_status cvw_sensor(const cvw_mesh* mesh, const cvw_params* prm, const void* u
 /* HWENO limiter (Sec. 3: the cell-vertex reconstruction u_h^{e,*} of eq.
  * finalweno may overwrite the DG solution u_h^e; Sec. 3.2: the vertex
  * candidates with cell averages corrected to that of u_h^e).  DG
- * quadrilaterals only.  On every cell whose sensor value gamma_e (eq. gamma,
+ * quadrilaterals and DG triangles.  On every cell whose sensor value gamma_e (eq. gamma,
  * of the sensor field = variable 0, plain or fixed sensor) is below
  * `threshold`, the nodal values of each variable are replaced by those of its
  * own reconstruction (componentwise: each variable with its own vertex

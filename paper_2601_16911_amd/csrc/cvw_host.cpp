@@ -1245,8 +1245,9 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
                      void* gamma_out, void* ws, size_t ws_bytes, void* stream) {
   cvw_status st = check_common(m, prm, ws_bytes, 2, ws);
   if (st != CVW_OK) return st;
-  if (!(m->cell == CVW_QUAD && m->space == CVW_DG)) {
-    set_error("HWENO limiter: DG quadrilaterals only"); return CVW_EUNSUPPORTED;
+  const bool tri = m->cell == CVW_TRI && m->space == CVW_DG;
+  if (!(m->cell == CVW_QUAD && m->space == CVW_DG) && !tri) {
+    set_error("HWENO limiter: DG quadrilaterals and triangles only"); return CVW_EUNSUPPORTED;
   }
   if (prm->sensor == CVW_SENSOR_LEARNED) {
     set_error("HWENO limiter: plain or fixed sensor"); return CVW_EUNSUPPORTED;
@@ -1275,6 +1276,26 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
   lp += align256(static_cast<size_t>(m->Nv));
   int32_t* vlist = reinterpret_cast<int32_t*>(lp);
   const float* uf = static_cast<const float*>(u);
+  if (tri) {
+    // every variable's vertex candidates, the sensor values, the selection
+    for (int v = 0; v < nv; ++v)
+      if ((st = tri_candidates(m, prm, uf + static_cast<int64_t>(v) * m->E * m->nloc,
+                               cand + static_cast<int64_t>(v) * m->Nv * m->nk, s)) != CVW_OK)
+        return st;
+    if ((st = tri_eval(m, prm, MODE_SENSOR, uf, nullptr, nullptr, gam, nullptr, cand, w.status, 0.f, 0.f, 0.f, s)) !=
+        CVW_OK)
+      return st;
+    const bool all = threshold > 1.0 && (prm->sensor != CVW_SENSOR_FIXED || prm->fixed_gamma < threshold);
+    if (!all) {
+      if (u_out != u &&
+          hipMemcpyAsync(u_out, u, static_cast<size_t>(m->E) * m->nloc * nv * sizeof(float), hipMemcpyDeviceToDevice,
+                         s) != hipSuccess) {
+        set_error("state copy failed"); return CVW_EDEVICE;
+      }
+      if ((st = limit_select(gam, m->E, threshold, count, list, s)) != CVW_OK) return st;
+    }
+    return tri_limit(m, prm, uf, static_cast<float*>(u_out), cand, count, all ? nullptr : list, s);
+  }
   // the sensor field's vertex candidates (the other variables' follow inside
   // the limiter, where they are needed; every candidate is taken from the
   // state before the reconstruction writes, so u_out may be u)

@@ -6,6 +6,16 @@
 
 namespace cvw {
 
+// the cells with gamma_e < threshold appended to list[0 .. count[0]) (any
+// order); count[1] is cleared as well
+cvw_status limit_select(const float* gamma, int64_t E, double threshold, uint32_t* count, int32_t* list,
+                        hipStream_t s);
+
+// HWENO limiter on DG triangles (cvw_tri.hip): cand holds every variable's
+// vertex candidates [n_var][Nv][n_k]; list == nullptr: every cell
+cvw_status tri_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, const float* cand,
+                     const uint32_t* count, const int32_t* list, hipStream_t s);
+
 // Zhang-Shu positivity limiter, Euler on DG quadrilaterals
 cvw_status dgquad_positivity(const cvw_mesh* m, const float* u, float* out, const LimitNodes& ln, double gam,
                              double eps0, hipStream_t s);

@@ -268,6 +268,14 @@ __global__ __launch_bounds__(256) void dgq_limit_kernel(const float* __restrict_
   }
 }
 
+cvw_status limit_select(const float* gamma, int64_t E, double threshold, uint32_t* count, int32_t* list,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(dgq_limit_clear_kernel, dim3(1), dim3(64), 0, s, count);
+  hipLaunchKernelGGL(dgq_limit_select_kernel, dim3(static_cast<unsigned>((E + 1023) / 1024)), dim3(1024), 0, s, gamma,
+                     E, threshold, count, list);
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
 cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, float* cand,
                         const float* gamma, const LimitNodes& ln, double threshold, uint32_t* count,
                         int32_t* list, uint8_t* vflag, int32_t* vlist, hipStream_t s) {

@@ -19,6 +19,7 @@
 // that are uniform across a wavefront (scalar loads), except the neighbour-
 // face tables, which live in LDS.
 #include "cvw_device.h"
+#include "cvw_limit.h"
 
 namespace cvw {
 
@@ -153,6 +154,128 @@ __device__ __forceinline__ void candidate_at_x0(const float* __restrict__ cand, 
   if (l == 1) { dx = -G.J[0][0]; dy = -G.J[1][0]; }
   if (l == 2) { dx = -G.J[0][1]; dy = -G.J[1][1]; }
   taylor_eval<P>(c, dx, dy, s);
+}
+
+// value at x_0 + d of the polynomial with D^k = t[k] at x_0 (1 <= |k| <= P)
+// and value 0 at x_0
+template <int P>
+__device__ __forceinline__ double taylor_value0(const double* t, double dx, double dy) {
+  constexpr double fct[4] = {1.0, 1.0, 2.0, 6.0};
+  double s = 0.0;
+#pragma unroll
+  for (int n = 1; n <= P; ++n)
+#pragma unroll
+    for (int j = 0; j <= n; ++j) {
+      double m = t[kbase(n) + j] / (fct[n - j] * fct[j]);
+#pragma unroll
+      for (int i = 0; i < n - j; ++i) m *= dx;
+#pragma unroll
+      for (int i = 0; i < j; ++i) m *= dy;
+      s += m;
+    }
+  return s;
+}
+
+// HWENO limiter (Sec. 3; candidates with corrected cell averages, Sec. 3.2),
+// one thread per (listed cell, variable), float64:
+//   u* = w_0 u_h^e + (1 - w_0) mean(u_h^e) + V - mean(V),
+//   V(x) = sum_k cb_k (x - x_0)^k / k!,  cb = sum_{l>=1} w_l D^k u_{h,l}(x_0),
+// the candidates and the weights exactly as in the sensor.  Nodes: (i/P, j/P)
+// on the reference triangle, j outer.
+template <int P, int NV>
+__global__ __launch_bounds__(256) void tri_limit_kernel(const float* __restrict__ u, float* __restrict__ out,
+                                                        const float* __restrict__ cand,
+                                                        const uint32_t* __restrict__ count,
+                                                        const int32_t* __restrict__ list,
+                                                        const int32_t* __restrict__ cell_vtx,
+                                                        const double* __restrict__ geot,
+                                                        const TriTables* __restrict__ tab, int64_t E, int64_t Nv,
+                                                        MethodScalars ms) {
+  constexpr int NLOC = (P + 1) * (P + 2) / 2, NK = NLOC - 1, NQ = (P + 1) * (P + 1);
+  const int64_t gid = blockIdx.x * 256LL + threadIdx.x;
+  const int64_t k = gid / NV;
+  const int v = static_cast<int>(gid % NV);
+  if (k >= (list ? static_cast<int64_t>(*count) : E)) return;
+  const int64_t e = list ? list[k] : k;
+  const float* ue = u + (static_cast<int64_t>(v) * E + e) * NLOC;
+  double uv[NLOC];
+#pragma unroll
+  for (int j = 0; j < NLOC; ++j) uv[j] = ue[j];
+  const TriGeo G = load_trigeo(geot, e);
+  double hw[P];
+  order_weights<P>(G.h, hw);
+  // own Taylor coefficients at x_0 and element semi-norm
+  double a[NK];
+  {
+    double R[NK];
+#pragma unroll
+    for (int m = 0; m < NK; ++m) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 1; j < NLOC; ++j) s = fma(tab->TV[0][m][j], uv[j] - uv[0], s);
+      R[m] = s;
+    }
+    phys_from_ref<P>(G.A, R, a);
+  }
+  const double n2 = seminorm_sq<P>(a, G, hw, tab);
+  // weights of the cell candidate and the three vertex candidates
+  const float* cv = cand + static_cast<int64_t>(v) * Nv * NK;
+  const double qb = static_cast<double>(ms.q_beta), rr = static_cast<double>(ms.r);
+  auto wfun = [&](double lin, double b2) {
+    const double beta = ms.fast_exp ? sqrt(b2) : pow(sqrt(b2), qb);
+    const double den = ms.eps_cd + beta;
+    return ms.fast_exp ? lin / (den * den) : lin * pow(den, -rr);
+  };
+  int32_t vtx[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) vtx[l] = cell_vtx[e * 3 + l];
+  double wt[4];
+  wt[0] = wfun(1.0 - 3.0 * ms.lin_wd, n2);
+  double tot = wt[0];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    double s[NK];
+    candidate_at_x0<P>(cv, vtx[l], l, G, s);
+    wt[l + 1] = wfun(ms.lin_wd, seminorm_sq<P>(s, G, hw, tab));
+    tot += wt[l + 1];
+  }
+  double cb[NK], wrest = 0.0;
+#pragma unroll
+  for (int t = 0; t < NK; ++t) cb[t] = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    double s[NK];
+    candidate_at_x0<P>(cv, vtx[l], l, G, s);
+    const double om = wt[l + 1] / tot;
+    wrest += om;
+#pragma unroll
+    for (int t = 0; t < NK; ++t) cb[t] = fma(om, s[t], cb[t]);
+  }
+  // cell means of u_h^e and of V on the volume rule (weights sum to 1/2)
+  double mu = 0.0, mv = 0.0;
+#pragma unroll 1
+  for (int q = 0; q < NQ; ++q) {
+    const double xi = tab->xqd[q], eta = tab->yqd[q];
+    double uq = 0.0;
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) uq = fma(static_cast<double>(tab->B[q][j]), uv[j], uq);
+    mu = fma(tab->wqd[q], uq, mu);
+    mv = fma(tab->wqd[q], taylor_value0<P>(cb, G.J[0][0] * xi + G.J[0][1] * eta, G.J[1][0] * xi + G.J[1][1] * eta), mv);
+  }
+  mu *= 2.0;
+  mv *= 2.0;
+  const double om0 = wt[0] / tot;
+  float* oe = out + (static_cast<int64_t>(v) * E + e) * NLOC;
+  int node = 0;
+#pragma unroll
+  for (int jj = 0; jj <= P; ++jj)
+#pragma unroll
+    for (int ii = 0; ii <= P - jj; ++ii) {
+      const double xi = static_cast<double>(ii) / P, eta = static_cast<double>(jj) / P;
+      const double V = taylor_value0<P>(cb, G.J[0][0] * xi + G.J[0][1] * eta, G.J[1][0] * xi + G.J[1][1] * eta);
+      oe[node] = static_cast<float>(om0 * uv[node] + wrest * mu + V - mv);
+      ++node;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -582,6 +705,28 @@ cvw_status tri_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const fl
     default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
   }
   if (st != CVW_OK) return st;
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+cvw_status tri_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, const float* cand,
+                     const uint32_t* count, const int32_t* list, hipStream_t s) {
+  const MethodScalars ms = make_scalars(prm);
+  const int nv = prm->flux == CVW_EULER ? 4 : 1;
+  const dim3 g(nblk(m->E * nv, 256)), b(256);
+#define CVW_TRI_LIMIT(P)                                                                                            \
+  if (nv == 4)                                                                                                      \
+    hipLaunchKernelGGL((tri_limit_kernel<P, 4>), g, b, 0, s, u, out, cand, count, list, m->d_cell_vtx, m->d_geot,   \
+                       m->d_trit, m->E, m->Nv, ms);                                                                 \
+  else                                                                                                              \
+    hipLaunchKernelGGL((tri_limit_kernel<P, 1>), g, b, 0, s, u, out, cand, count, list, m->d_cell_vtx, m->d_geot,   \
+                       m->d_trit, m->E, m->Nv, ms);
+  switch (m->degree) {
+    case 1: CVW_TRI_LIMIT(1) break;
+    case 2: CVW_TRI_LIMIT(2) break;
+    case 3: CVW_TRI_LIMIT(3) break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+#undef CVW_TRI_LIMIT
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 

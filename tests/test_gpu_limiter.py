@@ -225,3 +225,33 @@ def test_rkdg_step_with_limiter(p):
         for v in range(4):
             assert np.abs(got[v] - ref[v]).max() <= 1e-5 * np.abs(U0[v]).max(), ("limiter", v)
     assert limited >= 30
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("threshold", [0.9, 2.0])
+def test_limiter_triangles(p, threshold):
+    """Jittered periodic triangles: the same construction on the triangle path."""
+    mesh = synth.tri_mesh(9, 8, jitter=0.1, seed=p)
+    sp = build_space(mesh, p, 1)
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    u = f32(rough_scalar(sp, 0))
+    prm = Params()
+    got, gam = _run(gm, prm, u, threshold)
+    g_o = sensor_gamma(sp, u, prm)
+    ref = hweno_limit(sp, u, prm, threshold, gamma=g_o)
+    sure = np.abs(g_o - threshold) >= 1e-4
+    assert (g_o < threshold).sum() >= 3
+    assert np.abs(got - ref)[sure].max() <= 1e-5 * np.abs(u).max()
+    kept = sure & (g_o >= threshold)
+    assert np.array_equal(got[kept], u.astype(np.float32)[kept])
+
+
+def test_limiter_triangles_euler():
+    mesh = synth.tri_mesh(8, 7, jitter=0.1, seed=5)
+    sp = build_space(mesh, 2, 1, 4)
+    gm = cvw.Mesh(mesh, 2, cvw.DG)
+    U = f32(sp.to_cells(euler_state(sp, k=200.0)))
+    got, _ = _run(gm, EULER, U, 2.0)
+    ref = hweno_limit(sp, U, EULER, 2.0)
+    for v in range(4):
+        assert np.abs(got[v] - ref[v]).max() <= 1e-5 * np.abs(U[v]).max(), v
