@@ -354,9 +354,14 @@ def bench_triangles(torch, cvw, steps: int):
     dt = 0.1 * h_min / (2 * p + 1)
     t_res = _timed(torch, stream, lambda: cvw.residual(gm, cp, U, R, None, ws), 10)
     t_step = _timed(torch, stream, lambda: cvw.step(gm, cp, U, dt, steps, ws), 1) / steps
+    # the HWENO limiter on the same state (threshold 0.9, out of place)
+    wl = cvw.alloc_workspace(gm, cp, cvw.OP_LIMIT)
+    Ul = torch.empty_like(U)
+    t_lim = _timed(torch, stream, lambda: cvw.limit(gm, cp, U, Ul, 0.9, None, wl), 5)
     return {"workload": f"KPP, DG P3 on {mesh.n_cells} jittered triangles", "dofs": dofs,
             "residual": {"value": dofs / t_res, "unit": "DOF-updates/s", "ms": t_res * 1e3},
             "step": {"value": 3.0 * dofs / t_step, "unit": "DOF-updates/s", "ms_per_step": t_step * 1e3},
+            "hweno_limiter": {"threshold": 0.9, "value": dofs / t_lim, "unit": "DOF-updates/s", "ms": t_lim * 1e3},
             "status_flags": cvw.poll_status(gm, ws)}
 
 
