@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 5
+#define CVW_ABI_VERSION 6
 
 typedef enum {
   CVW_OK = 0,
@@ -167,9 +167,10 @@ cvw_status cvw_mesh_set_grid(cvw_mesh* mesh, int blocks);
 cvw_status cvw_mesh_export(const cvw_mesh* mesh, int which, void* host_dst, size_t bytes);
 
 /* Workspace size in bytes for an operation: 0 = sensor / residual / candidates,
- * 1 = time step, 2 = HWENO limiter.  The workspace holds the vertex candidates, the status word and
- * (time step) the Runge-Kutta stage states; it must stay untouched between the
- * calls of one operation and may be reused afterwards. */
+ * 1 = time step, 2 = HWENO limiter, 3 = positivity limiter.  The workspace
+ * holds the vertex candidates, the status word, (time step) the Runge-Kutta
+ * stage states and (limiters) the lists of cells to limit; it must stay
+ * untouched between the calls of one operation and may be reused afterwards. */
 size_t cvw_workspace_bytes(const cvw_mesh* mesh, const cvw_params* prm, int op);
 
 /* Vertex stage of the cell-vertex reconstruction (Sec. 3.2, eq. taylorcand and
@@ -220,10 +221,12 @@ cvw_status cvw_limit(const cvw_mesh* mesh, const cvw_params* prm, const void* u,
  * is float32, so the bound holds up to the rounding of the stored values
  * (choose eps0 well above it, e.g. 1e-6 of the data's scale).
  * u, u_out: device float32 [4][E][n_loc]; u_out may be u, any other overlap
- * is rejected.  No workspace.  Errors: CVW_EUNSUPPORTED for other meshes,
- * fluxes or precisions; CVW_EINVAL for null pointers, eps0 <= 0 or gamma <= 1. */
+ * is rejected.  ws: cvw_workspace_bytes(mesh, prm, 3) bytes (256 + 4 E
+ * rounded up to 256), 256-byte aligned.  Errors: CVW_EUNSUPPORTED for other
+ * meshes, fluxes or precisions; CVW_EINVAL for null pointers, eps0 <= 0,
+ * gamma <= 1 or a small workspace. */
 cvw_status cvw_positivity(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* u_out, double eps0,
-                          void* stream);
+                          void* ws, size_t ws_bytes, void* stream);
 
 /* Stabilised residual R of M dU/dt = -R (eq. stabform / sdstab): Galerkin
  * volume term, the blended stabilisation s_h with nonlinear quadrature

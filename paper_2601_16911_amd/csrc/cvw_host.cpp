@@ -1065,6 +1065,7 @@ static size_t cg_extra(const cvw_mesh* m, const cvw_params* prm, size_t es) {
 
 size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (!m || !prm) return 0;
+  if (op == 3) return 256 + align256(static_cast<size_t>(m->E) * 4);   // positivity: count, cell list
   const size_t es = prm->dtype == CVW_F64 ? 8 : 4;
   size_t b = 256 + TOT_SCRATCH + align256(static_cast<size_t>(m->nk) * m->Nv * es) + cg_extra(m, prm, es);
   if (prm->sensor == CVW_SENSOR_LEARNED)
@@ -1316,8 +1317,11 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
 }
 
 cvw_status cvw_positivity(const cvw_mesh* m, const cvw_params* prm, const void* u, void* u_out, double eps0,
-                          void* stream) {
+                          void* ws, size_t ws_bytes, void* stream) {
   if (!m || !prm) { set_error("null argument"); return CVW_EINVAL; }
+  if (!ws) { set_error("null workspace"); return CVW_EINVAL; }
+  if (ws_bytes < cvw_workspace_bytes(m, prm, 3)) { set_error("workspace too small"); return CVW_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(ws) % 256) { set_error("workspace must be 256-byte aligned"); return CVW_EINVAL; }
   if (!(m->cell == CVW_QUAD && m->space == CVW_DG && m->uniform)) {
     set_error("positivity limiter: DG quadrilaterals (congruent axis-aligned cells) only"); return CVW_EUNSUPPORTED;
   }
@@ -1340,7 +1344,9 @@ cvw_status cvw_positivity(const cvw_mesh* m, const cvw_params* prm, const void* 
     ln.xi[i] = x[i];
     ln.w[i] = wq[i];
   }
-  return dgquad_positivity(m, static_cast<const float*>(u), static_cast<float*>(u_out), ln, gam, eps0,
+  uint32_t* count = static_cast<uint32_t*>(ws);
+  int32_t* list = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
+  return dgquad_positivity(m, static_cast<const float*>(u), static_cast<float*>(u_out), ln, gam, eps0, count, list,
                            static_cast<hipStream_t>(stream));
 }
 

@@ -16,8 +16,9 @@ cvw_status limit_select(const float* gamma, int64_t E, double threshold, uint32_
 cvw_status tri_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, const float* cand,
                      const uint32_t* count, const int32_t* list, hipStream_t s);
 
-// Zhang-Shu positivity limiter, Euler on DG quadrilaterals
+// Zhang-Shu positivity limiter, Euler on DG quadrilaterals; count: 256 bytes,
+// list: [E] (the cells the float64 stage takes)
 cvw_status dgquad_positivity(const cvw_mesh* m, const float* u, float* out, const LimitNodes& ln, double gam,
-                             double eps0, hipStream_t s);
+                             double eps0, uint32_t* count, int32_t* list, hipStream_t s);
 
 }  // namespace cvw

@@ -364,13 +364,86 @@ __device__ __forceinline__ double pos_root(double a, double b, double c) {
   return t <= 1.0 ? t : 0.0;
 }
 
+// Stage 1, one thread per cell: the float32 pre-check below, the copy to
+// out (out of place), and the list of cells that fail the pre-check:
+// list[0 .. count[0]).
+template <int P>
+__global__ __launch_bounds__(1024) void dgq_positivity_check_kernel(const float* __restrict__ u,
+                                                                    float* __restrict__ out, int64_t E,
+                                                                    PositivityTraces tr, double gam, double eps0,
+                                                                    uint32_t* __restrict__ count,
+                                                                    int32_t* __restrict__ list) {
+  constexpr int N1 = P + 1, NLOC = N1 * N1, NQ = NLOC + 4 * N1;
+  const int64_t e = blockIdx.x * 1024LL + threadIdx.x;
+  bool pass = true;
+  if (e < E)
+  // float32 pre-check at the nodes and face points.  Each face value carries
+  // the bound 1e-5 * sum |l_i u_i| on its float32 rounding (the true error is
+  // below 4e-7 times that sum), and the density and pressure are bounded from
+  // below with those errors.  A cell whose bounds clear 2 eps0 has float64
+  // density and pressure >= eps0 >= eps at every point, so the float64 path
+  // below would leave it unchanged: it is skipped.
+  {
+    bool clear = true;
+    const float gm1f = static_cast<float>(gam - 1.0);
+    const float tol = 2.0f * static_cast<float>(eps0);
+    float F[4][NLOC];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) F[v][j] = u[(static_cast<int64_t>(v) * E + e) * NLOC + j];
+    if (out != u) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int j = 0; j < NLOC; ++j) out[(static_cast<int64_t>(v) * E + e) * NLOC + j] = F[v][j];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      float w[4], d[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (q < NLOC) {
+          w[v] = F[v][q];
+          d[v] = 0.0f;
+        } else {
+          const int f = (q - NLOC) / N1, k = (q - NLOC) % N1;
+          float sv = 0.0f, sa = 0.0f;
+#pragma unroll
+          for (int i = 0; i < N1; ++i) {
+            const float li = static_cast<float>((f == 0 || f == 2) ? tr.l0[i] : tr.l0[P - i]);
+            const float x = (f < 2) ? F[v][i + N1 * k] : F[v][k + N1 * i];
+            sv = fmaf(li, x, sv);
+            sa = fmaf(fabsf(li), fabsf(x), sa);
+          }
+          w[v] = sv;
+          d[v] = 1e-5f * sa;
+        }
+      }
+      const float rlo = w[0] - d[0] - 1e-5f * fabsf(w[0]);
+      const float mx = fabsf(w[1]) + d[1], my = fabsf(w[2]) + d[2];
+      const float kin = 0.5f * (mx * mx + my * my) / rlo;
+      const float elo = w[3] - d[3];
+      const float plo = gm1f * (elo - kin - 1e-5f * (fabsf(elo) + kin));
+      clear = clear && (rlo > tol) && (plo > tol);
+    }
+    pass = clear;
+  }
+  append_selected(e < E && !pass, e, count, list);
+}
+
+// Stage 2, one thread per listed cell (the grid covers every cell; threads
+// past the count leave): the limiter in float64.  out already holds u.
 template <int P>
 __global__ __launch_bounds__(128) void dgq_positivity_kernel(const float* __restrict__ u, float* __restrict__ out,
                                                               int64_t E, LimitNodes ln, PositivityTraces tr,
-                                                              double gam, double eps0) {
+                                                              double gam, double eps0,
+                                                              const uint32_t* __restrict__ count,
+                                                              const int32_t* __restrict__ list) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NQ = NLOC + 4 * N1;
-  const int64_t e = blockIdx.x * 128LL + threadIdx.x;
-  if (e >= E) return;
+  const int64_t k = blockIdx.x * 128LL + threadIdx.x;
+  if (k >= static_cast<int64_t>(*count) || k >= E) return;
+  const int64_t e = list[k];
   double U[4][NLOC];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
@@ -440,19 +513,24 @@ __global__ __launch_bounds__(128) void dgq_positivity_kernel(const float* __rest
 }
 
 cvw_status dgquad_positivity(const cvw_mesh* m, const float* u, float* out, const LimitNodes& ln, double gam,
-                             double eps0, hipStream_t s) {
+                             double eps0, uint32_t* count, int32_t* list, hipStream_t s) {
   PositivityTraces tr{};
   for (int i = 0; i <= MAXP; ++i) tr.l0[i] = m->tens.Ld[0][i];
-  // out of place: copy once, the kernel then writes the limited cells only
-  if (out != u && hipMemcpyAsync(out, u, static_cast<size_t>(m->E) * m->nloc * 4 * sizeof(float),
-                                 hipMemcpyDeviceToDevice, s) != hipSuccess) {
-    set_error("state copy failed"); return CVW_EDEVICE;
-  }
-  const dim3 g(static_cast<unsigned>((m->E + 127) / 128)), b(128);
+  hipLaunchKernelGGL(dgq_limit_clear_kernel, dim3(1), dim3(64), 0, s, count);
+  const dim3 g1(static_cast<unsigned>((m->E + 1023) / 1024)), b1(1024);
+  const dim3 g2(static_cast<unsigned>((m->E + 127) / 128)), b2(128);
   switch (m->degree) {
-    case 1: hipLaunchKernelGGL(dgq_positivity_kernel<1>, g, b, 0, s, u, out, m->E, ln, tr, gam, eps0); break;
-    case 2: hipLaunchKernelGGL(dgq_positivity_kernel<2>, g, b, 0, s, u, out, m->E, ln, tr, gam, eps0); break;
-    case 3: hipLaunchKernelGGL(dgq_positivity_kernel<3>, g, b, 0, s, u, out, m->E, ln, tr, gam, eps0); break;
+#define CVW_POS(PP)                                                                                  \
+  case PP:                                                                                           \
+    hipLaunchKernelGGL(dgq_positivity_check_kernel<PP>, g1, b1, 0, s, u, out, m->E, tr, gam, eps0,   \
+                       count, list);                                                                 \
+    hipLaunchKernelGGL(dgq_positivity_kernel<PP>, g2, b2, 0, s, u, out, m->E, ln, tr, gam, eps0,     \
+                       static_cast<const uint32_t*>(count), static_cast<const int32_t*>(list));      \
+    break;
+    CVW_POS(1)
+    CVW_POS(2)
+    CVW_POS(3)
+#undef CVW_POS
     default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
   }
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;

@@ -20,7 +20,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENUMERIC = range(6)
 SEG, TRI, QUAD = 1, 2, 3
 CG, DG = 0, 1
 F32, F64 = 0, 1
-OP_EVAL, OP_STEP, OP_LIMIT = 0, 1, 2
+OP_EVAL, OP_STEP, OP_LIMIT, OP_POS = 0, 1, 2, 3
 EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXPORT_CELL_DOF = range(6)
 
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
@@ -93,7 +93,7 @@ def load():
     lib.cvw_vertex_candidates.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, sz, vp]
     lib.cvw_sensor.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, sz, vp]
     lib.cvw_limit.argtypes = [vp, C.POINTER(ParamsC), vp, vp, C.c_double, vp, vp, sz, vp]
-    lib.cvw_positivity.argtypes = [vp, C.POINTER(ParamsC), vp, vp, C.c_double, vp]
+    lib.cvw_positivity.argtypes = [vp, C.POINTER(ParamsC), vp, vp, C.c_double, vp, sz, vp]
     lib.cvw_residual.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, sz, vp]
     lib.cvw_rk_stage.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                  vp, sz, vp]
@@ -295,11 +295,12 @@ def limit(mesh, prm, u, u_out, threshold: float, gamma_out, ws, stream=None):
                             ws.numel(), _stream(stream)))
 
 
-def positivity(mesh, prm, u, u_out, eps0: float, stream=None):
-    """Zhang-Shu positivity limiter (cvw_positivity); u_out may be u."""
+def positivity(mesh, prm, u, u_out, eps0: float, ws, stream=None):
+    """Zhang-Shu positivity limiter (cvw_positivity): u_out may be u; ws from
+    alloc_workspace(mesh, prm, OP_POS)."""
     n = _state_len(mesh, prm)
     _check(load().cvw_positivity(mesh.handle, C.byref(prm), _fp(u, prm, n, "u"), _fp(u_out, prm, n, "u_out"),
-                                 float(eps0), _stream(stream)))
+                                 float(eps0), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def residual(mesh, prm, u, R, gamma_out, ws, stream=None):
