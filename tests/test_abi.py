@@ -59,6 +59,9 @@ def test_last_error_and_null_arguments_without_gpu():
     assert lib.cvw_mesh_build(None, None) == cvw.EINVAL
     assert b"null" in lib.cvw_last_error()
     assert lib.cvw_workspace_bytes(None, None, 0) == 0
+    assert lib.cvw_workspace_bytes(None, None, cvw.OP_POS) == 0
+    assert lib.cvw_positivity(None, None, None, None, 1e-13, None, 0, None) == cvw.EINVAL
+    assert b"null" in lib.cvw_last_error()
 
 
 def test_params_defaults_marshal():
