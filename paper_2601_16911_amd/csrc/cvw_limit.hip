@@ -78,7 +78,8 @@ __device__ __forceinline__ double centred_seminorm_d(const double (&ch)[KSet<P>:
   return hx * hy * tot;
 }
 
-// Appends the ids of the selected threads of a 1024-thread block to
+// Appends the ids of the selected threads of a block (a multiple of 64
+// threads, at most 1024) to
 // list[0 .. *count): one atomic per block (atomics on one address serialise
 // in the cache, so they are kept few), the threads in order behind it (the
 // blocks in any order).  Every thread of the block must call it.
@@ -94,7 +95,7 @@ __device__ __forceinline__ void append_selected(bool sel, int64_t id, uint32_t* 
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t run = 0;
-    for (int w = 0; w < 16; ++w) {
+    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
       const uint32_t c = wbase[w];
       wbase[w] = run;
       run += c;
@@ -364,17 +365,17 @@ __device__ __forceinline__ double pos_root(double a, double b, double c) {
   return t <= 1.0 ? t : 0.0;
 }
 
-// Stage 1, one thread per cell: the float32 pre-check below, the copy to
+// Stage 1, one thread per cell (512-thread blocks): the float32 pre-check below, the copy to
 // out (out of place), and the list of cells that fail the pre-check:
 // list[0 .. count[0]).
 template <int P>
-__global__ __launch_bounds__(1024) void dgq_positivity_check_kernel(const float* __restrict__ u,
+__global__ __launch_bounds__(512) void dgq_positivity_check_kernel(const float* __restrict__ u,
                                                                     float* __restrict__ out, int64_t E,
                                                                     PositivityTraces tr, double gam, double eps0,
                                                                     uint32_t* __restrict__ count,
                                                                     int32_t* __restrict__ list) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NQ = NLOC + 4 * N1;
-  const int64_t e = blockIdx.x * 1024LL + threadIdx.x;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   bool pass = true;
   if (e < E)
   // float32 pre-check at the nodes and face points.  Each face value carries
@@ -517,7 +518,8 @@ cvw_status dgquad_positivity(const cvw_mesh* m, const float* u, float* out, cons
   PositivityTraces tr{};
   for (int i = 0; i <= MAXP; ++i) tr.l0[i] = m->tens.Ld[0][i];
   hipLaunchKernelGGL(dgq_limit_clear_kernel, dim3(1), dim3(64), 0, s, count);
-  const dim3 g1(static_cast<unsigned>((m->E + 1023) / 1024)), b1(1024);
+  constexpr int CHECK_BS = 512;      // measured: 1024, 512, 256 threads
+  const dim3 g1(static_cast<unsigned>((m->E + CHECK_BS - 1) / CHECK_BS)), b1(CHECK_BS);
   const dim3 g2(static_cast<unsigned>((m->E + 127) / 128)), b2(128);
   switch (m->degree) {
 #define CVW_POS(PP)                                                                                  \
