@@ -235,6 +235,40 @@ def bench_learned(torch, cvw, gm, prm, U, dt, steps: int):
             "status_flags": [cvw.poll_status(gm, wsp), cvw.poll_status(gm, wsl)]}
 
 
+def sensor_only(torch, cvw, n: int, part: str, calls: int, warmup: int):
+    """Only the sensor pass (cvw_sensor, gamma of every cell) on the benchmark
+    state, plain or learned (a network trained briefly as in bench_learned)."""
+    import synth
+    from paper_2601_16911_amd import learned
+    mesh = synth.quad_mesh(n, n)
+    gm = cvw.Mesh(mesh, 3, cvw.DG)
+    prm = synth.Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0))
+    U = torch.from_numpy(euler_config4_state(n, gauss_nodes_2d(3), SMOOTH_K * n / 1024).reshape(-1)).cuda()
+    cp = cvw.make_params(prm)
+    if part == "learned":
+        ns = 256
+        gs = cvw.Mesh(synth.quad_mesh(ns, ns), 3, cvw.DG)
+        Us = torch.from_numpy(euler_config4_state(ns, gauss_nodes_2d(3), SMOOTH_K * ns / 1024).reshape(-1)).cuda()
+        F, G = learned.collect(gs, prm, Us, 1e-5, 8, 4, learned.sigma_reference(gs, cp, Us))
+        net = cvw.Mlp(learned.init_params(4))
+        learned.train(net, F, G, epochs=5, batch=4096, lr=1e-3, seed=4)
+        sref = learned.sigma_reference(gm, cp, U)
+        cp = cvw.make_params(synth.Params(**{**prm.__dict__, "sensor": cvw.LEARNED}), mlp=net, sigma_ref=sref)
+    ws = cvw.alloc_workspace(gm, cp, 1)
+    E = mesh.n_cells
+    gam = torch.empty(E, dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        cvw.sensor(gm, cp, U, gam, None, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        cvw.sensor(gm, cp, U, gam, None, ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(calls, 1)
+    return {"part": part, "cells": E, "calls": calls, "ms_per_call_wall": dt * 1e3,
+            "status_flags": cvw.poll_status(gm, ws)}
+
+
 def bench_ensemble(torch, cvw, steps: int, tune: bool = True):
     """The 64-instance DG ensemble (periodic unit squares, n in [64, 512], p in
     {1, 2, 3}, advection or Burgers, seeded), all instances stepped together by
@@ -379,6 +413,9 @@ def main():
                     help="also run one 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch shapes (no autotuner launches before the timed region)")
+    ap.add_argument("--part", choices=("step", "sensor", "learned"), default="step",
+                    help="sensor / learned: only the plain or learned sensor pass, --steps calls after --warmup "
+                         "(a short program for kernel traces and counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is benchmarked on one MI355X; "
@@ -390,6 +427,9 @@ def main():
     from paper_2601_16911_amd import cvw
 
     torch.cuda.set_device(0)
+    if args.part != "step":
+        print(json.dumps(sensor_only(torch, cvw, args.n, args.part, args.steps, args.warmup)))
+        return
     n, p, nv = args.n, 3, 4
     mesh = synth.quad_mesh(n, n)
     gm = cvw.Mesh(mesh, p, cvw.DG)
@@ -417,10 +457,10 @@ def main():
     grid = 0
     if not args.no_tune:
         from paper_2601_16911_amd import autotune
-        grid = autotune.apply_cached(gm, n_var=nv)
+        grid = autotune.apply_cached(gm, cp)
         if grid is None:
             cvw.vertex_candidates(gm, cp, U, cand, ws)
-            grid = autotune.tune_mesh(gm, cp, U, cand, ws, n_var=nv)
+            grid = autotune.tune_mesh(gm, cp, U, cand, ws)
 
     # every timing event is created and recorded once before the timed region
     # (the first event record of a process initialises the runtime's event

@@ -259,7 +259,9 @@ cvw_status cvw_step(const cvw_mesh* mesh, const cvw_params* prm, void* u, double
                     void* ws, size_t ws_bytes, void* stream);
 
 /* Synchronises `stream`, returns the device status bits in *flags and clears
- * them: bit 0 non-finite residual, bit 1 non-positive density or pressure.
+ * them: bit 0 non-finite residual, bit 1 non-positive density or pressure,
+ * bit 2 a CG mass solve (PCG) that ended its fixed iteration count above its
+ * tolerance.
  * Returns CVW_ENUMERIC when any bit was set. */
 cvw_status cvw_poll_status(const cvw_mesh* mesh, void* ws, size_t ws_bytes, uint32_t* flags, void* stream);
 

@@ -6,9 +6,10 @@ and of the batched work-list kernels (cvw_batch_set_grid).  Results do not
 depend on them; the tuner checks that every candidate reproduces the first
 candidate's output bit for bit before it keeps a timing.
 
-The choice is cached in a JSON file keyed by (device architecture, cell type,
-degree, number of variables, cell count), so a later run with the same
-workload applies it without timing:
+The choice is cached in a JSON file keyed by (device architecture, degree,
+space, nodes per cell, flux (which also fixes the number of variables), cell
+count), so a later run with the same workload applies it without timing
+(`params` is the struct from cvw.make_params):
 
     best = tune_mesh(mesh, params, u, cand, ws)        # times, caches, applies
     apply_cached(mesh, params)                          # applies a cached choice
@@ -35,9 +36,12 @@ def arch() -> str:
     return str(getattr(props, "gcnArchName", props.name)).split(":")[0]
 
 
-def mesh_key(mesh, n_var: int) -> str:
+def mesh_key(mesh, params) -> str:
     info = mesh.info
-    return f"{arch()}|mesh|deg{mesh.degree}|space{mesh.space}|nloc{info['n_loc']}|nvar{n_var}|cells{info['n_cells']}"
+    flux = int(params.flux)
+    n_var = 4 if flux == cvw.EULER else 1
+    return (f"{arch()}|mesh|deg{mesh.degree}|space{mesh.space}|nloc{info['n_loc']}|flux{flux}|nvar{n_var}"
+            f"|cells{info['n_cells']}")
 
 
 def batch_key(batch) -> str:
@@ -92,7 +96,7 @@ def pick(timings: dict) -> int:
     return best
 
 
-def tune_mesh(mesh, params, u, cand, ws, n_var: int = 1, candidates=MESH_CANDIDATES, reps: int = 10,
+def tune_mesh(mesh, params, u, cand, ws, candidates=MESH_CANDIDATES, reps: int = 10,
               path: str | None = None) -> int:
     """Time one Runge-Kutta stage (cvw_rk_stage from u) for each candidate grid,
     check the outputs are bitwise equal, keep and apply the fastest."""
@@ -111,14 +115,14 @@ def tune_mesh(mesh, params, u, cand, ws, n_var: int = 1, candidates=MESH_CANDIDA
         timings[c] = _time(torch, lambda: cvw.rk_stage(mesh, params, u, cand, u, out, 1e-6, 0.75, 0.25, ws), reps)
     best = pick(timings)
     mesh.set_grid(best)
-    store(mesh_key(mesh, n_var), {"grid": best, "ms": timings[best], "timings_ms": {str(k): v for k, v in
+    store(mesh_key(mesh, params), {"grid": best, "ms": timings[best], "timings_ms": {str(k): v for k, v in
                                                                                    timings.items()}}, path)
     return best
 
 
-def apply_cached(mesh, n_var: int = 1, path: str | None = None):
-    """Apply a cached grid for this mesh; returns it, or None if none is cached."""
-    entry = load_cache(path).get(mesh_key(mesh, n_var))
+def apply_cached(mesh, params, path: str | None = None):
+    """Apply a cached grid for this mesh and flux; returns it, or None if none is cached."""
+    entry = load_cache(path).get(mesh_key(mesh, params))
     if entry is None:
         return None
     mesh.set_grid(int(entry["grid"]))

@@ -214,6 +214,12 @@ __global__ __launch_bounds__(PCG_THREADS) void pcg_scalar_kernel(const double* _
   }
 }
 
+// After the fixed launch sequence: a solve that has not met its tolerance
+// (nor broken down) sets ST_PCG_STALL in the workspace status word.
+__global__ void pcg_check_kernel(const double* __restrict__ S, uint32_t* __restrict__ status) {
+  if (threadIdx.x == 0 && !pcg_done(S)) atomicOr(status, ST_PCG_STALL);
+}
+
 __global__ void pcg_setup_kernel(double* __restrict__ S, double tol2) {
   if (threadIdx.x != 0) return;
   for (int i = 0; i < 8; ++i) S[i] = 0.0;
@@ -266,7 +272,7 @@ size_t pcg_partials(int64_t n) { return nbk(n, PCG_THREADS); }
 template <typename Real>
 cvw_status cg_mass_solve(const cvw_mesh* m, const Real* b, Real* x, Real* r, Real* z, Real* p, Real* Ap,
                          Real* ycell, double* part, double* S, const Real* dinv, double tol, int maxit,
-                         hipStream_t s) {
+                         uint32_t* status, hipStream_t s) {
   const int64_t n = m->ndof;
   const int nb = static_cast<int>(nbk(n, PCG_THREADS));
   const dim3 g(nb), t(PCG_THREADS);
@@ -282,6 +288,7 @@ cvw_status cg_mass_solve(const cvw_mesh* m, const Real* b, Real* x, Real* r, Rea
     hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), t, 0, s, part, nb, S, 2);
     hipLaunchKernelGGL((pcg_direction_kernel<Real>), g, t, 0, s, p, z, n, S);
   }
+  hipLaunchKernelGGL(pcg_check_kernel, dim3(1), dim3(64), 0, s, S, status);
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 
@@ -294,9 +301,11 @@ cvw_status stage_update(const Real* us, const Real* un, const Real* x, const Rea
 }
 
 template cvw_status cg_mass_solve<float>(const cvw_mesh*, const float*, float*, float*, float*, float*, float*,
-                                         float*, double*, double*, const float*, double, int, hipStream_t);
+                                         float*, double*, double*, const float*, double, int, uint32_t*,
+                                         hipStream_t);
 template cvw_status cg_mass_solve<double>(const cvw_mesh*, const double*, double*, double*, double*, double*,
-                                          double*, double*, double*, double*, const double*, double, int, hipStream_t);
+                                          double*, double*, double*, double*, const double*, double, int,
+                                          uint32_t*, hipStream_t);
 template cvw_status stage_update<float>(const float*, const float*, const float*, const float*, float*, double,
                                         double, double, int64_t, hipStream_t);
 template cvw_status stage_update<double>(const double*, const double*, const double*, const double*, double*,

@@ -1406,7 +1406,7 @@ cvw_status generic_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, 
     Real* x = static_cast<Real*>(w.x);
     st = cg_mass_solve<Real>(m, rhs, x, static_cast<Real*>(w.r), static_cast<Real*>(w.z), static_cast<Real*>(w.p),
                              static_cast<Real*>(w.Ap), static_cast<Real*>(w.rcell), w.part, w.S, dinv,
-                             f64 ? PCG_TOL_F64 : PCG_TOL_F32, f64 ? PCG_MAXIT_F64 : PCG_MAXIT_F32, s);
+                             f64 ? PCG_TOL_F64 : PCG_TOL_F32, f64 ? PCG_MAXIT_F64 : PCG_MAXIT_F32, w.status, s);
     if (st != CVW_OK) return st;
     return stage_update<Real>(us, un, x, nullptr, uo, a0, b0, dt, n, s);
   }

@@ -12,7 +12,7 @@
 namespace cvw {
 
 // status bits of the workspace status word
-enum : uint32_t { ST_NONFINITE = 1u, ST_NONPOSITIVE = 2u };
+enum : uint32_t { ST_NONFINITE = 1u, ST_NONPOSITIVE = 2u, ST_PCG_STALL = 4u };
 
 // operation modes of the evaluation kernels
 enum Mode : int { MODE_SENSOR = 0, MODE_RESIDUAL = 1, MODE_STAGE = 2 };
@@ -360,7 +360,7 @@ size_t pcg_partials(int64_t n);
 template <typename Real>
 cvw_status cg_mass_solve(const cvw_mesh* m, const Real* b, Real* x, Real* r, Real* z, Real* p, Real* Ap,
                          Real* ycell, double* part, double* S, const Real* dinv, double tol, int maxit,
-                         hipStream_t s);
+                         uint32_t* status, hipStream_t s);
 template <typename Real>
 cvw_status stage_update(const Real* us, const Real* un, const Real* x, const Real* dinv, Real* uo, double a0,
                         double b0, double dt, int64_t n, hipStream_t s);

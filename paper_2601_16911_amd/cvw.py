@@ -21,6 +21,7 @@ SEG, TRI, QUAD = 1, 2, 3
 CG, DG = 0, 1
 F32, F64 = 0, 1
 OP_EVAL, OP_STEP, OP_LIMIT, OP_POS = 0, 1, 2, 3
+ADVECT_CONST, ADVECT_ROT, BURGERS, KPP, EULER = 0, 1, 2, 3, 4     # cvw_flux
 EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXPORT_CELL_DOF = range(6)
 
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",

@@ -23,12 +23,16 @@ def test_tune_mesh(tmp_path):
     ws = cvw.alloc_workspace(gm, cp, 0)
     cand = torch.empty((mesh.n_vertices, 9), dtype=torch.float32, device="cuda")
     cvw.vertex_candidates(gm, cp, U, cand, ws)
-    best = autotune.tune_mesh(gm, cp, U, cand, ws, n_var=4, candidates=(8, 24, 0), reps=3, path=path)
+    best = autotune.tune_mesh(gm, cp, U, cand, ws, candidates=(8, 24, 0), reps=3, path=path)
     assert best in (8, 24, 0)
     gm.set_grid(0)
-    assert autotune.apply_cached(gm, n_var=4, path=path) == best
-    entry = autotune.load_cache(path)[autotune.mesh_key(gm, 4)]
+    assert autotune.apply_cached(gm, cp, path=path) == best
+    entry = autotune.load_cache(path)[autotune.mesh_key(gm, cp)]
     assert set(entry["timings_ms"]) == {"8", "24", "0"}
+    # another flux on the same mesh has its own entry
+    cp_adv = cvw.make_params(synth.Params(flux=synth.ADVECT_CONST, flux_param=(1.0, 0.5, 0, 0)))
+    assert autotune.mesh_key(gm, cp_adv) != autotune.mesh_key(gm, cp)
+    assert autotune.apply_cached(gm, cp_adv, path=path) is None
 
 
 def test_tune_batch_restores_states(tmp_path):
