@@ -10,17 +10,21 @@ from the stated ranges) with its quadrant interfaces smoothed over about half
 a cell, so that the sensor and the shock-capturing weights are active along
 the interfaces.  Everything is resident in HBM before timing starts.
 
-One step = one SSP-RK3 time step = three stages, each stage = the vertex
-HWENO pass (vertex candidates) plus the fused cell pass (sensor, viscosity,
-shock-capturing weights, volume and interface terms, mass inverse, stage
-update).  value = stabilised-residual DOF updates per second
+One step = one SSP-RK3 time step = three stages, each stage = the fused
+sensor pass (vertex HWENO candidates and the cell sensor gamma_e in one
+kernel) plus the cell pass (viscosity, shock-capturing weights, volume and
+interface terms, mass inverse, stage update).  value = stabilised-residual DOF updates per second
 = 3 * n_dof * n_var * K / (time of K steps).
 
-The roofline object describes the dominant kernel (the fused cell pass,
-dgq_eval_kernel): its launches are bracketed by HIP events on the stream they
-run on, inside the timed region.  The kernel is bound by VALU instruction
-issue, not by HBM: valu_issue relates its counted VALU wave instructions per
-launch (profiles/valu_dgq_eval_config4.json) to the issue roof of the chip.
+The roofline object describes the dominant kernel (the cell pass,
+dgq_eval_kernel, with gamma supplied by the sensor pass): its launches are
+bracketed by HIP events on the stream they run on, inside the timed region.
+It is bound by vector-ALU instruction issue ("alu": algorithmic flops per
+launch against the fp32 vector peak; valu_issue relates the counted VALU wave
+instructions per launch, profiles/valu_dgq_eval_config4.json, to the issue
+roof; hbm_view gives its compulsory bytes against HBM).  sensor_pass gives the
+fused sensor pass (one launch per stage) against HBM with its compulsory
+bytes: read the sensor field once, write gamma.
 """
 from __future__ import annotations
 
@@ -98,6 +102,28 @@ def measured_valu():
 # VALU issue roof: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles of
 # a 16-lane SIMD, 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+# published fp32 vector peak (it counts packed fp32, which this build does not
+# issue: ordinary fp32 code tops out at half of it)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def cell_pass_flops(p: int, nv: int) -> float:
+    """Algorithmic flops per cell of one DG quadrilateral cell pass (Euler,
+    collocated Gauss rule, n = (p+1)^2 points, 4 (p+1) face points): the
+    arithmetic the discretisation needs, counted once (an FMA is 2 flops)."""
+    n1 = p + 1
+    n = n1 * n1
+    nf = 4 * n1
+    grad = nv * n * 2 * n1 * 2                 # du/dxi, du/deta at every point (sum factorised)
+    flux = 18 * n                              # Euler flux at the points
+    speed = 6 * n + n                          # |v| + c and the cell maximum
+    stab = nv * n * 2 * 3                      # W (nu (1 - gamma) alpha grad u - f)
+    test = nv * n * 2 * n1 * 2                 # contraction with the test-function gradients
+    traces = 2 * nv * nf * n1 * 2              # own and neighbour traces at the face points
+    hll = 72 * nf + nv * nf                    # HLL flux with Davis speeds, face weight
+    lift = nv * nf * n1 * 2                    # face flux back to the nodes of its normal line
+    update = 5 * nv * n                        # mass inverse and the Shu-Osher update
+    return float(grad + flux + speed + stab + test + traces + hll + lift + update)
 
 
 def cpu_baseline(target_seconds: float = 15.0):
@@ -466,25 +492,30 @@ def main():
     # (the first event record of a process initialises the runtime's event
     # machinery, a host stall of tens of ms)
     hev = HipEvents()
-    ev = [(hev.create(), hev.create()) for _ in range(3 * args.steps)]
+    ev = [(hev.create(), hev.create(), hev.create()) for _ in range(3 * args.steps)]
     t_start, t_end = hev.create(), hev.create()
-    for e in [t_start, t_end] + [x for pair in ev for x in pair]:
+    for e in [t_start, t_end] + [x for tri in ev for x in tri]:
         hev.record(e, stream)
     torch.cuda.synchronize()
     n_rec = [0]
+    gam = torch.empty(E, dtype=torch.float32, device="cuda")
 
     def rk_step(record: bool):
+        # one stage: the sensor pass (gamma_e of u_stage), then the cell pass
+        # with that gamma (viscosity, SC weights, volume and interface terms,
+        # mass inverse, stage update); events before, between and after
         stages = ((U, None, U1, 0.0, 1.0), (U1, U, U2, 0.75, 0.25), (U2, U, U, 1.0 / 3.0, 2.0 / 3.0))
         for (us, un, uo, a0, b0) in stages:
-            cvw.vertex_candidates(gm, cp, us, cand, ws)
             if record:
-                e0, e1 = ev[n_rec[0]]
+                e0, e1, e2 = ev[n_rec[0]]
                 n_rec[0] += 1
                 hev.record(e0, stream)
-                cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
+            cvw.sensor(gm, cp, us, gam, None, ws)
+            if record:
                 hev.record(e1, stream)
-            else:
-                cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
+            cvw.rk_stage_gamma(gm, cp, us, gam, un, uo, dt, a0, b0, ws)
+            if record:
+                hev.record(e2, stream)
 
     for _ in range(args.warmup):
         rk_step(False)
@@ -497,8 +528,9 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     t_total = hev.elapsed_ms(t_start, t_end) / 1e3
-    eval_ms = [hev.elapsed_ms(a, b) for a, b in ev]
-    hev.destroy(t_start, t_end, *[x for pair in ev for x in pair])
+    sensor_ms = [hev.elapsed_ms(a, b) for a, b, _ in ev]
+    eval_ms = [hev.elapsed_ms(b, c) for _, b, c in ev]
+    hev.destroy(t_start, t_end, *[x for tri in ev for x in tri])
     flags = cvw.poll_status(gm, ws)
 
     # residual-only timing (vertex pass + fused cell pass writing R), same state
@@ -519,15 +551,18 @@ def main():
     torch.cuda.synchronize()
     t_res = r0.elapsed_time(r1) / 1e3 / nres
 
-    # algorithmic bytes of one fused cell-pass launch (stage mode, averaged over
-    # the three stages): read u_stage, write u_out, read u_n in stages 2 and 3,
-    # read the vertex candidates once per vertex
-    state_bytes = nv * ndof * 4
-    alg_bytes = state_bytes * (1 + 1 + 2.0 / 3.0) + mesh.n_vertices * nk * 4
+    # the cell pass (dominant kernel): algorithmic flops per launch, and the
+    # bytes it must move (read u_stage and gamma, write u_out, read u_n in
+    # stages 2 and 3: averaged over the three stages)
     t_eval = float(np.mean(eval_ms)) / 1e3
-    achieved = alg_bytes / t_eval / 1e9
+    flops = cell_pass_flops(p, nv) * E
+    state_bytes = nv * ndof * 4
+    alg_bytes = state_bytes * (1 + 1 + 2.0 / 3.0) + 4 * E
     traffic = measured_traffic()
     valu = measured_valu()
+    # the sensor pass (fused: read the sensor field once, write gamma)
+    t_sens = float(np.mean(sensor_ms)) / 1e3
+    sens_bytes = (4 * nloc + 4) * E
 
     value = 3.0 * ndof * nv * args.steps / t_total
     out = {
@@ -538,16 +573,23 @@ def main():
         "config": {"workload": f"2D Euler DG Q3, periodic {n}x{n} quads ({E} cells, {ndof * nv} DOFs), "
                                "four-quadrant data with interfaces smoothed over ~2 cells, plain CV-WENO sensor + SC "
                                "quadrature, SSP-RK3", "cells": E, "degree": p, "n_var": nv,
-                   "dofs": ndof * nv, "step": "one SSP-RK3 step = 3 x (vertex pass + fused cell pass)",
+                   "dofs": ndof * nv, "step": "one SSP-RK3 step = 3 x (fused sensor pass + cell pass)",
                    "cell_pass_blocks": grid if grid else "default"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "dgq_eval_kernel<3, EULER> (fused cell pass, stage mode)",
-                     "avg_launch_ms": t_eval * 1e3, "alg_bytes_per_launch": alg_bytes},
+        "roofline": {"bound": "alu", "achieved": flops / t_eval / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / t_eval / 1e12 / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "dgq_eval_kernel<3, EULER> (cell pass, stage mode, gamma supplied)",
+                     "avg_launch_ms": t_eval * 1e3, "alg_flops_per_launch": flops,
+                     "flops_per_cell": cell_pass_flops(p, nv)},
+        "hbm_view": {"achieved": alg_bytes / t_eval / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg_bytes / t_eval / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
         "valu_issue": {"instr_per_launch": valu, "achieved": (valu / t_eval) if valu else None,
                        "peak": VALU_ISSUE_PEAK, "unit": "wave-instr/s",
                        "frac": (valu / t_eval / VALU_ISSUE_PEAK) if valu else None,
                        "kernel": "dgq_eval_kernel<3, EULER>"},
+        "sensor_pass": {"bound": "hbm", "kernel": "dgq_sensor_tile_kernel<3> (fused plain sensor pass)",
+                        "avg_launch_ms": t_sens * 1e3, "value": E / t_sens, "unit_value": "cells/s",
+                        "achieved": sens_bytes / t_sens / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": sens_bytes / t_sens / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": sens_bytes},
         "residual_only": {"value": ndof * nv / t_res, "unit": "DOF-updates/s", "ms": t_res * 1e3},
         "status_flags": flags,
         "wall_s_timed": wall,

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 6
+#define CVW_ABI_VERSION 7
 
 typedef enum {
   CVW_OK = 0,
@@ -123,6 +123,10 @@ typedef struct {
   int32_t n_faces;
   int32_t uniform;           /* 1: congruent axis-aligned cells (structured fast path) */
   double hx, hy;             /* cell sizes when uniform                          */
+  int64_t grid_nx, grid_ny;  /* DG quadrilaterals on a structured periodic grid (cells
+                                numbered e = i + grid_nx j, four cells at every vertex):
+                                the grid's size, which enables the fused sensor pass;
+                                0 otherwise                                         */
 } cvw_mesh_info;
 
 typedef struct cvw_mesh cvw_mesh;
@@ -187,7 +191,10 @@ cvw_status cvw_vertex_candidates(const cvw_mesh* mesh, const cvw_params* prm, co
  * shock-capturing quadrature weights alpha_q (eqs. alphaq / alpha_prelim,
  * applied where gamma_e < c_gamma, Sec. 5).  gamma: device [n_cells];
  * alpha: device [n_cells][n_q] or NULL.  For systems the sensor field is the
- * density (Sec. 5.4). */
+ * density (Sec. 5.4).  On a structured periodic DG quadrilateral grid
+ * (cvw_mesh_info.grid_nx > 0) the plain sensor runs as one fused pass that
+ * reads the sensor field once and writes gamma (vertex and cell stages meet in
+ * on-chip memory); elsewhere the vertex candidates go through the workspace. */
 cvw_status cvw_sensor(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* gamma,
                       void* alpha, void* ws, size_t ws_bytes, void* stream);
 
@@ -237,7 +244,9 @@ cvw_status cvw_residual(const cvw_mesh* mesh, const cvw_params* prm, const void*
                         void* gamma_out, void* ws, size_t ws_bytes, void* stream);
 
 /* One stage of the SSP Runge-Kutta method in Shu-Osher form (Sec. 5), given
- * the vertex candidates `cand` of u_stage (from cvw_vertex_candidates):
+ * the vertex candidates `cand` of u_stage (from cvw_vertex_candidates; not
+ * read, and may be NULL, on a structured periodic DG quadrilateral grid with
+ * the plain sensor, where the stage runs the fused sensor pass itself):
  *   u_out = a0 * u_n + b0 * (u_stage + dt * L(u_stage)),  L = -M^{-1} R
  * (eq. sdstab).  M: DG exact element mass (diagonal on Gauss-node quads and
  * segments, M_ref |det J| on triangles); CG the consistent global mass,
@@ -250,6 +259,16 @@ cvw_status cvw_residual(const cvw_mesh* mesh, const cvw_params* prm, const void*
 cvw_status cvw_rk_stage(const cvw_mesh* mesh, const cvw_params* prm, const void* u_stage, const void* cand,
                         const void* u_n, void* u_out, double dt, double a0, double b0, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* The same stage on DG quadrilaterals with the sensor values supplied:
+ * gamma (device float32 [n_cells]) gives gamma_e of eq. gamma for u_stage
+ * (from cvw_sensor with alpha = NULL, plain or learned), whatever prm->sensor
+ * says; the shock-capturing weights (eq. alphaq) are formed in the cell pass
+ * where gamma_e < c_gamma.  u_out must not alias u_stage or gamma; the other
+ * arguments and errors as for cvw_rk_stage (CVW_EUNSUPPORTED on other meshes). */
+cvw_status cvw_rk_stage_gamma(const cvw_mesh* mesh, const cvw_params* prm, const void* u_stage, const void* gamma,
+                              const void* u_n, void* u_out, double dt, double a0, double b0, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /* n_steps steps of the three-stage SSP Runge-Kutta method with fixed dt,
  * u updated in place (Sec. 2.2 / Sec. 5): per stage the vertex candidates

@@ -355,7 +355,13 @@ __device__ __forceinline__ void dgq_eval_body(
   // broadcasts give every lane all four (eq. taylorcand output)
   // neighbour of the lane's face point (degree 3), fetched early
   const int32_t en_pre = (P == 3) ? nbr[e * 4 + L.slot] : 0;
-  const bool plain = (ms.sensor_kind == CVW_SENSOR_PLAIN);
+  // gamma_e given (a sensor pass ran before: fused plain, learned) or fixed:
+  // the sensor-field derivatives below then serve only the shock-capturing
+  // weights, which are active only where gamma_e < c_gamma
+  const bool given = (gamma_in != nullptr);
+  const bool plain = !given && (ms.sensor_kind == CVW_SENSOR_PLAIN);
+  const float gpre = given ? gamma_in[e] : ms.fixed_gamma;
+  const bool need_du = plain || (ms.sc_on && __ballot(static_cast<double>(gpre) < ms.c_gammad) != 0);
   float myc[NK] = {};
   if (plain) {
     const int64_t vid = cell_vtx[e * 4 + a];
@@ -373,7 +379,7 @@ __device__ __forceinline__ void dgq_eval_body(
   // to its value at node (0, 0) so that constant data gives exactly zero
   // (needed by the plain sensor and by the shock-capturing weights only)
   float Du[NK] = {};
-  if (plain || ms.sc_on) {
+  if (need_du) {
     double rho = nd ? static_cast<double>(uv[0]) : 0.0;
     const double ref = rowbcastd<0>(rho);          // node (0, 0) = lane 0 of the row
     rho = nd ? rho - ref : 0.0;
@@ -418,10 +424,8 @@ __device__ __forceinline__ void dgq_eval_body(
 
   // ---- sensor gamma_e (cell stage of the cell-vertex reconstruction) --------
   float gam;
-  if (ms.sensor_kind == CVW_SENSOR_FIXED) {
-    gam = ms.fixed_gamma;
-  } else if (ms.sensor_kind == CVW_SENSOR_LEARNED) {
-    gam = gamma_in[e];                         // from the network, one value per cell
+  if (!plain) {
+    gam = gpre;                                // given per cell, or the fixed value
   } else {
     // The vertex candidates p_l (eq. taylorcand) are re-expanded about the
     // cell centre, one vertex per quad lane (lane a holds vertex a; the rows
@@ -712,7 +716,10 @@ __device__ __forceinline__ void dgq_eval_body_p1(
   }
   // neighbours across the lane's x and y face points, fetched early
   const int32_t enx = nbr[e * 4 + L.slotx], eny = nbr[e * 4 + L.sloty];
-  const bool plain = (ms.sensor_kind == CVW_SENSOR_PLAIN);
+  const bool given = (gamma_in != nullptr);
+  const bool plain = !given && (ms.sensor_kind == CVW_SENSOR_PLAIN);
+  const float gpre = given ? gamma_in[e] : ms.fixed_gamma;
+  const bool need_du = plain || (ms.sc_on && __ballot(static_cast<double>(gpre) < ms.c_gammad) != 0);
   float myc[NK] = {};
   if (plain) {                                 // lane l fetches vertex l (eq. taylorcand output)
     const int64_t vid = cell_vtx[e * 4 + l];
@@ -723,7 +730,7 @@ __device__ __forceinline__ void dgq_eval_body_p1(
   // first derivatives of the sensor field at the own node, float64, relative
   // to node (0, 0) of the cell
   float Du[NK] = {};
-  if (plain || ms.sc_on) {
+  if (need_du) {
     double rho = static_cast<double>(uv[0]);
     rho -= qbcastd<0>(rho);
     constexpr int X0 = 0 | (0 << 2) | (2 << 4) | (2 << 6), X1 = 1 | (1 << 2) | (3 << 4) | (3 << 6);
@@ -736,10 +743,8 @@ __device__ __forceinline__ void dgq_eval_body_p1(
   const float sw = order_weighted_dot<P>(Du, Du, he2);
 
   float gam;
-  if (ms.sensor_kind == CVW_SENSOR_FIXED) {
-    gam = ms.fixed_gamma;
-  } else if (ms.sensor_kind == CVW_SENSOR_LEARNED) {
-    gam = gamma_in[e];
+  if (!plain) {
+    gam = gpre;
   } else {
     const float n2 = quad_sum(Wq * sw);
     // the candidates' derivatives are constant: the centred expansion is the

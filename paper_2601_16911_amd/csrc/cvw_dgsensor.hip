@@ -1,0 +1,486 @@
+// Fused sensor pass for DG on a structured periodic grid of congruent
+// axis-aligned quadrilaterals (cells numbered e = i + nx j), p = 1..3, gfx950.
+//
+// One 256-thread block per 16 x 16 tile of cells, one thread per cell; the
+// vertex stage and the cell stage of the cell-vertex reconstruction (Sec. 3.2)
+// meet in LDS, so the sensor field is read from HBM once and only gamma_e is
+// written back.
+//
+//  (A) Every cell of the tile and of its one-cell halo ring turns its nodal
+//      values of the sensor field (variable 0) into Legendre coefficients
+//      c_mn (float64, data taken relative to node (0, 0) so that constants
+//      give exactly zero), and from them its Hermite data at the four corners
+//      (eq. taylorsol, reference derivatives, by the closed values of
+//      P_m^{(k)}(+-1)).  The pointwise indicator beta = ||u_h^e||_{x_i}
+//      (eq. pointsnorm) gives the Jiang-Shu weight w = (eps + beta)^{-r};
+//      w and w D^k u_h^e(x_i) are summed per vertex in LDS, corner by corner
+//      (one contribution per vertex per round: no atomics, fixed order).
+//  (B) Each tile cell reads its four vertex candidates (eq. taylorcand),
+//      moves them to the cell centre, writes them and its own polynomial in
+//      tensor Legendre coefficients and takes every element semi-norm
+//      (eq. snorm) in closed form from those coefficients (the derivative of
+//      a Legendre series is a Legendre series; the P_j are orthogonal).  The
+//      weights of eq. finalweno, the blend and ||u_h^e - u_h^{e,*}||_e give
+//      gamma_e (eq. gamma).
+//
+// Reference coordinates xi = 2 (x - x_c) / h_x, eta likewise; the nodes are
+// the Gauss points, lexicographic with x fastest.
+#include "cvw_device.h"
+#include "cvw_dgq_common.h"
+
+namespace cvw {
+
+namespace {
+
+constexpr double cfact(int n) { return n <= 1 ? 1.0 : n * cfact(n - 1); }
+
+// Legendre tables of degree < N1
+template <int N1>
+struct Leg {
+  double D[N1][N1][N1];   // D[k][j][m]: coefficient of P_j in the k-th derivative of P_m
+  double E[N1][N1];       // E[k][m] = P_m^{(k)}(+1); P_m^{(k)}(-1) = (-1)^{m+k} E[k][m]
+  double M[4][N1];        // xi^a / a! = sum_j M[a][j] P_j (a <= 3)
+  double Nr[N1];          // int_{-1}^{1} P_j^2 = 2 / (2j + 1)
+  constexpr Leg() : D{}, E{}, M{}, Nr{} {
+    double D1[N1][N1] = {};
+    for (int j = 0; j < N1; ++j)
+      for (int m = 0; m < N1; ++m) D1[j][m] = (m > j && ((m - j) & 1)) ? 2.0 * j + 1.0 : 0.0;
+    for (int j = 0; j < N1; ++j) D[0][j][j] = 1.0;
+    for (int k = 1; k < N1; ++k)
+      for (int j = 0; j < N1; ++j)
+        for (int m = 0; m < N1; ++m) {
+          double s = 0.0;
+          for (int i = 0; i < N1; ++i) s += D1[j][i] * D[k - 1][i][m];
+          D[k][j][m] = s;
+        }
+    for (int k = 0; k < N1; ++k)
+      for (int m = 0; m < N1; ++m) {
+        double p2 = 1.0;
+        for (int i = 0; i < k; ++i) p2 *= 2.0;
+        E[k][m] = (m >= k) ? cfact(m + k) / (cfact(m - k) * p2 * cfact(k)) : 0.0;
+      }
+    const double Mx[4][4] = {{1.0, 0.0, 0.0, 0.0},
+                             {0.0, 1.0, 0.0, 0.0},
+                             {1.0 / 6.0, 0.0, 1.0 / 3.0, 0.0},
+                             {0.0, 1.0 / 10.0, 0.0, 1.0 / 15.0}};
+    for (int a = 0; a < 4; ++a)
+      for (int j = 0; j < N1; ++j) M[a][j] = Mx[a][j];
+    for (int j = 0; j < N1; ++j) Nr[j] = 2.0 / (2.0 * j + 1.0);
+  }
+};
+template <int N1>
+inline constexpr Leg<N1> leg{};
+
+constexpr int TS = 16;            // tile side in cells
+constexpr int NVX = TS + 1;       // tile side in vertices
+
+// sum_k Sk[k] int_ref |d^k p|^2 for p = sum C[m][n] P_m(xi) P_n(eta) over
+// 1 <= |k| <= P (eq. snorm, squared; Sk carries h_e^{2|k|-2}, the map and the
+// cell area).  TOT: C[m][n] = 0 for m + n > P (a total-degree polynomial).
+template <int P, bool TOT>
+__device__ __forceinline__ float seminorm_sq(const float (&C)[P + 1][P + 1], const float* Sk) {
+  constexpr int N1 = P + 1;
+  constexpr KSet<P> ks = kset<P>;
+  constexpr Leg<N1> L = leg<N1>;
+  // X[kx][j][n] = sum_m D[kx][j][m] C[m][n]
+  float X[N1][N1][N1];
+#pragma unroll
+  for (int kx = 0; kx < N1; ++kx)
+#pragma unroll
+    for (int j = 0; j < N1; ++j)
+#pragma unroll
+      for (int n = 0; n < N1; ++n) {
+        float s = 0.0f;
+        bool any = false;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+          if (L.D[kx][j][m] == 0.0 || (TOT && m + n > P)) continue;
+          s = any ? fmaf(static_cast<float>(L.D[kx][j][m]), C[m][n], s) : static_cast<float>(L.D[kx][j][m]) * C[m][n];
+          any = true;
+        }
+        X[kx][j][n] = s;
+      }
+  float total = 0.0f;
+#pragma unroll
+  for (int t = 0; t < KSet<P>::NK; ++t) {
+    const int kx = ks.x[t], ky = ks.y[t];
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j + kx < N1; ++j)
+#pragma unroll
+      for (int l = 0; l + ky < N1; ++l) {
+        float v = 0.0f;
+        bool any = false;
+#pragma unroll
+        for (int n = 0; n < N1; ++n) {
+          if (L.D[ky][l][n] == 0.0) continue;
+          if (TOT) {   // skip products known to be zero
+            bool nz = false;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) nz = nz || (L.D[kx][j][m] != 0.0 && m + n <= P);
+            if (!nz) continue;
+          }
+          v = any ? fmaf(static_cast<float>(L.D[ky][l][n]), X[kx][j][n], v)
+                  : static_cast<float>(L.D[ky][l][n]) * X[kx][j][n];
+          any = true;
+        }
+        if (any) acc = fmaf(static_cast<float>(L.Nr[j] * L.Nr[l]) * v, v, acc);
+      }
+    total = fmaf(Sk[t], acc, total);
+  }
+  return total;
+}
+
+// Tensor Legendre coefficients (m + n <= P, the constant omitted) of the
+// total-degree polynomial with reference derivatives d[k] at the cell centre
+template <int P>
+__device__ __forceinline__ void taylor_to_legendre(const float (&d)[KSet<P>::NK], float (&C)[P + 1][P + 1]) {
+  constexpr int N1 = P + 1;
+  constexpr KSet<P> ks = kset<P>;
+  constexpr Leg<N1> L = leg<N1>;
+#pragma unroll
+  for (int m = 0; m < N1; ++m)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+      float s = 0.0f;
+      bool any = false;
+      if (m + n <= P && (m + n) > 0) {
+#pragma unroll
+        for (int t = 0; t < KSet<P>::NK; ++t) {
+          const double c = L.M[ks.x[t]][m] * L.M[ks.y[t]][n];
+          if (c == 0.0) continue;
+          s = any ? fmaf(static_cast<float>(c), d[t], s) : static_cast<float>(c) * d[t];
+          any = true;
+        }
+      }
+      C[m][n] = s;
+    }
+}
+
+// Corner data of one cell: Legendre coefficients of its sensor field (float64
+// in, float out) and, per corner l (SW, SE, NE, NW), the Jiang-Shu weight
+// W[l] and the weighted reference Hermite data WH[l][k].
+template <int P>
+__device__ __forceinline__ void cell_corners(const float* __restrict__ ue, const SensorTileArgs& A,
+                                             const MethodScalars& ms, float (&cf)[P + 1][P + 1],
+                                             float (&W)[4], float (&WH)[4][KSet<P>::NK]) {
+  constexpr int N1 = P + 1, NK = KSet<P>::NK;
+  constexpr KSet<P> ks = kset<P>;
+  constexpr Leg<N1> L = leg<N1>;
+  float uf[N1 * N1];
+  if constexpr (N1 == 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float4 v = reinterpret_cast<const float4*>(ue)[j];
+      uf[4 * j] = v.x;
+      uf[4 * j + 1] = v.y;
+      uf[4 * j + 2] = v.z;
+      uf[4 * j + 3] = v.w;
+    }
+  } else if constexpr (N1 == 2) {
+    const float4 v = *reinterpret_cast<const float4*>(ue);
+    uf[0] = v.x;
+    uf[1] = v.y;
+    uf[2] = v.z;
+    uf[3] = v.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < N1 * N1; ++i) uf[i] = ue[i];
+  }
+  // data relative to node (0, 0): exact in float64
+  const double r0 = static_cast<double>(uf[0]);
+  // x transform: tx[m][j] = sum_i T[m][i] (u_ij - u_00)
+  double tx[N1][N1];
+#pragma unroll
+  for (int j = 0; j < N1; ++j) {
+    double r[N1];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) r[i] = static_cast<double>(uf[i + N1 * j]) - r0;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      // node (0, 0) itself contributes exactly zero: row 0 starts at i = 1
+      const int ib = (j == 0) ? 1 : 0;
+      double s = A.T[m][ib] * r[ib];
+#pragma unroll
+      for (int i = ib + 1; i < N1; ++i) s = fma(A.T[m][i], r[i], s);
+      tx[m][j] = s;
+    }
+  }
+  // y transform: c[m][n] = sum_j T[n][j] tx[m][j] (c[0][0] is not needed)
+  double c[N1][N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+      if (m == 0 && n == 0) {
+        c[0][0] = 0.0;
+        continue;
+      }
+      double s = A.T[n][0] * tx[m][0];
+#pragma unroll
+      for (int j = 1; j < N1; ++j) s = fma(A.T[n][j], tx[m][j], s);
+      c[m][n] = s;
+      cf[m][n] = static_cast<float>(s);
+    }
+  cf[0][0] = 0.0f;
+  // x stage at xi = +-1: g[kx][n] = sum_m c[m][n] P_m^{(kx)}(+-1) = Ev +- Od
+  double gp[N1][N1], gm[N1][N1];
+#pragma unroll
+  for (int kx = 0; kx < N1; ++kx)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+      double ev = 0.0, od = 0.0;
+#pragma unroll
+      for (int m = kx; m < N1; ++m) {
+        if (((m - kx) & 1) == 0) ev = fma(L.E[kx][m], c[m][n], ev);
+        else od = fma(L.E[kx][m], c[m][n], od);
+      }
+      gp[kx][n] = ev + od;
+      gm[kx][n] = ev - od;
+    }
+  // y stage at eta = +-1 for every multi-index, then the corner weights
+  float H[4][NK];
+#pragma unroll
+  for (int t = 0; t < NK; ++t) {
+    const int kx = ks.x[t], ky = ks.y[t];
+#pragma unroll
+    for (int sxp = 0; sxp < 2; ++sxp) {
+      double ev = 0.0, od = 0.0;
+#pragma unroll
+      for (int n = ky; n < N1; ++n) {
+        const double g = sxp ? gp[kx][n] : gm[kx][n];
+        if (((n - ky) & 1) == 0) ev = fma(L.E[ky][n], g, ev);
+        else od = fma(L.E[ky][n], g, od);
+      }
+      // corners: SW (-,-) 0, SE (+,-) 1, NE (+,+) 2, NW (-,+) 3
+      H[sxp ? 1 : 0][t] = static_cast<float>(ev - od);
+      H[sxp ? 2 : 3][t] = static_cast<float>(ev + od);
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    float b2 = 0.0f;
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+      const float ek = A.sk[t] * H[l][t];
+      b2 = fmaf(ek, ek, b2);
+    }
+    float w;
+    if (ms.fast_exp) {
+      const float den = ms.eps_v + fsqrt(b2);
+      w = frcp(den * den);
+    } else {
+      w = powf(ms.eps_v + powf(sqrtf(b2), ms.q_beta), -ms.r);
+    }
+    W[l] = w;
+#pragma unroll
+    for (int t = 0; t < NK; ++t) WH[l][t] = w * H[l][t];
+  }
+}
+
+}  // namespace
+
+template <int P>
+__global__ __launch_bounds__(256) void dgq_sensor_tile_kernel(const float* __restrict__ u, float* __restrict__ gamma,
+                                                              SensorTileArgs A, MethodScalars ms, int64_t nb_padded) {
+  constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
+  constexpr KSet<P> ks = kset<P>;
+  __shared__ float V[NK + 1][NVX * NVX];   // per vertex: sum w D^k (k < NK), sum w (NK)
+  const int64_t lb = xcd_block(blockIdx.x, nb_padded);
+  if (lb >= A.ntiles) return;                           // the whole block leaves
+  const int TI = static_cast<int>(lb % A.tiles_x), TJ = static_cast<int>(lb / A.tiles_x);
+  const int i0 = TI * TS, j0 = TJ * TS;
+  const int w = min(TS, A.nx - i0), hgt = min(TS, A.ny - j0);
+  const int t = threadIdx.x;
+  const int ci = t & (TS - 1), cj = t / TS;
+  const bool own = ci < w && cj < hgt;
+  // the halo ring: rows j = -1 and j = hgt (i = -1 .. w), columns i = -1 and i = w (j = 0 .. hgt - 1)
+  const int nh = 2 * (w + 2) + 2 * hgt;
+  const bool halo = t < nh;
+  int hi = 0, hj = 0;
+  if (halo) {
+    if (t < w + 2) {
+      hi = t - 1;
+      hj = -1;
+    } else if (t < 2 * (w + 2)) {
+      hi = t - (w + 2) - 1;
+      hj = hgt;
+    } else if (t < 2 * (w + 2) + hgt) {
+      hi = -1;
+      hj = t - 2 * (w + 2);
+    } else {
+      hi = w;
+      hj = t - 2 * (w + 2) - hgt;
+    }
+  }
+  auto cell_of = [&](int li, int lj) -> int64_t {
+    int gi = i0 + li, gj = j0 + lj;
+    gi = gi < 0 ? gi + A.nx : (gi >= A.nx ? gi - A.nx : gi);
+    gj = gj < 0 ? gj + A.ny : (gj >= A.ny ? gj - A.ny : gj);
+    return static_cast<int64_t>(gi) + static_cast<int64_t>(A.nx) * gj;
+  };
+
+  float cf[N1][N1];
+  float Wo[4], WHo[4][NK];
+  if (own) cell_corners<P>(u + cell_of(ci, cj) * NLOC, A, ms, cf, Wo, WHo);
+  float Wh[4], WHh[4][NK];
+  if (halo) {
+    float cfh[N1][N1];
+    cell_corners<P>(u + cell_of(hi, hj) * NLOC, A, ms, cfh, Wh, WHh);
+  }
+  // vertex sums, one corner per round: corner l of cell (i, j) is vertex
+  // (i + dx_l, j + dy_l); each vertex of [0, w] x [0, hgt] has exactly one
+  // corner-l cell among the tile and its halo, and the corner-0 round covers
+  // them all
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const int dx = (l == 1 || l == 2) ? 1 : 0, dy = (l >= 2) ? 1 : 0;
+    if (own) {
+      const int v = (ci + dx) + NVX * (cj + dy);
+#pragma unroll
+      for (int k = 0; k < NK; ++k) V[k][v] = (l == 0) ? WHo[l][k] : V[k][v] + WHo[l][k];
+      V[NK][v] = (l == 0) ? Wo[l] : V[NK][v] + Wo[l];
+    }
+    if (halo) {
+      const int vx = hi + dx, vy = hj + dy;
+      if (vx >= 0 && vx <= w && vy >= 0 && vy <= hgt) {
+        const int v = vx + NVX * vy;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) V[k][v] = (l == 0) ? WHh[l][k] : V[k][v] + WHh[l][k];
+        V[NK][v] = (l == 0) ? Wh[l] : V[NK][v] + Wh[l];
+      }
+    }
+    __syncthreads();
+  }
+  if (!own) return;
+
+  // ---- cell stage -------------------------------------------------------------
+  const float n2 = seminorm_sq<P, false>(cf, A.Sk);
+  float Dc[4][NK];       // candidates' reference derivatives at the cell centre
+  float bl2[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const int dx = (l == 1 || l == 2) ? 1 : 0, dy = (l >= 2) ? 1 : 0;
+    const int v = (ci + dx) + NVX * (cj + dy);
+    const float inv = frcp(V[NK][v]);
+    float cv[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) cv[k] = V[k][v] * inv;
+    // Taylor expansion about the corner (sx, sy) = (2 dx - 1, 2 dy - 1), moved
+    // to the centre: D^m p(0) = sum_{k >= m} c[k] (-sx)^{kx-mx} (-sy)^{ky-my} / ((kx-mx)! (ky-my)!)
+#pragma unroll
+    for (int m = 0; m < NK; ++m) {
+      float s = cv[m];
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int ex = ks.x[k] - ks.x[m], ey = ks.y[k] - ks.y[m];
+        if (k == m || ex < 0 || ey < 0) continue;
+        // (-sx)^ex: sx = -1 (dx = 0) gives +1, sx = +1 (dx = 1) gives (-1)^ex
+        const double sgn = (((ex & 1) && dx) ? -1.0 : 1.0) * (((ey & 1) && dy) ? -1.0 : 1.0);
+        s = fmaf(static_cast<float>(sgn / (cfact(ex) * cfact(ey))), cv[k], s);
+      }
+      Dc[l][m] = s;
+    }
+    float C[N1][N1];
+    taylor_to_legendre<P>(Dc[l], C);
+    bl2[l] = seminorm_sq<P, true>(C, A.Sk);
+  }
+  // weights of eq. finalweno: linear weights 1 - 4 lin_w (cell), lin_w (vertices)
+  float w0, wv[4];
+  if (ms.fast_exp) {
+    const float d0 = ms.eps_c + fsqrt(n2);
+    w0 = (1.0f - 4.0f * ms.lin_w) * frcp(d0 * d0);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const float dv = ms.eps_c + fsqrt(bl2[l]);
+      wv[l] = ms.lin_w * frcp(dv * dv);
+    }
+  } else {
+    w0 = (1.0f - 4.0f * ms.lin_w) * powf(ms.eps_c + powf(sqrtf(n2), ms.q_beta), -ms.r);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) wv[l] = ms.lin_w * powf(ms.eps_c + powf(sqrtf(bl2[l]), ms.q_beta), -ms.r);
+  }
+  const float wq = (wv[0] + wv[1]) + (wv[2] + wv[3]);
+  const float oinv = frcp(w0 + wq);
+  // u_h - u* = sum_{l >= 1} omega_l (u_h - p_l) = (1 - omega_0) u_h - sum omega_l p_l
+  float db[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    float s = wv[0] * Dc[0][k];
+    s = fmaf(wv[1], Dc[1][k], s);
+    s = fmaf(wv[2], Dc[2][k], s);
+    s = fmaf(wv[3], Dc[3][k], s);
+    db[k] = s * oinv;
+  }
+  float Cb[N1][N1];
+  taylor_to_legendre<P>(db, Cb);
+  const float wrest = wq * oinv;
+  float dl[N1][N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) dl[m][n] = fmaf(wrest, cf[m][n], -Cb[m][n]);
+  const float d2 = seminorm_sq<P, false>(dl, A.Sk);
+  float g = 1.0f;
+  if (n2 > 0.0f) {
+    const float mr = fminf(1.0f, fsqrt(d2 / n2));     // n2 may be subnormal: IEEE division
+    g = 1.0f - (ms.fast_exp ? mr : powf(mr, ms.q_sensor));
+  }
+  gamma[cell_of(ci, cj)] = g;
+}
+
+// ---------------------------------------------------------------------------
+// launcher
+// ---------------------------------------------------------------------------
+SensorTileArgs make_sensor_tile_args(const cvw_mesh* m) {
+  SensorTileArgs A{};
+  const int p = m->degree, n1 = p + 1;
+  // T[m][i] = (2m + 1) / 2 w_i P_m(xi_i): Legendre coefficients from Gauss-node values
+  for (int i = 0; i < n1; ++i) {
+    const double x = m->tens.xi[i];
+    double P0 = 1.0, P1 = x;
+    for (int k = 0; k < n1; ++k) {
+      double Pk;
+      if (k == 0) Pk = 1.0;
+      else if (k == 1) Pk = x;
+      else {
+        Pk = ((2.0 * k - 1.0) * x * P1 - (k - 1.0) * P0) / k;
+        P0 = P1;
+        P1 = Pk;
+      }
+      A.T[k][i] = 0.5 * (2.0 * k + 1.0) * m->tens.wd[i] * Pk;
+    }
+  }
+  const double hx = m->hx, hy = m->hy, he = m->he;
+  auto pw = [](double x, int n) { double r = 1.0; for (int i = 0; i < n; ++i) r *= x; return r; };
+  int t = 0;
+  for (int n = 1; n <= p; ++n)
+    for (int j = 0; j <= n; ++j) {
+      const int kx = n - j, ky = j;
+      A.sk[t] = static_cast<float>(pw(he, n) * pw(2.0 / hx, kx) * pw(2.0 / hy, ky));
+      A.Sk[t] = static_cast<float>(0.25 * hx * hy * pw(he, 2 * n - 2) * pw(2.0 / hx, 2 * kx) * pw(2.0 / hy, 2 * ky));
+      ++t;
+    }
+  A.nx = static_cast<int>(m->grid_nx);
+  A.ny = static_cast<int>(m->grid_ny);
+  A.tiles_x = (A.nx + TS - 1) / TS;
+  A.tiles_y = (A.ny + TS - 1) / TS;
+  A.ntiles = static_cast<int64_t>(A.tiles_x) * A.tiles_y;
+  return A;
+}
+
+cvw_status dgquad_sensor_tile(const cvw_mesh* m, const cvw_params* prm, const float* u, float* gamma, hipStream_t s) {
+  if (m->grid_nx <= 0) { set_error("fused sensor pass needs a structured periodic grid"); return CVW_EUNSUPPORTED; }
+  const MethodScalars ms = make_scalars(prm);
+  const SensorTileArgs A = make_sensor_tile_args(m);
+  const int64_t nb = (A.ntiles + 7) / 8 * 8;
+  switch (m->degree) {
+    case 1: hipLaunchKernelGGL(dgq_sensor_tile_kernel<1>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, gamma, A, ms, nb); break;
+    case 2: hipLaunchKernelGGL(dgq_sensor_tile_kernel<2>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, gamma, A, ms, nb); break;
+    case 3: hipLaunchKernelGGL(dgq_sensor_tile_kernel<3>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, gamma, A, ms, nb); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+}  // namespace cvw

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -846,6 +847,21 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     }
   }
 
+  // ---- structured periodic DG grid (cells e = i + nx j, four cells at every
+  // vertex): the fused sensor pass reads the neighbours by index arithmetic
+  if (d->cell == CVW_QUAD && d->space == CVW_DG && m->uniform && m->closed) {
+    const int64_t nx = m->h_nbr[2];                 // north neighbour of cell 0
+    bool ok = nx >= 3 && E % nx == 0 && E / nx >= 3;
+    const int64_t ny = ok ? E / nx : 0;
+    for (int64_t e = 0; e < E && ok; ++e) {
+      const int64_t i = e % nx, j = e / nx;
+      ok = m->h_nbr[e * 4 + 0] == i + nx * ((j + ny - 1) % ny) && m->h_nbr[e * 4 + 1] == (i + 1) % nx + nx * j &&
+           m->h_nbr[e * 4 + 2] == i + nx * ((j + 1) % ny) && m->h_nbr[e * 4 + 3] == (i + nx - 1) % nx + nx * j;
+    }
+    for (int64_t v = 0; v < Nv && ok; ++v) ok = m->h_vtx_ptr[v + 1] - m->h_vtx_ptr[v] == 4;
+    if (ok) { m->grid_nx = nx; m->grid_ny = ny; }
+  }
+
   // ---- CG numbering, DOF patches, per-cell geometry ----
   std::vector<int32_t> dptr, dent;
   std::vector<float> geo, hef;
@@ -961,6 +977,7 @@ cvw_status cvw_mesh_get_info(const cvw_mesh* m, cvw_mesh_info* info) {
   info->n_cells = m->E; info->n_vertices = m->Nv; info->n_dof = m->ndof; info->nnz_vertex = m->nnz;
   info->n_loc = m->nloc; info->n_k = m->nk; info->n_q = m->nq; info->v_e = m->ve; info->n_faces = m->nf;
   info->uniform = m->uniform; info->hx = m->hx; info->hy = m->hy;
+  info->grid_nx = m->grid_nx; info->grid_ny = m->grid_ny;
   return CVW_OK;
 }
 
@@ -1068,8 +1085,9 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (op == 3) return 256 + align256(static_cast<size_t>(m->E) * 4);   // positivity: count, cell list
   const size_t es = prm->dtype == CVW_F64 ? 8 : 4;
   size_t b = 256 + TOT_SCRATCH + align256(static_cast<size_t>(m->nk) * m->Nv * es) + cg_extra(m, prm, es);
-  if (prm->sensor == CVW_SENSOR_LEARNED)
-    b += align256(static_cast<size_t>(m->E) * MLP_IN * 2) + align256(static_cast<size_t>(m->E) * 4);
+  if (prm->sensor == CVW_SENSOR_LEARNED) b += align256(static_cast<size_t>(m->E) * MLP_IN * 2);
+  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG))
+    b += align256(static_cast<size_t>(m->E) * 4);
   if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
   if (op == 2)    // limiter: vertex candidates of every variable, gamma, the selected cells and their count
     b += align256(static_cast<size_t>(n_var_of(prm->flux)) * m->nk * m->Nv * es) +
@@ -1142,8 +1160,8 @@ struct WS {
   void* x, *r, *z, *p, *Ap;        // PCG vectors (CG)
   double* part;                    // PCG block partials, followed by its 8 scalars
   double* S;
-  uint16_t* feat;                  // learned sensor: features [E][48] and gamma [E]
-  float* glearn;
+  uint16_t* feat;                  // learned sensor: features [E][48]
+  float* gam;                      // DG quadrilaterals / learned sensor: gamma_e of the stage [E]
   void* st1;
   void* st2;
 };
@@ -1180,7 +1198,9 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
   if (prm->sensor == CVW_SENSOR_LEARNED) {
     w.feat = reinterpret_cast<uint16_t*>(p);
     p += align256(static_cast<size_t>(m->E) * MLP_IN * 2);
-    w.glearn = reinterpret_cast<float*>(p);
+  }
+  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG)) {
+    w.gam = reinterpret_cast<float*>(p);
     p += align256(static_cast<size_t>(m->E) * 4);
   }
   w.st1 = p;
@@ -1195,7 +1215,20 @@ static cvw_status learned_gamma(const cvw_mesh* m, const cvw_params* prm, const 
   cvw_status st = dgquad_features(m, static_cast<const float*>(u), static_cast<const float*>(cand), prm->sigma_ref,
                                   w.feat, s);
   if (st != CVW_OK) return st;
-  return mlp_infer(prm->mlp->dev(), w.feat, m->E, w.glearn, s);
+  return mlp_infer(prm->mlp->dev(), w.feat, m->E, w.gam, s);
+}
+
+// CVW_SENSOR_PATH=twopass in the environment keeps the two-pass plain sensor
+// (vertex candidates in the workspace, then the cell pass) on structured grids
+// too; both paths compute eq. gamma and are tested against the oracle
+static bool twopass_forced() {
+  const char* v = std::getenv("CVW_SENSOR_PATH");
+  return v && std::strcmp(v, "twopass") == 0;
+}
+// the fused sensor pass applies: plain sensor on a structured periodic DG quadrilateral grid
+static bool use_tile(const cvw_mesh* m, const cvw_params* prm) {
+  return m->cell == CVW_QUAD && m->space == CVW_DG && m->grid_nx > 0 && prm->sensor == CVW_SENSOR_PLAIN &&
+         !twopass_forced();
 }
 
 static cvw_status candidates_any(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand,
@@ -1223,6 +1256,14 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
   if (!u || !gamma) { set_error("null device pointer"); return CVW_EINVAL; }
   const WS w = carve(m, prm, ws);
   auto s = static_cast<hipStream_t>(stream);
+  if (use_tile(m, prm)) {
+    // fused pass; the shock-capturing weights, when asked for, from the cell pass with that gamma
+    st = dgquad_sensor_tile(m, prm, static_cast<const float*>(u), static_cast<float*>(gamma), s);
+    if (st != CVW_OK || !alpha) return st;
+    return dgquad_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
+                       static_cast<float*>(alpha), nullptr, w.status, 0.f, 0.f, 0.f, s,
+                       static_cast<const float*>(gamma));
+  }
   if (prm->sensor != CVW_SENSOR_FIXED) {
     st = candidates_any(m, prm, u, w.cand, s);
     if (st != CVW_OK) return st;
@@ -1239,7 +1280,7 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
                        static_cast<float*>(alpha), w.status, s);
   return dgquad_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
                      static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s,
-                     w.glearn);
+                     w.gam);
 }
 
 cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, void* u_out, double threshold,
@@ -1358,6 +1399,12 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
   if (u == R) { set_error("R must not alias u"); return CVW_EINVAL; }
   const WS w = carve(m, prm, ws);
   auto s = static_cast<hipStream_t>(stream);
+  if (use_tile(m, prm)) {
+    st = dgquad_sensor_tile(m, prm, static_cast<const float*>(u), w.gam, s);
+    if (st != CVW_OK) return st;
+    return dgquad_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
+                       static_cast<float*>(gamma_out), nullptr, nullptr, w.status, 0.f, 0.f, 0.f, s, w.gam);
+  }
   if (prm->sensor != CVW_SENSOR_FIXED) {
     st = candidates_any(m, prm, u, w.cand, s);
     if (st != CVW_OK) return st;
@@ -1375,7 +1422,7 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
                        static_cast<float*>(gamma_out), nullptr, w.status, s);
   return dgquad_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
                      static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
-                     0.f, s, w.glearn);
+                     0.f, s, w.gam);
 }
 
 }  // extern "C"
@@ -1420,13 +1467,20 @@ cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, cons
                     static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
                     static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s);
   if (m->cell == CVW_QUAD && m->space == CVW_DG) {
+    if (use_tile(m, prm)) {
+      const cvw_status st = dgquad_sensor_tile(m, prm, static_cast<const float*>(us), w.gam, s);
+      if (st != CVW_OK) return st;
+      return dgquad_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
+                         static_cast<float*>(uo), nullptr, nullptr, nullptr, w.status, static_cast<float>(dt),
+                         static_cast<float>(a0), static_cast<float>(b0), s, w.gam);
+    }
     if (prm->sensor == CVW_SENSOR_LEARNED) {
       const cvw_status st = learned_gamma(m, prm, us, cand, w, s);
       if (st != CVW_OK) return st;
     }
     return dgquad_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
                        static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
-                       static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s, w.glearn);
+                       static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s, w.gam);
   }
   if (prm->dtype == CVW_F64)
     return generic_stage<double>(m, prm, w, static_cast<const double*>(us), static_cast<const double*>(cand),
@@ -1445,11 +1499,29 @@ cvw_status cvw_rk_stage(const cvw_mesh* m, const cvw_params* prm, const void* u_
   cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
   if (st != CVW_OK) return st;
   if (!has_stage(m)) { set_error("no Runge-Kutta stage for this mesh (degree out of range)"); return CVW_EUNSUPPORTED; }
-  if (!u_stage || !cand || !u_out || (a0 != 0.0 && !u_n)) { set_error("null device pointer"); return CVW_EINVAL; }
+  if (!u_stage || (!cand && !use_tile(m, prm)) || !u_out || (a0 != 0.0 && !u_n)) {
+    set_error("null device pointer"); return CVW_EINVAL;
+  }
   if (u_out == u_stage || u_out == cand) { set_error("u_out must not alias u_stage or cand"); return CVW_EINVAL; }
   if (!std::isfinite(dt) || !std::isfinite(a0) || !std::isfinite(b0)) { set_error("non-finite stage coefficients"); return CVW_EINVAL; }
   const WS w = carve(m, prm, ws);
   return any_stage(m, prm, w, u_stage, cand, u_n, u_out, dt, a0, b0, static_cast<hipStream_t>(stream));
+}
+
+cvw_status cvw_rk_stage_gamma(const cvw_mesh* m, const cvw_params* prm, const void* u_stage, const void* gamma,
+                              const void* u_n, void* u_out, double dt, double a0, double b0, void* ws,
+                              size_t ws_bytes, void* stream) {
+  cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
+  if (st != CVW_OK) return st;
+  if (!(m->cell == CVW_QUAD && m->space == CVW_DG)) { set_error("a given gamma: DG quadrilaterals only"); return CVW_EUNSUPPORTED; }
+  if (!u_stage || !gamma || !u_out || (a0 != 0.0 && !u_n)) { set_error("null device pointer"); return CVW_EINVAL; }
+  if (u_out == u_stage || u_out == gamma) { set_error("u_out must not alias u_stage or gamma"); return CVW_EINVAL; }
+  if (!std::isfinite(dt) || !std::isfinite(a0) || !std::isfinite(b0)) { set_error("non-finite stage coefficients"); return CVW_EINVAL; }
+  const WS w = carve(m, prm, ws);
+  return dgquad_eval(m, prm, MODE_STAGE, static_cast<const float*>(u_stage), static_cast<const float*>(u_n),
+                     static_cast<float*>(u_out), nullptr, nullptr, nullptr, w.status, static_cast<float>(dt),
+                     static_cast<float>(a0), static_cast<float>(b0), static_cast<hipStream_t>(stream),
+                     static_cast<const float*>(gamma));
 }
 
 cvw_status cvw_step(const cvw_mesh* m, const cvw_params* prm, void* u, double dt, int n_steps, void* ws,
@@ -1469,7 +1541,7 @@ cvw_status cvw_step(const cvw_mesh* m, const cvw_params* prm, void* u, double dt
       {u, w.st1, 0.0, 1.0}, {w.st1, w.st2, 0.75, 0.25}, {w.st2, u, third, two3}};
   for (int n = 0; n < n_steps; ++n)
     for (const auto& sg : stages) {
-      if (prm->sensor != CVW_SENSOR_FIXED) {
+      if (prm->sensor != CVW_SENSOR_FIXED && !use_tile(m, prm)) {
         st = candidates_any(m, prm, sg.in, w.cand, s);
         if (st != CVW_OK) return st;
       }

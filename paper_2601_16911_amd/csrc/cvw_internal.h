@@ -234,6 +234,16 @@ inline CellGeo make_cell_geo(double hx, double hy, double he, int p) {
   return g;
 }
 
+// Arguments of the fused DG quadrilateral sensor pass (structured periodic
+// grid, cells numbered e = i + nx j; 16 x 16 cells per block)
+struct SensorTileArgs {
+  double T[MAXP + 1][MAXP + 1];   // T[m][i] = (2m + 1) / 2 w_i P_m(xi_i): Legendre coefficients from Gauss-node values
+  float sk[(MAXP + 1) * (MAXP + 2) / 2 - 1];   // h_e^{|k|} (2/hx)^kx (2/hy)^ky: reference -> scaled physical derivatives
+  float Sk[(MAXP + 1) * (MAXP + 2) / 2 - 1];   // (hx hy / 4) h_e^{2|k|-2} (2/hx)^{2kx} (2/hy)^{2ky}: eq. snorm weights
+  int nx, ny, tiles_x, tiles_y;
+  int64_t ntiles;
+};
+
 // Per-instance descriptor of a batch of independent DG quadrilateral meshes
 // (device memory, written by the host before a batch step).  The Runge-Kutta
 // stage s reads state in[s] and writes out[s]: u -> st1 -> st2 -> u.
@@ -264,6 +274,7 @@ struct cvw_mesh {
   int nloc = 0, nk = 0, nq = 0, ve = 0, nf = 0;
   int uniform = 0;
   int closed = 0;                    // DG: every face has a neighbour
+  int64_t grid_nx = 0, grid_ny = 0;  // DG quadrilaterals: structured periodic grid e = i + nx j (0: not)
   double hx = 0, hy = 0, he = 0;
   int device = 0;
   int eval_grid = 0;                 // DG quad cell pass: blocks per launch (0 = default)
@@ -322,6 +333,9 @@ cvw_status dgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const
 cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, float* out, float* cand,
                         const float* gamma, const LimitNodes& ln, double threshold, uint32_t* count,
                         int32_t* list, uint8_t* vflag, int32_t* vlist, hipStream_t s);
+// fused sensor pass of a structured periodic DG quadrilateral grid: gamma_e
+// of every cell from the sensor field (variable 0 of u) (cvw_dgsensor.hip)
+cvw_status dgquad_sensor_tile(const cvw_mesh* m, const cvw_params* prm, const float* u, float* gamma, hipStream_t s);
 // learned-sensor features of every cell, bfloat16 [E][48] (cvw_dgquad.hip)
 cvw_status dgquad_features(const cvw_mesh* m, const float* u, const float* cand, double sigma_ref, uint16_t* feat,
                            hipStream_t s);

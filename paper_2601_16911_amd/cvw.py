@@ -27,7 +27,7 @@ EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXP
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
            "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_limit", "cvw_positivity",
            "cvw_residual",
-           "cvw_rk_stage", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_mesh_plan",
+           "cvw_rk_stage", "cvw_rk_stage_gamma", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_mesh_plan",
            "cvw_mesh_build_in", "cvw_batch_build",
            "cvw_batch_destroy",
            "cvw_batch_workspace_bytes", "cvw_batch_step", "cvw_batch_set_grid", "cvw_batch_poll_status",
@@ -64,7 +64,7 @@ class MeshInfoC(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_vertices", C.c_int64), ("n_dof", C.c_int64),
                 ("nnz_vertex", C.c_int64), ("n_loc", C.c_int32), ("n_k", C.c_int32), ("n_q", C.c_int32),
                 ("v_e", C.c_int32), ("n_faces", C.c_int32), ("uniform", C.c_int32), ("hx", C.c_double),
-                ("hy", C.c_double)]
+                ("hy", C.c_double), ("grid_nx", C.c_int64), ("grid_ny", C.c_int64)]
 
 
 _lib = None
@@ -98,6 +98,8 @@ def load():
     lib.cvw_residual.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, sz, vp]
     lib.cvw_rk_stage.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                  vp, sz, vp]
+    lib.cvw_rk_stage_gamma.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, C.c_double, C.c_double,
+                                       C.c_double, vp, sz, vp]
     lib.cvw_step.argtypes = [vp, C.POINTER(ParamsC), vp, C.c_double, C.c_int, vp, sz, vp]
     lib.cvw_poll_status.argtypes = [vp, vp, sz, C.POINTER(C.c_uint32), vp]
     lib.cvw_totals.argtypes = [vp, C.POINTER(ParamsC), vp, C.POINTER(C.c_double), vp, sz, vp]
@@ -317,6 +319,14 @@ def rk_stage(mesh, prm, u_stage, cand, u_n, u_out, dt: float, a0: float, b0: flo
                                _fp(cand, prm, _cand_len(mesh), "cand"), _fp(u_n, prm, n, "u_n"),
                                _fp(u_out, prm, n, "u_out"), float(dt), float(a0), float(b0), _ptr(ws), ws.numel(),
                                _stream(stream)))
+
+
+def rk_stage_gamma(mesh, prm, u_stage, gamma, u_n, u_out, dt: float, a0: float, b0: float, ws, stream=None):
+    n = _state_len(mesh, prm)
+    _check(load().cvw_rk_stage_gamma(mesh.handle, C.byref(prm), _fp(u_stage, prm, n, "u_stage"),
+                                     _fp(gamma, prm, mesh.info["n_cells"], "gamma"), _fp(u_n, prm, n, "u_n"),
+                                     _fp(u_out, prm, n, "u_out"), float(dt), float(a0), float(b0), _ptr(ws),
+                                     ws.numel(), _stream(stream)))
 
 
 def step(mesh, prm, u, dt: float, n_steps: int, ws, stream=None):

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(cvw.SYMBOLS)
-    assert lib.cvw_abi_version() == 6
+    assert lib.cvw_abi_version() == 7
 
 
 def test_struct_layouts_match_header():
@@ -35,9 +35,10 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "cvw.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(cvw_params), sizeof(cvw_mesh_desc), sizeof(cvw_mesh_info),
-         offsetof(cvw_params, fixed_gamma), offsetof(cvw_mesh_desc, periodic), offsetof(cvw_mesh_info, hx),
-         offsetof(cvw_params, mlp), sizeof(cvw_batch_instance), offsetof(cvw_batch_instance, dt));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(cvw_params), sizeof(cvw_mesh_desc),
+         sizeof(cvw_mesh_info), offsetof(cvw_params, fixed_gamma), offsetof(cvw_mesh_desc, periodic),
+         offsetof(cvw_mesh_info, hx), offsetof(cvw_params, mlp), sizeof(cvw_batch_instance),
+         offsetof(cvw_batch_instance, dt), offsetof(cvw_mesh_info, grid_ny));
   return 0;
 }
 '''
@@ -50,7 +51,8 @@ int main(void) {
         got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     exp = [C.sizeof(cvw.ParamsC), C.sizeof(cvw.MeshDescC), C.sizeof(cvw.MeshInfoC),
            cvw.ParamsC.fixed_gamma.offset, cvw.MeshDescC.periodic.offset, cvw.MeshInfoC.hx.offset,
-           cvw.ParamsC.mlp.offset, C.sizeof(cvw.BatchInstanceC), cvw.BatchInstanceC.dt.offset]
+           cvw.ParamsC.mlp.offset, C.sizeof(cvw.BatchInstanceC), cvw.BatchInstanceC.dt.offset,
+           cvw.MeshInfoC.grid_ny.offset]
     assert got == exp
 
 
