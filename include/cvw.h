@@ -108,10 +108,13 @@ typedef struct {
   double c_gamma;            /* SC active only where gamma_e < c_gamma           */
   double lambda_global;      /* > 0: global wave-speed bound used for nu_e and LLF */
   int32_t sensor;            /* cvw_sensor_kind                                  */
-  int32_t pad0;
+  int32_t audit_every;       /* CVW_SENSOR_LEARNED, cvw_step: audit the network against the
+                                plain sensor at the start of every audit_every-th step (0: never) */
   double fixed_gamma;        /* gamma_e for CVW_SENSOR_FIXED                     */
   double sigma_ref;          /* CVW_SENSOR_LEARNED: reference scale of the features (> 0) */
   const struct cvw_mlp* mlp; /* CVW_SENSOR_LEARNED: the network (cvw_mlp_create)  */
+  double audit_tol;          /* CVW_SENSOR_LEARNED: an audit whose mean |gamma_learned - gamma_plain|
+                                exceeds it switches the run to the plain sensor (cvw_learned_audit) */
 } cvw_params;
 
 typedef struct {
@@ -280,7 +283,9 @@ cvw_status cvw_step(const cvw_mesh* mesh, const cvw_params* prm, void* u, double
 /* Synchronises `stream`, returns the device status bits in *flags and clears
  * them: bit 0 non-finite residual, bit 1 non-positive density or pressure,
  * bit 2 a CG mass solve (PCG) that ended its fixed iteration count above its
- * tolerance.
+ * tolerance, bit 3 the learned sensor handed cells to the plain sensor (their
+ * count is cleared too), bit 4 an audit switched the learned sensor off (the
+ * latch itself stays set for the workspace).
  * Returns CVW_ENUMERIC when any bit was set. */
 cvw_status cvw_poll_status(const cvw_mesh* mesh, void* ws, size_t ws_bytes, uint32_t* flags, void* stream);
 
@@ -317,6 +322,25 @@ void cvw_mlp_destroy(cvw_mlp* mlp);
  * set also resets the Adam state. */
 cvw_status cvw_mlp_get_params(const cvw_mlp* mlp, float* params);
 cvw_status cvw_mlp_set_params(cvw_mlp* mlp, const float* params);
+
+/* Validity box of the network's 48 features (host arrays, lo[i] <= hi[i];
+ * -inf / +inf after cvw_mlp_create): the learned sensor hands a cell whose
+ * features leave the box (or whose output is not finite) to the plain sensor.
+ * Callers set it from the training data, e.g. its range widened by a margin. */
+cvw_status cvw_mlp_set_range(cvw_mlp* mlp, const float* lo, const float* hi);
+
+/* Audit of the learned sensor (the plain sensor as its judge) on state u, on
+ * a structured periodic DG quadrilateral grid: gamma of the network (guarded)
+ * and of eq. gamma for every cell; out_host[0] = mean |gamma_learned -
+ * gamma_plain|, [1] = the largest, [2] = cells handed to the plain sensor
+ * since the last poll, [3] = 1 when the audit latch is set.  A mean above
+ * prm->audit_tol sets the latch in the workspace: from then on every learned
+ * evaluation with this workspace hands all cells to the plain sensor (the run
+ * is switched to plain); cvw_poll_status reports bit 4 once.  cvw_step runs
+ * the same audit (without the host copy) every prm->audit_every steps.
+ * Synchronises `stream`.  ws: cvw_workspace_bytes(mesh, prm, 0) or more. */
+cvw_status cvw_learned_audit(const cvw_mesh* mesh, const cvw_params* prm, const void* u, double* out_host,
+                             void* ws, size_t ws_bytes, void* stream);
 
 /* Features of every cell (DG quadrilaterals, float32): u the state (the first
  * variable is the sensor field), cand its vertex candidates, prm->sigma_ref

@@ -280,81 +280,13 @@ __device__ __forceinline__ void cell_corners(const float* __restrict__ ue, const
 
 }  // namespace
 
+// gamma_e of the own cell from its Legendre coefficients cf and the vertex
+// sums in V (cell stage of the reconstruction)
 template <int P>
-__global__ __launch_bounds__(256) void dgq_sensor_tile_kernel(const float* __restrict__ u, float* __restrict__ gamma,
-                                                              SensorTileArgs A, MethodScalars ms, int64_t nb_padded) {
-  constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
+__device__ __forceinline__ float cell_gamma(const float (&cf)[P + 1][P + 1], const float (&V)[KSet<P>::NK + 1][NVX * NVX],
+                                            int ci, int cj, const SensorTileArgs& A, const MethodScalars& ms) {
+  constexpr int N1 = P + 1, NK = KSet<P>::NK;
   constexpr KSet<P> ks = kset<P>;
-  __shared__ float V[NK + 1][NVX * NVX];   // per vertex: sum w D^k (k < NK), sum w (NK)
-  const int64_t lb = xcd_block(blockIdx.x, nb_padded);
-  if (lb >= A.ntiles) return;                           // the whole block leaves
-  const int TI = static_cast<int>(lb % A.tiles_x), TJ = static_cast<int>(lb / A.tiles_x);
-  const int i0 = TI * TS, j0 = TJ * TS;
-  const int w = min(TS, A.nx - i0), hgt = min(TS, A.ny - j0);
-  const int t = threadIdx.x;
-  const int ci = t & (TS - 1), cj = t / TS;
-  const bool own = ci < w && cj < hgt;
-  // the halo ring: rows j = -1 and j = hgt (i = -1 .. w), columns i = -1 and i = w (j = 0 .. hgt - 1)
-  const int nh = 2 * (w + 2) + 2 * hgt;
-  const bool halo = t < nh;
-  int hi = 0, hj = 0;
-  if (halo) {
-    if (t < w + 2) {
-      hi = t - 1;
-      hj = -1;
-    } else if (t < 2 * (w + 2)) {
-      hi = t - (w + 2) - 1;
-      hj = hgt;
-    } else if (t < 2 * (w + 2) + hgt) {
-      hi = -1;
-      hj = t - 2 * (w + 2);
-    } else {
-      hi = w;
-      hj = t - 2 * (w + 2) - hgt;
-    }
-  }
-  auto cell_of = [&](int li, int lj) -> int64_t {
-    int gi = i0 + li, gj = j0 + lj;
-    gi = gi < 0 ? gi + A.nx : (gi >= A.nx ? gi - A.nx : gi);
-    gj = gj < 0 ? gj + A.ny : (gj >= A.ny ? gj - A.ny : gj);
-    return static_cast<int64_t>(gi) + static_cast<int64_t>(A.nx) * gj;
-  };
-
-  float cf[N1][N1];
-  float Wo[4], WHo[4][NK];
-  if (own) cell_corners<P>(u + cell_of(ci, cj) * NLOC, A, ms, cf, Wo, WHo);
-  float Wh[4], WHh[4][NK];
-  if (halo) {
-    float cfh[N1][N1];
-    cell_corners<P>(u + cell_of(hi, hj) * NLOC, A, ms, cfh, Wh, WHh);
-  }
-  // vertex sums, one corner per round: corner l of cell (i, j) is vertex
-  // (i + dx_l, j + dy_l); each vertex of [0, w] x [0, hgt] has exactly one
-  // corner-l cell among the tile and its halo, and the corner-0 round covers
-  // them all
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    const int dx = (l == 1 || l == 2) ? 1 : 0, dy = (l >= 2) ? 1 : 0;
-    if (own) {
-      const int v = (ci + dx) + NVX * (cj + dy);
-#pragma unroll
-      for (int k = 0; k < NK; ++k) V[k][v] = (l == 0) ? WHo[l][k] : V[k][v] + WHo[l][k];
-      V[NK][v] = (l == 0) ? Wo[l] : V[NK][v] + Wo[l];
-    }
-    if (halo) {
-      const int vx = hi + dx, vy = hj + dy;
-      if (vx >= 0 && vx <= w && vy >= 0 && vy <= hgt) {
-        const int v = vx + NVX * vy;
-#pragma unroll
-        for (int k = 0; k < NK; ++k) V[k][v] = (l == 0) ? WHh[l][k] : V[k][v] + WHh[l][k];
-        V[NK][v] = (l == 0) ? Wh[l] : V[NK][v] + Wh[l];
-      }
-    }
-    __syncthreads();
-  }
-  if (!own) return;
-
-  // ---- cell stage -------------------------------------------------------------
   const float n2 = seminorm_sq<P, false>(cf, A.Sk);
   float Dc[4][NK];       // candidates' reference derivatives at the cell centre
   float bl2[4];
@@ -426,7 +358,155 @@ __global__ __launch_bounds__(256) void dgq_sensor_tile_kernel(const float* __res
     const float mr = fminf(1.0f, fsqrt(d2 / n2));     // n2 may be subnormal: IEEE division
     g = 1.0f - (ms.fast_exp ? mr : powf(mr, ms.q_sensor));
   }
-  gamma[cell_of(ci, cj)] = g;
+  return g;
+}
+
+// mode TILE_ALL: gamma of every cell.  TILE_FALLBACK: only the tiles whose
+// flag is set, and there only the cells whose gamma holds NaN (the learned
+// sensor's hand-over); the flag is cleared.  TILE_AUDIT: gamma is not written;
+// the block's sum and maximum of |gamma_plain - g_ref| go to part[2 lb + 0, 1].
+template <int P>
+__global__ __launch_bounds__(256) void dgq_sensor_tile_kernel(const float* __restrict__ u, float* __restrict__ gamma,
+                                                              SensorTileArgs A, MethodScalars ms, int64_t nb_padded,
+                                                              int mode, uint8_t* __restrict__ tile_flag,
+                                                              const float* __restrict__ g_ref,
+                                                              double* __restrict__ part) {
+  constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
+  constexpr KSet<P> ks = kset<P>;
+  __shared__ float V[NK + 1][NVX * NVX];   // per vertex: sum w D^k (k < NK), sum w (NK)
+  const int64_t lb = xcd_block(blockIdx.x, nb_padded);
+  if (lb >= A.ntiles) return;                           // the whole block leaves
+  if (mode == TILE_FALLBACK && tile_flag[lb] == 0) return;
+  const int TI = static_cast<int>(lb % A.tiles_x), TJ = static_cast<int>(lb / A.tiles_x);
+  const int i0 = TI * TS, j0 = TJ * TS;
+  const int w = min(TS, A.nx - i0), hgt = min(TS, A.ny - j0);
+  const int t = threadIdx.x;
+  const int ci = t & (TS - 1), cj = t / TS;
+  const bool own = ci < w && cj < hgt;
+  // the halo ring: rows j = -1 and j = hgt (i = -1 .. w), columns i = -1 and i = w (j = 0 .. hgt - 1)
+  const int nh = 2 * (w + 2) + 2 * hgt;
+  const bool halo = t < nh;
+  int hi = 0, hj = 0;
+  if (halo) {
+    if (t < w + 2) {
+      hi = t - 1;
+      hj = -1;
+    } else if (t < 2 * (w + 2)) {
+      hi = t - (w + 2) - 1;
+      hj = hgt;
+    } else if (t < 2 * (w + 2) + hgt) {
+      hi = -1;
+      hj = t - 2 * (w + 2);
+    } else {
+      hi = w;
+      hj = t - 2 * (w + 2) - hgt;
+    }
+  }
+  auto cell_of = [&](int li, int lj) -> int64_t {
+    int gi = i0 + li, gj = j0 + lj;
+    gi = gi < 0 ? gi + A.nx : (gi >= A.nx ? gi - A.nx : gi);
+    gj = gj < 0 ? gj + A.ny : (gj >= A.ny ? gj - A.ny : gj);
+    return static_cast<int64_t>(gi) + static_cast<int64_t>(A.nx) * gj;
+  };
+
+  float cf[N1][N1];
+  float Wo[4], WHo[4][NK];
+  if (own) cell_corners<P>(u + cell_of(ci, cj) * NLOC, A, ms, cf, Wo, WHo);
+  float Wh[4], WHh[4][NK];
+  if (halo) {
+    float cfh[N1][N1];
+    cell_corners<P>(u + cell_of(hi, hj) * NLOC, A, ms, cfh, Wh, WHh);
+  }
+  // vertex sums, one corner per round: corner l of cell (i, j) is vertex
+  // (i + dx_l, j + dy_l); each vertex of [0, w] x [0, hgt] has exactly one
+  // corner-l cell among the tile and its halo, and the corner-0 round covers
+  // them all
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const int dx = (l == 1 || l == 2) ? 1 : 0, dy = (l >= 2) ? 1 : 0;
+    if (own) {
+      const int v = (ci + dx) + NVX * (cj + dy);
+#pragma unroll
+      for (int k = 0; k < NK; ++k) V[k][v] = (l == 0) ? WHo[l][k] : V[k][v] + WHo[l][k];
+      V[NK][v] = (l == 0) ? Wo[l] : V[NK][v] + Wo[l];
+    }
+    if (halo) {
+      const int vx = hi + dx, vy = hj + dy;
+      if (vx >= 0 && vx <= w && vy >= 0 && vy <= hgt) {
+        const int v = vx + NVX * vy;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) V[k][v] = (l == 0) ? WHh[l][k] : V[k][v] + WHh[l][k];
+        V[NK][v] = (l == 0) ? Wh[l] : V[NK][v] + Wh[l];
+      }
+    }
+    __syncthreads();
+  }
+  if (mode == TILE_FALLBACK && t == 0) tile_flag[lb] = 0;   // every thread has read it
+  float g = 1.0f;
+  if (own) g = cell_gamma<P>(cf, V, ci, cj, A, ms);
+  if (mode == TILE_AUDIT) {
+    // fixed-order block sums (float64) of the deviation from g_ref
+    __shared__ double rs[256], rm[256];
+    double d = 0.0;
+    if (own) {
+      const float r = g_ref[cell_of(ci, cj)];
+      d = isnan(r) ? 1.0 : fabs(static_cast<double>(g) - static_cast<double>(r));
+    }
+    rs[t] = d;
+    rm[t] = d;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (t < h) {
+        rs[t] += rs[t + h];
+        rm[t] = fmax(rm[t], rm[t + h]);
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      part[2 * lb] = rs[0];
+      part[2 * lb + 1] = rm[0];
+    }
+    return;
+  }
+  if (!own) return;
+  const int64_t e = cell_of(ci, cj);
+  if (mode == TILE_FALLBACK && !isnan(gamma[e])) return;
+  gamma[e] = g;
+}
+
+// Sum of the audit's block partials in a fixed order: out[0] = mean, out[1] =
+// largest |gamma_plain - gamma_learned| over the E cells; a mean above tol sets
+// the latch (status word 2: the plain sensor takes every cell from then on)
+// and the ST_LEARNED_OFF bit.
+__global__ __launch_bounds__(256) void audit_finalize_kernel(const double* __restrict__ part, int64_t ntiles,
+                                                             int64_t E, double tol, uint32_t* __restrict__ status,
+                                                             double* __restrict__ out) {
+  __shared__ double rs[256], rm[256];
+  const int t = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = t; i < ntiles; i += 256) {
+    a += part[2 * i];
+    b = fmax(b, part[2 * i + 1]);
+  }
+  rs[t] = a;
+  rm[t] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      rs[t] += rs[t + h];
+      rm[t] = fmax(rm[t], rm[t + h]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double mean = rs[0] / static_cast<double>(E);
+    out[0] = mean;
+    out[1] = rm[0];
+    if (!(mean <= tol)) {
+      status[2] = 1u;
+      atomicOr(status, ST_LEARNED_OFF);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -469,17 +549,32 @@ SensorTileArgs make_sensor_tile_args(const cvw_mesh* m) {
   return A;
 }
 
-cvw_status dgquad_sensor_tile(const cvw_mesh* m, const cvw_params* prm, const float* u, float* gamma, hipStream_t s) {
+cvw_status dgquad_sensor_tile(const cvw_mesh* m, const cvw_params* prm, const float* u, float* gamma, hipStream_t s,
+                              int mode, uint8_t* tile_flag, const float* g_ref, double* part) {
   if (m->grid_nx <= 0) { set_error("fused sensor pass needs a structured periodic grid"); return CVW_EUNSUPPORTED; }
-  const MethodScalars ms = make_scalars(prm);
+  // the plain sensor's constants whatever the params' kind (the fallback and
+  // the audit of the learned sensor run it too)
+  MethodScalars ms = make_scalars(prm);
+  ms.sensor_kind = CVW_SENSOR_PLAIN;
   const SensorTileArgs A = make_sensor_tile_args(m);
   const int64_t nb = (A.ntiles + 7) / 8 * 8;
+  const dim3 g(static_cast<unsigned>(nb)), b(256);
   switch (m->degree) {
-    case 1: hipLaunchKernelGGL(dgq_sensor_tile_kernel<1>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, gamma, A, ms, nb); break;
-    case 2: hipLaunchKernelGGL(dgq_sensor_tile_kernel<2>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, gamma, A, ms, nb); break;
-    case 3: hipLaunchKernelGGL(dgq_sensor_tile_kernel<3>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, gamma, A, ms, nb); break;
+    case 1: hipLaunchKernelGGL(dgq_sensor_tile_kernel<1>, g, b, 0, s, u, gamma, A, ms, nb, mode, tile_flag, g_ref, part); break;
+    case 2: hipLaunchKernelGGL(dgq_sensor_tile_kernel<2>, g, b, 0, s, u, gamma, A, ms, nb, mode, tile_flag, g_ref, part); break;
+    case 3: hipLaunchKernelGGL(dgq_sensor_tile_kernel<3>, g, b, 0, s, u, gamma, A, ms, nb, mode, tile_flag, g_ref, part); break;
     default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
   }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+int64_t sensor_tiles(const cvw_mesh* m) {
+  return m->grid_nx <= 0 ? 0 : ((m->grid_nx + TS - 1) / TS) * ((m->grid_ny + TS - 1) / TS);
+}
+
+cvw_status dgquad_audit_finalize(const cvw_mesh* m, const double* part, double tol, uint32_t* status, double* out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(audit_finalize_kernel, dim3(1), dim3(256), 0, s, part, sensor_tiles(m), m->E, tol, status, out);
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 

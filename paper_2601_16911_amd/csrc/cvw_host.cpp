@@ -1049,6 +1049,8 @@ struct cvw_mlp {
   uint16_t* W2t = nullptr;
   uint16_t* W2r = nullptr;
   uint16_t* w3 = nullptr;
+  float* lo = nullptr;               // validity box of the features [48] each (-inf / +inf at creation)
+  float* hi = nullptr;
   cvw::MlpDev dev() const { return {W1t, W2t, W2r, w3, b1, b2, b3}; }
   cvw::MlpDevMut mut() const { return {W1t, W2t, W2r, w3, b1, b2, b3}; }
 };
@@ -1057,6 +1059,20 @@ static size_t state_elems(const cvw_mesh* m, int nv) {
   return static_cast<size_t>(nv) * (m->space == CVW_DG ? static_cast<size_t>(m->E) * m->nloc : static_cast<size_t>(m->ndof));
 }
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// CVW_SENSOR_PATH=twopass in the environment keeps the two-pass plain sensor
+// (vertex candidates in the workspace, then the cell pass) on structured grids
+// too; both paths compute eq. gamma and are tested against the oracle
+static bool twopass_forced() {
+  const char* v = std::getenv("CVW_SENSOR_PATH");
+  return v && std::strcmp(v, "twopass") == 0;
+}
+// the fused sensor pass applies: plain sensor on a structured periodic DG quadrilateral grid
+static bool use_tile(const cvw_mesh* m, const cvw_params* prm) {
+  return m->cell == CVW_QUAD && m->space == CVW_DG && m->grid_nx > 0 && prm->sensor == CVW_SENSOR_PLAIN &&
+         !twopass_forced();
+}
+
 
 // true when the mesh has a time-stepping path (stages and steps)
 static bool has_stage(const cvw_mesh* m) {
@@ -1084,8 +1100,12 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (!m || !prm) return 0;
   if (op == 3) return 256 + align256(static_cast<size_t>(m->E) * 4);   // positivity: count, cell list
   const size_t es = prm->dtype == CVW_F64 ? 8 : 4;
-  size_t b = 256 + TOT_SCRATCH + align256(static_cast<size_t>(m->nk) * m->Nv * es) + cg_extra(m, prm, es);
-  if (prm->sensor == CVW_SENSOR_LEARNED) b += align256(static_cast<size_t>(m->E) * MLP_IN * 2);
+  // the vertex candidates go through the workspace except in the fused sensor pass
+  const size_t cand = use_tile(m, prm) ? 0 : align256(static_cast<size_t>(m->nk) * m->Nv * es);
+  size_t b = 256 + TOT_SCRATCH + cand + cg_extra(m, prm, es);
+  if (prm->sensor == CVW_SENSOR_LEARNED)      // features, tile flags, audit partials and results
+    b += align256(static_cast<size_t>(m->E) * MLP_IN * 2) + align256(static_cast<size_t>(sensor_tiles(m))) +
+         align256(static_cast<size_t>(sensor_tiles(m)) * 16) + 256;
   if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG))
     b += align256(static_cast<size_t>(m->E) * 4);
   if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
@@ -1110,6 +1130,11 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
       set_error("learned sensor needs a network and sigma_ref > 0"); return CVW_EINVAL;
     }
     if (prm->mlp->device != m->device) { set_error("network and mesh on different devices"); return CVW_EINVAL; }
+    if (m->grid_nx <= 0) {
+      set_error("learned sensor: structured periodic grids (its plain fallback is the fused pass)");
+      return CVW_EUNSUPPORTED;
+    }
+    if (prm->audit_every < 0 || !(prm->audit_tol >= 0)) { set_error("bad audit parameters"); return CVW_EINVAL; }
   } else if (prm->sensor != CVW_SENSOR_PLAIN && prm->sensor != CVW_SENSOR_FIXED) {
     set_error("unknown sensor kind"); return CVW_EINVAL;
   }
@@ -1160,7 +1185,10 @@ struct WS {
   void* x, *r, *z, *p, *Ap;        // PCG vectors (CG)
   double* part;                    // PCG block partials, followed by its 8 scalars
   double* S;
-  uint16_t* feat;                  // learned sensor: features [E][48]
+  uint16_t* feat;                  // learned sensor: features [E][48], tile flags, audit partials and results
+  uint8_t* tflag;
+  double* apart;
+  double* aout;
   float* gam;                      // DG quadrilaterals / learned sensor: gamma_e of the stage [E]
   void* st1;
   void* st2;
@@ -1173,8 +1201,10 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
   p += 256;
   w.tot = reinterpret_cast<double*>(p);
   p += TOT_SCRATCH;
-  w.cand = p;
-  p += align256(static_cast<size_t>(m->nk) * m->Nv * es);
+  if (!use_tile(m, prm)) {
+    w.cand = p;
+    p += align256(static_cast<size_t>(m->nk) * m->Nv * es);
+  }
   if (m->space == CVW_CG) {
     w.pg = p;
     p += align256(2 * static_cast<size_t>(m->ndof) * es);
@@ -1198,6 +1228,12 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
   if (prm->sensor == CVW_SENSOR_LEARNED) {
     w.feat = reinterpret_cast<uint16_t*>(p);
     p += align256(static_cast<size_t>(m->E) * MLP_IN * 2);
+    w.tflag = reinterpret_cast<uint8_t*>(p);
+    p += align256(static_cast<size_t>(sensor_tiles(m)));
+    w.apart = reinterpret_cast<double*>(p);
+    p += align256(static_cast<size_t>(sensor_tiles(m)) * 16);
+    w.aout = reinterpret_cast<double*>(p);
+    p += 256;
   }
   if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG)) {
     w.gam = reinterpret_cast<float*>(p);
@@ -1209,26 +1245,30 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
   return w;
 }
 
-// learned sensor: features of u, then the network; gamma in the workspace
+// learned sensor: features of u, then the network, guarded: cells outside
+// the network's feature box, with a non-finite output, or all cells once an
+// audit has set the latch, are handed to the plain sensor (the fused pass
+// over the flagged tiles only); gamma in the workspace
 static cvw_status learned_gamma(const cvw_mesh* m, const cvw_params* prm, const void* u, const void* cand, const WS& w,
                                 hipStream_t s) {
   cvw_status st = dgquad_features(m, static_cast<const float*>(u), static_cast<const float*>(cand), prm->sigma_ref,
                                   w.feat, s);
   if (st != CVW_OK) return st;
-  return mlp_infer(prm->mlp->dev(), w.feat, m->E, w.gam, s);
+  const MlpGuard G{prm->mlp->lo, prm->mlp->hi, w.status, w.tflag, m->grid_nx, (m->grid_nx + 15) / 16};
+  if ((st = mlp_infer(prm->mlp->dev(), w.feat, m->E, w.gam, s, &G)) != CVW_OK) return st;
+  return dgquad_sensor_tile(m, prm, static_cast<const float*>(u), w.gam, s, TILE_FALLBACK, w.tflag);
 }
 
-// CVW_SENSOR_PATH=twopass in the environment keeps the two-pass plain sensor
-// (vertex candidates in the workspace, then the cell pass) on structured grids
-// too; both paths compute eq. gamma and are tested against the oracle
-static bool twopass_forced() {
-  const char* v = std::getenv("CVW_SENSOR_PATH");
-  return v && std::strcmp(v, "twopass") == 0;
-}
-// the fused sensor pass applies: plain sensor on a structured periodic DG quadrilateral grid
-static bool use_tile(const cvw_mesh* m, const cvw_params* prm) {
-  return m->cell == CVW_QUAD && m->space == CVW_DG && m->grid_nx > 0 && prm->sensor == CVW_SENSOR_PLAIN &&
-         !twopass_forced();
+// audit of the learned sensor on state u: learned gamma (guarded) in the
+// workspace, the plain gamma of every cell against it; the mean deviation
+// above prm->audit_tol sets the latch (device side, no host synchronisation)
+static cvw_status learned_audit(const cvw_mesh* m, const cvw_params* prm, const void* u, const WS& w, hipStream_t s) {
+  cvw_status st = dgquad_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(w.cand), s);
+  if (st != CVW_OK || (st = learned_gamma(m, prm, u, w.cand, w, s)) != CVW_OK) return st;
+  if ((st = dgquad_sensor_tile(m, prm, static_cast<const float*>(u), nullptr, s, TILE_AUDIT, nullptr, w.gam,
+                               w.apart)) != CVW_OK)
+    return st;
+  return dgquad_audit_finalize(m, w.apart, prm->audit_tol, w.status, w.aout, s);
 }
 
 static cvw_status candidates_any(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand,
@@ -1539,7 +1579,10 @@ cvw_status cvw_step(const cvw_mesh* m, const cvw_params* prm, void* u, double dt
   const double two3 = f64 ? 2.0 / 3.0 : static_cast<double>(2.0f / 3.0f);
   const struct { const void* in; void* out; double a0, b0; } stages[3] = {
       {u, w.st1, 0.0, 1.0}, {w.st1, w.st2, 0.75, 0.25}, {w.st2, u, third, two3}};
-  for (int n = 0; n < n_steps; ++n)
+  for (int n = 0; n < n_steps; ++n) {
+    if (prm->sensor == CVW_SENSOR_LEARNED && prm->audit_every > 0 && n % prm->audit_every == 0 &&
+        (st = learned_audit(m, prm, u, w, s)) != CVW_OK)
+      return st;
     for (const auto& sg : stages) {
       if (prm->sensor != CVW_SENSOR_FIXED && !use_tile(m, prm)) {
         st = candidates_any(m, prm, sg.in, w.cand, s);
@@ -1548,6 +1591,28 @@ cvw_status cvw_step(const cvw_mesh* m, const cvw_params* prm, void* u, double dt
       st = any_stage(m, prm, w, sg.in, w.cand, u, sg.out, dt, sg.a0, sg.b0, s);
       if (st != CVW_OK) return st;
     }
+  }
+  return CVW_OK;
+}
+
+cvw_status cvw_learned_audit(const cvw_mesh* m, const cvw_params* prm, const void* u, double* out_host, void* ws,
+                             size_t ws_bytes, void* stream) {
+  cvw_status st = check_common(m, prm, ws_bytes, 0, ws);
+  if (st != CVW_OK) return st;
+  if (prm->sensor != CVW_SENSOR_LEARNED) { set_error("audit: the learned sensor's parameters"); return CVW_EINVAL; }
+  if (!u || !out_host) { set_error("null argument"); return CVW_EINVAL; }
+  const WS w = carve(m, prm, ws);
+  auto s = static_cast<hipStream_t>(stream);
+  if ((st = learned_audit(m, prm, u, w, s)) != CVW_OK) return st;
+  double r[2];
+  uint32_t words[3];
+  CVW_HIP(hipMemcpyAsync(r, w.aout, sizeof(r), hipMemcpyDeviceToHost, s));
+  CVW_HIP(hipMemcpyAsync(words, w.status, sizeof(words), hipMemcpyDeviceToHost, s));
+  CVW_HIP(hipStreamSynchronize(s));
+  out_host[0] = r[0];
+  out_host[1] = r[1];
+  out_host[2] = static_cast<double>(words[WS_FALLBACK_COUNT]);
+  out_host[3] = words[WS_LEARNED_OFF] ? 1.0 : 0.0;
   return CVW_OK;
 }
 
@@ -1557,8 +1622,8 @@ cvw_status cvw_poll_status(const cvw_mesh* m, void* ws, size_t ws_bytes, uint32_
   uint32_t h = 0;
   CVW_HIP(hipMemcpyAsync(&h, ws, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   CVW_HIP(hipStreamSynchronize(s));
-  const uint32_t zero = 0;
-  CVW_HIP(hipMemcpyAsync(ws, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  const uint32_t zero[2] = {0, 0};             // the status bits and the hand-over count; the latch stays
+  CVW_HIP(hipMemcpyAsync(ws, zero, sizeof(zero), hipMemcpyHostToDevice, s));
   CVW_HIP(hipStreamSynchronize(s));
   *flags = h;
   return h ? CVW_ENUMERIC : CVW_OK;
@@ -1862,7 +1927,7 @@ cvw_status cvw_mlp_create(const float* params, cvw_mlp** out) {
   auto* m = new cvw_mlp();
   (void)hipGetDevice(&m->device);
   const size_t nf = 3 * static_cast<size_t>(MLP_NPARAM) + 2 * MLP_HID + 1;
-  const size_t bytes = align256(nf * 4) + align256(MLP_BF16 * 2);
+  const size_t bytes = align256(nf * 4) + align256(MLP_BF16 * 2) + align256(2 * MLP_IN * 4);
   if (hipMalloc(&m->mem, bytes) != hipSuccess) { delete m; set_error("hipMalloc failed"); return CVW_ENOMEM; }
   float* f = static_cast<float*>(m->mem);
   m->master = f;
@@ -1876,7 +1941,15 @@ cvw_status cvw_mlp_create(const float* params, cvw_mlp** out) {
   m->W2t = m->W1t + MLP_IN * MLP_HID;
   m->W2r = m->W2t + MLP_HID * MLP_HID;
   m->w3 = m->W2r + MLP_HID * MLP_HID;
+  m->lo = reinterpret_cast<float*>(static_cast<char*>(m->mem) + align256(nf * 4) + align256(MLP_BF16 * 2));
+  m->hi = m->lo + MLP_IN;
+  std::vector<float> box(2 * MLP_IN);
+  for (int i = 0; i < MLP_IN; ++i) {
+    box[i] = -INFINITY;
+    box[MLP_IN + i] = INFINITY;
+  }
   if (hipMemset(m->mem, 0, bytes) != hipSuccess ||
+      hipMemcpy(m->lo, box.data(), box.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->master, params, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       mlp_refresh(m, nullptr) != CVW_OK || hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(m->mem);
@@ -1911,6 +1984,17 @@ cvw_status cvw_mlp_set_params(cvw_mlp* mlp, const float* params) {
   const cvw_status st = mlp_refresh(mlp, nullptr);
   if (st != CVW_OK) return st;
   CVW_HIP(hipDeviceSynchronize());
+  return CVW_OK;
+}
+
+cvw_status cvw_mlp_set_range(cvw_mlp* mlp, const float* lo, const float* hi) {
+  if (!mlp || !lo || !hi) { set_error("null argument"); return CVW_EINVAL; }
+  for (int i = 0; i < MLP_IN; ++i)
+    if (std::isnan(lo[i]) || std::isnan(hi[i]) || lo[i] > hi[i]) { set_error("bad feature range"); return CVW_EINVAL; }
+  if (hipMemcpy(mlp->lo, lo, MLP_IN * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(mlp->hi, hi, MLP_IN * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("range upload failed"); return CVW_EDEVICE;
+  }
   return CVW_OK;
 }
 

@@ -12,7 +12,14 @@
 namespace cvw {
 
 // status bits of the workspace status word
-enum : uint32_t { ST_NONFINITE = 1u, ST_NONPOSITIVE = 2u, ST_PCG_STALL = 4u };
+enum : uint32_t { ST_NONFINITE = 1u, ST_NONPOSITIVE = 2u, ST_PCG_STALL = 4u, ST_LEARNED_FALLBACK = 8u,
+                  ST_LEARNED_OFF = 16u };
+// the first 256 bytes of a workspace: word 0 the status bits, word 1 the
+// cells the learned sensor handed to the plain one since the last poll, word 2
+// the audit latch (nonzero: the plain sensor takes every cell)
+enum { WS_STATUS = 0, WS_FALLBACK_COUNT = 1, WS_LEARNED_OFF = 2 };
+// modes of the fused sensor pass
+enum : int { TILE_ALL = 0, TILE_FALLBACK = 1, TILE_AUDIT = 2 };
 
 // operation modes of the evaluation kernels
 enum Mode : int { MODE_SENSOR = 0, MODE_RESIDUAL = 1, MODE_STAGE = 2 };
@@ -163,6 +170,18 @@ struct MlpDev {
   const float* b1;
   const float* b2;
   const float* b3;
+};
+// Guard of the learned sensor's inference (lo null: no guard): the
+// network's validity box of the 48 features, the workspace status words (the
+// hand-over count and the audit latch among them), per-tile flags of the
+// structured grid (nx cells per row, tiles_x 16 x 16 tiles per tile row)
+struct MlpGuard {
+  const float* lo;
+  const float* hi;
+  uint32_t* status;        // workspace words: status bits, hand-over count, audit latch
+  uint8_t* tile_flag;
+  int64_t nx;
+  int64_t tiles_x;
 };
 struct MlpDevMut {
   uint16_t* W1t;
@@ -335,7 +354,14 @@ cvw_status dgquad_limit(const cvw_mesh* m, const cvw_params* prm, const float* u
                         int32_t* list, uint8_t* vflag, int32_t* vlist, hipStream_t s);
 // fused sensor pass of a structured periodic DG quadrilateral grid: gamma_e
 // of every cell from the sensor field (variable 0 of u) (cvw_dgsensor.hip)
-cvw_status dgquad_sensor_tile(const cvw_mesh* m, const cvw_params* prm, const float* u, float* gamma, hipStream_t s);
+cvw_status dgquad_sensor_tile(const cvw_mesh* m, const cvw_params* prm, const float* u, float* gamma, hipStream_t s,
+                              int mode = TILE_ALL, uint8_t* tile_flag = nullptr, const float* g_ref = nullptr,
+                              double* part = nullptr);
+int64_t sensor_tiles(const cvw_mesh* m);   // 16 x 16 tiles of the fused pass (0: no structured grid)
+// audit of the learned sensor: the block partials of the TILE_AUDIT pass in a
+// fixed order; out (device, 2 doubles) = mean and largest deviation
+cvw_status dgquad_audit_finalize(const cvw_mesh* m, const double* part, double tol, uint32_t* status, double* out,
+                                 hipStream_t s);
 // learned-sensor features of every cell, bfloat16 [E][48] (cvw_dgquad.hip)
 cvw_status dgquad_features(const cvw_mesh* m, const float* u, const float* cand, double sigma_ref, uint16_t* feat,
                            hipStream_t s);
@@ -357,7 +383,8 @@ cvw_status batch_vertex_pass(int P, const BatchInst* inst, const int2* items, in
 cvw_status batch_eval_pass(int P, int flux, const BatchInst* inst, const int2* items, int n_items,
                            const TensorTables* tabs, const LaneRec* lanes, int stage, int grid, hipStream_t s);
 // learned-sensor network (cvw_mlp.hip)
-cvw_status mlp_infer(const MlpDev& W, const uint16_t* feat, int64_t n, float* gamma, hipStream_t s);
+cvw_status mlp_infer(const MlpDev& W, const uint16_t* feat, int64_t n, float* gamma, hipStream_t s,
+                     const MlpGuard* guard = nullptr);
 cvw_status mlp_train(const MlpDev& W, const uint16_t* feat, const float* target, const int32_t* idx, int batch,
                      float* part, hipStream_t s);
 cvw_status mlp_update(const float* part, int nblk, float* master, float* m1, float* m2, float lr, double beta1,

@@ -87,9 +87,14 @@ __device__ __forceinline__ float gelu_prime(float x) {
 // ---------------------------------------------------------------------------
 // inference: 256 threads (4 waves), each wave one 32-cell tile per iteration
 // ---------------------------------------------------------------------------
+// With a guard G (learned sensor on a mesh): a cell whose features leave the
+// network's validity box [lo, hi] (NaN included) or whose output is not
+// finite, or every cell once the audit latch is set, gets gamma = NaN, its
+// tile flag and a count: the plain sensor takes those cells over.
 __global__ __launch_bounds__(256) void mlp_infer_kernel(const uint16_t* __restrict__ feat, int64_t n, MlpDev W,
-                                                        float* __restrict__ gamma) {
+                                                        float* __restrict__ gamma, MlpGuard G) {
   __shared__ float sb1[MLP_HID], sb2[MLP_HID], sw3[MLP_HID];
+  __shared__ float slo[MLP_IN], shi[MLP_IN];
   // the weight operands of every lane, fragment-major (14 fragments x 64 lanes):
   // read per tile from LDS rather than held in registers
   __shared__ u32x4 sA[14][64];
@@ -98,6 +103,12 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const uint16_t* __restri
     sb2[t] = W.b2[t];
     sw3[t] = bf16_value(W.w3[t]);
   }
+  const bool guard = G.lo != nullptr;
+  for (int t = threadIdx.x; t < MLP_IN; t += blockDim.x) {
+    slo[t] = guard ? G.lo[t] : 0.0f;
+    shi[t] = guard ? G.hi[t] : 0.0f;
+  }
+  const bool off = guard && G.status[WS_LEARNED_OFF] != 0u;
   for (int i = threadIdx.x; i < 14 * 64; i += blockDim.x) {
     const int f = i >> 6, l = i & 63, cl = l & 31, gl = l >> 5;
     bf16x8 a;
@@ -123,6 +134,21 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const uint16_t* __restri
     bf16x8 B1[3];
 #pragma unroll
     for (int kb = 0; kb < 3; ++kb) B1[kb] = ok ? load8(feat + cell * MLP_IN + 16 * kb + 8 * g) : zero8();
+    // the lane's 24 features against the validity box (lane group g holds k = 16 kb + 8 g + i)
+    bool outside = false;
+    if (guard) {
+#pragma unroll
+      for (int kb = 0; kb < 3; ++kb) {
+        const u32x4 w = __builtin_bit_cast(u32x4, B1[kb]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const uint16_t h = static_cast<uint16_t>((w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu);
+          const float x = bf16_value(h);
+          const int k = 16 * kb + 8 * g + i;
+          outside = outside || !(x >= slo[k] && x <= shi[k]);
+        }
+      }
+    }
     f32x16 C1[2];
 #pragma unroll
     for (int ht = 0; ht < 2; ++ht) {
@@ -159,7 +185,22 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const uint16_t* __restri
       }
     }
     z += __shfl_xor(z, 32);
-    if (g == 0 && ok) gamma[cell] = 1.0f / (1.0f + expf(-(z + b3)));
+    float gv = 1.0f / (1.0f + expf(-(z + b3)));
+    if (guard) {
+      const bool other = __shfl_xor(static_cast<int>(outside), 32) != 0;
+      const bool bad = ok && (off || outside || other || !isfinite(gv));
+      if (bad) gv = __builtin_nanf("");
+      if (bad && g == 0) {
+        const int64_t i = cell % G.nx, j = cell / G.nx;
+        G.tile_flag[(i / 16) + G.tiles_x * (j / 16)] = 1;
+      }
+      const unsigned long long m = __ballot(bad && g == 0);
+      if (m && (threadIdx.x & 63) == __builtin_ctzll(m)) {
+        atomicAdd(G.status + WS_FALLBACK_COUNT, static_cast<uint32_t>(__popcll(m)));
+        atomicOr(G.status + WS_STATUS, ST_LEARNED_FALLBACK);
+      }
+    }
+    if (g == 0 && ok) gamma[cell] = gv;
   }
 }
 
@@ -400,11 +441,13 @@ __global__ __launch_bounds__(256) void mlp_update_kernel(const float* __restrict
 }
 
 // ---------------------------------------------------------------------------
-cvw_status mlp_infer(const MlpDev& W, const uint16_t* feat, int64_t n, float* gamma, hipStream_t s) {
+cvw_status mlp_infer(const MlpDev& W, const uint16_t* feat, int64_t n, float* gamma, hipStream_t s,
+                     const MlpGuard* guard) {
   if (n <= 0) return CVW_OK;
   const int64_t tiles = (n + 31) / 32;
   const unsigned grid = static_cast<unsigned>(std::min<int64_t>((tiles + 3) / 4, 4096));
-  hipLaunchKernelGGL(mlp_infer_kernel, dim3(grid), dim3(256), 0, s, feat, n, W, gamma);
+  const MlpGuard G = guard ? *guard : MlpGuard{};
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3(grid), dim3(256), 0, s, feat, n, W, gamma, G);
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 

@@ -31,7 +31,8 @@ SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_dest
            "cvw_mesh_build_in", "cvw_batch_build",
            "cvw_batch_destroy",
            "cvw_batch_workspace_bytes", "cvw_batch_step", "cvw_batch_set_grid", "cvw_batch_poll_status",
-           "cvw_mlp_create", "cvw_mlp_destroy", "cvw_mlp_get_params", "cvw_mlp_set_params", "cvw_mlp_features",
+           "cvw_mlp_create", "cvw_mlp_destroy", "cvw_mlp_get_params", "cvw_mlp_set_params", "cvw_mlp_set_range",
+           "cvw_learned_audit", "cvw_mlp_features",
            "cvw_mlp_infer", "cvw_mlp_train_workspace_bytes", "cvw_mlp_train_step"]
 
 
@@ -52,8 +53,8 @@ class ParamsC(C.Structure):
                 ("eps_vertex", C.c_double), ("eps_cell", C.c_double), ("r", C.c_int32), ("sc_on", C.c_int32),
                 ("q_sensor", C.c_double), ("q_beta", C.c_double), ("lin_w_vertex", C.c_double),
                 ("c_gamma", C.c_double), ("lambda_global", C.c_double), ("sensor", C.c_int32),
-                ("pad0", C.c_int32), ("fixed_gamma", C.c_double), ("sigma_ref", C.c_double),
-                ("mlp", C.c_void_p)]
+                ("audit_every", C.c_int32), ("fixed_gamma", C.c_double), ("sigma_ref", C.c_double),
+                ("mlp", C.c_void_p), ("audit_tol", C.c_double)]
 
 
 class BatchInstanceC(C.Structure):
@@ -117,6 +118,8 @@ def load():
     lib.cvw_mlp_destroy.restype = None
     lib.cvw_mlp_get_params.argtypes = [vp, fp]
     lib.cvw_mlp_set_params.argtypes = [vp, fp]
+    lib.cvw_mlp_set_range.argtypes = [vp, fp, fp]
+    lib.cvw_learned_audit.argtypes = [vp, C.POINTER(ParamsC), vp, C.POINTER(C.c_double), vp, sz, vp]
     lib.cvw_mlp_features.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp]
     lib.cvw_mlp_infer.argtypes = [vp, vp, C.c_int64, vp, vp]
     lib.cvw_mlp_train_workspace_bytes.argtypes = [C.c_int]
@@ -136,11 +139,15 @@ def _check(status):
         raise CvwError(status, load().cvw_last_error().decode())
 
 
-def make_params(prm, dtype: int = F32, mlp=None, sigma_ref: float = 1.0) -> ParamsC:
+def make_params(prm, dtype: int = F32, mlp=None, sigma_ref: float = 1.0, audit_every: int = 0,
+                audit_tol: float = 0.05) -> ParamsC:
     """Marshal any object with the method-parameter attributes into the C struct
-    (mlp: a Mlp for the learned sensor, sigma_ref its reference scale)."""
+    (mlp: a Mlp for the learned sensor, sigma_ref its reference scale,
+    audit_every / audit_tol its audit against the plain sensor in cvw_step)."""
     p = ParamsC()
     p.sigma_ref = float(sigma_ref)
+    p.audit_every = int(audit_every)
+    p.audit_tol = float(audit_tol)
     p.mlp = mlp.handle if mlp is not None else None
     p.dtype = dtype
     p.flux = int(prm.flux)
@@ -329,6 +336,14 @@ def rk_stage_gamma(mesh, prm, u_stage, gamma, u_n, u_out, dt: float, a0: float, 
                                      ws.numel(), _stream(stream)))
 
 
+def learned_audit(mesh, prm, u, ws, stream=None) -> dict:
+    """Audit of the learned sensor against the plain one on state u (synchronises)."""
+    out = (C.c_double * 4)()
+    _check(load().cvw_learned_audit(mesh.handle, C.byref(prm), _fp(u, prm, _state_len(mesh, prm), "u"), out,
+                                    _ptr(ws), ws.numel(), _stream(stream)))
+    return {"mean_abs_dev": out[0], "max_abs_dev": out[1], "handed_over": int(out[2]), "switched_off": bool(out[3])}
+
+
 def step(mesh, prm, u, dt: float, n_steps: int, ws, stream=None):
     _check(load().cvw_step(mesh.handle, C.byref(prm), _fp(u, prm, _state_len(mesh, prm), "u"), float(dt),
                            int(n_steps), _ptr(ws), ws.numel(), _stream(stream)))
@@ -463,6 +478,15 @@ class Mlp:
     def set_params(self, params):
         v = np.ascontiguousarray(params, np.float32)
         _check(load().cvw_mlp_set_params(self._h, v.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def set_range(self, lo, hi):
+        """Validity box of the 48 features (outside it the plain sensor decides)."""
+        a = np.ascontiguousarray(lo, np.float32)
+        b = np.ascontiguousarray(hi, np.float32)
+        if a.size != MLP_IN or b.size != MLP_IN:
+            raise ValueError(f"{MLP_IN} bounds each expected")
+        _check(load().cvw_mlp_set_range(self._h, a.ctypes.data_as(C.POINTER(C.c_float)),
+                                        b.ctypes.data_as(C.POINTER(C.c_float))))
 
     def infer(self, feat, gamma, stream=None):
         import torch

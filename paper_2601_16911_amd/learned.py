@@ -99,9 +99,22 @@ def balanced_batches(targets: np.ndarray, batch: int, n_batches: int, seed: int,
     return out
 
 
+def feature_box(feats, margin: float = 0.25):
+    """Per-feature range of a feature set (int16 device tensor of bfloat16
+    bits), widened by `margin` times its span on either side: the network's
+    validity box (outside it the plain sensor decides)."""
+    torch = _torch()
+    v = ((feats.to(torch.int32) & 0xFFFF) << 16).view(torch.float32)
+    lo = v.min(0).values.cpu().numpy().astype(np.float64)
+    hi = v.max(0).values.cpu().numpy().astype(np.float64)
+    span = hi - lo
+    return (lo - margin * span).astype(np.float32), (hi + margin * span).astype(np.float32)
+
+
 def train(net, feats, targets, epochs: int, batch: int = 4096, lr: float = 1e-3, seed: int = 4):
-    """Adam on mean squared error against the plain sensor, balanced batches;
-    returns the loss-free step count (the losses are not read back)."""
+    """Adam on mean squared error against the plain sensor, balanced batches,
+    then the network's validity box from the training features; returns the
+    step count (the losses are not read back)."""
     torch = _torch()
     n = feats.shape[0]
     per_epoch = max(1, n // batch)
@@ -110,6 +123,7 @@ def train(net, feats, targets, epochs: int, batch: int = 4096, lr: float = 1e-3,
     ws = cvw.Mlp.train_workspace(batch)
     for b in range(idx.shape[0]):
         net.train_step(feats, targets, idx_d[b], lr, ws)
+    net.set_range(*feature_box(feats))
     torch.cuda.synchronize()
     return idx.shape[0]
 
