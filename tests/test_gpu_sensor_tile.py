@@ -84,10 +84,10 @@ def test_fused_and_twopass_agree(p, monkeypatch):
     U = f32(euler_state(sp, k=6.0))
     gm = cvw.Mesh(mesh, p, cvw.DG)
     cp = cvw.make_params(EULER)
-    ws = cvw.alloc_workspace(gm, cp, 0)
     Ud = _dev(U)
 
     def run():
+        ws = cvw.alloc_workspace(gm, cp, 0)        # the two-pass path needs room for the candidates
         g = torch.empty(sp.E, dtype=torch.float32, device="cuda")
         R = torch.empty_like(Ud)
         cvw.sensor(gm, cp, Ud, g, None, ws)
