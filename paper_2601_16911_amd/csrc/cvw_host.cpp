@@ -1245,6 +1245,12 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
   return w;
 }
 
+// the gamma the two-pass cell pass takes as given: the learned sensor's (in
+// the workspace), else none (the cell pass runs the plain sensor itself)
+static const float* learned_gamma_of(const cvw_params* prm, const WS& w) {
+  return prm->sensor == CVW_SENSOR_LEARNED ? w.gam : nullptr;
+}
+
 // learned sensor: features of u, then the network, guarded: cells outside
 // the network's feature box, with a non-finite output, or all cells once an
 // audit has set the latch, are handed to the plain sensor (the fused pass
@@ -1320,7 +1326,7 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
                        static_cast<float*>(alpha), w.status, s);
   return dgquad_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
                      static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s,
-                     w.gam);
+                     learned_gamma_of(prm, w));
 }
 
 cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, void* u_out, double threshold,
@@ -1462,7 +1468,7 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
                        static_cast<float*>(gamma_out), nullptr, w.status, s);
   return dgquad_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
                      static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
-                     0.f, s, w.gam);
+                     0.f, s, learned_gamma_of(prm, w));
 }
 
 }  // extern "C"
@@ -1520,7 +1526,8 @@ cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, cons
     }
     return dgquad_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
                        static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
-                       static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s, w.gam);
+                       static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s,
+                       learned_gamma_of(prm, w));
   }
   if (prm->dtype == CVW_F64)
     return generic_stage<double>(m, prm, w, static_cast<const double*>(us), static_cast<const double*>(cand),
