@@ -1388,10 +1388,14 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
   // the limiter, where they are needed; every candidate is taken from the
   // state before the reconstruction writes, so u_out may be u)
   if ((st = dgquad_candidates(m, prm, uf, cand, s)) != CVW_OK) return st;
-  // sensor values of the sensor field (variable 0)
-  if ((st = dgquad_eval(m, prm, MODE_SENSOR, uf, nullptr, nullptr, gam, nullptr, cand, w.status, 0.f, 0.f, 0.f, s)) !=
-      CVW_OK)
+  // sensor values of the sensor field (variable 0): the fused pass where it
+  // applies (the values of cvw_sensor), else the cell pass on the candidates
+  if (use_tile(m, prm)) {
+    if ((st = dgquad_sensor_tile(m, prm, uf, gam, s)) != CVW_OK) return st;
+  } else if ((st = dgquad_eval(m, prm, MODE_SENSOR, uf, nullptr, nullptr, gam, nullptr, cand, w.status, 0.f, 0.f,
+                               0.f, s)) != CVW_OK) {
     return st;
+  }
   LimitNodes ln{};
   std::vector<double> x, wq;
   gauss_rule(m->degree + 1, x, wq);
