@@ -62,11 +62,11 @@ def gauss_nodes_2d(p: int):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources of the fused DG cell kernel; HBM counter figures are
-    valid only for the kernel they were taken on."""
+    """Hash of the sources of the DG quadrilateral sensor and cell kernels;
+    counter figures are valid only for the kernels they were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("cvw_dgquad.hip", "cvw_device.h", "cvw_internal.h", "cvw_dgq_common.h"):
+    for f in ("cvw_dgquad.hip", "cvw_dgsensor.hip", "cvw_device.h", "cvw_internal.h", "cvw_dgq_common.h"):
         with open(os.path.join(ROOT, "paper_2601_16911_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

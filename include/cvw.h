@@ -246,6 +246,19 @@ cvw_status cvw_positivity(const cvw_mesh* mesh, const cvw_params* prm, const voi
 cvw_status cvw_residual(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* R,
                         void* gamma_out, void* ws, size_t ws_bytes, void* stream);
 
+/* cvw_residual without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  The workspace is a fixed 16 MiB (16777216 bytes)
+ * array of the library on each device it runs on, held until the process
+ * ends; the call allocates nothing.  Meshes and operations whose workspace
+ * (cvw_workspace_bytes(mesh, prm, 0)) exceeds it are refused with CVW_EINVAL
+ * (e.g. the fused path up to about 4.19 M cells).  The current device must be
+ * the mesh's.  Every call on a device shares its array: calls that overlap
+ * on one device race.  The status words are cleared at the start of every
+ * call and not reported. */
+cvw_status cvw_residual_noalloc(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* R,
+                                void* gamma_out, void* stream);
+
 /* One stage of the SSP Runge-Kutta method in Shu-Osher form (Sec. 5), given
  * the vertex candidates `cand` of u_stage (from cvw_vertex_candidates; not
  * read, and may be NULL, on a structured periodic DG quadrilateral grid with

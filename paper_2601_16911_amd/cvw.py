@@ -27,7 +27,7 @@ EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXP
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
            "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_limit", "cvw_positivity",
            "cvw_residual",
-           "cvw_rk_stage", "cvw_rk_stage_gamma", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_mesh_plan",
+           "cvw_rk_stage", "cvw_rk_stage_gamma", "cvw_residual_noalloc", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_mesh_plan",
            "cvw_mesh_build_in", "cvw_batch_build",
            "cvw_batch_destroy",
            "cvw_batch_workspace_bytes", "cvw_batch_step", "cvw_batch_set_grid", "cvw_batch_poll_status",
@@ -101,6 +101,7 @@ def load():
                                  vp, sz, vp]
     lib.cvw_rk_stage_gamma.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp, C.c_double, C.c_double,
                                        C.c_double, vp, sz, vp]
+    lib.cvw_residual_noalloc.argtypes = [vp, C.POINTER(ParamsC), vp, vp, vp, vp]
     lib.cvw_step.argtypes = [vp, C.POINTER(ParamsC), vp, C.c_double, C.c_int, vp, sz, vp]
     lib.cvw_poll_status.argtypes = [vp, vp, sz, C.POINTER(C.c_uint32), vp]
     lib.cvw_totals.argtypes = [vp, C.POINTER(ParamsC), vp, C.POINTER(C.c_double), vp, sz, vp]
@@ -326,6 +327,13 @@ def rk_stage(mesh, prm, u_stage, cand, u_n, u_out, dt: float, a0: float, b0: flo
                                _fp(cand, prm, _cand_len(mesh), "cand"), _fp(u_n, prm, n, "u_n"),
                                _fp(u_out, prm, n, "u_out"), float(dt), float(a0), float(b0), _ptr(ws), ws.numel(),
                                _stream(stream)))
+
+
+def residual_noalloc(mesh, prm, u, R, gamma_out=None, stream=None):
+    """cvw_residual with the library's per-device scratch array as workspace."""
+    n = _state_len(mesh, prm)
+    _check(load().cvw_residual_noalloc(mesh.handle, C.byref(prm), _fp(u, prm, n, "u"), _fp(R, prm, n, "R"),
+                                       _fp(gamma_out, prm, mesh.info["n_cells"], "gamma_out"), _stream(stream)))
 
 
 def rk_stage_gamma(mesh, prm, u_stage, gamma, u_n, u_out, dt: float, a0: float, b0: float, ws, stream=None):
