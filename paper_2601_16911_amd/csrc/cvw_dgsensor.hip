@@ -32,7 +32,9 @@ namespace cvw {
 
 namespace {
 
-constexpr double cfact(int n) { return n <= 1 ? 1.0 : n * cfact(n - 1); }
+// n! for n <= 7 (a table, so that device code never calls a function for it)
+constexpr double FACT[8] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0};
+constexpr double cfact(int n) { return FACT[n]; }
 
 // Legendre tables of degree < N1
 template <int N1>
@@ -82,10 +84,12 @@ __device__ __forceinline__ float seminorm_sq(const float (&C)[P + 1][P + 1], con
   constexpr int N1 = P + 1;
   constexpr KSet<P> ks = kset<P>;
   constexpr Leg<N1> L = leg<N1>;
-  // X[kx][j][n] = sum_m D[kx][j][m] C[m][n]
-  float X[N1][N1][N1];
+  float total = 0.0f;
+  // one x-derivative order at a time: X[j][n] = sum_m D[kx][j][m] C[m][n],
+  // then every multi-index (kx, ky) of the set with that kx
 #pragma unroll
-  for (int kx = 0; kx < N1; ++kx)
+  for (int kx = 0; kx < N1; ++kx) {
+    float X[N1][N1];
 #pragma unroll
     for (int j = 0; j < N1; ++j)
 #pragma unroll
@@ -98,35 +102,36 @@ __device__ __forceinline__ float seminorm_sq(const float (&C)[P + 1][P + 1], con
           s = any ? fmaf(static_cast<float>(L.D[kx][j][m]), C[m][n], s) : static_cast<float>(L.D[kx][j][m]) * C[m][n];
           any = true;
         }
-        X[kx][j][n] = s;
+        X[j][n] = s;
       }
-  float total = 0.0f;
 #pragma unroll
-  for (int t = 0; t < KSet<P>::NK; ++t) {
-    const int kx = ks.x[t], ky = ks.y[t];
-    float acc = 0.0f;
+    for (int t = 0; t < KSet<P>::NK; ++t) {
+      if (ks.x[t] != kx) continue;
+      const int ky = ks.y[t];
+      float acc = 0.0f;
 #pragma unroll
-    for (int j = 0; j + kx < N1; ++j)
+      for (int j = 0; j + kx < N1; ++j)
 #pragma unroll
-      for (int l = 0; l + ky < N1; ++l) {
-        float v = 0.0f;
-        bool any = false;
+        for (int l = 0; l + ky < N1; ++l) {
+          float v = 0.0f;
+          bool any = false;
 #pragma unroll
-        for (int n = 0; n < N1; ++n) {
-          if (L.D[ky][l][n] == 0.0) continue;
-          if (TOT) {   // skip products known to be zero
-            bool nz = false;
+          for (int n = 0; n < N1; ++n) {
+            if (L.D[ky][l][n] == 0.0) continue;
+            if (TOT) {   // skip products known to be zero
+              bool nz = false;
 #pragma unroll
-            for (int m = 0; m < N1; ++m) nz = nz || (L.D[kx][j][m] != 0.0 && m + n <= P);
-            if (!nz) continue;
+              for (int m = 0; m < N1; ++m) nz = nz || (L.D[kx][j][m] != 0.0 && m + n <= P);
+              if (!nz) continue;
+            }
+            v = any ? fmaf(static_cast<float>(L.D[ky][l][n]), X[j][n], v)
+                    : static_cast<float>(L.D[ky][l][n]) * X[j][n];
+            any = true;
           }
-          v = any ? fmaf(static_cast<float>(L.D[ky][l][n]), X[kx][j][n], v)
-                  : static_cast<float>(L.D[ky][l][n]) * X[kx][j][n];
-          any = true;
+          if (any) acc = fmaf(static_cast<float>(L.Nr[j] * L.Nr[l]) * v, v, acc);
         }
-        if (any) acc = fmaf(static_cast<float>(L.Nr[j] * L.Nr[l]) * v, v, acc);
-      }
-    total = fmaf(Sk[t], acc, total);
+      total = fmaf(Sk[t], acc, total);
+    }
   }
   return total;
 }
@@ -223,10 +228,13 @@ __device__ __forceinline__ void cell_corners(const float* __restrict__ ue, const
       cf[m][n] = static_cast<float>(s);
     }
   cf[0][0] = 0.0f;
-  // x stage at xi = +-1: g[kx][n] = sum_m c[m][n] P_m^{(kx)}(+-1) = Ev +- Od
-  double gp[N1][N1], gm[N1][N1];
+  // corner values, one x-derivative order kx at a time: at xi = +-1,
+  // g[n] = sum_m c[m][n] P_m^{(kx)}(+-1) = Ev +- Od; then at eta = +-1 every
+  // multi-index (kx, ky) of the set the same way
+  float H[4][NK];
 #pragma unroll
-  for (int kx = 0; kx < N1; ++kx)
+  for (int kx = 0; kx < N1; ++kx) {
+    double gp[N1], gm[N1];
 #pragma unroll
     for (int n = 0; n < N1; ++n) {
       double ev = 0.0, od = 0.0;
@@ -235,26 +243,26 @@ __device__ __forceinline__ void cell_corners(const float* __restrict__ ue, const
         if (((m - kx) & 1) == 0) ev = fma(L.E[kx][m], c[m][n], ev);
         else od = fma(L.E[kx][m], c[m][n], od);
       }
-      gp[kx][n] = ev + od;
-      gm[kx][n] = ev - od;
+      gp[n] = ev + od;
+      gm[n] = ev - od;
     }
-  // y stage at eta = +-1 for every multi-index, then the corner weights
-  float H[4][NK];
 #pragma unroll
-  for (int t = 0; t < NK; ++t) {
-    const int kx = ks.x[t], ky = ks.y[t];
+    for (int t = 0; t < NK; ++t) {
+      if (ks.x[t] != kx) continue;
+      const int ky = ks.y[t];
 #pragma unroll
-    for (int sxp = 0; sxp < 2; ++sxp) {
-      double ev = 0.0, od = 0.0;
+      for (int sxp = 0; sxp < 2; ++sxp) {
+        double ev = 0.0, od = 0.0;
 #pragma unroll
-      for (int n = ky; n < N1; ++n) {
-        const double g = sxp ? gp[kx][n] : gm[kx][n];
-        if (((n - ky) & 1) == 0) ev = fma(L.E[ky][n], g, ev);
-        else od = fma(L.E[ky][n], g, od);
+        for (int n = ky; n < N1; ++n) {
+          const double g = sxp ? gp[n] : gm[n];
+          if (((n - ky) & 1) == 0) ev = fma(L.E[ky][n], g, ev);
+          else od = fma(L.E[ky][n], g, od);
+        }
+        // corners: SW (-,-) 0, SE (+,-) 1, NE (+,+) 2, NW (-,+) 3
+        H[sxp ? 1 : 0][t] = static_cast<float>(ev - od);
+        H[sxp ? 2 : 3][t] = static_cast<float>(ev + od);
       }
-      // corners: SW (-,-) 0, SE (+,-) 1, NE (+,+) 2, NW (-,+) 3
-      H[sxp ? 1 : 0][t] = static_cast<float>(ev - od);
-      H[sxp ? 2 : 3][t] = static_cast<float>(ev + od);
     }
   }
 #pragma unroll
@@ -366,7 +374,7 @@ __device__ __forceinline__ float cell_gamma(const float (&cf)[P + 1][P + 1], con
 // sensor's hand-over); the flag is cleared.  TILE_AUDIT: gamma is not written;
 // the block's sum and maximum of |gamma_plain - g_ref| go to part[2 lb + 0, 1].
 template <int P>
-__global__ __launch_bounds__(256) void dgq_sensor_tile_kernel(const float* __restrict__ u, float* __restrict__ gamma,
+__global__ __launch_bounds__(256, 4) void dgq_sensor_tile_kernel(const float* __restrict__ u, float* __restrict__ gamma,
                                                               SensorTileArgs A, MethodScalars ms, int64_t nb_padded,
                                                               int mode, uint8_t* __restrict__ tile_flag,
                                                               const float* __restrict__ g_ref,
@@ -409,14 +417,31 @@ __global__ __launch_bounds__(256) void dgq_sensor_tile_kernel(const float* __res
     return static_cast<int64_t>(gi) + static_cast<int64_t>(A.nx) * gj;
   };
 
+  // the halo cell first: its corners that touch the tile's vertices (one or
+  // two) go to LDS, so that its registers are free again for the own cell
+  constexpr int NH = 2 * (TS + 2) + 2 * TS;
+  __shared__ float Hs[2][NK + 1][NH];
+  int hc0 = -1, hc1 = -1;
+  if (halo) {
+    float cfh[N1][N1], Wh[4], WHh[4][NK];
+    cell_corners<P>(u + cell_of(hi, hj) * NLOC, A, ms, cfh, Wh, WHh);
+    int c = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int vx = hi + ((l == 1 || l == 2) ? 1 : 0), vy = hj + ((l >= 2) ? 1 : 0);
+      if (vx >= 0 && vx <= w && vy >= 0 && vy <= hgt) {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) Hs[c][k][t] = WHh[l][k];
+        Hs[c][NK][t] = Wh[l];
+        if (c == 0) hc0 = l;
+        else hc1 = l;
+        ++c;
+      }
+    }
+  }
   float cf[N1][N1];
   float Wo[4], WHo[4][NK];
   if (own) cell_corners<P>(u + cell_of(ci, cj) * NLOC, A, ms, cf, Wo, WHo);
-  float Wh[4], WHh[4][NK];
-  if (halo) {
-    float cfh[N1][N1];
-    cell_corners<P>(u + cell_of(hi, hj) * NLOC, A, ms, cfh, Wh, WHh);
-  }
   // vertex sums, one corner per round: corner l of cell (i, j) is vertex
   // (i + dx_l, j + dy_l); each vertex of [0, w] x [0, hgt] has exactly one
   // corner-l cell among the tile and its halo, and the corner-0 round covers
@@ -430,14 +455,12 @@ __global__ __launch_bounds__(256) void dgq_sensor_tile_kernel(const float* __res
       for (int k = 0; k < NK; ++k) V[k][v] = (l == 0) ? WHo[l][k] : V[k][v] + WHo[l][k];
       V[NK][v] = (l == 0) ? Wo[l] : V[NK][v] + Wo[l];
     }
-    if (halo) {
-      const int vx = hi + dx, vy = hj + dy;
-      if (vx >= 0 && vx <= w && vy >= 0 && vy <= hgt) {
-        const int v = vx + NVX * vy;
+    if (hc0 == l || hc1 == l) {
+      const int sl = (hc0 == l) ? 0 : 1;
+      const int v = (hi + dx) + NVX * (hj + dy);
 #pragma unroll
-        for (int k = 0; k < NK; ++k) V[k][v] = (l == 0) ? WHh[l][k] : V[k][v] + WHh[l][k];
-        V[NK][v] = (l == 0) ? Wh[l] : V[NK][v] + Wh[l];
-      }
+      for (int k = 0; k < NK; ++k) V[k][v] = (l == 0) ? Hs[sl][k][t] : V[k][v] + Hs[sl][k][t];
+      V[NK][v] = (l == 0) ? Hs[sl][NK][t] : V[NK][v] + Hs[sl][NK][t];
     }
     __syncthreads();
   }
