@@ -72,31 +72,44 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per stage-mode launch of the fused cell kernel, from the
-    calibrated FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel
-    changed since they were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_dgq_eval_config4.json")
+def _measured(name: str, key: str):
+    """A counter figure from profiles/<name>.json, or None when the kernels
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        tr = json.load(f)
-    if tr.get("source_hash") != kernel_source_hash():
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
         return None
-    return tr.get("bytes_per_launch")
+    return d.get(key)
 
 
-def measured_valu():
-    """VALU wave instructions per stage-mode launch of the fused cell kernel,
-    from the SQ counter run, or None when the kernel changed since."""
-    path = os.path.join(ROOT, "profiles", "valu_dgq_eval_config4.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        v = json.load(f)
-    if v.get("source_hash") != kernel_source_hash():
-        return None
-    return v.get("valu_instr_per_launch")
+def measured_traffic(key: str = "bytes_per_launch"):
+    """HBM bytes per stage-mode launch of the cell pass (or, with
+    key="sensor_pass_bytes_per_launch", of the fused sensor pass) from the
+    calibrated FETCH_SIZE / WRITE_SIZE counter runs."""
+    return _measured("traffic_dgq_eval_config4", key)
+
+
+def measured_valu(key: str = "valu_instr_per_launch"):
+    """VALU wave instructions per stage-mode launch of the cell pass (or of
+    the sensor pass, key="sensor_pass_valu_instr_per_launch"), SQ counters."""
+    return _measured("valu_dgq_eval_config4", key)
+
+
+def host_cpu():
+    """(logical CPUs visible, CPU model) of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
 
 
 # VALU issue roof: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles of
@@ -126,29 +139,48 @@ def cell_pass_flops(p: int, nv: int) -> float:
     return float(grad + flux + speed + stab + test + traces + hll + lift + update)
 
 
-def cpu_baseline(target_seconds: float = 15.0):
-    """The float64 oracle timed on a bounded sample of the same workload: the
-    stabilised residual on periodic n x n sub-problems of the same recipe."""
+def _oracle_residuals(args):
+    """One worker of the CPU baseline: float64 oracle residuals of a periodic
+    n x n DG Q3 Euler sub-problem for about `seconds`; returns (DOFs, calls, s)."""
+    n, seconds = args
     import synth
     from oracle import build_space, nodal_interpolate, residual
     prm = synth.Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0))
-    n = 64
-    mesh = synth.quad_mesh(n, n)
-    sp = build_space(mesh, 3, 1, 4)
+    sp = build_space(synth.quad_mesh(n, n), 3, 1, 4)
     U = nodal_interpolate(sp, [(lambda c: (lambda x: synth.euler_state_config4(
         x[..., 0], x[..., 1], smooth_k=SMOOTH_K * n / 1024)[c]))(c) for c in range(4)])
-    dofs = U.size
     t0 = time.perf_counter()
-    reps = 0
+    calls = 0
     while True:
         residual(sp, U, prm)
-        reps += 1
-        if time.perf_counter() - t0 > target_seconds:
+        calls += 1
+        if time.perf_counter() - t0 > seconds:
             break
-    dt = time.perf_counter() - t0
-    return {"value": dofs * reps / dt, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} float64 oracle residual evaluations of a periodic {n}x{n} DG Q3 Euler "
-                      f"mesh ({dofs} DOFs) with the same state recipe, single process, {dt:.1f} s"}
+    return U.size, calls, time.perf_counter() - t0
+
+
+def cpu_baseline(seconds: float = 8.0, max_workers: int = 16):
+    """The float64 oracle timed on a bounded sample of the same workload (the
+    stabilised residual on periodic 64 x 64 DG Q3 Euler sub-problems of the
+    same recipe): one process on one core, then one process per core on all
+    the host cores the GPU's share allows (at most max_workers), each with one
+    BLAS thread; value = aggregate DOF-updates/s of the all-cores leg."""
+    import multiprocessing as mp
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    ncpu, model = host_cpu()
+    workers = max(1, min(ncpu, max_workers))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(1) as pool:
+        d1, c1, t1 = pool.map(_oracle_residuals, [(64, seconds)])[0]
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_residuals, [(64, seconds)] * workers)
+    agg = sum(d * c / t for d, c, t in res)
+    return {"value": agg, "unit": "DOF-updates/s", "cores": workers, "kind": "oracle",
+            "one_core": d1 * c1 / t1, "host_logical_cpus": ncpu, "cpu_model": model,
+            "sample": f"float64 oracle residuals of periodic 64x64 DG Q3 Euler meshes ({d1} DOFs each) with the "
+                      f"same state recipe, about {seconds:.0f} s per process: one process ({c1} calls), then "
+                      f"{workers} processes with one BLAS thread each ({sum(c for _, c, _ in res)} calls)"}
 
 
 class HipEvents:
@@ -251,7 +283,11 @@ def bench_learned(torch, cvw, gm, prm, U, dt, steps: int):
     cvw.vertex_candidates(gm, cpl, U, cand, wsl)
     t_feat = _timed(torch, stream, lambda: cvw.mlp_features(gm, cpl, U, cand, feat), 10)
     t_inf = _timed(torch, stream, lambda: net.infer(feat, gam), 10)
+    aud = cvw.learned_audit(gm, cvw.make_params(prm_l, mlp=net, sigma_ref=sref, audit_tol=1.0), U,
+                            cvw.alloc_workspace(gm, cpl, 0))
     return {"training": {"snapshot_cells": int(F.shape[0]), "epochs": 20, "batch": 4096, "seconds": t_train},
+            "audit_on_state": aud,
+            "equal_l1": equal_l1(torch, cvw, prm, net),
             "sensor_plain": {"value": E / t_sp, "unit": "cells/s", "ms": t_sp * 1e3},
             "sensor_learned": {"value": E / t_sl, "unit": "cells/s", "ms": t_sl * 1e3},
             "step_plain": {"value": 3.0 * ndof / t_step_p, "unit": "DOF-updates/s", "ms_per_step": t_step_p * 1e3},
@@ -259,6 +295,51 @@ def bench_learned(torch, cvw, gm, prm, U, dt, steps: int):
             "features_ms": t_feat * 1e3, "network_ms": t_inf * 1e3,
             "network_tflops": 14464.0 * E / t_inf / 1e12,
             "status_flags": [cvw.poll_status(gm, wsp), cvw.poll_status(gm, wsl)]}
+
+
+def cell_means(torch, U, n: int, p: int = 3):
+    """Cell averages [4, n, n] of a DG Q_p state on n x n cells (collocated Gauss rule)."""
+    _, w = np.polynomial.legendre.leggauss(p + 1)
+    w2 = torch.from_numpy(np.outer(w, w).ravel() / 4.0).to(U.device, torch.float64)
+    return (U.view(4, n * n, (p + 1) ** 2).double() @ w2).view(4, n, n)
+
+
+def equal_l1(torch, cvw, prm, net, n: int = 128, steps: int = 40):
+    """The learned sensor against the plain one at equal work on a reduced
+    copy of the benchmark problem (n x n, DG Q3 Euler, the four-quadrant data
+    with interfaces a fixed 0.02 wide): L1 errors of the cell averages after
+    `steps` steps, against a plain-sensor run on the 2n x 2n mesh with half
+    the step (its cell averages merged 2 x 2)."""
+    import synth
+    from paper_2601_16911_amd import learned
+    k = 50.0
+    res = {}
+    U0 = euler_config4_state(n, gauss_nodes_2d(3), k).reshape(-1)
+    rho, mx, my, En = (U0.reshape(4, -1)[c].astype(np.float64) for c in range(4))
+    lam = float((np.hypot(mx, my) / rho + np.sqrt(1.4 * 0.4 * (En - 0.5 * (mx * mx + my * my) / rho) / rho)).max())
+    dt = 0.1 * (1.0 / n) / (7 * lam)
+    # reference: plain, 2n x 2n, dt / 2
+    gf = cvw.Mesh(synth.quad_mesh(2 * n, 2 * n), 3, cvw.DG)
+    Uf = torch.from_numpy(euler_config4_state(2 * n, gauss_nodes_2d(3), k).reshape(-1)).cuda()
+    cpf = cvw.make_params(prm)
+    cvw.step(gf, cpf, Uf, dt / 2, 2 * steps, cvw.alloc_workspace(gf, cpf, 1))
+    ref = cell_means(torch, Uf, 2 * n).view(4, n, 2, n, 2).mean((2, 4))
+    gm = cvw.Mesh(synth.quad_mesh(n, n), 3, cvw.DG)
+    sref = learned.sigma_reference(gm, cvw.make_params(prm), torch.from_numpy(U0).cuda())
+    prm_l = synth.Params(**{**prm.__dict__, "sensor": cvw.LEARNED})
+    for name, cp in (("plain", cvw.make_params(prm)), ("learned", cvw.make_params(prm_l, mlp=net, sigma_ref=sref)),
+                     ("gamma_0", cvw.make_params(synth.Params(**{**prm.__dict__, "sensor": 2, "fixed_gamma": 0.0})))):
+        U = torch.from_numpy(U0.copy()).cuda()
+        ws = cvw.alloc_workspace(gm, cp, 1)
+        cvw.step(gm, cp, U, dt, steps, ws)
+        err = (cell_means(torch, U, n) - ref).abs().sum((1, 2)) / (n * n)
+        res[name] = {"l1_density": float(err[0].item()), "l1_all": float(err.sum().item()),
+                     "flags": cvw.poll_status(gm, ws)}
+    res["ratio_learned_to_plain"] = res["learned"]["l1_all"] / res["plain"]["l1_all"]
+    res["workload"] = (f"2D Euler DG Q3, periodic {n}x{n}, {steps} steps of dt = 0.1 h / (7 lambda_max); reference: "
+                       f"plain sensor on {2 * n}x{2 * n} with dt / 2, cell averages merged 2 x 2; L1 of the cell "
+                       "averages per unit area, summed over the 4 variables")
+    return res
 
 
 def sensor_only(torch, cvw, n: int, part: str, calls: int, warmup: int):
@@ -392,11 +473,16 @@ def bench_positivity(torch, cvw, gm, prm, U):
                                            "min_density_after": float(out[: E * nloc].min().item())}}
 
 
-def bench_triangles(torch, cvw, steps: int):
-    """512 x 512 squares split into 524,288 jittered triangles, DG P3, KPP."""
+def bench_triangles(torch, cvw, steps: int, n: int = 512, limiter: bool = True):
+    """n x n squares split into 2 n^2 jittered triangles (512: 524,288; 2048:
+    8,388,608, which no longer fits the 256 MB MALL), DG P3, KPP.  Roofline of
+    the residual (vertex pass + cell pass) from its compulsory bytes per cell:
+    read u and write R (2 x 40 B), the float64 geometry record (64 B), the
+    neighbour and vertex tables (24 B), the vertex candidates written and read
+    (9 floats per vertex, half a vertex per triangle: 36 B)."""
     import synth
     stream = torch.cuda.current_stream()
-    n, p = 512, 3
+    p = 3
     mesh = synth.tri_mesh(n, n, -2.0, 2.0, -2.5, 1.5, jitter=0.1, seed=1003)
     X = mesh.cell_coords
     nodes = np.array([(i / p, j / p) for j in range(p + 1) for i in range(p + 1 - j)])
@@ -415,15 +501,74 @@ def bench_triangles(torch, cvw, steps: int):
     dt = 0.1 * h_min / (2 * p + 1)
     t_res = _timed(torch, stream, lambda: cvw.residual(gm, cp, U, R, None, ws), 10)
     t_step = _timed(torch, stream, lambda: cvw.step(gm, cp, U, dt, steps, ws), 1) / steps
-    # the HWENO limiter on the same state (threshold 0.9, out of place)
-    wl = cvw.alloc_workspace(gm, cp, cvw.OP_LIMIT)
-    Ul = torch.empty_like(U)
-    t_lim = _timed(torch, stream, lambda: cvw.limit(gm, cp, U, Ul, 0.9, None, wl), 5)
-    return {"workload": f"KPP, DG P3 on {mesh.n_cells} jittered triangles", "dofs": dofs,
-            "residual": {"value": dofs / t_res, "unit": "DOF-updates/s", "ms": t_res * 1e3},
-            "step": {"value": 3.0 * dofs / t_step, "unit": "DOF-updates/s", "ms_per_step": t_step * 1e3},
-            "hweno_limiter": {"threshold": 0.9, "value": dofs / t_lim, "unit": "DOF-updates/s", "ms": t_lim * 1e3},
-            "status_flags": cvw.poll_status(gm, ws)}
+    alg = mesh.n_cells * (2 * 40 + 64 + 24 + 36)
+    out = {"workload": f"KPP, DG P3 on {mesh.n_cells} jittered triangles ({n}x{n} squares)", "dofs": dofs,
+           "residual": {"value": dofs / t_res, "unit": "DOF-updates/s", "ms": t_res * 1e3},
+           "residual_roofline": {"bound": "hbm", "achieved": alg / t_res / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": alg / t_res / 1e9 / HBM_PEAK_GBS, "alg_bytes": alg},
+           "step": {"value": 3.0 * dofs / t_step, "unit": "DOF-updates/s", "ms_per_step": t_step * 1e3},
+           "status_flags": cvw.poll_status(gm, ws)}
+    if limiter:
+        # the HWENO limiter on the same state (threshold 0.9, out of place)
+        wl = cvw.alloc_workspace(gm, cp, cvw.OP_LIMIT)
+        Ul = torch.empty_like(U)
+        t_lim = _timed(torch, stream, lambda: cvw.limit(gm, cp, U, Ul, 0.9, None, wl), 5)
+        out["hweno_limiter"] = {"threshold": 0.9, "value": dofs / t_lim, "unit": "DOF-updates/s", "ms": t_lim * 1e3}
+    return out
+
+
+def bench_small_configs(torch, cvw):
+    """The two small workloads, per stage: 1D advection (128 periodic cells,
+    CG P2, float64, the pulse and hump data, CFL 0.3) and solid-body rotation
+    (256 x 256 jittered bilinear Q2 cells, CG, float32, consistent mass by
+    PCG).  Both are launch- and latency-bound (a few MB, resident in caches)."""
+    import synth
+    stream = torch.cuda.current_stream()
+    out = {}
+    # 1D advection: 128 cells, CG P2 (Gauss-Lobatto nodes -1, 0, 1), float64
+    mesh = synth.segment_mesh(128)
+    gm = cvw.Mesh(mesh, 2, cvw.CG)
+    X = mesh.cell_coords[:, :, 0]
+    xn = X[:, :1] + (X[:, 1:] - X[:, :1]) * (np.array([-1.0, 0.0, 1.0])[None, :] + 1.0) / 2.0
+    u = torch.from_numpy(_cg_gather(gm, synth.u0_config1(xn))).cuda()
+    prm = synth.Params(flux=synth.ADVECT_CONST, flux_param=(1.0, 0, 0, 0))
+    cp = cvw.make_params(prm, cvw.F64)
+    ws = cvw.alloc_workspace(gm, cp, 1)
+    t = _timed(torch, stream, lambda: cvw.step(gm, cp, u, 0.3 * (1.0 / 128) / 2, 200, ws), 1) / 200
+    out["config1_1d_advection"] = {"workload": "1D advection, 128 periodic cells, CG P2, float64, 200 steps",
+                                   "dofs": u.numel(), "us_per_stage": t / 3 * 1e6, "ms_per_step": t * 1e3,
+                                   "value": 3 * u.numel() / t, "unit": "DOF-updates/s",
+                                   "status_flags": cvw.poll_status(gm, ws)}
+    # solid-body rotation: 256 x 256 jittered bilinear Q2 cells, CG, float32
+    n = 256
+    mesh = synth.quad_mesh(n, n, jitter=0.1, seed=1002)
+    gm = cvw.Mesh(mesh, 2, cvw.CG)
+    g = np.array([-1.0, 0.0, 1.0])
+    xi, eta = np.tile(g, 3), np.repeat(g, 3)                      # local nodes, x fastest
+    N = np.stack([(1 - xi) * (1 - eta), (1 + xi) * (1 - eta), (1 + xi) * (1 + eta), (1 - xi) * (1 + eta)]) / 4
+    P = np.einsum("vq,evd->eqd", N, mesh.cell_coords)
+    u = torch.from_numpy(_cg_gather(gm, synth.u0_config2(P[..., 0], P[..., 1])).astype(np.float32)).cuda()
+    prm = synth.Params(flux=synth.ADVECT_ROT, flux_param=(0.5, 0.5, 1.0, 0.0))
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, 1)
+    dt = 0.1 * (0.8 / n) / (5 * 0.5 * np.sqrt(2.0))
+    t = _timed(torch, stream, lambda: cvw.step(gm, cp, u, dt, 10, ws), 1) / 10
+    out["config2_rotation"] = {"workload": "solid-body rotation, 256x256 jittered bilinear Q2 cells, CG, float32, "
+                                           "consistent mass by PCG", "dofs": u.numel(),
+                               "us_per_stage": t / 3 * 1e6, "ms_per_step": t * 1e3, "value": 3 * u.numel() / t,
+                               "unit": "DOF-updates/s", "status_flags": cvw.poll_status(gm, ws)}
+    return out
+
+
+def _cg_gather(gm, vals):
+    """Global CG vector from values at every cell's local nodes [E, n_loc]
+    (the first occurrence of each DOF in (cell, local node) order)."""
+    cd = gm.export(5).reshape(vals.shape)
+    flat = cd.ravel()
+    _, first = np.unique(flat, return_index=True)
+    out = np.empty(int(flat.max()) + 1)
+    out[flat[first]] = np.asarray(vals, np.float64).ravel()[first]
+    return out
 
 
 def main():
@@ -589,7 +734,11 @@ def main():
         "sensor_pass": {"bound": "hbm", "kernel": "dgq_sensor_tile_kernel<3> (fused plain sensor pass)",
                         "avg_launch_ms": t_sens * 1e3, "value": E / t_sens, "unit_value": "cells/s",
                         "achieved": sens_bytes / t_sens / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": sens_bytes / t_sens / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": sens_bytes},
+                        "frac": sens_bytes / t_sens / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": sens_bytes,
+                        "traffic": measured_traffic("sensor_pass_bytes_per_launch"),
+                        "valu_issue_frac": (measured_valu("sensor_pass_valu_instr_per_launch") / t_sens /
+                                            VALU_ISSUE_PEAK) if measured_valu("sensor_pass_valu_instr_per_launch")
+                        else None},
         "residual_only": {"value": ndof * nv / t_res, "unit": "DOF-updates/s", "ms": t_res * 1e3},
         "status_flags": flags,
         "wall_s_timed": wall,
@@ -607,6 +756,10 @@ def main():
         out["ensemble_batch"] = bench_ensemble(torch, cvw, 10, tune=not args.no_tune)
         torch.cuda.empty_cache()
         out["triangles_kpp"] = bench_triangles(torch, cvw, 5)
+        torch.cuda.empty_cache()
+        out["triangles_kpp_2048"] = bench_triangles(torch, cvw, 2, n=2048, limiter=False)
+        torch.cuda.empty_cache()
+        out.update(bench_small_configs(torch, cvw))
         torch.cuda.empty_cache()
         out["hweno_limiter"] = bench_limiter(torch, cvw, gm, prm, U, dt)
         torch.cuda.empty_cache()
