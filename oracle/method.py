@@ -387,14 +387,27 @@ def positivity_limit(sp, U, prm: Params, eps0: float = 1e-13, iters: int = 200):
         p(Ubar + t (U_q - Ubar)) = eps (t = 1 where p(U_q) >= eps), found by
         bisection (p is concave along the segment, positive at t = 0).
     Cells with th = 1 keep their values bit for bit.
-    U: [4, E, n_loc] nodal values (Euler); returns the limited values."""
+    U: [4, E, n_loc] nodal values (Euler); returns the limited values.
+
+    Quadrilaterals: Q = the Gauss nodes (the volume rule) and the face Gauss
+    points.  Triangles: Q = the points of the volume rule (where the DG scheme
+    evaluates the state) and the Gauss points of the three edges; the cell
+    average is the volume rule's (exact for the element's polynomials)."""
     gam = prm.flux_param[0]
     U = np.asarray(U, np.float64).copy()
-    w1 = np.polynomial.legendre.leggauss(sp.p + 1)[1]
-    w = np.outer(w1, w1).ravel() / 4.0                        # collocated Gauss rule of the nodes
-    F = _face_trace_matrix(sp)
-    at_pts = lambda V: np.concatenate([V, V @ F.T], axis=-1)                         # nodes, then faces
-    mean = np.einsum("ven,n->ve", U, w)                                             # [4, E]
+    if sp.cell == 2:                                          # triangles
+        ref = sp.ref
+        Bv = ref.deriv(ref.vol_pts, (0, 0))                   # [nq, n_loc]
+        Bq = np.concatenate([Bv] + [ref.deriv(ref.face_points(f)[0], (0, 0)) for f in range(3)])
+        wn = (ref.vol_w / ref.vol_w.sum()) @ Bv               # the cell average from the nodal values
+        at_pts = lambda V: V @ Bq.T
+        mean = np.einsum("ven,n->ve", U, wn)
+    else:
+        w1 = np.polynomial.legendre.leggauss(sp.p + 1)[1]
+        w = np.outer(w1, w1).ravel() / 4.0                    # collocated Gauss rule of the nodes
+        F = _face_trace_matrix(sp)
+        at_pts = lambda V: np.concatenate([V, V @ F.T], axis=-1)                     # nodes, then faces
+        mean = np.einsum("ven,n->ve", U, w)                                         # [4, E]
     eps = np.minimum(eps0, np.minimum(mean[0], _pressure(mean, gam)))
     # (1) density
     rq = at_pts(U[0])

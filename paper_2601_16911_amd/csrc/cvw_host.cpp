@@ -434,6 +434,7 @@ static void fill_tri_tables(TriTables& T, int p) {
     T.yqd[q] = qy[q];
     T.wqd[q] = qw[q];
     for (int j = 0; j < n; ++j) {
+      T.Bd[q][j] = B.deriv(j, 0, 0, qx[q], qy[q]);
       T.B[q][j] = static_cast<float>(B.deriv(j, 0, 0, qx[q], qy[q]));
       T.Gx[q][j] = static_cast<float>(B.deriv(j, 1, 0, qx[q], qy[q]));
       T.Gy[q][j] = static_cast<float>(B.deriv(j, 0, 1, qx[q], qy[q]));
@@ -450,8 +451,20 @@ static void fill_tri_tables(TriTables& T, int p) {
       const double eta = 0.5 * (1.0 - gx[g]) * vy[f] + 0.5 * (1.0 + gx[g]) * vy[f1];
       T.xf[f][g] = static_cast<float>(xi);
       T.yf[f][g] = static_cast<float>(eta);
-      for (int j = 0; j < n; ++j) T.Bf[f][g][j] = static_cast<float>(B.deriv(j, 0, 0, xi, eta));
+      for (int j = 0; j < n; ++j) {
+        T.Bfd[f][g][j] = B.deriv(j, 0, 0, xi, eta);
+        T.Bf[f][g][j] = static_cast<float>(T.Bfd[f][g][j]);
+      }
     }
+  {
+    double ws = 0.0;
+    for (int q = 0; q < nq; ++q) ws += qw[q];
+    for (int j = 0; j < n; ++j) {
+      double a = 0.0;
+      for (int q = 0; q < nq; ++q) a += qw[q] * T.Bd[q][j];
+      T.mwd[j] = a / ws;
+    }
+  }
   for (int l = 0; l < 3; ++l) {
     int t = 0;
     for (int ord = 1; ord <= p; ++ord)
@@ -1413,11 +1426,13 @@ cvw_status cvw_positivity(const cvw_mesh* m, const cvw_params* prm, const void* 
   if (!ws) { set_error("null workspace"); return CVW_EINVAL; }
   if (ws_bytes < cvw_workspace_bytes(m, prm, 3)) { set_error("workspace too small"); return CVW_EINVAL; }
   if (reinterpret_cast<uintptr_t>(ws) % 256) { set_error("workspace must be 256-byte aligned"); return CVW_EINVAL; }
-  if (!(m->cell == CVW_QUAD && m->space == CVW_DG && m->uniform)) {
-    set_error("positivity limiter: DG quadrilaterals (congruent axis-aligned cells) only"); return CVW_EUNSUPPORTED;
+  const bool tri = m->cell == CVW_TRI && m->space == CVW_DG && m->d_trit;
+  if (!(m->cell == CVW_QUAD && m->space == CVW_DG && m->uniform) && !tri) {
+    set_error("positivity limiter: DG quadrilaterals (congruent axis-aligned cells) and DG triangles only");
+    return CVW_EUNSUPPORTED;
   }
   if (prm->flux != CVW_EULER) { set_error("positivity limiter: Euler equations only"); return CVW_EUNSUPPORTED; }
-  if (prm->dtype != CVW_F32) { set_error("DG quadrilaterals run in float32"); return CVW_EUNSUPPORTED; }
+  if (prm->dtype != CVW_F32) { set_error("the positivity limiter runs in float32"); return CVW_EUNSUPPORTED; }
   if (m->degree < 1 || m->degree > MAXP) { set_error("degree not on the GPU path"); return CVW_EUNSUPPORTED; }
   const double gam = prm->flux_param[0];
   if (!(gam > 1.0) || !std::isfinite(gam)) { set_error("gamma must be > 1"); return CVW_EINVAL; }
@@ -1428,6 +1443,9 @@ cvw_status cvw_positivity(const cvw_mesh* m, const cvw_params* prm, const void* 
     const uintptr_t n = static_cast<uintptr_t>(m->E) * m->nloc * 4 * sizeof(float);
     if (a != b && a < b + n && b < a + n) { set_error("u_out overlaps u without being u"); return CVW_EINVAL; }
   }
+  if (tri)
+    return tri_positivity(m, static_cast<const float*>(u), static_cast<float*>(u_out), gam, eps0,
+                          static_cast<hipStream_t>(stream));
   LimitNodes ln{};
   std::vector<double> x, wq;
   gauss_rule(m->degree + 1, x, wq);

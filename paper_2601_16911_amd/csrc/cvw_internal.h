@@ -141,6 +141,11 @@ struct TriTables {
   float mvec[TRI_NLOC];                    // int phi_j over the reference triangle
   double xqd[TRI_NQ], yqd[TRI_NQ], wqd[TRI_NQ];
   double TV[3][TRI_NK][TRI_NLOC];          // reference derivatives D^m phi_j at reference vertex l (|m| >= 1)
+  // float64 copies for the positivity limiter: phi_j at the volume and edge
+  // points, and the cell average as weights of the nodal values
+  double Bd[TRI_NQ][TRI_NLOC];
+  double Bfd[3][MAXP + 1][TRI_NLOC];
+  double mwd[TRI_NLOC];
 };
 
 // Scalars of the method in the precision of the kernels.

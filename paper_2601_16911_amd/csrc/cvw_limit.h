@@ -21,4 +21,9 @@ cvw_status tri_limit(const cvw_mesh* m, const cvw_params* prm, const float* u, f
 cvw_status dgquad_positivity(const cvw_mesh* m, const float* u, float* out, const LimitNodes& ln, double gam,
                              double eps0, uint32_t* count, int32_t* list, hipStream_t s);
 
+// Zhang-Shu positivity limiter, Euler on DG triangles: one float64 thread per
+// cell over the points of the volume rule and the edge Gauss points (every
+// cell written when out != u)
+cvw_status tri_positivity(const cvw_mesh* m, const float* u, float* out, double gam, double eps0, hipStream_t s);
+
 }  // namespace cvw

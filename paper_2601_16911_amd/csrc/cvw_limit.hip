@@ -513,6 +513,96 @@ __global__ __launch_bounds__(128) void dgq_positivity_kernel(const float* __rest
     for (int j = 0; j < NLOC; ++j) out[(static_cast<int64_t>(v) * E + e) * NLOC + j] = static_cast<float>(U[v][j]);
 }
 
+// The same limiter on DG triangles, one thread per cell, float64 inside: the
+// state at the points Q (the volume rule's, where the scheme evaluates it,
+// then the Gauss points of the three edges) from the float64 tables, the cell
+// average as weights of the nodal values; a limited cell is written, an
+// admissible one copied when not in place.
+template <int P>
+__global__ __launch_bounds__(128) void tri_positivity_kernel(const float* __restrict__ u, float* __restrict__ out,
+                                                             int64_t E, const TriTables* __restrict__ T,
+                                                             double gam, double eps0, int copy) {
+  constexpr int NL = (P + 1) * (P + 2) / 2, NQV = (P + 1) * (P + 1), NQ = NQV + 3 * (P + 1);
+  const int64_t e = blockIdx.x * 128LL + threadIdx.x;
+  if (e >= E) return;
+  double U[4][NL];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int j = 0; j < NL; ++j) U[v][j] = u[(static_cast<int64_t>(v) * E + e) * NL + j];
+  double m[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) s = fma(T->mwd[j], U[v][j], s);
+    m[v] = s;
+  }
+  const double gm1 = gam - 1.0;
+  auto pres = [&](double r, double mx, double my, double en) { return gm1 * (en - 0.5 * (mx * mx + my * my) / r); };
+  const double eps = fmin(eps0, fmin(m[0], pres(m[0], m[1], m[2], m[3])));
+  auto at = [&](const double (&V)[NL], int q) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const double b = (q < NQV) ? T->Bd[q][j] : T->Bfd[(q - NQV) / (P + 1)][(q - NQV) % (P + 1)][j];
+      s = fma(b, V[j], s);
+    }
+    return s;
+  };
+  // (1) density
+  double rmin = 1e300;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) rmin = fmin(rmin, at(U[0], q));
+  bool changed = false;
+  if (rmin < eps) {
+    const double th1 = fmin(1.0, (m[0] - eps) / (m[0] - rmin));
+#pragma unroll
+    for (int j = 0; j < NL; ++j) U[0][j] = m[0] + th1 * (U[0][j] - m[0]);
+    changed = true;
+  }
+  // (2) pressure: the smallest root in [0, 1] of p(Ubar + t (U_q - Ubar)) = eps over Q
+  double th2 = 1.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double r = at(U[0], q), mx = at(U[1], q), my = at(U[2], q), en = at(U[3], q);
+    if (pres(r, mx, my, en) >= eps) continue;
+    const double dr = r - m[0], dx = mx - m[1], dy = my - m[2], de = en - m[3];
+    const double k2 = 2.0 * eps / gm1;
+    const double a = 2.0 * dr * de - (dx * dx + dy * dy);
+    const double b = 2.0 * (m[0] * de + dr * m[3]) - 2.0 * (m[1] * dx + m[2] * dy) - k2 * dr;
+    const double c = 2.0 * m[0] * m[3] - (m[1] * m[1] + m[2] * m[2]) - k2 * m[0];
+    th2 = fmin(th2, pos_root(a, b, c));
+  }
+  if (th2 < 1.0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < NL; ++j) U[v][j] = m[v] + th2 * (U[v][j] - m[v]);
+    changed = true;
+  }
+  if (!changed && !copy) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int64_t i = (static_cast<int64_t>(v) * E + e) * NL + j;
+      out[i] = changed ? static_cast<float>(U[v][j]) : u[i];
+    }
+}
+
+cvw_status tri_positivity(const cvw_mesh* m, const float* u, float* out, double gam, double eps0, hipStream_t s) {
+  const dim3 g(static_cast<unsigned>((m->E + 127) / 128)), b(128);
+  const int copy = (out != u) ? 1 : 0;
+  switch (m->degree) {
+    case 1: hipLaunchKernelGGL(tri_positivity_kernel<1>, g, b, 0, s, u, out, m->E, m->d_trit, gam, eps0, copy); break;
+    case 2: hipLaunchKernelGGL(tri_positivity_kernel<2>, g, b, 0, s, u, out, m->E, m->d_trit, gam, eps0, copy); break;
+    case 3: hipLaunchKernelGGL(tri_positivity_kernel<3>, g, b, 0, s, u, out, m->E, m->d_trit, gam, eps0, copy); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
 cvw_status dgquad_positivity(const cvw_mesh* m, const float* u, float* out, const LimitNodes& ln, double gam,
                              double eps0, uint32_t* count, int32_t* list, hipStream_t s) {
   PositivityTraces tr{};

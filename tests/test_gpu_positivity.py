@@ -141,3 +141,35 @@ def test_full_size_one_percent_negative_sampled():
     ref = positivity_limit(sp, Vh[:, pick].astype(np.float64), EULER)
     for v in range(4):
         assert np.abs(Oh[v, pick] - ref[v]).max() <= 1e-5 * np.abs(Vh[v, pick]).max(), v
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_positivity_parity_triangles(p):
+    """DG triangles (jittered, Euler): the points are the volume rule's and the
+    edge Gauss points; limited cells match the oracle, admissible ones are
+    copied bit for bit, in place equals out of place, cell averages and
+    positivity hold on the stored result."""
+    from tests.test_oracle_positivity import _points as o_points, _means as o_means
+    sp, U, _ = inadmissible_state(p, seed=p, cell=synth.TRI)
+    U = f32(U)
+    gm = cvw.Mesh(sp.mesh, p, cvw.DG)
+    cp = cvw.make_params(EULER)
+    ws = cvw.alloc_workspace(gm, cp, cvw.OP_POS)
+    Ud = _dev(U)
+    out = torch.empty_like(Ud)
+    cvw.positivity(gm, cp, Ud, out, 1e-13, ws)
+    inplace = Ud.clone()
+    cvw.positivity(gm, cp, inplace, inplace, 1e-13, ws)
+    assert torch.equal(out, inplace)
+    got = out.cpu().numpy().reshape(U.shape)
+    ref = positivity_limit(sp, U, EULER)
+    changed = np.any(ref != U, axis=(0, 2))
+    assert changed.sum() >= 15
+    for v in range(4):
+        assert np.abs(got[v] - ref[v]).max() <= 1e-5 * np.abs(U[v]).max(), v
+    assert np.array_equal(got[:, ~changed], U.astype(np.float32)[:, ~changed])
+    g64 = got.astype(np.float64)
+    assert np.abs(o_means(sp, g64) - o_means(sp, U)).max() <= 1e-6 * np.abs(U).max()
+    Q = np.stack([o_points(sp, g64[v]) for v in range(4)])
+    scale = np.abs(U).max()
+    assert Q[0].min() >= -1e-6 * scale and _pressure(Q, 1.4).min() >= -1e-6 * scale

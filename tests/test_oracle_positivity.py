@@ -22,11 +22,14 @@ from tests.parity_helpers import euler_state
 EULER = Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0))
 
 
-def inadmissible_state(p, seed=0):
+def inadmissible_state(p, seed=0, cell=synth.QUAD):
     """The four-quadrant Euler data with negative density at one node of some
     cells and negative pressure at one node of others (cell averages stay
-    admissible)."""
-    mesh = synth.quad_mesh(10, 9)
+    admissible); quadrilaterals or jittered triangles."""
+    if cell == synth.TRI:
+        mesh = synth.tri_mesh(8, 7, jitter=0.1, seed=4)
+    else:
+        mesh = synth.quad_mesh(10, 9)
     sp = build_space(mesh, p, 1, 4)
     U = sp.to_cells(euler_state(sp, k=200.0)).copy()
     rng = np.random.default_rng(seed)
@@ -43,26 +46,46 @@ def inadmissible_state(p, seed=0):
 
 
 def _points(sp, V):
+    if sp.cell == synth.TRI:
+        ref = sp.ref
+        B = np.concatenate([ref.deriv(ref.vol_pts, (0, 0))] + [ref.deriv(ref.face_points(f)[0], (0, 0))
+                                                                 for f in range(3)])
+        return V @ B.T
     return np.concatenate([V, V @ _face_trace_matrix(sp).T], axis=-1)
 
 
 def _means(sp, U):
+    if sp.cell == synth.TRI:
+        # exact cell average of the element polynomial: a degree-2p Gauss rule
+        # on the collapsed square, independent of the volume rule
+        ref = sp.ref
+        g, w = np.polynomial.legendre.leggauss(sp.p + 2)
+        a, b = np.meshgrid((g + 1) / 2, (g + 1) / 2, indexing="xy")
+        pts = np.stack([(a * (1 - b)).ravel(), b.ravel()], axis=1)
+        wt = (np.outer(w, w) / 4 * (1 - b)).ravel() * 2.0        # weights of the unit-area triangle average
+        return np.einsum("ven,n->ve", U, wt @ ref.deriv(pts, (0, 0)))
     w1 = np.polynomial.legendre.leggauss(sp.p + 1)[1]
     return np.einsum("ven,n->ve", U, np.outer(w1, w1).ravel() / 4.0)
 
 
+CELLS = [synth.QUAD, synth.TRI]
+
+
+@pytest.mark.parametrize("cell", CELLS)
 @pytest.mark.parametrize("p", [1, 2, 3])
-def test_admissible_states_unchanged(p):
-    sp = build_space(synth.quad_mesh(10, 9), p, 1, 4)
+def test_admissible_states_unchanged(p, cell):
+    mesh = synth.tri_mesh(8, 7, jitter=0.1, seed=4) if cell == synth.TRI else synth.quad_mesh(10, 9)
+    sp = build_space(mesh, p, 1, 4)
     U = sp.to_cells(euler_state(sp, k=10.0))
     Q = np.stack([_points(sp, U[v]) for v in range(4)])
     assert Q[0].min() > 0 and _pressure(Q, 1.4).min() > 0
     assert np.array_equal(positivity_limit(sp, U, EULER), U)
 
 
+@pytest.mark.parametrize("cell", CELLS)
 @pytest.mark.parametrize("p", [1, 2, 3])
-def test_positivity_restored_optimally(p):
-    sp, U, cells = inadmissible_state(p)
+def test_positivity_restored_optimally(p, cell):
+    sp, U, cells = inadmissible_state(p, cell=cell)
     gam = 1.4
     m0 = _means(sp, U)
     eps = np.minimum(1e-13, np.minimum(m0[0], _pressure(m0, gam)))
@@ -84,11 +107,12 @@ def test_positivity_restored_optimally(p):
     assert np.array_equal(out[:, ~bad], U[:, ~bad])
 
 
+@pytest.mark.parametrize("cell", CELLS)
 @pytest.mark.parametrize("p", [2, 3])
-def test_single_factor_per_cell(p):
+def test_single_factor_per_cell(p, cell):
     """Cells whose density is admissible and pressure is not: the result is
     mean + theta (U - mean) with one theta for every variable and node."""
-    sp, U, cells = inadmissible_state(p, seed=3)
+    sp, U, cells = inadmissible_state(p, seed=3, cell=cell)
     m0 = _means(sp, U)
     out = positivity_limit(sp, U, EULER)
     for c in cells[12:]:
