@@ -1269,13 +1269,14 @@ static const float* learned_gamma_of(const cvw_params* prm, const WS& w) {
 // audit has set the latch, are handed to the plain sensor (the fused pass
 // over the flagged tiles only); gamma in the workspace
 static cvw_status learned_gamma(const cvw_mesh* m, const cvw_params* prm, const void* u, const void* cand, const WS& w,
-                                hipStream_t s) {
+                                hipStream_t s, float* gamma = nullptr) {
+  float* g = gamma ? gamma : w.gam;      // the caller's array, else the workspace's
   cvw_status st = dgquad_features(m, static_cast<const float*>(u), static_cast<const float*>(cand), prm->sigma_ref,
                                   w.feat, s);
   if (st != CVW_OK) return st;
   const MlpGuard G{prm->mlp->lo, prm->mlp->hi, w.status, w.tflag, m->grid_nx, (m->grid_nx + 15) / 16};
-  if ((st = mlp_infer(prm->mlp->dev(), w.feat, m->E, w.gam, s, &G)) != CVW_OK) return st;
-  return dgquad_sensor_tile(m, prm, static_cast<const float*>(u), w.gam, s, TILE_FALLBACK, w.tflag);
+  if ((st = mlp_infer(prm->mlp->dev(), w.feat, m->E, g, s, &G)) != CVW_OK) return st;
+  return dgquad_sensor_tile(m, prm, static_cast<const float*>(u), g, s, TILE_FALLBACK, w.tflag);
 }
 
 // audit of the learned sensor on state u: learned gamma (guarded) in the
@@ -1327,7 +1328,14 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
     st = candidates_any(m, prm, u, w.cand, s);
     if (st != CVW_OK) return st;
   }
-  if (prm->sensor == CVW_SENSOR_LEARNED && (st = learned_gamma(m, prm, u, w.cand, w, s)) != CVW_OK) return st;
+  if (prm->sensor == CVW_SENSOR_LEARNED) {
+    // the network (with its plain fallback) writes gamma; the cell pass only
+    // when the shock-capturing weights are asked for
+    if ((st = learned_gamma(m, prm, u, w.cand, w, s, static_cast<float*>(gamma))) != CVW_OK || !alpha) return st;
+    return dgquad_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
+                       static_cast<float*>(alpha), nullptr, w.status, 0.f, 0.f, 0.f, s,
+                       static_cast<const float*>(gamma));
+  }
   if (m->cell == CVW_SEG)
     return seg_eval(m, prm, MODE_SENSOR, u, w.cand, w.pg, w.rcell, nullptr, gamma, alpha, w.status, s);
   if (m->cell == CVW_TRI)
