@@ -19,7 +19,6 @@ from __future__ import annotations
 
 import numpy as np
 from numpy.polynomial import legendre as npleg
-from numpy.polynomial import polynomial as nppoly
 from scipy.special import roots_jacobi
 
 
@@ -41,26 +40,27 @@ def gauss_lobatto(n: int):
 
 
 class Lagrange1D:
-    """Lagrange polynomials l_j on the given nodes, with derivatives of any order."""
+    """Lagrange polynomials l_j on the given nodes, with derivatives of any order.
+
+    Each l_j is held as a Legendre series: with V[i, n] = P_n(x_i) the
+    Legendre-Vandermonde matrix of the nodes, l_j = sum_n (V^{-1})[n, j] P_n.
+    For Gauss and Gauss-Lobatto nodes V is well conditioned at every degree
+    (cond(V) ~ 10 at p = 32), whereas monomial coefficients of l_j lose about
+    five digits there; derivatives are taken term by term on the series.
+    """
 
     def __init__(self, nodes):
         self.nodes = np.asarray(nodes, dtype=np.float64)
         n = len(self.nodes)
-        self.coef = []
-        for j in range(n):
-            others = np.delete(self.nodes, j)
-            c = nppoly.polyfromroots(others)
-            c = c / np.prod(self.nodes[j] - others)
-            self.coef.append(c)
+        self.coef = np.linalg.inv(npleg.legvander(self.nodes, n - 1))      # [n (mode), n (j)]
 
     def __call__(self, x, order: int = 0):
         """Matrix [len(x), n] of d^order l_j / dx^order evaluated at x."""
         x = np.atleast_1d(np.asarray(x, dtype=np.float64))
-        cols = []
-        for c in self.coef:
-            d = nppoly.polyder(c, order) if order > 0 else c
-            cols.append(nppoly.polyval(x, d) if len(d) else np.zeros_like(x))
-        return np.stack(cols, axis=-1)
+        c = npleg.legder(self.coef, order, axis=0) if order > 0 else self.coef
+        if c.shape[0] == 0:
+            return np.zeros((len(x), self.coef.shape[1]))
+        return npleg.legval(x, c).T
 
 
 def stroud_triangle(n: int):

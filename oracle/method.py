@@ -38,8 +38,9 @@ import numpy as np
 import scipy.sparse as sps
 import scipy.sparse.linalg as spla
 
-from synth import Params, ADVECT_CONST, ADVECT_ROT, BURGERS, KPP, EULER
+from synth import Params, ADVECT_CONST, ADVECT_ROT, BURGERS, KPP, EULER, BC_NONE, BC_OUTFLOW, BC_WALL, BC_INFLOW
 from .geometry import physical_derivatives, map_jacobian, map_points, basis_gradients
+from .mesh import face_neighbours
 
 
 # ---------------------------------------------------------------------------
@@ -195,6 +196,11 @@ def flux(prm: Params, U, x):
         return np.stack([np.sin(U), np.cos(U)], axis=-1)
     if prm.flux == EULER:
         g = prm.flux_param[0]
+        if d == 1:                                  # (rho, m, E) on a line
+            rho, mx, En = U
+            vx = mx / rho
+            p = (g - 1.0) * (En - 0.5 * rho * vx * vx)
+            return np.stack([mx, mx * vx + p, (En + p) * vx])[..., None]
         rho, mx, my, En = U
         vx, vy = mx / rho, my / rho
         p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy))
@@ -218,8 +224,12 @@ def wave_speed(prm: Params, U, x):
         return np.ones(U.shape[1:])
     if prm.flux == EULER:
         g = prm.flux_param[0]
-        rho, mx, my, En = U
-        vx, vy = mx / rho, my / rho
+        if d == 1:
+            rho, mx, En = U
+            vx, vy = mx / rho, 0.0
+        else:
+            rho, mx, my, En = U
+            vx, vy = mx / rho, my / rho
         p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy))
         c = np.sqrt(np.maximum(g * p / rho, 0.0))
         return np.hypot(vx, vy) + c
@@ -235,10 +245,14 @@ def numerical_flux(prm: Params, Um, Up, n, x):
         g = prm.flux_param[0]
 
         def vn_c(U):
-            rho, mx, my, En = U
-            vx, vy = mx / rho, my / rho
+            if n.shape[-1] == 1:
+                rho, mx, En = U
+                vx, vy, ny = mx / rho, 0.0, 0.0
+            else:
+                rho, mx, my, En = U
+                vx, vy, ny = mx / rho, my / rho, n[..., 1]
             p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy))
-            return vx * n[..., 0] + vy * n[..., 1], np.sqrt(np.maximum(g * p / rho, 0.0))
+            return vx * n[..., 0] + vy * ny, np.sqrt(np.maximum(g * p / rho, 0.0))
 
         vm, cm = vn_c(Um)
         vp, cp = vn_c(Up)
@@ -477,8 +491,12 @@ def residual(sp, U, prm: Params, gamma=None, return_parts: bool = False, allow_b
     alpha = sc_weights(sp, s, gamma, prm, pg)
     r = (-np.einsum("eq,eqjd,veqd->vej", W, gphi, F)
          + np.einsum("e,eq,eq,eqjd,veqd->vej", nu, W, alpha, gphi, G))
+    ends = any(b != BC_NONE for b in prm.bc)
     if sp.kind == 1:
-        r = r + face_terms(sp, Uc, prm, allow_boundary)
+        r = r + face_terms(sp, Uc, prm, allow_boundary or ends)
+    if ends:
+        r = r + boundary_terms(sp, Uc, prm)
+    if sp.kind == 1:
         R = r.reshape(nv, -1)
     else:
         R = np.zeros((nv, sp.n_dof))
@@ -531,6 +549,55 @@ def face_terms(sp, Uc, prm: Params, allow_boundary: bool = False):
         Fs = numerical_flux(prm, Um, Up, nb, xf)                   # [nv, E, ng]
         Fs = np.where((en >= 0)[None, :, None], Fs, 0.0)
         out += np.einsum("g,e,gj,veg->vej", wf, Jf, phif, Fs)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# boundary data at the ends of a 1D domain (the paper's shock-tube and blast-
+# wave runs, Sec. 5.4: an inflow end and reflecting walls)
+# ---------------------------------------------------------------------------
+def boundary_state(prm: Params, Ub, n, end: int):
+    """Exterior state at a boundary point: outflow copies the interior trace,
+    an inflow end imposes the given state, a reflecting wall mirrors the
+    normal momentum (Euler only).  Ub [n_var, ...], n [..., d]."""
+    kind = prm.bc[end]
+    if kind == BC_OUTFLOW:
+        return Ub.copy()
+    if kind == BC_INFLOW:
+        st = np.asarray(prm.bc_state[end][:Ub.shape[0]], np.float64)
+        return np.broadcast_to(st.reshape((-1,) + (1,) * (Ub.ndim - 1)), Ub.shape).copy()
+    if kind == BC_WALL:
+        if prm.flux != EULER:
+            raise ValueError("a reflecting wall needs the Euler equations")
+        d = n.shape[-1]
+        out = Ub.copy()
+        mn = sum(Ub[1 + a] * n[..., a] for a in range(d))
+        for a in range(d):
+            out[1 + a] = Ub[1 + a] - 2.0 * mn * n[..., a]
+        return out
+    raise ValueError("boundary point without boundary data")
+
+
+def boundary_terms(sp, Uc, prm: Params):
+    """Weak boundary terms phi_j(x_b) f*(u_h(x_b), u_ext; n) at the two ends of a
+    1D domain, for DG and CG alike: face 0 of a cell without a left neighbour
+    is the left end (n = -1), face 1 without a right neighbour the right end."""
+    ref = sp.ref
+    if ref.dim != 1:
+        raise NotImplementedError("boundary data: 1D domains only")
+    nbr = sp.nbr if sp.nbr is not None else face_neighbours(sp.cell, sp.mesh.cell_vertices)[0]
+    out = np.zeros_like(Uc)
+    for f in range(2):
+        sel = nbr[:, f] < 0
+        if not sel.any():
+            continue
+        pts, _ = ref.face_points(f)
+        phif = ref.deriv(pts, (0,))[0]                              # [nloc]
+        Ub = np.einsum("vej,j->ve", Uc[:, sel], phif)[..., None]     # [nv, nb, 1]
+        n = np.full(Ub.shape[1:] + (1,), -1.0 if f == 0 else 1.0)
+        xf = map_points(sp.cell, sp.X[sel], pts)
+        Fs = numerical_flux(prm, Ub, boundary_state(prm, Ub, n, f), n, xf)   # [nv, nb, 1]
+        out[:, sel] += Fs[..., 0][..., None] * phif
     return out
 
 

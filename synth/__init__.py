@@ -27,6 +27,8 @@ import numpy as np
 SEG, TRI, QUAD = 1, 2, 3
 CG, DG = 0, 1
 ADVECT_CONST, ADVECT_ROT, BURGERS, KPP, EULER = 0, 1, 2, 3, 4
+# boundary data at the two ends of a non-periodic 1D domain
+BC_NONE, BC_OUTFLOW, BC_WALL, BC_INFLOW = 0, 1, 2, 3
 
 
 @dataclass
@@ -135,6 +137,10 @@ class Params:
     lambda_global: float = 0.0
     sensor: int = 0          # 0 plain HWENO sensor, 2 fixed gamma
     fixed_gamma: float = 1.0
+    # 1D domains with ends: the kind at the left and right end (BC_*) and the
+    # exterior state of an inflow end (conserved variables)
+    bc: tuple = (BC_NONE, BC_NONE)
+    bc_state: tuple = ((0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0))
 
 
 # ---------------------------------------------------------------------------
@@ -313,3 +319,42 @@ def smooth_field(x, y, seed: int, modes: int = 3):
 def random_nodal(shape, seed: int, scale: float = 1.0):
     """Seeded arbitrary nodal values (for tests that do not need a physical state)."""
     return np.random.default_rng(seed).uniform(-scale, scale, size=shape)
+
+
+# ---------------------------------------------------------------------------
+# One-dimensional Euler data (conserved variables rho, m = rho v, E), gamma 1.4
+# ---------------------------------------------------------------------------
+def euler1d_conserved(rho, v, p, gas_gamma: float = 1.4):
+    """(rho, rho v, p / (gamma - 1) + rho v^2 / 2) from primitive values."""
+    rho, v, p = np.broadcast_arrays(np.asarray(rho, np.float64), np.asarray(v, np.float64),
+                                    np.asarray(p, np.float64))
+    return rho, rho * v, p / (gas_gamma - 1.0) + 0.5 * rho * v * v
+
+
+def u0_modified_sod(x):
+    """Modified Sod shock tube on (0, 1): (rho, v, p) = (1, 0.75, 1) left of
+    x = 0.25, (0.125, 0, 0.1) right of it; conserved variables [3, ...]."""
+    x = np.asarray(x, np.float64)
+    left = x < 0.25
+    return np.stack(euler1d_conserved(np.where(left, 1.0, 0.125), np.where(left, 0.75, 0.0),
+                                      np.where(left, 1.0, 0.1)))
+
+
+def modified_sod_params(flux_gamma: float = 1.4) -> Params:
+    """Inflow of the left state at x = 0, reflecting wall at x = 1."""
+    inflow = tuple(float(c) for c in euler1d_conserved(1.0, 0.75, 1.0, flux_gamma)) + (0.0,)
+    return Params(flux=EULER, flux_param=(flux_gamma, 0.0, 0.0, 0.0), bc=(BC_INFLOW, BC_WALL),
+                  bc_state=(inflow, (0.0, 0.0, 0.0, 0.0)))
+
+
+def u0_blast_wave(x):
+    """Woodward-Colella blast waves on (0, 1): rho = 1, v = 0, p = 1000 / 0.01 /
+    100 on (0, 0.1) / [0.1, 0.9] / (0.9, 1); conserved variables [3, ...]."""
+    x = np.asarray(x, np.float64)
+    p = np.where(x < 0.1, 1000.0, np.where(x > 0.9, 100.0, 0.01))
+    return np.stack(euler1d_conserved(np.ones_like(x), np.zeros_like(x), p))
+
+
+def blast_wave_params(flux_gamma: float = 1.4) -> Params:
+    """Reflecting walls at both ends."""
+    return Params(flux=EULER, flux_param=(flux_gamma, 0.0, 0.0, 0.0), bc=(BC_WALL, BC_WALL))
