@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 7
+#define CVW_ABI_VERSION 8
 
 typedef enum {
   CVW_OK = 0,
@@ -66,8 +66,19 @@ typedef enum {
   CVW_ADVECT_ROT = 1,      /* f = v(x) u, v = w (cy - y, x - cx), (cx, cy, w) = flux_param[0..2] */
   CVW_BURGERS = 2,         /* f = u^2 / 2 (flux_param[0], flux_param[1])                     */
   CVW_KPP = 3,             /* f = (sin u, cos u)                                             */
-  CVW_EULER = 4            /* 2D Euler, 4 conserved variables, gas gamma = flux_param[0]     */
+  CVW_EULER = 4            /* Euler equations, gas gamma = flux_param[0]; dim + 2 conserved
+                              variables: (rho, m, E) on lines, (rho, m_x, m_y, E) in 2D        */
 } cvw_flux;
+/* Boundary data at the two ends of a line (1D meshes whose first and last
+ * vertex belong to one cell each; Sec. 5.4 of the paper: an inflow end and
+ * reflecting walls).  The boundary term phi_j(x_b) f*(u_h(x_b), u_ext; n) is
+ * added to the residual of both CG and DG, with the interface flux of the
+ * interior faces (HLL for the Euler equations, Lax-Friedrichs otherwise):
+ *   OUTFLOW: u_ext = u_h(x_b) (the physical flux of the trace),
+ *   WALL:    u_ext = (rho, -m, E) (Euler only),
+ *   INFLOW:  u_ext = bc_state[end] (conserved variables).
+ * The vertex patch of an end vertex is the one cell that contains it. */
+typedef enum { CVW_BC_NONE = 0, CVW_BC_OUTFLOW = 1, CVW_BC_WALL = 2, CVW_BC_INFLOW = 3 } cvw_bc;
 typedef enum { CVW_F32 = 0, CVW_F64 = 1 } cvw_dtype;
 typedef enum { CVW_SENSOR_PLAIN = 0, CVW_SENSOR_LEARNED = 1, CVW_SENSOR_FIXED = 2 } cvw_sensor_kind;
 
@@ -115,6 +126,9 @@ typedef struct {
   const struct cvw_mlp* mlp; /* CVW_SENSOR_LEARNED: the network (cvw_mlp_create)  */
   double audit_tol;          /* CVW_SENSOR_LEARNED: an audit whose mean |gamma_learned - gamma_plain|
                                 exceeds it switches the run to the plain sensor (cvw_learned_audit) */
+  int32_t bc[2];             /* lines with ends: cvw_bc at the left end (vertex 0 of its cell) and
+                                the right end; both must be set on such a line, ignored on closed meshes */
+  double bc_state[2][4];     /* CVW_BC_INFLOW: exterior conserved state at that end (first n_var used) */
 } cvw_params;
 
 typedef struct {

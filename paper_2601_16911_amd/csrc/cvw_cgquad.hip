@@ -174,8 +174,8 @@ __global__ __launch_bounds__(256) void cgq_pg_kernel(const float* __restrict__ u
   const int beg = dptr[I], end = dptr[I + 1];
   for (int it = beg; it < end; ++it) {
     const int ent = dent[it];
-    const int64_t e = ent >> 4;
-    const int j = ent & 15;
+    const int64_t e = ent / NLOC;
+    const int j = ent - static_cast<int>(e) * NLOC;
     const int a = j % N1, b = j / N1;
     float ue[NLOC];
     load_cell<P>(u, cdof, e, ue);
@@ -468,13 +468,13 @@ __global__ __launch_bounds__(128) void cgq_cell_kernel(const float* __restrict__
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void cg_assemble_kernel(const float* __restrict__ rcell, float* __restrict__ R,
                                                           const int32_t* __restrict__ dptr,
-                                                          const int32_t* __restrict__ dent, int nloc, int64_t ndof) {
+                                                          const int32_t* __restrict__ dent, int64_t ndof) {
   const int64_t I = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (I >= ndof) return;
   float s = 0.0f;
   for (int it = dptr[I]; it < dptr[I + 1]; ++it) {
     const int ent = dent[it];
-    s += rcell[static_cast<int64_t>(ent >> 4) * nloc + (ent & 15)];
+    s += rcell[ent];                      // ent = cell * nloc + local node
   }
   R[I] = s;
 }
@@ -534,7 +534,7 @@ cvw_status cgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const
   if (st != CVW_OK) return st;
   if (mode != MODE_SENSOR)
     hipLaunchKernelGGL(cg_assemble_kernel, dim3(nblk(m->ndof, 256)), dim3(256), 0, s, rcell, R, m->d_dof_ptr,
-                       m->d_dof_ent, m->nloc, m->ndof);
+                       m->d_dof_ent, m->ndof);
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 

@@ -18,6 +18,7 @@ namespace cvw {
 
 enum { S_RZ = 0, S_PAP = 1, S_RZ0 = 2, S_ALPHA = 3, S_BETA = 4, S_DONE = 5, S_TOL2 = 6, S_ITER = 7 };
 constexpr int PCG_THREADS = 256;
+static_assert(S_DONE == PCG_S_DONE, "mass-solve scalar layout");
 
 __device__ __forceinline__ bool pcg_done(const double* S) { return S[S_DONE] != 0.0; }
 
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(PCG_THREADS) void pcg_gather_dot_kernel(const Real*
                                                                      const Real* __restrict__ p, Real* __restrict__ Ap,
                                                                      double* __restrict__ part,
                                                                      const int32_t* __restrict__ dptr,
-                                                                     const int32_t* __restrict__ dent, int nloc,
+                                                                     const int32_t* __restrict__ dent,
                                                                      int64_t n, const double* __restrict__ S) {
   __shared__ double sh[PCG_THREADS];
   if (pcg_done(S)) return;
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(PCG_THREADS) void pcg_gather_dot_kernel(const Real*
     Real s = Real(0);
     for (int it = dptr[I]; it < dptr[I + 1]; ++it) {
       const int ent = dent[it];
-      s += ycell[static_cast<int64_t>(ent >> 4) * nloc + (ent & 15)];
+      s += ycell[ent];                    // ent = cell * nloc + local node
     }
     Ap[I] = s;
     d = static_cast<double>(p[I]) * static_cast<double>(s);
@@ -227,15 +228,15 @@ __global__ void pcg_setup_kernel(double* __restrict__ S, double tol2) {
 }
 
 // u_out = a0 u_n + b0 (u_s - dt x), x = M^{-1} R (dinv != null: x = dinv * R, a
-// diagonal mass); a0 = 0: u_n is not read
+// diagonal mass of nm entries shared by every variable); a0 = 0: u_n is not read
 template <typename Real>
 __global__ __launch_bounds__(256) void stage_update_kernel(const Real* __restrict__ us, const Real* __restrict__ un,
                                                            const Real* __restrict__ x, const Real* __restrict__ dinv,
                                                            Real* __restrict__ uo, Real a0, Real b0, Real dt,
-                                                           int64_t n) {
+                                                           int64_t n, int64_t nm) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
-  const Real xi = dinv ? x[i] * dinv[i] : x[i];
+  const Real xi = dinv ? x[i] * dinv[i % nm] : x[i];
   const Real base = (a0 != Real(0)) ? a0 * un[i] : Real(0);
   uo[i] = base + b0 * (us[i] - dt * xi);
 }
@@ -252,6 +253,10 @@ static void mass_cells(const cvw_mesh* m, const Real* x, Real* ycell, const doub
       else
         hipLaunchKernelGGL(cgq_mass_kernel<2>, g, b, 0, s, x, ycell, m->d_cell_dof, m->d_geo, m->d_cgt, m->E, S);
     }
+    return;
+  }
+  if (m->degree > MAXP) {               // any degree: one wave per cell, float64
+    if constexpr (std::is_same<Real, double>::value) seghp_mass_cells(m, x, ycell, S, s);
     return;
   }
   switch (m->degree) {
@@ -282,7 +287,7 @@ cvw_status cg_mass_solve(const cvw_mesh* m, const Real* b, Real* x, Real* r, Rea
   for (int it = 0; it < maxit; ++it) {
     mass_cells<Real>(m, p, ycell, S, s);
     hipLaunchKernelGGL((pcg_gather_dot_kernel<Real>), g, t, 0, s, ycell, p, Ap, part, m->d_dof_ptr, m->d_dof_ent,
-                       m->nloc, n, S);
+                       n, S);
     hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), t, 0, s, part, nb, S, 1);
     hipLaunchKernelGGL((pcg_update_kernel<Real>), g, t, 0, s, x, r, z, p, Ap, dinv, part, n, S);
     hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), t, 0, s, part, nb, S, 2);
@@ -294,9 +299,9 @@ cvw_status cg_mass_solve(const cvw_mesh* m, const Real* b, Real* x, Real* r, Rea
 
 template <typename Real>
 cvw_status stage_update(const Real* us, const Real* un, const Real* x, const Real* dinv, Real* uo, double a0,
-                        double b0, double dt, int64_t n, hipStream_t s) {
+                        double b0, double dt, int64_t n, hipStream_t s, int64_t nm) {
   hipLaunchKernelGGL((stage_update_kernel<Real>), dim3(nbk(n, 256)), dim3(256), 0, s, us, un, x, dinv, uo,
-                     static_cast<Real>(a0), static_cast<Real>(b0), static_cast<Real>(dt), n);
+                     static_cast<Real>(a0), static_cast<Real>(b0), static_cast<Real>(dt), n, nm > 0 ? nm : n);
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
 }
 
@@ -307,8 +312,8 @@ template cvw_status cg_mass_solve<double>(const cvw_mesh*, const double*, double
                                           double*, double*, double*, double*, const double*, double, int,
                                           uint32_t*, hipStream_t);
 template cvw_status stage_update<float>(const float*, const float*, const float*, const float*, float*, double,
-                                        double, double, int64_t, hipStream_t);
+                                        double, double, int64_t, hipStream_t, int64_t);
 template cvw_status stage_update<double>(const double*, const double*, const double*, const double*, double*,
-                                         double, double, double, int64_t, hipStream_t);
+                                         double, double, double, int64_t, hipStream_t, int64_t);
 
 }  // namespace cvw

@@ -20,7 +20,7 @@ static thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }
 
-int n_var_of(int flux) { return flux == CVW_EULER ? 4 : 1; }
+int n_var(const cvw_mesh* m, int flux) { return flux == CVW_EULER ? m->dim + 2 : 1; }
 
 MethodScalars make_scalars(const cvw_params* p) {
   MethodScalars s{};
@@ -45,6 +45,39 @@ MethodScalars make_scalars(const cvw_params* p) {
   s.fixed_gammad = p->fixed_gamma;
   for (int i = 0; i < 4; ++i) s.fpd[i] = p->flux_param[i];
   return s;
+}
+
+// The 1D kernels of any degree serve degrees above 3, the Euler equations and
+// lines with ends; scalar laws of degree <= 3 on closed lines keep the
+// one-thread-per-cell kernels.
+bool seg_hp(const cvw_mesh* m, const cvw_params* prm) {
+  return m->cell == CVW_SEG && (m->degree > MAXP || prm->flux == CVW_EULER || m->open_ends > 0);
+}
+
+SegHPArgs seghp_args(const cvw_mesh* m, const cvw_params* prm) {
+  SegHPArgs A{};
+  A.tab = m->d_hp;
+  A.cell_dof = m->d_cell_dof;
+  A.cell_vtx = m->d_cell_vtx;
+  A.nbr = m->d_nbr;
+  A.hcell = m->d_hcell;
+  A.vptr = m->d_vtx_ptr;
+  A.vent = m->d_vtx_ent;
+  A.dptr = m->d_dof_ptr;
+  A.dent = m->d_dof_ent;
+  A.E = m->E;
+  A.Nv = m->Nv;
+  A.ndof = m->ndof;
+  A.p = m->degree;
+  A.nv = n_var(m, prm->flux);
+  A.flux = prm->flux;
+  A.cg = m->space == CVW_CG ? 1 : 0;
+  for (int e = 0; e < 2; ++e) {
+    A.bc[e] = prm->bc[e];
+    for (int v = 0; v < 4; ++v) A.bcs[e][v] = prm->bc_state[e][v];
+  }
+  A.ms = make_scalars(prm);
+  return A;
 }
 
 // ---------------------------------------------------------------------------
@@ -508,6 +541,131 @@ static void fill_seg_tables(SegTables& T, int p, bool lobatto) {
     for (int i = 0; i <= p; ++i) T.Dn[a][i] = lagrange_deriv(xn, i, 1, xn[a]);
 }
 
+// ---------------------------------------------------------------------------
+// Reference operators of the 1D Lagrange basis at any degree (hp_off layout),
+// in extended precision: the nodes by Newton's method on the Legendre
+// polynomials, each l_j as a Legendre series (the inverse of the Legendre-
+// Vandermonde matrix of the nodes), and the derivatives of every order of the
+// P_n from the three-term recurrence differentiated m times:
+//   n P_n^(m)(x) = (2n - 1) (x P_{n-1}^(m)(x) + m P_{n-1}^(m-1)(x)) - (n - 1) P_{n-2}^(m)(x).
+// ---------------------------------------------------------------------------
+using ld = long double;
+
+// P_n^(m)(x) for n = 0..N, m = 0..M into T[m * (N + 1) + n]
+static void legendre_all(int N, int M, ld x, std::vector<ld>& T) {
+  T.assign(static_cast<size_t>(M + 1) * (N + 1), 0.0L);
+  for (int m = 0; m <= M; ++m)
+    for (int n = 0; n <= N; ++n) {
+      ld v;
+      if (n == 0) {
+        v = m == 0 ? 1.0L : 0.0L;
+      } else {
+        const ld a = T[m * (N + 1) + n - 1];
+        const ld b = m > 0 ? T[(m - 1) * (N + 1) + n - 1] : 0.0L;
+        const ld c = n >= 2 ? T[m * (N + 1) + n - 2] : 0.0L;
+        v = ((2 * n - 1) * (x * a + m * b) - (n - 1) * c) / n;
+      }
+      T[m * (N + 1) + n] = v;
+    }
+}
+
+// n-point Gauss rule (nodes ascending) or n-point Gauss-Lobatto nodes
+static void rule_ld(int n, bool lobatto, std::vector<ld>& x, std::vector<ld>& w) {
+  x.assign(n, 0.0L);
+  w.assign(n, 0.0L);
+  std::vector<ld> T;
+  if (!lobatto) {
+    for (int i = 0; i < n; ++i) {
+      ld z = -std::cos(static_cast<ld>(M_PI) * (i + 0.75L) / (n + 0.5L));
+      for (int it = 0; it < 100; ++it) {
+        legendre_all(n, 1, z, T);
+        const ld dz = T[n] / T[(n + 1) + n];
+        z -= dz;
+        if (std::fabs(dz) < 1e-19L) break;
+      }
+      legendre_all(n, 1, z, T);
+      x[i] = z;
+      w[i] = 2.0L / ((1.0L - z * z) * T[(n + 1) + n] * T[(n + 1) + n]);
+    }
+    return;
+  }
+  const int m = n - 1;               // interior nodes: roots of P_m'
+  x[0] = -1.0L;
+  x[n - 1] = 1.0L;
+  for (int i = 1; i < n - 1; ++i) {
+    ld z = -std::cos(static_cast<ld>(M_PI) * i / m);
+    for (int it = 0; it < 100; ++it) {
+      legendre_all(m, 2, z, T);
+      const ld dz = T[(m + 1) + m] / T[2 * (m + 1) + m];
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) break;
+    }
+    x[i] = z;
+  }
+}
+
+static std::vector<double> fill_hp_tables(int p, bool lobatto) {
+  const int n1 = p + 1;
+  const HPOff o = hp_off(p);
+  std::vector<double> out(o.size, 0.0);
+  std::vector<ld> xq, wq, xn, wn;
+  rule_ld(n1, false, xq, wq);
+  if (lobatto) rule_ld(n1, true, xn, wn); else xn = xq;
+  // C = V^{-1}, V[i][n] = P_n(xn_i): Gauss-Jordan with partial pivoting
+  std::vector<ld> V(n1 * n1), C(n1 * n1, 0.0L), T;
+  for (int i = 0; i < n1; ++i) {
+    legendre_all(p, 0, xn[i], T);
+    for (int n = 0; n < n1; ++n) V[i * n1 + n] = T[n];
+    C[i * n1 + i] = 1.0L;
+  }
+  for (int c = 0; c < n1; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n1; ++r)
+      if (std::fabs(V[r * n1 + c]) > std::fabs(V[piv * n1 + c])) piv = r;
+    for (int k = 0; k < n1; ++k) {
+      std::swap(V[c * n1 + k], V[piv * n1 + k]);
+      std::swap(C[c * n1 + k], C[piv * n1 + k]);
+    }
+    const ld d = V[c * n1 + c];
+    for (int k = 0; k < n1; ++k) { V[c * n1 + k] /= d; C[c * n1 + k] /= d; }
+    for (int r = 0; r < n1; ++r) {
+      if (r == c) continue;
+      const ld f = V[r * n1 + c];
+      if (f == 0.0L) continue;
+      for (int k = 0; k < n1; ++k) { V[r * n1 + k] -= f * V[c * n1 + k]; C[r * n1 + k] -= f * C[c * n1 + k]; }
+    }
+  }
+  // l_j^(m)(x) = sum_n C[n][j] P_n^(m)(x)   (C rows: modes n, columns: nodes j)
+  auto lag = [&](ld x, std::vector<ld>& L) {       // L[m * n1 + j], m = 0..p
+    legendre_all(p, p, x, T);
+    L.assign(n1 * n1, 0.0L);
+    for (int m = 0; m <= p; ++m)
+      for (int j = 0; j < n1; ++j) {
+        ld s = 0.0L;
+        for (int n = m; n <= p; ++n) s += C[n * n1 + j] * T[m * n1 + n];
+        L[m * n1 + j] = s;
+      }
+  };
+  std::vector<ld> L;
+  for (int q = 0; q < n1; ++q) {
+    out[o.xq + q] = static_cast<double>(xq[q]);
+    out[o.wq + q] = static_cast<double>(wq[q]);
+    lag(xq[q], L);
+    for (int m = 0; m <= p; ++m)
+      for (int j = 0; j < n1; ++j) out[o.DQ + (m * n1 + j) * n1 + q] = static_cast<double>(L[m * n1 + j]);
+  }
+  for (int v = 0; v < 2; ++v) {
+    lag(v == 0 ? -1.0L : 1.0L, L);
+    for (int j = 0; j < n1; ++j)
+      for (int m = 0; m <= p; ++m) out[o.DV + (v * n1 + j) * n1 + m] = static_cast<double>(L[m * n1 + j]);
+  }
+  for (int a = 0; a < n1; ++a) {
+    lag(xn[a], L);
+    for (int j = 0; j < n1; ++j) out[o.DN + a * n1 + j] = static_cast<double>(L[n1 + j]);
+  }
+  return out;
+}
+
 // Canonical CG numbering: vertex DOFs by vertex id, then edge DOFs (edges
 // sorted by (min, max) vertex id, oriented min -> max), then cell-interior
 // DOFs by cell id (lexicographic inside the cell).
@@ -635,25 +793,24 @@ static cvw_status upload(T** dst, const std::vector<T>& src) {
 static std::vector<double> diag_mass(const cvw_mesh* m, const cvw_mesh_desc* d) {
   std::vector<double> out;
   const int p = m->degree;
-  if (p < 1 || p > MAXP) return out;
   const int64_t E = m->E;
   if (d->cell == CVW_SEG) {
-    std::vector<double> xq, wq;
-    gauss_rule(p + 1, xq, wq);
-    std::vector<double> xn;
-    if (d->space == CVW_CG) lobatto_nodes(p + 1, xn); else xn = xq;
-    out.assign(d->space == CVW_CG ? m->ndof : E * (p + 1), 0.0);
+    const std::vector<double> tab = fill_hp_tables(p, d->space == CVW_CG);
+    const HPOff o = hp_off(p);
+    const int n1 = p + 1;
+    out.assign(d->space == CVW_CG ? m->ndof : E * n1, 0.0);
     for (int64_t e = 0; e < E; ++e) {
       const double jac = 0.5 * (d->cell_coords[e * 2 + 1] - d->cell_coords[e * 2]);
       for (int j = 0; j <= p; ++j) {
         double s = 0.0;
-        for (int q = 0; q <= p; ++q) s += wq[q] * lagrange_deriv(xn, j, 0, xq[q]);
-        const int64_t I = d->space == CVW_CG ? m->h_cell_dof[e * (p + 1) + j] : e * (p + 1) + j;
+        for (int q = 0; q <= p; ++q) s += tab[o.wq + q] * tab[o.DQ + j * n1 + q];
+        const int64_t I = d->space == CVW_CG ? m->h_cell_dof[e * n1 + j] : e * n1 + j;
         out[I] += jac * s;
       }
     }
     return out;
   }
+  if (p < 1 || p > MAXP) return out;
   if (d->cell == CVW_QUAD && d->space == CVW_CG && p <= 2) {
     std::vector<double> xq, wq, xn;
     gauss_rule(p + 1, xq, wq);
@@ -704,6 +861,7 @@ static void free_mesh(cvw_mesh* m) {
   (void)hipFree(m->d_cgt);
   (void)hipFree(m->d_hcell);
   (void)hipFree(m->d_segt);
+  (void)hipFree(m->d_hp);
   (void)hipFree(m->d_trit);
   (void)hipFree(m->d_geot);
   (void)hipFree(m->d_nbrf);
@@ -729,11 +887,13 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   else if (d->cell == CVW_TRI && d->dim == 2) { ve = 3; nf = 3; }
   else if (d->cell == CVW_QUAD && d->dim == 2) { ve = 4; nf = 4; }
   else { set_error("cell type / dimension mismatch"); return CVW_EINVAL; }
-  if (d->degree < 1 || d->degree > 16) { set_error("degree out of range"); return CVW_EINVAL; }
+  if (d->degree < 1 || d->degree > (d->cell == CVW_SEG ? HP_MAXP : 16)) { set_error("degree out of range"); return CVW_EINVAL; }
   if (d->space != CVW_CG && d->space != CVW_DG) { set_error("space must be CG or DG"); return CVW_EINVAL; }
   if (d->n_cells <= 0 || d->n_vertices <= 0) { set_error("empty mesh"); return CVW_EINVAL; }
-  // packed (cell, local index) entries: cell * 4 + local vertex, cell * 16 + local CG node
-  if (d->n_cells * (d->space == CVW_CG ? 16 : 4) >= (int64_t(1) << 31) || d->n_vertices >= (int64_t(1) << 31)) {
+  // packed (cell, local index) entries: cell * 4 + local vertex, cell * n_loc + local CG node
+  const int64_t nloc_d = d->cell == CVW_SEG ? d->degree + 1 : d->cell == CVW_QUAD ? (d->degree + 1) * (d->degree + 1)
+                                                                                : (d->degree + 1) * (d->degree + 2) / 2;
+  if (d->n_cells * std::max<int64_t>(4, nloc_d) >= (int64_t(1) << 31) || d->n_vertices >= (int64_t(1) << 31)) {
     set_error("mesh too large for 32-bit indices"); return CVW_EINVAL;
   }
   const int64_t E = d->n_cells, Nv = d->n_vertices;
@@ -812,6 +972,22 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     if (uni) { m->hx = hx0; m->hy = hy0; m->he = std::sqrt(hx0 * hx0 + hy0 * hy0); }
   }
 
+  // ---- ends of a line: vertices of one cell ----
+  if (d->cell == CVW_SEG) {
+    for (int64_t v = 0; v < Nv; ++v) m->open_ends += cnt[v] == 1 ? 1 : 0;
+    // every other vertex joins the right vertex of one cell to the left vertex of another
+    std::vector<int8_t> side(Nv, 0);
+    for (int64_t e = 0; e < E; ++e)
+      for (int l = 0; l < 2; ++l) {
+        const int32_t v = d->cell_vertices[e * 2 + l];
+        if (cnt[v] > 2 || (cnt[v] == 2 && (side[v] & (1 << l)))) {
+          free_mesh(m); set_error("a line's vertex must join the right end of one cell to the left end of another");
+          return CVW_EINVAL;
+        }
+        side[v] |= static_cast<int8_t>(1 << l);
+      }
+  }
+
   // ---- DG face neighbours ----
   if (d->space == CVW_DG) {
     struct FK { int64_t key; int32_t ef; };
@@ -888,7 +1064,7 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     dent.assign(E * m->nloc, 0);
     std::vector<int32_t> fp(dptr.begin(), dptr.end() - 1);
     for (int64_t e = 0; e < E; ++e)
-      for (int j = 0; j < m->nloc; ++j) dent[fp[m->h_cell_dof[e * m->nloc + j]]++] = static_cast<int32_t>(e * 16 + j);
+      for (int j = 0; j < m->nloc; ++j) dent[fp[m->h_cell_dof[e * m->nloc + j]]++] = static_cast<int32_t>(e * m->nloc + j);
   }
   if (d->dim == 2) {
     geo.assign(E * 8, 0.0f);
@@ -939,6 +1115,7 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     std::vector<SegTables> t1(1);
     fill_seg_tables(t1[0], std::min(p, MAXP), d->space == CVW_CG);
     if ((st = upload(&m->d_segt, t1)) != CVW_OK) { free_mesh(m); return st; }
+    if ((st = upload(&m->d_hp, fill_hp_tables(p, d->space == CVW_CG))) != CVW_OK) { free_mesh(m); return st; }
   }
   if (d->cell == CVW_TRI && d->space == CVW_DG && p <= MAXP) {
     std::vector<double> gt(E * 8, 0.0);
@@ -1095,16 +1272,25 @@ static bool has_stage(const cvw_mesh* m) {
 // float64 scratch of the totals: block partials of up to four variables and the results
 constexpr size_t TOT_SCRATCH = (4 * 1024 + 4) * sizeof(double) + 224;
 
+// CG scratch: P_h grad u (2D: two components; 1D: one per variable) and the
+// element rows of every variable
+static size_t pg_elems(const cvw_mesh* m, const cvw_params* prm) {
+  return static_cast<size_t>(std::max(2, n_var(m, prm->flux))) * m->ndof;
+}
+static size_t rcell_elems(const cvw_mesh* m, const cvw_params* prm) {
+  return static_cast<size_t>(n_var(m, prm->flux)) * m->E * m->nloc;
+}
+
 static size_t cg_extra(const cvw_mesh* m, const cvw_params* prm, size_t es) {
   size_t b = 0;
-  if (m->space == CVW_CG)
-    b += align256(2 * static_cast<size_t>(m->ndof) * es) + align256(static_cast<size_t>(m->E) * m->nloc * es);
+  if (m->space == CVW_CG) b += align256(pg_elems(m, prm) * es) + align256(rcell_elems(m, prm) * es);
   if (m->n_mass > 0) {
-    // stage right-hand side R, and for CG the PCG vectors x, r, z, p, Ap and
-    // its block partials and scalars
-    b += align256(state_elems(m, n_var_of(prm->flux)) * es);
+    // stage right-hand side R, and for CG the PCG vectors x (every variable),
+    // r, z, p, Ap (one variable at a time) and its block partials and scalars
+    b += align256(state_elems(m, n_var(m, prm->flux)) * es);
     if (m->space == CVW_CG)
-      b += 5 * align256(static_cast<size_t>(m->ndof) * es) + align256((pcg_partials(m->ndof) + 8) * sizeof(double));
+      b += align256(state_elems(m, n_var(m, prm->flux)) * es) + 4 * align256(static_cast<size_t>(m->ndof) * es) +
+           align256((pcg_partials(m->ndof) + 8) * sizeof(double));
   }
   return b;
 }
@@ -1121,9 +1307,9 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
          align256(static_cast<size_t>(sensor_tiles(m)) * 16) + 256;
   if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG))
     b += align256(static_cast<size_t>(m->E) * 4);
-  if (op == 1) b += 2 * align256(state_elems(m, n_var_of(prm->flux)) * es);
+  if (op == 1) b += 2 * align256(state_elems(m, n_var(m, prm->flux)) * es);
   if (op == 2)    // limiter: vertex candidates of every variable, gamma, the selected cells and their count
-    b += align256(static_cast<size_t>(n_var_of(prm->flux)) * m->nk * m->Nv * es) +
+    b += align256(static_cast<size_t>(n_var(m, prm->flux)) * m->nk * m->Nv * es) +
          2 * align256(static_cast<size_t>(m->E) * 4) + 256 + align256(static_cast<size_t>(m->Nv)) +
          align256(static_cast<size_t>(m->Nv) * 4);
   return b;
@@ -1167,11 +1353,34 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
   }
   if (!dgq && !cgq && !seg) { set_error("this cell / space combination is not on the GPU path yet"); return CVW_EUNSUPPORTED; }
   if (seg) {
-    if (m->degree > MAXP) { set_error("degree > 3 not on the GPU path"); return CVW_EUNSUPPORTED; }
-    if (prm->flux != CVW_ADVECT_CONST && prm->flux != CVW_BURGERS) {
-      set_error("1D path: constant-velocity advection and Burgers only"); return CVW_EUNSUPPORTED;
+    if (prm->flux != CVW_ADVECT_CONST && prm->flux != CVW_BURGERS && prm->flux != CVW_EULER) {
+      set_error("1D path: constant-velocity advection, Burgers and the Euler equations"); return CVW_EUNSUPPORTED;
     }
-    if (m->space == CVW_DG && !m->closed) { set_error("1D DG residual needs a periodic mesh"); return CVW_EUNSUPPORTED; }
+    if (seg_hp(m, prm) && prm->dtype != CVW_F64) {
+      set_error("1D path: degrees above 3, the Euler equations and lines with ends run in float64");
+      return CVW_EUNSUPPORTED;
+    }
+    if (m->open_ends > 0) {
+      if (m->open_ends != 2) { set_error("a line has two ends"); return CVW_EINVAL; }
+      for (int e = 0; e < 2; ++e) {
+        const int b = prm->bc[e];
+        if (b != CVW_BC_OUTFLOW && b != CVW_BC_WALL && b != CVW_BC_INFLOW) {
+          set_error("a line with ends needs boundary data (outflow, wall or inflow) at both ends"); return CVW_EINVAL;
+        }
+        if (b == CVW_BC_WALL && prm->flux != CVW_EULER) {
+          set_error("a reflecting wall needs the Euler equations"); return CVW_EINVAL;
+        }
+        if (b == CVW_BC_INFLOW) {
+          const double* q = prm->bc_state[e];
+          bool ok = std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]);
+          if (prm->flux == CVW_EULER && ok) {
+            const double pr = (prm->flux_param[0] - 1.0) * (q[2] - 0.5 * q[1] * q[1] / q[0]);
+            ok = q[0] > 0.0 && pr > 0.0;
+          }
+          if (!ok) { set_error("inflow state not finite (or not of positive density and pressure)"); return CVW_EINVAL; }
+        }
+      }
+    }
   }
   if (cgq) {
     if (m->degree > 2) { set_error("CG quadrilaterals: degree <= 2 on the GPU path"); return CVW_EUNSUPPORTED; }
@@ -1220,15 +1429,17 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
   }
   if (m->space == CVW_CG) {
     w.pg = p;
-    p += align256(2 * static_cast<size_t>(m->ndof) * es);
+    p += align256(pg_elems(m, prm) * es);
     w.rcell = p;
-    p += align256(static_cast<size_t>(m->E) * m->nloc * es);
+    p += align256(rcell_elems(m, prm) * es);
   }
   if (m->n_mass > 0) {
     w.rhs = p;
-    p += align256(state_elems(m, n_var_of(prm->flux)) * es);
+    p += align256(state_elems(m, n_var(m, prm->flux)) * es);
     if (m->space == CVW_CG) {
-      void** vecs[5] = {&w.x, &w.r, &w.z, &w.p, &w.Ap};
+      w.x = p;
+      p += align256(state_elems(m, n_var(m, prm->flux)) * es);
+      void** vecs[4] = {&w.r, &w.z, &w.p, &w.Ap};
       for (void** v : vecs) {
         *v = p;
         p += align256(static_cast<size_t>(m->ndof) * es);
@@ -1253,7 +1464,7 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
     p += align256(static_cast<size_t>(m->E) * 4);
   }
   w.st1 = p;
-  p += align256(state_elems(m, n_var_of(prm->flux)) * es);
+  p += align256(state_elems(m, n_var(m, prm->flux)) * es);
   w.st2 = p;
   return w;
 }
@@ -1363,7 +1574,7 @@ cvw_status cvw_limit(const cvw_mesh* m, const cvw_params* prm, const void* u, vo
   }
   if (!u || !u_out) { set_error("null device pointer"); return CVW_EINVAL; }
   if (std::isnan(threshold)) { set_error("threshold is NaN"); return CVW_EINVAL; }
-  const int nv = n_var_of(prm->flux);
+  const int nv = n_var(m, prm->flux);
   {
     // u_out is u or a separate array: a partial overlap would be read after written
     const uintptr_t a = reinterpret_cast<uintptr_t>(u), b = reinterpret_cast<uintptr_t>(u_out);
@@ -1524,16 +1735,19 @@ cvw_status generic_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, 
   if (st != CVW_OK) return st;
   const bool f64 = std::is_same<Real, double>::value;
   const Real* dinv = f64 ? reinterpret_cast<const Real*>(m->d_dinv_d) : reinterpret_cast<const Real*>(m->d_dinv_f);
-  const int64_t n = static_cast<int64_t>(state_elems(m, n_var_of(prm->flux)));
+  const int64_t n = static_cast<int64_t>(state_elems(m, n_var(m, prm->flux)));
   if (m->space == CVW_CG) {
     Real* x = static_cast<Real*>(w.x);
-    st = cg_mass_solve<Real>(m, rhs, x, static_cast<Real*>(w.r), static_cast<Real*>(w.z), static_cast<Real*>(w.p),
-                             static_cast<Real*>(w.Ap), static_cast<Real*>(w.rcell), w.part, w.S, dinv,
-                             f64 ? PCG_TOL_F64 : PCG_TOL_F32, f64 ? PCG_MAXIT_F64 : PCG_MAXIT_F32, w.status, s);
-    if (st != CVW_OK) return st;
+    for (int v = 0; v < n_var(m, prm->flux); ++v) {      // the same mass matrix for every variable
+      st = cg_mass_solve<Real>(m, rhs + v * m->ndof, x + v * m->ndof, static_cast<Real*>(w.r),
+                               static_cast<Real*>(w.z), static_cast<Real*>(w.p), static_cast<Real*>(w.Ap),
+                               static_cast<Real*>(w.rcell), w.part, w.S, dinv, f64 ? PCG_TOL_F64 : PCG_TOL_F32,
+                               f64 ? PCG_MAXIT_F64 : PCG_MAXIT_F32, w.status, s);
+      if (st != CVW_OK) return st;
+    }
     return stage_update<Real>(us, un, x, nullptr, uo, a0, b0, dt, n, s);
   }
-  return stage_update<Real>(us, un, rhs, dinv, uo, a0, b0, dt, n, s);
+  return stage_update<Real>(us, un, rhs, dinv, uo, a0, b0, dt, n, s, m->n_mass);
 }
 
 cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, const void* us, const void* cand,
@@ -1674,7 +1888,7 @@ cvw_status cvw_totals(const cvw_mesh* m, const cvw_params* prm, const void* u, d
   if (m->space != CVW_DG || (m->cell != CVW_QUAD && m->cell != CVW_TRI)) {
     set_error("totals are implemented for DG quadrilaterals and triangles"); return CVW_EUNSUPPORTED;
   }
-  const int nv = n_var_of(prm->flux);
+  const int nv = n_var(m, prm->flux);
   const WS w = carve(m, prm, ws);
   double* part = w.tot;
   double* res = part + 4 * 1024;

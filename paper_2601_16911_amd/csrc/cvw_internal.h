@@ -290,6 +290,50 @@ struct alignas(16) BatchInst {
 };
 
 
+// One-dimensional elements of any degree 1 <= p <= HP_MAXP (float64): the
+// reference operators of the Lagrange basis at the mesh's nodes, built on the
+// host, in one array of doubles with these offsets:
+//   xq[n1], wq[n1]                  (p+1)-point Gauss rule on [-1, 1]
+//   DQ[m][j][q] = l_j^{(m)}(xq_q)   m = 0..p (lanes over q read consecutively)
+//   DV[v][j][m] = l_j^{(m)}(-1 / +1) v = 0 / 1
+//   DN[a][j]    = l_j'(x_a)         at the nodes
+constexpr int HP_MAXP = 32;
+constexpr int PCG_S_DONE = 5;      // index of the 'converged' flag among the mass solve's scalars
+struct HPOff {
+  int xq, wq, DQ, DV, DN, size;
+};
+__host__ __device__ inline HPOff hp_off(int p) {
+  const int n1 = p + 1;
+  HPOff o;
+  o.xq = 0;
+  o.wq = n1;
+  o.DQ = 2 * n1;
+  o.DV = o.DQ + n1 * n1 * n1;
+  o.DN = o.DV + 2 * n1 * n1;
+  o.size = o.DN + n1 * n1;
+  return o;
+}
+
+// Arguments of the 1D kernels of any degree: the mesh, the method and the
+// boundary data of the two ends of a line (index 0: the end at the left
+// vertex of its cell, 1: the right one).
+struct SegHPArgs {
+  const double* tab;                // hp_off(p) layout
+  const int32_t* cell_dof;          // CG [E][p+1]
+  const int32_t* cell_vtx;          // [E][2]
+  const int32_t* nbr;               // DG [E][2] face neighbours
+  const double* hcell;              // [E] cell lengths
+  const int32_t* vptr;              // vertex patches (CSR, entries cell * 4 + local vertex)
+  const int32_t* vent;
+  const int32_t* dptr;              // CG: DOF patches (CSR, entries cell * (p+1) + local node)
+  const int32_t* dent;
+  int64_t E, Nv, ndof;
+  int p, nv, flux, cg;
+  int bc[2];
+  double bcs[2][4];
+  MethodScalars ms;
+};
+
 }  // namespace cvw
 
 struct cvw_mesh {
@@ -298,6 +342,7 @@ struct cvw_mesh {
   int nloc = 0, nk = 0, nq = 0, ve = 0, nf = 0;
   int uniform = 0;
   int closed = 0;                    // DG: every face has a neighbour
+  int open_ends = 0;                 // segments: vertices used by one cell only (the ends of a line)
   int64_t grid_nx = 0, grid_ny = 0;  // DG quadrilaterals: structured periodic grid e = i + nx j (0: not)
   double hx = 0, hy = 0, he = 0;
   int device = 0;
@@ -318,7 +363,7 @@ struct cvw_mesh {
   // CG
   int32_t* d_cell_dof = nullptr;     // [E][nloc]
   int32_t* d_dof_ptr = nullptr;      // [ndof + 1] CSR of the DOF patches
-  int32_t* d_dof_ent = nullptr;      // [E * nloc] packed cell * 16 + local node, ascending (cell, node)
+  int32_t* d_dof_ent = nullptr;      // [E * nloc] cell * nloc + local node, ascending (cell, node)
   float* d_geo = nullptr;            // [E][8] vertex 0 and the other vertices relative to it
   float* d_he = nullptr;             // [E] diam K_e
   cvw::CGTables cgt{};
@@ -326,6 +371,7 @@ struct cvw_mesh {
   // 1D
   double* d_hcell = nullptr;          // [E] cell length
   cvw::SegTables* d_segt = nullptr;
+  double* d_hp = nullptr;             // reference operators of any degree (hp_off layout)
   // time stepping: inverse of the lumped CG mass (PCG preconditioner) or of
   // the exact diagonal 1D DG mass, in both precisions
   // triangles
@@ -341,7 +387,7 @@ namespace cvw {
 
 void set_error(const std::string& msg);
 MethodScalars make_scalars(const cvw_params* prm);
-int n_var_of(int flux);
+int n_var(const cvw_mesh* m, int flux);   // conserved variables: 1, or dim + 2 for the Euler equations
 
 // kernel launchers (cvw_dgquad.hip)
 cvw_status dgquad_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand,
@@ -379,6 +425,17 @@ cvw_status cgquad_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const
 cvw_status seg_candidates(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand, hipStream_t s);
 cvw_status seg_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const void* u, const void* cand, void* pg,
                     void* rcell, void* R, void* gamma, void* alpha, uint32_t* status, hipStream_t s);
+// 1D elements of any degree in float64, systems and lines with ends
+// (cvw_seghp.hip): the candidates of the sensor variable [Nv][p], the
+// evaluation (modes as seg_eval; pg [nv][ndof] and rcell [nv][E][p+1] are CG
+// scratch), the element mass products of the CG mass solve
+bool seg_hp(const cvw_mesh* m, const cvw_params* prm);
+SegHPArgs seghp_args(const cvw_mesh* m, const cvw_params* prm);
+cvw_status seghp_candidates(const cvw_mesh* m, const cvw_params* prm, const double* u, double* cand, hipStream_t s);
+cvw_status seghp_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const double* u, const double* cand,
+                      double* pg, double* rcell, double* R, double* gamma, double* alpha, uint32_t* status,
+                      hipStream_t s);
+void seghp_mass_cells(const cvw_mesh* m, const double* x, double* ycell, const double* S, hipStream_t s);
 // batched DG quadrilateral stage over many meshes (cvw_dgquad.hip): the
 // vertex pass is launched once per degree P, the cell pass once per (P, flux);
 // items are (instance, logical block) pairs of the instances of that class,
@@ -407,9 +464,10 @@ template <typename Real>
 cvw_status cg_mass_solve(const cvw_mesh* m, const Real* b, Real* x, Real* r, Real* z, Real* p, Real* Ap,
                          Real* ycell, double* part, double* S, const Real* dinv, double tol, int maxit,
                          uint32_t* status, hipStream_t s);
+// dinv (a diagonal mass of nm entries, shared by the variables) or null
 template <typename Real>
 cvw_status stage_update(const Real* us, const Real* un, const Real* x, const Real* dinv, Real* uo, double a0,
-                        double b0, double dt, int64_t n, hipStream_t s);
+                        double b0, double dt, int64_t n, hipStream_t s, int64_t nm = 0);
 cvw_status totals_f32(const cvw_mesh* m, int nvar, const float* u, double* partial, double* out_dev,
                       hipStream_t s);
 

@@ -1,6 +1,8 @@
 // One-dimensional CG (Gauss-Lobatto nodes) and DG (Gauss nodes) elements of
 // degree p <= 3 with the (p+1)-point Gauss volume rule, in float64 or float32,
-// on gfx950.  One thread per vertex / DOF / cell:
+// for scalar laws on closed lines (higher degrees, the Euler equations and
+// lines with ends go to the one-wave-per-cell kernels of cvw_seghp.hip).
+// One thread per vertex / DOF / cell:
 //
 //  * seg_vertex_kernel   -- Hermite data D^k u_h^e at the vertex from the two
 //    cells sharing it, Jiang-Shu weights, vertex candidate (eq. taylorcand);
@@ -99,8 +101,8 @@ __global__ __launch_bounds__(256) void seg_pg_kernel(const Real* __restrict__ u,
   const int beg = dptr[I], end = dptr[I + 1];
   for (int it = beg; it < end; ++it) {
     const int ent = dent[it];
-    const int64_t e = ent >> 4;
-    const int a = ent & 15;
+    const int64_t e = ent / (P + 1);
+    const int a = ent - static_cast<int>(e) * (P + 1);
     Real ue[P + 1];
     seg_load<P, Real, true>(u, cdof, e, ue);
     Real d = Real(0);
@@ -297,13 +299,13 @@ __global__ __launch_bounds__(128) void seg_cell_kernel(const Real* __restrict__ 
 template <typename Real>
 __global__ __launch_bounds__(256) void seg_assemble_kernel(const Real* __restrict__ rcell, Real* __restrict__ R,
                                                            const int32_t* __restrict__ dptr,
-                                                           const int32_t* __restrict__ dent, int nloc, int64_t ndof) {
+                                                           const int32_t* __restrict__ dent, int64_t ndof) {
   const int64_t I = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (I >= ndof) return;
   Real s = Real(0);
   for (int it = dptr[I]; it < dptr[I + 1]; ++it) {
     const int ent = dent[it];
-    s += rcell[static_cast<int64_t>(ent >> 4) * nloc + (ent & 15)];
+    s += rcell[ent];                      // ent = cell * nloc + local node
   }
   R[I] = s;
 }
@@ -336,6 +338,8 @@ static cvw_status seg_cand_r(const cvw_mesh* m, const MethodScalars& ms, const v
 }
 
 cvw_status seg_candidates(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand, hipStream_t s) {
+  if (seg_hp(m, prm))
+    return seghp_candidates(m, prm, static_cast<const double*>(u), static_cast<double*>(cand), s);
   const MethodScalars ms = make_scalars(prm);
   const cvw_status st = prm->dtype == CVW_F64 ? seg_cand_r<double>(m, ms, u, cand, s)
                                               : seg_cand_r<float>(m, ms, u, cand, s);
@@ -360,7 +364,7 @@ static void seg_eval_l(const cvw_mesh* m, const MethodScalars& ms, int mode, con
     if (mode != MODE_SENSOR)
       hipLaunchKernelGGL((seg_assemble_kernel<Real>), dim3(nb1(m->ndof, 256)), dim3(256), 0, s,
                          static_cast<const Real*>(rcell), static_cast<Real*>(R), m->d_dof_ptr, m->d_dof_ent,
-                         m->nloc, m->ndof);
+                         m->ndof);
   }
 }
 
@@ -397,6 +401,10 @@ static cvw_status seg_eval_r(const cvw_mesh* m, const MethodScalars& ms, int flu
 
 cvw_status seg_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const void* u, const void* cand, void* pg,
                     void* rcell, void* R, void* gamma, void* alpha, uint32_t* status, hipStream_t s) {
+  if (seg_hp(m, prm))
+    return seghp_eval(m, prm, mode, static_cast<const double*>(u), static_cast<const double*>(cand),
+                      static_cast<double*>(pg), static_cast<double*>(rcell), static_cast<double*>(R),
+                      static_cast<double*>(gamma), static_cast<double*>(alpha), status, s);
   const MethodScalars ms = make_scalars(prm);
   const cvw_status st =
       prm->dtype == CVW_F64 ? seg_eval_r<double>(m, ms, prm->flux, mode, u, cand, pg, rcell, R, gamma, alpha, status, s)

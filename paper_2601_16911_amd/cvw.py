@@ -54,7 +54,8 @@ class ParamsC(C.Structure):
                 ("q_sensor", C.c_double), ("q_beta", C.c_double), ("lin_w_vertex", C.c_double),
                 ("c_gamma", C.c_double), ("lambda_global", C.c_double), ("sensor", C.c_int32),
                 ("audit_every", C.c_int32), ("fixed_gamma", C.c_double), ("sigma_ref", C.c_double),
-                ("mlp", C.c_void_p), ("audit_tol", C.c_double)]
+                ("mlp", C.c_void_p), ("audit_tol", C.c_double), ("bc", C.c_int32 * 2),
+                ("bc_state", (C.c_double * 4) * 2)]
 
 
 class BatchInstanceC(C.Structure):
@@ -162,6 +163,13 @@ def make_params(prm, dtype: int = F32, mlp=None, sigma_ref: float = 1.0, audit_e
     p.lambda_global = float(prm.lambda_global)
     p.sensor = int(prm.sensor)
     p.fixed_gamma = float(prm.fixed_gamma)
+    bc = getattr(prm, "bc", (0, 0))
+    bcs = getattr(prm, "bc_state", ((0.0,) * 4, (0.0,) * 4))
+    for e in range(2):
+        p.bc[e] = int(bc[e])
+        st = list(bcs[e]) + [0.0] * 4
+        for v in range(4):
+            p.bc_state[e][v] = float(st[v])
     return p
 
 
@@ -170,7 +178,7 @@ def _ptr(t):
 
 
 def _state_len(mesh, prm) -> int:
-    nv = 4 if prm.flux == 4 else 1
+    nv = mesh.n_var(prm.flux)
     i = mesh.info
     return nv * (i["n_dof"] if mesh.space == CG else i["n_cells"] * i["n_loc"])
 
@@ -236,6 +244,7 @@ class Mesh:
         self._buffer = device_buffer
         self._h = h
         self.degree, self.space = degree, space
+        self.dim = int(d.dim)
         info = MeshInfoC()
         _check(lib.cvw_mesh_get_info(h, C.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in MeshInfoC._fields_}
@@ -243,6 +252,10 @@ class Mesh:
     @property
     def handle(self):
         return self._h
+
+    def n_var(self, flux: int) -> int:
+        """Conserved variables of a flux on this mesh (Euler: dim + 2)."""
+        return self.dim + 2 if flux == EULER else 1
 
     def set_grid(self, blocks: int):
         """Blocks per launch of the DG quadrilateral cell pass (<= 0: default)."""

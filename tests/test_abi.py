@@ -26,7 +26,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(cvw.SYMBOLS)
-    assert lib.cvw_abi_version() == 7
+    assert lib.cvw_abi_version() == 8
 
 
 def test_struct_layouts_match_header():
@@ -35,10 +35,11 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "cvw.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(cvw_params), sizeof(cvw_mesh_desc),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(cvw_params), sizeof(cvw_mesh_desc),
          sizeof(cvw_mesh_info), offsetof(cvw_params, fixed_gamma), offsetof(cvw_mesh_desc, periodic),
          offsetof(cvw_mesh_info, hx), offsetof(cvw_params, mlp), sizeof(cvw_batch_instance),
-         offsetof(cvw_batch_instance, dt), offsetof(cvw_mesh_info, grid_ny));
+         offsetof(cvw_batch_instance, dt), offsetof(cvw_mesh_info, grid_ny), offsetof(cvw_params, bc),
+         offsetof(cvw_params, bc_state));
   return 0;
 }
 '''
@@ -52,7 +53,7 @@ int main(void) {
     exp = [C.sizeof(cvw.ParamsC), C.sizeof(cvw.MeshDescC), C.sizeof(cvw.MeshInfoC),
            cvw.ParamsC.fixed_gamma.offset, cvw.MeshDescC.periodic.offset, cvw.MeshInfoC.hx.offset,
            cvw.ParamsC.mlp.offset, C.sizeof(cvw.BatchInstanceC), cvw.BatchInstanceC.dt.offset,
-           cvw.MeshInfoC.grid_ny.offset]
+           cvw.MeshInfoC.grid_ny.offset, cvw.ParamsC.bc.offset, cvw.ParamsC.bc_state.offset]
     assert got == exp
 
 
@@ -71,6 +72,10 @@ def test_params_defaults_marshal():
     p = cvw.make_params(synth.Params())
     assert p.eps_vertex == 1e-6 and p.eps_cell == 1e-6 and p.r == 2 and p.c_gamma == 0.9
     assert p.lin_w_vertex == 1e-3 and p.sc_on == 1 and p.q_sensor == 1.0
+    assert list(p.bc) == [0, 0]
+    q = cvw.make_params(synth.modified_sod_params(), cvw.F64)
+    assert list(q.bc) == [synth.BC_INFLOW, synth.BC_WALL]
+    assert list(q.bc_state[0])[:3] == pytest.approx([1.0, 0.75, 1.0 / 0.4 + 0.5 * 0.75 ** 2], rel=1e-15)
 
 
 def test_mesh_plan_without_gpu():
