@@ -254,9 +254,12 @@ cvw_status cvw_positivity(const cvw_mesh* mesh, const cvw_params* prm, const voi
 
 /* Stabilised residual R of M dU/dt = -R (eq. stabform / sdstab): Galerkin
  * volume term, the blended stabilisation s_h with nonlinear quadrature
- * weights, DG interface fluxes (LLF / HLL), CG assembly.  R has the state's
- * layout and precision and must not alias u.  gamma_out: device [n_cells] or
- * NULL. */
+ * weights, DG interface fluxes (LLF / HLL), CG assembly, and on lines with
+ * ends the boundary terms of prm->bc.  R has the state's layout and precision
+ * and must not alias u.  gamma_out: device [n_cells] or NULL.
+ * Segments: scalar laws of degree <= 3 on closed lines in float32 or
+ * float64; degrees up to 32, the Euler equations (rho, m, E) and lines with
+ * ends in float64 only (CVW_EUNSUPPORTED otherwise). */
 cvw_status cvw_residual(const cvw_mesh* mesh, const cvw_params* prm, const void* u, void* R,
                         void* gamma_out, void* ws, size_t ws_bytes, void* stream);
 
