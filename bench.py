@@ -382,13 +382,14 @@ def bench_ensemble(torch, cvw, steps: int, tune: bool = True):
     the batched stage, graph-captured and eager."""
     import synth
     stream = torch.cuda.current_stream()
-    items, dofs = [], 0
+    items, dofs, cells = [], 0, 0
     for inst in synth.config5_instances():
         mesh, p, prm, U, dt = synth.instance_case(inst)
         gm = cvw.Mesh(mesh, p, cvw.DG)
         u = torch.from_numpy(np.asarray(U, np.float32)).cuda()
         items.append((gm, cvw.make_params(prm), u, dt))
         dofs += U.size
+        cells += mesh.n_cells
     b = cvw.Batch(items)
     ws = b.alloc_workspace()
     grid = 0
@@ -407,6 +408,17 @@ def bench_ensemble(torch, cvw, steps: int, tune: bool = True):
         t = _timed(torch, stream, lambda: b.step(steps, ws, use_graph=graph), 1) / steps
         out[name] = {"value": 3.0 * dofs / t, "unit": "DOF-updates/s", "ms_per_step": t * 1e3}
     out["status_flags"] = b.poll_status(ws)
+    # compulsory bytes per step: per stage the sensor pass reads the stage
+    # state and writes gamma, the cell pass reads the stage state and gamma and
+    # writes the next state, and stages 2 and 3 read u_n: (3 + 2/3) x 4 B per
+    # DOF and 8 B per cell, three stages
+    alg = 3.0 * ((3.0 + 2.0 / 3.0) * 4.0 * dofs + 8.0 * cells)
+    t = out["graph"]["ms_per_step"] * 1e-3
+    out["roofline"] = {"bound": "alu", "hbm_bytes_per_step": alg, "hbm_achieved_GBs": alg / t / 1e9,
+                       "hbm_peak_GBs": 8000.0, "hbm_frac": alg / t / 8e12,
+                       "note": "the cell pass (82 % of the step) is bound by vector instruction issue per cell: "
+                               "one variable per cell leaves the per-cell sensor, face and weight work "
+                               "unshared, and degree-2 cells use 9 of the 16 lanes of a row"}
     return out
 
 
@@ -560,6 +572,46 @@ def bench_small_configs(torch, cvw):
     return out
 
 
+def _line_nodes(p: int, space: int):
+    """Reference nodes of the 1D elements: Gauss points (DG) or Gauss-Lobatto
+    points (CG), ascending."""
+    if space == 1:
+        return np.polynomial.legendre.leggauss(p + 1)[0]
+    inner = np.sort(np.polynomial.legendre.Legendre.basis(p).deriv().roots().real)
+    return np.concatenate([[-1.0], inner, [1.0]])
+
+
+def bench_line_euler(torch, cvw, steps: int = 20):
+    """1D Euler on the modified shock tube (inflow at x = 0, reflecting wall at
+    x = 1, float64): the paper's extreme degree, p = 32 on eight elements (CG
+    and DG), and DG p = 8 on 4096 cells; SSP-RK3 steps of dt = 0.1 h / (2 p^2)."""
+    import synth
+    stream = torch.cuda.current_stream()
+    prm = synth.modified_sod_params()
+    out = {}
+    for space, p, N in ((cvw.CG, 32, 8), (cvw.DG, 32, 8), (cvw.DG, 8, 4096), (cvw.CG, 8, 4096)):
+        mesh = synth.segment_mesh(N, periodic=False)
+        gm = cvw.Mesh(mesh, p, space)
+        X = mesh.cell_coords[:, :, 0]
+        xn = X[:, :1] + (X[:, 1:] - X[:, :1]) * (_line_nodes(p, space)[None, :] + 1.0) / 2.0
+        left = xn < 0.25
+        U = np.stack(synth.euler1d_conserved(np.where(left, 1.0, 0.125), np.where(left, 0.75, 0.0),
+                                             np.where(left, 1.0, 0.1)))
+        U = np.concatenate([_cg_gather(gm, U[c]) for c in range(3)]) if space == cvw.CG else U.reshape(-1)
+        u = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+        cp = cvw.make_params(prm, cvw.F64)
+        ws = cvw.alloc_workspace(gm, cp, 1)
+        dt = 0.1 * (1.0 / N) / (2.0 * p * p)
+        cvw.step(gm, cp, u, dt, 2, ws)                       # warm-up
+        t = _timed(torch, stream, lambda: cvw.step(gm, cp, u, dt, steps, ws), 1) / steps
+        name = f"line_euler_{'cg' if space == cvw.CG else 'dg'}_p{p}_{N}"
+        out[name] = {"workload": f"1D Euler, modified shock tube (inflow / wall), {'CG' if space == cvw.CG else 'DG'} "
+                                 f"P{p} on {N} cells, float64", "dofs": u.numel(), "us_per_stage": t / 3 * 1e6,
+                     "ms_per_step": t * 1e3, "value": 3 * u.numel() / t, "unit": "DOF-updates/s",
+                     "status_flags": cvw.poll_status(gm, ws)}
+    return out
+
+
 def _cg_gather(gm, vals):
     """Global CG vector from values at every cell's local nodes [E, n_loc]
     (the first occurrence of each DOF in (cell, local node) order)."""
@@ -584,9 +636,10 @@ def main():
                     help="also run one 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch shapes (no autotuner launches before the timed region)")
-    ap.add_argument("--part", choices=("step", "sensor", "learned"), default="step",
+    ap.add_argument("--part", choices=("step", "sensor", "learned", "small"), default="step",
                     help="sensor / learned: only the plain or learned sensor pass, --steps calls after --warmup "
-                         "(a short program for kernel traces and counters)")
+                         "(a short program for kernel traces and counters); small: only the 1D and CG "
+                         "rotation workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is benchmarked on one MI355X; "
@@ -598,6 +651,11 @@ def main():
     from paper_2601_16911_amd import cvw
 
     torch.cuda.set_device(0)
+    if args.part == "small":
+        out = bench_small_configs(torch, cvw)
+        out.update(bench_line_euler(torch, cvw))
+        print(json.dumps(out))
+        return
     if args.part != "step":
         print(json.dumps(sensor_only(torch, cvw, args.n, args.part, args.steps, args.warmup)))
         return
@@ -760,6 +818,7 @@ def main():
         out["triangles_kpp_2048"] = bench_triangles(torch, cvw, 2, n=2048, limiter=False)
         torch.cuda.empty_cache()
         out.update(bench_small_configs(torch, cvw))
+        out.update(bench_line_euler(torch, cvw))
         torch.cuda.empty_cache()
         out["hweno_limiter"] = bench_limiter(torch, cvw, gm, prm, U, dt)
         torch.cuda.empty_cache()

@@ -394,8 +394,13 @@ cvw_status cvw_mlp_train_step(cvw_mlp* mlp, const void* feat, const void* target
 /* ---------------------------------------------------------------------------
  * Batched time stepping of many independent problems (an ensemble of DG
  * meshes, Sec. 2 and Sec. 5 applied per instance): every SSP-RK3 stage of all
- * instances runs as one vertex pass per degree and one cell pass per
+ * instances runs as one sensor pass per degree and one cell pass per
  * (degree, flux), captured once into a HIP graph that is replayed per step.
+ * The sensor pass is the fused one of cvw_sensor for instances with the plain
+ * sensor on a structured periodic grid (gamma of the stage in the workspace,
+ * read by the cell pass), else the vertex pass (CVW_SENSOR_PATH=twopass when
+ * the batch is built selects it for every instance); each instance's result
+ * is bitwise that of its own cvw_step on the same path.
  * Instances: DG, congruent axis-aligned periodic quadrilaterals, p <= 3,
  * float32, scalar flux (constant advection, Burgers, KPP), each with its own
  * parameters and fixed dt.

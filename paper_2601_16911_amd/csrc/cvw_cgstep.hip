@@ -8,7 +8,8 @@
 // launch sequence returns at once.  No host synchronisation, so a stage can
 // be captured in a graph.  Preconditioner: the inverse row sums of M (the
 // integrals of the nodal basis functions; positive for Gauss-Lobatto nodes).
-// Dot products are reduced in float64 in a fixed order (deterministic).
+// Dot products are reduced in float64 in a fixed order (deterministic).  On
+// a line (segments) the same iteration runs inside one workgroup.
 //
 // 1D DG: Gauss nodes with the (p+1)-point Gauss rule make the element mass
 // exactly diagonal, so the stage divides by it directly.
@@ -18,7 +19,6 @@ namespace cvw {
 
 enum { S_RZ = 0, S_PAP = 1, S_RZ0 = 2, S_ALPHA = 3, S_BETA = 4, S_DONE = 5, S_TOL2 = 6, S_ITER = 7 };
 constexpr int PCG_THREADS = 256;
-static_assert(S_DONE == PCG_S_DONE, "mass-solve scalar layout");
 
 __device__ __forceinline__ bool pcg_done(const double* S) { return S[S_DONE] != 0.0; }
 
@@ -72,36 +72,6 @@ __global__ __launch_bounds__(128) void cgq_mass_kernel(const float* __restrict__
     }
 #pragma unroll
   for (int j = 0; j < NLOC; ++j) ycell[e * NLOC + j] = y[j];
-}
-
-// ycell_e = M_e x_e on segments (Gauss rule, exact)
-template <int P, typename Real>
-__global__ __launch_bounds__(128) void seg_mass_kernel(const Real* __restrict__ x, Real* __restrict__ ycell,
-                                                       const int32_t* __restrict__ cdof,
-                                                       const double* __restrict__ hcell,
-                                                       const SegTables* __restrict__ tab, int64_t E,
-                                                       const double* __restrict__ S) {
-  if (pcg_done(S)) return;
-  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (e >= E) return;
-  Real xe[P + 1], y[P + 1];
-#pragma unroll
-  for (int j = 0; j <= P; ++j) {
-    xe[j] = x[cdof[e * (P + 1) + j]];
-    y[j] = Real(0);
-  }
-  const Real jac = static_cast<Real>(0.5 * hcell[e]);
-#pragma unroll
-  for (int q = 0; q <= P; ++q) {
-    Real xq = Real(0);
-#pragma unroll
-    for (int j = 0; j <= P; ++j) xq = fma(static_cast<Real>(tab->D[0][q][j]), xe[j], xq);
-    const Real Wx = static_cast<Real>(tab->wq[q]) * jac * xq;
-#pragma unroll
-    for (int j = 0; j <= P; ++j) y[j] = fma(static_cast<Real>(tab->D[0][q][j]), Wx, y[j]);
-  }
-#pragma unroll
-  for (int j = 0; j <= P; ++j) ycell[e * (P + 1) + j] = y[j];
 }
 
 // Ap_I = sum of the element entries sharing I (ascending (cell, node) order);
@@ -241,34 +211,112 @@ __global__ __launch_bounds__(256) void stage_update_kernel(const Real* __restric
   uo[i] = base + b0 * (us[i] - dt * xi);
 }
 
+// The whole PCG solve of a line (segments) in one workgroup per variable
+// (workgroup v: variable v; every vector is [n_var][ndof]): the same
+// iteration, tolerance and cap as the launch sequence above, with the phases
+// separated by workgroup barriers instead of kernel launches (a 1D mesh has
+// at most a few thousand DOFs, where the launch sequence costs ~3 us per
+// launch and the arithmetic well under that).  The element mass is
+// (h_e / 2) M_ref with M_ref = sum_q w_q l_i(x_q) l_j(x_q), formed in LDS from
+// the tables of any degree.  Dot products: per-thread partials in a fixed
+// stride order, then a fixed tree.
+constexpr int SMALL_THREADS = 1024;
+
+__device__ __forceinline__ double wg_sum(double v, double* sh) {
+  __syncthreads();
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = SMALL_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+template <typename Real>
+__global__ __launch_bounds__(SMALL_THREADS) void pcg_line_kernel(
+    const Real* __restrict__ b, Real* __restrict__ x, Real* __restrict__ r, Real* __restrict__ z,
+    Real* __restrict__ p, Real* __restrict__ Ap, Real* __restrict__ ycell, const Real* __restrict__ dinv,
+    const double* __restrict__ tab, const double* __restrict__ hcell, const int32_t* __restrict__ cdof,
+    const int32_t* __restrict__ dptr, const int32_t* __restrict__ dent, int deg, int64_t E, int64_t n, double tol2,
+    int maxit, uint32_t* __restrict__ status) {
+  __shared__ double sh[SMALL_THREADS];
+  __shared__ double Mref[(HP_MAXP + 1) * (HP_MAXP + 1)];
+  const int tid = threadIdx.x;
+  {
+    const int64_t off = static_cast<int64_t>(blockIdx.x) * n;   // this workgroup's variable
+    b += off; x += off; r += off; z += off; p += off; Ap += off;
+    ycell += static_cast<int64_t>(blockIdx.x) * E * (deg + 1);
+  }
+  const int n1 = deg + 1;
+  const HPOff o = hp_off(deg);
+  for (int w = tid; w < n1 * n1; w += SMALL_THREADS) {
+    const int i = w / n1, j = w - i * n1;
+    double s = 0.0;
+    for (int q = 0; q < n1; ++q) s += tab[o.wq + q] * tab[o.DQ + i * n1 + q] * tab[o.DQ + j * n1 + q];
+    Mref[w] = s;
+  }
+  double d = 0.0;
+  for (int64_t i = tid; i < n; i += SMALL_THREADS) {
+    const Real bi = b[i];
+    const Real zi = dinv[i] * bi;
+    x[i] = Real(0);
+    r[i] = bi;
+    z[i] = zi;
+    p[i] = zi;
+    d += static_cast<double>(bi) * static_cast<double>(zi);
+  }
+  double rz = wg_sum(d, sh);
+  const double rz0 = rz;
+  bool done = !(rz > 0.0);
+  for (int it = 0; it < maxit && !done; ++it) {
+    for (int64_t w = tid; w < E * n1; w += SMALL_THREADS) {
+      const int64_t e = w / n1;
+      const int i = static_cast<int>(w - e * n1);
+      double y = 0.0;
+      for (int j = 0; j < n1; ++j) y += Mref[i * n1 + j] * static_cast<double>(p[cdof[e * n1 + j]]);
+      ycell[w] = static_cast<Real>(0.5 * hcell[e] * y);
+    }
+    __syncthreads();
+    d = 0.0;
+    for (int64_t I = tid; I < n; I += SMALL_THREADS) {
+      Real s = Real(0);
+      for (int k = dptr[I]; k < dptr[I + 1]; ++k) s += ycell[dent[k]];
+      Ap[I] = s;
+      d += static_cast<double>(p[I]) * static_cast<double>(s);
+    }
+    const double al = rz / wg_sum(d, sh);
+    d = 0.0;
+    for (int64_t i = tid; i < n; i += SMALL_THREADS) {
+      x[i] = fma(static_cast<Real>(al), p[i], x[i]);
+      const Real ri = fma(static_cast<Real>(-al), Ap[i], r[i]);
+      const Real zi = dinv[i] * ri;
+      r[i] = ri;
+      z[i] = zi;
+      d += static_cast<double>(ri) * static_cast<double>(zi);
+    }
+    const double rzn = wg_sum(d, sh);
+    const double be = rzn / rz;
+    rz = rzn;
+    if (!(rzn > tol2 * rz0)) { done = true; break; }
+    for (int64_t i = tid; i < n; i += SMALL_THREADS) p[i] = fma(static_cast<Real>(be), p[i], z[i]);
+    __syncthreads();
+  }
+  if (tid == 0 && !done) atomicOr(status, ST_PCG_STALL);
+}
+
 static unsigned nbk(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
 
 template <typename Real>
 static void mass_cells(const cvw_mesh* m, const Real* x, Real* ycell, const double* S, hipStream_t s) {
+  // CG quadrilaterals (float32); lines take pcg_line_kernel
   const dim3 g(nbk(m->E, 128)), b(128);
-  if (m->cell == CVW_QUAD) {
-    if constexpr (std::is_same<Real, float>::value) {
-      if (m->degree == 1)
-        hipLaunchKernelGGL(cgq_mass_kernel<1>, g, b, 0, s, x, ycell, m->d_cell_dof, m->d_geo, m->d_cgt, m->E, S);
-      else
-        hipLaunchKernelGGL(cgq_mass_kernel<2>, g, b, 0, s, x, ycell, m->d_cell_dof, m->d_geo, m->d_cgt, m->E, S);
-    }
-    return;
-  }
-  if (m->degree > MAXP) {               // any degree: one wave per cell, float64
-    if constexpr (std::is_same<Real, double>::value) seghp_mass_cells(m, x, ycell, S, s);
-    return;
-  }
-  switch (m->degree) {
-    case 1:
-      hipLaunchKernelGGL((seg_mass_kernel<1, Real>), g, b, 0, s, x, ycell, m->d_cell_dof, m->d_hcell, m->d_segt, m->E, S);
-      break;
-    case 2:
-      hipLaunchKernelGGL((seg_mass_kernel<2, Real>), g, b, 0, s, x, ycell, m->d_cell_dof, m->d_hcell, m->d_segt, m->E, S);
-      break;
-    default:
-      hipLaunchKernelGGL((seg_mass_kernel<3, Real>), g, b, 0, s, x, ycell, m->d_cell_dof, m->d_hcell, m->d_segt, m->E, S);
-      break;
+  if constexpr (std::is_same<Real, float>::value) {
+    if (m->degree == 1)
+      hipLaunchKernelGGL(cgq_mass_kernel<1>, g, b, 0, s, x, ycell, m->d_cell_dof, m->d_geo, m->d_cgt, m->E, S);
+    else
+      hipLaunchKernelGGL(cgq_mass_kernel<2>, g, b, 0, s, x, ycell, m->d_cell_dof, m->d_geo, m->d_cgt, m->E, S);
   }
 }
 
@@ -277,8 +325,14 @@ size_t pcg_partials(int64_t n) { return nbk(n, PCG_THREADS); }
 template <typename Real>
 cvw_status cg_mass_solve(const cvw_mesh* m, const Real* b, Real* x, Real* r, Real* z, Real* p, Real* Ap,
                          Real* ycell, double* part, double* S, const Real* dinv, double tol, int maxit,
-                         uint32_t* status, hipStream_t s) {
+                         uint32_t* status, hipStream_t s, int nvar) {
   const int64_t n = m->ndof;
+  if (m->cell == CVW_SEG) {            // a line: the whole solve in one workgroup per variable
+    hipLaunchKernelGGL((pcg_line_kernel<Real>), dim3(nvar), dim3(SMALL_THREADS), 0, s, b, x, r, z, p, Ap, ycell, dinv,
+                       m->d_hp, m->d_hcell, m->d_cell_dof, m->d_dof_ptr, m->d_dof_ent, m->degree, m->E, n,
+                       tol * tol, maxit, status);
+    return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+  }
   const int nb = static_cast<int>(nbk(n, PCG_THREADS));
   const dim3 g(nb), t(PCG_THREADS);
   hipLaunchKernelGGL(pcg_setup_kernel, dim3(1), dim3(64), 0, s, S, tol * tol);
@@ -307,10 +361,10 @@ cvw_status stage_update(const Real* us, const Real* un, const Real* x, const Rea
 
 template cvw_status cg_mass_solve<float>(const cvw_mesh*, const float*, float*, float*, float*, float*, float*,
                                          float*, double*, double*, const float*, double, int, uint32_t*,
-                                         hipStream_t);
+                                         hipStream_t, int);
 template cvw_status cg_mass_solve<double>(const cvw_mesh*, const double*, double*, double*, double*, double*,
                                           double*, double*, double*, double*, const double*, double, int,
-                                          uint32_t*, hipStream_t);
+                                          uint32_t*, hipStream_t, int);
 template cvw_status stage_update<float>(const float*, const float*, const float*, const float*, float*, double,
                                         double, double, int64_t, hipStream_t, int64_t);
 template cvw_status stage_update<double>(const double*, const double*, const double*, const double*, double*,

@@ -1265,10 +1265,10 @@ __global__ __launch_bounds__(256) void batch_eval_kernel(const BatchInst* __rest
     if constexpr (P == 1)
       dgq_eval_body_p1<FLUX>(I.u_in[stage], I.u, I.u_out[stage], nullptr, nullptr, I.cand, I.cell_vtx, I.nbr,
                              reinterpret_cast<const LaneRec1*>(sl), I.E, w.y, I.g, I.ms, MODE_STAGE, I.dt, a0, b0,
-                             I.status);
+                             I.status, I.gam);
     else
       dgq_eval_body<P, FLUX>(I.u_in[stage], I.u, I.u_out[stage], nullptr, nullptr, I.cand, I.cell_vtx, I.nbr, sl,
-                             tab, I.E, w.y, I.g, I.ms, MODE_STAGE, I.dt, a0, b0, I.status);
+                             tab, I.E, w.y, I.g, I.ms, MODE_STAGE, I.dt, a0, b0, I.status, I.gam);
   }
 }
 

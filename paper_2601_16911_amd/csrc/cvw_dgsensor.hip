@@ -373,17 +373,18 @@ __device__ __forceinline__ float cell_gamma(const float (&cf)[P + 1][P + 1], con
 // flag is set, and there only the cells whose gamma holds NaN (the learned
 // sensor's hand-over); the flag is cleared.  TILE_AUDIT: gamma is not written;
 // the block's sum and maximum of |gamma_plain - g_ref| go to part[2 lb + 0, 1].
+// One 16 x 16 tile lb of a mesh (the whole block); the block's threads call
+// it together (every exit is block-uniform).  The opening barrier lets a
+// block walk several tiles: the previous tile's readers of the LDS vertex
+// sums are done before this tile overwrites them.
 template <int P>
-__global__ __launch_bounds__(256, 4) void dgq_sensor_tile_kernel(const float* __restrict__ u, float* __restrict__ gamma,
-                                                              SensorTileArgs A, MethodScalars ms, int64_t nb_padded,
-                                                              int mode, uint8_t* __restrict__ tile_flag,
-                                                              const float* __restrict__ g_ref,
-                                                              double* __restrict__ part) {
+__device__ __forceinline__ void sensor_tile_body(const float* __restrict__ u, float* __restrict__ gamma,
+                                                 const SensorTileArgs& A, const MethodScalars& ms, int64_t lb,
+                                                 int mode, uint8_t* __restrict__ tile_flag,
+                                                 const float* __restrict__ g_ref, double* __restrict__ part) {
   constexpr int N1 = P + 1, NLOC = N1 * N1, NK = KSet<P>::NK;
-  constexpr KSet<P> ks = kset<P>;
   __shared__ float V[NK + 1][NVX * NVX];   // per vertex: sum w D^k (k < NK), sum w (NK)
-  const int64_t lb = xcd_block(blockIdx.x, nb_padded);
-  if (lb >= A.ntiles) return;                           // the whole block leaves
+  __syncthreads();
   if (mode == TILE_FALLBACK && tile_flag[lb] == 0) return;
   const int TI = static_cast<int>(lb % A.tiles_x), TJ = static_cast<int>(lb / A.tiles_x);
   const int i0 = TI * TS, j0 = TJ * TS;
@@ -497,6 +498,30 @@ __global__ __launch_bounds__(256, 4) void dgq_sensor_tile_kernel(const float* __
   gamma[e] = g;
 }
 
+template <int P>
+__global__ __launch_bounds__(256, 4) void dgq_sensor_tile_kernel(const float* __restrict__ u, float* __restrict__ gamma,
+                                                              SensorTileArgs A, MethodScalars ms, int64_t nb_padded,
+                                                              int mode, uint8_t* __restrict__ tile_flag,
+                                                              const float* __restrict__ g_ref,
+                                                              double* __restrict__ part) {
+  const int64_t lb = xcd_block(blockIdx.x, nb_padded);
+  if (lb >= A.ntiles) return;                           // the whole block leaves
+  sensor_tile_body<P>(u, gamma, A, ms, lb, mode, tile_flag, g_ref, part);
+}
+
+// Batched stages: the fused pass over the (instance, tile) items of every
+// instance of degree P, a fixed stride walk; each tile runs the single-mesh
+// body, so gamma is bitwise that of the single-mesh pass.
+template <int P>
+__global__ __launch_bounds__(256, 4) void batch_sensor_kernel(const BatchInst* __restrict__ inst,
+                                                           const int2* __restrict__ items, int n_items, int stage) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int2 w = items[it];
+    const BatchInst& I = inst[w.x];
+    sensor_tile_body<P>(I.u_in[stage], I.gam, I.sa, I.ms, w.y, TILE_ALL, nullptr, nullptr, nullptr);
+  }
+}
+
 // Sum of the audit's block partials in a fixed order: out[0] = mean, out[1] =
 // largest |gamma_plain - gamma_learned| over the E cells; a mean above tol sets
 // the latch (status word 2: the plain sensor takes every cell from then on)
@@ -586,6 +611,19 @@ cvw_status dgquad_sensor_tile(const cvw_mesh* m, const cvw_params* prm, const fl
     case 1: hipLaunchKernelGGL(dgq_sensor_tile_kernel<1>, g, b, 0, s, u, gamma, A, ms, nb, mode, tile_flag, g_ref, part); break;
     case 2: hipLaunchKernelGGL(dgq_sensor_tile_kernel<2>, g, b, 0, s, u, gamma, A, ms, nb, mode, tile_flag, g_ref, part); break;
     case 3: hipLaunchKernelGGL(dgq_sensor_tile_kernel<3>, g, b, 0, s, u, gamma, A, ms, nb, mode, tile_flag, g_ref, part); break;
+    default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+cvw_status batch_sensor_pass(int P, const BatchInst* inst, const int2* items, int n_items, int stage, int grid,
+                             hipStream_t s) {
+  if (n_items <= 0) return CVW_OK;
+  const dim3 g(std::max(1, std::min(grid, n_items))), b(256);
+  switch (P) {
+    case 1: hipLaunchKernelGGL(batch_sensor_kernel<1>, g, b, 0, s, inst, items, n_items, stage); break;
+    case 2: hipLaunchKernelGGL(batch_sensor_kernel<2>, g, b, 0, s, inst, items, n_items, stage); break;
+    case 3: hipLaunchKernelGGL(batch_sensor_kernel<3>, g, b, 0, s, inst, items, n_items, stage); break;
     default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
   }
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;

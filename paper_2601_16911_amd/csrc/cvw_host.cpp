@@ -1285,12 +1285,11 @@ static size_t cg_extra(const cvw_mesh* m, const cvw_params* prm, size_t es) {
   size_t b = 0;
   if (m->space == CVW_CG) b += align256(pg_elems(m, prm) * es) + align256(rcell_elems(m, prm) * es);
   if (m->n_mass > 0) {
-    // stage right-hand side R, and for CG the PCG vectors x (every variable),
-    // r, z, p, Ap (one variable at a time) and its block partials and scalars
+    // stage right-hand side R, and for CG the PCG vectors x, r, z, p, Ap (every
+    // variable) and its block partials and scalars
     b += align256(state_elems(m, n_var(m, prm->flux)) * es);
     if (m->space == CVW_CG)
-      b += align256(state_elems(m, n_var(m, prm->flux)) * es) + 4 * align256(static_cast<size_t>(m->ndof) * es) +
-           align256((pcg_partials(m->ndof) + 8) * sizeof(double));
+      b += 5 * align256(state_elems(m, n_var(m, prm->flux)) * es) + align256((pcg_partials(m->ndof) + 8) * sizeof(double));
   }
   return b;
 }
@@ -1437,12 +1436,10 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
     w.rhs = p;
     p += align256(state_elems(m, n_var(m, prm->flux)) * es);
     if (m->space == CVW_CG) {
-      w.x = p;
-      p += align256(state_elems(m, n_var(m, prm->flux)) * es);
-      void** vecs[4] = {&w.r, &w.z, &w.p, &w.Ap};
+      void** vecs[5] = {&w.x, &w.r, &w.z, &w.p, &w.Ap};
       for (void** v : vecs) {
         *v = p;
-        p += align256(static_cast<size_t>(m->ndof) * es);
+        p += align256(state_elems(m, n_var(m, prm->flux)) * es);
       }
       w.part = reinterpret_cast<double*>(p);
       w.S = w.part + pcg_partials(m->ndof);
@@ -1738,13 +1735,11 @@ cvw_status generic_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, 
   const int64_t n = static_cast<int64_t>(state_elems(m, n_var(m, prm->flux)));
   if (m->space == CVW_CG) {
     Real* x = static_cast<Real*>(w.x);
-    for (int v = 0; v < n_var(m, prm->flux); ++v) {      // the same mass matrix for every variable
-      st = cg_mass_solve<Real>(m, rhs + v * m->ndof, x + v * m->ndof, static_cast<Real*>(w.r),
-                               static_cast<Real*>(w.z), static_cast<Real*>(w.p), static_cast<Real*>(w.Ap),
-                               static_cast<Real*>(w.rcell), w.part, w.S, dinv, f64 ? PCG_TOL_F64 : PCG_TOL_F32,
-                               f64 ? PCG_MAXIT_F64 : PCG_MAXIT_F32, w.status, s);
-      if (st != CVW_OK) return st;
-    }
+    st = cg_mass_solve<Real>(m, rhs, x, static_cast<Real*>(w.r), static_cast<Real*>(w.z), static_cast<Real*>(w.p),
+                             static_cast<Real*>(w.Ap), static_cast<Real*>(w.rcell), w.part, w.S, dinv,
+                             f64 ? PCG_TOL_F64 : PCG_TOL_F32, f64 ? PCG_MAXIT_F64 : PCG_MAXIT_F32, w.status, s,
+                             n_var(m, prm->flux));
+    if (st != CVW_OK) return st;
     return stage_update<Real>(us, un, x, nullptr, uo, a0, b0, dt, n, s);
   }
   return stage_update<Real>(us, un, rhs, dinv, uo, a0, b0, dt, n, s, m->n_mass);
@@ -1914,11 +1909,11 @@ struct cvw_batch {
   std::vector<cvw_params> prms;
   std::vector<void*> u;
   std::vector<double> dt;
-  std::vector<size_t> off_cand, off_st1, off_st2;
+  std::vector<size_t> off_cand, off_st1, off_st2, off_gam;   // off_gam 0: no fused sensor pass
   size_t ws_bytes = 0;
-  // work lists: vertex pass per degree, cell pass per (degree, flux)
+  // work lists: fused sensor pass and vertex pass per degree, cell pass per (degree, flux)
   struct List { int P = 0, flux = 0, n = 0; int2* d = nullptr; };
-  std::vector<List> vlists, elists;
+  std::vector<List> slists, vlists, elists;
   cvw::BatchInst* d_inst = nullptr;
   cvw::TensorTables* d_tabs = nullptr;            // [4], index = degree
   cvw::LaneRec* d_lanes = nullptr;                // [4][16]
@@ -1939,6 +1934,7 @@ static void batch_drop_graph(cvw_batch* b) {
 static void batch_free(cvw_batch* b) {
   if (!b) return;
   batch_drop_graph(b);
+  for (auto& l : b->slists) (void)hipFree(l.d);
   for (auto& l : b->vlists) (void)hipFree(l.d);
   for (auto& l : b->elists) (void)hipFree(l.d);
   (void)hipFree(b->d_inst);
@@ -1949,6 +1945,10 @@ static void batch_free(cvw_batch* b) {
 
 // one pass of every stage kernel on stream s (used eagerly and under capture)
 static cvw_status batch_launch_stage(const cvw_batch* b, int stage, hipStream_t s) {
+  for (const auto& l : b->slists) {
+    const cvw_status st = batch_sensor_pass(l.P, b->d_inst, l.d, l.n, stage, b->grid > 0 ? b->grid : l.n, s);
+    if (st != CVW_OK) return st;
+  }
   for (const auto& l : b->vlists) {
     const cvw_status st = batch_vertex_pass(l.P, b->d_inst, l.d, l.n, b->d_tabs, stage,
                                             b->grid > 0 ? b->grid : l.n, s);
@@ -1976,7 +1976,7 @@ static cvw_status batch_upload_descriptors(cvw_batch* b, void* ws) {
     I.u_in[1] = s1; I.u_out[1] = s2;
     I.u_in[2] = s2; I.u_out[2] = u;
     I.u = u;
-    I.cand = reinterpret_cast<float*>(base + b->off_cand[i]);
+    I.cand = b->off_cand[i] ? reinterpret_cast<float*>(base + b->off_cand[i]) : nullptr;
     I.cell_vtx = m->d_cell_vtx;
     I.nbr = m->d_nbr;
     I.vptr = m->d_vtx_ptr;
@@ -1990,6 +1990,8 @@ static cvw_status batch_upload_descriptors(cvw_batch* b, void* ws) {
     I.flux = b->prms[i].flux;
     I.status = reinterpret_cast<uint32_t*>(base);
     I.ms = make_scalars(&b->prms[i]);
+    I.gam = b->off_gam[i] ? reinterpret_cast<float*>(base + b->off_gam[i]) : nullptr;
+    if (I.gam) I.sa = make_sensor_tile_args(m);
   }
   CVW_HIP(hipMemcpy(b->d_inst, h.data(), h.size() * sizeof(BatchInst), hipMemcpyHostToDevice));
   return CVW_OK;
@@ -2005,7 +2007,7 @@ cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** ou
   (void)hipGetDevice(&b->device);
   size_t off = 256;
   struct Item { double cost; int inst, blk; };
-  std::vector<Item> vitems[MAXP + 1];
+  std::vector<Item> sitems[MAXP + 1], vitems[MAXP + 1];
   std::vector<Item> eitems[MAXP + 1][CVW_EULER + 1];
   for (int i = 0; i < n; ++i) {
     const cvw_mesh* m = inst[i].mesh;
@@ -2029,18 +2031,28 @@ cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** ou
     b->prms.push_back(*prm);
     b->u.push_back(inst[i].u);
     b->dt.push_back(inst[i].dt);
-    b->off_cand.push_back(off);
-    off += align256(static_cast<size_t>(m->Nv) * m->nk * 4);
+    // the plain sensor on a structured periodic grid takes the fused pass
+    // (gamma of the stage in the workspace), like a single instance's stage;
+    // otherwise the vertex candidates go through the workspace
+    const bool tile = use_tile(m, prm);
+    b->off_cand.push_back(tile ? 0 : off);
+    if (!tile) off += align256(static_cast<size_t>(m->Nv) * m->nk * 4);
+    b->off_gam.push_back(tile ? off : 0);
+    if (tile) off += align256(static_cast<size_t>(m->E) * 4);
     b->off_st1.push_back(off);
     off += align256(static_cast<size_t>(m->E) * m->nloc * 4);
     b->off_st2.push_back(off);
     off += align256(static_cast<size_t>(m->E) * m->nloc * 4);
     // estimated cost of a block: proportional to the nodes per cell
     const double c = static_cast<double>(m->nloc);
-    const int nvb = static_cast<int>((m->Nv + VTX_PER_BLOCK - 1) / VTX_PER_BLOCK);
     const int cpt = cells_per_tile(m->degree);
     const int neb = static_cast<int>((m->E + cpt - 1) / cpt);
-    for (int k = 0; k < nvb; ++k) vitems[m->degree].push_back({c, i, k});
+    if (tile) {
+      for (int64_t k = 0; k < sensor_tiles(m); ++k) sitems[m->degree].push_back({c, i, static_cast<int>(k)});
+    } else if (prm->sensor != CVW_SENSOR_FIXED) {
+      const int nvb = static_cast<int>((m->Nv + VTX_PER_BLOCK - 1) / VTX_PER_BLOCK);
+      for (int k = 0; k < nvb; ++k) vitems[m->degree].push_back({c, i, k});
+    }
     for (int k = 0; k < neb; ++k) eitems[m->degree][prm->flux].push_back({c, i, k});
   }
   b->ws_bytes = off;
@@ -2061,6 +2073,7 @@ cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** ou
   };
   cvw_status st;
   for (int P = MAXP; P >= 1; --P) {
+    if ((st = upload_list(sitems[P], P, 0, b->slists)) != CVW_OK) { batch_free(b); return st; }
     if ((st = upload_list(vitems[P], P, 0, b->vlists)) != CVW_OK) { batch_free(b); return st; }
     for (int f = 0; f <= CVW_EULER; ++f)
       if ((st = upload_list(eitems[P][f], P, f, b->elists)) != CVW_OK) { batch_free(b); return st; }

@@ -287,6 +287,8 @@ struct alignas(16) BatchInst {
   int P, flux;
   uint32_t* status;
   MethodScalars ms;
+  float* gam;                       // fused sensor pass: gamma of the stage [E] (null: vertex candidates)
+  SensorTileArgs sa;                // its tile arguments
 };
 
 
@@ -298,7 +300,6 @@ struct alignas(16) BatchInst {
 //   DV[v][j][m] = l_j^{(m)}(-1 / +1) v = 0 / 1
 //   DN[a][j]    = l_j'(x_a)         at the nodes
 constexpr int HP_MAXP = 32;
-constexpr int PCG_S_DONE = 5;      // index of the 'converged' flag among the mass solve's scalars
 struct HPOff {
   int xq, wq, DQ, DV, DN, size;
 };
@@ -426,16 +427,20 @@ cvw_status seg_candidates(const cvw_mesh* m, const cvw_params* prm, const void* 
 cvw_status seg_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const void* u, const void* cand, void* pg,
                     void* rcell, void* R, void* gamma, void* alpha, uint32_t* status, hipStream_t s);
 // 1D elements of any degree in float64, systems and lines with ends
-// (cvw_seghp.hip): the candidates of the sensor variable [Nv][p], the
+// (cvw_seghp.hip): the candidates of the sensor variable [Nv][p] and the
 // evaluation (modes as seg_eval; pg [nv][ndof] and rcell [nv][E][p+1] are CG
-// scratch), the element mass products of the CG mass solve
+// scratch)
 bool seg_hp(const cvw_mesh* m, const cvw_params* prm);
 SegHPArgs seghp_args(const cvw_mesh* m, const cvw_params* prm);
 cvw_status seghp_candidates(const cvw_mesh* m, const cvw_params* prm, const double* u, double* cand, hipStream_t s);
 cvw_status seghp_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const double* u, const double* cand,
                       double* pg, double* rcell, double* R, double* gamma, double* alpha, uint32_t* status,
                       hipStream_t s);
-void seghp_mass_cells(const cvw_mesh* m, const double* x, double* ycell, const double* S, hipStream_t s);
+// batched fused sensor pass over (instance, tile) items of degree P
+// (cvw_dgsensor.hip), and the tile arguments of a mesh
+cvw_status batch_sensor_pass(int P, const BatchInst* inst, const int2* items, int n_items, int stage, int grid,
+                             hipStream_t s);
+SensorTileArgs make_sensor_tile_args(const cvw_mesh* m);
 // batched DG quadrilateral stage over many meshes (cvw_dgquad.hip): the
 // vertex pass is launched once per degree P, the cell pass once per (P, flux);
 // items are (instance, logical block) pairs of the instances of that class,
@@ -460,10 +465,12 @@ cvw_status tri_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const fl
 cvw_status tri_totals(const cvw_mesh* m, int nvar, const float* u, double* partial, double* out_dev, hipStream_t s);
 // time stepping (cvw_cgstep.hip)
 size_t pcg_partials(int64_t n);
+// M x = b for every variable: lines solve all nvar variables at once (vectors
+// [nvar][ndof], ycell [nvar][E][n_loc]); quadrilaterals one variable (nvar 1)
 template <typename Real>
 cvw_status cg_mass_solve(const cvw_mesh* m, const Real* b, Real* x, Real* r, Real* z, Real* p, Real* Ap,
                          Real* ycell, double* part, double* S, const Real* dinv, double tol, int maxit,
-                         uint32_t* status, hipStream_t s);
+                         uint32_t* status, hipStream_t s, int nvar = 1);
 // dinv (a diagonal mass of nm entries, shared by the variables) or null
 template <typename Real>
 cvw_status stage_update(const Real* us, const Real* un, const Real* x, const Real* dinv, Real* uo, double a0,

@@ -23,7 +23,7 @@
 //    alpha_q (eqs. dissrateorig to alpha_prelim), the element residual (eq.
 //    sdstab) with interface and boundary fluxes.
 //  * hp_assemble_kernel -- CG: R_I = sum of the element rows sharing I.
-//  * hp_mass_kernel     -- CG: element products M_e x_e for the mass solve.
+// (The CG mass solve of a line runs in one workgroup, cvw_cgstep.hip.)
 #include "cvw_device.h"
 
 namespace cvw {
@@ -146,6 +146,7 @@ __global__ __launch_bounds__(64) void hp_vertex_kernel(SegHPArgs A, const double
     if (k <= p) {
       // derivatives annihilate constants: take them of the data relative to its first node
       const double u0 = su[0];
+#pragma unroll 8
       for (int j = 0; j < n1; ++j) H = fma(A.tab[o.DV + (lv * n1 + j) * n1 + k], su[j] - u0, H);
       hH = ipow(2.0, k) * H;               // h^k D^k s = 2^k d^k s / dxi^k
       H *= ipow(2.0 / h, k);
@@ -235,6 +236,7 @@ __global__ __launch_bounds__(64) void hp_cell_kernel(SegHPArgs A, const double* 
     hm2 *= h * h;
     double D = 0.0;
     const double* dq = A.tab + o.DQ + (m * n1) * n1 + q;
+#pragma unroll 8
     for (int j = 0; j < n1; ++j) D = fma(dq[j * n1], su[0][j] - u0, D);
     D = qok ? D * sm : 0.0;
     if (m == 1) du1 = D;
@@ -385,6 +387,7 @@ __global__ __launch_bounds__(64) void hp_cell_kernel(SegHPArgs A, const double* 
     for (int v = 0; v < 3; ++v) {
       if (v >= nv) break;
       double r = 0.0;
+#pragma unroll 8
       for (int qq = 0; qq < n1; ++qq) r = fma(d1[qq], sG[v][qq], r);
       if (sHas[0]) r = fma(l0, sF[0][v], r);
       if (sHas[1]) r = fma(l1, sF[1][v], r);
@@ -408,31 +411,6 @@ __global__ __launch_bounds__(256) void hp_assemble_kernel(SegHPArgs A, const dou
   }
 }
 
-// ycell_e = M_e x_e with the (p+1)-point Gauss rule (exact); S: the mass
-// solve's scalars, a converged solve skips the launch
-__global__ __launch_bounds__(64) void hp_mass_kernel(SegHPArgs A, const double* __restrict__ x,
-                                                     double* __restrict__ ycell, const double* __restrict__ S) {
-  __shared__ double sx[N1MAX], sw[N1MAX];
-  if (S[PCG_S_DONE] != 0.0) return;
-  const int64_t e = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int n1 = A.p + 1;
-  const HPOff o = hp_off(A.p);
-  if (lane < n1) sx[lane] = x[A.cell_dof[e * n1 + lane]];
-  __syncthreads();
-  if (lane < n1) {
-    double v = 0.0;
-    for (int j = 0; j < n1; ++j) v = fma(A.tab[o.DQ + j * n1 + lane], sx[j], v);
-    sw[lane] = A.tab[o.wq + lane] * 0.5 * A.hcell[e] * v;
-  }
-  __syncthreads();
-  if (lane < n1) {
-    double y = 0.0;
-    for (int qq = 0; qq < n1; ++qq) y = fma(A.tab[o.DQ + lane * n1 + qq], sw[qq], y);
-    ycell[e * n1 + lane] = y;
-  }
-}
-
 // ---------------------------------------------------------------------------
 static unsigned nbh(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
 
@@ -452,13 +430,6 @@ cvw_status seghp_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const 
   if (A.cg && mode != MODE_SENSOR)
     hipLaunchKernelGGL(hp_assemble_kernel, dim3(nbh(m->ndof, 256)), dim3(256), 0, s, A, rcell, R);
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
-}
-
-void seghp_mass_cells(const cvw_mesh* m, const double* x, double* ycell, const double* S, hipStream_t s) {
-  cvw_params prm{};
-  prm.dtype = CVW_F64;
-  const SegHPArgs A = seghp_args(m, &prm);
-  hipLaunchKernelGGL(hp_mass_kernel, dim3(static_cast<unsigned>(m->E)), dim3(64), 0, s, A, x, ycell, S);
 }
 
 }  // namespace cvw

@@ -2,9 +2,12 @@
 quadrilateral problems (mixed degree 1..3, advection / Burgers), through the
 C ABI.
 
-Every work item runs the block body of the single-mesh kernels of the
-two-pass sensor path, so a batch step must equal cvw_step of each instance
-alone on that path bit for bit, with or without the graph, for any grid size.  Graph replays are checked one by one against eager
+Every work item runs the block body of the single-mesh kernels (the fused
+sensor pass over 16 x 16 tiles and the cell pass with that gamma; or, with
+CVW_SENSOR_PATH=twopass when the batch is built, the vertex pass and the
+cell pass with its candidates), so a batch step must equal cvw_step of each
+instance alone on the same path bit for bit, with or without the graph, for
+any grid size.  Graph replays are checked one by one against eager
 launches, with eager work and synchronisations between them.  One instance is
 also checked stage by stage against the float64 oracle.
 """
@@ -61,15 +64,15 @@ def test_ensemble_mix():
     assert {c[2].flux for c in cases} == {synth.ADVECT_CONST, synth.BURGERS}
 
 
+@pytest.mark.parametrize("path", ["fused", "twopass"])
 @pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_step_equals_single_instances(use_graph, monkeypatch):
-    # the batch runs the two-pass sensor (vertex candidates, then the cell
-    # pass); the single meshes take the same path when told to
+def test_batch_step_equals_single_instances(use_graph, path, monkeypatch):
     cases = _ensemble()
-    monkeypatch.setenv("CVW_SENSOR_PATH", "twopass")
+    if path == "twopass":
+        monkeypatch.setenv("CVW_SENSOR_PATH", "twopass")
     ref = _single_steps(cases, 2)
-    monkeypatch.delenv("CVW_SENSOR_PATH")
     b, states = _batch(cases)
+    monkeypatch.delenv("CVW_SENSOR_PATH", raising=False)
     ws = b.alloc_workspace()
     b.step(2, ws, use_graph=use_graph)
     for k, (u, r) in enumerate(zip(states, ref)):

@@ -99,16 +99,15 @@ def test_tri_kpp_trajectory():
     assert _rel_l1(got, ref, 1)[0] <= 1e-2
 
 
-def test_full_ensemble_one_step_bitwise(monkeypatch):
+def test_full_ensemble_one_step_bitwise():
     """All 64 ensemble instances at their real sizes (64^2 .. 512^2 cells,
     41.6 M DOFs): one batched, graph-captured step equals each instance's own
-    cvw_step (on the batch's two-pass sensor path) bit for bit."""
+    cvw_step bit for bit (both take the fused sensor pass)."""
     cases = []
     for inst in synth.config5_instances():
         mesh, p, prm, U, dt = synth.instance_case(inst)
         cases.append((cvw.Mesh(mesh, p, cvw.DG), cvw.make_params(prm), np.asarray(U, np.float32), dt))
     assert sum(c[2].size for c in cases) == 41609216
-    monkeypatch.setenv("CVW_SENSOR_PATH", "twopass")
     singles = []
     for gm, cp, U, dt in cases:
         u = torch.from_numpy(U.copy()).cuda()
@@ -116,7 +115,6 @@ def test_full_ensemble_one_step_bitwise(monkeypatch):
         cvw.step(gm, cp, u, dt, 1, ws)
         singles.append(u)
         del ws
-    monkeypatch.delenv("CVW_SENSOR_PATH")
     states = [torch.from_numpy(U.copy()).cuda() for _, _, U, _ in cases]
     b = cvw.Batch([(gm, cp, u, dt) for (gm, cp, _, dt), u in zip(cases, states)])
     ws = b.alloc_workspace()
