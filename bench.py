@@ -636,10 +636,11 @@ def main():
                     help="also run one 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch shapes (no autotuner launches before the timed region)")
-    ap.add_argument("--part", choices=("step", "sensor", "learned", "small"), default="step",
+    ap.add_argument("--part", choices=("step", "sensor", "learned", "small", "tri"), default="step",
                     help="sensor / learned: only the plain or learned sensor pass, --steps calls after --warmup "
                          "(a short program for kernel traces and counters); small: only the 1D and CG "
-                         "rotation workloads")
+                         "rotation workloads; tri: only the KPP triangle residual on 2048 x 2048 squares, --steps "
+                         "calls")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is benchmarked on one MI355X; "
@@ -651,6 +652,9 @@ def main():
     from paper_2601_16911_amd import cvw
 
     torch.cuda.set_device(0)
+    if args.part == "tri":
+        print(json.dumps(bench_triangles(torch, cvw, args.steps, n=2048, limiter=False)))
+        return
     if args.part == "small":
         out = bench_small_configs(torch, cvw)
         out.update(bench_line_euler(torch, cvw))
