@@ -864,6 +864,7 @@ static void free_mesh(cvw_mesh* m) {
   (void)hipFree(m->d_hp);
   (void)hipFree(m->d_trit);
   (void)hipFree(m->d_geot);
+  (void)hipFree(m->d_geov);
   (void)hipFree(m->d_nbrf);
   (void)hipFree(m->d_dinv_f);
   (void)hipFree(m->d_dinv_d);
@@ -1131,6 +1132,20 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
       }
     }
     if ((st = upload(&m->d_geot, gt)) != CVW_OK) { free_mesh(m); return st; }
+    // the vertex pass reads each triangle from all three of its vertices: a
+    // 32-byte float32 record of what it needs (the inverse Jacobian and h_e)
+    std::vector<float> gv(E * 8, 0.0f);
+    for (int64_t e = 0; e < E; ++e) {
+      const double* g = gt.data() + e * 8;
+      const double det = g[2] * g[5] - g[4] * g[3];
+      float* o = gv.data() + e * 8;
+      o[0] = static_cast<float>(g[5] / det);       // A = J^{-1}, J = [[x1-x0, x2-x0], [y1-y0, y2-y0]]
+      o[1] = static_cast<float>(-g[4] / det);
+      o[2] = static_cast<float>(-g[3] / det);
+      o[3] = static_cast<float>(g[2] / det);
+      o[4] = static_cast<float>(g[6]);
+    }
+    if ((st = upload(&m->d_geov, gv)) != CVW_OK) { free_mesh(m); return st; }
     std::vector<int32_t> nf32(E * 3);
     for (int64_t i = 0; i < E * 3; ++i) nf32[i] = m->h_nbr[i] < 0 ? -1 : m->h_nbr[i] * 4 + m->h_nbr_face[i];
     if ((st = upload(&m->d_nbrf, nf32)) != CVW_OK) { free_mesh(m); return st; }

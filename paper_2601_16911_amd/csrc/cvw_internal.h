@@ -378,6 +378,7 @@ struct cvw_mesh {
   // triangles
   cvw::TriTables* d_trit = nullptr;
   double* d_geot = nullptr;           // [E][8] x0, y0, x1-x0, y1-y0, x2-x0, y2-y0, diam, 0
+  float* d_geov = nullptr;            // [E][8] vertex pass: inverse Jacobian A00, A01, A10, A11, diam, 0, 0, 0
   int32_t* d_nbrf = nullptr;          // [E][3] neighbour cell * 4 + its face
   float* d_dinv_f = nullptr;          // [n_mass]
   double* d_dinv_d = nullptr;         // [n_mass]

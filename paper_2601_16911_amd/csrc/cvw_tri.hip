@@ -283,7 +283,7 @@ template <int P>
 __global__ __launch_bounds__(256) void tri_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
                                                          const int32_t* __restrict__ vptr,
                                                          const int32_t* __restrict__ vent,
-                                                         const double* __restrict__ geot,
+                                                         const float4* __restrict__ geov,
                                                          const TriTables* __restrict__ tab, int64_t Nv,
                                                          MethodScalars ms) {
   constexpr int NLOC = (P + 1) * (P + 2) / 2, NK = NLOC - 1;
@@ -296,7 +296,10 @@ __global__ __launch_bounds__(256) void tri_vertex_kernel(const float* __restrict
     const int ent = vent[it];
     const int64_t e = ent >> 2;
     const int lv = ent & 3;
-    const TriGeo G = load_trigeo(geot, e);
+    const float4 ga = geov[2 * e], gb = geov[2 * e + 1];   // A (row major), h_e
+    const double A[2][2] = {{static_cast<double>(ga.x), static_cast<double>(ga.y)},
+                            {static_cast<double>(ga.z), static_cast<double>(ga.w)}};
+    const double h = static_cast<double>(gb.x);
     double uc[NLOC];
     const float* ue = u + e * NLOC;
     const double u0 = static_cast<double>(ue[0]);
@@ -310,11 +313,11 @@ __global__ __launch_bounds__(256) void tri_vertex_kernel(const float* __restrict
       for (int j = 1; j < NLOC; ++j) s = fma(tab->TV[lv][m][j], uc[j], s);
       R[m] = s;
     }
-    phys_from_ref<P>(G.A, R, H);
+    phys_from_ref<P>(A, R, H);
     // eq. (pointsnorm) with h of the cell whose polynomial is measured
     double hw[P];
-    order_weights<P>(G.h, hw);
-    const double beta0 = G.h * sqrt(weighted_sq<P>(H, hw));
+    order_weights<P>(h, hw);
+    const double beta0 = h * sqrt(weighted_sq<P>(H, hw));
     const double beta = ms.fast_exp ? beta0 : pow(beta0, static_cast<double>(ms.q_beta));
     const double wt = ms.fast_exp ? 1.0 / ((ms.eps_vd + beta) * (ms.eps_vd + beta))
                                   : pow(ms.eps_vd + beta, -static_cast<double>(ms.r));
@@ -662,9 +665,9 @@ cvw_status tri_candidates(const cvw_mesh* m, const cvw_params* prm, const float*
   const MethodScalars ms = make_scalars(prm);
   const dim3 g(nblk(m->Nv, 256)), b(256);
   switch (m->degree) {
-    case 1: hipLaunchKernelGGL(tri_vertex_kernel<1>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geot, m->d_trit, m->Nv, ms); break;
-    case 2: hipLaunchKernelGGL(tri_vertex_kernel<2>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geot, m->d_trit, m->Nv, ms); break;
-    case 3: hipLaunchKernelGGL(tri_vertex_kernel<3>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geot, m->d_trit, m->Nv, ms); break;
+    case 1: hipLaunchKernelGGL(tri_vertex_kernel<1>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, reinterpret_cast<const float4*>(m->d_geov), m->d_trit, m->Nv, ms); break;
+    case 2: hipLaunchKernelGGL(tri_vertex_kernel<2>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, reinterpret_cast<const float4*>(m->d_geov), m->d_trit, m->Nv, ms); break;
+    case 3: hipLaunchKernelGGL(tri_vertex_kernel<3>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, reinterpret_cast<const float4*>(m->d_geov), m->d_trit, m->Nv, ms); break;
     default: set_error("degree not supported on the GPU path"); return CVW_EUNSUPPORTED;
   }
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
