@@ -263,34 +263,19 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 // sqrtf costs a dozen instructions of range scaling and correction
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// sin and cos together (the KPP flux): Cody-Waite reduction by pi/2 in three
-// parts (k pi/2 exact for |k| < 2^11) and the Taylor polynomials of sin and cos
-// on [-pi/4, pi/4] to degrees 9 and 10 (truncation below 2e-9); about 7e-8
-// absolute error for |x| <= 200.  Beyond |x| = 1000 the library functions.
+// sin and cos together (the KPP flux): the hardware v_sin_f32 / v_cos_f32,
+// whose argument is in revolutions (valid within +-256 revolutions); the
+// scaling by 1/(2 pi) rounds the argument by 6e-8 relative, about 1e-6
+// absolute at |x| = 16.  Beyond |x| = 1000 the library functions.
 __device__ __forceinline__ void kpp_sincos(float x, float& s, float& c) {
   if (fabsf(x) > 1.0e3f) {
     s = sinf(x);
     c = cosf(x);
     return;
   }
-  const float k = rintf(x * 0.636619772f);                 // x 2 / pi
-  float r = fmaf(-k, 1.5703125f, x);
-  r = fmaf(-k, 4.83751297e-04f, r);
-  r = fmaf(-k, 7.54979013e-08f, r);
-  const float r2 = r * r;
-  float ps = fmaf(r2, 2.75573192e-06f, -1.98412698e-04f);  // 1/9!, -1/7!
-  ps = fmaf(ps, r2, 8.33333333e-03f);                      // 1/5!
-  ps = fmaf(ps, r2, -1.66666667e-01f);                     // -1/3!
-  const float sr = fmaf(ps * r2, r, r);
-  float pc = fmaf(r2, -2.75573192e-07f, 2.48015873e-05f);   // -1/10!, 1/8!
-  pc = fmaf(pc, r2, -1.38888889e-03f);                      // -1/6!
-  pc = fmaf(pc, r2, 4.16666667e-02f);                       // 1/4!
-  pc = fmaf(pc, r2, -0.5f);
-  const float cr = fmaf(pc, r2, 1.0f);
-  const int q = static_cast<int>(k) & 3;                    // quadrant
-  const float s0 = (q & 1) ? cr : sr, c0 = (q & 1) ? sr : cr;
-  s = (q & 2) ? -s0 : s0;
-  c = ((q + 1) & 2) ? -c0 : c0;
+  const float rev = x * 0.159154943f;
+  s = __builtin_amdgcn_sinf(rev);
+  c = __builtin_amdgcn_cosf(rev);
 }
 
 template <int FLUX> struct NVar { static constexpr int value = 1; };
