@@ -14,8 +14,9 @@
 // The sensor works on Taylor coefficients: the cell polynomial and the three
 // vertex candidates (Taylor polynomials about their vertices) are all written
 // as D^m v(x_0), |m| >= 1, about the cell's vertex 0, and each element
-// semi-norm (eq. snorm) is evaluated with the Stroud rule (exact: the
-// integrands have degree <= 2p - 2).  Reference tables are read with indices
+// semi-norm (eq. snorm) is a quadratic form in them whose entries are the
+// cell's moments about x_0 up to degree 2p - 2, taken once per cell with the
+// Stroud rule (exact for those degrees).  Reference tables are read with indices
 // that are uniform across a wavefront (scalar loads), except the neighbour-
 // face tables, which live in LDS.
 #include "cvw_device.h"
@@ -124,20 +125,73 @@ __device__ __forceinline__ double weighted_sq(const double* D, const double* hw)
   return s;
 }
 
-// ||v||_e^2 of eq. (snorm) for v given by its Taylor coefficients at x_0
+// Moments of the cell about x_0 (vertex 0): mu[midx(ax, ay)] = int_T (x - x0)^ax
+// (y - y0)^ay dx, ax + ay <= 2P - 2, from the Stroud rule (exact for them).
+__host__ __device__ constexpr int midx(int ax, int ay) { return (ax + ay) * (ax + ay + 1) / 2 + ay; }
+template <int P> constexpr int NMOM = (2 * P - 1) * (2 * P) / 2;
+
 template <int P>
-__device__ __forceinline__ double seminorm_sq(const double* t, const TriGeo& G, const double* hw,
-                                              const TriTables* __restrict__ tab) {
-  constexpr int NQ = (P + 1) * (P + 1), NK = (P + 1) * (P + 2) / 2 - 1;
+__device__ __forceinline__ void mom_add(double w, double dx, double dy, double* mu) {
+  double px[2 * P - 1], py[2 * P - 1];
+  px[0] = w;
+  py[0] = 1.0;
+#pragma unroll
+  for (int a = 1; a < 2 * P - 1; ++a) {
+    px[a] = px[a - 1] * dx;
+    py[a] = py[a - 1] * dy;
+  }
+#pragma unroll
+  for (int n = 0; n <= 2 * P - 2; ++n)
+#pragma unroll
+    for (int ay = 0; ay <= n; ++ay) mu[midx(n - ay, ay)] = fma(px[n - ay], py[ay], mu[midx(n - ay, ay)]);
+}
+
+template <int P>
+__device__ __forceinline__ void cell_moments(const TriGeo& G, const TriTables* __restrict__ tab, double* mu) {
+  constexpr int NQ = (P + 1) * (P + 1);
+#pragma unroll
+  for (int i = 0; i < NMOM<P>; ++i) mu[i] = 0.0;
   const double adet = fabs(G.det);
-  double s = 0.0;
 #pragma unroll 1
   for (int q = 0; q < NQ; ++q) {
     const double xi = tab->xqd[q], eta = tab->yqd[q];
-    double D[NK];
-    taylor_eval<P>(t, G.J[0][0] * xi + G.J[0][1] * eta, G.J[1][0] * xi + G.J[1][1] * eta, D);
-    s = fma(tab->wqd[q] * adet, weighted_sq<P>(D, hw), s);
+    mom_add<P>(tab->wqd[q] * adet, G.J[0][0] * xi + G.J[0][1] * eta, G.J[1][0] * xi + G.J[1][1] * eta, mu);
   }
+}
+
+// ||v||_e^2 of eq. (snorm), sum_m h^{2|m|-2} int_T |D^m v|^2, for v given by its
+// Taylor coefficients t at x_0: with D^m v(x) = sum_{k >= m} t_k (x - x0)^{k-m} / (k-m)!
+// every integral is a combination of the moments mu
+template <int P>
+__device__ __forceinline__ double seminorm_mom(const double* t, const double* mu, const double* hw) {
+  constexpr double ifct[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
+  double s = 0.0;
+#pragma unroll
+  for (int n = 1; n <= P; ++n)
+#pragma unroll
+    for (int j = 0; j <= n; ++j) {
+      const int mx = n - j, my = j;
+      double sm = 0.0;
+#pragma unroll
+      for (int n2 = n; n2 <= P; ++n2)
+#pragma unroll
+        for (int j2 = 0; j2 <= n2; ++j2) {
+          const int kx = n2 - j2, ky = j2;
+          if (kx < mx || ky < my) continue;
+          double inner = 0.0;
+#pragma unroll
+          for (int n3 = n; n3 <= P; ++n3)
+#pragma unroll
+            for (int j3 = 0; j3 <= n3; ++j3) {
+              const int lx = n3 - j3, ly = j3;
+              if (lx < mx || ly < my) continue;
+              inner = fma(t[kbase(n3) + j3] * (ifct[lx - mx] * ifct[ly - my]),
+                          mu[midx(kx - mx + lx - mx, ky - my + ly - my)], inner);
+            }
+          sm = fma(t[kbase(n2) + j2] * (ifct[kx - mx] * ifct[ky - my]), inner, sm);
+        }
+      s = fma(hw[n - 1], sm, s);
+    }
   return s;
 }
 
@@ -217,7 +271,9 @@ __global__ __launch_bounds__(256) void tri_limit_kernel(const float* __restrict_
     }
     phys_from_ref<P>(G.A, R, a);
   }
-  const double n2 = seminorm_sq<P>(a, G, hw, tab);
+  double mom[NMOM<P>];
+  cell_moments<P>(G, tab, mom);
+  const double n2 = seminorm_mom<P>(a, mom, hw);
   // weights of the cell candidate and the three vertex candidates
   const float* cv = cand + static_cast<int64_t>(v) * Nv * NK;
   const double qb = static_cast<double>(ms.q_beta), rr = static_cast<double>(ms.r);
@@ -236,7 +292,7 @@ __global__ __launch_bounds__(256) void tri_limit_kernel(const float* __restrict_
   for (int l = 0; l < 3; ++l) {
     double s[NK];
     candidate_at_x0<P>(cv, vtx[l], l, G, s);
-    wt[l + 1] = wfun(ms.lin_wd, seminorm_sq<P>(s, G, hw, tab));
+    wt[l + 1] = wfun(ms.lin_wd, seminorm_mom<P>(s, mom, hw));
     tot += wt[l + 1];
   }
   double cb[NK], wrest = 0.0;
@@ -346,8 +402,8 @@ __global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float*
   constexpr int NLOC = (P + 1) * (P + 2) / 2, NK = NLOC - 1, NQ = (P + 1) * (P + 1), NG = P + 1;
   constexpr int NV = NVar<FLUX>::value;
   __shared__ float sBf[3][NG][NLOC];
-  // per-thread values at the volume points: pointwise semi-norm and |grad s|^2
-  __shared__ float s_at[NQ][TRI_EVAL_THREADS], s_g2[NQ][TRI_EVAL_THREADS];
+  // per-thread pointwise semi-norm at the volume points (where SC is active)
+  __shared__ float s_at[NQ][TRI_EVAL_THREADS];
   const int tid = threadIdx.x;
   for (int t = threadIdx.x; t < 3 * NG * NLOC; t += blockDim.x) {
     const int f = t / (NG * NLOC), g = (t / NLOC) % NG, j = t % NLOC;
@@ -382,22 +438,12 @@ __global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float*
     }
     phys_from_ref<P>(G.A, R, a);
   }
-  double n2 = 0.0;
-#pragma unroll 1
-  for (int q = 0; q < NQ; ++q) {
-    const double xi = tab->xqd[q], eta = tab->yqd[q];
-    double D[NK];
-    taylor_eval<P>(a, G.J[0][0] * xi + G.J[0][1] * eta, G.J[1][0] * xi + G.J[1][1] * eta, D);
-    const double pq = weighted_sq<P>(D, hw);
-    n2 = fma(tab->wqd[q] * adet, pq, n2);
-    s_at[q][tid] = static_cast<float>(G.h * sqrt(pq));      // eq. (pointsnorm) at x_q
-    s_g2[q][tid] = static_cast<float>(D[0] * D[0] + D[1] * D[1]);
-  }
-
   // ---- sensor gamma_e (float64) ----
   double gam = ms.fixed_gammad;
   if (plain) {
-    const double n0 = sqrt(n2);
+    double mu[NMOM<P>];
+    cell_moments<P>(G, tab, mu);
+    const double n0 = sqrt(seminorm_mom<P>(a, mu, hw));
     const double qb = static_cast<double>(ms.q_beta), rr = static_cast<double>(ms.r);
     double beta[4];
     beta[0] = ms.fast_exp ? n0 : pow(n0, qb);
@@ -408,7 +454,7 @@ __global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float*
     for (int l = 0; l < 3; ++l) {
       double s[NK];
       candidate_at_x0<P>(cand, vtx[l], l, G, s);
-      const double nl = sqrt(seminorm_sq<P>(s, G, hw, tab));
+      const double nl = sqrt(seminorm_mom<P>(s, mu, hw));
       beta[l + 1] = ms.fast_exp ? nl : pow(nl, qb);
     }
     double wt[4], tot = 0.0;
@@ -430,7 +476,7 @@ __global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float*
 #pragma unroll
       for (int k = 0; k < NK; ++k) diff[k] = fma(om, a[k] - s[k], diff[k]);
     }
-    const double d = sqrt(seminorm_sq<P>(diff, G, hw, tab));
+    const double d = sqrt(seminorm_mom<P>(diff, mu, hw));
     if (n0 > 0.0) {
       const double ratio = fmin(1.0, d / n0);
       gam = 1.0 - (ms.q_sensor == 1.0f ? ratio : pow(ratio, static_cast<double>(ms.q_sensor)));
@@ -467,17 +513,24 @@ __global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float*
   }
   const float nu = lam * static_cast<float>(G.h) / (2.0f * P);
 
-  // ---- shock-capturing weights (eq. alphaq), from the sensor field ----
+  // ---- shock-capturing weights (eq. alphaq), from the sensor field: the
+  // derivatives at the volume points (float64) only in cells where they can
+  // be active (a wave whose cells all have gamma_e >= C_gamma skips them) ----
   bool sc_active = false;
   float ratio = 1.0f;
   if (ms.sc_on && gam < ms.c_gammad) {
     float S = 0.0f, T = 0.0f;
 #pragma unroll 1
     for (int q = 0; q < NQ; ++q) {
-      const float f = (1.0f - gf) * s_g2[q][tid];
+      const double xi = tab->xqd[q], eta = tab->yqd[q];
+      double D[NK];
+      taylor_eval<P>(a, G.J[0][0] * xi + G.J[0][1] * eta, G.J[1][0] * xi + G.J[1][1] * eta, D);
+      const float at = static_cast<float>(G.h * sqrt(weighted_sq<P>(D, hw)));   // eq. (pointsnorm) at x_q
+      s_at[q][tid] = at;
+      const float f = (1.0f - gf) * static_cast<float>(D[0] * D[0] + D[1] * D[1]);
       const float W = tab->wq[q] * fdet;
       S = fmaf(W, f, S);
-      T = fmaf(W * s_at[q][tid], f, T);
+      T = fmaf(W * at, f, T);
     }
     sc_active = S > 0.0f && T > 0.0f;
     if (sc_active) ratio = S / T;
