@@ -343,7 +343,9 @@ __global__ __launch_bounds__(256) void tri_vertex_kernel(const float* __restrict
                                                          const TriTables* __restrict__ tab, int64_t Nv,
                                                          MethodScalars ms) {
   constexpr int NLOC = (P + 1) * (P + 2) / 2, NK = NLOC - 1;
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  // XCD-aware order: each XCD walks a contiguous range of vertices, so the
+  // cells shared by neighbouring vertex rows are read again from its own L2
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= Nv) return;
   double num[NK], den = 0.0;
 #pragma unroll
@@ -410,7 +412,8 @@ __global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float*
     sBf[f][g][j] = tab->Bf[f][g][j];
   }
   __syncthreads();
-  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  // XCD-aware order (the neighbours across the next row of squares then share an L2)
+  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (e >= E) return;
   const int64_t stride = E * NLOC;
   float uv[NV][NLOC];
@@ -713,10 +716,12 @@ __global__ __launch_bounds__(256) void tri_totals_final(const double* __restrict
 
 // ---------------------------------------------------------------------------
 static unsigned nblk(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
+// block count rounded up to a multiple of 8 (the XCD-aware kernels; the extra blocks exit)
+static unsigned nblk8(int64_t n, int t) { return (nblk(n, t) + 7u) / 8u * 8u; }
 
 cvw_status tri_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s) {
   const MethodScalars ms = make_scalars(prm);
-  const dim3 g(nblk(m->Nv, 256)), b(256);
+  const dim3 g(nblk8(m->Nv, 256)), b(256);
   switch (m->degree) {
     case 1: hipLaunchKernelGGL(tri_vertex_kernel<1>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, reinterpret_cast<const float4*>(m->d_geov), m->d_trit, m->Nv, ms); break;
     case 2: hipLaunchKernelGGL(tri_vertex_kernel<2>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, reinterpret_cast<const float4*>(m->d_geov), m->d_trit, m->Nv, ms); break;
@@ -730,7 +735,7 @@ template <int P, int FLUX>
 static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
                         float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
                         float a0, float b0, hipStream_t s) {
-  hipLaunchKernelGGL((tri_eval_kernel<P, FLUX>), dim3(nblk(m->E, TRI_EVAL_THREADS)), dim3(TRI_EVAL_THREADS), 0, s, u, u0, out, gamma, alpha,
+  hipLaunchKernelGGL((tri_eval_kernel<P, FLUX>), dim3(nblk8(m->E, TRI_EVAL_THREADS)), dim3(TRI_EVAL_THREADS), 0, s, u, u0, out, gamma, alpha,
                      cand, m->d_cell_vtx, m->d_nbrf, m->d_geot, m->d_trit, m->E, ms, mode, dt, a0, b0, status);
 }
 
