@@ -17,9 +17,12 @@
  *   residual, sensor, workspace) are owned by the caller; they must be
  *   allocations on the current HIP device, 256-byte aligned and not aliased
  *   unless stated.  The library never allocates in the evaluation calls; only
- *   cvw_mesh_build allocates (the mesh's device arrays, freed by
- *   cvw_mesh_destroy; cvw_mesh_build_in puts them in a caller buffer instead),
- *   and the learned-sensor and batch handles their small descriptor arrays.
+ *   the handle constructors allocate: cvw_mesh_build (the mesh's device
+ *   arrays, freed by cvw_mesh_destroy), cvw_mlp_create (the network's
+ *   parameters and Adam state) and cvw_batch_build (descriptors, work lists,
+ *   tables).  Each has a variant that places them in a caller-owned device
+ *   buffer instead (cvw_mesh_build_in, cvw_mlp_create_in, cvw_batch_build_in,
+ *   sized by cvw_mesh_plan, cvw_mlp_device_bytes, cvw_batch_plan).
  * - `stream` is a hipStream_t (NULL = default stream).  Evaluation calls only
  *   enqueue work on it and return; argument errors are detected on the host
  *   before anything is enqueued.  Numerical trouble detected on the device
@@ -48,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 8
+#define CVW_ABI_VERSION 9
 
 typedef enum {
   CVW_OK = 0,
@@ -347,6 +350,12 @@ typedef struct cvw_mlp cvw_mlp;
 /* Creates a network on the current device from packed host parameters (read
  * during the call).  Adam moments start at zero. */
 cvw_status cvw_mlp_create(const float* params, cvw_mlp** out);
+/* The same network with its device memory in a caller-owned buffer (device,
+ * 256-byte aligned, at least cvw_mlp_device_bytes() bytes; it must outlive the
+ * handle and is not freed by cvw_mlp_destroy).  CVW_EINVAL for a null,
+ * misaligned or small buffer. */
+size_t cvw_mlp_device_bytes(void);
+cvw_status cvw_mlp_create_in(const float* params, void* device_buffer, size_t bytes, cvw_mlp** out);
 void cvw_mlp_destroy(cvw_mlp* mlp);
 /* Copies the float32 master parameters to / from host memory (synchronous);
  * set also resets the Adam state. */
@@ -419,6 +428,13 @@ typedef struct {
  * estimated cost and uploads the reference tables.  Host arrays are read during
  * the call only.  The batch handle owns its device descriptors. */
 cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** out);
+/* Device bytes the batch's arrays take (host work only; the same validation
+ * as cvw_batch_build), and the batch built with them in a caller-owned device
+ * buffer (256-byte aligned, at least that size; it must outlive the handle and
+ * is not freed by cvw_batch_destroy).  CVW_EINVAL for a small buffer. */
+cvw_status cvw_batch_plan(const cvw_batch_instance* inst, int n, size_t* device_bytes);
+cvw_status cvw_batch_build_in(const cvw_batch_instance* inst, int n, void* device_buffer, size_t bytes,
+                              cvw_batch** out);
 void cvw_batch_destroy(cvw_batch* batch);
 
 /* Workspace bytes for cvw_batch_step (256-byte aligned device buffer): a status

@@ -756,7 +756,7 @@ static thread_local MeshArena* g_arena = nullptr;
 
 static cvw_status dev_alloc(void** dst, size_t bytes) {
   if (!g_arena) {
-    if (hipMalloc(dst, bytes) != hipSuccess) { set_error("hipMalloc failed for mesh arrays"); return CVW_ENOMEM; }
+    if (hipMalloc(dst, bytes) != hipSuccess) { set_error("hipMalloc failed"); return CVW_ENOMEM; }
     return CVW_OK;
   }
   MeshArena& A = *g_arena;
@@ -767,7 +767,7 @@ static cvw_status dev_alloc(void** dst, size_t bytes) {
     return CVW_OK;
   }
   if (A.off + bytes > A.size) {
-    set_error("device buffer too small for the mesh (cvw_mesh_plan gives the size)");
+    set_error("device buffer too small (cvw_mesh_plan / cvw_batch_plan give the size)");
     return CVW_EINVAL;
   }
   *dst = A.base + A.off;
@@ -1243,6 +1243,7 @@ cvw_status cvw_mesh_export(const cvw_mesh* m, int which, void* dst, size_t bytes
 struct cvw_mlp {
   int device = 0;
   int64_t steps = 0;
+  int external = 0;                  // mem is the caller's buffer (cvw_mlp_create_in): not freed here
   void* mem = nullptr;
   float* master = nullptr;
   float* m1 = nullptr;
@@ -1919,6 +1920,7 @@ cvw_status cvw_totals(const cvw_mesh* m, const cvw_params* prm, const void* u, d
 struct cvw_batch {
   int n = 0;
   int device = 0;
+  int external = 0;                               // device arrays in a caller buffer (cvw_batch_build_in)
   int grid = 0;                                   // blocks per launch (<= 0: one per item)
   std::vector<const cvw_mesh*> meshes;
   std::vector<cvw_params> prms;
@@ -1949,12 +1951,14 @@ static void batch_drop_graph(cvw_batch* b) {
 static void batch_free(cvw_batch* b) {
   if (!b) return;
   batch_drop_graph(b);
-  for (auto& l : b->slists) (void)hipFree(l.d);
-  for (auto& l : b->vlists) (void)hipFree(l.d);
-  for (auto& l : b->elists) (void)hipFree(l.d);
-  (void)hipFree(b->d_inst);
-  (void)hipFree(b->d_tabs);
-  (void)hipFree(b->d_lanes);
+  if (!b->external) {
+    for (auto& l : b->slists) (void)hipFree(l.d);
+    for (auto& l : b->vlists) (void)hipFree(l.d);
+    for (auto& l : b->elists) (void)hipFree(l.d);
+    (void)hipFree(b->d_inst);
+    (void)hipFree(b->d_tabs);
+    (void)hipFree(b->d_lanes);
+  }
   delete b;
 }
 
@@ -2019,6 +2023,7 @@ cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** ou
   *out = nullptr;
   auto* b = new cvw_batch();
   b->n = n;
+  b->external = g_arena != nullptr;
   (void)hipGetDevice(&b->device);
   size_t off = 256;
   struct Item { double cost; int inst, blk; };
@@ -2101,11 +2106,40 @@ cvw_status cvw_batch_build(const cvw_batch_instance* inst, int n, cvw_batch** ou
   }
   if ((st = upload(&b->d_tabs, tabs)) != CVW_OK) { batch_free(b); return st; }
   if ((st = upload(&b->d_lanes, lanes)) != CVW_OK) { batch_free(b); return st; }
-  if (hipMalloc(reinterpret_cast<void**>(&b->d_inst), n * sizeof(BatchInst)) != hipSuccess) {
-    batch_free(b); set_error("hipMalloc failed"); return CVW_ENOMEM;
+  {
+    void* p = nullptr;
+    if ((st = dev_alloc(&p, n * sizeof(BatchInst))) != CVW_OK) { batch_free(b); return st; }
+    b->d_inst = static_cast<BatchInst*>(p);
   }
   *out = b;
   return CVW_OK;
+}
+
+cvw_status cvw_batch_plan(const cvw_batch_instance* inst, int n, size_t* device_bytes) {
+  if (!device_bytes) { set_error("null argument"); return CVW_EINVAL; }
+  MeshArena A;
+  A.count_only = true;
+  g_arena = &A;
+  cvw_batch* b = nullptr;
+  const cvw_status st = cvw_batch_build(inst, n, &b);
+  g_arena = nullptr;
+  if (st != CVW_OK) return st;
+  batch_free(b);
+  *device_bytes = (A.off + 255) / 256 * 256;
+  return CVW_OK;
+}
+
+cvw_status cvw_batch_build_in(const cvw_batch_instance* inst, int n, void* device_buffer, size_t bytes,
+                              cvw_batch** out) {
+  if (!device_buffer || !out) { set_error("null argument"); return CVW_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(device_buffer) % 256) { set_error("device buffer must be 256-byte aligned"); return CVW_EINVAL; }
+  MeshArena A;
+  A.base = static_cast<char*>(device_buffer);
+  A.size = bytes;
+  g_arena = &A;
+  const cvw_status st = cvw_batch_build(inst, n, out);
+  g_arena = nullptr;
+  return st;
 }
 
 void cvw_batch_destroy(cvw_batch* batch) { batch_free(batch); }
@@ -2199,15 +2233,25 @@ bool finite_params(const float* p) {
 
 extern "C" {
 
-cvw_status cvw_mlp_create(const float* params, cvw_mlp** out) {
+size_t cvw_mlp_device_bytes(void) {
+  const size_t nf = 3 * static_cast<size_t>(MLP_NPARAM) + 2 * MLP_HID + 1;
+  return align256(nf * 4) + align256(MLP_BF16 * 2) + align256(2 * MLP_IN * 4);
+}
+
+static cvw_status mlp_create_at(const float* params, void* buf, cvw_mlp** out) {
   if (!params || !out) { set_error("null argument"); return CVW_EINVAL; }
   *out = nullptr;
   if (!finite_params(params)) { set_error("non-finite network parameters"); return CVW_EINVAL; }
   auto* m = new cvw_mlp();
   (void)hipGetDevice(&m->device);
   const size_t nf = 3 * static_cast<size_t>(MLP_NPARAM) + 2 * MLP_HID + 1;
-  const size_t bytes = align256(nf * 4) + align256(MLP_BF16 * 2) + align256(2 * MLP_IN * 4);
-  if (hipMalloc(&m->mem, bytes) != hipSuccess) { delete m; set_error("hipMalloc failed"); return CVW_ENOMEM; }
+  const size_t bytes = cvw_mlp_device_bytes();
+  if (buf) {
+    m->mem = buf;
+    m->external = 1;
+  } else if (hipMalloc(&m->mem, bytes) != hipSuccess) {
+    delete m; set_error("hipMalloc failed"); return CVW_ENOMEM;
+  }
   float* f = static_cast<float*>(m->mem);
   m->master = f;
   m->m1 = f + MLP_NPARAM;
@@ -2231,7 +2275,7 @@ cvw_status cvw_mlp_create(const float* params, cvw_mlp** out) {
       hipMemcpy(m->lo, box.data(), box.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->master, params, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       mlp_refresh(m, nullptr) != CVW_OK || hipDeviceSynchronize() != hipSuccess) {
-    (void)hipFree(m->mem);
+    if (!m->external) (void)hipFree(m->mem);
     delete m;
     set_error("network upload failed");
     return CVW_EDEVICE;
@@ -2240,9 +2284,18 @@ cvw_status cvw_mlp_create(const float* params, cvw_mlp** out) {
   return CVW_OK;
 }
 
+cvw_status cvw_mlp_create(const float* params, cvw_mlp** out) { return mlp_create_at(params, nullptr, out); }
+
+cvw_status cvw_mlp_create_in(const float* params, void* device_buffer, size_t bytes, cvw_mlp** out) {
+  if (!device_buffer) { set_error("null device buffer"); return CVW_EINVAL; }
+  if (reinterpret_cast<uintptr_t>(device_buffer) % 256) { set_error("device buffer must be 256-byte aligned"); return CVW_EINVAL; }
+  if (bytes < cvw_mlp_device_bytes()) { set_error("device buffer too small for the network (cvw_mlp_device_bytes)"); return CVW_EINVAL; }
+  return mlp_create_at(params, device_buffer, out);
+}
+
 void cvw_mlp_destroy(cvw_mlp* mlp) {
   if (!mlp) return;
-  (void)hipFree(mlp->mem);
+  if (!mlp->external) (void)hipFree(mlp->mem);
   delete mlp;
 }
 

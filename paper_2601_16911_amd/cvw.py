@@ -28,10 +28,10 @@ SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_dest
            "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_limit", "cvw_positivity",
            "cvw_residual",
            "cvw_rk_stage", "cvw_rk_stage_gamma", "cvw_residual_noalloc", "cvw_step", "cvw_poll_status", "cvw_totals", "cvw_mesh_set_grid", "cvw_mesh_plan",
-           "cvw_mesh_build_in", "cvw_batch_build",
+           "cvw_mesh_build_in", "cvw_batch_build", "cvw_batch_plan", "cvw_batch_build_in",
            "cvw_batch_destroy",
            "cvw_batch_workspace_bytes", "cvw_batch_step", "cvw_batch_set_grid", "cvw_batch_poll_status",
-           "cvw_mlp_create", "cvw_mlp_destroy", "cvw_mlp_get_params", "cvw_mlp_set_params", "cvw_mlp_set_range",
+           "cvw_mlp_create", "cvw_mlp_create_in", "cvw_mlp_device_bytes", "cvw_mlp_destroy", "cvw_mlp_get_params", "cvw_mlp_set_params", "cvw_mlp_set_range",
            "cvw_learned_audit", "cvw_mlp_features",
            "cvw_mlp_infer", "cvw_mlp_train_workspace_bytes", "cvw_mlp_train_step"]
 
@@ -107,6 +107,8 @@ def load():
     lib.cvw_poll_status.argtypes = [vp, vp, sz, C.POINTER(C.c_uint32), vp]
     lib.cvw_totals.argtypes = [vp, C.POINTER(ParamsC), vp, C.POINTER(C.c_double), vp, sz, vp]
     lib.cvw_batch_build.argtypes = [C.POINTER(BatchInstanceC), C.c_int, C.POINTER(vp)]
+    lib.cvw_batch_plan.argtypes = [C.POINTER(BatchInstanceC), C.c_int, C.POINTER(sz)]
+    lib.cvw_batch_build_in.argtypes = [C.POINTER(BatchInstanceC), C.c_int, vp, sz, C.POINTER(vp)]
     lib.cvw_batch_destroy.argtypes = [vp]
     lib.cvw_batch_destroy.restype = None
     lib.cvw_batch_workspace_bytes.argtypes = [vp]
@@ -116,6 +118,9 @@ def load():
     lib.cvw_batch_poll_status.argtypes = [vp, sz, C.POINTER(C.c_uint32), vp]
     fp = C.POINTER(C.c_float)
     lib.cvw_mlp_create.argtypes = [fp, C.POINTER(vp)]
+    lib.cvw_mlp_create_in.argtypes = [fp, vp, sz, C.POINTER(vp)]
+    lib.cvw_mlp_device_bytes.argtypes = []
+    lib.cvw_mlp_device_bytes.restype = sz
     lib.cvw_mlp_destroy.argtypes = [vp]
     lib.cvw_mlp_destroy.restype = None
     lib.cvw_mlp_get_params.argtypes = [vp, fp]
@@ -385,6 +390,27 @@ def totals(mesh, prm, u, ws, stream=None, n_var: int = 1):
     return np.array(out[:])
 
 
+def _batch_array(instances):
+    arr = (BatchInstanceC * len(instances))()
+    for k, (mesh, prm, u, dt) in enumerate(instances):
+        arr[k].mesh = mesh.handle
+        arr[k].params = prm
+        arr[k].u = _fp(u, prm, _state_len(mesh, prm), "u")
+        arr[k].dt = float(dt)
+    return arr
+
+
+def batch_plan(instances) -> int:
+    """Device bytes cvw_batch_build_in needs for these instances (host work only)."""
+    n = C.c_size_t(0)
+    _check(load().cvw_batch_plan(_batch_array(instances), len(instances), C.byref(n)))
+    return int(n.value)
+
+
+def mlp_device_bytes() -> int:
+    return int(load().cvw_mlp_device_bytes())
+
+
 class Batch:
     """An ensemble of DG quadrilateral problems stepped together (cvw_batch_*).
 
@@ -392,17 +418,20 @@ class Batch:
     the instance's state, updated in place by step().  The batch keeps
     references to the meshes and states it was built on."""
 
-    def __init__(self, instances):
-        arr = (BatchInstanceC * len(instances))()
-        self._keep = []
-        for k, (mesh, prm, u, dt) in enumerate(instances):
-            arr[k].mesh = mesh.handle
-            arr[k].params = prm
-            arr[k].u = _fp(u, prm, _state_len(mesh, prm), "u")
-            arr[k].dt = float(dt)
-            self._keep.append((mesh, u))
+    def __init__(self, instances, device_buffer=None):
+        """device_buffer: a device tensor of at least batch_plan(instances) bytes
+        that holds the batch's device arrays (kept alive by the batch); by
+        default the library allocates them."""
+        arr = _batch_array(instances)
+        self._keep = [(mesh, u) for mesh, _, u, _ in instances]
+        self._buffer = device_buffer
         h = C.c_void_p()
-        _check(load().cvw_batch_build(arr, len(instances), C.byref(h)))
+        if device_buffer is None:
+            _check(load().cvw_batch_build(arr, len(instances), C.byref(h)))
+        else:
+            nbytes = device_buffer.numel() * device_buffer.element_size()
+            _check(load().cvw_batch_build_in(arr, len(instances), C.c_void_p(device_buffer.data_ptr()), nbytes,
+                                             C.byref(h)))
         self._h = h
         self._sig = ";".join(f"{m.degree}:{p.flux}:{m.info['n_cells']}" for m, p, _, _ in instances)
 
@@ -479,12 +508,21 @@ def unpack_params(v) -> dict:
 class Mlp:
     """The learned-sensor network on the current device (cvw_mlp_*)."""
 
-    def __init__(self, params):
+    def __init__(self, params, device_buffer=None):
+        """device_buffer: a device tensor of at least mlp_device_bytes() bytes that
+        holds the network (kept alive by the handle); by default the library
+        allocates it."""
         v = np.ascontiguousarray(params, np.float32)
         if v.size != MLP_NPARAM:
             raise ValueError(f"{v.size} parameters, {MLP_NPARAM} expected")
         h = C.c_void_p()
-        _check(load().cvw_mlp_create(v.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)))
+        pp = v.ctypes.data_as(C.POINTER(C.c_float))
+        self._buffer = device_buffer
+        if device_buffer is None:
+            _check(load().cvw_mlp_create(pp, C.byref(h)))
+        else:
+            nbytes = device_buffer.numel() * device_buffer.element_size()
+            _check(load().cvw_mlp_create_in(pp, C.c_void_p(device_buffer.data_ptr()), nbytes, C.byref(h)))
         self._h = h
 
     @property

@@ -156,3 +156,29 @@ def test_batch_error_paths():
     with pytest.raises(cvw.CvwError) as ei:
         b.step(1, torch.zeros(256, dtype=torch.uint8, device="cuda"))
     assert ei.value.status == cvw.EINVAL
+
+
+def test_batch_in_caller_buffer():
+    """cvw_batch_build_in: the batch's device arrays in a buffer the caller
+    owns (sized by cvw_batch_plan) step bitwise like the allocating build; a
+    buffer one byte short is refused before anything is written."""
+    cases = _ensemble()
+    b1, s1 = _batch(cases)
+    states, items = [], []
+    for mesh, p, prm, U, dt in cases:
+        gm = cvw.Mesh(mesh, p, cvw.DG)
+        u = torch.from_numpy(U.copy()).cuda()
+        states.append(u)
+        items.append((gm, cvw.make_params(prm), u, dt))
+    need = cvw.batch_plan(items)
+    assert need > 0 and need % 256 == 0
+    with pytest.raises(cvw.CvwError):
+        cvw.Batch(items, device_buffer=torch.zeros(need - 1, dtype=torch.uint8, device="cuda"))
+    buf = torch.zeros(need, dtype=torch.uint8, device="cuda")
+    b2 = cvw.Batch(items, device_buffer=buf)
+    w1, w2 = b1.alloc_workspace(), b2.alloc_workspace()
+    b1.step(2, w1)
+    b2.step(2, w2)
+    for x, y in zip(s1, states):
+        assert torch.equal(x, y)
+    assert b2.poll_status(w2) == 0

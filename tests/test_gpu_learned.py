@@ -100,6 +100,29 @@ def test_inference(n):
     assert np.quantile(d, 0.99) <= 1e-4
 
 
+def test_network_in_caller_buffer():
+    """cvw_mlp_create_in: the network's device memory in a buffer the caller
+    owns gives bitwise the inference of the allocating handle; a misaligned
+    or short buffer is refused."""
+    packed = cvw.pack_params(_random_net(7))
+    need = cvw.mlp_device_bytes()
+    assert need > 0 and need % 256 == 0
+    buf = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(cvw.CvwError):
+        cvw.Mlp(packed, device_buffer=buf[:need - 1])
+    with pytest.raises(cvw.CvwError):
+        cvw.Mlp(packed, device_buffer=buf[8:])
+    a, b = cvw.Mlp(packed), cvw.Mlp(packed, device_buffer=buf)
+    X = bf16_round(np.random.default_rng(2).normal(size=(777, N_FEAT)))
+    feat = _float_to_bits(X.reshape(-1)).reshape(-1)
+    ga = torch.empty(777, device="cuda")
+    gb = torch.empty(777, device="cuda")
+    a.infer(feat, ga)
+    b.infer(feat, gb)
+    assert torch.equal(ga, gb)
+    assert np.array_equal(a.get_params(), b.get_params())
+
+
 def test_gradient_against_reference():
     P = _random_net(5)
     net = cvw.Mlp(cvw.pack_params(P))
