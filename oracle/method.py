@@ -491,7 +491,7 @@ def residual(sp, U, prm: Params, gamma=None, return_parts: bool = False, allow_b
     alpha = sc_weights(sp, s, gamma, prm, pg)
     r = (-np.einsum("eq,eqjd,veqd->vej", W, gphi, F)
          + np.einsum("e,eq,eq,eqjd,veqd->vej", nu, W, alpha, gphi, G))
-    ends = any(b != BC_NONE for b in prm.bc)
+    ends = any(b != BC_NONE for b in prm.bc) or prm.bc_face_kind is not None
     if sp.kind == 1:
         r = r + face_terms(sp, Uc, prm, allow_boundary or ends)
     if ends:
@@ -556,15 +556,14 @@ def face_terms(sp, Uc, prm: Params, allow_boundary: bool = False):
 # boundary data at the ends of a 1D domain (the paper's shock-tube and blast-
 # wave runs, Sec. 5.4: an inflow end and reflecting walls)
 # ---------------------------------------------------------------------------
-def boundary_state(prm: Params, Ub, n, end: int):
-    """Exterior state at a boundary point: outflow copies the interior trace,
-    an inflow end imposes the given state, a reflecting wall mirrors the
-    normal momentum (Euler only).  Ub [n_var, ...], n [..., d]."""
-    kind = prm.bc[end]
+def ghost_state(prm: Params, kind: int, state, Ub, n):
+    """Exterior state at boundary points of one kind: outflow copies the
+    interior trace, inflow imposes the given state, a reflecting wall mirrors
+    the normal momentum (Euler only).  Ub [n_var, ...], n [..., d]."""
     if kind == BC_OUTFLOW:
         return Ub.copy()
     if kind == BC_INFLOW:
-        st = np.asarray(prm.bc_state[end][:Ub.shape[0]], np.float64)
+        st = np.asarray(state[:Ub.shape[0]], np.float64)
         return np.broadcast_to(st.reshape((-1,) + (1,) * (Ub.ndim - 1)), Ub.shape).copy()
     if kind == BC_WALL:
         if prm.flux != EULER:
@@ -578,13 +577,24 @@ def boundary_state(prm: Params, Ub, n, end: int):
     raise ValueError("boundary point without boundary data")
 
 
+def boundary_state(prm: Params, Ub, n, end: int):
+    """Exterior state at an end of a line (the end's kind and state)."""
+    return ghost_state(prm, prm.bc[end], prm.bc_state[end], Ub, n)
+
+
+def boundary_faces(sp):
+    """Boundary faces (cell [nb], local face [nb]) in ascending (cell, face) order."""
+    nbr = sp.nbr if sp.nbr is not None else face_neighbours(sp.cell, sp.mesh.cell_vertices)[0]
+    return np.nonzero(nbr < 0)
+
+
 def boundary_terms(sp, Uc, prm: Params):
     """Weak boundary terms phi_j(x_b) f*(u_h(x_b), u_ext; n) at the two ends of a
     1D domain, for DG and CG alike: face 0 of a cell without a left neighbour
     is the left end (n = -1), face 1 without a right neighbour the right end."""
     ref = sp.ref
     if ref.dim != 1:
-        raise NotImplementedError("boundary data: 1D domains only")
+        return boundary_terms_2d(sp, Uc, prm)
     nbr = sp.nbr if sp.nbr is not None else face_neighbours(sp.cell, sp.mesh.cell_vertices)[0]
     out = np.zeros_like(Uc)
     for f in range(2):
@@ -598,6 +608,38 @@ def boundary_terms(sp, Uc, prm: Params):
         xf = map_points(sp.cell, sp.X[sel], pts)
         Fs = numerical_flux(prm, Ub, boundary_state(prm, Ub, n, f), n, xf)   # [nv, nb, 1]
         out[:, sel] += Fs[..., 0][..., None] * phif
+    return out
+
+
+def boundary_terms_2d(sp, Uc, prm: Params):
+    """Weak boundary terms int_f phi_j f*(u_h, u_ext; n) over the boundary faces
+    of a 2D mesh, each face with its own kind and state (prm.bc_face_kind,
+    prm.bc_face_state in the order of boundary_faces)."""
+    ref = sp.ref
+    cells, faces = boundary_faces(sp)
+    if prm.bc_face_kind is None:
+        raise ValueError("boundary faces without boundary data")
+    kinds = np.asarray(prm.bc_face_kind)
+    states = np.asarray(prm.bc_face_state, np.float64) if prm.bc_face_state is not None else \
+        np.zeros((len(cells), Uc.shape[0]))
+    if len(kinds) != len(cells):
+        raise ValueError("one boundary kind per boundary face")
+    out = np.zeros_like(Uc)
+    for f in range(ref.n_faces):
+        on_f = np.nonzero(faces == f)[0]
+        if len(on_f) == 0:
+            continue
+        pts, wf = ref.face_points(f)
+        phif = ref.deriv(pts, (0,) * ref.dim)                       # [ng, nloc]
+        n_all, Jf_all = face_geometry(sp, f)
+        for b in on_f:
+            e = cells[b]
+            Ub = np.einsum("vj,gj->vg", Uc[:, e], phif)              # [nv, ng]
+            nb = np.broadcast_to(n_all[e], (len(wf), n_all.shape[1]))
+            Ug = ghost_state(prm, int(kinds[b]), states[b], Ub, nb)
+            xf = map_points(sp.cell, sp.X[e:e + 1], pts)[0]
+            Fs = numerical_flux(prm, Ub, Ug, nb, xf)                 # [nv, ng]
+            out[:, e] += np.einsum("g,gj,vg->vj", wf * Jf_all[e], phif, Fs)
     return out
 
 

@@ -141,6 +141,10 @@ class Params:
     # exterior state of an inflow end (conserved variables)
     bc: tuple = (BC_NONE, BC_NONE)
     bc_state: tuple = ((0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0))
+    # 2D meshes with boundary faces: the kind (BC_*) and exterior state of each
+    # boundary face, in ascending (cell, local face) order ([n_bfaces], [n_bfaces, n_var])
+    bc_face_kind: object = None
+    bc_face_state: object = None
 
 
 # ---------------------------------------------------------------------------

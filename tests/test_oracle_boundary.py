@@ -206,3 +206,87 @@ def test_euler1d_dg_convergence():
         errs.append(np.abs(U - state(T)).max())
     rate = np.log2(errs[0] / errs[1])
     assert rate > p + 0.5, errs
+
+
+# ---------------------------------------------------------------------------
+# 2D meshes with boundary faces (one kind and state per face)
+# ---------------------------------------------------------------------------
+from oracle.method import boundary_faces  # noqa: E402
+
+EULER2 = dict(flux=synth.EULER, flux_param=(G, 0, 0, 0))
+
+
+def _cons2(rho, vx, vy, p):
+    return np.array([rho, rho * vx, rho * vy, p / (G - 1) + 0.5 * rho * (vx * vx + vy * vy)])
+
+
+def _euler2_smooth(sp, seed):
+    rng = np.random.default_rng(seed)
+    a, b, ph = rng.uniform(0.1, 0.3, 3)
+
+    def prim(x):
+        X, Y = x[..., 0], x[..., 1]
+        return (1.0 + a * np.sin(2 * np.pi * X + ph) * np.cos(2 * np.pi * Y),
+                b * np.cos(2 * np.pi * X) + 0.1, b * np.sin(2 * np.pi * Y),
+                1.0 + b * np.cos(2 * np.pi * (X + Y) + ph))
+    return nodal_interpolate(sp, [lambda x, c=c: _cons2(*prim(x))[c] for c in range(4)])
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_2d_wall_equals_mirror_domain(p):
+    """Walls at x = 0 and x = 1 (periodic in y) against the periodic domain
+    [0, 2] x [0, 1] holding the state and its mirror image (DG quads, fixed
+    gamma)."""
+    N, M = 4, 3
+    sp = build_space(synth.quad_mesh(N, M, periodic=(False, True)), p, 1, 4)
+    cells, _ = boundary_faces(sp)
+    U = sp.to_cells(_euler2_smooth(sp, 2))
+    base = dict(EULER2, sensor=2, fixed_gamma=0.4)
+    R = residual(sp, U.ravel(), Params(**base, bc_face_kind=np.full(len(cells), synth.BC_WALL))).reshape(4, N * M, -1)
+    sp2 = build_space(synth.quad_mesh(2 * N, M, 0.0, 2.0, periodic=(True, True)), p, 1, 4)
+    n1 = p + 1
+    U2 = np.zeros((4, 2 * N * M, n1 * n1))
+    for j in range(M):
+        for i in range(N):
+            src = U[:, i + N * j].reshape(4, n1, n1)               # [v, b, a]
+            U2[:, i + 2 * N * j] = src.reshape(4, -1)
+            mir = src[:, :, ::-1].copy()                             # x -> 2 - x: node a -> p - a
+            mir[1] = -mir[1]
+            U2[:, (2 * N - 1 - i) + 2 * N * j] = mir.reshape(4, -1)
+    R2 = residual(sp2, U2.ravel(), Params(**base)).reshape(4, 2 * N * M, -1)
+    own = np.array([i + 2 * N * j for j in range(M) for i in range(N)])
+    assert np.abs(R - R2[:, own]).max() <= 1e-12 * np.abs(R).max()
+
+
+@pytest.mark.parametrize("cell", ["quad", "tri"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_2d_free_streams_and_wall_conservation(cell, p):
+    mesh = synth.quad_mesh(4, 3, periodic=(False, False)) if cell == "quad" else \
+        synth.tri_mesh(4, 3, jitter=0.1, seed=5, periodic=(False, False))
+    sp = build_space(mesh, p, 1, 4)
+    nb = len(boundary_faces(sp)[0])
+    st = _cons2(0.9, 0.5, -0.3, 1.1)
+    U = nodal_interpolate(sp, [lambda x, c=c: np.full(x.shape[:-1], st[c]) for c in range(4)])
+    kinds = np.where(np.arange(nb) % 2 == 0, synth.BC_INFLOW, synth.BC_OUTFLOW)
+    prm = Params(**EULER2, bc_face_kind=kinds, bc_face_state=np.tile(st, (nb, 1)))
+    assert np.abs(residual(sp, U, prm)).max() <= 1e-13 * np.abs(st).max()
+    rest = _cons2(1.2, 0.0, 0.0, 0.8)
+    U = nodal_interpolate(sp, [lambda x, c=c: np.full(x.shape[:-1], rest[c]) for c in range(4)])
+    walls = Params(**EULER2, bc_face_kind=np.full(nb, synth.BC_WALL))
+    assert np.abs(residual(sp, U, walls)).max() <= 1e-13 * np.abs(rest).max()
+    # walls all round conserve mass and energy (plain sensor, smooth data)
+    R = residual(sp, _euler2_smooth(sp, 4), walls).reshape(4, -1)
+    scale = np.abs(R).max()
+    assert scale > 1e-2
+    assert abs(R[0].sum()) <= 1e-12 * scale * R.shape[1]
+    assert abs(R[3].sum()) <= 1e-12 * scale * R.shape[1]
+
+
+def test_boundary_face_order():
+    """Boundary faces come in ascending (cell, local face) order: the order in
+    which boundary data are given, on both sides of the library boundary."""
+    sp = build_space(synth.tri_mesh(3, 3, jitter=0.1, seed=2, periodic=(False, True)), 1, 1)
+    c, f = boundary_faces(sp)
+    key = c * 8 + f
+    assert len(c) == 2 * 3 and np.all(np.diff(key) > 0)
+    assert np.all(sp.nbr[c, f] < 0) and (sp.nbr < 0).sum() == len(c)
