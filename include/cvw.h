@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 9
+#define CVW_ABI_VERSION 10
 
 typedef enum {
   CVW_OK = 0,
@@ -82,6 +82,11 @@ typedef enum {
  *   INFLOW:  u_ext = bc_state[end] (conserved variables).
  * The vertex patch of an end vertex is the one cell that contains it. */
 typedef enum { CVW_BC_NONE = 0, CVW_BC_OUTFLOW = 1, CVW_BC_WALL = 2, CVW_BC_INFLOW = 3 } cvw_bc;
+/* On 2D DG meshes with boundary faces (quadrilaterals, triangles) the same
+ * kinds are given per boundary face (cvw_params.bc_face_kind / bc_face_state,
+ * device arrays owned by the caller, who may rewrite them between calls for
+ * time-dependent data), and the wall mirrors the normal momentum:
+ * m_ext = m - 2 (m . n) n. */
 typedef enum { CVW_F32 = 0, CVW_F64 = 1 } cvw_dtype;
 typedef enum { CVW_SENSOR_PLAIN = 0, CVW_SENSOR_LEARNED = 1, CVW_SENSOR_FIXED = 2 } cvw_sensor_kind;
 
@@ -132,6 +137,11 @@ typedef struct {
   int32_t bc[2];             /* lines with ends: cvw_bc at the left end (vertex 0 of its cell) and
                                 the right end; both must be set on such a line, ignored on closed meshes */
   double bc_state[2][4];     /* CVW_BC_INFLOW: exterior conserved state at that end (first n_var used) */
+  const int32_t* bc_face_kind; /* 2D DG meshes with boundary faces: device [n_bfaces] cvw_bc of each
+                                boundary face, in the order of CVW_EXPORT_BFACE (required there,
+                                ignored on closed meshes); a wall on a scalar law acts as outflow */
+  const float* bc_face_state;  /* device [n_bfaces][4] exterior conserved state of the inflow faces
+                                (float32, like the 2D DG state); may be NULL without inflow faces */
 } cvw_params;
 
 typedef struct {
@@ -147,6 +157,7 @@ typedef struct {
                                 numbered e = i + grid_nx j, four cells at every vertex):
                                 the grid's size, which enables the fused sensor pass;
                                 0 otherwise                                         */
+  int64_t n_bfaces;          /* DG: faces without a neighbour (the boundary faces)  */
 } cvw_mesh_info;
 
 typedef struct cvw_mesh cvw_mesh;
@@ -158,7 +169,9 @@ enum {
   CVW_EXPORT_VTX_LV = 2,     /* [nnz] local vertex of each patch entry              */
   CVW_EXPORT_NBR = 3,        /* DG: [n_cells][n_faces] face neighbour, -1 = boundary */
   CVW_EXPORT_NBR_FACE = 4,   /* DG: [n_cells][n_faces] neighbour's local face        */
-  CVW_EXPORT_CELL_DOF = 5    /* CG: [n_cells][n_loc] global DOF of each local node   */
+  CVW_EXPORT_CELL_DOF = 5,   /* CG: [n_cells][n_loc] global DOF of each local node   */
+  CVW_EXPORT_BFACE = 6       /* DG: [n_bfaces][2] (cell, local face) of each boundary face,
+                                ascending: the order of the per-face boundary data */
 };
 
 int cvw_abi_version(void);

@@ -335,6 +335,27 @@ __device__ __forceinline__ float wave_speed(const MethodScalars& ms, const float
 }
 
 // interface flux f*(u-, u+, n): local Lax-Friedrichs for scalars, HLL with
+// Exterior state at a boundary point of a 2D DG mesh: the neighbour table
+// holds -(b + 1) for boundary face b, whose kind and state come with the
+// method scalars.  Inflow imposes the state, a wall mirrors the normal
+// momentum (Euler; a scalar law takes it as outflow), outflow copies the trace.
+template <int FLUX>
+__device__ __forceinline__ void ghost_state(const MethodScalars& ms, int32_t code, const float* um, float nx, float ny,
+                                            float* up) {
+  constexpr int NV = NVar<FLUX>::value;
+  const int32_t b = -code - 1;
+  const int kind = ms.bck[b];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) up[v] = (kind == CVW_BC_INFLOW) ? ms.bcs[4 * b + v] : um[v];
+  if constexpr (FLUX == CVW_EULER) {
+    if (kind == CVW_BC_WALL) {
+      const float mn = um[1] * nx + um[2] * ny;
+      up[1] = fmaf(-2.0f * mn, nx, um[1]);
+      up[2] = fmaf(-2.0f * mn, ny, um[2]);
+    }
+  }
+}
+
 // Davis wave-speed estimates for the Euler equations
 template <int FLUX>
 __device__ __forceinline__ void num_flux(const MethodScalars& ms, const float* um, const float* up, float nx,

@@ -311,8 +311,10 @@ __device__ __forceinline__ float colbcast(float x, const int (&srcb)[4]) {
 
 // One block of 16 cells (logical block index blk); sl = the lane tables in LDS.
 // BUF: the state arrays (all variables) and the candidates are each under
-// 4 GiB and are accessed as raw buffers with 32-bit offsets.
-template <int P, int FLUX, bool BUF = false>
+// 4 GiB and are accessed as raw buffers with 32-bit offsets.  OPEN: the mesh
+// has boundary faces (negative neighbour codes); closed meshes compile
+// without the boundary branches.
+template <int P, int FLUX, bool BUF = false, bool OPEN = false>
 __device__ __forceinline__ void dgq_eval_body(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
@@ -549,7 +551,9 @@ __device__ __forceinline__ void dgq_eval_body(
     // assignment and the lane's coefficients are in its lane record)
     const bool xf = (a == 0 || a == 3);
     const bool inner = !xf && (b == 1 || b == 2);
-    const float* un0 = u + static_cast<int64_t>(en_pre) * NLOC + L.noff;
+    const bool bnd = OPEN && en_pre < 0;               // a boundary face: exterior state from its data
+    const int64_t enc = bnd ? 0 : en_pre;
+    const float* un0 = u + enc * NLOC + L.noff;
     const int nst = L.nstep;
     float um[NV], up[NV];
 #pragma unroll
@@ -559,18 +563,21 @@ __device__ __forceinline__ void dgq_eval_body(
       const float tc = dpp<(0 | (0 << 2) | (3 << 4) | (3 << 6))>(tS[v]);
       um[v] = xf ? tW[v] : (inner ? tc : tS[v]);
       float s2 = 0.0f;
-      if constexpr (BUF) {
-        const uint32_t o0 = static_cast<uint32_t>((static_cast<int64_t>(en_pre) * NLOC + L.noff) * 4);
+      if (!bnd) {
+        if constexpr (BUF) {
+          const uint32_t o0 = static_cast<uint32_t>((enc * NLOC + L.noff) * 4);
 #pragma unroll
-        for (int ii = 0; ii < N1; ++ii)
-          s2 = fmaf(L.FB[ii], buf_load(buf_rsrc(u, sbytes * NV), o0 + 4u * nst * ii, v * sbytes), s2);
-      } else {
-        const float* un = un0 + v * stride;
+          for (int ii = 0; ii < N1; ++ii)
+            s2 = fmaf(L.FB[ii], buf_load(buf_rsrc(u, sbytes * NV), o0 + 4u * nst * ii, v * sbytes), s2);
+        } else {
+          const float* un = un0 + v * stride;
 #pragma unroll
-        for (int ii = 0; ii < N1; ++ii) s2 = fmaf(L.FB[ii], un[nst * ii], s2);
+          for (int ii = 0; ii < N1; ++ii) s2 = fmaf(L.FB[ii], un[nst * ii], s2);
+        }
       }
       up[v] = s2;
     }
+    if (bnd) ghost_state<FLUX>(ms, en_pre, um, L.nx, L.ny, up);
     float fs[NV];
     num_flux<FLUX>(ms, um, up, L.nx, L.ny, 0.0f, 0.0f, fs);
     const float wpt = fmaf(L.fwx, G.hy, L.fwy * G.hx);
@@ -593,15 +600,20 @@ __device__ __forceinline__ void dgq_eval_body(
     for (int v = 0; v < NV; ++v) fW[v] = fE[v] = fS[v] = fN[v] = 0.0f;
     if (nd && (a == 0 || a == P)) {
       const bool west = (a == 0);
-      const int64_t en = nbr[e * 4 + (west ? 3 : 1)];
+      const int32_t code = nbr[e * 4 + (west ? 3 : 1)];
       float up[NV];
+      if (!OPEN || code >= 0) {
+        const int64_t en = code;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const float* un = u + v * stride + en * NLOC + N1 * b;
-        float s2 = 0.0f;
+        for (int v = 0; v < NV; ++v) {
+          const float* un = u + v * stride + en * NLOC + N1 * b;
+          float s2 = 0.0f;
 #pragma unroll
-        for (int ii = 0; ii < N1; ++ii) s2 = fmaf(west ? tab.B[1][ii] : tab.B[0][ii], un[ii], s2);
-        up[v] = s2;
+          for (int ii = 0; ii < N1; ++ii) s2 = fmaf(west ? tab.B[1][ii] : tab.B[0][ii], un[ii], s2);
+          up[v] = s2;
+        }
+      } else {
+        ghost_state<FLUX>(ms, code, west ? tW : tE, west ? -1.0f : 1.0f, 0.0f, up);
       }
       float fs[NV];
       num_flux<FLUX>(ms, west ? tW : tE, up, west ? -1.0f : 1.0f, 0.0f, 0.0f, 0.0f, fs);
@@ -613,15 +625,20 @@ __device__ __forceinline__ void dgq_eval_body(
     }
     if (nd && (b == 0 || b == P)) {
       const bool south = (b == 0);
-      const int64_t en = nbr[e * 4 + (south ? 0 : 2)];
+      const int32_t code = nbr[e * 4 + (south ? 0 : 2)];
       float up[NV];
+      if (!OPEN || code >= 0) {
+        const int64_t en = code;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const float* un = u + v * stride + en * NLOC + a;
-        float s2 = 0.0f;
+        for (int v = 0; v < NV; ++v) {
+          const float* un = u + v * stride + en * NLOC + a;
+          float s2 = 0.0f;
 #pragma unroll
-        for (int jj = 0; jj < N1; ++jj) s2 = fmaf(south ? tab.B[1][jj] : tab.B[0][jj], un[N1 * jj], s2);
-        up[v] = s2;
+          for (int jj = 0; jj < N1; ++jj) s2 = fmaf(south ? tab.B[1][jj] : tab.B[0][jj], un[N1 * jj], s2);
+          up[v] = s2;
+        }
+      } else {
+        ghost_state<FLUX>(ms, code, south ? tS : tN, 0.0f, south ? -1.0f : 1.0f, up);
       }
       float fs[NV];
       num_flux<FLUX>(ms, south ? tS : tN, up, 0.0f, south ? -1.0f : 1.0f, 0.0f, 0.0f, fs);
@@ -684,7 +701,7 @@ __device__ __forceinline__ void dgq_eval_body(
 // gamma_e (eq. gamma; the candidates' first derivatives are constant, so their
 // centred expansion is the candidate itself), lambda_e, alpha_q, volume and
 // interface terms, stage update.
-template <int FLUX, bool BUF = false>
+template <int FLUX, bool BUF = false, bool OPEN = false>
 __device__ __forceinline__ void dgq_eval_body_p1(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
@@ -809,21 +826,28 @@ __device__ __forceinline__ void dgq_eval_body_p1(
 
   // ---- interface terms: x face (side a, point b) and y face (side b, point a)
   float px[NV], py[NV];
+  // boundary faces (negative neighbour codes) take the exterior state of their data
+  const bool bx_ = OPEN && enx < 0, by_ = OPEN && eny < 0;
+  const int64_t ecx = bx_ ? 0 : enx, ecy = by_ ? 0 : eny;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const int64_t ox = v * stride + static_cast<int64_t>(enx) * NLOC + 2 * b;
-    const int64_t oy = v * stride + static_cast<int64_t>(eny) * NLOC + a;
+    const int64_t ox = v * stride + ecx * NLOC + 2 * b;
+    const int64_t oy = v * stride + ecy * NLOC + a;
+    px[v] = 0.0f;
+    py[v] = 0.0f;
     if constexpr (BUF) {
       const __amdgpu_buffer_rsrc_t ru = buf_rsrc(u, sbytes * NV);
-      const uint32_t bx = static_cast<uint32_t>((static_cast<int64_t>(enx) * NLOC + 2 * b) * 4);
-      const uint32_t by = static_cast<uint32_t>((static_cast<int64_t>(eny) * NLOC + a) * 4);
-      px[v] = fmaf(L.FX[1], buf_load(ru, bx + 4u, v * sbytes), L.FX[0] * buf_load(ru, bx, v * sbytes));
-      py[v] = fmaf(L.FY[1], buf_load(ru, by + 8u, v * sbytes), L.FY[0] * buf_load(ru, by, v * sbytes));
+      const uint32_t bx = static_cast<uint32_t>((ecx * NLOC + 2 * b) * 4);
+      const uint32_t by = static_cast<uint32_t>((ecy * NLOC + a) * 4);
+      if (!bx_) px[v] = fmaf(L.FX[1], buf_load(ru, bx + 4u, v * sbytes), L.FX[0] * buf_load(ru, bx, v * sbytes));
+      if (!by_) py[v] = fmaf(L.FY[1], buf_load(ru, by + 8u, v * sbytes), L.FY[0] * buf_load(ru, by, v * sbytes));
     } else {
-      px[v] = fmaf(L.FX[1], u[ox + 1], L.FX[0] * u[ox]);
-      py[v] = fmaf(L.FY[1], u[oy + 2], L.FY[0] * u[oy]);
+      if (!bx_) px[v] = fmaf(L.FX[1], u[ox + 1], L.FX[0] * u[ox]);
+      if (!by_) py[v] = fmaf(L.FY[1], u[oy + 2], L.FY[0] * u[oy]);
     }
   }
+  if (bx_) ghost_state<FLUX>(ms, enx, tX, L.nx, 0.0f, px);
+  if (by_) ghost_state<FLUX>(ms, eny, tY, 0.0f, L.ny, py);
   float fsx[NV], fsy[NV];
   num_flux<FLUX>(ms, tX, px, L.nx, 0.0f, 0.0f, 0.0f, fsx);
   num_flux<FLUX>(ms, tY, py, 0.0f, L.ny, 0.0f, 0.0f, fsy);
@@ -887,7 +911,7 @@ __device__ __forceinline__ void load_lane_tables(const LaneRec* __restrict__ lan
 #ifndef CVW_EVAL_WPE
 #define CVW_EVAL_WPE
 #endif
-template <int P, int FLUX, bool BUF>
+template <int P, int FLUX, bool BUF, bool OPEN>
 __global__ __launch_bounds__(256) CVW_EVAL_WPE void dgq_eval_kernel(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out,
     float* __restrict__ gamma_out, float* __restrict__ alpha_out, const float* __restrict__ cand,
@@ -911,11 +935,11 @@ __global__ __launch_bounds__(256) CVW_EVAL_WPE void dgq_eval_kernel(
                  "+s"(g.my2), "+s"(g.qx4), "+s"(g.qy4), "+s"(g.area4), "+s"(g.hhx), "+s"(g.hhy), "+s"(g.nuf)
                  :: "memory");
     if constexpr (P == 1)
-      dgq_eval_body_p1<FLUX, BUF>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr,
+      dgq_eval_body_p1<FLUX, BUF, OPEN>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr,
                                   reinterpret_cast<const LaneRec1*>(sl), E, blk, g, ms, mode, dt, a0, b0, status,
                                   gamma_in);
     else
-      dgq_eval_body<P, FLUX, BUF>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E, blk, g, ms,
+      dgq_eval_body<P, FLUX, BUF, OPEN>(u, u0, out, gamma_out, alpha_out, cand, cell_vtx, nbr, sl, tab, E, blk, g, ms,
                                   mode, dt, a0, b0, status, gamma_in);
   }
 }
@@ -976,14 +1000,12 @@ static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, co
   const bool buf = !wide_addressing_forced() && m->E * m->nloc * NV * 4 < (int64_t(1) << 32) - 4096 &&
                    m->Nv * m->nk * 4 < (int64_t(1) << 32) - 4096;
   const CellGeo geo = make_cell_geo(m->hx, m->hy, m->he, P);
-  if (buf)
-    hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX, true>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0,
-                       out, gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, ntile, tpb, geo,
-                       ms, mode, dt, a0, b0, status, gamma_in);
-  else
-    hipLaunchKernelGGL((dgq_eval_kernel<P, FLUX, false>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0,
-                       out, gamma, alpha, cand, m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, ntile, tpb, geo,
-                       ms, mode, dt, a0, b0, status, gamma_in);
+  // one variant per addressing mode and per closed / open mesh
+  auto kern = buf ? (m->closed ? dgq_eval_kernel<P, FLUX, true, false> : dgq_eval_kernel<P, FLUX, true, true>)
+                  : (m->closed ? dgq_eval_kernel<P, FLUX, false, false> : dgq_eval_kernel<P, FLUX, false, true>);
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, u, u0, out, gamma, alpha, cand,
+                     m->d_cell_vtx, m->d_nbr, m->d_lanes, m->tens, m->E, ntile, tpb, geo, ms, mode, dt, a0, b0, status,
+                     gamma_in);
 }
 
 template <int P>

@@ -44,6 +44,8 @@ MethodScalars make_scalars(const cvw_params* p) {
   s.lam_gd = p->lambda_global;
   s.fixed_gammad = p->fixed_gamma;
   for (int i = 0; i < 4; ++i) s.fpd[i] = p->flux_param[i];
+  s.bck = p->bc_face_kind;
+  s.bcs = p->bc_face_state;
   return s;
 }
 
@@ -766,7 +768,9 @@ static cvw_status dev_alloc(void** dst, size_t bytes) {
     A.off += bytes;
     return CVW_OK;
   }
-  if (A.off + bytes > A.size) {
+  // the plan is the rounded end of the last piece: check that, so that every
+  // buffer smaller than the plan is refused
+  if ((A.off + bytes + 255) / 256 * 256 > A.size) {
     set_error("device buffer too small (cvw_mesh_plan / cvw_batch_plan give the size)");
     return CVW_EINVAL;
   }
@@ -1025,15 +1029,21 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
       i = j + 1;
     }
     m->closed = std::all_of(m->h_nbr.begin(), m->h_nbr.end(), [](int32_t x) { return x >= 0; }) ? 1 : 0;
+    for (int64_t i = 0; i < E * nf; ++i)
+      if (m->h_nbr[i] < 0) {
+        m->h_bface.push_back(static_cast<int32_t>(i / nf));
+        m->h_bface.push_back(static_cast<int32_t>(i % nf));
+      }
+    m->n_bfaces = static_cast<int64_t>(m->h_bface.size() / 2);
     if (m->cell == CVW_SEG && m->closed) {
       // the 1D kernels read the neighbour across face f through its face 1 - f
       for (int64_t i = 0; i < E * 2; ++i)
         if (m->h_nbr_face[i] != 1 - (i % 2)) { m->closed = 0; break; }
     }
-    if (m->cell == CVW_QUAD && m->closed) {
+    if (m->cell == CVW_QUAD) {
       // the structured DG path reads the neighbour across face f through its face (f + 2) mod 4
       for (int64_t i = 0; i < E * 4; ++i)
-        if (m->h_nbr_face[i] != (i % 4 + 2) % 4) { m->uniform = 0; break; }
+        if (m->h_nbr[i] >= 0 && m->h_nbr_face[i] != (i % 4 + 2) % 4) { m->uniform = 0; break; }
     }
   }
 
@@ -1092,7 +1102,14 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   if ((st = upload(&m->d_vtx_ptr, ptr32)) != CVW_OK) { free_mesh(m); return st; }
   if ((st = upload(&m->d_vtx_ent, ent)) != CVW_OK) { free_mesh(m); return st; }
   if ((st = upload(&m->d_cell_vtx, m->h_cell_vtx)) != CVW_OK) { free_mesh(m); return st; }
-  if ((st = upload(&m->d_nbr, m->h_nbr)) != CVW_OK) { free_mesh(m); return st; }
+  {
+    // device neighbour table: boundary face b (ascending (cell, face)) as -(b + 1)
+    std::vector<int32_t> dn(m->h_nbr);
+    int32_t b = 0;
+    for (auto& x : dn)
+      if (x < 0) x = -(++b);
+    if ((st = upload(&m->d_nbr, dn)) != CVW_OK) { free_mesh(m); return st; }
+  }
   if ((st = upload(&m->d_cell_dof, m->h_cell_dof)) != CVW_OK) { free_mesh(m); return st; }
   if ((st = upload(&m->d_dof_ptr, dptr)) != CVW_OK) { free_mesh(m); return st; }
   if ((st = upload(&m->d_dof_ent, dent)) != CVW_OK) { free_mesh(m); return st; }
@@ -1147,7 +1164,8 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     }
     if ((st = upload(&m->d_geov, gv)) != CVW_OK) { free_mesh(m); return st; }
     std::vector<int32_t> nf32(E * 3);
-    for (int64_t i = 0; i < E * 3; ++i) nf32[i] = m->h_nbr[i] < 0 ? -1 : m->h_nbr[i] * 4 + m->h_nbr_face[i];
+    int32_t nbf = 0;
+    for (int64_t i = 0; i < E * 3; ++i) nf32[i] = m->h_nbr[i] < 0 ? -(++nbf) : m->h_nbr[i] * 4 + m->h_nbr_face[i];
     if ((st = upload(&m->d_nbrf, nf32)) != CVW_OK) { free_mesh(m); return st; }
     std::vector<TriTables> tt(1);
     fill_tri_tables(tt[0], p);
@@ -1183,6 +1201,7 @@ cvw_status cvw_mesh_get_info(const cvw_mesh* m, cvw_mesh_info* info) {
   info->n_loc = m->nloc; info->n_k = m->nk; info->n_q = m->nq; info->v_e = m->ve; info->n_faces = m->nf;
   info->uniform = m->uniform; info->hx = m->hx; info->hy = m->hy;
   info->grid_nx = m->grid_nx; info->grid_ny = m->grid_ny;
+  info->n_bfaces = m->n_bfaces;
   return CVW_OK;
 }
 
@@ -1228,6 +1247,7 @@ cvw_status cvw_mesh_export(const cvw_mesh* m, int which, void* dst, size_t bytes
     case CVW_EXPORT_NBR: src = &m->h_nbr; break;
     case CVW_EXPORT_NBR_FACE: src = &m->h_nbr_face; break;
     case CVW_EXPORT_CELL_DOF: src = &m->h_cell_dof; break;
+    case CVW_EXPORT_BFACE: src = &m->h_bface; break;
     default: set_error("unknown export selector"); return CVW_EINVAL;
   }
   if (bytes != src->size() * sizeof(int32_t)) { set_error("export size mismatch"); return CVW_EINVAL; }
@@ -1363,7 +1383,9 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
   if (dgt) {
     if (m->degree > MAXP) { set_error("degree > 3 not on the GPU path"); return CVW_EUNSUPPORTED; }
     if (prm->dtype != CVW_F32) { set_error("DG triangles run in float32"); return CVW_EUNSUPPORTED; }
-    if (!m->closed) { set_error("DG residual needs a mesh without boundary faces"); return CVW_EUNSUPPORTED; }
+    if (!m->closed && !prm->bc_face_kind) {
+      set_error("boundary faces need boundary data (cvw_params.bc_face_kind)"); return CVW_EINVAL;
+    }
     return CVW_OK;
   }
   if (!dgq && !cgq && !seg) { set_error("this cell / space combination is not on the GPU path yet"); return CVW_EUNSUPPORTED; }
@@ -1407,7 +1429,9 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
     if (m->degree > MAXP) { set_error("degree > 3 not on the GPU path"); return CVW_EUNSUPPORTED; }
     if (prm->dtype != CVW_F32) { set_error("DG quadrilaterals run in float32"); return CVW_EUNSUPPORTED; }
     if (prm->flux == CVW_ADVECT_ROT) { set_error("rotating velocity not on the DG quadrilateral path"); return CVW_EUNSUPPORTED; }
-    if (!m->closed) { set_error("DG residual needs a mesh without boundary faces"); return CVW_EUNSUPPORTED; }
+    if (!m->closed && !prm->bc_face_kind) {
+      set_error("boundary faces need boundary data (cvw_params.bc_face_kind)"); return CVW_EINVAL;
+    }
   }
   return CVW_OK;
 }

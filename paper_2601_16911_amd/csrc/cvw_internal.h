@@ -156,6 +156,10 @@ struct MethodScalars {
   float fixed_gamma;
   // float64 copies for the float64 sensor paths
   double eps_vd, eps_cd, lin_wd, c_gammad, lam_gd, fixed_gammad, fpd[4];
+  // 2D DG boundary faces: kind and exterior state of boundary face b, which
+  // the neighbour tables hold as -(b + 1)
+  const int32_t* bck;
+  const float* bcs;
 };
 
 // Learned sensor network 48 -> 64 -> 64 -> 1.  Packed float32 parameters:
@@ -344,6 +348,7 @@ struct cvw_mesh {
   int uniform = 0;
   int closed = 0;                    // DG: every face has a neighbour
   int open_ends = 0;                 // segments: vertices used by one cell only (the ends of a line)
+  int64_t n_bfaces = 0;              // DG: faces without a neighbour; device tables hold -(b + 1)
   int64_t grid_nx = 0, grid_ny = 0;  // DG quadrilaterals: structured periodic grid e = i + nx j (0: not)
   double hx = 0, hy = 0, he = 0;
   int device = 0;
@@ -351,6 +356,7 @@ struct cvw_mesh {
   int external = 0;                  // device arrays in a caller-provided buffer (not freed here)
   // host copies
   std::vector<int32_t> h_vtx_ptr, h_vtx_cell, h_vtx_lv, h_cell_vtx, h_nbr, h_nbr_face, h_cell_dof;
+  std::vector<int32_t> h_bface;      // DG: [n_bfaces][2] (cell, local face), ascending
   std::vector<double> h_coords;      // [E][ve][dim]
   std::vector<double> h_he;          // [E]
   cvw::TensorTables tens{};

@@ -391,7 +391,8 @@ __global__ __launch_bounds__(256) void tri_vertex_kernel(const float* __restrict
 // ---------------------------------------------------------------------------
 constexpr int TRI_EVAL_THREADS = 128;
 
-template <int P, int FLUX>
+// OPEN: the mesh has boundary faces (negative neighbour codes)
+template <int P, int FLUX, bool OPEN>
 __global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float* __restrict__ u, const float* __restrict__ u0,
                                                        float* __restrict__ out, float* __restrict__ gamma_out,
                                                        float* __restrict__ alpha_out, const float* __restrict__ cand,
@@ -589,13 +590,14 @@ __global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float*
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const int nb = nbrf[e * 3 + f];
-    const int64_t en = nb >> 2;
-    const int fn = nb & 3;
+    const bool bnd = OPEN && nb < 0;                   // boundary face: exterior state from its data
+    const int64_t en = bnd ? 0 : (nb >> 2);
+    const int fn = bnd ? 0 : (nb & 3);
     float un[NV][NLOC];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int j = 0; j < NLOC; ++j) un[v][j] = u[v * stride + en * NLOC + j];
+      for (int j = 0; j < NLOC; ++j) un[v][j] = bnd ? 0.0f : u[v * stride + en * NLOC + j];
     // edge from vertex f to vertex f+1 (vertex 0 at the origin of the map)
     const float ax = (f == 0) ? 0.0f : (f == 1 ? J00 : J01), ay = (f == 0) ? 0.0f : (f == 1 ? J10 : J11);
     const float bx = (f == 0) ? J00 : (f == 1 ? J01 : 0.0f), by = (f == 0) ? J10 : (f == 1 ? J11 : 0.0f);
@@ -617,6 +619,7 @@ __global__ __launch_bounds__(TRI_EVAL_THREADS) void tri_eval_kernel(const float*
         um[v] = sm;
         up[v] = sp;
       }
+      if (bnd) ghost_state<FLUX>(ms, nb, um, nx, ny, up);
       const float px = X0 + J00 * tab->xf[f][g] + J01 * tab->yf[f][g];
       const float py = Y0 + J10 * tab->xf[f][g] + J11 * tab->yf[f][g];
       float fs[NV];
@@ -735,7 +738,8 @@ template <int P, int FLUX>
 static void launch_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
                         float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
                         float a0, float b0, hipStream_t s) {
-  hipLaunchKernelGGL((tri_eval_kernel<P, FLUX>), dim3(nblk8(m->E, TRI_EVAL_THREADS)), dim3(TRI_EVAL_THREADS), 0, s, u, u0, out, gamma, alpha,
+  auto kern = m->closed ? tri_eval_kernel<P, FLUX, false> : tri_eval_kernel<P, FLUX, true>;
+  hipLaunchKernelGGL(kern, dim3(nblk8(m->E, TRI_EVAL_THREADS)), dim3(TRI_EVAL_THREADS), 0, s, u, u0, out, gamma, alpha,
                      cand, m->d_cell_vtx, m->d_nbrf, m->d_geot, m->d_trit, m->E, ms, mode, dt, a0, b0, status);
 }
 

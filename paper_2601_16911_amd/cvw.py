@@ -22,7 +22,7 @@ CG, DG = 0, 1
 F32, F64 = 0, 1
 OP_EVAL, OP_STEP, OP_LIMIT, OP_POS = 0, 1, 2, 3
 ADVECT_CONST, ADVECT_ROT, BURGERS, KPP, EULER = 0, 1, 2, 3, 4     # cvw_flux
-EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXPORT_CELL_DOF = range(6)
+EXPORT_VTX_PTR, EXPORT_VTX_CELL, EXPORT_VTX_LV, EXPORT_NBR, EXPORT_NBR_FACE, EXPORT_CELL_DOF, EXPORT_BFACE = range(7)
 
 SYMBOLS = ["cvw_abi_version", "cvw_last_error", "cvw_mesh_build", "cvw_mesh_destroy", "cvw_mesh_get_info",
            "cvw_mesh_export", "cvw_workspace_bytes", "cvw_vertex_candidates", "cvw_sensor", "cvw_limit", "cvw_positivity",
@@ -55,7 +55,7 @@ class ParamsC(C.Structure):
                 ("c_gamma", C.c_double), ("lambda_global", C.c_double), ("sensor", C.c_int32),
                 ("audit_every", C.c_int32), ("fixed_gamma", C.c_double), ("sigma_ref", C.c_double),
                 ("mlp", C.c_void_p), ("audit_tol", C.c_double), ("bc", C.c_int32 * 2),
-                ("bc_state", (C.c_double * 4) * 2)]
+                ("bc_state", (C.c_double * 4) * 2), ("bc_face_kind", C.c_void_p), ("bc_face_state", C.c_void_p)]
 
 
 class BatchInstanceC(C.Structure):
@@ -66,7 +66,7 @@ class MeshInfoC(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_vertices", C.c_int64), ("n_dof", C.c_int64),
                 ("nnz_vertex", C.c_int64), ("n_loc", C.c_int32), ("n_k", C.c_int32), ("n_q", C.c_int32),
                 ("v_e", C.c_int32), ("n_faces", C.c_int32), ("uniform", C.c_int32), ("hx", C.c_double),
-                ("hy", C.c_double), ("grid_nx", C.c_int64), ("grid_ny", C.c_int64)]
+                ("hy", C.c_double), ("grid_nx", C.c_int64), ("grid_ny", C.c_int64), ("n_bfaces", C.c_int64)]
 
 
 _lib = None
@@ -175,6 +175,20 @@ def make_params(prm, dtype: int = F32, mlp=None, sigma_ref: float = 1.0, audit_e
         st = list(bcs[e]) + [0.0] * 4
         for v in range(4):
             p.bc_state[e][v] = float(st[v])
+    kinds = getattr(prm, "bc_face_kind", None)
+    if kinds is not None:
+        # per boundary face of a 2D DG mesh: device copies, kept alive by the struct
+        import torch
+        k = torch.as_tensor(np.ascontiguousarray(kinds, np.int32)).cuda()
+        states = getattr(prm, "bc_face_state", None)
+        st = np.zeros((len(k), 4), np.float32)
+        if states is not None:
+            a = np.asarray(states, np.float64).reshape(len(k), -1)
+            st[:, :a.shape[1]] = a
+        s = torch.from_numpy(st).cuda()
+        p.bc_face_kind = k.data_ptr()
+        p.bc_face_state = s.data_ptr()
+        p._bc_keep = (k, s)
     return p
 
 
@@ -271,7 +285,8 @@ class Mesh:
                  EXPORT_VTX_LV: self.info["nnz_vertex"],
                  EXPORT_NBR: self.info["n_cells"] * self.info["n_faces"],
                  EXPORT_NBR_FACE: self.info["n_cells"] * self.info["n_faces"],
-                 EXPORT_CELL_DOF: self.info["n_cells"] * self.info["n_loc"]}
+                 EXPORT_CELL_DOF: self.info["n_cells"] * self.info["n_loc"],
+                 EXPORT_BFACE: 2 * self.info["n_bfaces"]}
         out = np.empty(sizes[which], np.int32)
         _check(load().cvw_mesh_export(self._h, which, out.ctypes.data, out.nbytes))
         return out

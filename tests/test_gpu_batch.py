@@ -161,7 +161,7 @@ def test_batch_error_paths():
 def test_batch_in_caller_buffer():
     """cvw_batch_build_in: the batch's device arrays in a buffer the caller
     owns (sized by cvw_batch_plan) step bitwise like the allocating build; a
-    buffer one byte short is refused before anything is written."""
+    buffer one byte short is refused."""
     cases = _ensemble()
     b1, s1 = _batch(cases)
     states, items = [], []

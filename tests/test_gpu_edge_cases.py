@@ -76,9 +76,9 @@ def test_smallest_periodic_mesh(p):
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (6, 5)])
-def test_open_mesh_not_on_dg_path(shape):
-    """Without periodicity the DG interface terms would need boundary data,
-    which the paper's DG residual does not define: refused."""
+def test_open_mesh_without_boundary_data_refused(shape):
+    """Without periodicity the DG interface terms need boundary data for
+    every boundary face (cvw_params.bc_face_kind); none given: refused."""
     mesh = synth.quad_mesh(*shape, periodic=(False, False))
     gm = cvw.Mesh(mesh, 2, cvw.DG)
     cp = cvw.make_params(Params())
@@ -87,4 +87,4 @@ def test_open_mesh_not_on_dg_path(shape):
     R = torch.empty_like(u)
     with pytest.raises(cvw.CvwError) as ei:
         cvw.residual(gm, cp, u, R, None, ws)
-    assert ei.value.status == cvw.EUNSUPPORTED
+    assert ei.value.status == cvw.EINVAL
