@@ -8,6 +8,7 @@ if the library is missing, load() raises.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 
@@ -190,6 +191,31 @@ def make_params(prm, dtype: int = F32, mlp=None, sigma_ref: float = 1.0, audit_e
         p.bc_face_state = s.data_ptr()
         p._bc_keep = (k, s)
     return p
+
+
+def set_boundary_data(p, kinds=None, states=None, stream=None):
+    """Rewrite, in place and in stream order, the per-face boundary arrays
+    that make_params created (time-dependent data between stages): kinds
+    [n_bfaces], states [n_bfaces, <= 4]."""
+    import torch
+    keep = getattr(p, "_bc_keep", None)
+    if keep is None:
+        raise ValueError("these parameters carry no per-face boundary data")
+    k, s = keep
+    ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+    with ctx:
+        if kinds is not None:
+            kh = np.ascontiguousarray(kinds, np.int32).reshape(-1)
+            if kh.size != k.numel():
+                raise ValueError("one kind per boundary face")
+            k.copy_(torch.from_numpy(kh), non_blocking=False)
+        if states is not None:
+            a = np.asarray(states, np.float64).reshape(k.numel(), -1)
+            if a.shape[1] > 4:
+                raise ValueError("at most 4 state components")
+            st = np.zeros((k.numel(), 4), np.float32)
+            st[:, :a.shape[1]] = a
+            s.copy_(torch.from_numpy(st), non_blocking=False)
 
 
 def _ptr(t):

@@ -335,6 +335,51 @@ def euler1d_conserved(rho, v, p, gas_gamma: float = 1.4):
     return rho, rho * v, p / (gas_gamma - 1.0) + 0.5 * rho * v * v
 
 
+# ---------------------------------------------------------------------------
+# Double Mach reflection (Sec. 5.4) on (0, 4) x (0, 1), gamma 1.4
+# ---------------------------------------------------------------------------
+def dmr_states(gas_gamma: float = 1.4):
+    """Post-shock (L) and pre-shock (R) conserved states (rho, m_x, m_y, E):
+    (rho, v_x, v_y, p) = (8, 8.25 cos 30deg, -8.25 sin 30deg, 116.5) and
+    (1.4, 0, 0, 1)."""
+    def cons(rho, vx, vy, p):
+        return np.array([rho, rho * vx, rho * vy, p / (gas_gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy)])
+    a = np.deg2rad(30.0)
+    return cons(8.0, 8.25 * np.cos(a), -8.25 * np.sin(a), 116.5), cons(1.4, 0.0, 0.0, 1.0)
+
+
+def dmr_shock_x(y, t):
+    """x of the moving Mach 10 shock at height y and time t."""
+    return 1.0 / 6.0 + (y + 20.0 * t) / np.sqrt(3.0)
+
+
+def u0_dmr(x, y, gas_gamma: float = 1.4):
+    """Initial data: the post-shock state left of the shock line, pre-shock
+    right of it; conserved variables [4, ...]."""
+    L, R = dmr_states(gas_gamma)
+    left = np.asarray(x) < dmr_shock_x(np.asarray(y), 0.0)
+    return np.where(left[None], L.reshape((4,) + (1,) * left.ndim), R.reshape((4,) + (1,) * left.ndim))
+
+
+def dmr_boundary(mid, normal, t: float, gas_gamma: float = 1.4):
+    """Kind and exterior state of each boundary face from its midpoint
+    [nb, 2] and outward normal [nb, 2] at time t: the bottom is inflow of the
+    post-shock state for x < 1/6 and a reflecting wall beyond; the left side
+    inflow (post-shock); the right side outflow; the top inflow of the
+    post-shock state left of the moving shock and the pre-shock state right
+    of it.  Returns (kinds [nb] int32, states [nb, 4])."""
+    L, R = dmr_states(gas_gamma)
+    mid = np.asarray(mid, np.float64)
+    n = np.asarray(normal, np.float64)
+    kinds = np.full(len(mid), BC_INFLOW, np.int32)
+    states = np.tile(L, (len(mid), 1))
+    bottom, top, right = n[:, 1] < -0.7, n[:, 1] > 0.7, n[:, 0] > 0.7
+    kinds[bottom & (mid[:, 0] >= 1.0 / 6.0)] = BC_WALL
+    kinds[right] = BC_OUTFLOW
+    states[top & (mid[:, 0] >= dmr_shock_x(1.0, t))] = R
+    return kinds, states
+
+
 def u0_modified_sod(x):
     """Modified Sod shock tube on (0, 1): (rho, v, p) = (1, 0.75, 1) left of
     x = 0.25, (0.125, 0, 0.1) right of it; conserved variables [3, ...]."""
