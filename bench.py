@@ -612,6 +612,86 @@ def bench_line_euler(torch, cvw, steps: int = 20):
     return out
 
 
+def bench_dmr(torch, cvw, ny: int = 96, t_end: float = 0.2, lam_bound: float = 20.0, max_wall: float = 60.0):
+    """The double Mach reflection run of Sec. 5.4 on the paper's mesh (DG Q2,
+    4 ny x ny cells on (0, 4) x (0, 1), 384 x 96 at ny = 96) to t = 0.2: per
+    stage the vertex candidates, the stage (plain sensor, SC quadrature, HLL
+    faces, boundary faces) and the Zhang-Shu limiter in place; the top
+    boundary's states follow the moving shock (rewritten when a face's
+    midpoint is passed).  dt = 0.1 h / ((2p + 1) lam_bound), lam_bound above
+    the largest signal speed of the run.  Reports the step time and the
+    density range at the end (the paper prints its range for the same run)."""
+    import synth
+    p = 2
+    mesh = synth.quad_mesh(4 * ny, ny, x1=4.0, periodic=(False, False))
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    E = mesh.n_cells
+    corners = mesh.cell_coords                                     # [E, 4, 2]
+    nodes = gauss_nodes_2d(p)
+    h = 1.0 / ny
+    X = corners[:, :1, 0] + 0.5 * h * (nodes[None, :, 0] + 1.0)
+    Y = corners[:, :1, 1] + 0.5 * h * (nodes[None, :, 1] + 1.0)
+    U0 = np.asarray(synth.u0_dmr(X, Y), np.float32).reshape(-1)   # [4, E, 9]
+    bf = gm.export(cvw.EXPORT_BFACE).reshape(-1, 2)
+    c, f = bf[:, 0], bf[:, 1]
+    mid = 0.5 * (corners[c, f] + corners[c, (f + 1) % 4])
+    nrm = np.array([[0.0, -1.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]])[f]
+    kinds, states = synth.dmr_boundary(mid, nrm, 0.0)
+    prm = synth.Params(flux=synth.EULER, flux_param=(1.4, 0, 0, 0), bc_face_kind=kinds, bc_face_state=states)
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, cvw.OP_STEP)
+    wp = cvw.alloc_workspace(gm, cp, cvw.OP_POS)
+    cand = torch.zeros(gm.info["n_vertices"] * gm.info["n_k"], dtype=torch.float32, device="cuda")
+    V = torch.from_numpy(U0).cuda()
+    V1, V2 = torch.empty_like(V), torch.empty_like(V)
+    eps0 = 1e-4
+    cvw.positivity(gm, cp, V, V, eps0, wp)
+    dt = 0.1 * h / ((2 * p + 1) * lam_bound)
+    n_steps = int(np.ceil(t_end / dt))
+    dt = t_end / n_steps
+    top = nrm[:, 1] > 0.7
+    cur = [int((top & (mid[:, 0] >= synth.dmr_shock_x(1.0, 0.0))).sum())]
+
+    def stage(us, un, uo, a0, b0, ts):
+        n_r = int((top & (mid[:, 0] >= synth.dmr_shock_x(1.0, ts))).sum())
+        if n_r != cur[0]:                                          # a top face changed sides
+            cvw.set_boundary_data(cp, states=synth.dmr_boundary(mid, nrm, ts)[1])
+            cur[0] = n_r
+        cvw.vertex_candidates(gm, cp, us, cand, ws)
+        cvw.rk_stage(gm, cp, us, cand, un, uo, dt, a0, b0, ws)
+        cvw.positivity(gm, cp, uo, uo, eps0, wp)
+
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    t, done = 0.0, 0
+    for _ in range(n_steps):
+        stage(V, None, V1, 0.0, 1.0, t)
+        stage(V1, V, V2, 0.75, 0.25, t + dt)
+        stage(V2, V, V, 1.0 / 3.0, 2.0 / 3.0, t + 0.5 * dt)
+        t += dt
+        done += 1
+        if done % 500 == 0:
+            torch.cuda.synchronize()
+            if time.perf_counter() - w0 > max_wall:
+                break
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_s = e0.elapsed_time(e1) / 1e3
+    flags = cvw.poll_status(gm, ws)
+    rho = V[:E * 9]
+    return {"workload": f"double Mach reflection, DG Q2 on {4 * ny} x {ny} quads (0,4)x(0,1), Euler, plain sensor + "
+                        f"SC quadrature, Zhang-Shu limiter (eps0 {eps0}) after every stage, moving top boundary data",
+            "cells": E, "dofs": 4 * E * 9, "steps": done, "t_reached": t, "dt": dt,
+            "ms_per_step": gpu_s / done * 1e3, "wall_s": wall,
+            "value": 3 * 4 * E * 9 * done / gpu_s, "unit": "DOF-updates/s",
+            "rho_min": float(rho.min()), "rho_max": float(rho.max()),
+            "paper_rho_range_sc": [1.274, 22.423], "status_flags": flags}
+
+
 def _cg_gather(gm, vals):
     """Global CG vector from values at every cell's local nodes [E, n_loc]
     (the first occurrence of each DOF in (cell, local node) order)."""
@@ -636,11 +716,11 @@ def main():
                     help="also run one 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch shapes (no autotuner launches before the timed region)")
-    ap.add_argument("--part", choices=("step", "sensor", "learned", "small", "tri"), default="step",
+    ap.add_argument("--part", choices=("step", "sensor", "learned", "small", "tri", "dmr"), default="step",
                     help="sensor / learned: only the plain or learned sensor pass, --steps calls after --warmup "
                          "(a short program for kernel traces and counters); small: only the 1D and CG "
                          "rotation workloads; tri: only the KPP triangle residual on 2048 x 2048 squares, --steps "
-                         "calls")
+                         "calls; dmr: only the double Mach reflection run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is benchmarked on one MI355X; "
@@ -654,6 +734,9 @@ def main():
     torch.cuda.set_device(0)
     if args.part == "tri":
         print(json.dumps(bench_triangles(torch, cvw, args.steps, n=2048, limiter=False)))
+        return
+    if args.part == "dmr":
+        print(json.dumps(bench_dmr(torch, cvw)))
         return
     if args.part == "small":
         out = bench_small_configs(torch, cvw)
@@ -827,6 +910,8 @@ def main():
         out["hweno_limiter"] = bench_limiter(torch, cvw, gm, prm, U, dt)
         torch.cuda.empty_cache()
         out["positivity_limiter"] = bench_positivity(torch, cvw, gm, prm, U)
+        torch.cuda.empty_cache()
+        out["double_mach"] = bench_dmr(torch, cvw)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
