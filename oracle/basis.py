@@ -86,14 +86,20 @@ def stroud_triangle(n: int):
 
 def multi_indices(dim: int, p: int):
     """Derivative multi-indices k with 1 <= |k| <= p, ordered by |k|, then by
-    decreasing first component: (1,0),(0,1),(2,0),(1,1),(0,2),..."""
+    decreasing first component, then decreasing second: (1,0),(0,1),(2,0),
+    (1,1),(0,2),... in 2D; (1,0,0),(0,1,0),(0,0,1),(2,0,0),(1,1,0),(1,0,1),
+    (0,2,0),... in 3D."""
     out = []
     for n in range(1, p + 1):
         if dim == 1:
             out.append((n,))
-        else:
+        elif dim == 2:
             for j in range(n + 1):
                 out.append((n - j, j))
+        else:
+            for a in range(n, -1, -1):
+                for b in range(n - a, -1, -1):
+                    out.append((a, b, n - a - b))
     return out
 
 
@@ -204,8 +210,64 @@ class RefTri:
         return pts, self.face_w
 
 
+class RefHex:
+    """Tensor-product Lagrange element on [-1, 1]^3 (DG: Gauss-Legendre nodes),
+    local node a + (p+1) b + (p+1)^2 c (x fastest).  Vertices in the order of
+    the mesh: the face z = -1 counter-clockwise from (-1,-1), then z = +1.
+    Faces: 2 axis + side (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z); the points of a
+    face are the tensor Gauss rule in its two tangential directions, the
+    lower axis fastest, so that opposite faces share one parametrisation."""
+    dim = 3
+    n_vert = 8
+    n_faces = 6
+
+    def __init__(self, p: int, nodes: str):
+        self.p = p
+        x, _ = gauss_legendre(p + 1) if nodes == "gauss" else gauss_lobatto(p + 1)
+        self.x1d = x
+        self.L = Lagrange1D(x)
+        self.n_loc = (p + 1) ** 3
+        self.nodes = self._tensor(x)
+        self.vertices = np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
+                                  [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], dtype=np.float64)
+        qx, qw = gauss_legendre(p + 1)
+        self.vol_pts = self._tensor(qx)
+        self.vol_w = np.einsum("c,b,a->cba", qw, qw, qw).ravel()
+        qx2, qw2 = gauss_legendre(p + 2)
+        self.norm_pts = self._tensor(qx2)
+        self.norm_w = np.einsum("c,b,a->cba", qw2, qw2, qw2).ravel()
+        self.face_x, self.face_w1 = gauss_legendre(p + 1)
+
+    @staticmethod
+    def _tensor(x):
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")          # x fastest
+        return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+    def deriv(self, pts, m):
+        pts = np.asarray(pts)
+        Lx = self.L(pts[:, 0], m[0])
+        Ly = self.L(pts[:, 1], m[1])
+        Lz = self.L(pts[:, 2], m[2])
+        return (Lz[:, :, None, None] * Ly[:, None, :, None] * Lx[:, None, None, :]).reshape(len(pts), -1)
+
+    def face_points(self, f):
+        axis, side = divmod(f, 2)
+        t = [a for a in range(3) if a != axis]
+        s = self.face_x
+        S1, S0 = np.meshgrid(s, s, indexing="ij")             # t[0] fastest
+        pts = np.empty((S0.size, 3))
+        pts[:, axis] = 1.0 if side else -1.0
+        pts[:, t[0]] = S0.ravel()
+        pts[:, t[1]] = S1.ravel()
+        return pts, np.outer(self.face_w1, self.face_w1).ravel()
+
+
 def make_ref(cell: int, p: int, space: int):
-    """cell: 1 segment, 2 triangle, 3 quadrilateral; space: 0 CG, 1 DG."""
+    """cell: 1 segment, 2 triangle, 3 quadrilateral, 4 hexahedron; space: 0 CG, 1 DG."""
+    if cell == 4:
+        if space != 1:
+            raise NotImplementedError("hexahedra: DG only")
+        return RefHex(p, "gauss")
     if cell == 1:
         return RefSeg(p, "lobatto" if space == 0 else "gauss")
     if cell == 3:

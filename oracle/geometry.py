@@ -6,7 +6,8 @@ rule with the constant inverse Jacobian A = J^{-1}:
 
     d^n u / dx_{a1}..dx_{an} = sum_{b1..bn} A_{b1 a1} .. A_{bn an} d^n u / dxi_{b1}..dxi_{bn}.
 
-Jittered quadrilaterals are bilinear, not affine (a reading of the paper for
+Hexahedra are trilinear maps of [-1, 1]^3 (affine for the boxes of the
+structured meshes used here).  Jittered quadrilaterals are bilinear, not affine (a reading of the paper for
 that workload): there the second derivatives gain the term of the inverse
 map's Hessian,
 
@@ -37,6 +38,8 @@ def map_jacobian(cell: int, X: np.ndarray, pts: np.ndarray):
         J1 = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]], axis=-1)   # [E, d, 2]
         J = np.broadcast_to(J1[:, None], (E, n, 2, 2)).copy()
         return J, np.zeros((E, n, 2, 2, 2))
+    if cell == 4:
+        return _trilinear_jacobian(X, pts)
     # bilinear quadrilateral, reference vertices (-1,-1),(1,-1),(1,1),(-1,1)
     s = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], dtype=np.float64)
     xi, eta = pts[:, 0], pts[:, 1]
@@ -52,8 +55,38 @@ def map_jacobian(cell: int, X: np.ndarray, pts: np.ndarray):
     return J, H
 
 
+_HEX_S = np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
+                   [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], dtype=np.float64)
+
+
+def _trilinear_shape(pts):
+    """Shape functions N_v = prod_a (1 + s_va xi_a) / 8 [n, 8], their first
+    derivatives [n, 8, 3] and second derivatives [n, 8, 3, 3] (zero diagonal)."""
+    f = 1.0 + _HEX_S[None, :, :] * pts[:, None, :]              # [n, 8, 3]
+    N = f.prod(-1) / 8.0
+    dN = np.empty(f.shape)
+    d2N = np.zeros(f.shape + (3,))
+    for a in range(3):
+        o = [b for b in range(3) if b != a]
+        dN[:, :, a] = _HEX_S[None, :, a] * f[:, :, o[0]] * f[:, :, o[1]] / 8.0
+        for b in o:
+            c = 3 - a - b
+            d2N[:, :, a, b] = _HEX_S[None, :, a] * _HEX_S[None, :, b] * f[:, :, c] / 8.0
+    return N, dN, d2N
+
+
+def _trilinear_jacobian(X, pts):
+    _, dN, d2N = _trilinear_shape(np.asarray(pts, np.float64))
+    J = np.einsum("nva,evm->enma", dN, X)
+    H = np.einsum("nvab,evm->enmab", d2N, X)
+    return J, H
+
+
 def map_points(cell: int, X: np.ndarray, pts: np.ndarray):
     """Physical coordinates [E, n, d] of reference points pts [n, d]."""
+    if cell == 4:
+        N, _, _ = _trilinear_shape(np.asarray(pts, np.float64))
+        return np.einsum("nv,evd->end", N, X)
     if cell == 1:
         return (X[:, 0, 0][:, None] + 0.5 * (pts[None, :, 0] + 1.0) * (X[:, 1, 0] - X[:, 0, 0])[:, None])[..., None]
     if cell == 2:

@@ -36,6 +36,33 @@ def face_vertex_pairs(cell: int, cell_vertices: np.ndarray):
     return np.stack([a, b], axis=2)
 
 
+# local vertices of the six faces of a hexahedron, face 2 axis + side
+# (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z), vertex order of synth.hex_mesh
+HEX_FACE_VERTICES = np.array([[0, 3, 7, 4], [1, 2, 6, 5], [0, 1, 5, 4], [3, 2, 6, 7],
+                              [0, 1, 2, 3], [4, 5, 6, 7]])
+
+
+def hex_face_neighbours(cell_vertices: np.ndarray):
+    """(nbr [E, 6], nbr_face [E, 6]) of hexahedra: two faces match when they
+    hold the same four vertices; -1 on boundary faces."""
+    E = cell_vertices.shape[0]
+    fv = np.sort(cell_vertices[:, HEX_FACE_VERTICES], axis=2).astype(np.int64)   # [E, 6, 4]
+    keys = {}
+    for e in range(E):
+        for f in range(6):
+            keys.setdefault(tuple(fv[e, f]), []).append((e, f))
+    nbr = -np.ones((E, 6), np.int64)
+    nbr_face = -np.ones((E, 6), np.int64)
+    for ents in keys.values():
+        if len(ents) > 2:
+            raise ValueError("non-conforming mesh: face shared by more than two cells")
+        if len(ents) == 2:
+            (e0, f0), (e1, f1) = ents
+            nbr[e0, f0], nbr_face[e0, f0] = e1, f1
+            nbr[e1, f1], nbr_face[e1, f1] = e0, f0
+    return nbr, nbr_face
+
+
 def face_neighbours(cell: int, cell_vertices: np.ndarray):
     """(nbr [E, F], nbr_face [E, F]); -1 on boundary faces.
 
@@ -43,6 +70,8 @@ def face_neighbours(cell: int, cell_vertices: np.ndarray):
     consistently oriented mesh the neighbour traverses the shared face in the
     opposite direction, which is checked here.
     """
+    if cell == 4:
+        return hex_face_neighbours(cell_vertices)
     E = cell_vertices.shape[0]
     fv = face_vertex_pairs(cell, cell_vertices)
     F = fv.shape[1]

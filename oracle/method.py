@@ -182,6 +182,8 @@ def sc_weights(sp, s, gamma, prm: Params, pg=None, return_parts: bool = False):
 def flux(prm: Params, U, x):
     """Physical flux f(U) [n_var, ..., d] at points x [..., d]."""
     d = x.shape[-1]
+    if prm.flux in (KPP, ADVECT_ROT) and d != 2:
+        raise ValueError("the KPP and rotating-advection fluxes are two-dimensional")
     if prm.flux == ADVECT_CONST:
         v = np.array(prm.flux_param[:d])
         return U[..., None] * v
@@ -196,6 +198,8 @@ def flux(prm: Params, U, x):
         return np.stack([np.sin(U), np.cos(U)], axis=-1)
     if prm.flux == EULER:
         g = prm.flux_param[0]
+        if d == 3:
+            raise NotImplementedError("the Euler equations in 3D")
         if d == 1:                                  # (rho, m, E) on a line
             rho, mx, En = U
             vx = mx / rho
@@ -508,11 +512,24 @@ def residual(sp, U, prm: Params, gamma=None, return_parts: bool = False, allow_b
 
 
 def face_geometry(sp, f):
-    """Outward unit normal [E, d] and face Jacobian (length / 2) [E] of face f."""
+    """Outward unit normal [E, d] and face Jacobian [E] of face f (the length / 2
+    of an edge; the area / 4 of a flat hexahedron face, whose reference face
+    [-1, 1]^2 has area 4)."""
     X = sp.X
     if sp.cell == 1:
         n = np.full((sp.E, 1), -1.0 if f == 0 else 1.0)
         return n, np.ones(sp.E)
+    if sp.cell == 4:
+        from .mesh import HEX_FACE_VERTICES
+        c = HEX_FACE_VERTICES[f]
+        t1 = 0.5 * (X[:, c[1]] - X[:, c[0]])
+        t2 = 0.5 * (X[:, c[3]] - X[:, c[0]])
+        cr = np.cross(t1, t2)
+        area4 = np.linalg.norm(cr, axis=1)
+        n = cr / area4[:, None]
+        out = (X[:, c].mean(1) - X.mean(1))                      # from the cell centre to the face centre
+        n = np.where(((n * out).sum(1) < 0)[:, None], -n, n)
+        return n, area4
     nvx = X.shape[1]
     t = X[:, (f + 1) % nvx] - X[:, f]
     L = np.hypot(t[:, 0], t[:, 1])
@@ -535,7 +552,9 @@ def face_terms(sp, Uc, prm: Params, allow_boundary: bool = False):
         Um = np.einsum("vej,gj->veg", Uc, phif)
         en, fn = sp.nbr[:, f], sp.nbr_face[:, f]
         Up = Um.copy()                                             # boundary faces: zero jump, dropped below
-        for f2 in range(ref.n_faces):
+        if sp.cell == 4:
+            Up[:, en >= 0] = _hex_neighbour_traces(sp, Uc, f, en, fn)[:, en >= 0]
+        for f2 in range(ref.n_faces if sp.cell != 4 else 0):
             sel = fn == f2
             if not sel.any():
                 continue
@@ -549,6 +568,31 @@ def face_terms(sp, Uc, prm: Params, allow_boundary: bool = False):
         Fs = numerical_flux(prm, Um, Up, nb, xf)                   # [nv, E, ng]
         Fs = np.where((en >= 0)[None, :, None], Fs, 0.0)
         out += np.einsum("g,e,gj,veg->vej", wf, Jf, phif, Fs)
+    return out
+
+
+def _hex_neighbour_traces(sp, Uc, f, en, fn):
+    """The neighbour's trace at the points of face f of every cell [nv, E, ng].
+    The points are paired by position: the neighbour's face points, moved by
+    the offset between the two face centres (zero, or a period of the domain
+    when the neighbour lies across a periodic boundary), must coincide with
+    the cell's own."""
+    ref = sp.ref
+    pts, _ = ref.face_points(f)
+    xf = map_points(sp.cell, sp.X, pts)                            # [E, ng, 3]
+    out = np.zeros((Uc.shape[0], sp.E, len(pts)))
+    for e in range(sp.E):
+        if en[e] < 0:
+            continue
+        p2, _ = ref.face_points(int(fn[e]))
+        x2 = map_points(sp.cell, sp.X[en[e]:en[e] + 1], p2)[0]
+        x2 = x2 - x2.mean(0) + xf[e].mean(0)
+        dist = np.linalg.norm(xf[e][:, None, :] - x2[None, :, :], axis=2)
+        perm = dist.argmin(1)
+        if dist[np.arange(len(pts)), perm].max() > 1e-9 * sp.h[e] or len(set(perm)) != len(pts):
+            raise ValueError("face points of neighbouring cells do not coincide")
+        phi2 = ref.deriv(p2[perm], (0,) * ref.dim)
+        out[:, e] = np.einsum("vj,gj->vg", Uc[:, en[e]], phi2)
     return out
 
 

@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SEG, TRI, QUAD = 1, 2, 3
+SEG, TRI, QUAD, HEX = 1, 2, 3, 4
 CG, DG = 0, 1
 ADVECT_CONST, ADVECT_ROT, BURGERS, KPP, EULER = 0, 1, 2, 3, 4
 # boundary data at the two ends of a non-periodic 1D domain
@@ -39,7 +39,7 @@ class MeshDesc:
     cell_vertices: np.ndarray  # int32 [E, v_e]
     cell_coords: np.ndarray    # float64 [E, v_e, dim]
     periodic: tuple = (1, 1)
-    shape: tuple = ()          # logical (nx,) or (nx, ny), informative only
+    shape: tuple = ()          # logical (nx,), (nx, ny) or (nx, ny, nz), informative only
 
     @property
     def n_cells(self) -> int:
@@ -117,6 +117,28 @@ def tri_mesh(nx: int, ny: int, x0=0.0, x1=1.0, y0=0.0, y1=1.0, jitter: float = 0
         cv[t::2] = np.stack([vid(a, b) for a, b in tri], axis=1)
         cc[t::2] = np.stack([pos(a, b) for a, b in tri], axis=1)
     return MeshDesc(2, TRI, nv, cv, cc, tuple(int(p) for p in periodic), (nx, ny))
+
+
+def hex_mesh(nx: int, ny: int, nz: int, x0=0.0, x1=1.0, y0=0.0, y1=1.0, z0=0.0, z1=1.0,
+             periodic=(True, True, True)) -> MeshDesc:
+    """Structured mesh of congruent axis-aligned boxes, cell e = i + nx (j + ny k).
+    Local vertices: the bottom face (z = z_k) counter-clockwise from (i, j),
+    then the top face in the same order.  Coordinates are unwrapped per cell
+    (a cell across a periodic boundary keeps its own box)."""
+    hx, hy, hz = (x1 - x0) / nx, (y1 - y0) / ny, (z1 - z0) / nz
+    px, py, pz = periodic
+    nvx, nvy, nvz = (nx if px else nx + 1), (ny if py else ny + 1), (nz if pz else nz + 1)
+
+    def vid(i, j, k):
+        return ((i % nx if px else i) + nvx * ((j % ny if py else j) + nvy * (k % nz if pz else k)))
+
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    corners = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+    cv = np.stack([vid(i + a, j + b, k + c) for a, b, c in corners], axis=1).astype(np.int32)
+    cc = np.stack([np.stack([x0 + (i + a) * hx, y0 + (j + b) * hy, z0 + (k + c) * hz], axis=-1)
+                   for a, b, c in corners], axis=1).astype(np.float64)
+    return MeshDesc(3, HEX, nvx * nvy * nvz, cv, cc, tuple(int(q) for q in periodic), (nx, ny, nz))
 
 
 # ---------------------------------------------------------------------------
