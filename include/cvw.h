@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 10
+#define CVW_ABI_VERSION 11
 
 typedef enum {
   CVW_OK = 0,
@@ -62,7 +62,16 @@ typedef enum {
   CVW_ENUMERIC = 5         /* cvw_poll_status: device flagged a numerical problem   */
 } cvw_status;
 
-typedef enum { CVW_SEG = 1, CVW_TRI = 2, CVW_QUAD = 3 } cvw_cell;
+/* Hexahedra (CVW_HEX, dim 3): DG Q_p, p <= 2, on congruent axis-aligned
+ * boxes of a periodic mesh, scalar fluxes (constant advection, Burgers),
+ * float32.  The vertex-based candidates of a cube: eight per cell (Sec. 3.2,
+ * the remark on stencil sizes).  Local vertices: the face z = z0
+ * counter-clockwise from the lowest corner, then the face z = z0 + hz in the
+ * same order; local node a + (p+1) b + (p+1)^2 c at the tensor Gauss points
+ * (x fastest); local faces 2 axis + side (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z);
+ * cell_coords [E][8][3]; flux_param[0..2] is the velocity (or the Burgers
+ * direction) (vx, vy, vz). */
+typedef enum { CVW_SEG = 1, CVW_TRI = 2, CVW_QUAD = 3, CVW_HEX = 4 } cvw_cell;
 typedef enum { CVW_CG = 0, CVW_DG = 1 } cvw_space;
 typedef enum {
   CVW_ADVECT_CONST = 0,    /* f = v u, v = (flux_param[0], flux_param[1])                    */

@@ -1,0 +1,448 @@
+// DG on hexahedra (Q_1, Q_2 on congruent axis-aligned boxes, Gauss nodes):
+//
+//  * hex_vertex_kernel -- one thread per mesh vertex: the Hermite data
+//    D^k u^e(x_i), 1 <= |k| <= p, of each of the eight cells of the vertex
+//    patch (eq. taylorsol) from tabulated corner derivatives of the Lagrange
+//    basis, the pointwise smoothness indicators and Jiang-Shu weights, and the
+//    vertex candidate (eq. taylorcand), Sec. 3.2.  Float64 accumulation.
+//  * hex_eval_kernel -- a team of lanes per cell, one lane per node (8 lanes
+//    for Q_1, 27 of 32 for Q_2): the cell-vertex WENO sensor (eq. finalweno,
+//    eq. gamma) in float64, the viscosity (eq. lostab), the shock-capturing
+//    weights (eqs. dissrateorig to alphaq), the volume and interface terms of
+//    the DG residual in float32, and optionally the Runge-Kutta stage update
+//    with the exact (diagonal, Gauss-collocated) element mass.
+//
+// The sensor works in the monomials xi^A of the cell's reference coordinates
+// about its centre: the cell polynomial (its nodal values less the first one,
+// so that constant data gives exact zeros) and the eight vertex candidates
+// (Taylor polynomials about the corners, re-expanded about the centre) are
+// coefficient vectors, and every element semi-norm of eq. snorm is the
+// quadratic form of one Gram matrix of the monomials (exact integrals, built
+// on the host for the mesh's box).  The team exchanges nodal values,
+// coefficients and quadrature terms through LDS and reduces with
+// cross-lane shuffles; idle lanes of a Q_2 team carry zeros.
+#include "cvw_device.h"
+
+namespace cvw {
+
+template <int P>
+struct HexShape {
+  static constexpr int N1 = P + 1, NL = N1 * N1 * N1, NK = (P + 1) * (P + 2) * (P + 3) / 6 - 1;
+  static constexpr int TEAM = NL <= 8 ? 8 : 32;      // lanes per cell, a power of two within a wavefront
+  static constexpr int CPB = 256 / TEAM;             // cells per block of 256 threads
+};
+
+template <int TEAM>
+__device__ __forceinline__ double team_sum(double x) {
+#pragma unroll
+  for (int m = TEAM / 2; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+  return x;
+}
+template <int TEAM>
+__device__ __forceinline__ float team_sumf(float x) {
+#pragma unroll
+  for (int m = TEAM / 2; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+  return x;
+}
+template <int TEAM>
+__device__ __forceinline__ float team_maxf(float x) {
+#pragma unroll
+  for (int m = TEAM / 2; m >= 1; m >>= 1) x = fmaxf(x, __shfl_xor(x, m));
+  return x;
+}
+
+// scalar fluxes in 3D: f_d(u) = v_d u (constant advection) or u^2 / 2 b_d (Burgers)
+template <int FLUX>
+__device__ __forceinline__ float hex_flux(const MethodScalars& ms, float u, int d) {
+  if constexpr (FLUX == CVW_BURGERS) return 0.5f * u * u * ms.fp[d];
+  else return ms.fp[d] * u;
+}
+template <int FLUX>
+__device__ __forceinline__ float hex_speed(const MethodScalars& ms, float u) {
+  const float vn = fsqrt(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1] + ms.fp[2] * ms.fp[2]);
+  if constexpr (FLUX == CVW_BURGERS) return fabsf(u) * vn;
+  else return vn;
+}
+
+// ---------------------------------------------------------------------------
+// vertex pass
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void hex_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
+                                                         const int32_t* __restrict__ vptr,
+                                                         const int32_t* __restrict__ vent,
+                                                         const HexTables* __restrict__ tab, int64_t Nv,
+                                                         MethodScalars ms) {
+  using S = HexShape<P>;
+  constexpr int NL = S::NL, NK = S::NK;
+  __shared__ double sHV[8][NK][NL];
+  for (int i = threadIdx.x; i < 8 * NK * NL; i += blockDim.x) {
+    const int l = i / (NK * NL), r = i % (NK * NL);
+    sHV[l][r / NL][r % NL] = tab->HV[l][r / NL][r % NL];
+  }
+  __syncthreads();
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= Nv) return;
+  double acc[NK], wsum = 0.0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) acc[k] = 0.0;
+  for (int32_t i = vptr[v]; i < vptr[v + 1]; ++i) {
+    const int32_t ent = vent[i];
+    const int64_t ce = ent >> 3;
+    const int lv = ent & 7;
+    const float* uc = u + ce * NL;
+    const double u0 = static_cast<double>(uc[0]);
+    double H[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) H[k] = 0.0;
+#pragma unroll
+    for (int j = 1; j < NL; ++j) {
+      const double dj = static_cast<double>(uc[j]) - u0;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) H[k] = fma(sHV[lv][k][j], dj, H[k]);
+    }
+    double b2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) b2 = fma(tab->hb[k] * H[k], H[k], b2);
+    double beta = sqrt(b2);
+    double w;
+    if (ms.fast_exp) {
+      const double t = ms.eps_vd + beta;
+      w = 1.0 / (t * t);
+    } else {
+      beta = pow(beta, static_cast<double>(ms.q_beta));
+      w = pow(ms.eps_vd + beta, -static_cast<double>(ms.r));
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) acc[k] = fma(w, H[k], acc[k]);
+    wsum += w;
+  }
+  const double iw = 1.0 / wsum;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) cand[v * NK + k] = static_cast<float>(acc[k] * iw);
+}
+
+// ---------------------------------------------------------------------------
+// cell pass
+// ---------------------------------------------------------------------------
+// reference derivative d_xi^kx d_eta^ky d_zeta^kz of the cell polynomial at
+// node (ta, tb, tc) from the nodal values in LDS (orders 0..2 per direction)
+template <int N1>
+__device__ __forceinline__ float hex_ref_deriv(const HexTables* __restrict__ tab, const float* su, int ta, int tb,
+                                               int tc, int kx, int ky, int kz) {
+  float out = 0.0f;
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    const float cx = kx == 0 ? (i == ta ? 1.0f : 0.0f) : (kx == 1 ? tab->D1[ta][i] : tab->D2[ta][i]);
+    if (cx == 0.0f) continue;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      const float cy = ky == 0 ? (j == tb ? 1.0f : 0.0f) : (ky == 1 ? tab->D1[tb][j] : tab->D2[tb][j]);
+      if (cy == 0.0f) continue;
+#pragma unroll
+      for (int l = 0; l < N1; ++l) {
+        const float cz = kz == 0 ? (l == tc ? 1.0f : 0.0f) : (kz == 1 ? tab->D1[tc][l] : tab->D2[tc][l]);
+        out = fmaf(cx * cy * cz, su[i + N1 * (j + N1 * l)], out);
+      }
+    }
+  }
+  return out;
+}
+
+template <int P, int FLUX>
+__global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__ u, const float* __restrict__ u0,
+                                                       float* __restrict__ out, float* __restrict__ gamma_out,
+                                                       float* __restrict__ alpha_out, const float* __restrict__ cand,
+                                                       const int32_t* __restrict__ cell_vtx,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const HexTables* __restrict__ tab, int64_t E, int64_t nblk,
+                                                       MethodScalars ms, int mode, float dt, float a0, float b0,
+                                                       uint32_t* __restrict__ status) {
+  using S = HexShape<P>;
+  constexpr int N1 = S::N1, NL = S::NL, NK = S::NK, TEAM = S::TEAM, CPB = S::CPB;
+  __shared__ double sG[NL][NL];
+  __shared__ double sR[8][NK][NK];
+  __shared__ int sMono[NK];
+  __shared__ float su[CPB][NL];
+  __shared__ float sn[CPB][6][NL];
+  __shared__ double sa[CPB][NL], sb[CPB][NL];
+  __shared__ double ss[CPB][8][NK], sq[CPB][8][NK];
+  __shared__ float sv[CPB][3][NL];
+  for (int i = threadIdx.x; i < NL * NL; i += blockDim.x) sG[i / NL][i % NL] = tab->G[i / NL][i % NL];
+  for (int i = threadIdx.x; i < 8 * NK * NK; i += blockDim.x) {
+    const int l = i / (NK * NK), r = i % (NK * NK);
+    sR[l][r / NK][r % NK] = tab->R[l][r / NK][r % NK];
+  }
+  if (threadIdx.x < NK)
+    sMono[threadIdx.x] = tab->kk[threadIdx.x][0] + N1 * (tab->kk[threadIdx.x][1] + N1 * tab->kk[threadIdx.x][2]);
+  const int slot = threadIdx.x / TEAM, t = threadIdx.x % TEAM;
+  const bool lane_on = t < NL;
+  const int tn = lane_on ? t : 0;
+  const int ta = tn % N1, tb = (tn / N1) % N1, tc = tn / (N1 * N1);
+  const float W = tab->w1[ta] * tab->w1[tb] * tab->w1[tc] * tab->W0;
+  const bool plain = ms.sensor_kind != CVW_SENSOR_FIXED;
+  bool nonfinite = false;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t e = blk * CPB + slot;
+    const bool cell_on = e < E;
+    const bool on = lane_on && cell_on;
+    // ---- nodal values of the cell and of its six face neighbours
+    const float uv = on ? u[e * NL + t] : 0.0f;
+    if (lane_on) su[slot][t] = uv;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int64_t en = cell_on ? nbr[e * 6 + f] : 0;
+      if (lane_on) sn[slot][f][t] = on ? u[en * NL + t] : 0.0f;
+    }
+    __syncthreads();
+
+    // ---- sensor gamma_e (float64)
+    float gam = ms.fixed_gamma;
+    if (plain) {
+      const double u00 = static_cast<double>(su[slot][0]);
+      if (lane_on) {                     // monomial coefficients of u - u_0: x, then y, then z
+        double c = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j)
+          c = fma(tab->T1[ta][j], static_cast<double>(su[slot][j + N1 * (tb + N1 * tc)]) - u00, c);
+        sa[slot][t] = c;
+      }
+      __syncthreads();
+      if (lane_on) {
+        double c = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) c = fma(tab->T1[tb][j], sa[slot][ta + N1 * (j + N1 * tc)], c);
+        sb[slot][t] = c;
+      }
+      __syncthreads();
+      double cA = 0.0;
+      if (lane_on) {
+#pragma unroll
+        for (int j = 0; j < N1; ++j) cA = fma(tab->T1[tc][j], sb[slot][ta + N1 * (tb + N1 * j)], cA);
+        sa[slot][t] = cA;
+      }
+      // the vertex candidates about the centre: lane pairs (vertex l, multi-index a)
+      for (int i = t; i < 8 * NK; i += TEAM) {
+        const int l = i / NK, a = i % NK;
+        double acc = 0.0;
+        if (cell_on) {
+          const float* cv = cand + static_cast<int64_t>(cell_vtx[e * 8 + l]) * NK;
+#pragma unroll
+          for (int k = 0; k < NK; ++k) acc = fma(sR[l][a][k], static_cast<double>(cv[k]), acc);
+        }
+        ss[slot][l][a] = acc;
+      }
+      __syncthreads();
+      // ||u_h||_e^2 = c^T G c
+      double g = 0.0;
+      if (lane_on) {
+#pragma unroll
+        for (int B = 0; B < NL; ++B) g = fma(sG[t][B], sa[slot][B], g);
+      }
+      const double n02 = team_sum<TEAM>(cA * g);
+      for (int i = t; i < 8 * NK; i += TEAM) {
+        const int l = i / NK, a = i % NK;
+        double q = 0.0;
+#pragma unroll
+        for (int b = 0; b < NK; ++b) q = fma(sG[sMono[a]][sMono[b]], ss[slot][l][b], q);
+        sq[slot][l][a] = ss[slot][l][a] * q;
+      }
+      __syncthreads();
+      // weights of the cell candidate and the eight vertex candidates (every lane alike)
+      double om[9], beta[9];
+      beta[0] = sqrt(fmax(n02, 0.0));
+#pragma unroll
+      for (int l = 0; l < 8; ++l) {
+        double b2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < NK; ++a) b2 += sq[slot][l][a];
+        beta[l + 1] = sqrt(fmax(b2, 0.0));
+      }
+      const double n0 = beta[0];
+      double wsum = 0.0;
+#pragma unroll
+      for (int l = 0; l < 9; ++l) {
+        const double lin = l == 0 ? 1.0 - 8.0 * ms.lin_wd : ms.lin_wd;
+        double w;
+        if (ms.fast_exp) {
+          const double tt = ms.eps_cd + beta[l];
+          w = lin / (tt * tt);
+        } else {
+          w = lin * pow(ms.eps_cd + pow(beta[l], static_cast<double>(ms.q_beta)), -static_cast<double>(ms.r));
+        }
+        om[l] = w;
+        wsum += w;
+      }
+      double osum = 0.0;
+#pragma unroll
+      for (int l = 0; l < 9; ++l) {
+        om[l] /= wsum;
+        if (l > 0) osum += om[l];
+      }
+      // u_h - sum_l omega_l (u_h - s_l)'s complement: diff = sum_l omega_l (u_h - s_l)
+      double Dv = 0.0;
+      if (lane_on) {
+        Dv = osum * cA;
+        const int a = tab->kmono[t];
+        if (a >= 0) {
+#pragma unroll
+          for (int l = 0; l < 8; ++l) Dv = fma(-om[l + 1], ss[slot][l][a], Dv);
+        }
+        sb[slot][t] = Dv;
+      }
+      __syncthreads();
+      double gd = 0.0;
+      if (lane_on) {
+#pragma unroll
+        for (int B = 0; B < NL; ++B) gd = fma(sG[t][B], sb[slot][B], gd);
+      }
+      const double d2 = team_sum<TEAM>(Dv * gd);
+      if (n0 > 0.0) {
+        double ratio = fmin(1.0, sqrt(fmax(d2, 0.0)) / n0);
+        if (!ms.fast_exp) ratio = pow(ratio, static_cast<double>(ms.q_sensor));
+        gam = static_cast<float>(1.0 - ratio);
+      } else {
+        gam = 1.0f;
+      }
+    }
+
+    // ---- viscosity (eq. lostab) and the physical gradient at the node
+    float lam = ms.lam_g;
+    if (!(lam > 0.0f)) lam = team_maxf<TEAM>(lane_on ? hex_speed<FLUX>(ms, uv) : 0.0f);
+    const float nu = lam * tab->nuf;
+    float gr[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      gr[0] = fmaf(tab->D1[ta][j], su[slot][j + N1 * (tb + N1 * tc)], gr[0]);
+      gr[1] = fmaf(tab->D1[tb][j], su[slot][ta + N1 * (j + N1 * tc)], gr[1]);
+      gr[2] = fmaf(tab->D1[tc][j], su[slot][ta + N1 * (tb + N1 * j)], gr[2]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gr[d] *= tab->sc[d];
+
+    // ---- shock-capturing weights (cells with gamma_e < C_gamma)
+    float alpha = 1.0f;
+    if (ms.sc_on && gam < ms.c_gamma) {
+      float a2 = 0.0f;
+      for (int k = 0; k < NK; ++k) {
+        const float dk = hex_ref_deriv<N1>(tab, su[slot], ta, tb, tc, tab->kk[k][0], tab->kk[k][1], tab->kk[k][2]);
+        a2 = fmaf(tab->wa[k] * dk, dk, a2);
+      }
+      const float at = fsqrt(a2);
+      const float f = lane_on ? (1.0f - gam) * (gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]) : 0.0f;
+      const float Sv = team_sumf<TEAM>(W * f), Tv = team_sumf<TEAM>(W * at * f);
+      if (Sv > 0.0f && Tv > 0.0f) alpha = at * (Sv / Tv);
+    }
+    if (mode == MODE_SENSOR) {
+      if (on && t == 0 && gamma_out) gamma_out[e] = gam;
+      if (on && alpha_out) alpha_out[e * NL + t] = alpha;
+      __syncthreads();
+      continue;
+    }
+
+    // ---- volume terms: -grad phi_j . f(u) + nu alpha (1 - gamma) grad phi_j . grad u
+    const float gs = nu * alpha * (1.0f - gam);
+    if (lane_on) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sv[slot][d][t] = W * tab->sc[d] * (gs * gr[d] - hex_flux<FLUX>(ms, uv, d));
+    }
+    __syncthreads();
+    float r = 0.0f;
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+      r = fmaf(tab->D1[q][ta], sv[slot][0][q + N1 * (tb + N1 * tc)], r);
+      r = fmaf(tab->D1[q][tb], sv[slot][1][ta + N1 * (q + N1 * tc)], r);
+      r = fmaf(tab->D1[q][tc], sv[slot][2][ta + N1 * (tb + N1 * q)], r);
+    }
+
+    // ---- interface terms: face f = 2 d + s, the neighbour read through its face f ^ 1
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int ad = d == 0 ? ta : (d == 1 ? tb : tc);
+      const float wt = d == 0 ? tab->w1[tb] * tab->w1[tc] : (d == 1 ? tab->w1[ta] * tab->w1[tc] : tab->w1[ta] * tab->w1[tb]);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        float um = 0.0f, up = 0.0f;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) {
+          const int idx = d == 0 ? j + N1 * (tb + N1 * tc) : (d == 1 ? ta + N1 * (j + N1 * tc) : ta + N1 * (tb + N1 * j));
+          um = fmaf(tab->Lend[s][j], su[slot][idx], um);
+          up = fmaf(tab->Lend[1 - s][j], sn[slot][2 * d + s][idx], up);
+        }
+        const float sg = s ? 1.0f : -1.0f;
+        float lf = ms.lam_g;
+        if (!(lf > 0.0f)) {
+          if constexpr (FLUX == CVW_BURGERS) lf = fmaxf(fabsf(um), fabsf(up)) * fabsf(ms.fp[d]);
+          else lf = fabsf(ms.fp[d]);
+        }
+        const float fs = 0.5f * sg * (hex_flux<FLUX>(ms, um, d) + hex_flux<FLUX>(ms, up, d)) - 0.5f * lf * (up - um);
+        r = fmaf(tab->Lend[s][ad] * wt * tab->Jf[d], fs, r);
+      }
+    }
+
+    // ---- output
+    if (on) {
+      const int64_t idx = e * NL + t;
+      float o;
+      if (mode == MODE_RESIDUAL) {
+        o = r;
+      } else {
+        const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
+        o = base + b0 * (uv - dt * r / W);
+      }
+      nonfinite = nonfinite || !isfinite(o);
+      out[idx] = o;
+      if (t == 0 && gamma_out) gamma_out[e] = gam;
+    }
+    __syncthreads();
+  }
+  if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(status, ST_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static unsigned hex_blocks(int64_t n, int per) { return static_cast<unsigned>((n + per - 1) / per); }
+
+cvw_status hex_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s) {
+  const MethodScalars ms = make_scalars(prm);
+  const dim3 g(hex_blocks(m->Nv, 256)), b(256);
+  switch (m->degree) {
+    case 1: hipLaunchKernelGGL(hex_vertex_kernel<1>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_hext, m->Nv, ms); break;
+    case 2: hipLaunchKernelGGL(hex_vertex_kernel<2>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_hext, m->Nv, ms); break;
+    default: set_error("hexahedra: degree 1 or 2"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+template <int P, int FLUX>
+static void launch_hex_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
+                            float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
+                            float a0, float b0, hipStream_t s) {
+  constexpr int CPB = HexShape<P>::CPB;
+  const int64_t nblk = (m->E + CPB - 1) / CPB;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(nblk, 16384));
+  hipLaunchKernelGGL((hex_eval_kernel<P, FLUX>), dim3(grid), dim3(256), 0, s, u, u0, out, gamma, alpha, cand,
+                     m->d_cell_vtx, m->d_nbr, m->d_hext, m->E, nblk, ms, mode, dt, a0, b0, status);
+}
+
+cvw_status hex_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
+                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
+                    hipStream_t s) {
+  const MethodScalars ms = make_scalars(prm);
+  const bool burgers = prm->flux == CVW_BURGERS;
+  switch (m->degree) {
+    case 1:
+      if (burgers) launch_hex_eval<1, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      else launch_hex_eval<1, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      break;
+    case 2:
+      if (burgers) launch_hex_eval<2, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      else launch_hex_eval<2, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      break;
+    default: set_error("hexahedra: degree 1 or 2"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+}  // namespace cvw

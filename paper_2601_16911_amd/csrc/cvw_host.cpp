@@ -3,6 +3,7 @@
 // the gfx950 kernels.  Everything here runs once per mesh (cvw_mesh_build) or
 // once per call; no host work depends on the state.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -606,6 +607,131 @@ static void rule_ld(int n, bool lobatto, std::vector<ld>& x, std::vector<ld>& w)
   }
 }
 
+// ---------------------------------------------------------------------------
+// hexahedra (DG Q_p on boxes hx x hy x hz), in extended precision: the
+// Lagrange basis of the Gauss nodes through the inverse of its Vandermonde
+// matrix in the monomials xi^a, its derivatives at the nodes and at the
+// corners, the semi-norm Gram matrix of the monomials of a cell (Sec. 3.2,
+// eq. snorm with h_e^{2|k|-d}, d = 3), and the re-expansion of a vertex
+// candidate (Taylor data about the vertex, eq. taylorcand) about the centre.
+// ---------------------------------------------------------------------------
+static void fill_hex_tables(HexTables& T, int p, double hx, double hy, double hz) {
+  T = HexTables{};
+  const int n1 = p + 1;
+  T.p = p; T.n1 = n1; T.nl = n1 * n1 * n1;
+  std::vector<ld> x, w;
+  rule_ld(n1, false, x, w);
+  // V[j][a] = x_j^a; C = V^{-1}: l_j(xi) = sum_a C[a][j] xi^a
+  std::vector<ld> V(n1 * n1), C(n1 * n1, 0.0L);
+  for (int j = 0; j < n1; ++j)
+    for (int a = 0; a < n1; ++a) V[j * n1 + a] = std::pow(x[j], static_cast<ld>(a));
+  for (int i = 0; i < n1; ++i) C[i * n1 + i] = 1.0L;
+  for (int c = 0; c < n1; ++c) {                 // Gauss-Jordan with partial pivoting
+    int piv = c;
+    for (int r = c + 1; r < n1; ++r)
+      if (std::fabs(V[r * n1 + c]) > std::fabs(V[piv * n1 + c])) piv = r;
+    for (int k = 0; k < n1; ++k) { std::swap(V[c * n1 + k], V[piv * n1 + k]); std::swap(C[c * n1 + k], C[piv * n1 + k]); }
+    const ld d = V[c * n1 + c];
+    for (int k = 0; k < n1; ++k) { V[c * n1 + k] /= d; C[c * n1 + k] /= d; }
+    for (int r = 0; r < n1; ++r)
+      if (r != c) {
+        const ld f = V[r * n1 + c];
+        for (int k = 0; k < n1; ++k) { V[r * n1 + k] -= f * V[c * n1 + k]; C[r * n1 + k] -= f * C[c * n1 + k]; }
+      }
+  }
+  // C now holds V^{-1} with rows indexed by the monomial power: C[a][j]
+  auto ffall = [](int a, int m) { ld r = 1.0L; for (int i = 0; i < m; ++i) r *= (a - i); return r; };  // a!/(a-m)!
+  auto lder = [&](int j, int m, ld t) {         // l_j^{(m)}(t)
+    ld v = 0.0L;
+    for (int a = m; a < n1; ++a) v += C[a * n1 + j] * ffall(a, m) * std::pow(t, static_cast<ld>(a - m));
+    return v;
+  };
+  for (int q = 0; q < n1; ++q) {
+    T.w1[q] = static_cast<float>(w[q]);
+    for (int j = 0; j < n1; ++j) {
+      T.D1[q][j] = static_cast<float>(lder(j, 1, x[q]));
+      T.D2[q][j] = static_cast<float>(lder(j, 2, x[q]));
+      T.T1[q][j] = static_cast<double>(C[q * n1 + j]);
+    }
+  }
+  for (int j = 0; j < n1; ++j) { T.Lend[0][j] = static_cast<float>(lder(j, 0, -1.0L)); T.Lend[1][j] = static_cast<float>(lder(j, 0, 1.0L)); }
+  const ld h[3] = {hx, hy, hz};
+  const ld he = std::sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  const ld W0 = h[0] * h[1] * h[2] / 8.0L;
+  for (int d = 0; d < 3; ++d) T.sc[d] = static_cast<float>(2.0L / h[d]);
+  T.W0 = static_cast<float>(W0);
+  T.Jf[0] = static_cast<float>(h[1] * h[2] / 4.0L);
+  T.Jf[1] = static_cast<float>(h[0] * h[2] / 4.0L);
+  T.Jf[2] = static_cast<float>(h[0] * h[1] / 4.0L);
+  T.he = static_cast<float>(he);
+  T.nuf = static_cast<float>(he / (2.0L * p));
+  // multi-indices 1 <= |k| <= p
+  std::vector<std::array<int, 3>> ks;
+  for (int n = 1; n <= p; ++n)
+    for (int a = n; a >= 0; --a)
+      for (int b = n - a; b >= 0; --b) ks.push_back({a, b, n - a - b});
+  T.nk = static_cast<int>(ks.size());
+  auto mono = [&](int a, int b, int c) { return a + n1 * (b + n1 * c); };
+  for (int A = 0; A < T.nl; ++A) T.kmono[A] = -1;
+  for (int k = 0; k < T.nk; ++k) {
+    const auto& kk = ks[k];
+    const int ord = kk[0] + kk[1] + kk[2];
+    ld sc2 = 1.0L;
+    for (int d = 0; d < 3; ++d) {
+      T.kk[k][d] = static_cast<int8_t>(kk[d]);
+      sc2 *= std::pow(2.0L / h[d], static_cast<ld>(2 * kk[d]));
+    }
+    T.wa[k] = static_cast<float>(std::pow(he, static_cast<ld>(2 * ord)) * sc2);
+    T.hb[k] = static_cast<double>(std::pow(he, static_cast<ld>(2 * ord)));
+    T.kmono[mono(kk[0], kk[1], kk[2])] = static_cast<int8_t>(k);
+  }
+  // G[A][B] = sum_k h_e^{2|k|-3} prod_d (2/h_d)^{2 k_d} W0 prod_d int_{-1}^{1} d^{k_d} xi^{A_d} d^{k_d} xi^{B_d}
+  auto I1 = [&](int a, int b, int m) -> ld {
+    if (a < m || b < m) return 0.0L;
+    const int n = a + b - 2 * m;
+    return (n % 2) ? 0.0L : ffall(a, m) * ffall(b, m) * 2.0L / (n + 1);
+  };
+  for (int A = 0; A < T.nl; ++A)
+    for (int B = 0; B < T.nl; ++B) {
+      const int Ad[3] = {A % n1, (A / n1) % n1, A / (n1 * n1)}, Bd[3] = {B % n1, (B / n1) % n1, B / (n1 * n1)};
+      ld g = 0.0L;
+      for (int k = 0; k < T.nk; ++k) {
+        const auto& kk = ks[k];
+        const int ord = kk[0] + kk[1] + kk[2];
+        ld t = std::pow(he, static_cast<ld>(2 * ord - 3)) * W0;
+        for (int d = 0; d < 3; ++d) t *= std::pow(2.0L / h[d], static_cast<ld>(2 * kk[d])) * I1(Ad[d], Bd[d], kk[d]);
+        g += t;
+      }
+      T.G[A][B] = static_cast<double>(g);
+    }
+  // corners: sigma = (+-1, +-1, +-1) in the local vertex order of the mesh
+  static const int SG[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                               {-1, -1, 1}, {1, -1, 1}, {1, 1, 1}, {-1, 1, 1}};
+  for (int l = 0; l < 8; ++l)
+    for (int k = 0; k < T.nk; ++k) {
+      const auto& kk = ks[k];
+      for (int j = 0; j < T.nl; ++j) {
+        const int jd[3] = {j % n1, (j / n1) % n1, j / (n1 * n1)};
+        ld v = 1.0L;
+        for (int d = 0; d < 3; ++d)
+          v *= std::pow(2.0L / h[d], static_cast<ld>(kk[d])) * lder(jd[d], kk[d], static_cast<ld>(SG[l][d]));
+        T.HV[l][k][j] = static_cast<double>(v);
+      }
+      // (x - x_l)^k / k! = prod_d (h_d/2)^{k_d} sum_{a_d <= k_d} xi^{a_d} (-sigma_d)^{k_d - a_d} / (a_d! (k_d - a_d)!)
+      for (int a = 0; a < T.nk; ++a) {
+        const auto& aa = ks[a];
+        ld v = 1.0L;
+        for (int d = 0; d < 3 && v != 0.0L; ++d) {
+          if (aa[d] > kk[d]) { v = 0.0L; break; }
+          const int r = kk[d] - aa[d];
+          v *= std::pow(h[d] / 2.0L, static_cast<ld>(kk[d])) * std::pow(static_cast<ld>(-SG[l][d]), static_cast<ld>(r)) /
+               (std::tgamma(static_cast<ld>(aa[d] + 1)) * std::tgamma(static_cast<ld>(r + 1)));
+        }
+        T.R[l][a][k] = static_cast<double>(v);
+      }
+    }
+}
+
 static std::vector<double> fill_hp_tables(int p, bool lobatto) {
   const int n1 = p + 1;
   const HPOff o = hp_off(p);
@@ -870,6 +996,7 @@ static void free_mesh(cvw_mesh* m) {
   (void)hipFree(m->d_geot);
   (void)hipFree(m->d_geov);
   (void)hipFree(m->d_nbrf);
+  (void)hipFree(m->d_hext);
   (void)hipFree(m->d_dinv_f);
   (void)hipFree(m->d_dinv_d);
   delete m;
@@ -891,14 +1018,17 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   if (d->cell == CVW_SEG && d->dim == 1) { ve = 2; nf = 2; }
   else if (d->cell == CVW_TRI && d->dim == 2) { ve = 3; nf = 3; }
   else if (d->cell == CVW_QUAD && d->dim == 2) { ve = 4; nf = 4; }
+  else if (d->cell == CVW_HEX && d->dim == 3) { ve = 8; nf = 6; }
   else { set_error("cell type / dimension mismatch"); return CVW_EINVAL; }
+  if (d->cell == CVW_HEX && d->space != CVW_DG) { set_error("hexahedra: DG only"); return CVW_EUNSUPPORTED; }
   if (d->degree < 1 || d->degree > (d->cell == CVW_SEG ? HP_MAXP : 16)) { set_error("degree out of range"); return CVW_EINVAL; }
   if (d->space != CVW_CG && d->space != CVW_DG) { set_error("space must be CG or DG"); return CVW_EINVAL; }
   if (d->n_cells <= 0 || d->n_vertices <= 0) { set_error("empty mesh"); return CVW_EINVAL; }
   // packed (cell, local index) entries: cell * 4 + local vertex, cell * n_loc + local CG node
   const int64_t nloc_d = d->cell == CVW_SEG ? d->degree + 1 : d->cell == CVW_QUAD ? (d->degree + 1) * (d->degree + 1)
-                                                                                : (d->degree + 1) * (d->degree + 2) / 2;
-  if (d->n_cells * std::max<int64_t>(4, nloc_d) >= (int64_t(1) << 31) || d->n_vertices >= (int64_t(1) << 31)) {
+                          : d->cell == CVW_HEX ? (d->degree + 1) * (d->degree + 1) * (d->degree + 1)
+                                               : (d->degree + 1) * (d->degree + 2) / 2;
+  if (d->n_cells * std::max<int64_t>(8, nloc_d) >= (int64_t(1) << 31) || d->n_vertices >= (int64_t(1) << 31)) {
     set_error("mesh too large for 32-bit indices"); return CVW_EINVAL;
   }
   const int64_t E = d->n_cells, Nv = d->n_vertices;
@@ -909,8 +1039,9 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   const int p = d->degree;
   if (d->cell == CVW_TRI) { m->nloc = (p + 1) * (p + 2) / 2; m->nq = (p + 1) * (p + 1); }
   else if (d->cell == CVW_QUAD) { m->nloc = (p + 1) * (p + 1); m->nq = (p + 1) * (p + 1); }
+  else if (d->cell == CVW_HEX) { m->nloc = (p + 1) * (p + 1) * (p + 1); m->nq = m->nloc; }
   else { m->nloc = p + 1; m->nq = p + 1; }
-  m->nk = (d->dim == 1) ? p : (p + 1) * (p + 2) / 2 - 1;
+  m->nk = (d->dim == 1) ? p : d->dim == 2 ? (p + 1) * (p + 2) / 2 - 1 : (p + 1) * (p + 2) * (p + 3) / 6 - 1;
   (void)hipGetDevice(&m->device);
 
   // ---- validation and vertex patches (CSR in ascending (cell, local vertex)) ----
@@ -940,7 +1071,7 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
       const int32_t pos = fill[v]++;
       m->h_vtx_cell[pos] = static_cast<int32_t>(e);
       m->h_vtx_lv[pos] = l;
-      ent[pos] = static_cast<int32_t>(e * 4 + l);
+      ent[pos] = static_cast<int32_t>(e * (ve == 8 ? 8 : 4) + l);
     }
 
   // ---- geometry ----
@@ -977,6 +1108,23 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     if (uni) { m->hx = hx0; m->hy = hy0; m->he = std::sqrt(hx0 * hx0 + hy0 * hy0); }
   }
 
+  if (d->cell == CVW_HEX) {
+    // congruent axis-aligned boxes, vertices at the corners in the local order
+    // (the face z = z0 counter-clockwise from the lowest corner, then z = z0 + hz)
+    static const int SG[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+    const double* X = d->cell_coords;
+    const double h0[3] = {X[3] - X[0], X[10] - X[1], X[14] - X[2]};
+    bool uni = h0[0] > 0 && h0[1] > 0 && h0[2] > 0;
+    const double tol = 1e-9;
+    for (int64_t e = 0; e < E && uni; ++e) {
+      const double* c = X + e * 24;
+      for (int v = 0; v < 8 && uni; ++v)
+        for (int a = 0; a < 3 && uni; ++a) uni = std::fabs(c[v * 3 + a] - c[a] - SG[v][a] * h0[a]) <= tol * h0[a];
+    }
+    m->uniform = uni ? 1 : 0;
+    if (uni) { m->hx = h0[0]; m->hy = h0[1]; m->hz = h0[2]; m->he = std::sqrt(h0[0] * h0[0] + h0[1] * h0[1] + h0[2] * h0[2]); }
+  }
+
   // ---- ends of a line: vertices of one cell ----
   if (d->cell == CVW_SEG) {
     for (int64_t v = 0; v < Nv; ++v) m->open_ends += cnt[v] == 1 ? 1 : 0;
@@ -994,7 +1142,41 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   }
 
   // ---- DG face neighbours ----
-  if (d->space == CVW_DG) {
+  if (d->space == CVW_DG && d->cell == CVW_HEX) {
+    // a face of a hexahedron is its four vertices (local faces 2 axis + side)
+    static const int FV[6][4] = {{0, 3, 7, 4}, {1, 2, 6, 5}, {0, 1, 5, 4}, {3, 2, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
+    struct HK { std::array<int32_t, 4> v; int32_t ef; };
+    std::vector<HK> keys(E * 6);
+    for (int64_t e = 0; e < E; ++e)
+      for (int f = 0; f < 6; ++f) {
+        HK k;
+        for (int i = 0; i < 4; ++i) k.v[i] = d->cell_vertices[e * 8 + FV[f][i]];
+        std::sort(k.v.begin(), k.v.end());
+        k.ef = static_cast<int32_t>(e * 6 + f);
+        keys[e * 6 + f] = k;
+      }
+    std::sort(keys.begin(), keys.end(), [](const HK& a, const HK& b) { return a.v < b.v || (a.v == b.v && a.ef < b.ef); });
+    m->h_nbr.assign(E * 6, -1);
+    m->h_nbr_face.assign(E * 6, -1);
+    for (size_t i = 0; i < keys.size();) {
+      size_t j = i;
+      while (j + 1 < keys.size() && keys[j + 1].v == keys[i].v) ++j;
+      if (j - i + 1 > 2) { free_mesh(m); set_error("non-conforming mesh: face shared by more than two cells"); return CVW_EINVAL; }
+      if (j == i + 1) {
+        const int32_t a = keys[i].ef, b = keys[j].ef;
+        m->h_nbr[a] = b / 6; m->h_nbr_face[a] = b % 6;
+        m->h_nbr[b] = a / 6; m->h_nbr_face[b] = a % 6;
+      }
+      i = j + 1;
+    }
+    m->closed = std::all_of(m->h_nbr.begin(), m->h_nbr.end(), [](int32_t x) { return x >= 0; }) ? 1 : 0;
+    for (int64_t i = 0; i < E * 6; ++i)
+      if (m->h_nbr[i] < 0) { m->h_bface.push_back(static_cast<int32_t>(i / 6)); m->h_bface.push_back(static_cast<int32_t>(i % 6)); }
+    m->n_bfaces = static_cast<int64_t>(m->h_bface.size() / 2);
+    // the cell pass reads the neighbour across face f through its face f ^ 1
+    for (int64_t i = 0; i < E * 6; ++i)
+      if (m->h_nbr[i] >= 0 && m->h_nbr_face[i] != ((i % 6) ^ 1)) { m->uniform = 0; break; }
+  } else if (d->space == CVW_DG) {
     struct FK { int64_t key; int32_t ef; };
     std::vector<FK> keys(E * nf);
     for (int64_t e = 0; e < E; ++e)
@@ -1171,6 +1353,11 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     fill_tri_tables(tt[0], p);
     if ((st = upload(&m->d_trit, tt)) != CVW_OK) { free_mesh(m); return st; }
   }
+  if (d->cell == CVW_HEX && m->uniform && p <= HEX_MAXP) {
+    std::vector<HexTables> ht(1);
+    fill_hex_tables(ht[0], p, m->hx, m->hy, m->hz);
+    if ((st = upload(&m->d_hext, ht)) != CVW_OK) { free_mesh(m); return st; }
+  }
   {
     const std::vector<double> dm = diag_mass(m, d);
     for (double v : dm)
@@ -1302,7 +1489,8 @@ static bool use_tile(const cvw_mesh* m, const cvw_params* prm) {
 
 // true when the mesh has a time-stepping path (stages and steps)
 static bool has_stage(const cvw_mesh* m) {
-  return m->n_mass > 0 || (m->space == CVW_DG && (m->cell == CVW_QUAD || (m->cell == CVW_TRI && m->d_trit)));
+  return m->n_mass > 0 || (m->space == CVW_DG && (m->cell == CVW_QUAD || (m->cell == CVW_TRI && m->d_trit) ||
+                                                  (m->cell == CVW_HEX && m->d_hext)));
 }
 
 // float64 scratch of the totals: block partials of up to four variables and the results
@@ -1380,6 +1568,17 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
   const bool cgq = m->cell == CVW_QUAD && m->space == CVW_CG;
   const bool seg = m->cell == CVW_SEG;
   const bool dgt = m->cell == CVW_TRI && m->space == CVW_DG;
+  if (m->cell == CVW_HEX) {
+    if (!m->uniform || !m->d_hext) {
+      set_error("DG hexahedra: congruent axis-aligned boxes, degree <= 2"); return CVW_EUNSUPPORTED;
+    }
+    if (!m->closed) { set_error("DG hexahedra: meshes without boundary faces (periodic)"); return CVW_EUNSUPPORTED; }
+    if (prm->dtype != CVW_F32) { set_error("DG hexahedra run in float32"); return CVW_EUNSUPPORTED; }
+    if (prm->flux != CVW_ADVECT_CONST && prm->flux != CVW_BURGERS) {
+      set_error("DG hexahedra: constant-velocity advection and Burgers"); return CVW_EUNSUPPORTED;
+    }
+    return CVW_OK;
+  }
   if (dgt) {
     if (m->degree > MAXP) { set_error("degree > 3 not on the GPU path"); return CVW_EUNSUPPORTED; }
     if (prm->dtype != CVW_F32) { set_error("DG triangles run in float32"); return CVW_EUNSUPPORTED; }
@@ -1542,6 +1741,8 @@ static cvw_status learned_audit(const cvw_mesh* m, const cvw_params* prm, const 
 static cvw_status candidates_any(const cvw_mesh* m, const cvw_params* prm, const void* u, void* cand,
                                  hipStream_t s) {
   if (m->cell == CVW_SEG) return seg_candidates(m, prm, u, cand, s);
+  if (m->cell == CVW_HEX)
+    return hex_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
   if (m->cell == CVW_TRI)
     return tri_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
   if (m->space == CVW_CG)
@@ -1586,6 +1787,9 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
   }
   if (m->cell == CVW_SEG)
     return seg_eval(m, prm, MODE_SENSOR, u, w.cand, w.pg, w.rcell, nullptr, gamma, alpha, w.status, s);
+  if (m->cell == CVW_HEX)
+    return hex_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
+                    static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s);
   if (m->cell == CVW_TRI)
     return tri_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
                     static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s);
@@ -1736,6 +1940,10 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
   if (prm->sensor == CVW_SENSOR_LEARNED && (st = learned_gamma(m, prm, u, w.cand, w, s)) != CVW_OK) return st;
   if (m->cell == CVW_SEG)
     return seg_eval(m, prm, MODE_RESIDUAL, u, w.cand, w.pg, w.rcell, R, gamma_out, nullptr, w.status, s);
+  if (m->cell == CVW_HEX)
+    return hex_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
+                    static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
+                    0.f, s);
   if (m->cell == CVW_TRI)
     return tri_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
                     static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
@@ -1787,6 +1995,10 @@ cvw_status generic_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, 
 
 cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, const void* us, const void* cand,
                      const void* un, void* uo, double dt, double a0, double b0, hipStream_t s) {
+  if (m->cell == CVW_HEX)
+    return hex_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
+                    static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
+                    static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s);
   if (m->cell == CVW_TRI)
     return tri_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
                     static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,

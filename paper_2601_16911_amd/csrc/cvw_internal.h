@@ -148,6 +148,35 @@ struct TriTables {
   double mwd[TRI_NLOC];
 };
 
+// Hexahedra: DG Q_p (p <= HEX_MAXP) on congruent axis-aligned boxes.  Local
+// node a + n1 b + n1^2 c (x fastest) at the Gauss points; the polynomial of a
+// cell in the monomials xi^A of its reference coordinates, A = (a, b, c),
+// index a + n1 b + n1^2 c; multi-indices k, 1 <= |k| <= p, in the order of
+// the Hermite data (by |k|, then decreasing first, then decreasing second
+// component).  Built for the mesh's box sides (hx, hy, hz).
+constexpr int HEX_MAXP = 2;
+constexpr int HEX_N1 = HEX_MAXP + 1, HEX_NL = HEX_N1 * HEX_N1 * HEX_N1;
+constexpr int HEX_NK = (HEX_MAXP + 1) * (HEX_MAXP + 2) * (HEX_MAXP + 3) / 6 - 1;
+struct HexTables {
+  int p, n1, nl, nk;
+  float w1[HEX_N1];                      // Gauss weights on [-1, 1]
+  float D1[HEX_N1][HEX_N1];              // l_j'(x_q)
+  float D2[HEX_N1][HEX_N1];              // l_j''(x_q)
+  float Lend[2][HEX_N1];                 // l_j(-1), l_j(+1)
+  float sc[3];                           // 2 / h_d
+  float W0;                              // hx hy hz / 8
+  float Jf[3];                           // face Jacobian of the faces normal to axis d (area / 4)
+  float he, nuf;                         // diam K_e, h_e / (2p)
+  float wa[HEX_NK];                      // alpha~: h_e^{2|k|} prod_d (2 / h_d)^{2 k_d}
+  int8_t kk[HEX_NK][3];                  // the multi-indices
+  int8_t kmono[HEX_NL];                  // monomial A -> its index among the k (-1: A = 0 or |A| > p)
+  double hb[HEX_NK];                     // vertex beta: h_e^{2|k|}
+  double T1[HEX_N1][HEX_N1];             // u(xi) = sum_a (sum_j T1[a][j] u_j) xi^a along one direction
+  double G[HEX_NL][HEX_NL];              // sum_k h_e^{2|k|-3} int_K D^k xi^A D^k xi^B dx
+  double HV[8][HEX_NK][HEX_NL];          // D^k u(x_l) from the nodal values less the first one
+  double R[8][HEX_NK][HEX_NK];           // vertex candidate of vertex l (Taylor data) -> coefficient of xi^a, a in k
+};
+
 // Scalars of the method in the precision of the kernels.
 struct MethodScalars {
   float eps_v, eps_c, r, q_sensor, q_beta, lin_w, c_gamma, lam_g;
@@ -362,7 +391,7 @@ struct cvw_mesh {
   cvw::TensorTables tens{};
   // device arrays (owned)
   int32_t* d_vtx_ptr = nullptr;      // [Nv + 1]
-  int32_t* d_vtx_ent = nullptr;      // [nnz] packed cell * ve + lv
+  int32_t* d_vtx_ent = nullptr;      // [nnz] packed cell * 4 + lv (hexahedra: cell * 8 + lv)
   int32_t* d_cell_vtx = nullptr;     // [E][ve]
   int32_t* d_nbr = nullptr;          // [E][nf]
   cvw::TensorTables* d_tens = nullptr;
@@ -386,6 +415,9 @@ struct cvw_mesh {
   double* d_geot = nullptr;           // [E][8] x0, y0, x1-x0, y1-y0, x2-x0, y2-y0, diam, 0
   float* d_geov = nullptr;            // [E][8] vertex pass: inverse Jacobian A00, A01, A10, A11, diam, 0, 0, 0
   int32_t* d_nbrf = nullptr;          // [E][3] neighbour cell * 4 + its face
+  // hexahedra
+  double hz = 0;
+  cvw::HexTables* d_hext = nullptr;
   float* d_dinv_f = nullptr;          // [n_mass]
   double* d_dinv_d = nullptr;         // [n_mass]
   int64_t n_mass = 0;
@@ -470,6 +502,12 @@ cvw_status tri_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const fl
                     float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
                     hipStream_t s);
 cvw_status tri_totals(const cvw_mesh* m, int nvar, const float* u, double* partial, double* out_dev, hipStream_t s);
+// DG hexahedra (cvw_hex.hip): vertex candidates (one thread per vertex) and
+// the cell pass (one team of lanes per cell, a lane per node)
+cvw_status hex_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
+cvw_status hex_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
+                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
+                    hipStream_t s);
 // time stepping (cvw_cgstep.hip)
 size_t pcg_partials(int64_t n);
 // M x = b for every variable: lines solve all nvar variables at once (vectors
