@@ -529,6 +529,58 @@ def bench_triangles(torch, cvw, steps: int, n: int = 512, limiter: bool = True):
     return out
 
 
+def bench_hex(torch, cvw, n: int = 128, p: int = 2, steps: int = 5):
+    """3D: constant advection, DG Q_p on n^3 periodic cubes (128^3: 2,097,152
+    cells, 56.6 M DOFs at p = 2), a smooth field plus a ball-shaped jump.
+    Kernel times of the vertex pass (cvw_vertex_candidates) and of the cell
+    pass in stage mode (cvw_rk_stage), the residual and the SSP-RK3 step.
+    Roofline of the cell pass from its compulsory bytes per cell and stage:
+    read u and write u_out (2 n_loc floats), u_n in two of three stages, the
+    candidates of one vertex per cell (n_k floats); the vertex pass: read u
+    (n_loc floats per cell, one cell per vertex) and write the candidates."""
+    import synth
+    stream = torch.cuda.current_stream()
+    mesh = synth.hex_mesh(n, n, n)
+    n1 = p + 1
+    x1 = np.polynomial.legendre.leggauss(n1)[0]
+    Z, Y, X = np.meshgrid(x1, x1, x1, indexing="ij")
+    nodes = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    h = 1.0 / n
+    c0 = mesh.cell_coords[:, 0, :]
+    pts = c0[:, None, :] + 0.5 * h * (nodes[None, :, :] + 1.0)
+    x, y, z = pts[..., 0], pts[..., 1], pts[..., 2]
+    u0 = (np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 0.5 * np.sin(2 * np.pi * z)
+          + 1.5 * (((x - 0.45) ** 2 + (y - 0.4) ** 2 + (z - 0.5) ** 2) < 0.06))
+    U = torch.from_numpy(np.asarray(u0, np.float32).ravel()).cuda()
+    del pts, x, y, z, u0
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    prm = synth.Params(flux=synth.ADVECT_CONST, flux_param=(1.0, -0.6, 0.8, 0))
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, 1)
+    R = torch.empty_like(U)
+    V = torch.empty_like(U)
+    nk = gm.info["n_k"]
+    cand = torch.empty(mesh.n_vertices * nk, dtype=torch.float32, device="cuda")
+    dofs = U.numel()
+    dt = 0.1 * h / ((2 * p + 1) * float(np.linalg.norm(prm.flux_param[:3])))
+    t_vtx = _timed(torch, stream, lambda: cvw.vertex_candidates(gm, cp, U, cand, ws), 10)
+    t_cell = _timed(torch, stream, lambda: cvw.rk_stage(gm, cp, U, cand, U, V, dt, 0.75, 0.25, ws), 10)
+    t_res = _timed(torch, stream, lambda: cvw.residual(gm, cp, U, R, None, ws), 10)
+    t_step = _timed(torch, stream, lambda: cvw.step(gm, cp, U, dt, steps, ws), 1) / steps
+    E = mesh.n_cells
+    nl = n1 ** 3
+    alg_cell = E * 4 * (2 * nl + 2.0 / 3.0 * nl + nk)
+    alg_vtx = E * 4 * (nl + nk)
+    return {"workload": f"3D constant advection, DG Q{p} on {n}^3 periodic cubes ({E} cells)", "dofs": dofs,
+            "vertex_pass": {"ms": t_vtx * 1e3, "achieved": alg_vtx / t_vtx / 1e9, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": alg_vtx / t_vtx / 1e9 / HBM_PEAK_GBS},
+            "cell_pass": {"ms": t_cell * 1e3, "achieved": alg_cell / t_cell / 1e9, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": alg_cell / t_cell / 1e9 / HBM_PEAK_GBS},
+            "residual": {"value": dofs / t_res, "unit": "DOF-updates/s", "ms": t_res * 1e3},
+            "step": {"value": 3.0 * dofs / t_step, "unit": "DOF-updates/s", "ms_per_step": t_step * 1e3},
+            "status_flags": cvw.poll_status(gm, ws)}
+
+
 def bench_small_configs(torch, cvw):
     """The two small workloads, per stage: 1D advection (128 periodic cells,
     CG P2, float64, the pulse and hump data, CFL 0.3) and solid-body rotation
@@ -716,11 +768,11 @@ def main():
                     help="also run one 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch shapes (no autotuner launches before the timed region)")
-    ap.add_argument("--part", choices=("step", "sensor", "learned", "small", "tri", "dmr"), default="step",
+    ap.add_argument("--part", choices=("step", "sensor", "learned", "small", "tri", "dmr", "hex"), default="step",
                     help="sensor / learned: only the plain or learned sensor pass, --steps calls after --warmup "
                          "(a short program for kernel traces and counters); small: only the 1D and CG "
                          "rotation workloads; tri: only the KPP triangle residual on 2048 x 2048 squares, --steps "
-                         "calls; dmr: only the double Mach reflection run")
+                         "calls; dmr: only the double Mach reflection run; hex: only the 3D DG Q2 advection")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is benchmarked on one MI355X; "
@@ -737,6 +789,9 @@ def main():
         return
     if args.part == "dmr":
         print(json.dumps(bench_dmr(torch, cvw)))
+        return
+    if args.part == "hex":
+        print(json.dumps(bench_hex(torch, cvw)))
         return
     if args.part == "small":
         out = bench_small_configs(torch, cvw)
@@ -912,6 +967,8 @@ def main():
         out["positivity_limiter"] = bench_positivity(torch, cvw, gm, prm, U)
         torch.cuda.empty_cache()
         out["double_mach"] = bench_dmr(torch, cvw)
+        torch.cuda.empty_cache()
+        out["hexahedra_q2"] = bench_hex(torch, cvw)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -51,6 +51,15 @@ __device__ __forceinline__ float team_maxf(float x) {
   return x;
 }
 
+// A team lives inside one wavefront and its LDS slots are its own: an
+// exchange needs only the wavefront's LDS operations kept in program order
+// (they complete in issue order), not a workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // scalar fluxes in 3D: f_d(u) = v_d u (constant advection) or u^2 / 2 b_d (Burgers)
 template <int FLUX>
 __device__ __forceinline__ float hex_flux(const MethodScalars& ms, float u, int d) {
@@ -125,80 +134,120 @@ __global__ __launch_bounds__(256) void hex_vertex_kernel(const float* __restrict
 // ---------------------------------------------------------------------------
 // cell pass
 // ---------------------------------------------------------------------------
-// reference derivative d_xi^kx d_eta^ky d_zeta^kz of the cell polynomial at
-// node (ta, tb, tc) from the nodal values in LDS (orders 0..2 per direction)
-template <int N1>
-__device__ __forceinline__ float hex_ref_deriv(const HexTables* __restrict__ tab, const float* su, int ta, int tb,
-                                               int tc, int kx, int ky, int kz) {
-  float out = 0.0f;
+// alpha~^2 at node (ta, tb, tc) (eq. alpha_prelim with the pointwise
+// semi-norm): sum_k h_e^{2|k|} |D^k u|^2 over 1 <= |k| <= p, from the
+// reference first derivatives g (already at the node) and, for p = 2, the
+// second derivatives along the node's lines (l'' at the nodes) and across
+// them (l' x l'); wa folds h_e^{2|k|} and the factors (2/h_d)^{2 k_d}.
+template <int P>
+__device__ __forceinline__ float hex_atil2(const HexTables* __restrict__ tab, const float* su, int ta, int tb, int tc,
+                                           const float (&g)[3]) {
+  constexpr int N1 = P + 1;
+  float a2 = tab->wa[0] * g[0] * g[0] + tab->wa[1] * g[1] * g[1] + tab->wa[2] * g[2] * g[2];
+  if constexpr (P == 2) {
+    float xx = 0.0f, yy = 0.0f, zz = 0.0f, xy = 0.0f, xz = 0.0f, yz = 0.0f;
 #pragma unroll
-  for (int i = 0; i < N1; ++i) {
-    const float cx = kx == 0 ? (i == ta ? 1.0f : 0.0f) : (kx == 1 ? tab->D1[ta][i] : tab->D2[ta][i]);
-    if (cx == 0.0f) continue;
+    for (int i = 0; i < N1; ++i) {
+      xx = fmaf(tab->D2[ta][i], su[i + N1 * (tb + N1 * tc)], xx);
+      yy = fmaf(tab->D2[tb][i], su[ta + N1 * (i + N1 * tc)], yy);
+      zz = fmaf(tab->D2[tc][i], su[ta + N1 * (tb + N1 * i)], zz);
 #pragma unroll
-    for (int j = 0; j < N1; ++j) {
-      const float cy = ky == 0 ? (j == tb ? 1.0f : 0.0f) : (ky == 1 ? tab->D1[tb][j] : tab->D2[tb][j]);
-      if (cy == 0.0f) continue;
-#pragma unroll
-      for (int l = 0; l < N1; ++l) {
-        const float cz = kz == 0 ? (l == tc ? 1.0f : 0.0f) : (kz == 1 ? tab->D1[tc][l] : tab->D2[tc][l]);
-        out = fmaf(cx * cy * cz, su[i + N1 * (j + N1 * l)], out);
+      for (int j = 0; j < N1; ++j) {
+        xy = fmaf(tab->D1[ta][i] * tab->D1[tb][j], su[i + N1 * (j + N1 * tc)], xy);
+        xz = fmaf(tab->D1[ta][i] * tab->D1[tc][j], su[i + N1 * (tb + N1 * j)], xz);
+        yz = fmaf(tab->D1[tb][i] * tab->D1[tc][j], su[ta + N1 * (i + N1 * j)], yz);
       }
     }
+    // multi-index order (2,0,0), (1,1,0), (1,0,1), (0,2,0), (0,1,1), (0,0,2)
+    a2 = fmaf(tab->wa[3] * xx, xx, a2);
+    a2 = fmaf(tab->wa[4] * xy, xy, a2);
+    a2 = fmaf(tab->wa[5] * xz, xz, a2);
+    a2 = fmaf(tab->wa[6] * yy, yy, a2);
+    a2 = fmaf(tab->wa[7] * yz, yz, a2);
+    a2 = fmaf(tab->wa[8] * zz, zz, a2);
   }
-  return out;
+  return a2;
 }
 
-template <int P, int FLUX>
-__global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__ u, const float* __restrict__ u0,
-                                                       float* __restrict__ out, float* __restrict__ gamma_out,
-                                                       float* __restrict__ alpha_out, const float* __restrict__ cand,
-                                                       const int32_t* __restrict__ cell_vtx,
-                                                       const int32_t* __restrict__ nbr,
-                                                       const HexTables* __restrict__ tab, int64_t E, int64_t nblk,
-                                                       MethodScalars ms, int mode, float dt, float a0, float b0,
-                                                       uint32_t* __restrict__ status) {
+template <int P>
+__global__ __launch_bounds__(256) void hex_sensor_kernel(const float* __restrict__ u, float* __restrict__ gamma,
+                                                         const float* __restrict__ cand,
+                                                         const int32_t* __restrict__ cell_vtx,
+                                                         const HexTables* __restrict__ tab, int64_t E, int64_t nblk,
+                                                         MethodScalars ms) {
   using S = HexShape<P>;
   constexpr int N1 = S::N1, NL = S::NL, NK = S::NK, TEAM = S::TEAM, CPB = S::CPB;
-  __shared__ double sG[NL][NL];
+  __shared__ double sgv[NL][8], ssv[NK][NK];
+  __shared__ int8_t sgb[NL][8], sgn[NL], ssb[NK][NK], ssn[NK], srk[NK][NK], srn[NK];
   __shared__ double sR[8][NK][NK];
-  __shared__ int sMono[NK];
   __shared__ float su[CPB][NL];
-  __shared__ float sn[CPB][6][NL];
   __shared__ double sa[CPB][NL], sb[CPB][NL];
   __shared__ double ss[CPB][8][NK], sq[CPB][8][NK];
-  __shared__ float sv[CPB][3][NL];
-  for (int i = threadIdx.x; i < NL * NL; i += blockDim.x) sG[i / NL][i % NL] = tab->G[i / NL][i % NL];
+  __shared__ double som[CPB][9];
+  __shared__ float scand[CPB][8 * NK];
+  for (int i = threadIdx.x; i < NL * 8; i += blockDim.x) {
+    sgv[i / 8][i % 8] = tab->gv[i / 8][i % 8];
+    sgb[i / 8][i % 8] = tab->gb[i / 8][i % 8];
+  }
+  for (int i = threadIdx.x; i < NK * NK; i += blockDim.x) {
+    ssv[i / NK][i % NK] = tab->sv[i / NK][i % NK];
+    ssb[i / NK][i % NK] = tab->sb[i / NK][i % NK];
+    srk[i / NK][i % NK] = tab->rk[i / NK][i % NK];
+  }
+  if (threadIdx.x < NL) sgn[threadIdx.x] = tab->gn[threadIdx.x];
+  if (threadIdx.x < NK) {
+    ssn[threadIdx.x] = tab->sn[threadIdx.x];
+    srn[threadIdx.x] = tab->rn[threadIdx.x];
+  }
   for (int i = threadIdx.x; i < 8 * NK * NK; i += blockDim.x) {
     const int l = i / (NK * NK), r = i % (NK * NK);
     sR[l][r / NK][r % NK] = tab->R[l][r / NK][r % NK];
   }
-  if (threadIdx.x < NK)
-    sMono[threadIdx.x] = tab->kk[threadIdx.x][0] + N1 * (tab->kk[threadIdx.x][1] + N1 * tab->kk[threadIdx.x][2]);
+  __syncthreads();
   const int slot = threadIdx.x / TEAM, t = threadIdx.x % TEAM;
   const bool lane_on = t < NL;
   const int tn = lane_on ? t : 0;
   const int ta = tn % N1, tb = (tn / N1) % N1, tc = tn / (N1 * N1);
-  const float W = tab->w1[ta] * tab->w1[tb] * tab->w1[tc] * tab->W0;
-  const bool plain = ms.sensor_kind != CVW_SENSOR_FIXED;
-  bool nonfinite = false;
+  // software pipeline: the next block's nodal values and vertex ids are
+  // requested at the top of an iteration, its candidates half-way through,
+  // and all of it is consumed at the top of the next iteration.  The loads are
+  // unconditional (indices clamped into the mesh) so that no wait is placed
+  // at the load; out-of-range cells get zeros when stored.
+  constexpr int NCL = (8 * NK + TEAM - 1) / TEAM;
+  float pu = 0.0f, pc[NCL];
+  int32_t pv[NCL];
+  auto fetch_a = [&](int64_t b) {
+    const int64_t ec = b * CPB + slot < E ? b * CPB + slot : E - 1;
+    pu = u[ec * NL + tn];
+#pragma unroll
+    for (int r = 0; r < NCL; ++r) {
+      const int i = t + r * TEAM < 8 * NK ? t + r * TEAM : 8 * NK - 1;
+      pv[r] = cell_vtx[ec * 8 + i / NK];
+    }
+  };
+  auto fetch_b = [&]() {
+#pragma unroll
+    for (int r = 0; r < NCL; ++r) {
+      const int i = t + r * TEAM < 8 * NK ? t + r * TEAM : 8 * NK - 1;
+      pc[r] = cand[static_cast<int64_t>(pv[r]) * NK + i % NK];
+    }
+  };
+  fetch_a(blockIdx.x);
+  fetch_b();
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const int64_t e = blk * CPB + slot;
     const bool cell_on = e < E;
     const bool on = lane_on && cell_on;
-    // ---- nodal values of the cell and of its six face neighbours
-    const float uv = on ? u[e * NL + t] : 0.0f;
-    if (lane_on) su[slot][t] = uv;
+    if (lane_on) su[slot][t] = on ? pu : 0.0f;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      const int64_t en = cell_on ? nbr[e * 6 + f] : 0;
-      if (lane_on) sn[slot][f][t] = on ? u[en * NL + t] : 0.0f;
-    }
-    __syncthreads();
-
+    for (int r = 0; r < NCL; ++r)
+      if (t + r * TEAM < 8 * NK) scand[slot][t + r * TEAM] = cell_on ? pc[r] : 0.0f;
+    wave_sync();
+    const int64_t nxt = blk + gridDim.x < nblk ? blk + gridDim.x : blk;
+    fetch_a(nxt);
     // ---- sensor gamma_e (float64)
-    float gam = ms.fixed_gamma;
-    if (plain) {
+    float gam = 1.0f;
+    {
       const double u00 = static_cast<double>(su[slot][0]);
       if (lane_on) {                     // monomial coefficients of u - u_0: x, then y, then z
         double c = 0.0;
@@ -207,14 +256,14 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
           c = fma(tab->T1[ta][j], static_cast<double>(su[slot][j + N1 * (tb + N1 * tc)]) - u00, c);
         sa[slot][t] = c;
       }
-      __syncthreads();
+      wave_sync();
       if (lane_on) {
         double c = 0.0;
 #pragma unroll
         for (int j = 0; j < N1; ++j) c = fma(tab->T1[tb][j], sa[slot][ta + N1 * (j + N1 * tc)], c);
         sb[slot][t] = c;
       }
-      __syncthreads();
+      wave_sync();
       double cA = 0.0;
       if (lane_on) {
 #pragma unroll
@@ -225,76 +274,76 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
       for (int i = t; i < 8 * NK; i += TEAM) {
         const int l = i / NK, a = i % NK;
         double acc = 0.0;
-        if (cell_on) {
-          const float* cv = cand + static_cast<int64_t>(cell_vtx[e * 8 + l]) * NK;
-#pragma unroll
-          for (int k = 0; k < NK; ++k) acc = fma(sR[l][a][k], static_cast<double>(cv[k]), acc);
+        for (int r = 0; r < srn[a]; ++r) {
+          const int k = srk[a][r];
+          acc = fma(sR[l][a][k], static_cast<double>(scand[slot][l * NK + k]), acc);
         }
         ss[slot][l][a] = acc;
       }
-      __syncthreads();
+      wave_sync();
+      fetch_b();
       // ||u_h||_e^2 = c^T G c
       double g = 0.0;
       if (lane_on) {
-#pragma unroll
-        for (int B = 0; B < NL; ++B) g = fma(sG[t][B], sa[slot][B], g);
+        for (int r = 0; r < sgn[t]; ++r) g = fma(sgv[t][r], sa[slot][sgb[t][r]], g);
       }
       const double n02 = team_sum<TEAM>(cA * g);
       for (int i = t; i < 8 * NK; i += TEAM) {
         const int l = i / NK, a = i % NK;
         double q = 0.0;
-#pragma unroll
-        for (int b = 0; b < NK; ++b) q = fma(sG[sMono[a]][sMono[b]], ss[slot][l][b], q);
+        for (int r = 0; r < ssn[a]; ++r) q = fma(ssv[a][r], ss[slot][l][ssb[a][r]], q);
         sq[slot][l][a] = ss[slot][l][a] * q;
       }
-      __syncthreads();
-      // weights of the cell candidate and the eight vertex candidates (every lane alike)
-      double om[9], beta[9];
-      beta[0] = sqrt(fmax(n02, 0.0));
+      wave_sync();
+      // weights of the cell candidate (l = 0) and the eight vertex candidates:
+      // lane t takes l = t and l = t + TEAM (a team of 8 lanes has nine weights)
+      const double n0 = sqrt(fmax(n02, 0.0));
+      double wv[2] = {0.0, 0.0}, wpart = 0.0;
 #pragma unroll
-      for (int l = 0; l < 8; ++l) {
-        double b2 = 0.0;
+      for (int j = 0; j < 2; ++j) {
+        const int l = t + j * TEAM;
+        if (l > 8) continue;
+        double b = n0;
+        if (l >= 1) {
+          double b2 = 0.0;
 #pragma unroll
-        for (int a = 0; a < NK; ++a) b2 += sq[slot][l][a];
-        beta[l + 1] = sqrt(fmax(b2, 0.0));
-      }
-      const double n0 = beta[0];
-      double wsum = 0.0;
-#pragma unroll
-      for (int l = 0; l < 9; ++l) {
-        const double lin = l == 0 ? 1.0 - 8.0 * ms.lin_wd : ms.lin_wd;
-        double w;
-        if (ms.fast_exp) {
-          const double tt = ms.eps_cd + beta[l];
-          w = lin / (tt * tt);
-        } else {
-          w = lin * pow(ms.eps_cd + pow(beta[l], static_cast<double>(ms.q_beta)), -static_cast<double>(ms.r));
+          for (int a = 0; a < NK; ++a) b2 += sq[slot][l - 1][a];
+          b = sqrt(fmax(b2, 0.0));
         }
-        om[l] = w;
-        wsum += w;
+        const double lin = l == 0 ? 1.0 - 8.0 * ms.lin_wd : ms.lin_wd;
+        if (ms.fast_exp) {
+          const double tt = ms.eps_cd + b;
+          wv[j] = lin / (tt * tt);
+        } else {
+          wv[j] = lin * pow(ms.eps_cd + pow(b, static_cast<double>(ms.q_beta)), -static_cast<double>(ms.r));
+        }
+        wpart += wv[j];
       }
-      double osum = 0.0;
+      const double wsum = team_sum<TEAM>(wpart);
 #pragma unroll
-      for (int l = 0; l < 9; ++l) {
-        om[l] /= wsum;
-        if (l > 0) osum += om[l];
+      for (int j = 0; j < 2; ++j) {
+        const int l = t + j * TEAM;
+        if (l <= 8) som[slot][l] = wv[j] / wsum;
       }
-      // u_h - sum_l omega_l (u_h - s_l)'s complement: diff = sum_l omega_l (u_h - s_l)
+      wave_sync();
+      // diff = sum_{l >= 1} omega_l (u_h - s_l)
       double Dv = 0.0;
       if (lane_on) {
+        double osum = 0.0;
+#pragma unroll
+        for (int l = 1; l <= 8; ++l) osum += som[slot][l];
         Dv = osum * cA;
         const int a = tab->kmono[t];
         if (a >= 0) {
 #pragma unroll
-          for (int l = 0; l < 8; ++l) Dv = fma(-om[l + 1], ss[slot][l][a], Dv);
+          for (int l = 0; l < 8; ++l) Dv = fma(-som[slot][l + 1], ss[slot][l][a], Dv);
         }
         sb[slot][t] = Dv;
       }
-      __syncthreads();
+      wave_sync();
       double gd = 0.0;
       if (lane_on) {
-#pragma unroll
-        for (int B = 0; B < NL; ++B) gd = fma(sG[t][B], sb[slot][B], gd);
+        for (int r = 0; r < sgn[t]; ++r) gd = fma(sgv[t][r], sb[slot][sgb[t][r]], gd);
       }
       const double d2 = team_sum<TEAM>(Dv * gd);
       if (n0 > 0.0) {
@@ -305,6 +354,66 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
         gam = 1.0f;
       }
     }
+
+    if (on && t == 0) gamma[e] = gam;
+    wave_sync();
+  }
+}
+
+template <int P, int FLUX>
+__global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__ u, const float* __restrict__ u0,
+                                                       float* __restrict__ out, float* __restrict__ gamma_out,
+                                                       float* __restrict__ alpha_out,
+                                                       const float* __restrict__ gamma_in,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const HexTables* __restrict__ tab, int64_t E, int64_t nblk,
+                                                       MethodScalars ms, int mode, float dt, float a0, float b0,
+                                                       uint32_t* __restrict__ status) {
+  using S = HexShape<P>;
+  constexpr int N1 = S::N1, NL = S::NL, TEAM = S::TEAM, CPB = S::CPB;
+  __shared__ float su[CPB][NL];
+  __shared__ float sn[CPB][6][NL];
+  __shared__ float sv[CPB][3][NL];
+  const int slot = threadIdx.x / TEAM, t = threadIdx.x % TEAM;
+  const bool lane_on = t < NL;
+  const int tn = lane_on ? t : 0;
+  const int ta = tn % N1, tb = (tn / N1) % N1, tc = tn / (N1 * N1);
+  const float W = tab->w1[ta] * tab->w1[tb] * tab->w1[tc] * tab->W0;
+  const bool plain = ms.sensor_kind != CVW_SENSOR_FIXED;
+  bool nonfinite = false;
+  // software pipeline as in the sensor pass: the next block's nodal values,
+  // gamma_e and neighbour ids at the top of an iteration, the neighbours'
+  // nodal values half-way through (clamped, unconditional loads)
+  float pu = 0.0f, pg = 0.0f, pn[6];
+  int32_t pid[6];
+  auto fetch_a = [&](int64_t b) {
+    const int64_t ec = b * CPB + slot < E ? b * CPB + slot : E - 1;
+    pu = u[ec * NL + tn];
+    pg = plain ? gamma_in[ec] : ms.fixed_gamma;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) pid[f] = nbr[ec * 6 + f];
+  };
+  auto fetch_b = [&]() {
+#pragma unroll
+    for (int f = 0; f < 6; ++f) pn[f] = u[static_cast<int64_t>(pid[f]) * NL + tn];
+  };
+  fetch_a(blockIdx.x);
+  fetch_b();
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t e = blk * CPB + slot;
+    const bool cell_on = e < E;
+    const bool on = lane_on && cell_on;
+    // ---- nodal values of the cell and of its six face neighbours
+    const float uv = on ? pu : 0.0f;
+    const float gam = pg;                // gamma_e: from the sensor pass, or the fixed value
+    if (lane_on) {
+      su[slot][t] = uv;
+#pragma unroll
+      for (int f = 0; f < 6; ++f) sn[slot][f][t] = on ? pn[f] : 0.0f;
+    }
+    wave_sync();
+    const int64_t nxt = blk + gridDim.x < nblk ? blk + gridDim.x : blk;
+    fetch_a(nxt);
 
     // ---- viscosity (eq. lostab) and the physical gradient at the node
     float lam = ms.lam_g;
@@ -317,18 +426,15 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
       gr[1] = fmaf(tab->D1[tb][j], su[slot][ta + N1 * (j + N1 * tc)], gr[1]);
       gr[2] = fmaf(tab->D1[tc][j], su[slot][ta + N1 * (tb + N1 * j)], gr[2]);
     }
+    fetch_b();
+    const float gref[3] = {gr[0], gr[1], gr[2]};      // reference derivatives
 #pragma unroll
     for (int d = 0; d < 3; ++d) gr[d] *= tab->sc[d];
 
     // ---- shock-capturing weights (cells with gamma_e < C_gamma)
     float alpha = 1.0f;
     if (ms.sc_on && gam < ms.c_gamma) {
-      float a2 = 0.0f;
-      for (int k = 0; k < NK; ++k) {
-        const float dk = hex_ref_deriv<N1>(tab, su[slot], ta, tb, tc, tab->kk[k][0], tab->kk[k][1], tab->kk[k][2]);
-        a2 = fmaf(tab->wa[k] * dk, dk, a2);
-      }
-      const float at = fsqrt(a2);
+      const float at = fsqrt(hex_atil2<P>(tab, su[slot], ta, tb, tc, gref));
       const float f = lane_on ? (1.0f - gam) * (gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]) : 0.0f;
       const float Sv = team_sumf<TEAM>(W * f), Tv = team_sumf<TEAM>(W * at * f);
       if (Sv > 0.0f && Tv > 0.0f) alpha = at * (Sv / Tv);
@@ -336,7 +442,7 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     if (mode == MODE_SENSOR) {
       if (on && t == 0 && gamma_out) gamma_out[e] = gam;
       if (on && alpha_out) alpha_out[e * NL + t] = alpha;
-      __syncthreads();
+      wave_sync();
       continue;
     }
 
@@ -346,7 +452,7 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
 #pragma unroll
       for (int d = 0; d < 3; ++d) sv[slot][d][t] = W * tab->sc[d] * (gs * gr[d] - hex_flux<FLUX>(ms, uv, d));
     }
-    __syncthreads();
+    wave_sync();
     float r = 0.0f;
 #pragma unroll
     for (int q = 0; q < N1; ++q) {
@@ -394,7 +500,7 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
       out[idx] = o;
       if (t == 0 && gamma_out) gamma_out[e] = gam;
     }
-    __syncthreads();
+    wave_sync();
   }
   if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(status, ST_NONFINITE);
 }
@@ -417,28 +523,35 @@ cvw_status hex_candidates(const cvw_mesh* m, const cvw_params* prm, const float*
 
 template <int P, int FLUX>
 static void launch_hex_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
-                            float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
-                            float a0, float b0, hipStream_t s) {
+                            float* out, float* gamma, float* alpha, const float* cand, float* gbuf, uint32_t* status,
+                            float dt, float a0, float b0, hipStream_t s) {
   constexpr int CPB = HexShape<P>::CPB;
   const int64_t nblk = (m->E + CPB - 1) / CPB;
   const unsigned grid = static_cast<unsigned>(std::min<int64_t>(nblk, 16384));
-  hipLaunchKernelGGL((hex_eval_kernel<P, FLUX>), dim3(grid), dim3(256), 0, s, u, u0, out, gamma, alpha, cand,
-                     m->d_cell_vtx, m->d_nbr, m->d_hext, m->E, nblk, ms, mode, dt, a0, b0, status);
+  // the sensor pass writes gamma_e into the caller's array when there is one, else into the scratch
+  float* g = gamma ? gamma : gbuf;
+  if (ms.sensor_kind != CVW_SENSOR_FIXED)
+    hipLaunchKernelGGL((hex_sensor_kernel<P>), dim3(grid), dim3(256), 0, s, u, g, cand, m->d_cell_vtx, m->d_hext, m->E,
+                       nblk, ms);
+  // gamma_e is already in the caller's array when the sensor pass wrote it there
+  float* gout = (ms.sensor_kind != CVW_SENSOR_FIXED && gamma) ? nullptr : gamma;
+  hipLaunchKernelGGL((hex_eval_kernel<P, FLUX>), dim3(grid), dim3(256), 0, s, u, u0, out, gout, alpha, g, m->d_nbr,
+                     m->d_hext, m->E, nblk, ms, mode, dt, a0, b0, status);
 }
 
 cvw_status hex_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
-                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
-                    hipStream_t s) {
+                    float* gamma, float* alpha, const float* cand, float* gbuf, uint32_t* status, float dt, float a0,
+                    float b0, hipStream_t s) {
   const MethodScalars ms = make_scalars(prm);
   const bool burgers = prm->flux == CVW_BURGERS;
   switch (m->degree) {
     case 1:
-      if (burgers) launch_hex_eval<1, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
-      else launch_hex_eval<1, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      if (burgers) launch_hex_eval<1, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      else launch_hex_eval<1, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       break;
     case 2:
-      if (burgers) launch_hex_eval<2, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
-      else launch_hex_eval<2, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      if (burgers) launch_hex_eval<2, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      else launch_hex_eval<2, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       break;
     default: set_error("hexahedra: degree 1 or 2"); return CVW_EUNSUPPORTED;
   }

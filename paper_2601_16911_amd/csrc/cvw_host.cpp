@@ -730,6 +730,24 @@ static void fill_hex_tables(HexTables& T, int p, double hx, double hy, double hz
         T.R[l][a][k] = static_cast<double>(v);
       }
     }
+  // sparse lists (exact zeros by parity and by k >= a; the dense tables hold the same values)
+  for (int A = 0; A < T.nl; ++A) {
+    int n = 0;
+    for (int B = 0; B < T.nl; ++B)
+      if (T.G[A][B] != 0.0) { T.gb[A][n] = static_cast<int8_t>(B); T.gv[A][n] = T.G[A][B]; ++n; }
+    T.gn[A] = static_cast<int8_t>(n);
+  }
+  for (int a = 0; a < T.nk; ++a) {
+    int n = 0, r = 0;
+    const int Aa = mono(ks[a][0], ks[a][1], ks[a][2]);
+    for (int b = 0; b < T.nk; ++b) {
+      const double g = T.G[Aa][mono(ks[b][0], ks[b][1], ks[b][2])];
+      if (g != 0.0) { T.sb[a][n] = static_cast<int8_t>(b); T.sv[a][n] = g; ++n; }
+      if (ks[b][0] >= ks[a][0] && ks[b][1] >= ks[a][1] && ks[b][2] >= ks[a][2]) T.rk[a][r++] = static_cast<int8_t>(b);
+    }
+    T.sn[a] = static_cast<int8_t>(n);
+    T.rn[a] = static_cast<int8_t>(r);
+  }
 }
 
 static std::vector<double> fill_hp_tables(int p, bool lobatto) {
@@ -1528,7 +1546,7 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (prm->sensor == CVW_SENSOR_LEARNED)      // features, tile flags, audit partials and results
     b += align256(static_cast<size_t>(m->E) * MLP_IN * 2) + align256(static_cast<size_t>(sensor_tiles(m))) +
          align256(static_cast<size_t>(sensor_tiles(m)) * 16) + 256;
-  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG))
+  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG) || m->cell == CVW_HEX)
     b += align256(static_cast<size_t>(m->E) * 4);
   if (op == 1) b += 2 * align256(state_elems(m, n_var(m, prm->flux)) * es);
   if (op == 2)    // limiter: vertex candidates of every variable, gamma, the selected cells and their count
@@ -1695,7 +1713,7 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
     w.aout = reinterpret_cast<double*>(p);
     p += 256;
   }
-  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG)) {
+  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG) || m->cell == CVW_HEX) {
     w.gam = reinterpret_cast<float*>(p);
     p += align256(static_cast<size_t>(m->E) * 4);
   }
@@ -1789,7 +1807,7 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
     return seg_eval(m, prm, MODE_SENSOR, u, w.cand, w.pg, w.rcell, nullptr, gamma, alpha, w.status, s);
   if (m->cell == CVW_HEX)
     return hex_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
-                    static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s);
+                    static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.gam, w.status, 0.f, 0.f, 0.f, s);
   if (m->cell == CVW_TRI)
     return tri_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
                     static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s);
@@ -1942,8 +1960,8 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
     return seg_eval(m, prm, MODE_RESIDUAL, u, w.cand, w.pg, w.rcell, R, gamma_out, nullptr, w.status, s);
   if (m->cell == CVW_HEX)
     return hex_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
-                    static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
-                    0.f, s);
+                    static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.gam, w.status, 0.f,
+                    0.f, 0.f, s);
   if (m->cell == CVW_TRI)
     return tri_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
                     static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
@@ -1997,7 +2015,7 @@ cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, cons
                      const void* un, void* uo, double dt, double a0, double b0, hipStream_t s) {
   if (m->cell == CVW_HEX)
     return hex_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
-                    static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
+                    static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.gam, w.status,
                     static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s);
   if (m->cell == CVW_TRI)
     return tri_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),

@@ -175,6 +175,13 @@ struct HexTables {
   double G[HEX_NL][HEX_NL];              // sum_k h_e^{2|k|-3} int_K D^k xi^A D^k xi^B dx
   double HV[8][HEX_NK][HEX_NL];          // D^k u(x_l) from the nodal values less the first one
   double R[8][HEX_NK][HEX_NK];           // vertex candidate of vertex l (Taylor data) -> coefficient of xi^a, a in k
+  // the nonzero pattern of G (monomials of equal parity in every direction)
+  // and of R (k >= a componentwise), as short lists
+  int8_t gn[HEX_NL], gb[HEX_NL][8];      // row A of G: its nonzero columns
+  double gv[HEX_NL][8];
+  int8_t sn[HEX_NK], sb[HEX_NK][HEX_NK]; // G between the monomials of the multi-indices a, b
+  double sv[HEX_NK][HEX_NK];
+  int8_t rn[HEX_NK], rk[HEX_NK][HEX_NK]; // R[l][a][k] != 0 only for k in rk[a]
 };
 
 // Scalars of the method in the precision of the kernels.
@@ -502,12 +509,14 @@ cvw_status tri_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const fl
                     float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
                     hipStream_t s);
 cvw_status tri_totals(const cvw_mesh* m, int nvar, const float* u, double* partial, double* out_dev, hipStream_t s);
-// DG hexahedra (cvw_hex.hip): vertex candidates (one thread per vertex) and
-// the cell pass (one team of lanes per cell, a lane per node)
+// DG hexahedra (cvw_hex.hip): vertex candidates (one thread per vertex), the
+// sensor pass and the cell pass (one team of lanes per cell, a lane per node)
 cvw_status hex_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
+// the sensor pass (unless the sensor is fixed) writes gamma_e into gamma, or
+// into gbuf [E] when gamma is null; the cell pass reads it from there
 cvw_status hex_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
-                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
-                    hipStream_t s);
+                    float* gamma, float* alpha, const float* cand, float* gbuf, uint32_t* status, float dt, float a0,
+                    float b0, hipStream_t s);
 // time stepping (cvw_cgstep.hip)
 size_t pcg_partials(int64_t n);
 // M x = b for every variable: lines solve all nvar variables at once (vectors
