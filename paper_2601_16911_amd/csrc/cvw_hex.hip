@@ -32,22 +32,37 @@ struct HexShape {
   static constexpr int CPB = 256 / TEAM;             // cells per block of 256 threads
 };
 
+// Team reductions: the butterfly of the row reductions (quad pairs, the
+// mirrored lane of the other quad, of the other half row) over 8 or 16 lanes,
+// then the other row of a 32-lane team; every lane of the team receives
+// bitwise the same value.
 template <int TEAM>
 __device__ __forceinline__ double team_sum(double x) {
-#pragma unroll
-  for (int m = TEAM / 2; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+#pragma clang fp contract(off)
+  x = x + dppd<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
+  x = x + dppd<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+  x = x + dppd<0x141>(x);
+  if constexpr (TEAM >= 16) x = x + dppd<0x140>(x);
+  if constexpr (TEAM >= 32) x = x + __shfl_xor(x, 16);
   return x;
 }
 template <int TEAM>
 __device__ __forceinline__ float team_sumf(float x) {
-#pragma unroll
-  for (int m = TEAM / 2; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+#pragma clang fp contract(off)
+  x = x + dpp<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
+  x = x + dpp<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+  x = x + dpp<0x141>(x);
+  if constexpr (TEAM >= 16) x = x + dpp<0x140>(x);
+  if constexpr (TEAM >= 32) x = x + __shfl_xor(x, 16);
   return x;
 }
 template <int TEAM>
 __device__ __forceinline__ float team_maxf(float x) {
-#pragma unroll
-  for (int m = TEAM / 2; m >= 1; m >>= 1) x = fmaxf(x, __shfl_xor(x, m));
+  x = fmaxf(x, dpp<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x));
+  x = fmaxf(x, dpp<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x));
+  x = fmaxf(x, dpp<0x141>(x));
+  if constexpr (TEAM >= 16) x = fmaxf(x, dpp<0x140>(x));
+  if constexpr (TEAM >= 32) x = fmaxf(x, __shfl_xor(x, 16));
   return x;
 }
 
