@@ -17,6 +17,8 @@ All routines are plain numpy in float64.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 from numpy.polynomial import legendre as npleg
 from scipy.special import roots_jacobi
@@ -82,6 +84,45 @@ def stroud_triangle(n: int):
             pts.append((a[ia] * (1.0 - b[ib]), b[ib]))
             wts.append(wa[ia] * wb[ib])
     return np.array(pts), np.array(wts)
+
+
+def stroud_tet(n: int):
+    """n^3-point conical-product rule on the tetrahedron (0,0,0), (1,0,0),
+    (0,1,0), (0,0,1): collapsed coordinates x = a (1 - b)(1 - c),
+    y = b (1 - c), z = c with Gauss-Legendre in a, Gauss-Jacobi with weight
+    (1 - b) in b and (1 - c)^2 in c (all on [0, 1]).  Exact for total degree
+    2n - 1.  Point index = ia + n (ib + n ic)."""
+    xa, wa = gauss_legendre(n)
+    a, wa = 0.5 * (xa + 1.0), 0.5 * wa
+    xb, wb = roots_jacobi(n, 1.0, 0.0)
+    b, wb = 0.5 * (xb + 1.0), wb / 4.0
+    xc, wc = roots_jacobi(n, 2.0, 0.0)
+    c, wc = 0.5 * (xc + 1.0), wc / 8.0
+    pts, wts = [], []
+    for ic in range(n):
+        for ib in range(n):
+            for ia in range(n):
+                pts.append((a[ia] * (1.0 - b[ib]) * (1.0 - c[ic]), b[ib] * (1.0 - c[ic]), c[ic]))
+                wts.append(wa[ia] * wb[ib] * wc[ic])
+    return np.array(pts), np.array(wts)
+
+
+def radon_triangle():
+    """Radon's 7-point rule of degree 5 on the triangle (0,0),(1,0),(0,1),
+    symmetric under every permutation of the vertices: the centroid and two
+    orbits of three points, barycentric (a, a, 1 - 2a) with
+    a = (6 -+ sqrt 15) / 21, weights 9/40 and (155 -+ sqrt 15) / 1200 of the
+    area (1/2).  Returns points [7, 2] (the last two barycentric coordinates)
+    and weights [7]."""
+    r = math.sqrt(15.0)
+    bary = [(1 / 3, 1 / 3, 1 / 3)]
+    wts = [9 / 40]
+    for a, w in (((6 - r) / 21, (155 - r) / 1200), ((6 + r) / 21, (155 + r) / 1200)):
+        b = 1.0 - 2.0 * a
+        bary += [(a, a, b), (a, b, a), (b, a, a)]
+        wts += [w, w, w]
+    bary = np.array(bary)
+    return bary[:, 1:], 0.5 * np.array(wts)
 
 
 def multi_indices(dim: int, p: int):
@@ -262,8 +303,60 @@ class RefHex:
         return pts, np.outer(self.face_w1, self.face_w1).ravel()
 
 
+class RefTet:
+    """Lagrange P_p on the tetrahedron (0,0,0), (1,0,0), (0,1,0), (0,0,1) at
+    the equispaced lattice points (i, j, k) / p, i + j + k <= p, ordered with
+    i fastest, then j, then k.  Face f is opposite vertex f; its points are
+    Radon's degree-5 rule on its three vertices (weights summing to 1/2, the
+    area of the parameter triangle).  The rule is symmetric under the
+    permutations of a triangle's vertices, so the two cells of a face
+    integrate over one and the same set of points (conservation), whatever
+    the order in which each holds the face's vertices."""
+    dim = 3
+    n_vert = 4
+    n_faces = 4
+    FACE_VERTICES = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]
+
+    def __init__(self, p: int, nodes: str = "equispaced"):
+        self.p = p
+        nd = []
+        for k in range(p + 1):
+            for j in range(p + 1 - k):
+                for i in range(p + 1 - j - k):
+                    nd.append((i / p, j / p, k / p))
+        self.nodes = np.array(nd)
+        self.n_loc = len(nd)
+        self.mono = [(a, b, n - a - b) for n in range(p + 1) for a in range(n, -1, -1) for b in range(n - a, -1, -1)]
+        V = np.stack([self.nodes[:, 0] ** a * self.nodes[:, 1] ** b * self.nodes[:, 2] ** c for a, b, c in self.mono], axis=1)
+        self.Vinv = np.linalg.inv(V)      # column j = monomial coefficients of phi_j
+        self.vertices = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+        self.vol_pts, self.vol_w = stroud_tet(p + 1)
+        self.norm_pts, self.norm_w = self.vol_pts, self.vol_w
+        self.face_st, self.face_w = radon_triangle()
+
+    def deriv(self, pts, m):
+        pts = np.asarray(pts)
+        cols = []
+        for a, b, c in self.mono:
+            if a < m[0] or b < m[1] or c < m[2]:
+                cols.append(np.zeros(len(pts)))
+                continue
+            f = math.perm(a, m[0]) * math.perm(b, m[1]) * math.perm(c, m[2])
+            cols.append(f * pts[:, 0] ** (a - m[0]) * pts[:, 1] ** (b - m[1]) * pts[:, 2] ** (c - m[2]))
+        return np.stack(cols, axis=1) @ self.Vinv
+
+    def face_points(self, f):
+        va, vb, vc = (self.vertices[i] for i in self.FACE_VERTICES[f])
+        s, t = self.face_st[:, 0:1], self.face_st[:, 1:2]
+        return va + s * (vb - va) + t * (vc - va), self.face_w
+
+
 def make_ref(cell: int, p: int, space: int):
-    """cell: 1 segment, 2 triangle, 3 quadrilateral, 4 hexahedron; space: 0 CG, 1 DG."""
+    """cell: 1 segment, 2 triangle, 3 quadrilateral, 4 hexahedron, 5 tetrahedron; space: 0 CG, 1 DG."""
+    if cell == 5:
+        if space != 1:
+            raise NotImplementedError("tetrahedra: DG only")
+        return RefTet(p)
     if cell == 4:
         if space != 1:
             raise NotImplementedError("hexahedra: DG only")

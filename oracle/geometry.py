@@ -40,6 +40,9 @@ def map_jacobian(cell: int, X: np.ndarray, pts: np.ndarray):
         return J, np.zeros((E, n, 2, 2, 2))
     if cell == 4:
         return _trilinear_jacobian(X, pts)
+    if cell == 5:
+        J1 = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=-1)   # [E, 3, 3]
+        return np.broadcast_to(J1[:, None], (E, n, 3, 3)).copy(), np.zeros((E, n, 3, 3, 3))
     # bilinear quadrilateral, reference vertices (-1,-1),(1,-1),(1,1),(-1,1)
     s = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], dtype=np.float64)
     xi, eta = pts[:, 0], pts[:, 1]
@@ -87,6 +90,9 @@ def map_points(cell: int, X: np.ndarray, pts: np.ndarray):
     if cell == 4:
         N, _, _ = _trilinear_shape(np.asarray(pts, np.float64))
         return np.einsum("nv,evd->end", N, X)
+    if cell == 5:
+        J1 = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=-1)
+        return X[:, None, 0, :] + np.einsum("edk,nk->end", J1, np.asarray(pts, np.float64))
     if cell == 1:
         return (X[:, 0, 0][:, None] + 0.5 * (pts[None, :, 0] + 1.0) * (X[:, 1, 0] - X[:, 0, 0])[:, None])[..., None]
     if cell == 2:

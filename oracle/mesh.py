@@ -42,17 +42,23 @@ HEX_FACE_VERTICES = np.array([[0, 3, 7, 4], [1, 2, 6, 5], [0, 1, 5, 4], [3, 2, 6
                               [0, 1, 2, 3], [4, 5, 6, 7]])
 
 
-def hex_face_neighbours(cell_vertices: np.ndarray):
-    """(nbr [E, 6], nbr_face [E, 6]) of hexahedra: two faces match when they
-    hold the same four vertices; -1 on boundary faces."""
+# local vertices of the four faces of a tetrahedron, face f opposite vertex f
+TET_FACE_VERTICES = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]])
+
+
+def hex_face_neighbours(cell_vertices: np.ndarray, table=HEX_FACE_VERTICES):
+    """(nbr [E, F], nbr_face [E, F]) of 3D cells whose faces are the vertex
+    sets of `table` (hexahedra by default): two faces match when they hold the
+    same vertices; -1 on boundary faces."""
     E = cell_vertices.shape[0]
-    fv = np.sort(cell_vertices[:, HEX_FACE_VERTICES], axis=2).astype(np.int64)   # [E, 6, 4]
+    F = len(table)
+    fv = np.sort(cell_vertices[:, table], axis=2).astype(np.int64)   # [E, F, nv]
     keys = {}
     for e in range(E):
-        for f in range(6):
+        for f in range(F):
             keys.setdefault(tuple(fv[e, f]), []).append((e, f))
-    nbr = -np.ones((E, 6), np.int64)
-    nbr_face = -np.ones((E, 6), np.int64)
+    nbr = -np.ones((E, F), np.int64)
+    nbr_face = -np.ones((E, F), np.int64)
     for ents in keys.values():
         if len(ents) > 2:
             raise ValueError("non-conforming mesh: face shared by more than two cells")
@@ -72,6 +78,8 @@ def face_neighbours(cell: int, cell_vertices: np.ndarray):
     """
     if cell == 4:
         return hex_face_neighbours(cell_vertices)
+    if cell == 5:
+        return hex_face_neighbours(cell_vertices, TET_FACE_VERTICES)
     E = cell_vertices.shape[0]
     fv = face_vertex_pairs(cell, cell_vertices)
     F = fv.shape[1]

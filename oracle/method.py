@@ -514,11 +514,21 @@ def residual(sp, U, prm: Params, gamma=None, return_parts: bool = False, allow_b
 def face_geometry(sp, f):
     """Outward unit normal [E, d] and face Jacobian [E] of face f (the length / 2
     of an edge; the area / 4 of a flat hexahedron face, whose reference face
-    [-1, 1]^2 has area 4)."""
+    [-1, 1]^2 has area 4; twice the area of a tetrahedron face, whose
+    parameter triangle has area 1/2)."""
     X = sp.X
     if sp.cell == 1:
         n = np.full((sp.E, 1), -1.0 if f == 0 else 1.0)
         return n, np.ones(sp.E)
+    if sp.cell == 5:
+        from .mesh import TET_FACE_VERTICES
+        c = TET_FACE_VERTICES[f]
+        cr = np.cross(X[:, c[1]] - X[:, c[0]], X[:, c[2]] - X[:, c[0]])
+        jac = np.linalg.norm(cr, axis=1)                         # twice the area: the parameter triangle has area 1/2
+        n = cr / jac[:, None]
+        out = X[:, c].mean(1) - X.mean(1)
+        n = np.where(((n * out).sum(1) < 0)[:, None], -n, n)
+        return n, jac
     if sp.cell == 4:
         from .mesh import HEX_FACE_VERTICES
         c = HEX_FACE_VERTICES[f]
@@ -553,8 +563,10 @@ def face_terms(sp, Uc, prm: Params, allow_boundary: bool = False):
         en, fn = sp.nbr[:, f], sp.nbr_face[:, f]
         Up = Um.copy()                                             # boundary faces: zero jump, dropped below
         if sp.cell == 4:
-            Up[:, en >= 0] = _hex_neighbour_traces(sp, Uc, f, en, fn)[:, en >= 0]
-        for f2 in range(ref.n_faces if sp.cell != 4 else 0):
+            Up[:, en >= 0] = _neighbour_traces_by_position(sp, Uc, f, en, fn)[:, en >= 0]
+        elif sp.cell == 5:
+            Up[:, en >= 0] = _tet_neighbour_traces(sp, Uc, f, en, fn)[:, en >= 0]
+        for f2 in range(ref.n_faces if sp.cell not in (4, 5) else 0):
             sel = fn == f2
             if not sel.any():
                 continue
@@ -571,7 +583,7 @@ def face_terms(sp, Uc, prm: Params, allow_boundary: bool = False):
     return out
 
 
-def _hex_neighbour_traces(sp, Uc, f, en, fn):
+def _neighbour_traces_by_position(sp, Uc, f, en, fn):
     """The neighbour's trace at the points of face f of every cell [nv, E, ng].
     The points are paired by position: the neighbour's face points, moved by
     the offset between the two face centres (zero, or a period of the domain
@@ -593,6 +605,33 @@ def _hex_neighbour_traces(sp, Uc, f, en, fn):
             raise ValueError("face points of neighbouring cells do not coincide")
         phi2 = ref.deriv(p2[perm], (0,) * ref.dim)
         out[:, e] = np.einsum("vj,gj->vg", Uc[:, en[e]], phi2)
+    return out
+
+
+def _tet_neighbour_traces(sp, Uc, f, en, fn):
+    """The neighbour's trace at the cell's own points of face f [nv, E, ng]:
+    each point, moved by the offset between the two face centres (zero, or a
+    period of the domain), is mapped into the neighbour's reference
+    coordinates by the inverse of its affine map and must lie on the
+    neighbour's face fn (the face rule is not symmetric under a permutation of
+    the face's vertices, so the two cells' point sets differ)."""
+    from .mesh import TET_FACE_VERTICES
+    ref = sp.ref
+    pts, _ = ref.face_points(f)
+    X = sp.X
+    xf = map_points(sp.cell, X, pts)                               # [E, ng, 3]
+    out = np.zeros((Uc.shape[0], sp.E, len(pts)))
+    for e in range(sp.E):
+        if en[e] < 0:
+            continue
+        e2, f2 = int(en[e]), int(fn[e])
+        shift = X[e2, TET_FACE_VERTICES[f2]].mean(0) - X[e, TET_FACE_VERTICES[f]].mean(0)
+        J2 = np.stack([X[e2, 1] - X[e2, 0], X[e2, 2] - X[e2, 0], X[e2, 3] - X[e2, 0]], axis=-1)
+        xi = np.linalg.solve(J2, (xf[e] + shift - X[e2, 0]).T).T   # [ng, 3]
+        bary = np.concatenate([1.0 - xi.sum(1, keepdims=True), xi], axis=1)
+        if np.abs(bary[:, f2]).max() > 1e-10 or bary.min() < -1e-10:
+            raise ValueError("face points of neighbouring cells do not coincide")
+        out[:, e] = np.einsum("vj,gj->vg", Uc[:, e2], ref.deriv(xi, (0, 0, 0)))
     return out
 
 

@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SEG, TRI, QUAD, HEX = 1, 2, 3, 4
+SEG, TRI, QUAD, HEX, TET = 1, 2, 3, 4, 5
 CG, DG = 0, 1
 ADVECT_CONST, ADVECT_ROT, BURGERS, KPP, EULER = 0, 1, 2, 3, 4
 # boundary data at the two ends of a non-periodic 1D domain
@@ -139,6 +139,28 @@ def hex_mesh(nx: int, ny: int, nz: int, x0=0.0, x1=1.0, y0=0.0, y1=1.0, z0=0.0, 
     cc = np.stack([np.stack([x0 + (i + a) * hx, y0 + (j + b) * hy, z0 + (k + c) * hz], axis=-1)
                    for a, b, c in corners], axis=1).astype(np.float64)
     return MeshDesc(3, HEX, nvx * nvy * nvz, cv, cc, tuple(int(q) for q in periodic), (nx, ny, nz))
+
+
+def tet_mesh(nx: int, ny: int, nz: int, x0=0.0, x1=1.0, y0=0.0, y1=1.0, z0=0.0, z1=1.0,
+             periodic=(True, True, True)) -> MeshDesc:
+    """Each box of hex_mesh split into six tetrahedra around its diagonal from
+    the lowest to the highest corner (the same split in every box, so the
+    faces match across boxes); cell 6 box + t; every tetrahedron positively
+    oriented (vertices 1, 2 swapped where needed)."""
+    h = hex_mesh(nx, ny, nz, x0, x1, y0, y1, z0, z1, periodic)
+    paths = [(1, 2), (1, 5), (3, 2), (3, 7), (4, 5), (4, 7)]     # corners between 0 and 6
+    E = h.n_cells
+    cv = np.empty((6 * E, 4), np.int32)
+    cc = np.empty((6 * E, 4, 3), np.float64)
+    for t, (a, b) in enumerate(paths):
+        loc = [0, a, b, 6]
+        X = h.cell_coords[:, loc]
+        det = np.linalg.det(np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=-1))
+        if det[0] < 0:
+            loc = [0, b, a, 6]
+        cv[t::6] = h.cell_vertices[:, loc]
+        cc[t::6] = h.cell_coords[:, loc]
+    return MeshDesc(3, TET, h.n_vertices, cv, cc, h.periodic, h.shape)
 
 
 # ---------------------------------------------------------------------------
