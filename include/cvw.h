@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CVW_ABI_VERSION 11
+#define CVW_ABI_VERSION 12
 
 typedef enum {
   CVW_OK = 0,
@@ -71,7 +71,13 @@ typedef enum {
  * (x fastest); local faces 2 axis + side (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z);
  * cell_coords [E][8][3]; flux_param[0..2] is the velocity (or the Burgers
  * direction) (vx, vy, vz). */
-typedef enum { CVW_SEG = 1, CVW_TRI = 2, CVW_QUAD = 3, CVW_HEX = 4 } cvw_cell;
+/* Tetrahedra (CVW_TET, dim 3): DG P_p, p <= 2, on periodic meshes of
+ * positively oriented tetrahedra (every face shared by two cells), scalar
+ * fluxes, float32; four vertex candidates per cell.  Local nodes: the
+ * equispaced lattice (i, j, k) / p, i + j + k <= p, of the reference cell
+ * (0,0,0), (1,0,0), (0,1,0), (0,0,1), i fastest; face f opposite vertex f;
+ * cell_coords [E][4][3]. */
+typedef enum { CVW_SEG = 1, CVW_TRI = 2, CVW_QUAD = 3, CVW_HEX = 4, CVW_TET = 5 } cvw_cell;
 typedef enum { CVW_CG = 0, CVW_DG = 1 } cvw_space;
 typedef enum {
   CVW_ADVECT_CONST = 0,    /* f = v u, v = (flux_param[0], flux_param[1])                    */

@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["cvw_host.cpp", "cvw_dgquad.hip", "cvw_cgquad.hip", "cvw_seg.hip", "cvw_cgstep.hip", "cvw_tri.hip", "cvw_mlp.hip",
            "cvw_limit.hip", "cvw_dgsensor.hip",
-           "cvw_noalloc.hip", "cvw_seghp.hip", "cvw_hex.hip"]
+           "cvw_noalloc.hip", "cvw_seghp.hip", "cvw_hex.hip", "cvw_tet.hip"]
 
 # -ffp-contract=on: a * b + c is fused only within one expression, so kernels
 # that share a device body (single mesh, batch) round identically

@@ -750,6 +750,178 @@ static void fill_hex_tables(HexTables& T, int p, double hx, double hy, double hz
   }
 }
 
+// ---------------------------------------------------------------------------
+// tetrahedra: the equispaced Lagrange basis (inverse Vandermonde in the
+// monomials), the conical-product volume rule (Gauss-Legendre x Gauss-Jacobi
+// (1-b) x Gauss-Jacobi (1-c)^2), Radon's symmetric 7-point face rule, the
+// reference mass matrix, and the derivatives of the basis at the vertices
+// ---------------------------------------------------------------------------
+// Gauss rule for the weight (1 - x)^al on [-1, 1] (integer al >= 0): roots of
+// P_n^{(al,0)} (recurrence, sign scan and bisection), weights from the moments
+static double jacobi_a0(int n, int al, double x) {
+  const double a = al, b = 0.0;
+  double p0 = 1.0, p1 = (a + 1.0) + (a + b + 2.0) * (x - 1.0) / 2.0;
+  if (n == 0) return p0;
+  for (int k = 2; k <= n; ++k) {
+    const double c = 2.0 * k + a + b;
+    const double p2 = ((c - 1.0) * (c * (c - 2.0) * x + a * a - b * b) * p1 - 2.0 * (k + a - 1.0) * (k + b - 1.0) * c * p0) /
+                      (2.0 * k * (k + a + b) * (c - 2.0));
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+static void gauss_jacobi_a0(int n, int al, std::vector<double>& x, std::vector<double>& w) {
+  x.clear();
+  const int scan = 4000;
+  double xa = -1.0, fa = jacobi_a0(n, al, xa);
+  for (int i = 1; i <= scan && static_cast<int>(x.size()) < n; ++i) {
+    const double xb = -1.0 + 2.0 * i / scan, fb = jacobi_a0(n, al, xb);
+    if (fa == 0.0) { x.push_back(xa); }
+    else if (fa * fb < 0.0) {
+      double lo = xa, hi = xb, flo = fa;
+      for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        const double fm = jacobi_a0(n, al, mid);
+        if ((fm < 0.0) == (flo < 0.0)) { lo = mid; flo = fm; } else { hi = mid; }
+      }
+      x.push_back(0.5 * (lo + hi));
+    }
+    xa = xb;
+    fa = fb;
+  }
+  // moments int_{-1}^{1} x^k (1 - x)^al dx = sum_i C(al, i) (-1)^i int x^{k+i}
+  std::vector<double> V(n * n), m(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double binom = 1.0;
+    for (int i = 0; i <= al; ++i) {
+      if (i > 0) binom = binom * (al - i + 1) / i;
+      if ((k + i) % 2 == 0) m[k] += ((i % 2) ? -1.0 : 1.0) * binom * 2.0 / (k + i + 1);
+    }
+    for (int i = 0; i < n; ++i) V[k * n + i] = std::pow(x[i], k);
+  }
+  solve_dense(V, m, n);
+  w = m;
+}
+
+static void fill_tet_tables(TetTables& T, int p) {
+  std::memset(&T, 0, sizeof(T));
+  T.p = p;
+  // monomials x^a y^b z^c, a + b + c <= p (by total degree, then decreasing a, then decreasing b)
+  std::vector<std::array<int, 3>> mono;
+  for (int n = 0; n <= p; ++n)
+    for (int a = n; a >= 0; --a)
+      for (int b = n - a; b >= 0; --b) mono.push_back({a, b, n - a - b});
+  const int n = static_cast<int>(mono.size());
+  T.nloc = n;
+  T.nk = n - 1;
+  std::vector<std::array<double, 3>> nodes;
+  for (int k = 0; k <= p; ++k)
+    for (int j = 0; j <= p - k; ++j)
+      for (int i = 0; i <= p - j - k; ++i) nodes.push_back({double(i) / p, double(j) / p, double(k) / p});
+  std::vector<double> V(n * n), C(n * n, 0.0);
+  for (int r = 0; r < n; ++r) {
+    for (int i = 0; i < n; ++i)
+      V[r * n + i] = std::pow(nodes[r][0], mono[i][0]) * std::pow(nodes[r][1], mono[i][1]) * std::pow(nodes[r][2], mono[i][2]);
+    C[r * n + r] = 1.0;
+  }
+  solve_dense(V, C, n);          // C[i][j]: coefficient of monomial i in phi_j
+  auto ff = [](int a, int m) { double r = 1.0; for (int t = 0; t < m; ++t) r *= (a - t); return r; };
+  auto der = [&](int j, int mx, int my, int mz, double x, double y, double z) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const auto& mm = mono[i];
+      if (mm[0] < mx || mm[1] < my || mm[2] < mz) continue;
+      s += C[i * n + j] * ff(mm[0], mx) * ff(mm[1], my) * ff(mm[2], mz) * std::pow(x, mm[0] - mx) *
+           std::pow(y, mm[1] - my) * std::pow(z, mm[2] - mz);
+    }
+    return s;
+  };
+  // volume rule
+  const int n1 = p + 1;
+  std::vector<double> xa, wa, xb, wb, xc, wc;
+  gauss_rule(n1, xa, wa);
+  gauss_jacobi_a0(n1, 1, xb, wb);
+  gauss_jacobi_a0(n1, 2, xc, wc);
+  int q = 0;
+  for (int ic = 0; ic < n1; ++ic)
+    for (int ib = 0; ib < n1; ++ib)
+      for (int ia = 0; ia < n1; ++ia, ++q) {
+        const double a = 0.5 * (xa[ia] + 1.0), b = 0.5 * (xb[ib] + 1.0), c = 0.5 * (xc[ic] + 1.0);
+        T.xq[q][0] = a * (1.0 - b) * (1.0 - c);
+        T.xq[q][1] = b * (1.0 - c);
+        T.xq[q][2] = c;
+        T.wq[q] = 0.5 * wa[ia] * wb[ib] / 4.0 * wc[ic] / 8.0;
+      }
+  T.nq = q;
+  for (int qq = 0; qq < q; ++qq)
+    for (int j = 0; j < n; ++j) {
+      const double x = T.xq[qq][0], y = T.xq[qq][1], z = T.xq[qq][2];
+      T.B[qq][j] = der(j, 0, 0, 0, x, y, z);
+      T.G[0][qq][j] = der(j, 1, 0, 0, x, y, z);
+      T.G[1][qq][j] = der(j, 0, 1, 0, x, y, z);
+      T.G[2][qq][j] = der(j, 0, 0, 1, x, y, z);
+    }
+  static const int H[6][3] = {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
+  for (int h = 0; h < 6; ++h)
+    for (int j = 0; j < n; ++j) T.H2[h][j] = der(j, H[h][0], H[h][1], H[h][2], 0.25, 0.25, 0.25);
+  // multi-indices 1 <= |k| <= p and the derivatives at the reference vertices
+  static const double RV[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  std::vector<std::array<int, 3>> ks(mono.begin() + 1, mono.end());
+  for (int k = 0; k < T.nk; ++k) {
+    for (int d = 0; d < 3; ++d) T.kk[k][d] = static_cast<int8_t>(ks[k][d]);
+    for (int l = 0; l < 4; ++l)
+      for (int j = 0; j < n; ++j) T.TV[l][k][j] = der(j, ks[k][0], ks[k][1], ks[k][2], RV[l][0], RV[l][1], RV[l][2]);
+  }
+  // reference mass matrix (the volume rule is exact for degree 2p) and its inverse
+  std::vector<double> M(n * n, 0.0), Mi(n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j)
+      for (int qq = 0; qq < q; ++qq) M[i * n + j] += T.wq[qq] * T.B[qq][i] * T.B[qq][j];
+    Mi[i * n + i] = 1.0;
+  }
+  solve_dense(M, Mi, n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T.Minv[i][j] = static_cast<float>(Mi[i * n + j]);
+  // Radon's 7-point rule of degree 5: the centroid and two orbits (a, a, 1 - 2a), a = (6 -+ sqrt 15) / 21
+  double bary[TET_NFP][3], wr[TET_NFP];
+  const double r15 = std::sqrt(15.0);
+  bary[0][0] = bary[0][1] = bary[0][2] = 1.0 / 3.0;
+  wr[0] = 9.0 / 40.0;
+  for (int o = 0; o < 2; ++o) {
+    const double a = o == 0 ? (6.0 - r15) / 21.0 : (6.0 + r15) / 21.0, b = 1.0 - 2.0 * a;
+    const double w = o == 0 ? (155.0 - r15) / 1200.0 : (155.0 + r15) / 1200.0;
+    const double P3[3][3] = {{a, a, b}, {a, b, a}, {b, a, a}};
+    for (int i = 0; i < 3; ++i) {
+      for (int d = 0; d < 3; ++d) bary[1 + 3 * o + i][d] = P3[i][d];
+      wr[1 + 3 * o + i] = w;
+    }
+  }
+  for (int g = 0; g < TET_NFP; ++g) T.wf[g] = static_cast<float>(0.5 * wr[g]);
+  static const int FV[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+  for (int f = 0; f < 4; ++f)
+    for (int g = 0; g < TET_NFP; ++g) {
+      double x[3] = {0, 0, 0};
+      for (int i = 0; i < 3; ++i)
+        for (int d = 0; d < 3; ++d) x[d] += bary[g][i] * RV[FV[f][i]][d];
+      for (int j = 0; j < n; ++j) T.Bf[f][g][j] = static_cast<float>(der(j, 0, 0, 0, x[0], x[1], x[2]));
+    }
+  // permutations sigma of the face's three vertices (lexicographic order):
+  // the point with barycentrics lambda becomes the point with lambda o sigma
+  static const int SIG[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  for (int sg = 0; sg < 6; ++sg)
+    for (int g = 0; g < TET_NFP; ++g) {
+      int found = -1;
+      for (int h = 0; h < TET_NFP && found < 0; ++h) {
+        bool same = true;
+        for (int j = 0; j < 3; ++j) same = same && std::fabs(bary[h][j] - bary[g][SIG[sg][j]]) < 1e-12;
+        if (same) found = h;
+      }
+      T.perm[sg][g] = static_cast<int8_t>(found);
+    }
+}
+
 static std::vector<double> fill_hp_tables(int p, bool lobatto) {
   const int n1 = p + 1;
   const HPOff o = hp_off(p);
@@ -1015,6 +1187,9 @@ static void free_mesh(cvw_mesh* m) {
   (void)hipFree(m->d_geov);
   (void)hipFree(m->d_nbrf);
   (void)hipFree(m->d_hext);
+  (void)hipFree(m->d_tett);
+  (void)hipFree(m->d_geoth);
+  (void)hipFree(m->d_nbrt);
   (void)hipFree(m->d_dinv_f);
   (void)hipFree(m->d_dinv_d);
   delete m;
@@ -1037,14 +1212,17 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   else if (d->cell == CVW_TRI && d->dim == 2) { ve = 3; nf = 3; }
   else if (d->cell == CVW_QUAD && d->dim == 2) { ve = 4; nf = 4; }
   else if (d->cell == CVW_HEX && d->dim == 3) { ve = 8; nf = 6; }
+  else if (d->cell == CVW_TET && d->dim == 3) { ve = 4; nf = 4; }
   else { set_error("cell type / dimension mismatch"); return CVW_EINVAL; }
   if (d->cell == CVW_HEX && d->space != CVW_DG) { set_error("hexahedra: DG only"); return CVW_EUNSUPPORTED; }
+  if (d->cell == CVW_TET && d->space != CVW_DG) { set_error("tetrahedra: DG only"); return CVW_EUNSUPPORTED; }
   if (d->degree < 1 || d->degree > (d->cell == CVW_SEG ? HP_MAXP : 16)) { set_error("degree out of range"); return CVW_EINVAL; }
   if (d->space != CVW_CG && d->space != CVW_DG) { set_error("space must be CG or DG"); return CVW_EINVAL; }
   if (d->n_cells <= 0 || d->n_vertices <= 0) { set_error("empty mesh"); return CVW_EINVAL; }
   // packed (cell, local index) entries: cell * 4 + local vertex, cell * n_loc + local CG node
   const int64_t nloc_d = d->cell == CVW_SEG ? d->degree + 1 : d->cell == CVW_QUAD ? (d->degree + 1) * (d->degree + 1)
                           : d->cell == CVW_HEX ? (d->degree + 1) * (d->degree + 1) * (d->degree + 1)
+                          : d->cell == CVW_TET ? (d->degree + 1) * (d->degree + 2) * (d->degree + 3) / 6
                                                : (d->degree + 1) * (d->degree + 2) / 2;
   if (d->n_cells * std::max<int64_t>(8, nloc_d) >= (int64_t(1) << 31) || d->n_vertices >= (int64_t(1) << 31)) {
     set_error("mesh too large for 32-bit indices"); return CVW_EINVAL;
@@ -1058,6 +1236,7 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   if (d->cell == CVW_TRI) { m->nloc = (p + 1) * (p + 2) / 2; m->nq = (p + 1) * (p + 1); }
   else if (d->cell == CVW_QUAD) { m->nloc = (p + 1) * (p + 1); m->nq = (p + 1) * (p + 1); }
   else if (d->cell == CVW_HEX) { m->nloc = (p + 1) * (p + 1) * (p + 1); m->nq = m->nloc; }
+  else if (d->cell == CVW_TET) { m->nloc = (p + 1) * (p + 2) * (p + 3) / 6; m->nq = (p + 1) * (p + 1) * (p + 1); }
   else { m->nloc = p + 1; m->nq = p + 1; }
   m->nk = (d->dim == 1) ? p : d->dim == 2 ? (p + 1) * (p + 2) / 2 - 1 : (p + 1) * (p + 2) * (p + 3) / 6 - 1;
   (void)hipGetDevice(&m->device);
@@ -1089,7 +1268,7 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
       const int32_t pos = fill[v]++;
       m->h_vtx_cell[pos] = static_cast<int32_t>(e);
       m->h_vtx_lv[pos] = l;
-      ent[pos] = static_cast<int32_t>(e * (ve == 8 ? 8 : 4) + l);
+      ent[pos] = static_cast<int32_t>(e * (ve == 8 ? 8 : 4) + l);   // tetrahedra: cell * 4 + lv
     }
 
   // ---- geometry ----
@@ -1160,40 +1339,46 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   }
 
   // ---- DG face neighbours ----
-  if (d->space == CVW_DG && d->cell == CVW_HEX) {
-    // a face of a hexahedron is its four vertices (local faces 2 axis + side)
-    static const int FV[6][4] = {{0, 3, 7, 4}, {1, 2, 6, 5}, {0, 1, 5, 4}, {3, 2, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
+  if (d->space == CVW_DG && (d->cell == CVW_HEX || d->cell == CVW_TET)) {
+    // a face of a hexahedron is its four vertices (local faces 2 axis + side);
+    // of a tetrahedron its three vertices (face f opposite vertex f)
+    static const int FVH[6][4] = {{0, 3, 7, 4}, {1, 2, 6, 5}, {0, 1, 5, 4}, {3, 2, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
+    static const int FVT[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    const bool hexc = d->cell == CVW_HEX;
+    const int nfv = hexc ? 4 : 3;
     struct HK { std::array<int32_t, 4> v; int32_t ef; };
-    std::vector<HK> keys(E * 6);
+    std::vector<HK> keys(E * nf);
     for (int64_t e = 0; e < E; ++e)
-      for (int f = 0; f < 6; ++f) {
+      for (int f = 0; f < nf; ++f) {
         HK k;
-        for (int i = 0; i < 4; ++i) k.v[i] = d->cell_vertices[e * 8 + FV[f][i]];
+        k.v = {-1, -1, -1, -1};
+        for (int i = 0; i < nfv; ++i) k.v[i] = d->cell_vertices[e * ve + (hexc ? FVH[f][i] : FVT[f][i])];
         std::sort(k.v.begin(), k.v.end());
-        k.ef = static_cast<int32_t>(e * 6 + f);
-        keys[e * 6 + f] = k;
+        k.ef = static_cast<int32_t>(e * nf + f);
+        keys[e * nf + f] = k;
       }
     std::sort(keys.begin(), keys.end(), [](const HK& a, const HK& b) { return a.v < b.v || (a.v == b.v && a.ef < b.ef); });
-    m->h_nbr.assign(E * 6, -1);
-    m->h_nbr_face.assign(E * 6, -1);
+    m->h_nbr.assign(E * nf, -1);
+    m->h_nbr_face.assign(E * nf, -1);
     for (size_t i = 0; i < keys.size();) {
       size_t j = i;
       while (j + 1 < keys.size() && keys[j + 1].v == keys[i].v) ++j;
       if (j - i + 1 > 2) { free_mesh(m); set_error("non-conforming mesh: face shared by more than two cells"); return CVW_EINVAL; }
       if (j == i + 1) {
         const int32_t a = keys[i].ef, b = keys[j].ef;
-        m->h_nbr[a] = b / 6; m->h_nbr_face[a] = b % 6;
-        m->h_nbr[b] = a / 6; m->h_nbr_face[b] = a % 6;
+        m->h_nbr[a] = b / nf; m->h_nbr_face[a] = b % nf;
+        m->h_nbr[b] = a / nf; m->h_nbr_face[b] = a % nf;
       }
       i = j + 1;
     }
     m->closed = std::all_of(m->h_nbr.begin(), m->h_nbr.end(), [](int32_t x) { return x >= 0; }) ? 1 : 0;
-    for (int64_t i = 0; i < E * 6; ++i)
-      if (m->h_nbr[i] < 0) { m->h_bface.push_back(static_cast<int32_t>(i / 6)); m->h_bface.push_back(static_cast<int32_t>(i % 6)); }
+    for (int64_t i = 0; i < E * nf; ++i)
+      if (m->h_nbr[i] < 0) { m->h_bface.push_back(static_cast<int32_t>(i / nf)); m->h_bface.push_back(static_cast<int32_t>(i % nf)); }
     m->n_bfaces = static_cast<int64_t>(m->h_bface.size() / 2);
-    // the cell pass reads the neighbour across face f through its face f ^ 1
-    for (int64_t i = 0; i < E * 6; ++i)
-      if (m->h_nbr[i] >= 0 && m->h_nbr_face[i] != ((i % 6) ^ 1)) { m->uniform = 0; break; }
+    // the hexahedron cell pass reads the neighbour across face f through its face f ^ 1
+    if (hexc)
+      for (int64_t i = 0; i < E * 6; ++i)
+        if (m->h_nbr[i] >= 0 && m->h_nbr_face[i] != ((i % 6) ^ 1)) { m->uniform = 0; break; }
   } else if (d->space == CVW_DG) {
     struct FK { int64_t key; int32_t ef; };
     std::vector<FK> keys(E * nf);
@@ -1376,6 +1561,55 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     fill_hex_tables(ht[0], p, m->hx, m->hy, m->hz);
     if ((st = upload(&m->d_hext, ht)) != CVW_OK) { free_mesh(m); return st; }
   }
+  if (d->cell == CVW_TET) {
+    // per-cell geometry: vertex 0, J = [x1 - x0, x2 - x0, x3 - x0] (columns), diam; positive orientation
+    std::vector<double> gt(E * 16, 0.0);
+    for (int64_t e = 0; e < E; ++e) {
+      const double* X = d->cell_coords + e * 12;
+      double* g = gt.data() + e * 16;
+      for (int a = 0; a < 3; ++a) {
+        g[a] = X[a];
+        for (int b = 0; b < 3; ++b) g[3 + 3 * a + b] = X[3 * (b + 1) + a] - X[a];
+      }
+      g[12] = m->h_he[e];
+      const double* J = g + 3;
+      const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) + J[2] * (J[3] * J[7] - J[4] * J[6]);
+      if (!(det > 0.0)) { free_mesh(m); set_error("tetrahedra must be positively oriented and non-degenerate"); return CVW_EINVAL; }
+    }
+    if ((st = upload(&m->d_geoth, gt)) != CVW_OK) { free_mesh(m); return st; }
+    if (E >= (int64_t(1) << 26)) { free_mesh(m); set_error("tetrahedral mesh too large for the packed neighbour codes"); return CVW_EINVAL; }
+    // neighbour code: cell * 32 + its face * 8 + the permutation taking this face's
+    // vertex order (face f opposite vertex f, increasing) to the neighbour's
+    static const int FVT[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    static const int SIG[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    std::vector<int32_t> nc(E * 4, -1);
+    for (int64_t e = 0; e < E; ++e)
+      for (int f = 0; f < 4; ++f) {
+        const int32_t e2 = m->h_nbr[e * 4 + f];
+        if (e2 < 0) continue;
+        const int f2 = m->h_nbr_face[e * 4 + f];
+        int Gv[3], Hv[3];
+        for (int i = 0; i < 3; ++i) {
+          Gv[i] = d->cell_vertices[e * 4 + FVT[f][i]];
+          Hv[i] = d->cell_vertices[static_cast<int64_t>(e2) * 4 + FVT[f2][i]];
+        }
+        // sigma(j) = i with H[j] = G[i]: the neighbour's barycentric j is the own barycentric sigma(j)
+        int sg = -1;
+        for (int c = 0; c < 6 && sg < 0; ++c) {
+          bool ok = true;
+          for (int j = 0; j < 3; ++j) ok = ok && Hv[j] == Gv[SIG[c][j]];
+          if (ok) sg = c;
+        }
+        if (sg < 0) { free_mesh(m); set_error("tetrahedral faces do not match"); return CVW_EINVAL; }
+        nc[e * 4 + f] = e2 * 32 + f2 * 8 + sg;
+      }
+    if ((st = upload(&m->d_nbrt, nc)) != CVW_OK) { free_mesh(m); return st; }
+    if (p <= TET_MAXP) {
+      std::vector<TetTables> tt(1);
+      fill_tet_tables(tt[0], p);
+      if ((st = upload(&m->d_tett, tt)) != CVW_OK) { free_mesh(m); return st; }
+    }
+  }
   {
     const std::vector<double> dm = diag_mass(m, d);
     for (double v : dm)
@@ -1508,7 +1742,7 @@ static bool use_tile(const cvw_mesh* m, const cvw_params* prm) {
 // true when the mesh has a time-stepping path (stages and steps)
 static bool has_stage(const cvw_mesh* m) {
   return m->n_mass > 0 || (m->space == CVW_DG && (m->cell == CVW_QUAD || (m->cell == CVW_TRI && m->d_trit) ||
-                                                  (m->cell == CVW_HEX && m->d_hext)));
+                                                  (m->cell == CVW_HEX && m->d_hext) || (m->cell == CVW_TET && m->d_tett)));
 }
 
 // float64 scratch of the totals: block partials of up to four variables and the results
@@ -1586,6 +1820,15 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
   const bool cgq = m->cell == CVW_QUAD && m->space == CVW_CG;
   const bool seg = m->cell == CVW_SEG;
   const bool dgt = m->cell == CVW_TRI && m->space == CVW_DG;
+  if (m->cell == CVW_TET) {
+    if (!m->d_tett) { set_error("DG tetrahedra: degree <= 2"); return CVW_EUNSUPPORTED; }
+    if (!m->closed) { set_error("DG tetrahedra: meshes without boundary faces (periodic)"); return CVW_EUNSUPPORTED; }
+    if (prm->dtype != CVW_F32) { set_error("DG tetrahedra run in float32"); return CVW_EUNSUPPORTED; }
+    if (prm->flux != CVW_ADVECT_CONST && prm->flux != CVW_BURGERS) {
+      set_error("DG tetrahedra: constant-velocity advection and Burgers"); return CVW_EUNSUPPORTED;
+    }
+    return CVW_OK;
+  }
   if (m->cell == CVW_HEX) {
     if (!m->uniform || !m->d_hext) {
       set_error("DG hexahedra: congruent axis-aligned boxes, degree <= 2"); return CVW_EUNSUPPORTED;
@@ -1761,6 +2004,8 @@ static cvw_status candidates_any(const cvw_mesh* m, const cvw_params* prm, const
   if (m->cell == CVW_SEG) return seg_candidates(m, prm, u, cand, s);
   if (m->cell == CVW_HEX)
     return hex_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
+  if (m->cell == CVW_TET)
+    return tet_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
   if (m->cell == CVW_TRI)
     return tri_candidates(m, prm, static_cast<const float*>(u), static_cast<float*>(cand), s);
   if (m->space == CVW_CG)
@@ -1805,6 +2050,9 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
   }
   if (m->cell == CVW_SEG)
     return seg_eval(m, prm, MODE_SENSOR, u, w.cand, w.pg, w.rcell, nullptr, gamma, alpha, w.status, s);
+  if (m->cell == CVW_TET)
+    return tet_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
+                    static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s);
   if (m->cell == CVW_HEX)
     return hex_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
                     static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.gam, w.status, 0.f, 0.f, 0.f, s);
@@ -1958,6 +2206,10 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
   if (prm->sensor == CVW_SENSOR_LEARNED && (st = learned_gamma(m, prm, u, w.cand, w, s)) != CVW_OK) return st;
   if (m->cell == CVW_SEG)
     return seg_eval(m, prm, MODE_RESIDUAL, u, w.cand, w.pg, w.rcell, R, gamma_out, nullptr, w.status, s);
+  if (m->cell == CVW_TET)
+    return tet_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
+                    static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
+                    0.f, s);
   if (m->cell == CVW_HEX)
     return hex_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
                     static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.gam, w.status, 0.f,
@@ -2013,6 +2265,10 @@ cvw_status generic_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, 
 
 cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, const void* us, const void* cand,
                      const void* un, void* uo, double dt, double a0, double b0, hipStream_t s) {
+  if (m->cell == CVW_TET)
+    return tet_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
+                    static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
+                    static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s);
   if (m->cell == CVW_HEX)
     return hex_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
                     static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.gam, w.status,

@@ -184,6 +184,28 @@ struct HexTables {
   int8_t rn[HEX_NK], rk[HEX_NK][HEX_NK]; // R[l][a][k] != 0 only for k in rk[a]
 };
 
+// Tetrahedra: DG P_p (p <= TET_MAXP) at the equispaced lattice points of the
+// reference tetrahedron (0,0,0), (1,0,0), (0,1,0), (0,0,1) (i fastest, then
+// j, then k); volume rule the conical product of (p+1)^3 points; face f is
+// opposite vertex f, its points Radon's symmetric 7-point rule on the face's
+// vertices (f+1.., increasing).  Multi-indices as for hexahedra.
+constexpr int TET_MAXP = 2;
+constexpr int TET_NLOC = (TET_MAXP + 1) * (TET_MAXP + 2) * (TET_MAXP + 3) / 6;
+constexpr int TET_NK = TET_NLOC - 1, TET_NQ = (TET_MAXP + 1) * (TET_MAXP + 1) * (TET_MAXP + 1), TET_NFP = 7;
+struct TetTables {
+  int p, nloc, nk, nq;
+  double B[TET_NQ][TET_NLOC];            // phi_j at the volume points
+  double G[3][TET_NQ][TET_NLOC];         // d phi_j / d xi_b at the volume points
+  double H2[6][TET_NLOC];                // second reference derivatives (xx, xy, xz, yy, yz, zz; constant for p <= 2)
+  double xq[TET_NQ][3], wq[TET_NQ];      // volume points and weights (the weights sum to 1/6)
+  double TV[4][TET_NK][TET_NLOC];        // reference derivatives D^m phi_j at reference vertex l, 1 <= |m| <= p
+  float Bf[4][TET_NFP][TET_NLOC];        // phi_j at the points of face f
+  float wf[TET_NFP];                     // face weights (sum 1/2)
+  int8_t perm[6][TET_NFP];               // the rule point a point becomes under a permutation of the face's vertices
+  float Minv[TET_NLOC][TET_NLOC];        // inverse reference mass matrix
+  int8_t kk[TET_NK][3];                  // the multi-indices
+};
+
 // Scalars of the method in the precision of the kernels.
 struct MethodScalars {
   float eps_v, eps_c, r, q_sensor, q_beta, lin_w, c_gamma, lam_g;
@@ -425,6 +447,10 @@ struct cvw_mesh {
   // hexahedra
   double hz = 0;
   cvw::HexTables* d_hext = nullptr;
+  // tetrahedra
+  cvw::TetTables* d_tett = nullptr;
+  double* d_geoth = nullptr;          // [E][16] vertex 0, J (row-major, J[a][b] = dx_a / dxi_b), diam, padding
+  int32_t* d_nbrt = nullptr;          // [E][4] neighbour cell * 32 + its face * 8 + face permutation
   float* d_dinv_f = nullptr;          // [n_mass]
   double* d_dinv_d = nullptr;         // [n_mass]
   int64_t n_mass = 0;
@@ -512,6 +538,12 @@ cvw_status tri_totals(const cvw_mesh* m, int nvar, const float* u, double* parti
 // DG hexahedra (cvw_hex.hip): vertex candidates (one thread per vertex), the
 // sensor pass and the cell pass (one team of lanes per cell, a lane per node)
 cvw_status hex_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
+// DG tetrahedra (cvw_tet.hip): vertex candidates (one thread per vertex) and
+// the cell pass (one thread per cell: sensor, viscosity, SC weights, residual)
+cvw_status tet_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
+cvw_status tet_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
+                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
+                    hipStream_t s);
 // the sensor pass (unless the sensor is fixed) writes gamma_e into gamma, or
 // into gbuf [E] when gamma is null; the cell pass reads it from there
 cvw_status hex_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,

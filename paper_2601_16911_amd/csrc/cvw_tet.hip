@@ -1,0 +1,562 @@
+// DG on tetrahedra (P_1, P_2 at the equispaced lattice points; affine cells):
+//
+//  * tet_vertex_kernel -- one thread per mesh vertex: the Hermite data
+//    D^k u^e(x_i), 1 <= |k| <= p, of every cell of the vertex patch (eq.
+//    taylorsol) from reference derivatives of the basis at the reference
+//    vertex and the chain rule with the cell's inverse Jacobian, the pointwise
+//    smoothness indicators and Jiang-Shu weights, and the vertex candidate
+//    (eq. taylorcand), Sec. 3.2.  Float64.
+//  * tet_eval_kernel -- one thread per cell: the cell-vertex WENO sensor (eq.
+//    finalweno, eq. gamma) in float64 with the element semi-norms (eq. snorm,
+//    h_e^{2|k|-3}) taken by the volume rule (exact for these degrees), the
+//    viscosity (eq. lostab), the shock-capturing weights (eqs. dissrateorig
+//    to alphaq), the volume and interface terms of the DG residual in float32
+//    and optionally the Runge-Kutta stage update with the exact element mass.
+//
+// A face's points are Radon's symmetric rule; the neighbour's trace at the
+// cell's own point g is the neighbour's basis at its rule point perm[s][g],
+// s the permutation between the two cells' orders of the face's vertices
+// (packed with the neighbour's id and face by the mesh build).
+#include "cvw_device.h"
+
+namespace cvw {
+
+constexpr int TET_THREADS = 64;
+
+template <int P>
+struct TetShape {
+  static constexpr int NLOC = (P + 1) * (P + 2) * (P + 3) / 6, NK = NLOC - 1, NQ = (P + 1) * (P + 1) * (P + 1);
+};
+
+struct TetGeo {
+  double x0[3];
+  double J[3][3];   // J[a][b] = d x_a / d xi_b
+  double A[3][3];   // J^{-1}: A[b][a] = d xi_b / d x_a
+  double det, h;
+};
+
+__device__ __forceinline__ TetGeo load_tetgeo(const double* __restrict__ g, int64_t e) {
+  TetGeo G;
+  const double* p = g + e * 16;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    G.x0[a] = p[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) G.J[a][b] = p[3 + 3 * a + b];
+  }
+  G.h = p[12];
+  const double (&J)[3][3] = G.J;
+  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2],
+               c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  G.det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  const double inv = 1.0 / G.det;
+  G.A[0][0] = c00 * inv;
+  G.A[1][0] = c01 * inv;
+  G.A[2][0] = c02 * inv;
+  G.A[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * inv;
+  G.A[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * inv;
+  G.A[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * inv;
+  G.A[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * inv;
+  G.A[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * inv;
+  G.A[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * inv;
+  return G;
+}
+
+// physical derivatives (multi-index order (1,0,0),(0,1,0),(0,0,1),(2,0,0),
+// (1,1,0),(1,0,1),(0,2,0),(0,1,1),(0,0,2)) from reference derivatives in the
+// same order: d/dx_a = sum_b A[b][a] d/dxi_b
+template <int P>
+__device__ __forceinline__ void tet_phys(const double (&A)[3][3], const double* R, double* D) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) D[a] = A[0][a] * R[0] + A[1][a] * R[1] + A[2][a] * R[2];
+  if constexpr (P >= 2) {
+    double H[3][3];
+    H[0][0] = R[3]; H[0][1] = H[1][0] = R[4]; H[0][2] = H[2][0] = R[5];
+    H[1][1] = R[6]; H[1][2] = H[2][1] = R[7]; H[2][2] = R[8];
+    const int ia[6] = {0, 0, 0, 1, 1, 2}, ic[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s = fma(A[b][ia[t]] * A[d][ic[t]], H[b][d], s);
+      D[3 + t] = s;
+    }
+  }
+}
+
+// first derivatives at the offset dx of a Taylor polynomial t about its point (P = 2: plus
+// the constant second derivatives, already in t[3..8])
+template <int P>
+__device__ __forceinline__ void taylor_first(const double* t, const double (&dx)[3], double (&D)[3]) {
+  D[0] = t[0];
+  D[1] = t[1];
+  D[2] = t[2];
+  if constexpr (P >= 2) {
+    D[0] += t[3] * dx[0] + t[4] * dx[1] + t[5] * dx[2];
+    D[1] += t[4] * dx[0] + t[6] * dx[1] + t[7] * dx[2];
+    D[2] += t[5] * dx[0] + t[7] * dx[1] + t[8] * dx[2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// vertex pass
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void tet_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
+                                                         const int32_t* __restrict__ vptr,
+                                                         const int32_t* __restrict__ vent,
+                                                         const double* __restrict__ geot,
+                                                         const TetTables* __restrict__ tab, int64_t Nv,
+                                                         MethodScalars ms) {
+  using S = TetShape<P>;
+  constexpr int NLOC = S::NLOC, NK = S::NK;
+  __shared__ double sTV[4][NK][NLOC];
+  for (int i = threadIdx.x; i < 4 * NK * NLOC; i += blockDim.x) {
+    const int l = i / (NK * NLOC), r = i % (NK * NLOC);
+    sTV[l][r / NLOC][r % NLOC] = tab->TV[l][r / NLOC][r % NLOC];
+  }
+  __syncthreads();
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= Nv) return;
+  double acc[NK], wsum = 0.0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) acc[k] = 0.0;
+  for (int32_t i = vptr[v]; i < vptr[v + 1]; ++i) {
+    const int32_t ent = vent[i];
+    const int64_t ce = ent >> 2;
+    const int lv = ent & 3;
+    const TetGeo G = load_tetgeo(geot, ce);
+    const float* uc = u + ce * NLOC;
+    const double u0 = static_cast<double>(uc[0]);
+    double R[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) R[k] = 0.0;
+#pragma unroll
+    for (int j = 1; j < NLOC; ++j) {
+      const double dj = static_cast<double>(uc[j]) - u0;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) R[k] = fma(sTV[lv][k][j], dj, R[k]);
+    }
+    double D[NK];
+    tet_phys<P>(G.A, R, D);
+    // pointwise semi-norm with h_e^{2|k|} of this cell
+    const double h2 = G.h * G.h;
+    double b2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) b2 = fma((k < 3 ? h2 : h2 * h2) * D[k], D[k], b2);
+    double beta = sqrt(b2);
+    double w;
+    if (ms.fast_exp) {
+      const double t = ms.eps_vd + beta;
+      w = 1.0 / (t * t);
+    } else {
+      beta = pow(beta, static_cast<double>(ms.q_beta));
+      w = pow(ms.eps_vd + beta, -static_cast<double>(ms.r));
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) acc[k] = fma(w, D[k], acc[k]);
+    wsum += w;
+  }
+  const double iw = 1.0 / wsum;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) cand[v * NK + k] = static_cast<float>(acc[k] * iw);
+}
+
+// ---------------------------------------------------------------------------
+// cell pass
+// ---------------------------------------------------------------------------
+template <int FLUX>
+__device__ __forceinline__ float tet_fn(const MethodScalars& ms, float u, const float (&n)[3]) {
+  const float vn = ms.fp[0] * n[0] + ms.fp[1] * n[1] + ms.fp[2] * n[2];
+  if constexpr (FLUX == CVW_BURGERS) return 0.5f * u * u * vn;
+  else return vn * u;
+}
+
+template <int P, int FLUX>
+__global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
+    const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out, float* __restrict__ gamma_out,
+    float* __restrict__ alpha_out, const float* __restrict__ cand, const int32_t* __restrict__ cell_vtx,
+    const int32_t* __restrict__ nbrt, const double* __restrict__ geot, const TetTables* __restrict__ tab, int64_t E,
+    MethodScalars ms, int mode, float dt, float a0, float b0, uint32_t* __restrict__ status) {
+  using S = TetShape<P>;
+  constexpr int NLOC = S::NLOC, NK = S::NK, NQ = S::NQ;
+  __shared__ double sc[TET_THREADS][4 * NK + 1];    // the four vertex candidates of the thread's cell
+  const int tid = threadIdx.x;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * TET_THREADS + tid;
+  if (e >= E) return;
+  const TetGeo G = load_tetgeo(geot, e);
+  float uv[NLOC];
+#pragma unroll
+  for (int j = 0; j < NLOC; ++j) uv[j] = u[e * NLOC + j];
+  const double vol = G.det / 6.0;
+  const double h2 = G.h * G.h;
+  const double hw1 = 1.0 / G.h, hw2 = G.h;          // h_e^{2|k|-3}: |k| = 1, 2
+
+  // ---- sensor gamma_e (float64)
+  float gam = ms.fixed_gamma;
+  if (ms.sensor_kind != CVW_SENSOR_FIXED) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const float* cv = cand + static_cast<int64_t>(cell_vtx[e * 4 + l]) * NK;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) sc[tid][l * NK + k] = static_cast<double>(cv[k]);
+    }
+    double du[NLOC];
+    const double u00 = static_cast<double>(uv[0]);
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) du[j] = static_cast<double>(uv[j]) - u00;
+    // constant second derivatives (P = 2) of u_h and the candidates
+    double Hu[6] = {0, 0, 0, 0, 0, 0};
+    if constexpr (P >= 2) {
+      double R[NK];
+#pragma unroll
+      for (int k = 0; k < NK; ++k) R[k] = 0.0;
+#pragma unroll
+      for (int t = 0; t < 6; ++t)
+#pragma unroll
+        for (int j = 1; j < NLOC; ++j) R[3 + t] = fma(tab->H2[t][j], du[j], R[3 + t]);
+      double D[NK];
+      tet_phys<P>(G.A, R, D);
+#pragma unroll
+      for (int t = 0; t < 6; ++t) Hu[t] = D[3 + t];
+    }
+    // vertex positions
+    double xv[4][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      xv[0][a] = G.x0[a];
+#pragma unroll
+      for (int l = 1; l < 4; ++l) xv[l][a] = G.x0[a] + G.J[a][l - 1];
+    }
+    // pass 1: ||u_h||_e^2 and the candidates' semi-norms
+    double n02 = 0.0, b2[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < NQ; ++q) {
+      const double W = tab->wq[q] * G.det;
+      double gref[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int j = 1; j < NLOC; ++j) {
+        gref[0] = fma(tab->G[0][q][j], du[j], gref[0]);
+        gref[1] = fma(tab->G[1][q][j], du[j], gref[1]);
+        gref[2] = fma(tab->G[2][q][j], du[j], gref[2]);
+      }
+      double xq[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        xq[a] = G.x0[a] + G.J[a][0] * tab->xq[q][0] + G.J[a][1] * tab->xq[q][1] + G.J[a][2] * tab->xq[q][2];
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double d = G.A[0][a] * gref[0] + G.A[1][a] * gref[1] + G.A[2][a] * gref[2];
+        s = fma(d, d, s);
+      }
+      n02 = fma(W * hw1, s, n02);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const double dx[3] = {xq[0] - xv[l][0], xq[1] - xv[l][1], xq[2] - xv[l][2]};
+        double D[3];
+        taylor_first<P>(&sc[tid][l * NK], dx, D);
+        b2[l] = fma(W * hw1, D[0] * D[0] + D[1] * D[1] + D[2] * D[2], b2[l]);
+      }
+    }
+    if constexpr (P >= 2) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t) n02 = fma(vol * hw2 * Hu[t], Hu[t], n02);
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int t = 0; t < 6; ++t) b2[l] = fma(vol * hw2 * sc[tid][l * NK + 3 + t], sc[tid][l * NK + 3 + t], b2[l]);
+    }
+    // weights of the cell candidate and the four vertex candidates
+    const double n0 = sqrt(fmax(n02, 0.0));
+    double om[5], wsum = 0.0;
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      const double b = l == 0 ? n0 : sqrt(fmax(b2[l - 1], 0.0));
+      const double lin = l == 0 ? 1.0 - 4.0 * ms.lin_wd : ms.lin_wd;
+      if (ms.fast_exp) {
+        const double t = ms.eps_cd + b;
+        om[l] = lin / (t * t);
+      } else {
+        om[l] = lin * pow(ms.eps_cd + pow(b, static_cast<double>(ms.q_beta)), -static_cast<double>(ms.r));
+      }
+      wsum += om[l];
+    }
+    double osum = 0.0;
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      om[l] /= wsum;
+      if (l > 0) osum += om[l];
+    }
+    // pass 2: the semi-norm of diff = sum_l omega_l (u_h - s_l)
+    double d2 = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+      const double W = tab->wq[q] * G.det;
+      double gref[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int j = 1; j < NLOC; ++j) {
+        gref[0] = fma(tab->G[0][q][j], du[j], gref[0]);
+        gref[1] = fma(tab->G[1][q][j], du[j], gref[1]);
+        gref[2] = fma(tab->G[2][q][j], du[j], gref[2]);
+      }
+      double xq[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        xq[a] = G.x0[a] + G.J[a][0] * tab->xq[q][0] + G.J[a][1] * tab->xq[q][1] + G.J[a][2] * tab->xq[q][2];
+      double Dd[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) Dd[a] = osum * (G.A[0][a] * gref[0] + G.A[1][a] * gref[1] + G.A[2][a] * gref[2]);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const double dx[3] = {xq[0] - xv[l][0], xq[1] - xv[l][1], xq[2] - xv[l][2]};
+        double D[3];
+        taylor_first<P>(&sc[tid][l * NK], dx, D);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Dd[a] = fma(-om[l + 1], D[a], Dd[a]);
+      }
+      d2 = fma(W * hw1, Dd[0] * Dd[0] + Dd[1] * Dd[1] + Dd[2] * Dd[2], d2);
+    }
+    if constexpr (P >= 2) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        double hd = osum * Hu[t];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) hd = fma(-om[l + 1], sc[tid][l * NK + 3 + t], hd);
+        d2 = fma(vol * hw2 * hd, hd, d2);
+      }
+    }
+    if (n0 > 0.0) {
+      double ratio = fmin(1.0, sqrt(fmax(d2, 0.0)) / n0);
+      if (!ms.fast_exp) ratio = pow(ratio, static_cast<double>(ms.q_sensor));
+      gam = static_cast<float>(1.0 - ratio);
+    } else {
+      gam = 1.0f;
+    }
+  }
+
+  // ---- residual (float32)
+  float A[3][3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) A[b][a] = static_cast<float>(G.A[b][a]);
+  const float fdet = static_cast<float>(G.det);
+  // second derivatives (P = 2; constant), for alpha~
+  float hs2 = 0.0f;
+  if constexpr (P >= 2) {
+    double R[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) R[k] = 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) R[3 + t] = fma(tab->H2[t][j], static_cast<double>(uv[j]), R[3 + t]);
+    double D[NK];
+    tet_phys<P>(G.A, R, D);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) hs2 += static_cast<float>(D[3 + t] * D[3 + t]);
+  }
+  float lam = ms.lam_g;
+  if (!(lam > 0.0f)) {
+    const float vn = fsqrt(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1] + ms.fp[2] * ms.fp[2]);
+    lam = 0.0f;
+    for (int q = 0; q < NQ; ++q) {
+      float uq = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) uq = fmaf(static_cast<float>(tab->B[q][j]), uv[j], uq);
+      lam = fmaxf(lam, FLUX == CVW_BURGERS ? fabsf(uq) * vn : vn);
+    }
+  }
+  const float nu = lam * static_cast<float>(G.h) / (2.0f * P);
+  // SC weights: S = sum W f, T = sum W alpha~ f over the volume points
+  const bool sc_active = ms.sc_on && gam < ms.c_gamma;
+  float Sv = 0.0f, Tv = 0.0f;
+  const float fh2 = static_cast<float>(h2);
+  if (sc_active) {
+    for (int q = 0; q < NQ; ++q) {
+      float gr[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gr[b] = fmaf(static_cast<float>(tab->G[b][q][j]), uv[j], gr[b]);
+      float g2 = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float d = A[0][a] * gr[0] + A[1][a] * gr[1] + A[2][a] * gr[2];
+        g2 = fmaf(d, d, g2);
+      }
+      const float at = fsqrt(fh2 * g2 + fh2 * fh2 * hs2);
+      const float W = static_cast<float>(tab->wq[q]) * fdet;
+      const float f = (1.0f - gam) * g2;
+      Sv = fmaf(W, f, Sv);
+      Tv = fmaf(W * at, f, Tv);
+    }
+  }
+  const bool use_alpha = sc_active && Sv > 0.0f && Tv > 0.0f;
+  const float ratioST = use_alpha ? Sv / Tv : 0.0f;
+  float r[NLOC];
+#pragma unroll
+  for (int j = 0; j < NLOC; ++j) r[j] = 0.0f;
+  for (int q = 0; q < NQ; ++q) {
+    float uq = 0.0f, gr[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) {
+      uq = fmaf(static_cast<float>(tab->B[q][j]), uv[j], uq);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) gr[b] = fmaf(static_cast<float>(tab->G[b][q][j]), uv[j], gr[b]);
+    }
+    float gp[3], g2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      gp[a] = A[0][a] * gr[0] + A[1][a] * gr[1] + A[2][a] * gr[2];
+      g2 = fmaf(gp[a], gp[a], g2);
+    }
+    float alpha = 1.0f;
+    if (use_alpha) alpha = fsqrt(fh2 * g2 + fh2 * fh2 * hs2) * ratioST;
+    const float W = static_cast<float>(tab->wq[q]) * fdet;
+    const float gs = nu * alpha * (1.0f - gam);
+    if (mode == MODE_SENSOR) {
+      if (alpha_out) alpha_out[e * NQ + q] = alpha;
+      continue;
+    }
+    float V[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float fa = FLUX == CVW_BURGERS ? 0.5f * uq * uq * ms.fp[a] : ms.fp[a] * uq;
+      V[a] = W * (gs * gp[a] - fa);
+    }
+    float Vr[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Vr[b] = A[b][0] * V[0] + A[b][1] * V[1] + A[b][2] * V[2];
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) r[j] = fmaf(static_cast<float>(tab->G[b][q][j]), Vr[b], r[j]);
+  }
+  if (mode == MODE_SENSOR) {
+    if (gamma_out) gamma_out[e] = gam;
+    return;
+  }
+
+  // ---- interface terms (face f opposite vertex f)
+  float xvf[4][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    xvf[0][a] = 0.0f;
+#pragma unroll
+    for (int l = 1; l < 4; ++l) xvf[l][a] = static_cast<float>(G.J[a][l - 1]);   // relative to vertex 0
+  }
+  const int FV[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int32_t code = nbrt[e * 4 + f];
+    const int64_t e2 = code >> 5;
+    const int f2 = (code >> 3) & 3, sg = code & 7;
+    const float* va = xvf[FV[f][0]];
+    const float* vb = xvf[FV[f][1]];
+    const float* vc = xvf[FV[f][2]];
+    const float t1[3] = {vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]};
+    const float t2[3] = {vc[0] - va[0], vc[1] - va[1], vc[2] - va[2]};
+    float n[3] = {t1[1] * t2[2] - t1[2] * t2[1], t1[2] * t2[0] - t1[0] * t2[2], t1[0] * t2[1] - t1[1] * t2[0]};
+    const float jf = fsqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const float ij = 1.0f / jf;
+    const float* vo = xvf[f];
+    const float side = n[0] * (vo[0] - va[0]) + n[1] * (vo[1] - va[1]) + n[2] * (vo[2] - va[2]);
+    const float sgn = side > 0.0f ? -ij : ij;          // outward: away from the opposite vertex
+#pragma unroll
+    for (int a = 0; a < 3; ++a) n[a] *= sgn;
+    float un[NLOC];
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) un[j] = u[e2 * NLOC + j];
+    float lfv = 0.0f;
+    if constexpr (FLUX != CVW_BURGERS) lfv = fabsf(ms.fp[0] * n[0] + ms.fp[1] * n[1] + ms.fp[2] * n[2]);
+    const float bn = fabsf(ms.fp[0] * n[0] + ms.fp[1] * n[1] + ms.fp[2] * n[2]);
+#pragma unroll
+    for (int g = 0; g < TET_NFP; ++g) {
+      const int g2 = tab->perm[sg][g];
+      float um = 0.0f, up = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) {
+        um = fmaf(tab->Bf[f][g][j], uv[j], um);
+        up = fmaf(tab->Bf[f2][g2][j], un[j], up);
+      }
+      float lf = ms.lam_g;
+      if (!(lf > 0.0f)) lf = FLUX == CVW_BURGERS ? fmaxf(fabsf(um), fabsf(up)) * bn : lfv;
+      const float fs = 0.5f * (tet_fn<FLUX>(ms, um, n) + tet_fn<FLUX>(ms, up, n)) - 0.5f * lf * (up - um);
+      const float w = tab->wf[g] * jf * fs;
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) r[j] = fmaf(tab->Bf[f][g][j], w, r[j]);
+    }
+  }
+
+  // ---- output
+  bool nonfinite = false;
+  if (mode == MODE_RESIDUAL) {
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) {
+      nonfinite = nonfinite || !isfinite(r[j]);
+      out[e * NLOC + j] = r[j];
+    }
+  } else {
+    // u_out = a0 u_n + b0 (u - dt M_e^{-1} r), M_e = det J M_ref
+    const float scl = dt / fdet;
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) {
+      float x = 0.0f;
+#pragma unroll
+      for (int i = 0; i < NLOC; ++i) x = fmaf(tab->Minv[j][i], r[i], x);
+      const int64_t idx = e * NLOC + j;
+      const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
+      const float o = base + b0 * (uv[j] - scl * x);
+      nonfinite = nonfinite || !isfinite(o);
+      out[idx] = o;
+    }
+  }
+  if (gamma_out) gamma_out[e] = gam;
+  if (nonfinite) atomicOr(status, ST_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+cvw_status tet_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s) {
+  const MethodScalars ms = make_scalars(prm);
+  const dim3 g(static_cast<unsigned>((m->Nv + 255) / 256)), b(256);
+  switch (m->degree) {
+    case 1: hipLaunchKernelGGL(tet_vertex_kernel<1>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geoth, m->d_tett, m->Nv, ms); break;
+    case 2: hipLaunchKernelGGL(tet_vertex_kernel<2>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geoth, m->d_tett, m->Nv, ms); break;
+    default: set_error("tetrahedra: degree 1 or 2"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+template <int P, int FLUX>
+static void launch_tet_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
+                            float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
+                            float a0, float b0, hipStream_t s) {
+  const dim3 g(static_cast<unsigned>((m->E + TET_THREADS - 1) / TET_THREADS)), b(TET_THREADS);
+  hipLaunchKernelGGL((tet_eval_kernel<P, FLUX>), g, b, 0, s, u, u0, out, gamma, alpha, cand, m->d_cell_vtx, m->d_nbrt,
+                     m->d_geoth, m->d_tett, m->E, ms, mode, dt, a0, b0, status);
+}
+
+cvw_status tet_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
+                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
+                    hipStream_t s) {
+  const MethodScalars ms = make_scalars(prm);
+  const bool burgers = prm->flux == CVW_BURGERS;
+  switch (m->degree) {
+    case 1:
+      if (burgers) launch_tet_eval<1, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      else launch_tet_eval<1, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      break;
+    case 2:
+      if (burgers) launch_tet_eval<2, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      else launch_tet_eval<2, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      break;
+    default: set_error("tetrahedra: degree 1 or 2"); return CVW_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;
+}
+
+}  // namespace cvw

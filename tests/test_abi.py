@@ -26,7 +26,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(cvw.SYMBOLS)
-    assert lib.cvw_abi_version() == 11
+    assert lib.cvw_abi_version() == 12
 
 
 def test_struct_layouts_match_header():
