@@ -862,7 +862,10 @@ static void fill_tet_tables(TetTables& T, int p) {
       T.G[0][qq][j] = der(j, 1, 0, 0, x, y, z);
       T.G[1][qq][j] = der(j, 0, 1, 0, x, y, z);
       T.G[2][qq][j] = der(j, 0, 0, 1, x, y, z);
+      T.Bs[qq][j] = static_cast<float>(T.B[qq][j]);
+      for (int b = 0; b < 3; ++b) T.Gs[b][qq][j] = static_cast<float>(T.G[b][qq][j]);
     }
+  for (int qq = 0; qq < q; ++qq) T.wqs[qq] = static_cast<float>(T.wq[qq]);
   static const int H[6][3] = {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
   for (int h = 0; h < 6; ++h)
     for (int j = 0; j < n; ++j) T.H2[h][j] = der(j, H[h][0], H[h][1], H[h][2], 0.25, 0.25, 0.25);
@@ -1780,7 +1783,8 @@ size_t cvw_workspace_bytes(const cvw_mesh* m, const cvw_params* prm, int op) {
   if (prm->sensor == CVW_SENSOR_LEARNED)      // features, tile flags, audit partials and results
     b += align256(static_cast<size_t>(m->E) * MLP_IN * 2) + align256(static_cast<size_t>(sensor_tiles(m))) +
          align256(static_cast<size_t>(sensor_tiles(m)) * 16) + 256;
-  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG) || m->cell == CVW_HEX)
+  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG) || m->cell == CVW_HEX ||
+      m->cell == CVW_TET)
     b += align256(static_cast<size_t>(m->E) * 4);
   if (op == 1) b += 2 * align256(state_elems(m, n_var(m, prm->flux)) * es);
   if (op == 2)    // limiter: vertex candidates of every variable, gamma, the selected cells and their count
@@ -1956,7 +1960,8 @@ static WS carve(const cvw_mesh* m, const cvw_params* prm, void* ws) {
     w.aout = reinterpret_cast<double*>(p);
     p += 256;
   }
-  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG) || m->cell == CVW_HEX) {
+  if (prm->sensor == CVW_SENSOR_LEARNED || (m->cell == CVW_QUAD && m->space == CVW_DG) || m->cell == CVW_HEX ||
+      m->cell == CVW_TET) {
     w.gam = reinterpret_cast<float*>(p);
     p += align256(static_cast<size_t>(m->E) * 4);
   }
@@ -2052,7 +2057,7 @@ cvw_status cvw_sensor(const cvw_mesh* m, const cvw_params* prm, const void* u, v
     return seg_eval(m, prm, MODE_SENSOR, u, w.cand, w.pg, w.rcell, nullptr, gamma, alpha, w.status, s);
   if (m->cell == CVW_TET)
     return tet_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
-                    static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.status, 0.f, 0.f, 0.f, s);
+                    static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.gam, w.status, 0.f, 0.f, 0.f, s);
   if (m->cell == CVW_HEX)
     return hex_eval(m, prm, MODE_SENSOR, static_cast<const float*>(u), nullptr, nullptr, static_cast<float*>(gamma),
                     static_cast<float*>(alpha), static_cast<const float*>(w.cand), w.gam, w.status, 0.f, 0.f, 0.f, s);
@@ -2208,8 +2213,8 @@ cvw_status cvw_residual(const cvw_mesh* m, const cvw_params* prm, const void* u,
     return seg_eval(m, prm, MODE_RESIDUAL, u, w.cand, w.pg, w.rcell, R, gamma_out, nullptr, w.status, s);
   if (m->cell == CVW_TET)
     return tet_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
-                    static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.status, 0.f, 0.f,
-                    0.f, s);
+                    static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.gam, w.status, 0.f,
+                    0.f, 0.f, s);
   if (m->cell == CVW_HEX)
     return hex_eval(m, prm, MODE_RESIDUAL, static_cast<const float*>(u), nullptr, static_cast<float*>(R),
                     static_cast<float*>(gamma_out), nullptr, static_cast<const float*>(w.cand), w.gam, w.status, 0.f,
@@ -2267,7 +2272,7 @@ cvw_status any_stage(const cvw_mesh* m, const cvw_params* prm, const WS& w, cons
                      const void* un, void* uo, double dt, double a0, double b0, hipStream_t s) {
   if (m->cell == CVW_TET)
     return tet_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),
-                    static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.status,
+                    static_cast<float*>(uo), nullptr, nullptr, static_cast<const float*>(cand), w.gam, w.status,
                     static_cast<float>(dt), static_cast<float>(a0), static_cast<float>(b0), s);
   if (m->cell == CVW_HEX)
     return hex_eval(m, prm, MODE_STAGE, static_cast<const float*>(us), static_cast<const float*>(un),

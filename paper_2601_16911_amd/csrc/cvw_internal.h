@@ -198,6 +198,9 @@ struct TetTables {
   double G[3][TET_NQ][TET_NLOC];         // d phi_j / d xi_b at the volume points
   double H2[6][TET_NLOC];                // second reference derivatives (xx, xy, xz, yy, yz, zz; constant for p <= 2)
   double xq[TET_NQ][3], wq[TET_NQ];      // volume points and weights (the weights sum to 1/6)
+  float Bs[TET_NQ][TET_NLOC];            // float32 copies for the residual: phi_j, d phi_j / d xi_b, weights
+  float Gs[3][TET_NQ][TET_NLOC];
+  float wqs[TET_NQ];
   double TV[4][TET_NK][TET_NLOC];        // reference derivatives D^m phi_j at reference vertex l, 1 <= |m| <= p
   float Bf[4][TET_NFP][TET_NLOC];        // phi_j at the points of face f
   float wf[TET_NFP];                     // face weights (sum 1/2)
@@ -538,12 +541,14 @@ cvw_status tri_totals(const cvw_mesh* m, int nvar, const float* u, double* parti
 // DG hexahedra (cvw_hex.hip): vertex candidates (one thread per vertex), the
 // sensor pass and the cell pass (one team of lanes per cell, a lane per node)
 cvw_status hex_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
-// DG tetrahedra (cvw_tet.hip): vertex candidates (one thread per vertex) and
-// the cell pass (one thread per cell: sensor, viscosity, SC weights, residual)
+// DG tetrahedra (cvw_tet.hip): vertex candidates (one thread per vertex), the
+// sensor pass and the cell pass (one thread per cell)
 cvw_status tet_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);
+// (the sensor pass writes gamma_e into gamma, or into gbuf [E] when gamma is
+// null; the cell pass reads it from there)
 cvw_status tet_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
-                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
-                    hipStream_t s);
+                    float* gamma, float* alpha, const float* cand, float* gbuf, uint32_t* status, float dt, float a0,
+                    float b0, hipStream_t s);
 // the sensor pass (unless the sensor is fixed) writes gamma_e into gamma, or
 // into gbuf [E] when gamma is null; the cell pass reads it from there
 cvw_status hex_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,

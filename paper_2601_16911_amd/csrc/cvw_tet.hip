@@ -6,12 +6,13 @@
 //    vertex and the chain rule with the cell's inverse Jacobian, the pointwise
 //    smoothness indicators and Jiang-Shu weights, and the vertex candidate
 //    (eq. taylorcand), Sec. 3.2.  Float64.
-//  * tet_eval_kernel -- one thread per cell: the cell-vertex WENO sensor (eq.
-//    finalweno, eq. gamma) in float64 with the element semi-norms (eq. snorm,
-//    h_e^{2|k|-3}) taken by the volume rule (exact for these degrees), the
-//    viscosity (eq. lostab), the shock-capturing weights (eqs. dissrateorig
-//    to alphaq), the volume and interface terms of the DG residual in float32
-//    and optionally the Runge-Kutta stage update with the exact element mass.
+//  * tet_sensor_kernel -- one thread per cell: the cell-vertex WENO sensor
+//    (eq. finalweno, eq. gamma) in float64 with the element semi-norms (eq.
+//    snorm, h_e^{2|k|-3}) taken by the volume rule (exact for these degrees).
+//  * tet_eval_kernel -- one thread per cell, float32: the viscosity (eq.
+//    lostab), the shock-capturing weights (eqs. dissrateorig to alphaq), the
+//    volume and interface terms of the DG residual and optionally the
+//    Runge-Kutta stage update with the exact element mass.
 //
 // A face's points are Radon's symmetric rule; the neighbour's trace at the
 // cell's own point g is the neighbour's basis at its rule point perm[s][g],
@@ -174,12 +175,13 @@ __device__ __forceinline__ float tet_fn(const MethodScalars& ms, float u, const 
   else return vn * u;
 }
 
-template <int P, int FLUX>
-__global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
-    const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out, float* __restrict__ gamma_out,
-    float* __restrict__ alpha_out, const float* __restrict__ cand, const int32_t* __restrict__ cell_vtx,
-    const int32_t* __restrict__ nbrt, const double* __restrict__ geot, const TetTables* __restrict__ tab, int64_t E,
-    MethodScalars ms, int mode, float dt, float a0, float b0, uint32_t* __restrict__ status) {
+template <int P>
+__global__ __launch_bounds__(TET_THREADS) void tet_sensor_kernel(const float* __restrict__ u, float* __restrict__ gamma,
+                                                                 const float* __restrict__ cand,
+                                                                 const int32_t* __restrict__ cell_vtx,
+                                                                 const double* __restrict__ geot,
+                                                                 const TetTables* __restrict__ tab, int64_t E,
+                                                                 MethodScalars ms) {
   using S = TetShape<P>;
   constexpr int NLOC = S::NLOC, NK = S::NK, NQ = S::NQ;
   __shared__ double sc[TET_THREADS][4 * NK + 1];    // the four vertex candidates of the thread's cell
@@ -191,12 +193,10 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
 #pragma unroll
   for (int j = 0; j < NLOC; ++j) uv[j] = u[e * NLOC + j];
   const double vol = G.det / 6.0;
-  const double h2 = G.h * G.h;
   const double hw1 = 1.0 / G.h, hw2 = G.h;          // h_e^{2|k|-3}: |k| = 1, 2
-
   // ---- sensor gamma_e (float64)
-  float gam = ms.fixed_gamma;
-  if (ms.sensor_kind != CVW_SENSOR_FIXED) {
+  float gam = 1.0f;
+  {
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const float* cv = cand + static_cast<int64_t>(cell_vtx[e * 4 + l]) * NK;
@@ -335,6 +335,28 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
     }
   }
 
+  gamma[e] = gam;
+}
+
+template <int P, int FLUX>
+__global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
+    const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out, float* __restrict__ gamma_out,
+    float* __restrict__ alpha_out, const float* __restrict__ gamma_in, const int32_t* __restrict__ nbrt, const double* __restrict__ geot, const TetTables* __restrict__ tab, int64_t E,
+    MethodScalars ms, int mode, float dt, float a0, float b0, uint32_t* __restrict__ status) {
+  using S = TetShape<P>;
+  constexpr int NLOC = S::NLOC, NK = S::NK, NQ = S::NQ;
+  const int tid = threadIdx.x;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * TET_THREADS + tid;
+  if (e >= E) return;
+  const TetGeo G = load_tetgeo(geot, e);
+  float uv[NLOC];
+#pragma unroll
+  for (int j = 0; j < NLOC; ++j) uv[j] = u[e * NLOC + j];
+  const double h2 = G.h * G.h;
+
+  // ---- gamma_e: from the sensor pass, or the fixed value
+  const float gam = ms.sensor_kind != CVW_SENSOR_FIXED ? gamma_in[e] : ms.fixed_gamma;
+
   // ---- residual (float32)
   float A[3][3];
 #pragma unroll
@@ -364,7 +386,7 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
     for (int q = 0; q < NQ; ++q) {
       float uq = 0.0f;
 #pragma unroll
-      for (int j = 0; j < NLOC; ++j) uq = fmaf(static_cast<float>(tab->B[q][j]), uv[j], uq);
+      for (int j = 0; j < NLOC; ++j) uq = fmaf(tab->Bs[q][j], uv[j], uq);
       lam = fmaxf(lam, FLUX == CVW_BURGERS ? fabsf(uq) * vn : vn);
     }
   }
@@ -379,7 +401,7 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
 #pragma unroll
       for (int j = 0; j < NLOC; ++j)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) gr[b] = fmaf(static_cast<float>(tab->G[b][q][j]), uv[j], gr[b]);
+        for (int b = 0; b < 3; ++b) gr[b] = fmaf(tab->Gs[b][q][j], uv[j], gr[b]);
       float g2 = 0.0f;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -387,7 +409,7 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
         g2 = fmaf(d, d, g2);
       }
       const float at = fsqrt(fh2 * g2 + fh2 * fh2 * hs2);
-      const float W = static_cast<float>(tab->wq[q]) * fdet;
+      const float W = tab->wqs[q] * fdet;
       const float f = (1.0f - gam) * g2;
       Sv = fmaf(W, f, Sv);
       Tv = fmaf(W * at, f, Tv);
@@ -402,9 +424,9 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
     float uq = 0.0f, gr[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int j = 0; j < NLOC; ++j) {
-      uq = fmaf(static_cast<float>(tab->B[q][j]), uv[j], uq);
+      uq = fmaf(tab->Bs[q][j], uv[j], uq);
 #pragma unroll
-      for (int b = 0; b < 3; ++b) gr[b] = fmaf(static_cast<float>(tab->G[b][q][j]), uv[j], gr[b]);
+      for (int b = 0; b < 3; ++b) gr[b] = fmaf(tab->Gs[b][q][j], uv[j], gr[b]);
     }
     float gp[3], g2 = 0.0f;
 #pragma unroll
@@ -414,7 +436,7 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
     }
     float alpha = 1.0f;
     if (use_alpha) alpha = fsqrt(fh2 * g2 + fh2 * fh2 * hs2) * ratioST;
-    const float W = static_cast<float>(tab->wq[q]) * fdet;
+    const float W = tab->wqs[q] * fdet;
     const float gs = nu * alpha * (1.0f - gam);
     if (mode == MODE_SENSOR) {
       if (alpha_out) alpha_out[e * NQ + q] = alpha;
@@ -432,7 +454,7 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
 #pragma unroll
     for (int j = 0; j < NLOC; ++j)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) r[j] = fmaf(static_cast<float>(tab->G[b][q][j]), Vr[b], r[j]);
+      for (int b = 0; b < 3; ++b) r[j] = fmaf(tab->Gs[b][q][j], Vr[b], r[j]);
   }
   if (mode == MODE_SENSOR) {
     if (gamma_out) gamma_out[e] = gam;
@@ -533,26 +555,32 @@ cvw_status tet_candidates(const cvw_mesh* m, const cvw_params* prm, const float*
 
 template <int P, int FLUX>
 static void launch_tet_eval(const cvw_mesh* m, const MethodScalars& ms, int mode, const float* u, const float* u0,
-                            float* out, float* gamma, float* alpha, const float* cand, uint32_t* status, float dt,
-                            float a0, float b0, hipStream_t s) {
+                            float* out, float* gamma, float* alpha, const float* cand, float* gbuf, uint32_t* status,
+                            float dt, float a0, float b0, hipStream_t s) {
   const dim3 g(static_cast<unsigned>((m->E + TET_THREADS - 1) / TET_THREADS)), b(TET_THREADS);
-  hipLaunchKernelGGL((tet_eval_kernel<P, FLUX>), g, b, 0, s, u, u0, out, gamma, alpha, cand, m->d_cell_vtx, m->d_nbrt,
-                     m->d_geoth, m->d_tett, m->E, ms, mode, dt, a0, b0, status);
+  // the sensor pass writes gamma_e into the caller's array when there is one, else into the scratch
+  float* gs = gamma ? gamma : gbuf;
+  const bool plain = ms.sensor_kind != CVW_SENSOR_FIXED;
+  if (plain)
+    hipLaunchKernelGGL((tet_sensor_kernel<P>), g, b, 0, s, u, gs, cand, m->d_cell_vtx, m->d_geoth, m->d_tett, m->E, ms);
+  float* gout = (plain && gamma) ? nullptr : gamma;
+  hipLaunchKernelGGL((tet_eval_kernel<P, FLUX>), g, b, 0, s, u, u0, out, gout, alpha, gs, m->d_nbrt, m->d_geoth,
+                     m->d_tett, m->E, ms, mode, dt, a0, b0, status);
 }
 
 cvw_status tet_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const float* u, const float* u0, float* out,
-                    float* gamma, float* alpha, const float* cand, uint32_t* status, float dt, float a0, float b0,
-                    hipStream_t s) {
+                    float* gamma, float* alpha, const float* cand, float* gbuf, uint32_t* status, float dt, float a0,
+                    float b0, hipStream_t s) {
   const MethodScalars ms = make_scalars(prm);
   const bool burgers = prm->flux == CVW_BURGERS;
   switch (m->degree) {
     case 1:
-      if (burgers) launch_tet_eval<1, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
-      else launch_tet_eval<1, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      if (burgers) launch_tet_eval<1, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      else launch_tet_eval<1, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       break;
     case 2:
-      if (burgers) launch_tet_eval<2, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
-      else launch_tet_eval<2, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, status, dt, a0, b0, s);
+      if (burgers) launch_tet_eval<2, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      else launch_tet_eval<2, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       break;
     default: set_error("tetrahedra: degree 1 or 2"); return CVW_EUNSUPPORTED;
   }
