@@ -22,6 +22,7 @@
 // coefficients and quadrature terms through LDS and reduces with
 // cross-lane shuffles; idle lanes of a Q_2 team carry zeros.
 #include "cvw_device.h"
+#include "cvw_cells3d.h"
 
 namespace cvw {
 

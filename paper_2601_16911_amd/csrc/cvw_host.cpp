@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "cvw_internal.h"
+#include "cvw_cells3d.h"
 #include "cvw_limit.h"
 
 namespace cvw {

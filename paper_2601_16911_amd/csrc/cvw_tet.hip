@@ -19,6 +19,7 @@
 // s the permutation between the two cells' orders of the face's vertices
 // (packed with the neighbour's id and face by the mesh build).
 #include "cvw_device.h"
+#include "cvw_cells3d.h"
 
 namespace cvw {
 
