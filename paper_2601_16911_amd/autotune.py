@@ -39,7 +39,7 @@ def arch() -> str:
 def mesh_key(mesh, params) -> str:
     info = mesh.info
     flux = int(params.flux)
-    n_var = 4 if flux == cvw.EULER else 1
+    n_var = mesh.n_var(flux)
     return (f"{arch()}|mesh|deg{mesh.degree}|space{mesh.space}|nloc{info['n_loc']}|flux{flux}|nvar{n_var}"
             f"|cells{info['n_cells']}")
 
