@@ -312,34 +312,36 @@ __global__ __launch_bounds__(256) void hex_sensor_kernel(const float* __restrict
       }
       wave_sync();
       // weights of the cell candidate (l = 0) and the eight vertex candidates:
-      // lane t takes l = t and l = t + TEAM (a team of 8 lanes has nine weights)
-      const double n0 = sqrt(fmax(n02, 0.0));
-      double wv[2] = {0.0, 0.0}, wpart = 0.0;
+      // lane t takes l = t and l = t + TEAM (a team of 8 lanes has nine
+      // weights).  The semi-norms are float64 sums; their square roots and the
+      // weights are taken in float32 (relative rounding 1e-7 in gamma_e).
+      const float n0 = fsqrt(static_cast<float>(fmax(n02, 0.0)));
+      float wv[2] = {0.0f, 0.0f}, wpart = 0.0f;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int l = t + j * TEAM;
         if (l > 8) continue;
-        double b = n0;
+        float b = n0;
         if (l >= 1) {
           double b2 = 0.0;
 #pragma unroll
           for (int a = 0; a < NK; ++a) b2 += sq[slot][l - 1][a];
-          b = sqrt(fmax(b2, 0.0));
+          b = fsqrt(static_cast<float>(fmax(b2, 0.0)));
         }
-        const double lin = l == 0 ? 1.0 - 8.0 * ms.lin_wd : ms.lin_wd;
+        const float lin = l == 0 ? 1.0f - 8.0f * ms.lin_w : ms.lin_w;
         if (ms.fast_exp) {
-          const double tt = ms.eps_cd + b;
+          const float tt = ms.eps_c + b;
           wv[j] = lin / (tt * tt);
         } else {
-          wv[j] = lin * pow(ms.eps_cd + pow(b, static_cast<double>(ms.q_beta)), -static_cast<double>(ms.r));
+          wv[j] = lin * powf(ms.eps_c + powf(b, ms.q_beta), -ms.r);
         }
         wpart += wv[j];
       }
-      const double wsum = team_sum<TEAM>(wpart);
+      const float wsum = team_sumf<TEAM>(wpart);
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int l = t + j * TEAM;
-        if (l <= 8) som[slot][l] = wv[j] / wsum;
+        if (l <= 8) som[slot][l] = static_cast<double>(wv[j] / wsum);
       }
       wave_sync();
       // diff = sum_{l >= 1} omega_l (u_h - s_l)
@@ -362,10 +364,10 @@ __global__ __launch_bounds__(256) void hex_sensor_kernel(const float* __restrict
         for (int r = 0; r < sgn[t]; ++r) gd = fma(sgv[t][r], sb[slot][sgb[t][r]], gd);
       }
       const double d2 = team_sum<TEAM>(Dv * gd);
-      if (n0 > 0.0) {
-        double ratio = fmin(1.0, sqrt(fmax(d2, 0.0)) / n0);
-        if (!ms.fast_exp) ratio = pow(ratio, static_cast<double>(ms.q_sensor));
-        gam = static_cast<float>(1.0 - ratio);
+      if (n02 > 0.0) {
+        float ratio = fminf(1.0f, fsqrt(static_cast<float>(fmax(d2, 0.0))) / n0);
+        if (!ms.fast_exp) ratio = powf(ratio, ms.q_sensor);
+        gam = 1.0f - ratio;
       } else {
         gam = 1.0f;
       }

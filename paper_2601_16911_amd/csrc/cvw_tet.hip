@@ -269,27 +269,30 @@ __global__ __launch_bounds__(TET_THREADS) void tet_sensor_kernel(const float* __
 #pragma unroll
         for (int t = 0; t < 6; ++t) b2[l] = fma(vol * hw2 * sc[tid][l * NK + 3 + t], sc[tid][l * NK + 3 + t], b2[l]);
     }
-    // weights of the cell candidate and the four vertex candidates
-    const double n0 = sqrt(fmax(n02, 0.0));
-    double om[5], wsum = 0.0;
+    // weights of the cell candidate and the four vertex candidates: the
+    // semi-norms are float64 sums, their square roots and the weights float32
+    const float n0 = fsqrt(static_cast<float>(fmax(n02, 0.0)));
+    double om[5];
+    {
+      float wf[5], wsum = 0.0f;
 #pragma unroll
-    for (int l = 0; l < 5; ++l) {
-      const double b = l == 0 ? n0 : sqrt(fmax(b2[l - 1], 0.0));
-      const double lin = l == 0 ? 1.0 - 4.0 * ms.lin_wd : ms.lin_wd;
-      if (ms.fast_exp) {
-        const double t = ms.eps_cd + b;
-        om[l] = lin / (t * t);
-      } else {
-        om[l] = lin * pow(ms.eps_cd + pow(b, static_cast<double>(ms.q_beta)), -static_cast<double>(ms.r));
+      for (int l = 0; l < 5; ++l) {
+        const float b = l == 0 ? n0 : fsqrt(static_cast<float>(fmax(b2[l - 1], 0.0)));
+        const float lin = l == 0 ? 1.0f - 4.0f * ms.lin_w : ms.lin_w;
+        if (ms.fast_exp) {
+          const float t = ms.eps_c + b;
+          wf[l] = lin / (t * t);
+        } else {
+          wf[l] = lin * powf(ms.eps_c + powf(b, ms.q_beta), -ms.r);
+        }
+        wsum += wf[l];
       }
-      wsum += om[l];
+#pragma unroll
+      for (int l = 0; l < 5; ++l) om[l] = static_cast<double>(wf[l] / wsum);
     }
     double osum = 0.0;
 #pragma unroll
-    for (int l = 0; l < 5; ++l) {
-      om[l] /= wsum;
-      if (l > 0) osum += om[l];
-    }
+    for (int l = 1; l < 5; ++l) osum += om[l];
     // pass 2: the semi-norm of diff = sum_l omega_l (u_h - s_l)
     double d2 = 0.0;
     for (int q = 0; q < NQ; ++q) {
@@ -327,10 +330,10 @@ __global__ __launch_bounds__(TET_THREADS) void tet_sensor_kernel(const float* __
         d2 = fma(vol * hw2 * hd, hd, d2);
       }
     }
-    if (n0 > 0.0) {
-      double ratio = fmin(1.0, sqrt(fmax(d2, 0.0)) / n0);
-      if (!ms.fast_exp) ratio = pow(ratio, static_cast<double>(ms.q_sensor));
-      gam = static_cast<float>(1.0 - ratio);
+    if (n02 > 0.0) {
+      float ratio = fminf(1.0f, fsqrt(static_cast<float>(fmax(d2, 0.0))) / n0);
+      if (!ms.fast_exp) ratio = powf(ratio, ms.q_sensor);
+      gam = 1.0f - ratio;
     } else {
       gam = 1.0f;
     }
