@@ -32,13 +32,6 @@ struct HexTables {
   double G[HEX_NL][HEX_NL];              // sum_k h_e^{2|k|-3} int_K D^k xi^A D^k xi^B dx
   double HV[8][HEX_NK][HEX_NL];          // D^k u(x_l) from the nodal values less the first one
   double R[8][HEX_NK][HEX_NK];           // vertex candidate of vertex l (Taylor data) -> coefficient of xi^a, a in k
-  // the nonzero pattern of G (monomials of equal parity in every direction)
-  // and of R (k >= a componentwise), as short lists
-  int8_t gn[HEX_NL], gb[HEX_NL][8];      // row A of G: its nonzero columns
-  double gv[HEX_NL][8];
-  int8_t sn[HEX_NK], sb[HEX_NK][HEX_NK]; // G between the monomials of the multi-indices a, b
-  double sv[HEX_NK][HEX_NK];
-  int8_t rn[HEX_NK], rk[HEX_NK][HEX_NK]; // R[l][a][k] != 0 only for k in rk[a]
 };
 
 // Tetrahedra: DG P_p (p <= TET_MAXP) at the equispaced lattice points of the
@@ -67,7 +60,8 @@ struct TetTables {
 };
 
 // DG hexahedra (cvw_hex.hip): vertex candidates (one thread per vertex), the
-// sensor pass and the cell pass (one team of lanes per cell, a lane per node);
+// sensor pass (one thread per cell) and the cell pass (one team of lanes per
+// cell, a lane per node);
 // the sensor pass (unless the sensor is fixed) writes gamma_e into gamma, or
 // into gbuf [E] when gamma is null, and the cell pass reads it from there
 cvw_status hex_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s);

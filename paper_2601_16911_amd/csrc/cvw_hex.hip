@@ -5,12 +5,14 @@
 //    patch (eq. taylorsol) from tabulated corner derivatives of the Lagrange
 //    basis, the pointwise smoothness indicators and Jiang-Shu weights, and the
 //    vertex candidate (eq. taylorcand), Sec. 3.2.  Float64 accumulation.
+//  * hex_sensor_kernel -- one thread per cell: the cell-vertex WENO sensor
+//    (eq. finalweno, eq. gamma).
 //  * hex_eval_kernel -- a team of lanes per cell, one lane per node (8 lanes
-//    for Q_1, 27 of 32 for Q_2): the cell-vertex WENO sensor (eq. finalweno,
-//    eq. gamma) in float64, the viscosity (eq. lostab), the shock-capturing
-//    weights (eqs. dissrateorig to alphaq), the volume and interface terms of
-//    the DG residual in float32, and optionally the Runge-Kutta stage update
-//    with the exact (diagonal, Gauss-collocated) element mass.
+//    for Q_1, 27 of 32 for Q_2): the viscosity (eq. lostab), the
+//    shock-capturing weights (eqs. dissrateorig to alphaq), the volume and
+//    interface terms of the DG residual in float32, and optionally the
+//    Runge-Kutta stage update with the exact (diagonal, Gauss-collocated)
+//    element mass.
 //
 // The sensor works in the monomials xi^A of the cell's reference coordinates
 // about its centre: the cell polynomial (its nodal values less the first one,
@@ -18,8 +20,9 @@
 // (Taylor polynomials about the corners, re-expanded about the centre) are
 // coefficient vectors, and every element semi-norm of eq. snorm is the
 // quadratic form of one Gram matrix of the monomials (exact integrals, built
-// on the host for the mesh's box).  The team exchanges nodal values,
-// coefficients and quadrature terms through LDS and reduces with
+// on the host for the mesh's box; nonzero only between monomials whose
+// exponents have equal parity in every direction).  The cell pass's team
+// exchanges nodal values and quadrature terms through LDS and reduces with
 // cross-lane shuffles; idle lanes of a Q_2 team carry zeros.
 #include "cvw_device.h"
 #include "cvw_cells3d.h"
@@ -37,16 +40,6 @@ struct HexShape {
 // mirrored lane of the other quad, of the other half row) over 8 or 16 lanes,
 // then the other row of a 32-lane team; every lane of the team receives
 // bitwise the same value.
-template <int TEAM>
-__device__ __forceinline__ double team_sum(double x) {
-#pragma clang fp contract(off)
-  x = x + dppd<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
-  x = x + dppd<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
-  x = x + dppd<0x141>(x);
-  if constexpr (TEAM >= 16) x = x + dppd<0x140>(x);
-  if constexpr (TEAM >= 32) x = x + __shfl_xor(x, 16);
-  return x;
-}
 template <int TEAM>
 __device__ __forceinline__ float team_sumf(float x) {
 #pragma clang fp contract(off)
@@ -185,197 +178,180 @@ __device__ __forceinline__ float hex_atil2(const HexTables* __restrict__ tab, co
   return a2;
 }
 
+// The multi-indices 1 <= |k| <= P in the order of the Hermite data (by |k|,
+// then decreasing first, then decreasing second component) and the index of
+// the monomial xi^k among the cell's monomials.
+template <int P>
+struct HexKSet {
+  static constexpr int N1 = P + 1, NK = (P + 1) * (P + 2) * (P + 3) / 6 - 1;
+  int x[NK], y[NK], z[NK], mono[NK];
+  constexpr HexKSet() : x{}, y{}, z{}, mono{} {
+    int t = 0;
+    for (int n = 1; n <= P; ++n)
+      for (int a = n; a >= 0; --a)
+        for (int b = n - a; b >= 0; --b) {
+          x[t] = a;
+          y[t] = b;
+          z[t] = n - a - b;
+          mono[t] = a + N1 * (b + N1 * (n - a - b));
+          ++t;
+        }
+  }
+};
+template <int P>
+inline constexpr HexKSet<P> hex_kset{};
+
+// monomials A, B (index a + n1 b + n1^2 c) with exponents of equal parity in
+// every direction: the only pairs where the semi-norm Gram matrix can be
+// nonzero (the reference cell is symmetric about its centre)
+template <int N1>
+constexpr bool hex_pair(int A, int B) {
+  return ((A % N1 + B % N1) % 2 == 0) && (((A / N1) % N1 + (B / N1) % N1) % 2 == 0) &&
+         ((A / (N1 * N1) + B / (N1 * N1)) % 2 == 0);
+}
+
+// c^T G c for the coefficients c of monomials MONO[0..N) (row and column of
+// the constant vanish); G is read with compile-time offsets, i.e. through the
+// scalar unit
+template <int N1, int N, typename IDX>
+__device__ __forceinline__ double hex_quad(const double (&c)[N], IDX mono, const HexTables* __restrict__ tab) {
+  double q = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int A = mono(i);
+    if (A == 0) continue;
+    double t = 0.0;
+#pragma unroll
+    for (int j = i + 1; j < N; ++j) {
+      const int B = mono(j);
+      if (B == 0 || !hex_pair<N1>(A, B)) continue;
+      t = fma(tab->G[A][B], c[j], t);
+    }
+    q = fma(c[i], fma(2.0, t, tab->G[A][A] * c[i]), q);
+  }
+  return q;
+}
+
+// Jiang-Shu weight of a candidate with semi-norm b and linear weight lin
+__device__ __forceinline__ float hex_weight(const MethodScalars& ms, float lin, float b) {
+  if (ms.fast_exp) {
+    const float tt = ms.eps_c + b;
+    return lin / (tt * tt);
+  }
+  return lin * powf(ms.eps_c + powf(b, ms.q_beta), -ms.r);
+}
+
+// Sensor pass: one thread per cell.  The block's nodal values are staged
+// through LDS (coalesced reads); each thread then works in registers: the
+// monomial coefficients of its cell (three one-dimensional passes), their
+// semi-norm, the eight vertex candidates re-expanded about the centre one at
+// a time (their semi-norms, weights and weighted sum), the difference
+// u_h - u_h^{e,*} and its semi-norm, gamma_e (eq. finalweno, eq. gamma).
+// Coefficients, re-expansions and quadratic forms in float64; the weights,
+// square roots and the ratio in float32 (relative rounding 1e-7 in gamma_e).
 template <int P>
 __global__ __launch_bounds__(256) void hex_sensor_kernel(const float* __restrict__ u, float* __restrict__ gamma,
                                                          const float* __restrict__ cand,
                                                          const int32_t* __restrict__ cell_vtx,
-                                                         const HexTables* __restrict__ tab, int64_t E, int64_t nblk,
+                                                         const HexTables* __restrict__ tab, int64_t E,
                                                          MethodScalars ms) {
   using S = HexShape<P>;
-  constexpr int N1 = S::N1, NL = S::NL, NK = S::NK, TEAM = S::TEAM, CPB = S::CPB;
-  __shared__ double sgv[NL][8], ssv[NK][NK];
-  __shared__ int8_t sgb[NL][8], sgn[NL], ssb[NK][NK], ssn[NK], srk[NK][NK], srn[NK];
-  __shared__ double sR[8][NK][NK];
-  __shared__ float su[CPB][NL];
-  __shared__ double sa[CPB][NL], sb[CPB][NL];
-  __shared__ double ss[CPB][8][NK], sq[CPB][8][NK];
-  __shared__ double som[CPB][9];
-  __shared__ float scand[CPB][8 * NK];
-  for (int i = threadIdx.x; i < NL * 8; i += blockDim.x) {
-    sgv[i / 8][i % 8] = tab->gv[i / 8][i % 8];
-    sgb[i / 8][i % 8] = tab->gb[i / 8][i % 8];
-  }
-  for (int i = threadIdx.x; i < NK * NK; i += blockDim.x) {
-    ssv[i / NK][i % NK] = tab->sv[i / NK][i % NK];
-    ssb[i / NK][i % NK] = tab->sb[i / NK][i % NK];
-    srk[i / NK][i % NK] = tab->rk[i / NK][i % NK];
-  }
-  if (threadIdx.x < NL) sgn[threadIdx.x] = tab->gn[threadIdx.x];
-  if (threadIdx.x < NK) {
-    ssn[threadIdx.x] = tab->sn[threadIdx.x];
-    srn[threadIdx.x] = tab->rn[threadIdx.x];
-  }
-  for (int i = threadIdx.x; i < 8 * NK * NK; i += blockDim.x) {
-    const int l = i / (NK * NK), r = i % (NK * NK);
-    sR[l][r / NK][r % NK] = tab->R[l][r / NK][r % NK];
-  }
+  constexpr int N1 = S::N1, NL = S::NL, NK = S::NK;
+  constexpr HexKSet<P> ks = hex_kset<P>;
+  __shared__ float su[256 * NL];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * 256;
+  const int64_t ncell = E - base < 256 ? E - base : 256;
+  for (int64_t i = threadIdx.x; i < ncell * NL; i += 256) su[i] = u[base * NL + i];
   __syncthreads();
-  const int slot = threadIdx.x / TEAM, t = threadIdx.x % TEAM;
-  const bool lane_on = t < NL;
-  const int tn = lane_on ? t : 0;
-  const int ta = tn % N1, tb = (tn / N1) % N1, tc = tn / (N1 * N1);
-  // software pipeline: the next block's nodal values and vertex ids are
-  // requested at the top of an iteration, its candidates half-way through,
-  // and all of it is consumed at the top of the next iteration.  The loads are
-  // unconditional (indices clamped into the mesh) so that no wait is placed
-  // at the load; out-of-range cells get zeros when stored.
-  constexpr int NCL = (8 * NK + TEAM - 1) / TEAM;
-  float pu = 0.0f, pc[NCL];
-  int32_t pv[NCL];
-  auto fetch_a = [&](int64_t b) {
-    const int64_t ec = b * CPB + slot < E ? b * CPB + slot : E - 1;
-    pu = u[ec * NL + tn];
-#pragma unroll
-    for (int r = 0; r < NCL; ++r) {
-      const int i = t + r * TEAM < 8 * NK ? t + r * TEAM : 8 * NK - 1;
-      pv[r] = cell_vtx[ec * 8 + i / NK];
-    }
-  };
-  auto fetch_b = [&]() {
-#pragma unroll
-    for (int r = 0; r < NCL; ++r) {
-      const int i = t + r * TEAM < 8 * NK ? t + r * TEAM : 8 * NK - 1;
-      pc[r] = cand[static_cast<int64_t>(pv[r]) * NK + i % NK];
-    }
-  };
-  fetch_a(blockIdx.x);
-  fetch_b();
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t e = blk * CPB + slot;
-    const bool cell_on = e < E;
-    const bool on = lane_on && cell_on;
-    if (lane_on) su[slot][t] = on ? pu : 0.0f;
-#pragma unroll
-    for (int r = 0; r < NCL; ++r)
-      if (t + r * TEAM < 8 * NK) scand[slot][t + r * TEAM] = cell_on ? pc[r] : 0.0f;
-    wave_sync();
-    const int64_t nxt = blk + gridDim.x < nblk ? blk + gridDim.x : blk;
-    fetch_a(nxt);
-    // ---- sensor gamma_e (float64)
-    float gam = 1.0f;
-    {
-      const double u00 = static_cast<double>(su[slot][0]);
-      if (lane_on) {                     // monomial coefficients of u - u_0: x, then y, then z
-        double c = 0.0;
-#pragma unroll
-        for (int j = 0; j < N1; ++j)
-          c = fma(tab->T1[ta][j], static_cast<double>(su[slot][j + N1 * (tb + N1 * tc)]) - u00, c);
-        sa[slot][t] = c;
-      }
-      wave_sync();
-      if (lane_on) {
-        double c = 0.0;
-#pragma unroll
-        for (int j = 0; j < N1; ++j) c = fma(tab->T1[tb][j], sa[slot][ta + N1 * (j + N1 * tc)], c);
-        sb[slot][t] = c;
-      }
-      wave_sync();
-      double cA = 0.0;
-      if (lane_on) {
-#pragma unroll
-        for (int j = 0; j < N1; ++j) cA = fma(tab->T1[tc][j], sb[slot][ta + N1 * (tb + N1 * j)], cA);
-        sa[slot][t] = cA;
-      }
-      // the vertex candidates about the centre: lane pairs (vertex l, multi-index a)
-      for (int i = t; i < 8 * NK; i += TEAM) {
-        const int l = i / NK, a = i % NK;
-        double acc = 0.0;
-        for (int r = 0; r < srn[a]; ++r) {
-          const int k = srk[a][r];
-          acc = fma(sR[l][a][k], static_cast<double>(scand[slot][l * NK + k]), acc);
-        }
-        ss[slot][l][a] = acc;
-      }
-      wave_sync();
-      fetch_b();
-      // ||u_h||_e^2 = c^T G c
-      double g = 0.0;
-      if (lane_on) {
-        for (int r = 0; r < sgn[t]; ++r) g = fma(sgv[t][r], sa[slot][sgb[t][r]], g);
-      }
-      const double n02 = team_sum<TEAM>(cA * g);
-      for (int i = t; i < 8 * NK; i += TEAM) {
-        const int l = i / NK, a = i % NK;
-        double q = 0.0;
-        for (int r = 0; r < ssn[a]; ++r) q = fma(ssv[a][r], ss[slot][l][ssb[a][r]], q);
-        sq[slot][l][a] = ss[slot][l][a] * q;
-      }
-      wave_sync();
-      // weights of the cell candidate (l = 0) and the eight vertex candidates:
-      // lane t takes l = t and l = t + TEAM (a team of 8 lanes has nine
-      // weights).  The semi-norms are float64 sums; their square roots and the
-      // weights are taken in float32 (relative rounding 1e-7 in gamma_e).
-      const float n0 = fsqrt(static_cast<float>(fmax(n02, 0.0)));
-      float wv[2] = {0.0f, 0.0f}, wpart = 0.0f;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int l = t + j * TEAM;
-        if (l > 8) continue;
-        float b = n0;
-        if (l >= 1) {
-          double b2 = 0.0;
-#pragma unroll
-          for (int a = 0; a < NK; ++a) b2 += sq[slot][l - 1][a];
-          b = fsqrt(static_cast<float>(fmax(b2, 0.0)));
-        }
-        const float lin = l == 0 ? 1.0f - 8.0f * ms.lin_w : ms.lin_w;
-        if (ms.fast_exp) {
-          const float tt = ms.eps_c + b;
-          wv[j] = lin / (tt * tt);
-        } else {
-          wv[j] = lin * powf(ms.eps_c + powf(b, ms.q_beta), -ms.r);
-        }
-        wpart += wv[j];
-      }
-      const float wsum = team_sumf<TEAM>(wpart);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int l = t + j * TEAM;
-        if (l <= 8) som[slot][l] = static_cast<double>(wv[j] / wsum);
-      }
-      wave_sync();
-      // diff = sum_{l >= 1} omega_l (u_h - s_l)
-      double Dv = 0.0;
-      if (lane_on) {
-        double osum = 0.0;
-#pragma unroll
-        for (int l = 1; l <= 8; ++l) osum += som[slot][l];
-        Dv = osum * cA;
-        const int a = tab->kmono[t];
-        if (a >= 0) {
-#pragma unroll
-          for (int l = 0; l < 8; ++l) Dv = fma(-som[slot][l + 1], ss[slot][l][a], Dv);
-        }
-        sb[slot][t] = Dv;
-      }
-      wave_sync();
-      double gd = 0.0;
-      if (lane_on) {
-        for (int r = 0; r < sgn[t]; ++r) gd = fma(sgv[t][r], sb[slot][sgb[t][r]], gd);
-      }
-      const double d2 = team_sum<TEAM>(Dv * gd);
-      if (n02 > 0.0) {
-        float ratio = fminf(1.0f, fsqrt(static_cast<float>(fmax(d2, 0.0))) / n0);
-        if (!ms.fast_exp) ratio = powf(ratio, ms.q_sensor);
-        gam = 1.0f - ratio;
-      } else {
-        gam = 1.0f;
-      }
-    }
+  if (threadIdx.x >= ncell) return;
+  const int64_t e = base + threadIdx.x;
+  const int4 va = reinterpret_cast<const int4*>(cell_vtx + e * 8)[0];
+  const int4 vb = reinterpret_cast<const int4*>(cell_vtx + e * 8)[1];
+  const int32_t vid[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
 
-    if (on && t == 0) gamma[e] = gam;
-    wave_sync();
+  // monomial coefficients of u - u_0 (node 0's value: constants give exact zeros)
+  double c[NL];
+  {
+    const float* ue = su + threadIdx.x * NL;     // stride NL (odd for p = 2): no bank conflicts
+    const double u00 = static_cast<double>(ue[0]);
+    c[0] = 0.0;
+#pragma unroll
+    for (int j = 1; j < NL; ++j) c[j] = static_cast<double>(ue[j]) - u00;
   }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {                  // x, then y, then z
+    const int st = d == 0 ? 1 : (d == 1 ? N1 : N1 * N1);
+#pragma unroll
+    for (int r = 0; r < NL / N1; ++r) {
+      const int b0 = d == 0 ? r * N1 : (d == 1 ? (r % N1) + N1 * N1 * (r / N1) : r);
+      double in[N1];
+#pragma unroll
+      for (int j = 0; j < N1; ++j) in[j] = c[b0 + st * j];
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) v = fma(tab->T1[a][j], in[j], v);
+        c[b0 + st * a] = v;
+      }
+    }
+  }
+  const double n02 = hex_quad<N1>(c, [](int i) { return i; }, tab);
+
+  // the eight vertex candidates, re-expanded about the centre
+  double acc[NK];
+#pragma unroll
+  for (int a = 0; a < NK; ++a) acc[a] = 0.0;
+  float wv = 0.0f;
+  double wvd = 0.0;
+  // one vertex per iteration (a rolled loop: one copy of the quadratic form
+  // and of the weight); the next vertex's candidate is requested before the
+  // current one is used
+  float cn[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) cn[k] = cand[static_cast<int64_t>(vid[0]) * NK + k];
+#pragma unroll 1
+  for (int l = 0; l < 8; ++l) {
+    float cl[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) cl[k] = cn[k];
+    const int32_t vn = vid[l < 7 ? l + 1 : 7];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) cn[k] = cand[static_cast<int64_t>(vn) * NK + k];
+    double sl[NK];
+#pragma unroll
+    for (int a = 0; a < NK; ++a) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < NK; ++k)
+        if (ks.x[k] >= ks.x[a] && ks.y[k] >= ks.y[a] && ks.z[k] >= ks.z[a])
+          v = fma(tab->R[l][a][k], static_cast<double>(cl[k]), v);
+      sl[a] = v;
+    }
+    const double b2 = hex_quad<N1>(sl, [](int i) { return hex_kset<P>.mono[i]; }, tab);
+    const float w = hex_weight(ms, ms.lin_w, fsqrt(static_cast<float>(fmax(b2, 0.0))));
+    wv += w;
+    wvd += static_cast<double>(w);
+#pragma unroll
+    for (int a = 0; a < NK; ++a) acc[a] = fma(static_cast<double>(w), sl[a], acc[a]);
+  }
+  const float n0 = fsqrt(static_cast<float>(fmax(n02, 0.0)));
+  const float wsum = hex_weight(ms, 1.0f - 8.0f * ms.lin_w, n0) + wv;
+  // u_h - u_h^{e,*} = sum_{l >= 1} omega_l (u_h - s_l), omega_l = w_l / sum w
+  const double iw = 1.0 / static_cast<double>(wsum);
+  const double osum = wvd * iw;
+#pragma unroll
+  for (int A = 0; A < NL; ++A) c[A] *= osum;
+#pragma unroll
+  for (int a = 0; a < NK; ++a) c[ks.mono[a]] = fma(-iw, acc[a], c[ks.mono[a]]);
+  const double d2 = hex_quad<N1>(c, [](int i) { return i; }, tab);
+  float gam = 1.0f;
+  if (n02 > 0.0) {
+    float ratio = fminf(1.0f, fsqrt(static_cast<float>(fmax(d2, 0.0))) / n0);
+    if (!ms.fast_exp) ratio = powf(ratio, ms.q_sensor);
+    gam = 1.0f - ratio;
+  }
+  gamma[e] = gam;
 }
 
 template <int P, int FLUX>
@@ -549,8 +525,8 @@ static void launch_hex_eval(const cvw_mesh* m, const MethodScalars& ms, int mode
   // the sensor pass writes gamma_e into the caller's array when there is one, else into the scratch
   float* g = gamma ? gamma : gbuf;
   if (ms.sensor_kind != CVW_SENSOR_FIXED)
-    hipLaunchKernelGGL((hex_sensor_kernel<P>), dim3(grid), dim3(256), 0, s, u, g, cand, m->d_cell_vtx, m->d_hext, m->E,
-                       nblk, ms);
+    hipLaunchKernelGGL((hex_sensor_kernel<P>), dim3(hex_blocks(m->E, 256)), dim3(256), 0, s, u, g, cand, m->d_cell_vtx,
+                       m->d_hext, m->E, ms);
   // gamma_e is already in the caller's array when the sensor pass wrote it there
   float* gout = (ms.sensor_kind != CVW_SENSOR_FIXED && gamma) ? nullptr : gamma;
   hipLaunchKernelGGL((hex_eval_kernel<P, FLUX>), dim3(grid), dim3(256), 0, s, u, u0, out, gout, alpha, g, m->d_nbr,

@@ -616,7 +616,7 @@ static void rule_ld(int n, bool lobatto, std::vector<ld>& x, std::vector<ld>& w)
 // eq. snorm with h_e^{2|k|-d}, d = 3), and the re-expansion of a vertex
 // candidate (Taylor data about the vertex, eq. taylorcand) about the centre.
 // ---------------------------------------------------------------------------
-static void fill_hex_tables(HexTables& T, int p, double hx, double hy, double hz) {
+static bool fill_hex_tables(HexTables& T, int p, double hx, double hy, double hz) {
   T = HexTables{};
   const int n1 = p + 1;
   T.p = p; T.n1 = n1; T.nl = n1 * n1 * n1;
@@ -731,24 +731,16 @@ static void fill_hex_tables(HexTables& T, int p, double hx, double hy, double hz
         T.R[l][a][k] = static_cast<double>(v);
       }
     }
-  // sparse lists (exact zeros by parity and by k >= a; the dense tables hold the same values)
-  for (int A = 0; A < T.nl; ++A) {
-    int n = 0;
-    for (int B = 0; B < T.nl; ++B)
-      if (T.G[A][B] != 0.0) { T.gb[A][n] = static_cast<int8_t>(B); T.gv[A][n] = T.G[A][B]; ++n; }
-    T.gn[A] = static_cast<int8_t>(n);
-  }
-  for (int a = 0; a < T.nk; ++a) {
-    int n = 0, r = 0;
-    const int Aa = mono(ks[a][0], ks[a][1], ks[a][2]);
-    for (int b = 0; b < T.nk; ++b) {
-      const double g = T.G[Aa][mono(ks[b][0], ks[b][1], ks[b][2])];
-      if (g != 0.0) { T.sb[a][n] = static_cast<int8_t>(b); T.sv[a][n] = g; ++n; }
-      if (ks[b][0] >= ks[a][0] && ks[b][1] >= ks[a][1] && ks[b][2] >= ks[a][2]) T.rk[a][r++] = static_cast<int8_t>(b);
+  // the sensor pass visits only the pairs of monomials with exponents of
+  // equal parity in every direction: every other entry of G is an exact zero
+  bool fits = true;
+  for (int A = 0; A < T.nl; ++A)
+    for (int B = 0; B < T.nl; ++B) {
+      const bool pair = (A % n1 + B % n1) % 2 == 0 && ((A / n1) % n1 + (B / n1) % n1) % 2 == 0 &&
+                        (A / (n1 * n1) + B / (n1 * n1)) % 2 == 0;
+      fits = fits && (pair || T.G[A][B] == 0.0);
     }
-    T.sn[a] = static_cast<int8_t>(n);
-    T.rn[a] = static_cast<int8_t>(r);
-  }
+  return fits;
 }
 
 // ---------------------------------------------------------------------------
@@ -1562,7 +1554,7 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
   }
   if (d->cell == CVW_HEX && m->uniform && p <= HEX_MAXP) {
     std::vector<HexTables> ht(1);
-    fill_hex_tables(ht[0], p, m->hx, m->hy, m->hz);
+    if (!fill_hex_tables(ht[0], p, m->hx, m->hy, m->hz)) { free_mesh(m); return CVW_EUNSUPPORTED; }
     if ((st = upload(&m->d_hext, ht)) != CVW_OK) { free_mesh(m); return st; }
   }
   if (d->cell == CVW_TET) {
