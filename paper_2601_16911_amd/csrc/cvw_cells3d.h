@@ -47,6 +47,7 @@ struct TetTables {
   double B[TET_NQ][TET_NLOC];            // phi_j at the volume points
   double G[3][TET_NQ][TET_NLOC];         // d phi_j / d xi_b at the volume points
   double H2[6][TET_NLOC];                // second reference derivatives (xx, xy, xz, yy, yz, zz; constant for p <= 2)
+  double Gc[3][TET_NLOC];                // d phi_j / d xi_b at the centroid (1/4, 1/4, 1/4)
   double xq[TET_NQ][3], wq[TET_NQ];      // volume points and weights (the weights sum to 1/6)
   float Bs[TET_NQ][TET_NLOC];            // float32 copies for the residual: phi_j, d phi_j / d xi_b, weights
   float Gs[3][TET_NQ][TET_NLOC];

@@ -862,6 +862,11 @@ static void fill_tet_tables(TetTables& T, int p) {
   static const int H[6][3] = {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
   for (int h = 0; h < 6; ++h)
     for (int j = 0; j < n; ++j) T.H2[h][j] = der(j, H[h][0], H[h][1], H[h][2], 0.25, 0.25, 0.25);
+  for (int j = 0; j < n; ++j) {
+    T.Gc[0][j] = der(j, 1, 0, 0, 0.25, 0.25, 0.25);
+    T.Gc[1][j] = der(j, 0, 1, 0, 0.25, 0.25, 0.25);
+    T.Gc[2][j] = der(j, 0, 0, 1, 0.25, 0.25, 0.25);
+  }
   // multi-indices 1 <= |k| <= p and the derivatives at the reference vertices
   static const double RV[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
   std::vector<std::array<int, 3>> ks(mono.begin() + 1, mono.end());

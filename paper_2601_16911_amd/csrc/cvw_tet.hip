@@ -8,7 +8,8 @@
 //    (eq. taylorcand), Sec. 3.2.  Float64.
 //  * tet_sensor_kernel -- one thread per cell: the cell-vertex WENO sensor
 //    (eq. finalweno, eq. gamma) in float64 with the element semi-norms (eq.
-//    snorm, h_e^{2|k|-3}) taken by the volume rule (exact for these degrees).
+//    snorm, h_e^{2|k|-3}) in closed form from the cell's volume and central
+//    second moments (every polynomial involved has degree <= 2).
 //  * tet_eval_kernel -- one thread per cell, float32: the viscosity (eq.
 //    lostab), the shock-capturing weights (eqs. dissrateorig to alphaq), the
 //    volume and interface terms of the DG residual and optionally the
@@ -176,6 +177,40 @@ __device__ __forceinline__ float tet_fn(const MethodScalars& ms, float u, const 
   else return vn * u;
 }
 
+// Element semi-norm (eq. snorm, weights h_e^{2|k|-3}) of a polynomial of
+// degree <= 2 on an affine cell, in closed form: its gradient is affine,
+// g + H (x - x_c) with g the gradient at the centroid x_c and H the constant
+// Hessian (xx, xy, xz, yy, yz, zz), so that
+//   int_K |grad p|^2 = vol |g|^2 + tr(M H H),  M = int_K (x - x_c)(x - x_c)^T,
+//   int_K |D^k p|^2 = vol H_k^2 for |k| = 2.
+template <int P>
+__device__ __forceinline__ double tet_snorm(const double (&g)[3], const double (&H)[6], const double (&M)[6], double vol,
+                                            double hw1, double hw2) {
+  double s1 = vol * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  if constexpr (P >= 2) {
+    const double Hf[3][3] = {{H[0], H[1], H[2]}, {H[1], H[3], H[4]}, {H[2], H[4], H[5]}};
+    const double Mf[3][3] = {{M[0], M[1], M[2]}, {M[1], M[3], M[4]}, {M[2], M[4], M[5]}};
+    // tr(M H H) = sum_{a,c} (M H)_{ac} H_{ca}
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double mh = Mf[a][0] * Hf[0][c] + Mf[a][1] * Hf[1][c] + Mf[a][2] * Hf[2][c];
+        s1 = fma(mh, Hf[c][a], s1);
+      }
+    double s2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) s2 = fma(H[t], H[t], s2);
+    return fma(hw1, s1, hw2 * vol * s2);
+  } else {
+    return hw1 * s1;
+  }
+}
+
+// Sensor pass: one thread per cell, float64 (the weights, square roots and
+// the ratio of gamma_e in float32).  u_h, the four vertex candidates (Taylor
+// polynomials about the vertices, eq. taylorcand) and u_h - u_h^{e,*} are
+// polynomials of degree <= p, each semi-norm the closed form above.
 template <int P>
 __global__ __launch_bounds__(TET_THREADS) void tet_sensor_kernel(const float* __restrict__ u, float* __restrict__ gamma,
                                                                  const float* __restrict__ cand,
@@ -184,161 +219,129 @@ __global__ __launch_bounds__(TET_THREADS) void tet_sensor_kernel(const float* __
                                                                  const TetTables* __restrict__ tab, int64_t E,
                                                                  MethodScalars ms) {
   using S = TetShape<P>;
-  constexpr int NLOC = S::NLOC, NK = S::NK, NQ = S::NQ;
-  __shared__ double sc[TET_THREADS][4 * NK + 1];    // the four vertex candidates of the thread's cell
-  const int tid = threadIdx.x;
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * TET_THREADS + tid;
+  constexpr int NLOC = S::NLOC, NK = S::NK;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * TET_THREADS + threadIdx.x;
   if (e >= E) return;
+  const int4 vid = *reinterpret_cast<const int4*>(cell_vtx + e * 4);
   const TetGeo G = load_tetgeo(geot, e);
   float uv[NLOC];
 #pragma unroll
   for (int j = 0; j < NLOC; ++j) uv[j] = u[e * NLOC + j];
   const double vol = G.det / 6.0;
   const double hw1 = 1.0 / G.h, hw2 = G.h;          // h_e^{2|k|-3}: |k| = 1, 2
-  // ---- sensor gamma_e (float64)
-  float gam = 1.0f;
+  // centroid offset from vertex 0 and the central second moments
+  // M = vol / 20 sum_i y_i y_i^T (y_i the vertices about the centroid)
+  double cc[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) cc[a] = 0.25 * (G.J[a][0] + G.J[a][1] + G.J[a][2]);
+  double M[6];
   {
+    const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      const float* cv = cand + static_cast<int64_t>(cell_vtx[e * 4 + l]) * NK;
-#pragma unroll
-      for (int k = 0; k < NK; ++k) sc[tid][l * NK + k] = static_cast<double>(cv[k]);
-    }
-    double du[NLOC];
-    const double u00 = static_cast<double>(uv[0]);
-#pragma unroll
-    for (int j = 0; j < NLOC; ++j) du[j] = static_cast<double>(uv[j]) - u00;
-    // constant second derivatives (P = 2) of u_h and the candidates
-    double Hu[6] = {0, 0, 0, 0, 0, 0};
-    if constexpr (P >= 2) {
-      double R[NK];
-#pragma unroll
-      for (int k = 0; k < NK; ++k) R[k] = 0.0;
-#pragma unroll
-      for (int t = 0; t < 6; ++t)
-#pragma unroll
-        for (int j = 1; j < NLOC; ++j) R[3 + t] = fma(tab->H2[t][j], du[j], R[3 + t]);
-      double D[NK];
-      tet_phys<P>(G.A, R, D);
-#pragma unroll
-      for (int t = 0; t < 6; ++t) Hu[t] = D[3 + t];
-    }
-    // vertex positions
-    double xv[4][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      xv[0][a] = G.x0[a];
-#pragma unroll
-      for (int l = 1; l < 4; ++l) xv[l][a] = G.x0[a] + G.J[a][l - 1];
-    }
-    // pass 1: ||u_h||_e^2 and the candidates' semi-norms
-    double n02 = 0.0, b2[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int q = 0; q < NQ; ++q) {
-      const double W = tab->wq[q] * G.det;
-      double gref[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int j = 1; j < NLOC; ++j) {
-        gref[0] = fma(tab->G[0][q][j], du[j], gref[0]);
-        gref[1] = fma(tab->G[1][q][j], du[j], gref[1]);
-        gref[2] = fma(tab->G[2][q][j], du[j], gref[2]);
-      }
-      double xq[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        xq[a] = G.x0[a] + G.J[a][0] * tab->xq[q][0] + G.J[a][1] * tab->xq[q][1] + G.J[a][2] * tab->xq[q][2];
-      double s = 0.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double d = G.A[0][a] * gref[0] + G.A[1][a] * gref[1] + G.A[2][a] * gref[2];
-        s = fma(d, d, s);
-      }
-      n02 = fma(W * hw1, s, n02);
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const double dx[3] = {xq[0] - xv[l][0], xq[1] - xv[l][1], xq[2] - xv[l][2]};
-        double D[3];
-        taylor_first<P>(&sc[tid][l * NK], dx, D);
-        b2[l] = fma(W * hw1, D[0] * D[0] + D[1] * D[1] + D[2] * D[2], b2[l]);
-      }
-    }
-    if constexpr (P >= 2) {
-#pragma unroll
-      for (int t = 0; t < 6; ++t) n02 = fma(vol * hw2 * Hu[t], Hu[t], n02);
-#pragma unroll
-      for (int l = 0; l < 4; ++l)
-#pragma unroll
-        for (int t = 0; t < 6; ++t) b2[l] = fma(vol * hw2 * sc[tid][l * NK + 3 + t], sc[tid][l * NK + 3 + t], b2[l]);
-    }
-    // weights of the cell candidate and the four vertex candidates: the
-    // semi-norms are float64 sums, their square roots and the weights float32
-    const float n0 = fsqrt(static_cast<float>(fmax(n02, 0.0)));
-    double om[5];
-    {
-      float wf[5], wsum = 0.0f;
-#pragma unroll
-      for (int l = 0; l < 5; ++l) {
-        const float b = l == 0 ? n0 : fsqrt(static_cast<float>(fmax(b2[l - 1], 0.0)));
-        const float lin = l == 0 ? 1.0f - 4.0f * ms.lin_w : ms.lin_w;
-        if (ms.fast_exp) {
-          const float t = ms.eps_c + b;
-          wf[l] = lin / (t * t);
-        } else {
-          wf[l] = lin * powf(ms.eps_c + powf(b, ms.q_beta), -ms.r);
-        }
-        wsum += wf[l];
-      }
-#pragma unroll
-      for (int l = 0; l < 5; ++l) om[l] = static_cast<double>(wf[l] / wsum);
-    }
-    double osum = 0.0;
-#pragma unroll
-    for (int l = 1; l < 5; ++l) osum += om[l];
-    // pass 2: the semi-norm of diff = sum_l omega_l (u_h - s_l)
-    double d2 = 0.0;
-    for (int q = 0; q < NQ; ++q) {
-      const double W = tab->wq[q] * G.det;
-      double gref[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int j = 1; j < NLOC; ++j) {
-        gref[0] = fma(tab->G[0][q][j], du[j], gref[0]);
-        gref[1] = fma(tab->G[1][q][j], du[j], gref[1]);
-        gref[2] = fma(tab->G[2][q][j], du[j], gref[2]);
-      }
-      double xq[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        xq[a] = G.x0[a] + G.J[a][0] * tab->xq[q][0] + G.J[a][1] * tab->xq[q][1] + G.J[a][2] * tab->xq[q][2];
-      double Dd[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) Dd[a] = osum * (G.A[0][a] * gref[0] + G.A[1][a] * gref[1] + G.A[2][a] * gref[2]);
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const double dx[3] = {xq[0] - xv[l][0], xq[1] - xv[l][1], xq[2] - xv[l][2]};
-        double D[3];
-        taylor_first<P>(&sc[tid][l * NK], dx, D);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) Dd[a] = fma(-om[l + 1], D[a], Dd[a]);
-      }
-      d2 = fma(W * hw1, Dd[0] * Dd[0] + Dd[1] * Dd[1] + Dd[2] * Dd[2], d2);
-    }
-    if constexpr (P >= 2) {
-#pragma unroll
-      for (int t = 0; t < 6; ++t) {
-        double hd = osum * Hu[t];
-#pragma unroll
-        for (int l = 0; l < 4; ++l) hd = fma(-om[l + 1], sc[tid][l * NK + 3 + t], hd);
-        d2 = fma(vol * hw2 * hd, hd, d2);
-      }
-    }
-    if (n02 > 0.0) {
-      float ratio = fminf(1.0f, fsqrt(static_cast<float>(fmax(d2, 0.0))) / n0);
-      if (!ms.fast_exp) ratio = powf(ratio, ms.q_sensor);
-      gam = 1.0f - ratio;
-    } else {
-      gam = 1.0f;
+    for (int t = 0; t < 6; ++t) {
+      const int a = ia[t], b = ib[t];
+      const double s = G.J[a][0] * G.J[b][0] + G.J[a][1] * G.J[b][1] + G.J[a][2] * G.J[b][2] - 4.0 * cc[a] * cc[b];
+      M[t] = vol / 20.0 * s;
     }
   }
-
+  // u_h: the gradient at the centroid and the Hessian, from the nodal values
+  // less the first one
+  double du[NLOC];
+  const double u00 = static_cast<double>(uv[0]);
+#pragma unroll
+  for (int j = 0; j < NLOC; ++j) du[j] = static_cast<double>(uv[j]) - u00;
+  double R[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) R[k] = 0.0;
+#pragma unroll
+  for (int j = 1; j < NLOC; ++j) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) R[b] = fma(tab->Gc[b][j], du[j], R[b]);
+    if constexpr (P >= 2) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t) R[3 + t] = fma(tab->H2[t][j], du[j], R[3 + t]);
+    }
+  }
+  double D[NK];
+  tet_phys<P>(G.A, R, D);
+  double gu[3] = {D[0], D[1], D[2]}, Hu[6] = {0, 0, 0, 0, 0, 0};
+  if constexpr (P >= 2) {
+#pragma unroll
+    for (int t = 0; t < 6; ++t) Hu[t] = D[3 + t];
+  }
+  const double n02 = tet_snorm<P>(gu, Hu, M, vol, hw1, hw2);
+  // the candidates: Taylor data about vertex l; gradient at the centroid
+  // t_grad + H (x_c - x_l)
+  double gl[4][3], Hl[4][6], b2[4];
+  const int32_t vv[4] = {vid.x, vid.y, vid.z, vid.w};
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const float* cv = cand + static_cast<int64_t>(vv[l]) * NK;
+    double t[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) t[k] = static_cast<double>(cv[k]);
+    double dx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dx[a] = l == 0 ? cc[a] : cc[a] - G.J[a][l - 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gl[l][a] = t[a];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) Hl[l][q] = 0.0;
+    if constexpr (P >= 2) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) Hl[l][q] = t[3 + q];
+      gl[l][0] += t[3] * dx[0] + t[4] * dx[1] + t[5] * dx[2];
+      gl[l][1] += t[4] * dx[0] + t[6] * dx[1] + t[7] * dx[2];
+      gl[l][2] += t[5] * dx[0] + t[7] * dx[1] + t[8] * dx[2];
+    }
+    b2[l] = tet_snorm<P>(gl[l], Hl[l], M, vol, hw1, hw2);
+  }
+  // weights of the cell candidate and the four vertex candidates
+  const float n0 = fsqrt(static_cast<float>(fmax(n02, 0.0)));
+  double om[5];
+  {
+    float wf[5], wsum = 0.0f;
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      const float b = l == 0 ? n0 : fsqrt(static_cast<float>(fmax(b2[l - 1], 0.0)));
+      const float lin = l == 0 ? 1.0f - 4.0f * ms.lin_w : ms.lin_w;
+      if (ms.fast_exp) {
+        const float tt = ms.eps_c + b;
+        wf[l] = lin / (tt * tt);
+      } else {
+        wf[l] = lin * powf(ms.eps_c + powf(b, ms.q_beta), -ms.r);
+      }
+      wsum += wf[l];
+    }
+#pragma unroll
+    for (int l = 0; l < 5; ++l) om[l] = static_cast<double>(wf[l] / wsum);
+  }
+  double osum = 0.0;
+#pragma unroll
+  for (int l = 1; l < 5; ++l) osum += om[l];
+  // u_h - u_h^{e,*} = sum_{l >= 1} omega_l (u_h - s_l)
+  double gd[3], Hd[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double v = osum * gu[a];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) v = fma(-om[l + 1], gl[l][a], v);
+    gd[a] = v;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double v = osum * Hu[q];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) v = fma(-om[l + 1], Hl[l][q], v);
+    Hd[q] = v;
+  }
+  const double d2 = tet_snorm<P>(gd, Hd, M, vol, hw1, hw2);
+  float gam = 1.0f;
+  if (n02 > 0.0) {
+    float ratio = fminf(1.0f, fsqrt(static_cast<float>(fmax(d2, 0.0))) / n0);
+    if (!ms.fast_exp) ratio = powf(ratio, ms.q_sensor);
+    gam = 1.0f - ratio;
+  }
   gamma[e] = gam;
 }
 
