@@ -30,7 +30,8 @@ struct HexTables {
   double hb[HEX_NK];                     // vertex beta: h_e^{2|k|}
   double T1[HEX_N1][HEX_N1];             // u(xi) = sum_a (sum_j T1[a][j] u_j) xi^a along one direction
   double G[HEX_NL][HEX_NL];              // sum_k h_e^{2|k|-3} int_K D^k xi^A D^k xi^B dx
-  double HV[8][HEX_NK][HEX_NL];          // D^k u(x_l) from the nodal values less the first one
+  double E1[HEX_N1][2][HEX_N1];          // l_j^{(m)}(-1), l_j^{(m)}(+1): reference derivatives at the ends
+  double hk[HEX_NK];                     // prod_d (2 / h_d)^{k_d}: reference -> physical derivatives
   double R[8][HEX_NK][HEX_NK];           // vertex candidate of vertex l (Taylor data) -> coefficient of xi^a, a in k
 };
 

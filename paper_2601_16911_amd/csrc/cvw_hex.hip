@@ -2,9 +2,10 @@
 //
 //  * hex_vertex_kernel -- one thread per mesh vertex: the Hermite data
 //    D^k u^e(x_i), 1 <= |k| <= p, of each of the eight cells of the vertex
-//    patch (eq. taylorsol) from tabulated corner derivatives of the Lagrange
-//    basis, the pointwise smoothness indicators and Jiang-Shu weights, and the
-//    vertex candidate (eq. taylorcand), Sec. 3.2.  Float64 accumulation.
+//    patch (eq. taylorsol) by one-dimensional passes with the derivatives of
+//    the Lagrange basis at the cell ends, the pointwise smoothness indicators
+//    and Jiang-Shu weights, and the vertex candidate (eq. taylorcand), Sec.
+//    3.2.  Float64.
 //  * hex_sensor_kernel -- one thread per cell: the cell-vertex WENO sensor
 //    (eq. finalweno, eq. gamma).
 //  * hex_eval_kernel -- a team of lanes per cell, one lane per node (8 lanes
@@ -85,39 +86,100 @@ __device__ __forceinline__ float hex_speed(const MethodScalars& ms, float u) {
 // ---------------------------------------------------------------------------
 // vertex pass
 // ---------------------------------------------------------------------------
+// The multi-indices 1 <= |k| <= P in the order of the Hermite data (by |k|,
+// then decreasing first, then decreasing second component) and the index of
+// the monomial xi^k among the cell's monomials.
+template <int P>
+struct HexKSet {
+  static constexpr int N1 = P + 1, NK = (P + 1) * (P + 2) * (P + 3) / 6 - 1;
+  int x[NK], y[NK], z[NK], mono[NK];
+  constexpr HexKSet() : x{}, y{}, z{}, mono{} {
+    int t = 0;
+    for (int n = 1; n <= P; ++n)
+      for (int a = n; a >= 0; --a)
+        for (int b = n - a; b >= 0; --b) {
+          x[t] = a;
+          y[t] = b;
+          z[t] = n - a - b;
+          mono[t] = a + N1 * (b + N1 * (n - a - b));
+          ++t;
+        }
+  }
+};
+template <int P>
+inline constexpr HexKSet<P> hex_kset{};
+
 template <int P>
 __global__ __launch_bounds__(256) void hex_vertex_kernel(const float* __restrict__ u, float* __restrict__ cand,
-                                                         const int32_t* __restrict__ vptr,
                                                          const int32_t* __restrict__ vent,
                                                          const HexTables* __restrict__ tab, int64_t Nv,
                                                          MethodScalars ms) {
   using S = HexShape<P>;
-  constexpr int NL = S::NL, NK = S::NK;
-  __shared__ double sHV[8][NK][NL];
-  for (int i = threadIdx.x; i < 8 * NK * NL; i += blockDim.x) {
-    const int l = i / (NK * NL), r = i % (NK * NL);
-    sHV[l][r / NL][r % NL] = tab->HV[l][r / NL][r % NL];
-  }
-  __syncthreads();
+  constexpr int N1 = S::N1, NL = S::NL, NK = S::NK;
+  constexpr HexKSet<P> ks = hex_kset<P>;
   const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= Nv) return;
+  // the patch in octant order: entry 8 v + l is the cell whose corner l is v
+  const int4 ea = reinterpret_cast<const int4*>(vent + v * 8)[0];
+  const int4 eb = reinterpret_cast<const int4*>(vent + v * 8)[1];
+  const int32_t ent[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
   double acc[NK], wsum = 0.0;
 #pragma unroll
   for (int k = 0; k < NK; ++k) acc[k] = 0.0;
-  for (int32_t i = vptr[v]; i < vptr[v + 1]; ++i) {
-    const int32_t ent = vent[i];
-    const int64_t ce = ent >> 3;
-    const int lv = ent & 7;
-    const float* uc = u + ce * NL;
+  float un[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) un[j] = u[static_cast<int64_t>(ent[0] >> 3) * NL + j];
+  // one corner per iteration (the same corner across the wavefront, so the
+  // end-value tables are read through the scalar unit); the next patch cell's
+  // values are requested before the current one is used
+#pragma unroll 1
+  for (int l = 0; l < 8; ++l) {
+    float uc[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) uc[j] = un[j];
+    const int64_t cn = ent[l < 7 ? l + 1 : 7] >> 3;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) un[j] = u[cn * NL + j];
+    // corner signs of local vertex l: x+ for l = 1, 2, 5, 6; y+ for 2, 3, 6, 7; z+ for 4..7
+    const int sx = (l ^ (l >> 1)) & 1, sy = (l >> 1) & 1, sz = (l >> 2) & 1;
     const double u0 = static_cast<double>(uc[0]);
+    // D^k u at the corner, one direction at a time: X[m][b][c] = sum_a l_a^{(m)}(s_x) u_abc,
+    // Y[mx][my][c] = sum_b l_b^{(my)}(s_y) X[mx][b][c], D = sum_c l_c^{(mz)}(s_z) Y[mx][my][c]
+    double X[N1][N1][N1];
+#pragma unroll
+    for (int b = 0; b < N1; ++b)
+#pragma unroll
+      for (int c = 0; c < N1; ++c) {
+        double r[N1];
+#pragma unroll
+        for (int a = 0; a < N1; ++a) r[a] = static_cast<double>(uc[a + N1 * (b + N1 * c)]) - u0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+          double s = 0.0;
+#pragma unroll
+          for (int a = 0; a < N1; ++a) s = fma(tab->E1[m][sx][a], r[a], s);
+          X[m][b][c] = s;
+        }
+      }
+    double Y[N1][N1][N1];
+#pragma unroll
+    for (int mx = 0; mx < N1; ++mx)
+#pragma unroll
+      for (int my = 0; mx + my < N1; ++my)
+#pragma unroll
+        for (int c = 0; c < N1; ++c) {
+          double s = 0.0;
+#pragma unroll
+          for (int b = 0; b < N1; ++b) s = fma(tab->E1[my][sy][b], X[mx][b][c], s);
+          Y[mx][my][c] = s;
+        }
     double H[NK];
 #pragma unroll
-    for (int k = 0; k < NK; ++k) H[k] = 0.0;
+    for (int k = 0; k < NK; ++k) {
+      double s = 0.0;
 #pragma unroll
-    for (int j = 1; j < NL; ++j) {
-      const double dj = static_cast<double>(uc[j]) - u0;
-#pragma unroll
-      for (int k = 0; k < NK; ++k) H[k] = fma(sHV[lv][k][j], dj, H[k]);
+      for (int c = 0; c < N1; ++c) s = fma(tab->E1[ks.z[k]][sz][c], Y[ks.x[k]][ks.y[k]][c], s);
+      H[k] = s * tab->hk[k];
     }
     double b2 = 0.0;
 #pragma unroll
@@ -177,29 +239,6 @@ __device__ __forceinline__ float hex_atil2(const HexTables* __restrict__ tab, co
   }
   return a2;
 }
-
-// The multi-indices 1 <= |k| <= P in the order of the Hermite data (by |k|,
-// then decreasing first, then decreasing second component) and the index of
-// the monomial xi^k among the cell's monomials.
-template <int P>
-struct HexKSet {
-  static constexpr int N1 = P + 1, NK = (P + 1) * (P + 2) * (P + 3) / 6 - 1;
-  int x[NK], y[NK], z[NK], mono[NK];
-  constexpr HexKSet() : x{}, y{}, z{}, mono{} {
-    int t = 0;
-    for (int n = 1; n <= P; ++n)
-      for (int a = n; a >= 0; --a)
-        for (int b = n - a; b >= 0; --b) {
-          x[t] = a;
-          y[t] = b;
-          z[t] = n - a - b;
-          mono[t] = a + N1 * (b + N1 * (n - a - b));
-          ++t;
-        }
-  }
-};
-template <int P>
-inline constexpr HexKSet<P> hex_kset{};
 
 // monomials A, B (index a + n1 b + n1^2 c) with exponents of equal parity in
 // every direction: the only pairs where the semi-norm Gram matrix can be
@@ -508,8 +547,8 @@ cvw_status hex_candidates(const cvw_mesh* m, const cvw_params* prm, const float*
   const MethodScalars ms = make_scalars(prm);
   const dim3 g(hex_blocks(m->Nv, 256)), b(256);
   switch (m->degree) {
-    case 1: hipLaunchKernelGGL(hex_vertex_kernel<1>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_hext, m->Nv, ms); break;
-    case 2: hipLaunchKernelGGL(hex_vertex_kernel<2>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_hext, m->Nv, ms); break;
+    case 1: hipLaunchKernelGGL(hex_vertex_kernel<1>, g, b, 0, s, u, cand, m->d_vtx_ent, m->d_hext, m->Nv, ms); break;
+    case 2: hipLaunchKernelGGL(hex_vertex_kernel<2>, g, b, 0, s, u, cand, m->d_vtx_ent, m->d_hext, m->Nv, ms); break;
     default: set_error("hexahedra: degree 1 or 2"); return CVW_EUNSUPPORTED;
   }
   return hipGetLastError() == hipSuccess ? CVW_OK : CVW_EDEVICE;

@@ -708,16 +708,19 @@ static bool fill_hex_tables(HexTables& T, int p, double hx, double hy, double hz
   // corners: sigma = (+-1, +-1, +-1) in the local vertex order of the mesh
   static const int SG[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
                                {-1, -1, 1}, {1, -1, 1}, {1, 1, 1}, {-1, 1, 1}};
+  for (int m = 0; m < n1; ++m)
+    for (int j = 0; j < n1; ++j) {
+      T.E1[m][0][j] = static_cast<double>(lder(j, m, -1.0L));
+      T.E1[m][1][j] = static_cast<double>(lder(j, m, 1.0L));
+    }
+  for (int k = 0; k < T.nk; ++k) {
+    ld v = 1.0L;
+    for (int d = 0; d < 3; ++d) v *= std::pow(2.0L / h[d], static_cast<ld>(ks[k][d]));
+    T.hk[k] = static_cast<double>(v);
+  }
   for (int l = 0; l < 8; ++l)
     for (int k = 0; k < T.nk; ++k) {
       const auto& kk = ks[k];
-      for (int j = 0; j < T.nl; ++j) {
-        const int jd[3] = {j % n1, (j / n1) % n1, j / (n1 * n1)};
-        ld v = 1.0L;
-        for (int d = 0; d < 3; ++d)
-          v *= std::pow(2.0L / h[d], static_cast<ld>(kk[d])) * lder(jd[d], kk[d], static_cast<ld>(SG[l][d]));
-        T.HV[l][k][j] = static_cast<double>(v);
-      }
       // (x - x_l)^k / k! = prod_d (h_d/2)^{k_d} sum_{a_d <= k_d} xi^{a_d} (-sigma_d)^{k_d - a_d} / (a_d! (k_d - a_d)!)
       for (int a = 0; a < T.nk; ++a) {
         const auto& aa = ks[a];
@@ -1484,6 +1487,24 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
 
   // ---- upload ----
   cvw_status st;
+  // hexahedra: each vertex's patch in the order of its octants (entry 8 v + l
+  // is the cell whose local vertex l it is) when every vertex has exactly one
+  // cell in each of its eight octants (closed conforming box meshes); the
+  // vertex pass of the GPU path needs that order
+  bool hex_oct = false;
+  if (d->cell == CVW_HEX) {
+    hex_oct = m->nnz == 8 * Nv;
+    std::vector<int32_t> eo(hex_oct ? m->nnz : 0, -1);
+    for (int64_t v = 0; v < Nv && hex_oct; ++v) {
+      if (m->h_vtx_ptr[v + 1] - m->h_vtx_ptr[v] != 8) { hex_oct = false; break; }
+      for (int32_t i = m->h_vtx_ptr[v]; i < m->h_vtx_ptr[v + 1] && hex_oct; ++i) {
+        const int l = m->h_vtx_lv[i];
+        if (eo[8 * v + l] >= 0) hex_oct = false;
+        else eo[8 * v + l] = ent[i];
+      }
+    }
+    if (hex_oct) ent.swap(eo);
+  }
   std::vector<int32_t> ptr32(m->h_vtx_ptr.begin(), m->h_vtx_ptr.end());
   if ((st = upload(&m->d_vtx_ptr, ptr32)) != CVW_OK) { free_mesh(m); return st; }
   if ((st = upload(&m->d_vtx_ent, ent)) != CVW_OK) { free_mesh(m); return st; }
@@ -1557,7 +1578,7 @@ cvw_status cvw_mesh_build(const cvw_mesh_desc* d, cvw_mesh** out) {
     fill_tri_tables(tt[0], p);
     if ((st = upload(&m->d_trit, tt)) != CVW_OK) { free_mesh(m); return st; }
   }
-  if (d->cell == CVW_HEX && m->uniform && p <= HEX_MAXP) {
+  if (d->cell == CVW_HEX && m->uniform && hex_oct && p <= HEX_MAXP) {
     std::vector<HexTables> ht(1);
     if (!fill_hex_tables(ht[0], p, m->hx, m->hy, m->hz)) { free_mesh(m); return CVW_EUNSUPPORTED; }
     if ((st = upload(&m->d_hext, ht)) != CVW_OK) { free_mesh(m); return st; }
@@ -1832,10 +1853,11 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
     return CVW_OK;
   }
   if (m->cell == CVW_HEX) {
-    if (!m->uniform || !m->d_hext) {
-      set_error("DG hexahedra: congruent axis-aligned boxes, degree <= 2"); return CVW_EUNSUPPORTED;
-    }
     if (!m->closed) { set_error("DG hexahedra: meshes without boundary faces (periodic)"); return CVW_EUNSUPPORTED; }
+    if (!m->uniform || !m->d_hext) {
+      set_error("DG hexahedra: congruent axis-aligned boxes with one cell in each octant of every vertex, degree <= 2");
+      return CVW_EUNSUPPORTED;
+    }
     if (prm->dtype != CVW_F32) { set_error("DG hexahedra run in float32"); return CVW_EUNSUPPORTED; }
     if (prm->flux != CVW_ADVECT_CONST && prm->flux != CVW_BURGERS) {
       set_error("DG hexahedra: constant-velocity advection and Burgers"); return CVW_EUNSUPPORTED;
