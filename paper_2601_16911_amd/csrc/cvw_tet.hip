@@ -1,6 +1,6 @@
 // DG on tetrahedra (P_1, P_2 at the equispaced lattice points; affine cells):
 //
-//  * tet_vertex_kernel -- one thread per mesh vertex: the Hermite data
+//  * tet_vertex_kernel -- eight lanes per mesh vertex: the Hermite data
 //    D^k u^e(x_i), 1 <= |k| <= p, of every cell of the vertex patch (eq.
 //    taylorsol) from reference derivatives of the basis at the reference
 //    vertex and the chain rule with the cell's inverse Jacobian, the pointwise
@@ -25,6 +25,17 @@
 namespace cvw {
 
 constexpr int TET_THREADS = 64;
+constexpr int TET_VLANES = 8;      // lanes per vertex in the vertex pass
+
+// sum over the eight lanes of the own half row (quad butterflies, then the
+// mirrored lane of the other quad); every lane receives bitwise the same value
+__device__ __forceinline__ double oct_sumd(double x) {
+#pragma clang fp contract(off)
+  x = x + dppd<(1 | (0 << 2) | (3 << 4) | (2 << 6))>(x);
+  x = x + dppd<(2 | (3 << 2) | (0 << 4) | (1 << 6))>(x);
+  x = x + dppd<0x141>(x);
+  return x;
+}
 
 template <int P>
 struct TetShape {
@@ -121,12 +132,15 @@ __global__ __launch_bounds__(256) void tet_vertex_kernel(const float* __restrict
     sTV[l][r / NLOC][r % NLOC] = tab->TV[l][r / NLOC][r % NLOC];
   }
   __syncthreads();
-  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= Nv) return;
+  // TET_VLANES lanes per vertex, each taking every TET_VLANES-th cell of the patch
+  const int64_t v = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / TET_VLANES;
+  const int sub = threadIdx.x % TET_VLANES;
+  const bool on = v < Nv;
   double acc[NK], wsum = 0.0;
 #pragma unroll
   for (int k = 0; k < NK; ++k) acc[k] = 0.0;
-  for (int32_t i = vptr[v]; i < vptr[v + 1]; ++i) {
+  const int32_t i0 = on ? vptr[v] + sub : 0, i1 = on ? vptr[v + 1] : 0;
+  for (int32_t i = i0; i < i1; i += TET_VLANES) {
     const int32_t ent = vent[i];
     const int64_t ce = ent >> 2;
     const int lv = ent & 3;
@@ -162,6 +176,11 @@ __global__ __launch_bounds__(256) void tet_vertex_kernel(const float* __restrict
     for (int k = 0; k < NK; ++k) acc[k] = fma(w, D[k], acc[k]);
     wsum += w;
   }
+  // sums over the vertex's lanes (all lanes of the wavefront take part)
+#pragma unroll
+  for (int k = 0; k < NK; ++k) acc[k] = oct_sumd(acc[k]);
+  wsum = oct_sumd(wsum);
+  if (!on || sub != 0) return;
   const double iw = 1.0 / wsum;
 #pragma unroll
   for (int k = 0; k < NK; ++k) cand[v * NK + k] = static_cast<float>(acc[k] * iw);
@@ -551,7 +570,7 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
 // ---------------------------------------------------------------------------
 cvw_status tet_candidates(const cvw_mesh* m, const cvw_params* prm, const float* u, float* cand, hipStream_t s) {
   const MethodScalars ms = make_scalars(prm);
-  const dim3 g(static_cast<unsigned>((m->Nv + 255) / 256)), b(256);
+  const dim3 g(static_cast<unsigned>((m->Nv * TET_VLANES + 255) / 256)), b(256);
   switch (m->degree) {
     case 1: hipLaunchKernelGGL(tet_vertex_kernel<1>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geoth, m->d_tett, m->Nv, ms); break;
     case 2: hipLaunchKernelGGL(tet_vertex_kernel<2>, g, b, 0, s, u, cand, m->d_vtx_ptr, m->d_vtx_ent, m->d_geoth, m->d_tett, m->Nv, ms); break;
