@@ -412,6 +412,25 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
   const int tn = lane_on ? t : 0;
   const int ta = tn % N1, tb = (tn / N1) % N1, tc = tn / (N1 * N1);
   const float W = tab->w1[ta] * tab->w1[tb] * tab->w1[tc] * tab->W0;
+  // the lane's rows and columns of the tables, in registers for the whole loop
+  // (the loop's wavefront fences keep the compiler from hoisting these loads)
+  float dr[3][N1], dc[3][N1], lw[3][2];
+#pragma unroll
+  for (int j = 0; j < N1; ++j) {
+    dr[0][j] = tab->D1[ta][j];
+    dr[1][j] = tab->D1[tb][j];
+    dr[2][j] = tab->D1[tc][j];
+    dc[0][j] = tab->D1[j][ta];
+    dc[1][j] = tab->D1[j][tb];
+    dc[2][j] = tab->D1[j][tc];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int ad = d == 0 ? ta : (d == 1 ? tb : tc);
+    const float wt = d == 0 ? tab->w1[tb] * tab->w1[tc] : (d == 1 ? tab->w1[ta] * tab->w1[tc] : tab->w1[ta] * tab->w1[tb]);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) lw[d][s] = tab->Lend[s][ad] * wt * tab->Jf[d];
+  }
   const bool plain = ms.sensor_kind != CVW_SENSOR_FIXED;
   bool nonfinite = false;
   // software pipeline as in the sensor pass: the next block's nodal values,
@@ -455,9 +474,9 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     float gr[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int j = 0; j < N1; ++j) {
-      gr[0] = fmaf(tab->D1[ta][j], su[slot][j + N1 * (tb + N1 * tc)], gr[0]);
-      gr[1] = fmaf(tab->D1[tb][j], su[slot][ta + N1 * (j + N1 * tc)], gr[1]);
-      gr[2] = fmaf(tab->D1[tc][j], su[slot][ta + N1 * (tb + N1 * j)], gr[2]);
+      gr[0] = fmaf(dr[0][j], su[slot][j + N1 * (tb + N1 * tc)], gr[0]);
+      gr[1] = fmaf(dr[1][j], su[slot][ta + N1 * (j + N1 * tc)], gr[1]);
+      gr[2] = fmaf(dr[2][j], su[slot][ta + N1 * (tb + N1 * j)], gr[2]);
     }
     fetch_b();
     const float gref[3] = {gr[0], gr[1], gr[2]};      // reference derivatives
@@ -489,16 +508,14 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     float r = 0.0f;
 #pragma unroll
     for (int q = 0; q < N1; ++q) {
-      r = fmaf(tab->D1[q][ta], sv[slot][0][q + N1 * (tb + N1 * tc)], r);
-      r = fmaf(tab->D1[q][tb], sv[slot][1][ta + N1 * (q + N1 * tc)], r);
-      r = fmaf(tab->D1[q][tc], sv[slot][2][ta + N1 * (tb + N1 * q)], r);
+      r = fmaf(dc[0][q], sv[slot][0][q + N1 * (tb + N1 * tc)], r);
+      r = fmaf(dc[1][q], sv[slot][1][ta + N1 * (q + N1 * tc)], r);
+      r = fmaf(dc[2][q], sv[slot][2][ta + N1 * (tb + N1 * q)], r);
     }
 
     // ---- interface terms: face f = 2 d + s, the neighbour read through its face f ^ 1
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int ad = d == 0 ? ta : (d == 1 ? tb : tc);
-      const float wt = d == 0 ? tab->w1[tb] * tab->w1[tc] : (d == 1 ? tab->w1[ta] * tab->w1[tc] : tab->w1[ta] * tab->w1[tb]);
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         float um = 0.0f, up = 0.0f;
@@ -515,7 +532,7 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
           else lf = fabsf(ms.fp[d]);
         }
         const float fs = 0.5f * sg * (hex_flux<FLUX>(ms, um, d) + hex_flux<FLUX>(ms, up, d)) - 0.5f * lf * (up - um);
-        r = fmaf(tab->Lend[s][ad] * wt * tab->Jf[d], fs, r);
+        r = fmaf(lw[d][s], fs, r);
       }
     }
 
