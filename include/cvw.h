@@ -63,7 +63,9 @@ typedef enum {
 } cvw_status;
 
 /* Hexahedra (CVW_HEX, dim 3): DG Q_p, p <= 2, on congruent axis-aligned
- * boxes of a periodic mesh, scalar fluxes (constant advection, Burgers),
+ * boxes of a periodic mesh with one cell in each of the eight octants of
+ * every vertex (any conforming closed box mesh; the GPU path refuses others
+ * with CVW_EUNSUPPORTED), scalar fluxes (constant advection, Burgers),
  * float32.  The vertex-based candidates of a cube: eight per cell (Sec. 3.2,
  * the remark on stencil sizes).  Local vertices: the face z = z0
  * counter-clockwise from the lowest corner, then the face z = z0 + hz in the
