@@ -11,7 +11,10 @@ boxes; the vertex-based candidates of a tetrahedron, four per cell, Sec. 3.2).
 * invariants: constant states, polynomials of the element degree (gamma_e = 1
   with complete and incomplete patches), conservation with the sensor and the
   shock-capturing weights active, the DG operator exact on polynomial data
-  of the element degree.
+  of the element degree;
+* the closed form of the element semi-norm of a polynomial of degree <= 2
+  (volume and central second moments of the cell) that the GPU sensor pass
+  evaluates, against the oracle's volume-rule value.
 """
 import math
 
@@ -237,3 +240,48 @@ def test_dg_operator_exact_on_polynomials(p):
     ex = -(v @ a + q * (v[0] * xn[..., 2] + v[2] * xn[..., 0]))
     assert inner.sum() == 216
     assert np.abs(dU[inner] - ex[inner]).max() < 1e-11
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_closed_form_seminorm(p):
+    """The element semi-norm (eq. snorm, d = 3) of a polynomial of degree <= 2
+    on an affine cell in closed form, the form the GPU sensor pass evaluates:
+    with g the gradient at the centroid, H the (constant) Hessian and
+    M = |K| / 20 sum_i y_i y_i^T the central second moments (y_i the vertices
+    about the centroid), ||p||^2 = h^-1 (|K| |g|^2 + tr(M H H)) + h |K| sum_{|k|=2} H_k^2.
+    Checked against the oracle's volume-rule value on every cell of a sheared,
+    stretched six-tetrahedra mesh with random Taylor data."""
+    from oracle.method import element_seminorm_sq, taylor_derivatives
+    from oracle.geometry import map_jacobian, map_points
+    m = synth.tet_mesh(2, 2, 2, periodic=(False, False, False))
+    L = np.array([[1.3, 0.4, -0.2], [0.1, 0.8, 0.3], [0.0, -0.25, 1.1]])
+    assert np.linalg.det(L) > 0
+    m.cell_coords[...] = m.cell_coords @ L.T
+    sp = build_space(m, p, 1)
+    ref = sp.ref
+    J, _ = map_jacobian(sp.cell, sp.X, ref.norm_pts)
+    W = ref.norm_w[None, :] * np.abs(np.linalg.det(J))
+    xq = map_points(sp.cell, sp.X, ref.norm_pts)
+    rng = np.random.default_rng(21)
+    coef = rng.normal(size=(sp.E, len(sp.ks)))
+    x0 = sp.X[:, 1]                                   # expansion point: a vertex
+    want = element_seminorm_sq(sp, taylor_derivatives(sp, coef, xq, x0), W)
+    idx = {tuple(k): i for i, k in enumerate(sp.ks)}
+    vol = W.sum(1)
+    yc = sp.X - sp.X.mean(1, keepdims=True)
+    M = vol[:, None, None] / 20.0 * np.einsum("eia,eib->eab", yc, yc)
+    H = np.zeros((sp.E, 3, 3))
+    if p == 2:
+        for a in range(3):
+            for b in range(3):
+                k = [0, 0, 0]
+                k[a] += 1
+                k[b] += 1
+                H[:, a, b] = coef[:, idx[tuple(k)]]
+    g = np.stack([coef[:, idx[(1, 0, 0)]], coef[:, idx[(0, 1, 0)]], coef[:, idx[(0, 0, 1)]]], 1)
+    g = g + np.einsum("eab,eb->ea", H, sp.X.mean(1) - x0)
+    h = sp.h
+    s1 = vol * (g * g).sum(1) + np.einsum("eab,ebc,eca->e", M, H, H)
+    s2 = sum(H[:, a, b] ** 2 for a in range(3) for b in range(a, 3))
+    got = s1 / h + h * vol * s2
+    assert np.allclose(got, want, rtol=1e-12, atol=0.0)
