@@ -23,7 +23,7 @@ the paper's definitions in its order and notation:
   below a threshold, u_h^e is overwritten by u_h^{e,*} built from vertex
   candidates with corrected cell averages (Sec. 3.2), componentwise.
 
-Readings of points the paper leaves open (all listed in the design doc):
+Readings of points the paper leaves open:
 q = 1 for every exponent, lambda_e = max of the wave speed over the volume
 quadrature points, h_e = diam(K_e) of the cell whose polynomial is measured,
 gamma_e = 1 when ||u_h^e||_e = 0, alpha_q = 1 when either sum in eq. (alphaq)
@@ -198,8 +198,15 @@ def flux(prm: Params, U, x):
         return np.stack([np.sin(U), np.cos(U)], axis=-1)
     if prm.flux == EULER:
         g = prm.flux_param[0]
-        if d == 3:
-            raise NotImplementedError("the Euler equations in 3D")
+        if d == 3:                                  # (rho, m_x, m_y, m_z, E)
+            rho, mx, my, mz, En = U
+            vx, vy, vz = mx / rho, my / rho, mz / rho
+            p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy + vz * vz))
+            F = [np.stack([m, mx * v, my * v, mz * v, (En + p) * v]) for m, v in ((mx, vx), (my, vy), (mz, vz))]
+            F[0][1] += p
+            F[1][2] += p
+            F[2][3] += p
+            return np.stack(F, axis=-1)
         if d == 1:                                  # (rho, m, E) on a line
             rho, mx, En = U
             vx = mx / rho
@@ -228,15 +235,19 @@ def wave_speed(prm: Params, U, x):
         return np.ones(U.shape[1:])
     if prm.flux == EULER:
         g = prm.flux_param[0]
+        vz = 0.0
         if d == 1:
             rho, mx, En = U
             vx, vy = mx / rho, 0.0
-        else:
+        elif d == 2:
             rho, mx, my, En = U
             vx, vy = mx / rho, my / rho
-        p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy))
+        else:
+            rho, mx, my, mz, En = U
+            vx, vy, vz = mx / rho, my / rho, mz / rho
+        p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy + vz * vz))
         c = np.sqrt(np.maximum(g * p / rho, 0.0))
-        return np.hypot(vx, vy) + c
+        return np.sqrt(vx * vx + vy * vy + vz * vz) + c
     raise ValueError(prm.flux)
 
 
@@ -249,14 +260,18 @@ def numerical_flux(prm: Params, Um, Up, n, x):
         g = prm.flux_param[0]
 
         def vn_c(U):
+            vz, nz = 0.0, 0.0
             if n.shape[-1] == 1:
                 rho, mx, En = U
                 vx, vy, ny = mx / rho, 0.0, 0.0
-            else:
+            elif n.shape[-1] == 2:
                 rho, mx, my, En = U
                 vx, vy, ny = mx / rho, my / rho, n[..., 1]
-            p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy))
-            return vx * n[..., 0] + vy * ny, np.sqrt(np.maximum(g * p / rho, 0.0))
+            else:
+                rho, mx, my, mz, En = U
+                vx, vy, vz, ny, nz = mx / rho, my / rho, mz / rho, n[..., 1], n[..., 2]
+            p = (g - 1.0) * (En - 0.5 * rho * (vx * vx + vy * vy + vz * vz))
+            return vx * n[..., 0] + vy * ny + vz * nz, np.sqrt(np.maximum(g * p / rho, 0.0))
 
         vm, cm = vn_c(Um)
         vp, cp = vn_c(Up)

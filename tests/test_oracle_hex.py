@@ -10,6 +10,9 @@ candidates of a cube, eight per cell, Sec. 3.2).
   the quadrilateral mesh of its x-y cross-section, exactly (up to rounding):
   the Galerkin and interface terms by the z-weights of the nodes, the
   stabilisation additionally by the ratio of the cell diameters (eq. lostab);
+* the Euler equations: data independent of one axis with no momentum along
+  it reduces to the 2D Euler residual on the cross-section (both in-plane
+  pairs), constant states, conservation;
 * invariants: constant states, polynomials of the element degree (gamma_e = 1
   with complete and incomplete vertex patches), conservation, and the
   consistency of the DG operator at order p on smooth periodic data.
@@ -225,6 +228,90 @@ def test_z_independent_data_reduces_to_2d(flux, fp, p):
             want = (R2g[e2] + scale * stab[e2]) * w1[c] * hz / 2
             assert np.abs(blk - want).max() <= 1e-12 * np.abs(R2).max(), (e, c)
     assert np.abs(stab).max() > 1e-3 * np.abs(R2).max()
+
+
+def _euler_fields(a2):
+    """rho, the two in-plane velocities and p of a smooth state with a density
+    jump, as functions of the two in-plane coordinates (x, w) of axis a2."""
+    L = {1: 0.75, 2: 0.6}[a2]
+    rho = lambda x: 1.0 + 0.3 * np.sin(2 * np.pi * x[..., 0]) + 0.2 * np.cos(2 * np.pi * x[..., a2] / L) \
+        + 0.5 * (x[..., 0] > 0.5)
+    u = lambda x: 0.4 * np.cos(2 * np.pi * x[..., a2] / L)
+    w = lambda x: 0.3 * np.sin(2 * np.pi * x[..., 0])
+    pr = lambda x: 1.0 + 0.2 * np.sin(2 * np.pi * (x[..., 0] + x[..., a2] / L))
+    return rho, u, w, pr
+
+
+@pytest.mark.parametrize("kept", [1, 2])
+@pytest.mark.parametrize("p", [1, 2])
+def test_euler_reduces_to_2d(kept, p):
+    """Euler data that does not depend on one axis, with no momentum along it:
+    the 3D residual's density, energy and in-plane momenta are the 2D Euler
+    residual on the cross-section (kept = 1: the x-y plane, z dropped; kept =
+    2: the x-z plane, y dropped), weighted as for the scalar fluxes, and the
+    dropped momentum's residual vanishes.  Pins where each flux component and
+    the HLL wave speeds sit in 3D."""
+    gam = 1.4
+    nx, ny, nz = 4, 3, 3
+    m3 = synth.hex_mesh(nx, ny, nz, x1=1.0, y1=0.75, z1=0.6)
+    n2 = ny if kept == 1 else nz
+    L2 = 0.75 if kept == 1 else 0.6
+    m2 = synth.quad_mesh(nx, n2, x1=1.0, y1=L2)
+    s3, s2 = build_space(m3, p, 1, n_var=5), build_space(m2, p, 1, n_var=4)
+    rho, u, w, pr = _euler_fields(kept)
+    En = lambda x: pr(x) / (gam - 1.0) + 0.5 * rho(x) * (u(x) ** 2 + w(x) ** 2)
+    zero = lambda x: 0.0 * x[..., 0]
+    m_u = lambda x: rho(x) * u(x)
+    m_w = lambda x: rho(x) * w(x)
+    if kept == 1:
+        U3 = nodal_interpolate(s3, [rho, m_u, m_w, zero, En])
+    else:
+        U3 = nodal_interpolate(s3, [rho, m_u, zero, m_w, En])
+    to2 = lambda f: (lambda x: f(np.stack([x[..., 0], x[..., 1], x[..., 1]], -1)))
+    U2 = nodal_interpolate(s2, [to2(f) for f in (rho, m_u, m_w, En)])
+    pp = dict(flux=synth.EULER, flux_param=(gam, 0, 0, 0), sensor=2, sc_on=0)
+    R3 = residual(s3, U3, Params(**pp, fixed_gamma=0.4)).reshape(5, s3.E, -1)
+    R2g = residual(s2, U2, Params(**pp, fixed_gamma=1.0)).reshape(4, s2.E, -1)
+    R2 = residual(s2, U2, Params(**pp, fixed_gamma=0.4)).reshape(4, s2.E, -1)
+    stab = R2 - R2g
+    n1 = p + 1
+    w1 = np.polynomial.legendre.leggauss(n1)[1]
+    hd = (0.6 / nz) if kept == 1 else (0.75 / ny)      # side of the dropped axis
+    scale = s3.h[0] / s2.h[0]                          # nu_e: the same wave speed, the box's diameter
+    var3 = [0, 1, 2, 4] if kept == 1 else [0, 1, 3, 4]
+    drop = 3 if kept == 1 else 2
+    tol = 1e-12 * np.abs(R2).max()
+    for e in range(s3.E):
+        i, j, k = e % nx, (e // nx) % ny, e // (nx * ny)
+        e2 = i + nx * (j if kept == 1 else k)
+        blk = R3[:, e].reshape(5, n1, n1, n1)            # [v, c, b, a]
+        for t in range(n1):
+            got = blk[:, t] if kept == 1 else blk[:, :, t]   # the dropped axis' node index t
+            want = (R2g[:, e2] + scale * stab[:, e2]).reshape(4, n1, n1) * w1[t] * hd / 2
+            assert np.abs(got[var3] - want).max() <= tol, (e, t)
+            assert np.abs(got[drop]).max() <= tol, (e, t)
+    assert np.abs(stab).max() > 1e-3 * np.abs(R2).max()
+
+
+def test_euler_constant_state_and_conservation():
+    """A constant Euler state has zero residual; with a density jump the sensor
+    and the SC weights are active and the residual sums to zero per variable
+    on a periodic mesh."""
+    gam = 1.4
+    sp = build_space(synth.hex_mesh(3, 3, 3), 2, 1, n_var=5)
+    c = [1.2, 0.3, -0.2, 0.1, 2.5]
+    U = nodal_interpolate(sp, [lambda x, v=v: v + 0.0 * x[..., 0] for v in c])
+    R = residual(sp, U, Params(flux=synth.EULER, flux_param=(gam, 0, 0, 0)))
+    assert np.abs(R).max() < 1e-13
+    rng = np.random.default_rng(4)
+    rho = lambda x: 1.0 + 2.0 * (np.abs(x[..., 1] - 0.45) < 0.2) + 0.3 * np.sin(2 * np.pi * x[..., 0]) * np.cos(2 * np.pi * x[..., 2])
+    U = nodal_interpolate(sp, [rho, lambda x: 0.3 * rho(x), lambda x: -0.2 * rho(x), lambda x: 0.1 * rho(x),
+                               lambda x: 2.0 + 0.5 * np.cos(2 * np.pi * x[..., 0])])
+    U = U + 0.002 * rng.normal(size=U.shape)
+    R, parts = residual(sp, U, Params(flux=synth.EULER, flux_param=(gam, 0, 0, 0)), return_parts=True)
+    assert parts["gamma"].min() < 0.9 and (parts["alpha"] != 1).any()
+    R = R.reshape(5, -1)
+    assert np.all(np.abs(R.sum(1)) < 1e-12 * np.abs(R).sum(1))
 
 
 # ---------------------------------------------------------------------------
