@@ -13,7 +13,8 @@
 //    shock-capturing weights (eqs. dissrateorig to alphaq), the volume and
 //    interface terms of the DG residual in float32, and optionally the
 //    Runge-Kutta stage update with the exact (diagonal, Gauss-collocated)
-//    element mass.
+//    element mass; scalar laws and the Euler equations (HLL at the faces,
+//    the sensor field and the SC weights from the density).
 //
 // The sensor works in the monomials xi^A of the cell's reference coordinates
 // about its centre: the cell polynomial (its nodal values less the first one,
@@ -81,6 +82,83 @@ __device__ __forceinline__ float hex_speed(const MethodScalars& ms, float u) {
   const float vn = fsqrt(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1] + ms.fp[2] * ms.fp[2]);
   if constexpr (FLUX == CVW_BURGERS) return fabsf(u) * vn;
   else return vn;
+}
+
+// Variables per node: one for the scalar laws, (rho, m_x, m_y, m_z, E) for
+// the Euler equations (gas gamma = fp[0])
+template <int FLUX>
+struct HexNV {
+  static constexpr int value = FLUX == CVW_EULER ? 5 : 1;
+};
+
+// f_d(U) along axis d, every variable
+template <int FLUX>
+__device__ __forceinline__ void hex_flux_all(const MethodScalars& ms, const float* u, int d, float* f) {
+  if constexpr (FLUX == CVW_EULER) {
+    const float inv = frcp(u[0]);
+    const float v[3] = {u[1] * inv, u[2] * inv, u[3] * inv};
+    const float p = (ms.fp[0] - 1.0f) * (u[4] - 0.5f * u[0] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+    f[0] = u[1 + d];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[1 + a] = u[1 + a] * v[d] + (a == d ? p : 0.0f);
+    f[4] = (u[4] + p) * v[d];
+  } else {
+    f[0] = hex_flux<FLUX>(ms, u[0], d);
+  }
+}
+
+// local maximum wave speed (Euler: |v| + c)
+template <int FLUX>
+__device__ __forceinline__ float hex_speed_all(const MethodScalars& ms, const float* u) {
+  if constexpr (FLUX == CVW_EULER) {
+    const float inv = frcp(u[0]);
+    const float v2 = (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * inv * inv;
+    const float p = (ms.fp[0] - 1.0f) * (u[4] - 0.5f * u[0] * v2);
+    return fsqrt(v2) + fsqrt(fmaxf(ms.fp[0] * p * inv, 0.0f));
+  } else {
+    return hex_speed<FLUX>(ms, u[0]);
+  }
+}
+
+// interface flux f*(u-, u+; n), n = sg e_d: local Lax-Friedrichs for the
+// scalar laws, HLL with Davis wave-speed estimates for the Euler equations
+template <int FLUX>
+__device__ __forceinline__ void hex_num_flux(const MethodScalars& ms, const float* um, const float* up, int d,
+                                             float sg, float* fs) {
+  if constexpr (FLUX == CVW_EULER) {
+    const float g = ms.fp[0];
+    const float im = frcp(um[0]), ip = frcp(up[0]);
+    const float vdm = um[1 + d] * im, vdp = up[1 + d] * ip;
+    const float pm = (g - 1.0f) * (um[4] - 0.5f * (um[1] * um[1] + um[2] * um[2] + um[3] * um[3]) * im);
+    const float pp = (g - 1.0f) * (up[4] - 0.5f * (up[1] * up[1] + up[2] * up[2] + up[3] * up[3]) * ip);
+    const float vm = sg * vdm, vp = sg * vdp;
+    const float cm = fsqrt(fmaxf(g * pm * im, 0.0f)), cp = fsqrt(fmaxf(g * pp * ip, 0.0f));
+    const float SL = fminf(vm - cm, vp - cp);
+    const float SR = fmaxf(vm + cm, vp + cp);
+    float Fm[5], Fp[5];
+    Fm[0] = um[0] * vm;
+    Fp[0] = up[0] * vp;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Fm[1 + a] = um[1 + a] * vm + (a == d ? sg * pm : 0.0f);
+      Fp[1 + a] = up[1 + a] * vp + (a == d ? sg * pp : 0.0f);
+    }
+    Fm[4] = (um[4] + pm) * vm;
+    Fp[4] = (up[4] + pp) * vp;
+    const float inv = frcp(SR - SL);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const float mid = (SR * Fm[v] - SL * Fp[v] + SL * SR * (up[v] - um[v])) * inv;
+      fs[v] = (SL >= 0.0f) ? Fm[v] : ((SR <= 0.0f) ? Fp[v] : mid);
+    }
+  } else {
+    float lf = ms.lam_g;
+    if (!(lf > 0.0f)) {
+      if constexpr (FLUX == CVW_BURGERS) lf = fmaxf(fabsf(um[0]), fabsf(up[0])) * fabsf(ms.fp[d]);
+      else lf = fabsf(ms.fp[d]);
+    }
+    fs[0] = 0.5f * sg * (hex_flux<FLUX>(ms, um[0], d) + hex_flux<FLUX>(ms, up[0], d)) - 0.5f * lf * (up[0] - um[0]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -403,9 +481,9 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
                                                        MethodScalars ms, int mode, float dt, float a0, float b0,
                                                        uint32_t* __restrict__ status) {
   using S = HexShape<P>;
-  constexpr int N1 = S::N1, NL = S::NL, TEAM = S::TEAM, CPB = S::CPB;
-  __shared__ float su[CPB][NL];
-  __shared__ float sn[CPB][6][NL];
+  constexpr int N1 = S::N1, NL = S::NL, TEAM = S::TEAM, CPB = S::CPB, NV = HexNV<FLUX>::value;
+  __shared__ float su[CPB][NV][NL];
+  __shared__ float sn[CPB][6][NV][NL];
   __shared__ float sv[CPB][3][NL];
   const int slot = threadIdx.x / TEAM, t = threadIdx.x % TEAM;
   const bool lane_on = t < NL;
@@ -435,19 +513,23 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
   bool nonfinite = false;
   // software pipeline as in the sensor pass: the next block's nodal values,
   // gamma_e and neighbour ids at the top of an iteration, the neighbours'
-  // nodal values half-way through (clamped, unconditional loads)
-  float pu = 0.0f, pg = 0.0f, pn[6];
+  // nodal values half-way through (clamped, unconditional loads); variable v
+  // of cell e at (v E + e) NL
+  float pu[NV], pg = 0.0f, pn[6][NV];
   int32_t pid[6];
   auto fetch_a = [&](int64_t b) {
     const int64_t ec = b * CPB + slot < E ? b * CPB + slot : E - 1;
-    pu = u[ec * NL + tn];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) pu[v] = u[(v * E + ec) * NL + tn];
     pg = plain ? gamma_in[ec] : ms.fixed_gamma;
 #pragma unroll
     for (int f = 0; f < 6; ++f) pid[f] = nbr[ec * 6 + f];
   };
   auto fetch_b = [&]() {
 #pragma unroll
-    for (int f = 0; f < 6; ++f) pn[f] = u[static_cast<int64_t>(pid[f]) * NL + tn];
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) pn[f][v] = u[(v * E + pid[f]) * NL + tn];
   };
   fetch_a(blockIdx.x);
   fetch_b();
@@ -456,37 +538,42 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     const bool cell_on = e < E;
     const bool on = lane_on && cell_on;
     // ---- nodal values of the cell and of its six face neighbours
-    const float uv = on ? pu : 0.0f;
+    float uv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uv[v] = on ? pu[v] : 0.0f;
     const float gam = pg;                // gamma_e: from the sensor pass, or the fixed value
     if (lane_on) {
-      su[slot][t] = uv;
 #pragma unroll
-      for (int f = 0; f < 6; ++f) sn[slot][f][t] = on ? pn[f] : 0.0f;
+      for (int v = 0; v < NV; ++v) {
+        su[slot][v][t] = uv[v];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) sn[slot][f][v][t] = on ? pn[f][v] : 0.0f;
+      }
     }
     wave_sync();
     const int64_t nxt = blk + gridDim.x < nblk ? blk + gridDim.x : blk;
     fetch_a(nxt);
 
-    // ---- viscosity (eq. lostab) and the physical gradient at the node
+    // ---- viscosity (eq. lostab) and the physical gradient of the sensor field at the node
     float lam = ms.lam_g;
-    if (!(lam > 0.0f)) lam = team_maxf<TEAM>(lane_on ? hex_speed<FLUX>(ms, uv) : 0.0f);
+    if (!(lam > 0.0f)) lam = team_maxf<TEAM>(on ? hex_speed_all<FLUX>(ms, uv) : 0.0f);
     const float nu = lam * tab->nuf;
     float gr[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int j = 0; j < N1; ++j) {
-      gr[0] = fmaf(dr[0][j], su[slot][j + N1 * (tb + N1 * tc)], gr[0]);
-      gr[1] = fmaf(dr[1][j], su[slot][ta + N1 * (j + N1 * tc)], gr[1]);
-      gr[2] = fmaf(dr[2][j], su[slot][ta + N1 * (tb + N1 * j)], gr[2]);
+      gr[0] = fmaf(dr[0][j], su[slot][0][j + N1 * (tb + N1 * tc)], gr[0]);
+      gr[1] = fmaf(dr[1][j], su[slot][0][ta + N1 * (j + N1 * tc)], gr[1]);
+      gr[2] = fmaf(dr[2][j], su[slot][0][ta + N1 * (tb + N1 * j)], gr[2]);
     }
     fetch_b();
     const float gref[3] = {gr[0], gr[1], gr[2]};      // reference derivatives
 #pragma unroll
     for (int d = 0; d < 3; ++d) gr[d] *= tab->sc[d];
 
-    // ---- shock-capturing weights (cells with gamma_e < C_gamma)
+    // ---- shock-capturing weights of the sensor field (cells with gamma_e < C_gamma)
     float alpha = 1.0f;
     if (ms.sc_on && gam < ms.c_gamma) {
-      const float at = fsqrt(hex_atil2<P>(tab, su[slot], ta, tb, tc, gref));
+      const float at = fsqrt(hex_atil2<P>(tab, su[slot][0], ta, tb, tc, gref));
       const float f = lane_on ? (1.0f - gam) * (gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]) : 0.0f;
       const float Sv = team_sumf<TEAM>(W * f), Tv = team_sumf<TEAM>(W * at * f);
       if (Sv > 0.0f && Tv > 0.0f) alpha = at * (Sv / Tv);
@@ -498,19 +585,41 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
       continue;
     }
 
-    // ---- volume terms: -grad phi_j . f(u) + nu alpha (1 - gamma) grad phi_j . grad u
+    // ---- volume terms: -grad phi_j . f(u) + nu alpha (1 - gamma) grad phi_j . grad u,
+    // one variable at a time through the team's LDS slot
     const float gs = nu * alpha * (1.0f - gam);
-    if (lane_on) {
+    float fl[3][NV];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) sv[slot][d][t] = W * tab->sc[d] * (gs * gr[d] - hex_flux<FLUX>(ms, uv, d));
-    }
-    wave_sync();
-    float r = 0.0f;
+    for (int d = 0; d < 3; ++d) hex_flux_all<FLUX>(ms, uv, d, fl[d]);
+    float r[NV];
 #pragma unroll
-    for (int q = 0; q < N1; ++q) {
-      r = fmaf(dc[0][q], sv[slot][0][q + N1 * (tb + N1 * tc)], r);
-      r = fmaf(dc[1][q], sv[slot][1][ta + N1 * (q + N1 * tc)], r);
-      r = fmaf(dc[2][q], sv[slot][2][ta + N1 * (tb + N1 * q)], r);
+    for (int v = 0; v < NV; ++v) {
+      float g[3] = {gr[0], gr[1], gr[2]};
+      if (v > 0) {
+        g[0] = g[1] = g[2] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) {
+          g[0] = fmaf(dr[0][j], su[slot][v][j + N1 * (tb + N1 * tc)], g[0]);
+          g[1] = fmaf(dr[1][j], su[slot][v][ta + N1 * (j + N1 * tc)], g[1]);
+          g[2] = fmaf(dr[2][j], su[slot][v][ta + N1 * (tb + N1 * j)], g[2]);
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[d] *= tab->sc[d];
+      }
+      if (v > 0) wave_sync();                       // the previous variable's terms are read
+      if (lane_on) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sv[slot][d][t] = W * tab->sc[d] * (gs * g[d] - fl[d][v]);
+      }
+      wave_sync();
+      float rv = 0.0f;
+#pragma unroll
+      for (int q = 0; q < N1; ++q) {
+        rv = fmaf(dc[0][q], sv[slot][0][q + N1 * (tb + N1 * tc)], rv);
+        rv = fmaf(dc[1][q], sv[slot][1][ta + N1 * (q + N1 * tc)], rv);
+        rv = fmaf(dc[2][q], sv[slot][2][ta + N1 * (tb + N1 * q)], rv);
+      }
+      r[v] = rv;
     }
 
     // ---- interface terms: face f = 2 d + s, the neighbour read through its face f ^ 1
@@ -518,36 +627,40 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        float um = 0.0f, up = 0.0f;
+        float um[NV], up[NV];
 #pragma unroll
-        for (int j = 0; j < N1; ++j) {
-          const int idx = d == 0 ? j + N1 * (tb + N1 * tc) : (d == 1 ? ta + N1 * (j + N1 * tc) : ta + N1 * (tb + N1 * j));
-          um = fmaf(tab->Lend[s][j], su[slot][idx], um);
-          up = fmaf(tab->Lend[1 - s][j], sn[slot][2 * d + s][idx], up);
+        for (int v = 0; v < NV; ++v) {
+          um[v] = 0.0f;
+          up[v] = 0.0f;
+#pragma unroll
+          for (int j = 0; j < N1; ++j) {
+            const int idx = d == 0 ? j + N1 * (tb + N1 * tc) : (d == 1 ? ta + N1 * (j + N1 * tc) : ta + N1 * (tb + N1 * j));
+            um[v] = fmaf(tab->Lend[s][j], su[slot][v][idx], um[v]);
+            up[v] = fmaf(tab->Lend[1 - s][j], sn[slot][2 * d + s][v][idx], up[v]);
+          }
         }
-        const float sg = s ? 1.0f : -1.0f;
-        float lf = ms.lam_g;
-        if (!(lf > 0.0f)) {
-          if constexpr (FLUX == CVW_BURGERS) lf = fmaxf(fabsf(um), fabsf(up)) * fabsf(ms.fp[d]);
-          else lf = fabsf(ms.fp[d]);
-        }
-        const float fs = 0.5f * sg * (hex_flux<FLUX>(ms, um, d) + hex_flux<FLUX>(ms, up, d)) - 0.5f * lf * (up - um);
-        r = fmaf(lw[d][s], fs, r);
+        float fs[NV];
+        hex_num_flux<FLUX>(ms, um, up, d, s ? 1.0f : -1.0f, fs);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r[v] = fmaf(lw[d][s], fs[v], r[v]);
       }
     }
 
     // ---- output
     if (on) {
-      const int64_t idx = e * NL + t;
-      float o;
-      if (mode == MODE_RESIDUAL) {
-        o = r;
-      } else {
-        const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
-        o = base + b0 * (uv - dt * r / W);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int64_t idx = (v * E + e) * NL + t;
+        float o;
+        if (mode == MODE_RESIDUAL) {
+          o = r[v];
+        } else {
+          const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
+          o = base + b0 * (uv[v] - dt * r[v] / W);
+        }
+        nonfinite = nonfinite || !isfinite(o);
+        out[idx] = o;
       }
-      nonfinite = nonfinite || !isfinite(o);
-      out[idx] = o;
       if (t == 0 && gamma_out) gamma_out[e] = gam;
     }
     wave_sync();
@@ -593,14 +706,16 @@ cvw_status hex_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const fl
                     float* gamma, float* alpha, const float* cand, float* gbuf, uint32_t* status, float dt, float a0,
                     float b0, hipStream_t s) {
   const MethodScalars ms = make_scalars(prm);
-  const bool burgers = prm->flux == CVW_BURGERS;
+  const int fl = prm->flux;
   switch (m->degree) {
     case 1:
-      if (burgers) launch_hex_eval<1, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      if (fl == CVW_BURGERS) launch_hex_eval<1, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      else if (fl == CVW_EULER) launch_hex_eval<1, CVW_EULER>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       else launch_hex_eval<1, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       break;
     case 2:
-      if (burgers) launch_hex_eval<2, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      if (fl == CVW_BURGERS) launch_hex_eval<2, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      else if (fl == CVW_EULER) launch_hex_eval<2, CVW_EULER>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       else launch_hex_eval<2, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       break;
     default: set_error("hexahedra: degree 1 or 2"); return CVW_EUNSUPPORTED;
