@@ -91,22 +91,6 @@ struct HexNV {
   static constexpr int value = FLUX == CVW_EULER ? 5 : 1;
 };
 
-// f_d(U) along axis d, every variable
-template <int FLUX>
-__device__ __forceinline__ void hex_flux_all(const MethodScalars& ms, const float* u, int d, float* f) {
-  if constexpr (FLUX == CVW_EULER) {
-    const float inv = frcp(u[0]);
-    const float v[3] = {u[1] * inv, u[2] * inv, u[3] * inv};
-    const float p = (ms.fp[0] - 1.0f) * (u[4] - 0.5f * u[0] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
-    f[0] = u[1 + d];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) f[1 + a] = u[1 + a] * v[d] + (a == d ? p : 0.0f);
-    f[4] = (u[4] + p) * v[d];
-  } else {
-    f[0] = hex_flux<FLUX>(ms, u[0], d);
-  }
-}
-
 // local maximum wave speed (Euler: |v| + c)
 template <int FLUX>
 __device__ __forceinline__ float hex_speed_all(const MethodScalars& ms, const float* u) {
@@ -513,9 +497,11 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
   bool nonfinite = false;
   // software pipeline as in the sensor pass: the next block's nodal values,
   // gamma_e and neighbour ids at the top of an iteration, the neighbours'
-  // nodal values half-way through (clamped, unconditional loads); variable v
-  // of cell e at (v E + e) NL
-  float pu[NV], pg = 0.0f, pn[6][NV];
+  // nodal values half-way through (clamped, unconditional loads; a system
+  // reads its neighbours' values in the iteration instead, for registers);
+  // variable v of cell e at (v E + e) NL
+  constexpr bool PFN = NV == 1;
+  float pu[NV], pg = 0.0f, pn[6][PFN ? NV : 1];
   int32_t pid[6];
   auto fetch_a = [&](int64_t b) {
     const int64_t ec = b * CPB + slot < E ? b * CPB + slot : E - 1;
@@ -526,10 +512,10 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     for (int f = 0; f < 6; ++f) pid[f] = nbr[ec * 6 + f];
   };
   auto fetch_b = [&]() {
+    if constexpr (PFN) {
 #pragma unroll
-    for (int f = 0; f < 6; ++f)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) pn[f][v] = u[(v * E + pid[f]) * NL + tn];
+      for (int f = 0; f < 6; ++f) pn[f][0] = u[static_cast<int64_t>(pid[f]) * NL + tn];
+    }
   };
   fetch_a(blockIdx.x);
   fetch_b();
@@ -547,7 +533,12 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
       for (int v = 0; v < NV; ++v) {
         su[slot][v][t] = uv[v];
 #pragma unroll
-        for (int f = 0; f < 6; ++f) sn[slot][f][v][t] = on ? pn[f][v] : 0.0f;
+        for (int f = 0; f < 6; ++f) {
+          float x = 0.0f;
+          if constexpr (PFN) x = pn[f][0];
+          else x = u[(v * E + pid[f]) * NL + tn];
+          sn[slot][f][v][t] = on ? x : 0.0f;
+        }
       }
     }
     wave_sync();
@@ -588,9 +579,15 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     // ---- volume terms: -grad phi_j . f(u) + nu alpha (1 - gamma) grad phi_j . grad u,
     // one variable at a time through the team's LDS slot
     const float gs = nu * alpha * (1.0f - gam);
-    float fl[3][NV];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) hex_flux_all<FLUX>(ms, uv, d, fl[d]);
+    // the node's velocity and pressure (systems), for the fluxes of every variable
+    float vel[3] = {0.0f, 0.0f, 0.0f}, pres = 0.0f;
+    if constexpr (FLUX == CVW_EULER) {
+      const float inv = frcp(uv[0]);
+      vel[0] = uv[1] * inv;
+      vel[1] = uv[2] * inv;
+      vel[2] = uv[3] * inv;
+      pres = (ms.fp[0] - 1.0f) * (uv[4] - 0.5f * uv[0] * (vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]));
+    }
     float r[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -609,7 +606,14 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
       if (v > 0) wave_sync();                       // the previous variable's terms are read
       if (lane_on) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sv[slot][d][t] = W * tab->sc[d] * (gs * g[d] - fl[d][v]);
+        for (int d = 0; d < 3; ++d) {
+          float fv;
+          if constexpr (FLUX == CVW_EULER)   // f_d of variable v: m_d, m_a v_d + p delta_ad, (E + p) v_d
+            fv = v == 0 ? uv[1 + d] : (v < 4 ? uv[v] * vel[d] + (v - 1 == d ? pres : 0.0f) : (uv[4] + pres) * vel[d]);
+          else
+            fv = hex_flux<FLUX>(ms, uv[0], d);
+          sv[slot][d][t] = W * tab->sc[d] * (gs * g[d] - fv);
+        }
       }
       wave_sync();
       float rv = 0.0f;
@@ -622,11 +626,15 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
       r[v] = rv;
     }
 
-    // ---- interface terms: face f = 2 d + s, the neighbour read through its face f ^ 1
+    // ---- interface terms: face f = 2 d + s, the neighbour read through its
+    // face f ^ 1 (a system keeps the face loop rolled, for registers)
+#pragma unroll(NV == 1 ? 6 : 1)
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1, s = f & 1;
+      float lws = 0.0f;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
+      for (int k = 0; k < 6; ++k) lws = k == f ? lw[k >> 1][k & 1] : lws;
+      {
         float um[NV], up[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -642,7 +650,7 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
         float fs[NV];
         hex_num_flux<FLUX>(ms, um, up, d, s ? 1.0f : -1.0f, fs);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) r[v] = fmaf(lw[d][s], fs[v], r[v]);
+        for (int v = 0; v < NV; ++v) r[v] = fmaf(lws, fs[v], r[v]);
       }
     }
 
