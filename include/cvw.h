@@ -65,8 +65,9 @@ typedef enum {
 /* Hexahedra (CVW_HEX, dim 3): DG Q_p, p <= 2, on congruent axis-aligned
  * boxes of a periodic mesh with one cell in each of the eight octants of
  * every vertex (any conforming closed box mesh; the GPU path refuses others
- * with CVW_EUNSUPPORTED), scalar fluxes (constant advection, Burgers),
- * float32.  The vertex-based candidates of a cube: eight per cell (Sec. 3.2,
+ * with CVW_EUNSUPPORTED), constant advection, Burgers and the Euler
+ * equations (five variables rho, m_x, m_y, m_z, E; HLL at the faces; the
+ * density is the sensor field), float32.  The vertex-based candidates of a cube: eight per cell (Sec. 3.2,
  * the remark on stencil sizes).  Local vertices: the face z = z0
  * counter-clockwise from the lowest corner, then the face z = z0 + hz in the
  * same order; local node a + (p+1) b + (p+1)^2 c at the tensor Gauss points
