@@ -1847,8 +1847,8 @@ static cvw_status check_common(const cvw_mesh* m, const cvw_params* prm, size_t 
     if (!m->d_tett) { set_error("DG tetrahedra: degree <= 2"); return CVW_EUNSUPPORTED; }
     if (!m->closed) { set_error("DG tetrahedra: meshes without boundary faces (periodic)"); return CVW_EUNSUPPORTED; }
     if (prm->dtype != CVW_F32) { set_error("DG tetrahedra run in float32"); return CVW_EUNSUPPORTED; }
-    if (prm->flux != CVW_ADVECT_CONST && prm->flux != CVW_BURGERS) {
-      set_error("DG tetrahedra: constant-velocity advection and Burgers"); return CVW_EUNSUPPORTED;
+    if (prm->flux != CVW_ADVECT_CONST && prm->flux != CVW_BURGERS && prm->flux != CVW_EULER) {
+      set_error("DG tetrahedra: constant-velocity advection, Burgers and the Euler equations"); return CVW_EUNSUPPORTED;
     }
     return CVW_OK;
   }

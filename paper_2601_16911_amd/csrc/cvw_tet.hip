@@ -13,7 +13,9 @@
 //  * tet_eval_kernel -- one thread per cell, float32: the viscosity (eq.
 //    lostab), the shock-capturing weights (eqs. dissrateorig to alphaq), the
 //    volume and interface terms of the DG residual and optionally the
-//    Runge-Kutta stage update with the exact element mass.
+//    Runge-Kutta stage update with the exact element mass; scalar laws and
+//    the Euler equations (HLL at the faces; the sensor field and the SC
+//    weights from the density).
 //
 // A face's points are Radon's symmetric rule; the neighbour's trace at the
 // cell's own point g is the neighbour's basis at its rule point perm[s][g],
@@ -364,20 +366,67 @@ __global__ __launch_bounds__(TET_THREADS) void tet_sensor_kernel(const float* __
   gamma[e] = gam;
 }
 
+// Variables per node (the Euler equations: rho, m_x, m_y, m_z, E)
+template <int FLUX>
+struct TetNV {
+  static constexpr int value = FLUX == CVW_EULER ? 5 : 1;
+};
+
+// Euler: velocity and pressure of a state
+__device__ __forceinline__ float tet_prim(const MethodScalars& ms, const float* u, float (&v)[3]) {
+  const float inv = frcp(u[0]);
+  v[0] = u[1] * inv;
+  v[1] = u[2] * inv;
+  v[2] = u[3] * inv;
+  return (ms.fp[0] - 1.0f) * (u[4] - 0.5f * u[0] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+}
+
+// HLL with Davis wave-speed estimates for the Euler equations, normal n
+__device__ __forceinline__ void tet_hll(const MethodScalars& ms, const float* um, const float* up, const float (&n)[3],
+                                        float* fs) {
+  const float g = ms.fp[0];
+  float vm3[3], vp3[3];
+  const float pm = tet_prim(ms, um, vm3), pp = tet_prim(ms, up, vp3);
+  const float vm = vm3[0] * n[0] + vm3[1] * n[1] + vm3[2] * n[2];
+  const float vp = vp3[0] * n[0] + vp3[1] * n[1] + vp3[2] * n[2];
+  const float cm = fsqrt(fmaxf(g * pm * frcp(um[0]), 0.0f)), cp = fsqrt(fmaxf(g * pp * frcp(up[0]), 0.0f));
+  const float SL = fminf(vm - cm, vp - cp);
+  const float SR = fmaxf(vm + cm, vp + cp);
+  float Fm[5], Fp[5];
+  Fm[0] = um[0] * vm;
+  Fp[0] = up[0] * vp;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Fm[1 + a] = um[1 + a] * vm + pm * n[a];
+    Fp[1 + a] = up[1 + a] * vp + pp * n[a];
+  }
+  Fm[4] = (um[4] + pm) * vm;
+  Fp[4] = (up[4] + pp) * vp;
+  const float inv = frcp(SR - SL);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const float mid = (SR * Fm[v] - SL * Fp[v] + SL * SR * (up[v] - um[v])) * inv;
+    fs[v] = (SL >= 0.0f) ? Fm[v] : ((SR <= 0.0f) ? Fp[v] : mid);
+  }
+}
+
 template <int P, int FLUX>
 __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
     const float* __restrict__ u, const float* __restrict__ u0, float* __restrict__ out, float* __restrict__ gamma_out,
     float* __restrict__ alpha_out, const float* __restrict__ gamma_in, const int32_t* __restrict__ nbrt, const double* __restrict__ geot, const TetTables* __restrict__ tab, int64_t E,
     MethodScalars ms, int mode, float dt, float a0, float b0, uint32_t* __restrict__ status) {
   using S = TetShape<P>;
-  constexpr int NLOC = S::NLOC, NK = S::NK, NQ = S::NQ;
+  constexpr int NLOC = S::NLOC, NK = S::NK, NQ = S::NQ, NV = TetNV<FLUX>::value;
   const int tid = threadIdx.x;
   const int64_t e = static_cast<int64_t>(blockIdx.x) * TET_THREADS + tid;
   if (e >= E) return;
   const TetGeo G = load_tetgeo(geot, e);
-  float uv[NLOC];
+  // variable v of cell e at (v E + e) NLOC
+  float uv[NV][NLOC];
 #pragma unroll
-  for (int j = 0; j < NLOC; ++j) uv[j] = u[e * NLOC + j];
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) uv[v][j] = u[(v * E + e) * NLOC + j];
   const double h2 = G.h * G.h;
 
   // ---- gamma_e: from the sensor pass, or the fixed value
@@ -390,7 +439,7 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
 #pragma unroll
     for (int a = 0; a < 3; ++a) A[b][a] = static_cast<float>(G.A[b][a]);
   const float fdet = static_cast<float>(G.det);
-  // second derivatives (P = 2; constant), for alpha~
+  // second derivatives of the sensor field (P = 2; constant), for alpha~
   float hs2 = 0.0f;
   if constexpr (P >= 2) {
     double R[NK];
@@ -399,7 +448,7 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
 #pragma unroll
     for (int t = 0; t < 6; ++t)
 #pragma unroll
-      for (int j = 0; j < NLOC; ++j) R[3 + t] = fma(tab->H2[t][j], static_cast<double>(uv[j]), R[3 + t]);
+      for (int j = 0; j < NLOC; ++j) R[3 + t] = fma(tab->H2[t][j], static_cast<double>(uv[0][j]), R[3 + t]);
     double D[NK];
     tet_phys<P>(G.A, R, D);
 #pragma unroll
@@ -410,14 +459,26 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
     const float vn = fsqrt(ms.fp[0] * ms.fp[0] + ms.fp[1] * ms.fp[1] + ms.fp[2] * ms.fp[2]);
     lam = 0.0f;
     for (int q = 0; q < NQ; ++q) {
-      float uq = 0.0f;
+      float uq[NV];
 #pragma unroll
-      for (int j = 0; j < NLOC; ++j) uq = fmaf(tab->Bs[q][j], uv[j], uq);
-      lam = fmaxf(lam, FLUX == CVW_BURGERS ? fabsf(uq) * vn : vn);
+      for (int v = 0; v < NV; ++v) {
+        uq[v] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NLOC; ++j) uq[v] = fmaf(tab->Bs[q][j], uv[v][j], uq[v]);
+      }
+      float sp;
+      if constexpr (FLUX == CVW_EULER) {
+        float vel[3];
+        const float pq = tet_prim(ms, uq, vel);
+        sp = fsqrt(vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]) + fsqrt(fmaxf(ms.fp[0] * pq * frcp(uq[0]), 0.0f));
+      } else {
+        sp = FLUX == CVW_BURGERS ? fabsf(uq[0]) * vn : vn;
+      }
+      lam = fmaxf(lam, sp);
     }
   }
   const float nu = lam * static_cast<float>(G.h) / (2.0f * P);
-  // SC weights: S = sum W f, T = sum W alpha~ f over the volume points
+  // SC weights (sensor field): S = sum W f, T = sum W alpha~ f over the volume points
   const bool sc_active = ms.sc_on && gam < ms.c_gamma;
   float Sv = 0.0f, Tv = 0.0f;
   const float fh2 = static_cast<float>(h2);
@@ -427,7 +488,7 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
 #pragma unroll
       for (int j = 0; j < NLOC; ++j)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) gr[b] = fmaf(tab->Gs[b][q][j], uv[j], gr[b]);
+        for (int b = 0; b < 3; ++b) gr[b] = fmaf(tab->Gs[b][q][j], uv[0][j], gr[b]);
       float g2 = 0.0f;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -443,44 +504,59 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
   }
   const bool use_alpha = sc_active && Sv > 0.0f && Tv > 0.0f;
   const float ratioST = use_alpha ? Sv / Tv : 0.0f;
-  float r[NLOC];
+  float r[NV][NLOC];
 #pragma unroll
-  for (int j = 0; j < NLOC; ++j) r[j] = 0.0f;
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int j = 0; j < NLOC; ++j) r[v][j] = 0.0f;
   for (int q = 0; q < NQ; ++q) {
-    float uq = 0.0f, gr[3] = {0.0f, 0.0f, 0.0f};
+    float uq[NV], gp[NV][3];
 #pragma unroll
-    for (int j = 0; j < NLOC; ++j) {
-      uq = fmaf(tab->Bs[q][j], uv[j], uq);
+    for (int v = 0; v < NV; ++v) {
+      float gr[3] = {0.0f, 0.0f, 0.0f};
+      uq[v] = 0.0f;
 #pragma unroll
-      for (int b = 0; b < 3; ++b) gr[b] = fmaf(tab->Gs[b][q][j], uv[j], gr[b]);
-    }
-    float gp[3], g2 = 0.0f;
+      for (int j = 0; j < NLOC; ++j) {
+        uq[v] = fmaf(tab->Bs[q][j], uv[v][j], uq[v]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      gp[a] = A[0][a] * gr[0] + A[1][a] * gr[1] + A[2][a] * gr[2];
-      g2 = fmaf(gp[a], gp[a], g2);
+        for (int b = 0; b < 3; ++b) gr[b] = fmaf(tab->Gs[b][q][j], uv[v][j], gr[b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gp[v][a] = A[0][a] * gr[0] + A[1][a] * gr[1] + A[2][a] * gr[2];
     }
     float alpha = 1.0f;
-    if (use_alpha) alpha = fsqrt(fh2 * g2 + fh2 * fh2 * hs2) * ratioST;
+    if (use_alpha) {
+      const float g2 = gp[0][0] * gp[0][0] + gp[0][1] * gp[0][1] + gp[0][2] * gp[0][2];
+      alpha = fsqrt(fh2 * g2 + fh2 * fh2 * hs2) * ratioST;
+    }
     const float W = tab->wqs[q] * fdet;
     const float gs = nu * alpha * (1.0f - gam);
     if (mode == MODE_SENSOR) {
       if (alpha_out) alpha_out[e * NQ + q] = alpha;
       continue;
     }
-    float V[3];
+    float vel[3] = {0.0f, 0.0f, 0.0f}, pres = 0.0f;
+    if constexpr (FLUX == CVW_EULER) pres = tet_prim(ms, uq, vel);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float fa = FLUX == CVW_BURGERS ? 0.5f * uq * uq * ms.fp[a] : ms.fp[a] * uq;
-      V[a] = W * (gs * gp[a] - fa);
+    for (int v = 0; v < NV; ++v) {
+      float V[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float fa;
+        if constexpr (FLUX == CVW_EULER)   // f_a of variable v: m_a, m_c v_a + p delta_ca, (E + p) v_a
+          fa = v == 0 ? uq[1 + a] : (v < 4 ? uq[v] * vel[a] + (v - 1 == a ? pres : 0.0f) : (uq[4] + pres) * vel[a]);
+        else
+          fa = FLUX == CVW_BURGERS ? 0.5f * uq[0] * uq[0] * ms.fp[a] : ms.fp[a] * uq[0];
+        V[a] = W * (gs * gp[v][a] - fa);
+      }
+      float Vr[3];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Vr[b] = A[b][0] * V[0] + A[b][1] * V[1] + A[b][2] * V[2];
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) r[v][j] = fmaf(tab->Gs[b][q][j], Vr[b], r[v][j]);
     }
-    float Vr[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) Vr[b] = A[b][0] * V[0] + A[b][1] * V[1] + A[b][2] * V[2];
-#pragma unroll
-    for (int j = 0; j < NLOC; ++j)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) r[j] = fmaf(tab->Gs[b][q][j], Vr[b], r[j]);
   }
   if (mode == MODE_SENSOR) {
     if (gamma_out) gamma_out[e] = gam;
@@ -495,46 +571,65 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
 #pragma unroll
     for (int l = 1; l < 4; ++l) xvf[l][a] = static_cast<float>(G.J[a][l - 1]);   // relative to vertex 0
   }
-  const int FV[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
-#pragma unroll
+#pragma unroll(NV == 1 ? 4 : 1)
   for (int f = 0; f < 4; ++f) {
     const int32_t code = nbrt[e * 4 + f];
     const int64_t e2 = code >> 5;
     const int f2 = (code >> 3) & 3, sg = code & 7;
-    const float* va = xvf[FV[f][0]];
-    const float* vb = xvf[FV[f][1]];
-    const float* vc = xvf[FV[f][2]];
+    float va[3], vb[3], vc[3], vo[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {     // the face's vertices and the opposite one (a select: f may be a loop variable)
+      float x0 = xvf[0][a], x1 = xvf[1][a], x2 = xvf[2][a], x3 = xvf[3][a];
+      va[a] = f == 0 ? x1 : x0;
+      vb[a] = f <= 1 ? x2 : x1;
+      vc[a] = f <= 2 ? x3 : x2;
+      vo[a] = f == 0 ? x0 : (f == 1 ? x1 : (f == 2 ? x2 : x3));
+    }
     const float t1[3] = {vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]};
     const float t2[3] = {vc[0] - va[0], vc[1] - va[1], vc[2] - va[2]};
     float n[3] = {t1[1] * t2[2] - t1[2] * t2[1], t1[2] * t2[0] - t1[0] * t2[2], t1[0] * t2[1] - t1[1] * t2[0]};
     const float jf = fsqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     const float ij = 1.0f / jf;
-    const float* vo = xvf[f];
     const float side = n[0] * (vo[0] - va[0]) + n[1] * (vo[1] - va[1]) + n[2] * (vo[2] - va[2]);
     const float sgn = side > 0.0f ? -ij : ij;          // outward: away from the opposite vertex
 #pragma unroll
     for (int a = 0; a < 3; ++a) n[a] *= sgn;
-    float un[NLOC];
+    float un[NV][NLOC];
 #pragma unroll
-    for (int j = 0; j < NLOC; ++j) un[j] = u[e2 * NLOC + j];
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) un[v][j] = u[(v * E + e2) * NLOC + j];
     float lfv = 0.0f;
     if constexpr (FLUX != CVW_BURGERS) lfv = fabsf(ms.fp[0] * n[0] + ms.fp[1] * n[1] + ms.fp[2] * n[2]);
     const float bn = fabsf(ms.fp[0] * n[0] + ms.fp[1] * n[1] + ms.fp[2] * n[2]);
 #pragma unroll
     for (int g = 0; g < TET_NFP; ++g) {
       const int g2 = tab->perm[sg][g];
-      float um = 0.0f, up = 0.0f;
+      float um[NV], up[NV];
 #pragma unroll
-      for (int j = 0; j < NLOC; ++j) {
-        um = fmaf(tab->Bf[f][g][j], uv[j], um);
-        up = fmaf(tab->Bf[f2][g2][j], un[j], up);
+      for (int v = 0; v < NV; ++v) {
+        um[v] = 0.0f;
+        up[v] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NLOC; ++j) {
+          um[v] = fmaf(tab->Bf[f][g][j], uv[v][j], um[v]);
+          up[v] = fmaf(tab->Bf[f2][g2][j], un[v][j], up[v]);
+        }
       }
-      float lf = ms.lam_g;
-      if (!(lf > 0.0f)) lf = FLUX == CVW_BURGERS ? fmaxf(fabsf(um), fabsf(up)) * bn : lfv;
-      const float fs = 0.5f * (tet_fn<FLUX>(ms, um, n) + tet_fn<FLUX>(ms, up, n)) - 0.5f * lf * (up - um);
-      const float w = tab->wf[g] * jf * fs;
+      float fs[NV];
+      if constexpr (FLUX == CVW_EULER) {
+        tet_hll(ms, um, up, n, fs);
+      } else {
+        float lf = ms.lam_g;
+        if (!(lf > 0.0f)) lf = FLUX == CVW_BURGERS ? fmaxf(fabsf(um[0]), fabsf(up[0])) * bn : lfv;
+        fs[0] = 0.5f * (tet_fn<FLUX>(ms, um[0], n) + tet_fn<FLUX>(ms, up[0], n)) - 0.5f * lf * (up[0] - um[0]);
+      }
 #pragma unroll
-      for (int j = 0; j < NLOC; ++j) r[j] = fmaf(tab->Bf[f][g][j], w, r[j]);
+      for (int v = 0; v < NV; ++v) {
+        const float w = tab->wf[g] * jf * fs[v];
+#pragma unroll
+        for (int j = 0; j < NLOC; ++j) r[v][j] = fmaf(tab->Bf[f][g][j], w, r[v][j]);
+      }
     }
   }
 
@@ -542,24 +637,28 @@ __global__ __launch_bounds__(TET_THREADS) void tet_eval_kernel(
   bool nonfinite = false;
   if (mode == MODE_RESIDUAL) {
 #pragma unroll
-    for (int j = 0; j < NLOC; ++j) {
-      nonfinite = nonfinite || !isfinite(r[j]);
-      out[e * NLOC + j] = r[j];
-    }
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < NLOC; ++j) {
+        nonfinite = nonfinite || !isfinite(r[v][j]);
+        out[(v * E + e) * NLOC + j] = r[v][j];
+      }
   } else {
     // u_out = a0 u_n + b0 (u - dt M_e^{-1} r), M_e = det J M_ref
     const float scl = dt / fdet;
 #pragma unroll
-    for (int j = 0; j < NLOC; ++j) {
-      float x = 0.0f;
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int i = 0; i < NLOC; ++i) x = fmaf(tab->Minv[j][i], r[i], x);
-      const int64_t idx = e * NLOC + j;
-      const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
-      const float o = base + b0 * (uv[j] - scl * x);
-      nonfinite = nonfinite || !isfinite(o);
-      out[idx] = o;
-    }
+      for (int j = 0; j < NLOC; ++j) {
+        float x = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NLOC; ++i) x = fmaf(tab->Minv[j][i], r[v][i], x);
+        const int64_t idx = (v * E + e) * NLOC + j;
+        const float base = (a0 != 0.0f) ? a0 * u0[idx] : 0.0f;
+        const float o = base + b0 * (uv[v][j] - scl * x);
+        nonfinite = nonfinite || !isfinite(o);
+        out[idx] = o;
+      }
   }
   if (gamma_out) gamma_out[e] = gam;
   if (nonfinite) atomicOr(status, ST_NONFINITE);
@@ -599,13 +698,16 @@ cvw_status tet_eval(const cvw_mesh* m, const cvw_params* prm, int mode, const fl
                     float b0, hipStream_t s) {
   const MethodScalars ms = make_scalars(prm);
   const bool burgers = prm->flux == CVW_BURGERS;
+  const bool euler = prm->flux == CVW_EULER;
   switch (m->degree) {
     case 1:
       if (burgers) launch_tet_eval<1, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      else if (euler) launch_tet_eval<1, CVW_EULER>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       else launch_tet_eval<1, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       break;
     case 2:
       if (burgers) launch_tet_eval<2, CVW_BURGERS>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
+      else if (euler) launch_tet_eval<2, CVW_EULER>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       else launch_tet_eval<2, CVW_ADVECT_CONST>(m, ms, mode, u, u0, out, gamma, alpha, cand, gbuf, status, dt, a0, b0, s);
       break;
     default: set_error("tetrahedra: degree 1 or 2"); return CVW_EUNSUPPORTED;
