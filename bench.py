@@ -601,15 +601,17 @@ def bench_hex(torch, cvw, n: int = 128, p: int = 2, steps: int = 5, euler: bool 
             "status_flags": cvw.poll_status(gm, ws)}
 
 
-def bench_tet(torch, cvw, n: int = 64, p: int = 2, steps: int = 5):
+def bench_tet(torch, cvw, n: int = 64, p: int = 2, steps: int = 5, euler: bool = False):
     """3D: constant advection, DG P_p on the six-tetrahedra split of n^3
     periodic cubes (64^3: 1,572,864 cells, 15.7 M DOFs at p = 2), a smooth
-    field plus a ball-shaped jump.  Kernel times of the vertex pass and of the
-    cell pass in stage mode, the residual and the SSP-RK3 step.  Roofline of
-    the cell pass from its compulsory bytes per cell and stage: read u and
-    write u_out (2 n_loc floats), u_n in two of three stages, the float64
-    geometry record (128 B), the neighbour codes (16 B) and the candidates of
-    1/6 vertex per cell (n_k floats)."""
+    field plus a ball-shaped jump; or (euler) the Euler equations, gas gamma
+    1.4, a smooth flow with a ball of dense, high-pressure gas.  Kernel times
+    of the vertex pass and of the cell pass in stage mode, the residual and
+    the SSP-RK3 step.  Roofline of the cell pass from its compulsory bytes per
+    cell and stage: read u and write u_out (2 n_loc floats per variable), u_n
+    in two of three stages, the float64 geometry record (128 B), the
+    neighbour codes (16 B) and the candidates of 1/6 vertex per cell (n_k
+    floats)."""
     import synth
     stream = torch.cuda.current_stream()
     mesh = synth.tet_mesh(n, n, n)
@@ -619,12 +621,28 @@ def bench_tet(torch, cvw, n: int = 64, p: int = 2, steps: int = 5):
     pts = X[:, None, 0, :] + np.einsum("edk,nk->end", np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0],
                                                                X[:, 3] - X[:, 0]], axis=-1), nodes)
     x, y, z = pts[..., 0], pts[..., 1], pts[..., 2]
-    u0 = (np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 0.5 * np.sin(2 * np.pi * z)
-          + 1.5 * (((x - 0.45) ** 2 + (y - 0.4) ** 2 + (z - 0.5) ** 2) < 0.06))
-    U = torch.from_numpy(np.asarray(u0, np.float32).ravel()).cuda()
-    del pts, x, y, z, u0
+    ball = ((x - 0.45) ** 2 + (y - 0.4) ** 2 + (z - 0.5) ** 2) < 0.06
+    if euler:
+        g = 1.4
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 1.0 * ball
+        vel = (0.4 * np.cos(2 * np.pi * z), -0.3 * np.sin(2 * np.pi * x), 0.2 * np.sin(2 * np.pi * y))
+        pr = 1.0 + 0.2 * np.cos(2 * np.pi * (x + z)) + 1.5 * ball
+        En = pr / (g - 1.0) + 0.5 * rho * sum(v * v for v in vel)
+        U = torch.from_numpy(np.concatenate([np.asarray(a, np.float32).ravel()
+                                             for a in (rho, rho * vel[0], rho * vel[1], rho * vel[2], En)])).cuda()
+        lam = float(np.max(np.sqrt(sum(v * v for v in vel)) + np.sqrt(g * pr / rho)))
+        del rho, vel, pr, En
+        prm = synth.Params(flux=synth.EULER, flux_param=(g, 0, 0, 0))
+        nv = 5
+    else:
+        u0 = np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 0.5 * np.sin(2 * np.pi * z) + 1.5 * ball
+        U = torch.from_numpy(np.asarray(u0, np.float32).ravel()).cuda()
+        del u0
+        prm = synth.Params(flux=synth.ADVECT_CONST, flux_param=(1.0, -0.6, 0.8, 0))
+        lam = float(np.linalg.norm(prm.flux_param[:3]))
+        nv = 1
+    del pts, x, y, z, ball
     gm = cvw.Mesh(mesh, p, cvw.DG)
-    prm = synth.Params(flux=synth.ADVECT_CONST, flux_param=(1.0, -0.6, 0.8, 0))
     cp = cvw.make_params(prm)
     ws = cvw.alloc_workspace(gm, cp, 1)
     R = torch.empty_like(U)
@@ -633,15 +651,16 @@ def bench_tet(torch, cvw, n: int = 64, p: int = 2, steps: int = 5):
     cand = torch.empty(mesh.n_vertices * nk, dtype=torch.float32, device="cuda")
     dofs = U.numel()
     h = 1.0 / n
-    dt = 0.05 * h / ((2 * p + 1) * float(np.linalg.norm(prm.flux_param[:3])))
+    dt = 0.05 * h / ((2 * p + 1) * lam)
     t_vtx = _timed(torch, stream, lambda: cvw.vertex_candidates(gm, cp, U, cand, ws), 10)
     t_cell = _timed(torch, stream, lambda: cvw.rk_stage(gm, cp, U, cand, U, V, dt, 0.75, 0.25, ws), 10)
     t_res = _timed(torch, stream, lambda: cvw.residual(gm, cp, U, R, None, ws), 10)
     t_step = _timed(torch, stream, lambda: cvw.step(gm, cp, U, dt, steps, ws), 1) / steps
     E = mesh.n_cells
     nl = gm.info["n_loc"]
-    alg_cell = E * (4 * (2 * nl + 2.0 / 3.0 * nl) + 128 + 16 + 4 * nk * mesh.n_vertices / E)
-    return {"workload": f"3D constant advection, DG P{p} on {E} tetrahedra ({n}^3 periodic cubes split in six)",
+    alg_cell = E * (4 * nv * (2 * nl + 2.0 / 3.0 * nl) + 128 + 16 + 4 * nk * mesh.n_vertices / E)
+    what = "Euler equations" if euler else "constant advection"
+    return {"workload": f"3D {what}, DG P{p} on {E} tetrahedra ({n}^3 periodic cubes split in six)",
             "dofs": dofs,
             "vertex_pass": {"ms": t_vtx * 1e3},
             "cell_pass": {"ms": t_cell * 1e3, "achieved": alg_cell / t_cell / 1e9, "peak": HBM_PEAK_GBS,
@@ -838,13 +857,15 @@ def main():
                     help="also run one 256 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch shapes (no autotuner launches before the timed region)")
-    ap.add_argument("--part", choices=("step", "sensor", "learned", "small", "tri", "dmr", "hex", "hexeuler", "tet"),
+    ap.add_argument("--part", choices=("step", "sensor", "learned", "small", "tri", "dmr", "hex", "hexeuler", "tet",
+                                       "teteuler"),
                     default="step",
                     help="sensor / learned: only the plain or learned sensor pass, --steps calls after --warmup "
                          "(a short program for kernel traces and counters); small: only the 1D and CG "
                          "rotation workloads; tri: only the KPP triangle residual on 2048 x 2048 squares, --steps "
                          "calls; dmr: only the double Mach reflection run; hex / tet: only the 3D DG advection "
-                         "on cubes / tetrahedra; hexeuler: only the 3D Euler equations on cubes")
+                         "on cubes / tetrahedra; hexeuler / teteuler: only the 3D Euler equations on cubes / "
+                         "tetrahedra")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is benchmarked on one MI355X; "
@@ -870,6 +891,9 @@ def main():
         return
     if args.part == "tet":
         print(json.dumps(bench_tet(torch, cvw)))
+        return
+    if args.part == "teteuler":
+        print(json.dumps(bench_tet(torch, cvw, euler=True)))
         return
     if args.part == "small":
         out = bench_small_configs(torch, cvw)
@@ -1051,6 +1075,8 @@ def main():
         out["hexahedra_q2_euler"] = bench_hex(torch, cvw, n=96, euler=True)
         torch.cuda.empty_cache()
         out["tetrahedra_p2"] = bench_tet(torch, cvw)
+        torch.cuda.empty_cache()
+        out["tetrahedra_p2_euler"] = bench_tet(torch, cvw, euler=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

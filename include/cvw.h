@@ -75,8 +75,9 @@ typedef enum {
  * cell_coords [E][8][3]; flux_param[0..2] is the velocity (or the Burgers
  * direction) (vx, vy, vz). */
 /* Tetrahedra (CVW_TET, dim 3): DG P_p, p <= 2, on periodic meshes of
- * positively oriented tetrahedra (every face shared by two cells), scalar
- * fluxes, float32; four vertex candidates per cell.  Local nodes: the
+ * positively oriented tetrahedra (every face shared by two cells), constant
+ * advection, Burgers and the Euler equations (as on hexahedra), float32;
+ * four vertex candidates per cell.  Local nodes: the
  * equispaced lattice (i, j, k) / p, i + j + k <= p, of the reference cell
  * (0,0,0), (1,0,0), (0,1,0), (0,0,1), i fastest; face f opposite vertex f;
  * cell_coords [E][4][3]. */
