@@ -497,11 +497,9 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
   bool nonfinite = false;
   // software pipeline as in the sensor pass: the next block's nodal values,
   // gamma_e and neighbour ids at the top of an iteration, the neighbours'
-  // nodal values half-way through (clamped, unconditional loads; a system
-  // reads its neighbours' values in the iteration instead, for registers);
-  // variable v of cell e at (v E + e) NL
-  constexpr bool PFN = NV == 1;
-  float pu[NV], pg = 0.0f, pn[6][PFN ? NV : 1];
+  // nodal values half-way through (clamped, unconditional loads); variable v
+  // of cell e at (v E + e) NL
+  float pu[NV], pg = 0.0f, pn[6][NV];
   int32_t pid[6];
   auto fetch_a = [&](int64_t b) {
     const int64_t ec = b * CPB + slot < E ? b * CPB + slot : E - 1;
@@ -512,10 +510,10 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     for (int f = 0; f < 6; ++f) pid[f] = nbr[ec * 6 + f];
   };
   auto fetch_b = [&]() {
-    if constexpr (PFN) {
 #pragma unroll
-      for (int f = 0; f < 6; ++f) pn[f][0] = u[static_cast<int64_t>(pid[f]) * NL + tn];
-    }
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) pn[f][v] = u[(v * E + pid[f]) * NL + tn];
   };
   fetch_a(blockIdx.x);
   fetch_b();
@@ -533,12 +531,7 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
       for (int v = 0; v < NV; ++v) {
         su[slot][v][t] = uv[v];
 #pragma unroll
-        for (int f = 0; f < 6; ++f) {
-          float x = 0.0f;
-          if constexpr (PFN) x = pn[f][0];
-          else x = u[(v * E + pid[f]) * NL + tn];
-          sn[slot][f][v][t] = on ? x : 0.0f;
-        }
+        for (int f = 0; f < 6; ++f) sn[slot][f][v][t] = on ? pn[f][v] : 0.0f;
       }
     }
     wave_sync();
