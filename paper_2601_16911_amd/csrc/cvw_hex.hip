@@ -469,6 +469,9 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
   __shared__ float su[CPB][NV][NL];
   __shared__ float sn[CPB][6][NV][NL];
   __shared__ float sv[CPB][3][NL];
+  // systems: the weighted flux at every face point of the cell, item f NP + pq
+  constexpr int NP = N1 * N1, NI = 6 * NP;
+  __shared__ float sf[CPB][NV > 1 ? NV : 1][NV > 1 ? NI : 1];
   const int slot = threadIdx.x / TEAM, t = threadIdx.x % TEAM;
   const bool lane_on = t < NL;
   const int tn = lane_on ? t : 0;
@@ -476,7 +479,7 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
   const float W = tab->w1[ta] * tab->w1[tb] * tab->w1[tc] * tab->W0;
   // the lane's rows and columns of the tables, in registers for the whole loop
   // (the loop's wavefront fences keep the compiler from hoisting these loads)
-  float dr[3][N1], dc[3][N1], lw[3][2];
+  float dr[3][N1], dc[3][N1], lw[3][2], le[3][2];
 #pragma unroll
   for (int j = 0; j < N1; ++j) {
     dr[0][j] = tab->D1[ta][j];
@@ -491,7 +494,10 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     const int ad = d == 0 ? ta : (d == 1 ? tb : tc);
     const float wt = d == 0 ? tab->w1[tb] * tab->w1[tc] : (d == 1 ? tab->w1[ta] * tab->w1[tc] : tab->w1[ta] * tab->w1[tb]);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) lw[d][s] = tab->Lend[s][ad] * wt * tab->Jf[d];
+    for (int s = 0; s < 2; ++s) {
+      lw[d][s] = tab->Lend[s][ad] * wt * tab->Jf[d];
+      le[d][s] = tab->Lend[s][ad];
+    }
   }
   const bool plain = ms.sensor_kind != CVW_SENSOR_FIXED;
   bool nonfinite = false;
@@ -620,9 +626,45 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
     }
 
     // ---- interface terms: face f = 2 d + s, the neighbour read through its
-    // face f ^ 1 (a system keeps the face loop rolled, for registers)
+    // face f ^ 1.  A system evaluates each face point's flux once (the N1
+    // lanes on the point's normal line share it through LDS) and then lifts
+    // it along the lines; a scalar law lets every lane evaluate its own.
+    if constexpr (NV > 1) {
+#pragma unroll
+      for (int k = 0; k < (NI + TEAM - 1) / TEAM; ++k) {
+        const int i = t + k * TEAM;
+        if (i < NI) {
+          const int f = i / NP, pq = i % NP, d = f >> 1, s = f & 1, p = pq % N1, q = pq / N1;
+          float um[NV], up[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            um[v] = 0.0f;
+            up[v] = 0.0f;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+              const int idx = d == 0 ? m + N1 * (p + N1 * q) : (d == 1 ? p + N1 * (m + N1 * q) : p + N1 * (q + N1 * m));
+              um[v] = fmaf(tab->Lend[s][m], su[slot][v][idx], um[v]);
+              up[v] = fmaf(tab->Lend[1 - s][m], sn[slot][f][v][idx], up[v]);
+            }
+          }
+          float fs[NV];
+          hex_num_flux<FLUX>(ms, um, up, d, s ? 1.0f : -1.0f, fs);
+          const float wq = tab->w1[p] * tab->w1[q] * tab->Jf[d];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sf[slot][v][i] = wq * fs[v];
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        const int pq = d == 0 ? tb + N1 * tc : (d == 1 ? ta + N1 * tc : ta + N1 * tb);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r[v] = fmaf(le[d][s], sf[slot][v][f * NP + pq], r[v]);
+      }
+    }
 #pragma unroll(NV == 1 ? 6 : 1)
-    for (int f = 0; f < 6; ++f) {
+    for (int f = 0; f < (NV == 1 ? 6 : 0); ++f) {
       const int d = f >> 1, s = f & 1;
       float lws = 0.0f;
 #pragma unroll
