@@ -501,10 +501,10 @@ __global__ __launch_bounds__(256) void hex_eval_kernel(const float* __restrict__
   }
   const bool plain = ms.sensor_kind != CVW_SENSOR_FIXED;
   bool nonfinite = false;
-  // software pipeline as in the sensor pass: the next block's nodal values,
-  // gamma_e and neighbour ids at the top of an iteration, the neighbours'
-  // nodal values half-way through (clamped, unconditional loads); variable v
-  // of cell e at (v E + e) NL
+  // software pipeline: the next block's nodal values, gamma_e and neighbour
+  // ids are requested at the top of an iteration, the neighbours' nodal
+  // values half-way through (clamped, unconditional loads, so that no wait
+  // sits at the load); variable v of cell e at (v E + e) NL
   float pu[NV], pg = 0.0f, pn[6][NV];
   int32_t pid[6];
   auto fetch_a = [&](int64_t b) {
