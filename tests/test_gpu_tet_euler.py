@@ -141,3 +141,22 @@ def test_trajectory(p):
     for v in range(5):
         g, u0 = got.reshape(5, -1)[v], U.reshape(5, -1)[v]
         assert abs((w * g).sum() - (w * u0).sum()) <= 1e-5 * (w * np.abs(u0)).sum() + 1e-6, v
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_fixed_sensor_and_global_lambda(p):
+    """The fixed sensor and a global wave speed: the viscosity takes the
+    global speed, the faces keep HLL (as in the oracle)."""
+    mesh = _mesh(4, 3, 3)
+    sp = _space(mesh, p)
+    prm = Params(flux=synth.EULER, flux_param=(GAM, 0, 0, 0), sensor=2, fixed_gamma=0.3, lambda_global=3.0)
+    u = f32(_state(sp, 4))
+    gm = cvw.Mesh(mesh, p, cvw.DG)
+    cp = cvw.make_params(prm)
+    ws = cvw.alloc_workspace(gm, cp, 0)
+    R = torch.empty(u.size, dtype=torch.float32, device="cuda")
+    cvw.residual(gm, cp, _dev(u), R, None, ws)
+    Rg = R.cpu().numpy().reshape(5, -1)
+    Ro = o_residual(sp, u.ravel(), prm).reshape(5, -1)
+    for v in range(5):
+        assert rel_err(Rg[v], Ro[v]) < 1e-5, v
